@@ -1,0 +1,944 @@
+/*
+ * FP64 CPU oracle for the ADMM collision-avoidance path of
+ * "GPU-Accelerated Optimization-Based Collision Avoidance" (arXiv 2406.07048).
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may include, link or
+ * call this file; only the test-suite, the smoke check and the CPU baseline of
+ * the benchmark do. It shares no code with the HIP library.
+ *
+ * It computes, plainly and slowly, in double precision:
+ *   - the scale-based detection LP (Sec. III-A, eq. scale_opt) through its
+ *     dual (Sec. III-B, eq. scale_opt_dual) with a textbook two-phase dense
+ *     tableau simplex (Bland's rule);
+ *   - one dual-update sub-problem (Sec. IV-C, eq. const_least_square) with the
+ *     Jacobi-scaled proximal term (reading: prox weight eps * ||row_l K||^2
+ *     around the previous iterate), by a primal active-set method;
+ *   - the state/input update (Sec. IV-B, eq. ADMM_state_updates) as one QP per
+ *     ADMM iteration (Sec. IV-B, SQP remark) with R(s), rho(s) linearised at the
+ *     current iterate, solved by condensing the dynamics and a Cholesky
+ *     factorisation of the input Hessian;
+ *   - the multiplier update (Sec. IV-B, eq. ADMM_residue_updates) with the exact
+ *     nonlinear T and R, and the stopping test (Sec. IV-B, stopping criteria).
+ *
+ * Layout conventions (shared documentation with the C ABI, not shared code):
+ * pair blocks enumerate (scenario, robot part i, obstacle j); a block holds
+ * the N pairs t = 1..N; its dual rows (lambda, mu, gamma) are stored row-major
+ * [row][t]; zeta[block*N + t-1]; xi[(block*dim + c)*N + t-1].
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdio.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MAXD 3
+#define MAXROWS 64
+#define MAXS 16
+
+/* ------------------------------------------------------------------ */
+/* dense helpers                                                       */
+/* ------------------------------------------------------------------ */
+
+/* Solve M z = r in place (M n x n row-major, destroyed), Gaussian elimination
+   with partial pivoting. Returns 0 on success, 1 if a pivot vanishes. */
+static int gauss_solve(int n, double *M, double *r)
+{
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = fabs(M[k * n + k]);
+        for (int i = k + 1; i < n; ++i)
+            if (fabs(M[i * n + k]) > best) { best = fabs(M[i * n + k]); p = i; }
+        if (best == 0.0) return 1;
+        if (p != k) {
+            for (int j = 0; j < n; ++j) { double t = M[k * n + j]; M[k * n + j] = M[p * n + j]; M[p * n + j] = t; }
+            double t = r[k]; r[k] = r[p]; r[p] = t;
+        }
+        for (int i = k + 1; i < n; ++i) {
+            double f = M[i * n + k] / M[k * n + k];
+            if (f == 0.0) continue;
+            for (int j = k; j < n; ++j) M[i * n + j] -= f * M[k * n + j];
+            r[i] -= f * r[k];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        double s = r[k];
+        for (int j = k + 1; j < n; ++j) s -= M[k * n + j] * r[j];
+        r[k] = s / M[k * n + k];
+    }
+    return 0;
+}
+
+/* Cholesky solve of an SPD system (M destroyed). Returns 1 if not SPD. */
+static int chol_solve(int n, double *M, double *r)
+{
+    for (int j = 0; j < n; ++j) {
+        double s = M[j * n + j];
+        for (int k = 0; k < j; ++k) s -= M[j * n + k] * M[j * n + k];
+        if (s <= 0.0) return 1;
+        double L = sqrt(s);
+        M[j * n + j] = L;
+        for (int i = j + 1; i < n; ++i) {
+            double t = M[i * n + j];
+            for (int k = 0; k < j; ++k) t -= M[i * n + k] * M[j * n + k];
+            M[i * n + j] = t / L;
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        double s = r[i];
+        for (int k = 0; k < i; ++k) s -= M[i * n + k] * r[k];
+        r[i] = s / M[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = r[i];
+        for (int k = i + 1; k < n; ++k) s -= M[k * n + i] * r[k];
+        r[i] = s / M[i * n + i];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* scale LP (Sec. III-A eq. scale_opt, Sec. III-B eq. scale_opt_dual)  */
+/* ------------------------------------------------------------------ */
+
+/*
+ * min c^T z  s.t.  E z = f (f >= 0), z >= 0, with m rows and n columns,
+ * by the two-phase tableau simplex with Bland's anti-cycling rule.
+ * Outputs z (n) and the simplex multipliers pi (m) of the optimal basis.
+ * Returns 0 optimal, 1 infeasible, 2 unbounded, 3 iteration cap.
+ */
+static int simplex_std(int m, int n, const double *E, const double *f, const double *c,
+                       double *z, double *pi)
+{
+    const int W = n + m + 1;           /* columns: structural, artificial, rhs */
+    double *T = (double *)calloc((size_t)(m + 1) * W, sizeof(double));
+    int *basis = (int *)malloc(sizeof(int) * m);
+    int status = 0;
+    double scale = 1.0;
+    for (int i = 0; i < m * n; ++i) if (fabs(E[i]) > scale) scale = fabs(E[i]);
+    for (int j = 0; j < n; ++j) if (fabs(c[j]) > scale) scale = fabs(c[j]);
+    const double tol = 1e-12 * scale;
+
+    for (int i = 0; i < m; ++i) {
+        for (int j = 0; j < n; ++j) T[i * W + j] = E[i * n + j];
+        T[i * W + n + i] = 1.0;
+        T[i * W + W - 1] = f[i];
+        basis[i] = n + i;
+    }
+    for (int phase = 1; phase <= 2; ++phase) {
+        double *obj = T + (size_t)m * W;
+        /* reduced costs of the current basis for this phase's cost vector */
+        for (int j = 0; j < W; ++j) {
+            double cj = (j == W - 1) ? 0.0 : (phase == 1 ? (j >= n ? 1.0 : 0.0) : (j < n ? c[j] : 0.0));
+            double s = cj;
+            for (int i = 0; i < m; ++i) {
+                int bj = basis[i];
+                double cb = phase == 1 ? (bj >= n ? 1.0 : 0.0) : (bj < n ? c[bj] : 0.0);
+                s -= cb * T[i * W + j];
+            }
+            obj[j] = s;   /* obj[W-1] = -objective value */
+        }
+        int it;
+        for (it = 0; it < 1000; ++it) {
+            int enter = -1;
+            int ncols = (phase == 1) ? n + m : n;   /* artificials never re-enter in phase 2 */
+            for (int j = 0; j < ncols; ++j)
+                if (obj[j] < -tol) { enter = j; break; }          /* Bland: lowest index */
+            if (enter < 0) break;
+            int leave = -1;
+            double best = 0.0;
+            for (int i = 0; i < m; ++i) {
+                double a = T[i * W + enter];
+                if (a > tol) {
+                    double ratio = T[i * W + W - 1] / a;
+                    if (leave < 0 || ratio < best - 1e-15 * (1.0 + fabs(best)) ||
+                        (fabs(ratio - best) <= 1e-15 * (1.0 + fabs(best)) && basis[i] < basis[leave])) {
+                        leave = i;
+                        best = ratio;
+                    }
+                }
+            }
+            if (leave < 0) { status = 2; goto done; }
+            double pv = T[leave * W + enter];
+            for (int j = 0; j < W; ++j) T[leave * W + j] /= pv;
+            for (int i = 0; i <= m; ++i) {
+                if (i == leave) continue;
+                double fct = T[i * W + enter];
+                if (fct == 0.0) continue;
+                for (int j = 0; j < W; ++j) T[i * W + j] -= fct * T[leave * W + j];
+            }
+            basis[leave] = enter;
+        }
+        if (it >= 1000) { status = 3; goto done; }
+        if (phase == 1) {
+            if (-obj[W - 1] > 1e-9 * (1.0 + scale)) { status = 1; goto done; }
+            /* drive remaining (zero-level) artificials out of the basis */
+            for (int i = 0; i < m; ++i) {
+                if (basis[i] < n) continue;
+                int piv = -1;
+                double best = 1e-9;
+                for (int j = 0; j < n; ++j)
+                    if (fabs(T[i * W + j]) > best) { best = fabs(T[i * W + j]); piv = j; }
+                if (piv < 0) continue;   /* redundant row: artificial stays at zero */
+                double pv = T[i * W + piv];
+                for (int j = 0; j < W; ++j) T[i * W + j] /= pv;
+                for (int r = 0; r <= m; ++r) {
+                    if (r == i) continue;
+                    double fct = T[r * W + piv];
+                    if (fct == 0.0) continue;
+                    for (int j = 0; j < W; ++j) T[r * W + j] -= fct * T[i * W + j];
+                }
+                basis[i] = piv;
+            }
+        }
+    }
+    for (int j = 0; j < n; ++j) z[j] = 0.0;
+    for (int i = 0; i < m; ++i) if (basis[i] < n) z[basis[i]] = T[i * W + W - 1];
+    /* multipliers: the artificial column k holds B^{-1} e_k, and its phase-2
+       reduced cost is 0 - pi_k */
+    for (int k = 0; k < m; ++k) pi[k] = -T[(size_t)m * W + n + k];
+done:
+    free(T);
+    free(basis);
+    return status;
+}
+
+/*
+ * Scale LP of one robot part against one obstacle, both expressed in the
+ * part's body frame (obstacle faces Cp = C R, offsets dp = d - C pos):
+ *     alpha* = min alpha  s.t.  A x <= alpha b,  Cp x <= dp.
+ * Solved through the dual max -dp^T mu s.t. b^T lam = 1,
+ * A^T lam + Cp^T mu = 0, lam, mu >= 0 (Sec. III-B). Returns alpha*, the primal
+ * point x* (from the simplex multipliers), the dual certificate and the
+ * duality gap (primal objective alpha* minus dual objective -dp^T mu*).
+ */
+int orc_scale_lp(int dim, int nr, const double *A, const double *b,
+                 int no, const double *Cp, const double *dp,
+                 double *alpha, double *x, double *lam, double *mu, double *gap)
+{
+    int m = dim + 1, n = nr + no;
+    double *E = (double *)calloc((size_t)m * n, sizeof(double));
+    double *cc = (double *)calloc(n, sizeof(double));
+    double *z = (double *)calloc(n, sizeof(double));
+    double f[MAXD + 1] = {0}, pi[MAXD + 1] = {0};
+    f[0] = 1.0;
+    for (int k = 0; k < nr; ++k) {
+        E[0 * n + k] = b[k];
+        for (int r = 0; r < dim; ++r) E[(1 + r) * n + k] = A[k * dim + r];
+    }
+    for (int l = 0; l < no; ++l) {
+        for (int r = 0; r < dim; ++r) E[(1 + r) * n + nr + l] = Cp[l * dim + r];
+        cc[nr + l] = dp[l];
+    }
+    int st = simplex_std(m, n, E, f, cc, z, pi);
+    double dual_obj = 0.0;
+    for (int k = 0; k < nr; ++k) lam[k] = z[k];
+    for (int l = 0; l < no; ++l) { mu[l] = z[nr + l]; dual_obj -= dp[l] * z[nr + l]; }
+    *alpha = -pi[0];
+    for (int r = 0; r < dim; ++r) x[r] = pi[1 + r];
+    if (gap) *gap = *alpha - dual_obj;
+    free(E); free(cc); free(z);
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* pair QP (Sec. IV-C eq. const_least_square, with proximal term)      */
+/* ------------------------------------------------------------------ */
+
+/* Rows of K (Sec. IV-C): lambda rows (0, A_k), mu rows (dp_l, Cp_l),
+   gamma row (1, 0). Fills K (n x (dim+1)) and returns n. */
+static int build_K(int dim, int nr, const double *A, int no, const double *Cp, const double *dp, double *K)
+{
+    int c = dim + 1, n = nr + no + 1;
+    memset(K, 0, sizeof(double) * n * c);
+    for (int k = 0; k < nr; ++k)
+        for (int r = 0; r < dim; ++r) K[k * c + 1 + r] = A[k * dim + r];
+    for (int l = 0; l < no; ++l) {
+        K[(nr + l) * c] = dp[l];
+        for (int r = 0; r < dim; ++r) K[(nr + l) * c + 1 + r] = Cp[l * dim + r];
+    }
+    K[(nr + no) * c] = 1.0;
+    return n;
+}
+
+/*
+ * One dual-update sub-problem:
+ *   min_y 1/2 ||K^T y + bhat||^2 + eps/2 sum_l D_l (y_l - yhat_l)^2
+ *   s.t.  b^T lam = 1,  y >= 0,
+ * with y = (lam, mu, gamma), bhat = (1 + zeta, xi), D_l = ||row_l K||^2.
+ * Primal active-set method (equality-constrained sub-QPs solved by Gaussian
+ * elimination). Output y (n); returns the number of active-set iterations,
+ * or -1 on failure.
+ */
+int orc_pair_qp(int dim, int nr, const double *A, const double *b,
+                int no, const double *Cp, const double *dp,
+                double zeta, const double *xi, const double *yhat, double eps,
+                double *y)
+{
+    const int c = dim + 1;
+    double K[MAXROWS * (MAXD + 1)];
+    int n = build_K(dim, nr, A, no, Cp, dp, K);
+    double bh[MAXD + 1];
+    bh[0] = 1.0 + zeta;
+    for (int r = 0; r < dim; ++r) bh[1 + r] = xi[r];
+    double G[MAXROWS * MAXROWS], g[MAXROWS], D[MAXROWS], kap[MAXROWS];
+    for (int l = 0; l < n; ++l) {
+        double s = 0.0;
+        for (int q = 0; q < c; ++q) s += K[l * c + q] * K[l * c + q];
+        D[l] = s;
+        kap[l] = (l < nr) ? b[l] : 0.0;
+    }
+    for (int l = 0; l < n; ++l) {
+        for (int m = 0; m < n; ++m) {
+            double s = 0.0;
+            for (int q = 0; q < c; ++q) s += K[l * c + q] * K[m * c + q];
+            G[l * n + m] = s + (l == m ? eps * D[l] : 0.0);
+        }
+        double s = 0.0;
+        for (int q = 0; q < c; ++q) s += K[l * c + q] * bh[q];
+        g[l] = s - eps * D[l] * yhat[l];
+    }
+    /* feasible start: yhat if feasible, else 1/b_k on the largest b_k */
+    int feasible = 1;
+    double ky = 0.0;
+    for (int l = 0; l < n; ++l) { if (!(yhat[l] >= 0.0)) feasible = 0; ky += kap[l] * yhat[l]; }
+    if (fabs(ky - 1.0) > 1e-12) feasible = 0;
+    int inW[MAXROWS];
+    if (feasible) {
+        for (int l = 0; l < n; ++l) { y[l] = yhat[l]; }
+        /* re-normalise the equality exactly onto the lambda part */
+        if (ky != 1.0) for (int k = 0; k < nr; ++k) y[k] /= ky;
+    } else {
+        int kb = 0;
+        for (int k = 1; k < nr; ++k) if (b[k] > b[kb]) kb = k;
+        for (int l = 0; l < n; ++l) y[l] = 0.0;
+        y[kb] = 1.0 / b[kb];
+    }
+    for (int l = 0; l < n; ++l) inW[l] = (y[l] == 0.0);
+
+    double gscale = 1.0;
+    for (int l = 0; l < n * n; ++l) if (fabs(G[l]) > gscale) gscale = fabs(G[l]);
+    /* After a full (unblocked) step the iterate is the minimiser of the
+       equality-constrained sub-problem on the current working set, so the
+       bound multipliers are checked directly instead of re-solving. */
+    int at_eqp_min = 0;
+    double nu = 0.0;
+    for (int iter = 0; iter < 50 * n; ++iter) {
+        int F[MAXROWS], nf = 0;
+        for (int l = 0; l < n; ++l) if (!inW[l]) F[nf++] = l;
+        double grad[MAXROWS];
+        for (int l = 0; l < n; ++l) {
+            double s = g[l];
+            for (int m = 0; m < n; ++m) s += G[l * n + m] * y[m];
+            grad[l] = s;
+        }
+        double p[MAXROWS] = {0};
+        double ymax = 1.0;
+        for (int l = 0; l < n; ++l) if (fabs(y[l]) > ymax) ymax = fabs(y[l]);
+        if (!at_eqp_min) {
+            int sz = nf + 1;
+            double M[(MAXROWS + 1) * (MAXROWS + 1)], rhs[MAXROWS + 1];
+            for (int a = 0; a < nf; ++a) {
+                for (int bq = 0; bq < nf; ++bq) M[a * sz + bq] = G[F[a] * n + F[bq]];
+                M[a * sz + nf] = -kap[F[a]];
+                M[nf * sz + a] = kap[F[a]];
+                rhs[a] = -grad[F[a]];
+            }
+            M[nf * sz + nf] = 0.0;
+            rhs[nf] = 0.0;
+            if (gauss_solve(sz, M, rhs)) return -1;
+            double pmax = 0.0;
+            for (int a = 0; a < nf; ++a) { p[F[a]] = rhs[a]; if (fabs(rhs[a]) > pmax) pmax = fabs(rhs[a]); }
+            nu = rhs[nf];
+            if (pmax <= 1e-13 * ymax) at_eqp_min = 1;
+        }
+        if (at_eqp_min) {
+            /* bound multipliers w = grad - kappa nu on the working set */
+            int drop = -1;
+            double wmin = -1e-12 * gscale * ymax;
+            for (int l = 0; l < n; ++l) {
+                if (!inW[l]) continue;
+                double w = grad[l] - kap[l] * nu;
+                if (w < wmin) { wmin = w; drop = l; }
+            }
+            if (drop < 0) return iter;
+            inW[drop] = 0;
+            at_eqp_min = 0;
+            continue;
+        }
+        double step = 1.0;
+        int block = -1;
+        for (int a = 0; a < nf; ++a) {
+            int l = F[a];
+            if (p[l] < 0.0) {
+                double s = -y[l] / p[l];
+                if (s < step) { step = s; block = l; }
+            }
+        }
+        for (int l = 0; l < n; ++l) y[l] += step * p[l];
+        if (block >= 0) { y[block] = 0.0; inW[block] = 1; }
+        else at_eqp_min = 1;
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------------------ */
+/* pose R(s), rho(s) and their derivatives                             */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    int dim, n_s, n_u, N, n_parts, n_scen;
+    const int *part_face_ptr;
+    const double *part_A, *part_b, *part_off;
+    const int *obs_ptr, *obs_face_ptr;
+    const double *obs_C, *obs_d;
+    const double *A_dyn, *B_dyn, *c_dyn;
+    const int *pos_idx, *att_idx;
+    int att_kind;                   /* 0: planar yaw, 1: ZYX Euler (phi, theta, psi) */
+    const double *Q_s, *Q_u, *x_ref, *x0;
+    double sigma, eps_prox, eps_pri, eps_dual;
+} orc_problem;
+
+static int n_att(const orc_problem *P) { return P->att_kind == 0 ? 1 : 3; }
+
+/* R(s) and dR/d(att_a) for a = 0..n_att-1 (dim x dim row-major each). */
+static void rotation(const orc_problem *P, const double *s, double *R, double *dR)
+{
+    if (P->att_kind == 0) {
+        double th = s[P->att_idx[0]], c = cos(th), sn = sin(th);
+        R[0] = c; R[1] = -sn; R[2] = sn; R[3] = c;
+        if (dR) { dR[0] = -sn; dR[1] = -c; dR[2] = c; dR[3] = -sn; }
+        return;
+    }
+    double ph = s[P->att_idx[0]], th = s[P->att_idx[1]], ps = s[P->att_idx[2]];
+    double cf = cos(ph), sf = sin(ph), ct = cos(th), st = sin(th), cp = cos(ps), sp = sin(ps);
+    double Rx[9] = {1, 0, 0, 0, cf, -sf, 0, sf, cf};
+    double Ry[9] = {ct, 0, st, 0, 1, 0, -st, 0, ct};
+    double Rz[9] = {cp, -sp, 0, sp, cp, 0, 0, 0, 1};
+    double dRx[9] = {0, 0, 0, 0, -sf, -cf, 0, cf, -sf};
+    double dRy[9] = {-st, 0, ct, 0, 0, 0, -ct, 0, -st};
+    double dRz[9] = {-sp, -cp, 0, cp, -sp, 0, 0, 0, 0};
+    const double *F1[4] = {Rz, Rz, dRz, Rz};
+    const double *F2[4] = {Ry, dRy, Ry, Ry};
+    const double *F3[4] = {Rx, Rx, Rx, dRx};
+    /* index 0: R; 1: d/dtheta; 2: d/dpsi; 3: d/dphi */
+    double out[4][9];
+    for (int v = 0; v < 4; ++v) {
+        double T1[9];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double acc = 0;
+                for (int k = 0; k < 3; ++k) acc += F1[v][i * 3 + k] * F2[v][k * 3 + j];
+                T1[i * 3 + j] = acc;
+            }
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double acc = 0;
+                for (int k = 0; k < 3; ++k) acc += T1[i * 3 + k] * F3[v][k * 3 + j];
+                out[v][i * 3 + j] = acc;
+            }
+    }
+    memcpy(R, out[0], sizeof(double) * 9);
+    if (dR) {
+        memcpy(dR + 0, out[3], sizeof(double) * 9);   /* d/dphi */
+        memcpy(dR + 9, out[1], sizeof(double) * 9);   /* d/dtheta */
+        memcpy(dR + 18, out[2], sizeof(double) * 9);  /* d/dpsi */
+    }
+}
+
+/* Part frame quantities at state s: R, pos_i = rho(s) + R o_i, the obstacle
+   faces in the part frame Cp = C R and offsets dp = d - C pos_i. */
+static void part_frame(const orc_problem *P, const double *s, int i, int j,
+                       double *R, double *pos, double *Cp, double *dp)
+{
+    int dim = P->dim;
+    rotation(P, s, R, NULL);
+    for (int r = 0; r < dim; ++r) {
+        double acc = s[P->pos_idx[r]];
+        for (int q = 0; q < dim; ++q) acc += R[r * dim + q] * P->part_off[i * dim + q];
+        pos[r] = acc;
+    }
+    int f0 = P->obs_face_ptr[j], f1 = P->obs_face_ptr[j + 1];
+    for (int l = 0; l < f1 - f0; ++l) {
+        const double *cl = P->obs_C + (size_t)(f0 + l) * dim;
+        double acc = P->obs_d[f0 + l];
+        for (int r = 0; r < dim; ++r) acc -= cl[r] * pos[r];
+        dp[l] = acc;
+        for (int q = 0; q < dim; ++q) {
+            double a = 0;
+            for (int r = 0; r < dim; ++r) a += cl[r] * R[r * dim + q];
+            Cp[l * dim + q] = a;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* block enumeration                                                   */
+/* ------------------------------------------------------------------ */
+
+typedef struct { int s, i, j, nr, no, n; long yoff; } orc_block;
+
+static int count_blocks(const orc_problem *P)
+{
+    return P->n_parts * P->obs_ptr[P->n_scen];
+}
+
+static void enumerate_blocks(const orc_problem *P, orc_block *B)
+{
+    int b = 0;
+    long off = 0;
+    for (int s = 0; s < P->n_scen; ++s)
+        for (int i = 0; i < P->n_parts; ++i)
+            for (int j = P->obs_ptr[s]; j < P->obs_ptr[s + 1]; ++j) {
+                orc_block *q = &B[b++];
+                q->s = s; q->i = i; q->j = j;
+                q->nr = P->part_face_ptr[i + 1] - P->part_face_ptr[i];
+                q->no = P->obs_face_ptr[j + 1] - P->obs_face_ptr[j];
+                q->n = q->nr + q->no + 1;
+                q->yoff = off;
+                off += (long)q->n * P->N;
+            }
+}
+
+long orc_y_size(const orc_problem *P)
+{
+    int nb = count_blocks(P);
+    orc_block *B = (orc_block *)malloc(sizeof(orc_block) * (nb > 0 ? nb : 1));
+    enumerate_blocks(P, B);
+    long tot = nb ? B[nb - 1].yoff + (long)B[nb - 1].n * P->N : 0;
+    free(B);
+    return tot;
+}
+
+static const double *state_at(const orc_problem *P, const double *x, int s, int t)
+{
+    return x + ((size_t)s * (P->N + 1) + t) * P->n_s;
+}
+
+/* ------------------------------------------------------------------ */
+/* trajectory QP (Sec. IV-B eq. ADMM_state_updates, one SQP QP)         */
+/* ------------------------------------------------------------------ */
+
+/*
+ * min sum_{t=1..N} (1/2 x_t^T H_t x_t + h_t^T x_t) + sum_{t=0..N-1} u_t^T Q_u u_t
+ * s.t. x_{t+1} = A x_t + B u_t + c, x_0 given.
+ * Condensed: x_t = z_t + sum_{k<t} A^{t-1-k} B u_k, then a dense Cholesky
+ * solve in the stacked inputs.  H: N blocks (t = 1..N) of n_s x n_s.
+ */
+int orc_traj_qp(int n_s, int n_u, int N, const double *A, const double *B, const double *c,
+                const double *x0, const double *H, const double *h, const double *Q_u,
+                double *x, double *u)
+{
+    int nU = N * n_u;
+    double *Mt = (double *)calloc((size_t)N * n_s * nU, sizeof(double));   /* dx_t/du, t=1..N */
+    double *z = (double *)calloc((size_t)(N + 1) * n_s, sizeof(double));
+    double *Hs = (double *)calloc((size_t)nU * nU, sizeof(double));
+    double *gr = (double *)calloc(nU, sizeof(double));
+    double *HM = (double *)calloc((size_t)n_s * nU, sizeof(double));
+    memcpy(z, x0, sizeof(double) * n_s);
+    for (int t = 1; t <= N; ++t) {
+        double *Mc = Mt + (size_t)(t - 1) * n_s * nU;
+        const double *Mp = (t >= 2) ? Mt + (size_t)(t - 2) * n_s * nU : NULL;
+        for (int r = 0; r < n_s; ++r) {
+            double acc = c[r];
+            for (int q = 0; q < n_s; ++q) acc += A[r * n_s + q] * z[(t - 1) * n_s + q];
+            z[t * n_s + r] = acc;
+            for (int col = 0; col < nU; ++col) {
+                double a = 0.0;
+                if (Mp) for (int q = 0; q < n_s; ++q) a += A[r * n_s + q] * Mp[q * nU + col];
+                Mc[r * nU + col] = a;
+            }
+            for (int k = 0; k < n_u; ++k) Mc[r * nU + (t - 1) * n_u + k] += B[r * n_u + k];
+        }
+    }
+    for (int k = 0; k < N; ++k)
+        for (int a = 0; a < n_u; ++a)
+            for (int bq = 0; bq < n_u; ++bq)
+                Hs[(k * n_u + a) * nU + k * n_u + bq] = 2.0 * Q_u[a * n_u + bq];
+    for (int t = 1; t <= N; ++t) {
+        const double *Mc = Mt + (size_t)(t - 1) * n_s * nU;
+        const double *Ht = H + (size_t)(t - 1) * n_s * n_s;
+        const double *ht = h + (size_t)(t - 1) * n_s;
+        for (int r = 0; r < n_s; ++r)
+            for (int col = 0; col < nU; ++col) {
+                double a = 0.0;
+                for (int q = 0; q < n_s; ++q) a += Ht[r * n_s + q] * Mc[q * nU + col];
+                HM[r * nU + col] = a;
+            }
+        for (int a = 0; a < nU; ++a) {
+            for (int bq = 0; bq < nU; ++bq) {
+                double acc = 0.0;
+                for (int r = 0; r < n_s; ++r) acc += Mc[r * nU + a] * HM[r * nU + bq];
+                Hs[a * nU + bq] += acc;
+            }
+            double acc = 0.0;
+            for (int r = 0; r < n_s; ++r) {
+                double Hz = ht[r];
+                for (int q = 0; q < n_s; ++q) Hz += Ht[r * n_s + q] * z[t * n_s + q];
+                acc += Mc[r * nU + a] * Hz;
+            }
+            gr[a] += acc;
+        }
+    }
+    for (int a = 0; a < nU; ++a) gr[a] = -gr[a];
+    int st = chol_solve(nU, Hs, gr);
+    if (!st) {
+        memcpy(u, gr, sizeof(double) * nU);
+        memcpy(x, x0, sizeof(double) * n_s);
+        for (int t = 0; t < N; ++t)
+            for (int r = 0; r < n_s; ++r) {
+                double acc = c[r];
+                for (int q = 0; q < n_s; ++q) acc += A[r * n_s + q] * x[t * n_s + q];
+                for (int k = 0; k < n_u; ++k) acc += B[r * n_u + k] * u[t * n_u + k];
+                x[(t + 1) * n_s + r] = acc;
+            }
+    }
+    free(Mt); free(z); free(Hs); free(gr); free(HM);
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* ADMM pieces                                                         */
+/* ------------------------------------------------------------------ */
+
+/* T and R of one pair (Sec. IV-A): T = 1 + dp^T mu + gamma,
+   R = A^T lam + Cp^T mu, where y holds block rows for one t with stride N. */
+static void pair_TR(const orc_problem *P, const orc_block *q, const double *s,
+                    const double *yb, int stride, double *Tout, double *Rout)
+{
+    int dim = P->dim;
+    double R[9], pos[3], Cp[MAXROWS * MAXD], dp[MAXROWS];
+    part_frame(P, s, q->i, q->j, R, pos, Cp, dp);
+    const double *A = P->part_A + (size_t)P->part_face_ptr[q->i] * dim;
+    double T = 1.0 + yb[(q->n - 1) * stride];
+    for (int l = 0; l < q->no; ++l) T += dp[l] * yb[(q->nr + l) * stride];
+    for (int r = 0; r < dim; ++r) {
+        double acc = 0.0;
+        for (int k = 0; k < q->nr; ++k) acc += A[k * dim + r] * yb[k * stride];
+        for (int l = 0; l < q->no; ++l) acc += Cp[l * dim + r] * yb[(q->nr + l) * stride];
+        Rout[r] = acc;
+    }
+    *Tout = T;
+}
+
+/* s^0: obstacle-free LQ solution (stage Hessian 2 Q_s, gradient -2 Q_s xref). */
+static int lq_stage_base(const orc_problem *P, int s, double *H, double *h)
+{
+    int n_s = P->n_s, N = P->N;
+    for (int t = 1; t <= N; ++t) {
+        const double *xr = P->x_ref + ((size_t)s * (N + 1) + t) * n_s;
+        for (int r = 0; r < n_s; ++r) {
+            double acc = 0.0;
+            for (int q = 0; q < n_s; ++q) {
+                H[((size_t)(t - 1) * n_s + r) * n_s + q] = 2.0 * P->Q_s[r * n_s + q];
+                acc += 2.0 * P->Q_s[r * n_s + q] * xr[q];
+            }
+            h[(size_t)(t - 1) * n_s + r] = -acc;
+        }
+    }
+    return 0;
+}
+
+/* Initial iterate: s^0 = obstacle-free LQ, zeta = xi = 0,
+   y^0 = (lam*, mu*, max(alpha* - 1, 0)) from the scale LP at s^0. */
+int orc_admm_init(const orc_problem *P, double *x, double *u, double *y, double *zeta, double *xi)
+{
+    int n_s = P->n_s, N = P->N, dim = P->dim;
+    double *H = (double *)malloc(sizeof(double) * N * n_s * n_s);
+    double *h = (double *)malloc(sizeof(double) * N * n_s);
+    int bad = 0;
+    for (int s = 0; s < P->n_scen; ++s) {
+        lq_stage_base(P, s, H, h);
+        bad |= orc_traj_qp(n_s, P->n_u, N, P->A_dyn, P->B_dyn, P->c_dyn, P->x0 + (size_t)s * n_s,
+                           H, h, P->Q_u, x + (size_t)s * (N + 1) * n_s, u + (size_t)s * N * P->n_u);
+    }
+    free(H); free(h);
+    int nb = count_blocks(P);
+    orc_block *B = (orc_block *)malloc(sizeof(orc_block) * (nb > 0 ? nb : 1));
+    enumerate_blocks(P, B);
+    int npairs = nb * N;
+    #pragma omp parallel for schedule(dynamic, 16) reduction(|:bad)
+    for (int pidx = 0; pidx < npairs; ++pidx) {
+        const orc_block *q = &B[pidx / N];
+        int t = pidx % N + 1;
+        const double *st = state_at(P, x, q->s, t);
+        double R[9], pos[3], Cp[MAXROWS * MAXD], dp[MAXROWS], xs[3], alpha, lam[MAXROWS], mu[MAXROWS];
+        part_frame(P, st, q->i, q->j, R, pos, Cp, dp);
+        const double *A = P->part_A + (size_t)P->part_face_ptr[q->i] * dim;
+        const double *b = P->part_b + P->part_face_ptr[q->i];
+        bad |= (orc_scale_lp(dim, q->nr, A, b, q->no, Cp, dp, &alpha, xs, lam, mu, NULL) != 0);
+        double *yb = y + q->yoff + (t - 1);
+        for (int k = 0; k < q->nr; ++k) yb[k * N] = lam[k];
+        for (int l = 0; l < q->no; ++l) yb[(q->nr + l) * N] = mu[l];
+        yb[(q->n - 1) * N] = alpha > 1.0 ? alpha - 1.0 : 0.0;
+        zeta[(size_t)(pidx / N) * N + t - 1] = 0.0;
+        for (int r = 0; r < dim; ++r) xi[((size_t)(pidx / N) * dim + r) * N + t - 1] = 0.0;
+    }
+    free(B);
+    return bad;
+}
+
+/* Scale alpha* of every pair at the trajectory x (certificate check). */
+int orc_scale_all(const orc_problem *P, const double *x, double *alpha_out)
+{
+    int N = P->N, dim = P->dim, nb = count_blocks(P), bad = 0;
+    orc_block *B = (orc_block *)malloc(sizeof(orc_block) * (nb > 0 ? nb : 1));
+    enumerate_blocks(P, B);
+    #pragma omp parallel for schedule(dynamic, 16) reduction(|:bad)
+    for (int pidx = 0; pidx < nb * N; ++pidx) {
+        const orc_block *q = &B[pidx / N];
+        int t = pidx % N + 1;
+        double R[9], pos[3], Cp[MAXROWS * MAXD], dp[MAXROWS], xs[3], lam[MAXROWS], mu[MAXROWS];
+        part_frame(P, state_at(P, x, q->s, t), q->i, q->j, R, pos, Cp, dp);
+        bad |= (orc_scale_lp(dim, q->nr, P->part_A + (size_t)P->part_face_ptr[q->i] * dim,
+                             P->part_b + P->part_face_ptr[q->i], q->no, Cp, dp,
+                             &alpha_out[pidx], xs, lam, mu, NULL) != 0);
+    }
+    free(B);
+    return bad;
+}
+
+/* Step 1 (Sec. IV-B eq. ADMM_dual_updates): every pair QP at (s^k, zeta^k,
+   xi^k) with proximal centre y^k.  y_in -> y_out. active: per-scenario mask
+   (NULL = all). Returns number of failed pair solves. */
+int orc_pair_phase(const orc_problem *P, const double *x, const double *y_in,
+                   const double *zeta, const double *xi, const unsigned char *active,
+                   double *y_out)
+{
+    int N = P->N, dim = P->dim, nb = count_blocks(P), bad = 0;
+    orc_block *B = (orc_block *)malloc(sizeof(orc_block) * (nb > 0 ? nb : 1));
+    enumerate_blocks(P, B);
+    #pragma omp parallel for schedule(dynamic, 16) reduction(+:bad)
+    for (int pidx = 0; pidx < nb * N; ++pidx) {
+        const orc_block *q = &B[pidx / N];
+        int t = pidx % N + 1;
+        if (active && !active[q->s]) continue;
+        double R[9], pos[3], Cp[MAXROWS * MAXD], dp[MAXROWS], yh[MAXROWS], yo[MAXROWS], xr[3];
+        part_frame(P, state_at(P, x, q->s, t), q->i, q->j, R, pos, Cp, dp);
+        for (int l = 0; l < q->n; ++l) yh[l] = y_in[q->yoff + (long)l * N + t - 1];
+        for (int r = 0; r < dim; ++r) xr[r] = xi[((size_t)(pidx / N) * dim + r) * N + t - 1];
+        int it = orc_pair_qp(dim, q->nr, P->part_A + (size_t)P->part_face_ptr[q->i] * dim,
+                             P->part_b + P->part_face_ptr[q->i], q->no, Cp, dp,
+                             zeta[(size_t)(pidx / N) * N + t - 1], xr, yh, P->eps_prox, yo);
+        if (it < 0) { bad += 1; if (getenv("ORC_DEBUG")) fprintf(stderr, "pair fail block %d t %d\n", pidx / N, t); }
+        for (int l = 0; l < q->n; ++l) y_out[q->yoff + (long)l * N + t - 1] = yo[l];
+    }
+    free(B);
+    return bad;
+}
+
+/*
+ * Step 2 (Sec. IV-B eq. ADMM_state_updates): T and R linearised in the pose
+ * coordinates at s^k with y^{k+1}; the penalty sigma/2 ||r + J (q - q^k)||^2
+ * is added to the tracking cost and the LQ problem is solved.
+ * x_in/u_in = s^k; writes x_out/u_out = s^{k+1}.
+ */
+int orc_traj_phase(const orc_problem *P, const double *x_in, const double *y,
+                   const double *zeta, const double *xi, const unsigned char *active,
+                   double *x_out, double *u_out)
+{
+    int n_s = P->n_s, N = P->N, dim = P->dim, na = n_att(P), nq = dim + na;
+    int nb = count_blocks(P), bad = 0;
+    orc_block *B = (orc_block *)malloc(sizeof(orc_block) * (nb > 0 ? nb : 1));
+    enumerate_blocks(P, B);
+    int qidx[6];
+    for (int r = 0; r < dim; ++r) qidx[r] = P->pos_idx[r];
+    for (int a = 0; a < na; ++a) qidx[dim + a] = P->att_idx[a];
+    #pragma omp parallel for schedule(dynamic, 1) reduction(|:bad)
+    for (int s = 0; s < P->n_scen; ++s) {
+        if (active && !active[s]) {
+            memcpy(x_out + (size_t)s * (N + 1) * n_s, x_in + (size_t)s * (N + 1) * n_s, sizeof(double) * (N + 1) * n_s);
+            continue;
+        }
+        double *H = (double *)malloc(sizeof(double) * N * n_s * n_s);
+        double *h = (double *)malloc(sizeof(double) * N * n_s);
+        double *uo = u_out + (size_t)s * N * P->n_u;
+        lq_stage_base(P, s, H, h);
+        for (int b = 0; b < nb; ++b) {
+            const orc_block *q = &B[b];
+            if (q->s != s) continue;
+            const double *A = P->part_A + (size_t)P->part_face_ptr[q->i] * dim;
+            const double *Cw = P->obs_C + (size_t)P->obs_face_ptr[q->j] * dim;
+            const double *o = P->part_off + (size_t)q->i * dim;
+            for (int t = 1; t <= N; ++t) {
+                const double *st = state_at(P, x_in, s, t);
+                const double *yb = y + q->yoff + (t - 1);
+                double Rm[9], dR[27];
+                rotation(P, st, Rm, dR);
+                double T, Rr[3];
+                pair_TR(P, q, st, yb, N, &T, Rr);
+                double r[4];
+                r[0] = T + zeta[(size_t)b * N + t - 1];
+                for (int c = 0; c < dim; ++c) r[1 + c] = Rr[c] + xi[((size_t)b * dim + c) * N + t - 1];
+                /* cbar = C^T mu (world frame) */
+                double cbar[3] = {0, 0, 0};
+                for (int l = 0; l < q->no; ++l)
+                    for (int c = 0; c < dim; ++c) cbar[c] += Cw[l * dim + c] * yb[(q->nr + l) * N];
+                (void)A;
+                /* J: (dim+1) x nq in pose coordinates (position, attitude) */
+                double J[4 * 6];
+                memset(J, 0, sizeof(J));
+                for (int c = 0; c < dim; ++c) J[0 * nq + c] = -cbar[c];
+                for (int a = 0; a < na; ++a) {
+                    const double *dRa = dR + a * dim * dim;
+                    double acc = 0.0;
+                    for (int r1 = 0; r1 < dim; ++r1)
+                        for (int q1 = 0; q1 < dim; ++q1) acc += cbar[r1] * dRa[r1 * dim + q1] * o[q1];
+                    J[0 * nq + dim + a] = -acc;
+                    for (int c = 0; c < dim; ++c) {
+                        double v = 0.0;
+                        for (int r1 = 0; r1 < dim; ++r1) v += dRa[r1 * dim + c] * cbar[r1];
+                        J[(1 + c) * nq + dim + a] = v;
+                    }
+                }
+                double qk[6];
+                for (int a = 0; a < nq; ++a) qk[a] = st[qidx[a]];
+                double e[4];
+                for (int m = 0; m <= dim; ++m) {
+                    double acc = r[m];
+                    for (int a = 0; a < nq; ++a) acc -= J[m * nq + a] * qk[a];
+                    e[m] = acc;
+                }
+                double *Ht = H + (size_t)(t - 1) * n_s * n_s;
+                double *ht = h + (size_t)(t - 1) * n_s;
+                for (int a = 0; a < nq; ++a) {
+                    for (int c = 0; c < nq; ++c) {
+                        double acc = 0.0;
+                        for (int m = 0; m <= dim; ++m) acc += J[m * nq + a] * J[m * nq + c];
+                        Ht[qidx[a] * n_s + qidx[c]] += P->sigma * acc;
+                    }
+                    double acc = 0.0;
+                    for (int m = 0; m <= dim; ++m) acc += J[m * nq + a] * e[m];
+                    ht[qidx[a]] += P->sigma * acc;
+                }
+            }
+        }
+        bad |= orc_traj_qp(n_s, P->n_u, N, P->A_dyn, P->B_dyn, P->c_dyn, P->x0 + (size_t)s * n_s,
+                           H, h, P->Q_u, x_out + (size_t)s * (N + 1) * n_s, uo);
+        free(H); free(h);
+    }
+    free(B);
+    return bad;
+}
+
+/* Step 3 (Sec. IV-B eq. ADMM_residue_updates): zeta += T(s^{k+1}, y^{k+1}),
+   xi += R(s^{k+1}, y^{k+1}); accumulates per-scenario sum of squared
+   multiplier changes into rpri (n_scen). */
+void orc_mult_phase(const orc_problem *P, const double *x, const double *y,
+                    const unsigned char *active, double *zeta, double *xi, double *rpri)
+{
+    int N = P->N, dim = P->dim, nb = count_blocks(P);
+    orc_block *B = (orc_block *)malloc(sizeof(orc_block) * (nb > 0 ? nb : 1));
+    enumerate_blocks(P, B);
+    for (int s = 0; s < P->n_scen; ++s) rpri[s] = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const orc_block *q = &B[b];
+        if (active && !active[q->s]) continue;
+        for (int t = 1; t <= N; ++t) {
+            double T, Rr[3];
+            pair_TR(P, q, state_at(P, x, q->s, t), y + q->yoff + (t - 1), N, &T, Rr);
+            zeta[(size_t)b * N + t - 1] += T;
+            double acc = T * T;
+            for (int c = 0; c < dim; ++c) {
+                xi[((size_t)b * dim + c) * N + t - 1] += Rr[c];
+                acc += Rr[c] * Rr[c];
+            }
+            rpri[q->s] += acc;
+        }
+    }
+    free(B);
+}
+
+/* Tracking cost F (Sec. IV-A eq. navigation_cost) over x_{1..N}, u_{0..N-1}. */
+double orc_cost(const orc_problem *P, int s, const double *x, const double *u)
+{
+    int n_s = P->n_s, n_u = P->n_u, N = P->N;
+    double F = 0.0;
+    for (int t = 1; t <= N; ++t) {
+        const double *xt = x + ((size_t)s * (N + 1) + t) * n_s;
+        const double *xr = P->x_ref + ((size_t)s * (N + 1) + t) * n_s;
+        for (int r = 0; r < n_s; ++r)
+            for (int q = 0; q < n_s; ++q) F += (xt[r] - xr[r]) * P->Q_s[r * n_s + q] * (xt[q] - xr[q]);
+    }
+    for (int t = 0; t < N; ++t) {
+        const double *ut = u + ((size_t)s * N + t) * n_u;
+        for (int r = 0; r < n_u; ++r)
+            for (int q = 0; q < n_u; ++q) F += ut[r] * P->Q_u[r * n_u + q] * ut[q];
+    }
+    return F;
+}
+
+/*
+ * Full ADMM run from the given iterate (x, u, y, zeta, xi) for at most
+ * max_iters iterations; each scenario stops at the first iteration at which
+ * both sums of squares fall below eps_pri and eps_dual (Sec. IV-B) and is
+ * left unchanged afterwards.  hist_* (max_iters x n_scen, may be NULL)
+ * receive r_pri, r_dual and F per iteration; iters_out (n_scen) the number of
+ * iterations each scenario ran. Returns the number of failed sub-solves.
+ */
+int orc_admm_run(const orc_problem *P, int max_iters, double *x, double *u, double *y,
+                 double *zeta, double *xi, double *hist_pri, double *hist_dual, double *hist_cost,
+                 int *iters_out)
+{
+    int S = P->n_scen, N = P->N, dim = P->dim;
+    long ny = orc_y_size(P);
+    int nb = count_blocks(P);
+    orc_block *B = (orc_block *)malloc(sizeof(orc_block) * (nb > 0 ? nb : 1));
+    enumerate_blocks(P, B);
+    double *ynew = (double *)malloc(sizeof(double) * (ny > 0 ? ny : 1));
+    double *xnew = (double *)malloc(sizeof(double) * S * (N + 1) * P->n_s);
+    double *rpri = (double *)calloc(S, sizeof(double));
+    double *rdual = (double *)calloc(S, sizeof(double));
+    unsigned char *active = (unsigned char *)malloc(S);
+    int bad = 0;
+    for (int s = 0; s < S; ++s) { active[s] = 1; iters_out[s] = 0; }
+    for (int k = 0; k < max_iters; ++k) {
+        int any = 0;
+        for (int s = 0; s < S; ++s) any |= active[s];
+        if (!any) break;
+        memcpy(ynew, y, sizeof(double) * ny);
+        bad += orc_pair_phase(P, x, y, zeta, xi, active, ynew);
+        bad += orc_traj_phase(P, x, ynew, zeta, xi, active, xnew, u);
+        for (int s = 0; s < S; ++s) rdual[s] = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            const orc_block *q = &B[b];
+            if (!active[q->s]) continue;
+            for (int l = 0; l < q->n - 1; ++l)      /* lambda and mu rows only */
+                for (int t = 0; t < N; ++t) {
+                    double dlt = ynew[q->yoff + (long)l * N + t] - y[q->yoff + (long)l * N + t];
+                    rdual[q->s] += dlt * dlt;
+                }
+        }
+        memcpy(y, ynew, sizeof(double) * ny);
+        memcpy(x, xnew, sizeof(double) * S * (N + 1) * P->n_s);
+        orc_mult_phase(P, x, y, active, zeta, xi, rpri);
+        for (int s = 0; s < S; ++s) {
+            if (!active[s]) {
+                if (hist_pri) { hist_pri[k * S + s] = NAN; hist_dual[k * S + s] = NAN; hist_cost[k * S + s] = NAN; }
+                continue;
+            }
+            iters_out[s] = k + 1;
+            if (hist_pri) {
+                hist_pri[k * S + s] = rpri[s];
+                hist_dual[k * S + s] = rdual[s];
+                hist_cost[k * S + s] = orc_cost(P, s, x, u);
+            }
+            if (rpri[s] <= P->eps_pri && rdual[s] <= P->eps_dual) active[s] = 0;
+        }
+    }
+    (void)dim;
+    free(B); free(ynew); free(xnew); free(rpri); free(rdual); free(active);
+    return bad;
+}
+
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}

@@ -1,0 +1,396 @@
+"""Seeded synthetic problem instances for the collision-avoidance ADMM path.
+
+This module only draws geometry, dynamics models, references and costs. It
+holds none of the method's arithmetic (no scale LP, no pair QP, no trajectory
+QP), so both the FP64 oracle and the HIP path can consume its output.
+
+Shapes follow the problem statement of the paper: robot = union of convex
+polytope parts {x : A_i x <= b_i} posed by the state (Sec. IV-A), obstacles =
+union of convex polytopes {y : C_j y <= d_j} (Sec. IV-A), dynamics
+s_{t+1} = s_t + f(s_t, u_t) (Sec. IV-A, system equation) given here already
+linearised about a straight reference, tracking cost with weights Q_s, Q_u
+(Sec. IV-A, navigation cost).
+
+Problem dictionary (all numpy arrays, float64 unless noted):
+  dim, n_s, n_u, N (horizon), dt
+  part_face_ptr int32[P+1], part_A [F_r, dim], part_b [F_r], part_off [P, dim]
+  obs_ptr int32[n_scen+1]       obstacle range of each scenario
+  obs_face_ptr int32[M_tot+1]   face range of each obstacle
+  obs_C [F_o, dim] (unit normals), obs_d [F_o]
+  A_dyn [n_s, n_s], B_dyn [n_s, n_u], c_dyn [n_s]   (time-invariant)
+  pos_idx int32[dim], att_idx int32[1|3], att_kind (0 planar yaw, 1 ZYX Euler)
+  Q_s [n_s, n_s], Q_u [n_u, n_u], x_ref [n_scen, N+1, n_s], x0 [n_scen, n_s]
+  sigma, eps_prox, eps_pri, eps_dual
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.spatial import ConvexHull
+
+ATT_YAW = 0
+ATT_EULER_ZYX = 1
+
+# ADMM penalty used in the paper's quadrotor experiment (Sec. V-A).
+SIGMA_PAPER = 300.0
+
+
+# --------------------------------------------------------------------------
+# geometry helpers
+# --------------------------------------------------------------------------
+def box_faces(half_extents, yaw=0.0):
+    """H-form of an axis-aligned box (optionally yawed about z) centred at 0."""
+    h = np.asarray(half_extents, dtype=np.float64)
+    d = h.size
+    A = np.concatenate([np.eye(d), -np.eye(d)], axis=0)
+    b = np.concatenate([h, h])
+    if yaw != 0.0:
+        c, s = np.cos(yaw), np.sin(yaw)
+        Rz = np.eye(d)
+        Rz[0, 0], Rz[0, 1], Rz[1, 0], Rz[1, 1] = c, -s, s, c
+        # {x : A Rz^T x <= b} is the box rotated by Rz
+        A = A @ Rz.T
+    return A, b
+
+
+def hull_faces(points, merge_tol=1e-9):
+    """Unit-normal H-form {x : C x <= d} of the convex hull of points."""
+    hull = ConvexHull(points)
+    eq = hull.equations  # n.x + off <= 0 inside
+    normals = eq[:, :-1]
+    offs = -eq[:, -1]
+    nn = np.linalg.norm(normals, axis=1)
+    normals = normals / nn[:, None]
+    offs = offs / nn
+    keep = []
+    for k in range(len(offs)):
+        dup = False
+        for q in keep:
+            if np.linalg.norm(normals[k] - normals[q]) < merge_tol and abs(offs[k] - offs[q]) < merge_tol:
+                dup = True
+                break
+        if not dup:
+            keep.append(k)
+    return normals[keep], offs[keep]
+
+
+def polygon_on_circle(rng, n_faces, radius):
+    """Convex polygon with n_faces vertices at sorted uniform angles on a circle."""
+    while True:
+        ang = np.sort(rng.uniform(0.0, 2 * np.pi, size=n_faces))
+        gaps = np.diff(np.concatenate([ang, ang[:1] + 2 * np.pi]))
+        if gaps.min() > 1e-3 and gaps.max() < np.pi - 1e-3:
+            break
+    pts = radius * np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    C, d = hull_faces(pts)
+    return C, d
+
+
+def disc_points(rng, n, r, dim):
+    """n points uniform (by volume) in a dim-ball of radius r."""
+    x = rng.normal(size=(n, dim))
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    rad = r * rng.uniform(size=(n, 1)) ** (1.0 / dim)
+    return x * rad
+
+
+# --------------------------------------------------------------------------
+# dynamics models (already linearised about a straight constant-speed line)
+# --------------------------------------------------------------------------
+def bicycle_model(v_ref, dt=0.1, wheelbase=2.7):
+    """Kinematic bicycle, state (p_x, p_y, theta, v), input (a, delta).
+
+    Euler-discretised and linearised about theta = 0, v = v_ref, delta = 0.
+    """
+    A = np.eye(4)
+    A[0, 3] = dt
+    A[1, 2] = dt * v_ref
+    B = np.zeros((4, 2))
+    B[2, 1] = dt * v_ref / wheelbase
+    B[3, 0] = dt
+    c = np.zeros(4)
+    return A, B, c
+
+
+def quadrotor_model(dt=0.1, mass=1.0, J=(0.01, 0.01, 0.02), g=9.81):
+    """12-state hover-linearised quadrotor (p, v, phi theta psi, omega).
+
+    Input (dF, tau_x, tau_y, tau_z). Euler-discretised.
+    """
+    Ac = np.zeros((12, 12))
+    Ac[0:3, 3:6] = np.eye(3)
+    Ac[3, 7] = g      # v_x' = g theta
+    Ac[4, 6] = -g     # v_y' = -g phi
+    Ac[6:9, 9:12] = np.eye(3)
+    Bc = np.zeros((12, 4))
+    Bc[5, 0] = 1.0 / mass
+    Bc[9, 1] = 1.0 / J[0]
+    Bc[10, 2] = 1.0 / J[1]
+    Bc[11, 3] = 1.0 / J[2]
+    return np.eye(12) + dt * Ac, dt * Bc, np.zeros(12)
+
+
+# --------------------------------------------------------------------------
+# problem assembly
+# --------------------------------------------------------------------------
+def _pack_parts(parts):
+    ptr = [0]
+    A, b, off = [], [], []
+    for (Ai, bi, oi) in parts:
+        A.append(Ai)
+        b.append(bi)
+        off.append(oi)
+        ptr.append(ptr[-1] + len(bi))
+    return (np.asarray(ptr, np.int32), np.concatenate(A), np.concatenate(b),
+            np.asarray(off, np.float64))
+
+
+def _pack_obstacles(scen_obstacles):
+    obs_ptr = [0]
+    face_ptr = [0]
+    C, d = [], []
+    for obs in scen_obstacles:
+        for (Cj, dj) in obs:
+            C.append(Cj)
+            d.append(dj)
+            face_ptr.append(face_ptr[-1] + len(dj))
+        obs_ptr.append(obs_ptr[-1] + len(obs))
+    dim = C[0].shape[1] if C else 2
+    return (np.asarray(obs_ptr, np.int32), np.asarray(face_ptr, np.int32),
+            np.concatenate(C) if C else np.zeros((0, dim)),
+            np.concatenate(d) if d else np.zeros(0))
+
+
+def _straight_ref(start, direction, speed, N, dt, n_s, pos_idx, vel_idx):
+    x = np.zeros((N + 1, n_s))
+    for t in range(N + 1):
+        x[t, pos_idx] = np.asarray(start) + np.asarray(direction) * speed * t * dt
+    if vel_idx is not None:
+        x[:, vel_idx] = np.asarray(direction) * speed if np.ndim(vel_idx) else speed
+    return x
+
+
+def _reject_near_start(center, radius, start_pts, robot_radius, margin=0.5):
+    for p in start_pts:
+        if np.linalg.norm(center - p) < radius + robot_radius + margin:
+            return True
+    return False
+
+
+def _obstacles_2d_hull(rng, M, field_lo, field_hi, start_pts, robot_radius, face_range,
+                       n_points=12, r=3.0):
+    obs = []
+    while len(obs) < M:
+        c = rng.uniform(field_lo, field_hi, size=2)
+        pts = disc_points(rng, n_points, r, 2)
+        C, dl = hull_faces(pts)
+        if not (face_range[0] <= len(dl) <= face_range[1]):
+            continue
+        rad = np.linalg.norm(pts, axis=1).max()
+        if _reject_near_start(c, rad, start_pts, robot_radius):
+            continue
+        obs.append((C, dl + C @ c))
+    return obs
+
+
+def _finish(prob):
+    prob.setdefault("eps_pri", 1e-4)
+    prob.setdefault("eps_dual", 1e-4)
+    prob.setdefault("eps_prox", 1e-1)
+    return prob
+
+
+def config_c1(seed=16):
+    """2D: one 4.5 x 2 m rectangle, 3 hull obstacles (4-8 faces) in a 40 x 40 m
+    field, bicycle at 20 m/s, N = 20, sigma = 1."""
+    rng = np.random.default_rng(seed)
+    N, dt, v = 20, 0.1, 20.0
+    A_r, b_r = box_faces([2.25, 1.0])
+    parts = [(A_r, b_r, np.zeros(2))]
+    start = np.array([0.0, 20.0])
+    start_pts = [start, start + np.array([v * dt, 0.0])]
+    obs = _obstacles_2d_hull(rng, 3, 0.0, 40.0, start_pts, np.hypot(2.25, 1.0), (4, 8))
+    return _assemble_2d(parts, [obs], N, dt, v, start[None, :], sigma=1.0)
+
+
+def config_c2(seed=10):
+    """2D: cab 3 x 2.5 + trailer 9 x 2.5 (rigid), 40 hull obstacles (3-10 faces)
+    in a 100 x 100 m field, bicycle at 20 m/s, N = 50 -> 4000 pairs, sigma as
+    in the paper's experiment."""
+    rng = np.random.default_rng(seed)
+    N, dt, v = 50, 0.1, 20.0
+    A_c, b_c = box_faces([1.5, 1.25])
+    A_t, b_t = box_faces([4.5, 1.25])
+    parts = [(A_c, b_c, np.array([4.5, 0.0])), (A_t, b_t, np.array([-1.5, 0.0]))]
+    start = np.array([0.0, 50.0])
+    start_pts = [start, start + np.array([v * dt, 0.0])]
+    obs = _obstacles_2d_hull(rng, 40, 0.0, 100.0, start_pts, np.hypot(6.0, 1.25), (3, 10))
+    return _assemble_2d(parts, [obs], N, dt, v, start[None, :], sigma=SIGMA_PAPER)
+
+
+def config_c4(seed=101, n_scen=256, m_range=(10, 80), f_range=(3, 12)):
+    """Batched 2D: n_scen scenarios of the C1 robot/model, obstacle counts
+    uniform in m_range, polygon faces uniform in f_range, 8 m/s, N = 50."""
+    N, dt, v = 50, 0.1, 8.0
+    A_r, b_r = box_faces([2.25, 1.0])
+    parts = [(A_r, b_r, np.zeros(2))]
+    scen = []
+    starts = []
+    for s in range(n_scen):
+        rng = np.random.default_rng(seed + s)
+        M = int(rng.integers(m_range[0], m_range[1] + 1))
+        start = np.array([0.0, 20.0])
+        start_pts = [start, start + np.array([v * dt, 0.0]), start + np.array([2 * v * dt, 0.0])]
+        obs = []
+        while len(obs) < M:
+            F = int(rng.integers(f_range[0], f_range[1] + 1))
+            rad = rng.uniform(0.5, 3.0)
+            c = rng.uniform(0.0, 40.0, size=2)
+            if _reject_near_start(c, rad, start_pts, np.hypot(2.25, 1.0)):
+                continue
+            C, dl = polygon_on_circle(rng, F, rad)
+            obs.append((C, dl + C @ c))
+        scen.append(obs)
+        starts.append(start)
+    return _assemble_2d(parts, scen, N, dt, v, np.asarray(starts), sigma=1.0)
+
+
+def _assemble_2d(parts, scen_obstacles, N, dt, v, starts, sigma):
+    ptr, A, b, off = _pack_parts(parts)
+    obs_ptr, face_ptr, C, d = _pack_obstacles(scen_obstacles)
+    Ad, Bd, cd = bicycle_model(v, dt)
+    n_scen = len(scen_obstacles)
+    x_ref = np.zeros((n_scen, N + 1, 4))
+    for s in range(n_scen):
+        x_ref[s] = _straight_ref(starts[s], [1.0, 0.0], v, N, dt, 4, [0, 1], None)
+        x_ref[s, :, 3] = v
+    return _finish(dict(
+        dim=2, n_s=4, n_u=2, N=N, dt=dt,
+        part_face_ptr=ptr, part_A=A, part_b=b, part_off=off,
+        obs_ptr=obs_ptr, obs_face_ptr=face_ptr, obs_C=C, obs_d=d,
+        A_dyn=Ad, B_dyn=Bd, c_dyn=cd,
+        pos_idx=np.array([0, 1], np.int32), att_idx=np.array([2], np.int32), att_kind=ATT_YAW,
+        Q_s=np.diag([1.0, 1.0, 0.1, 0.1]), Q_u=np.diag([0.1, 0.1]),
+        x_ref=x_ref, x0=x_ref[:, 0, :].copy(), sigma=sigma))
+
+
+def config_c3(seed=25, M=200, N=40, k_range=(7, 12)):
+    """3D: quadrotor = body box + two crossed arm boxes, M hull polyhedra
+    (hulls of k ~ U{7..12} points in a 1.5 m ball), 50^3 m box, 12.5 m/s, N = 40."""
+    rng = np.random.default_rng(seed)
+    dt, v = 0.1, 12.5
+    A_b, b_b = box_faces([0.15, 0.15, 0.05])
+    A_1, b_1 = box_faces([0.4, 0.03, 0.02], yaw=np.pi / 4)
+    A_2, b_2 = box_faces([0.4, 0.03, 0.02], yaw=-np.pi / 4)
+    parts = [(A_b, b_b, np.zeros(3)), (A_1, b_1, np.zeros(3)), (A_2, b_2, np.zeros(3))]
+    start = np.array([0.0, 25.0, 25.0])
+    start_pts = [start, start + np.array([v * dt, 0, 0])]
+    obs = []
+    while len(obs) < M:
+        k = int(rng.integers(k_range[0], k_range[1] + 1))
+        pts = disc_points(rng, k, 1.5, 3)
+        try:
+            C, dl = hull_faces(pts)
+        except Exception:
+            continue
+        if not (6 <= len(dl) <= 20):
+            continue
+        c = rng.uniform(0.0, 50.0, size=3)
+        rad = np.linalg.norm(pts, axis=1).max()
+        if _reject_near_start(c, rad, start_pts, 0.45):
+            continue
+        obs.append((C, dl + C @ c))
+    ptr, A, b, off = _pack_parts(parts)
+    obs_ptr, face_ptr, C, d = _pack_obstacles([obs])
+    Ad, Bd, cd = quadrotor_model(dt)
+    x_ref = np.zeros((1, N + 1, 12))
+    x_ref[0] = _straight_ref(start, [1.0, 0.0, 0.0], v, N, dt, 12, [0, 1, 2], None)
+    x_ref[0, :, 3] = v
+    return _finish(dict(
+        dim=3, n_s=12, n_u=4, N=N, dt=dt,
+        part_face_ptr=ptr, part_A=A, part_b=b, part_off=off,
+        obs_ptr=obs_ptr, obs_face_ptr=face_ptr, obs_C=C, obs_d=d,
+        A_dyn=Ad, B_dyn=Bd, c_dyn=cd,
+        pos_idx=np.array([0, 1, 2], np.int32), att_idx=np.array([6, 7, 8], np.int32),
+        att_kind=ATT_EULER_ZYX,
+        Q_s=np.diag([1, 1, 1, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1, 0.01, 0.01, 0.01]).astype(np.float64),
+        Q_u=np.diag([0.1, 1.0, 1.0, 1.0]),
+        x_ref=x_ref, x0=x_ref[:, 0, :].copy(), sigma=SIGMA_PAPER))
+
+
+CONFIGS = {
+    "c1": config_c1,
+    "c2": config_c2,
+    "c3": config_c3,
+    "c4": config_c4,
+}
+
+
+def make(name, **kw):
+    return CONFIGS[name](**kw)
+
+
+def select_scenarios(prob, idx):
+    """Sub-problem holding only the scenarios listed in idx (same robot/model)."""
+    out = dict(prob)
+    obs_ptr = prob["obs_ptr"]
+    fptr = prob["obs_face_ptr"]
+    new_obs_ptr = [0]
+    new_fptr = [0]
+    C, d = [], []
+    for s in idx:
+        for j in range(obs_ptr[s], obs_ptr[s + 1]):
+            C.append(prob["obs_C"][fptr[j]:fptr[j + 1]])
+            d.append(prob["obs_d"][fptr[j]:fptr[j + 1]])
+            new_fptr.append(new_fptr[-1] + fptr[j + 1] - fptr[j])
+        new_obs_ptr.append(new_obs_ptr[-1] + obs_ptr[s + 1] - obs_ptr[s])
+    dim = prob["dim"]
+    out["obs_ptr"] = np.asarray(new_obs_ptr, np.int32)
+    out["obs_face_ptr"] = np.asarray(new_fptr, np.int32)
+    out["obs_C"] = np.concatenate(C) if C else np.zeros((0, dim))
+    out["obs_d"] = np.concatenate(d) if d else np.zeros(0)
+    out["x_ref"] = prob["x_ref"][list(idx)].copy()
+    out["x0"] = prob["x0"][list(idx)].copy()
+    return out
+
+
+def with_obstacles(prob, scen_obstacles):
+    """Copy of prob with the obstacle lists replaced (one list per scenario)."""
+    out = dict(prob)
+    obs_ptr, face_ptr, C, d = _pack_obstacles(scen_obstacles)
+    if C.shape[0] == 0:
+        C = np.zeros((0, prob["dim"]))
+    out.update(obs_ptr=obs_ptr, obs_face_ptr=face_ptr, obs_C=C, obs_d=d)
+    return out
+
+
+def n_scenarios(prob):
+    return len(prob["obs_ptr"]) - 1
+
+
+def block_layout(prob):
+    """Canonical pair-block enumeration shared by both sides of the boundary.
+
+    Block b enumerates (scenario s, robot part i, obstacle j) in that nesting
+    order; it holds the N pairs t = 1..N. Block b has n_b = n_r,i + n_o,j + 1
+    dual rows (lambda, mu, gamma). Returns arrays (scen, part, obs, n_rows,
+    y_off) with y_off in floats (rows x N per block).
+    """
+    N = prob["N"]
+    P = len(prob["part_face_ptr"]) - 1
+    pf = prob["part_face_ptr"]
+    of = prob["obs_face_ptr"]
+    op = prob["obs_ptr"]
+    scen, part, obs, nrow, yoff = [], [], [], [], []
+    off = 0
+    for s in range(len(op) - 1):
+        for i in range(P):
+            for j in range(op[s], op[s + 1]):
+                n = (pf[i + 1] - pf[i]) + (of[j + 1] - of[j]) + 1
+                scen.append(s)
+                part.append(i)
+                obs.append(j)
+                nrow.append(n)
+                yoff.append(off)
+                off += n * N
+    return (np.asarray(scen, np.int64), np.asarray(part, np.int64), np.asarray(obs, np.int64),
+            np.asarray(nrow, np.int64), np.asarray(yoff, np.int64), off)
