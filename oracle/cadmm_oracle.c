@@ -141,22 +141,40 @@ static int simplex_std(int m, int n, const double *E, const double *f, const dou
         }
         int it;
         for (it = 0; it < 1000; ++it) {
+            /* phase 1 only seeks feasibility: stop once the artificial sum is 0 */
+            if (phase == 1 && -obj[W - 1] <= 1e-12 * (1.0 + scale)) break;
+            /* reduced-cost tolerance grows with the tableau entries, so that
+               rounding noise of large intermediate entries never drives a pivot */
+            double growth = 1.0;
+            for (int i = 0; i < m * W; ++i) if (fabs(T[i]) > growth) growth = fabs(T[i]);
+            const double rtol = tol * growth;
             int enter = -1;
             int ncols = (phase == 1) ? n + m : n;   /* artificials never re-enter in phase 2 */
             for (int j = 0; j < ncols; ++j)
-                if (obj[j] < -tol) { enter = j; break; }          /* Bland: lowest index */
+                if (obj[j] < -rtol) { enter = j; break; }          /* Bland: lowest index */
             if (enter < 0) break;
+            /* Harris two-pass ratio test: the minimum ratio with the right-hand
+               side relaxed by a small tolerance, then, among the rows within
+               it, the largest pivot element (never a pivot that is rounding
+               noise of a cancelled entry) */
             int leave = -1;
-            double best = 0.0;
+            double cmaxv = 0.0;
+            for (int i = 0; i < m; ++i) if (fabs(T[i * W + enter]) > cmaxv) cmaxv = fabs(T[i * W + enter]);
+            const double ptol = tol > 1e-9 * cmaxv ? tol : 1e-9 * cmaxv;
+            double theta = INFINITY;
             for (int i = 0; i < m; ++i) {
                 double a = T[i * W + enter];
-                if (a > tol) {
-                    double ratio = T[i * W + W - 1] / a;
-                    if (leave < 0 || ratio < best - 1e-15 * (1.0 + fabs(best)) ||
-                        (fabs(ratio - best) <= 1e-15 * (1.0 + fabs(best)) && basis[i] < basis[leave])) {
-                        leave = i;
-                        best = ratio;
-                    }
+                if (a > ptol) {
+                    double r = (T[i * W + W - 1] + tol) / a;
+                    if (r < theta) theta = r;
+                }
+            }
+            double bestpiv = 0.0;
+            for (int i = 0; i < m; ++i) {
+                double a = T[i * W + enter];
+                if (a > ptol && T[i * W + W - 1] / a <= theta && a > bestpiv) {
+                    bestpiv = a;
+                    leave = i;
                 }
             }
             if (leave < 0) { status = 2; goto done; }
@@ -169,6 +187,7 @@ static int simplex_std(int m, int n, const double *E, const double *f, const dou
                 for (int j = 0; j < W; ++j) T[i * W + j] -= fct * T[leave * W + j];
             }
             basis[leave] = enter;
+            for (int i = 0; i < m; ++i) if (T[i * W + W - 1] < 0.0) T[i * W + W - 1] = 0.0;
         }
         if (it >= 1000) { status = 3; goto done; }
         if (phase == 1) {
