@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark of the ADMM collision-avoidance hot path on one MI355X.
+
+A step is one complete solve of the workload with inputs resident in HBM:
+reset to the initial iterate (obstacle-free LQ trajectory, scale-LP
+certificates), the ADMM iterations (pair QPs, trajectory QP, multiplier
+update, residual test, all inside a HIP graph) and the final scale
+certificate at the last trajectory. The headline value is pair-QP solves per
+second over the timed steps; ADMM iterations per second and the residuals
+reached are reported beside it, together with the batched-vs-plain comparison
+on 256 scenarios, the pair kernel's roofline figure and the FP64 oracle timed
+on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "c2": dict(desc="2D cab+trailer (2 parts x 4 faces), 40 hull obstacles (3-10 faces), N=50, "
+                    "4000 pair QPs/iteration, 200 ADMM iterations, sigma=300", iters=200),
+    "c3": dict(desc="3D quadrotor (3 boxes), 200 hull polyhedra (6-20 faces), N=40, "
+                    "24000 pair QPs/iteration, 200 ADMM iterations, sigma=300", iters=200),
+    "c1": dict(desc="2D rectangle, 3 obstacles, N=20, 60 pair QPs/iteration, 50 ADMM iterations", iters=50),
+}
+
+
+def pair_bytes(prob, n_wg, nc):
+    """Algorithmic HBM bytes of one pair-phase launch: each pair reads its
+    previous duals (n floats), writes the new ones (n floats) and reads its
+    multipliers (1 + dim floats); each workgroup writes nc x 64 floats of
+    per-step contribution sums. Geometry and poses are cache-resident."""
+    sc, part, obs, nrow, yoff, tot = workloads.block_layout(prob)
+    N, dim = prob["N"], prob["dim"]
+    return 4.0 * (2 * tot + len(sc) * N * (1 + dim)) + 4.0 * n_wg * nc * 64
+
+
+def time_solves(h, iters, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h.reset()
+        h.iterate(iters)
+        h.scales()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(prob, iters, budget_s=12.0):
+    """The FP64 oracle on the host cores over a bounded sample of the same
+    solve: whole solves (init + iterations) repeated until the budget."""
+    import oracle
+    cores = oracle.set_threads(0)
+    P = oracle.Problem(prob)
+    n = 0
+    pairs = 0
+    t0 = time.perf_counter()
+    while True:
+        st = P.init_state()
+        hist = P.run(st, iters)
+        n += 1
+        pairs += P.n_blocks * prob["N"] * int(hist["iters"].max())
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return dict(value=pairs / el, unit="pair-QP solves/s", cores=int(cores), kind="oracle",
+                sample=f"{n} complete FP64 oracle solve(s) of the same workload "
+                       f"(init + {iters} iterations), {el:.1f} s wall")
+
+
+def batched_vs_plain(cadmm, torch, steps=2, iters=50):
+    """256 scenarios of the 2D batched configuration in one handle vs 256
+    separate handles launched one after another on one stream."""
+    prob = workloads.make("c4")
+    S = len(prob["obs_ptr"]) - 1
+    hb = cadmm.Handle(prob)
+    time_solves(hb, iters, 1, torch)
+    tb = time_solves(hb, iters, steps, torch)
+    _, nb, npairs, _ = cadmm.cadmm_workspace_size(prob)
+    wb = hb.launch_config()
+    hb.close()
+    plain = [cadmm.Handle(workloads.select_scenarios(prob, [s])) for s in range(S)]
+    for h in plain:
+        h.reset(); h.iterate(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for h in plain:
+            h.reset()
+            h.iterate(iters)
+            h.scales()
+    torch.cuda.synchronize()
+    tp = (time.perf_counter() - t0) / steps
+    for h in plain:
+        h.close()
+    solves = npairs * iters
+    return dict(workload=f"{S} 2D scenarios, obstacles U{{10..80}}, faces U{{3..12}}, N=50, {npairs} pair QPs "
+                         f"per iteration, {iters} iterations",
+                batched_pair_solves_per_s=solves / tb, plain_pair_solves_per_s=solves / tp,
+                batched_ms_per_solve=tb * 1e3, plain_ms_per_solve=tp * 1e3, speedup=tp / tb,
+                batched_waves_per_group=wb[0])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2406_07048_amd as cadmm
+
+    wl = WORKLOADS[args.workload]
+    prob = workloads.make(args.workload)
+    iters = wl["iters"]
+    h = cadmm.Handle(prob)
+    W, n_wg = h.launch_config()
+    _, nb, npairs, yf = cadmm.cadmm_workspace_size(prob)
+    for _ in range(args.warmup):
+        h.reset(); h.iterate(iters); h.scales()
+    print(f"[bench] {args.workload}: warmup done, W={W} workgroups={n_wg}", file=sys.stderr, flush=True)
+    sec = time_solves(h, iters, args.steps, torch)
+    code, res = h.solve(0)
+    rp, rd = h.history(iters)
+    it_done = max(r["iters"] for r in res)
+    reached = None
+    for k in range(rp.shape[0]):
+        if rp[k, 0] <= prob["eps_pri"] and rd[k, 0] <= prob["eps_dual"]:
+            reached = k + 1
+            break
+    solves = npairs * it_done
+    # roofline figure of the dominant kernel (pair phase), measured with HIP
+    # events on the handle's stream from the initial iterate
+    h.reset()
+    ph = h.phase_times(20)
+    nq = prob["dim"] + (1 if prob["dim"] == 2 else 3)
+    nc = nq * (nq + 1) // 2 + nq
+    bytes_launch = pair_bytes(prob, n_wg, nc)
+    achieved = bytes_launch / (ph[0] * 1e-3) / 1e9
+    out = {
+        "metric": "pair-QP solves/sec & ADMM iters/sec at res 1e-4 (batched vs plain); backward/forward ratio",
+        "value": solves / sec,
+        "unit": "pair-QP solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {wl['desc']}", "pairs_per_iteration": npairs,
+                   "admm_iterations": it_done, "parallelism": "single GPU"},
+        "admm_iters_per_s": it_done / sec,
+        "residuals": {"r_pri": res[0]["r_pri"], "r_dual": res[0]["r_dual"], "first_iter_at_1e-4": reached,
+                      "converged": res[0]["converged"], "min_alpha": res[0]["min_alpha"], "cost": res[0]["cost"]},
+        "phase_ms": {"pair": ph[0], "trajectory": ph[1], "multiplier": ph[2], "residual": ph[3]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "pair_phase_kernel", "bytes_per_launch": bytes_launch},
+    }
+    h.close()
+    if not args.no_batched:
+        print("[bench] batched vs plain (256 scenarios)", file=sys.stderr, flush=True)
+        out["batched"] = batched_vs_plain(cadmm, torch)
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (FP64 oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(prob, iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

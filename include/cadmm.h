@@ -1,0 +1,243 @@
+/*
+ * cadmm.h -- C ABI of the MI355X (gfx950) ADMM collision-avoidance library.
+ *
+ * Method: "GPU-Accelerated Optimization-Based Collision Avoidance"
+ * (arXiv 2406.07048). Robot = union of convex polytope parts {x : A_i x <= b_i}
+ * posed by the state through R(s), rho(s) (Sec. IV-A); obstacles = union of
+ * polytopes {y : C_j y <= d_j} (Sec. IV-A); collision-free constraint from the
+ * dual of the scale LP (Sec. III-B, eq. poly_colli_free_conts); MPC problem
+ * (Sec. IV-A, eq. MPC_opt_origin) split by ADMM (Sec. IV-B) into
+ *   (1) one small QP per (time step t, part i, obstacle j)  (eq. ADMM_dual_updates,
+ *       in the form of Sec. IV-C eq. const_least_square),
+ *   (2) one trajectory QP with R(s), rho(s) linearised at the current iterate
+ *       (eq. ADMM_state_updates, one SQP step per iteration),
+ *   (3) the scaled-multiplier update (eq. ADMM_residue_updates),
+ * stopped by the sums of squared changes of Sec. IV-B.
+ *
+ * Readings fixed by this library where the paper is silent:
+ *  - The dual-update QP carries a proximal term (eps/2) sum_l D_l (y_l - yhat_l)^2
+ *    with yhat the previous iterate and D_l = ||row_l K||^2, which makes every
+ *    sub-problem solution unique and vanishes at ADMM fixed points.
+ *  - Each robot part i is scaled about its own centre o_i (body frame);
+ *    world pose of part i: y = R(s)(x + o_i) + rho(s). Requires b_i > 0.
+ *  - Collision pairs exist for t = 1..N (x_0 is fixed data); cost
+ *    F = sum_{t=1..N} (x_t - xref_t)^T Q_s (x_t - xref_t) + sum_{t=0..N-1} u_t^T Q_u u_t.
+ *  - Dynamics are given already linearised: x_{t+1} = A x_t + B u_t + c.
+ *  - Initial iterate: obstacle-free LQ trajectory; zeta = xi = 0;
+ *    y = (lam*, mu*, max(alpha* - 1, 0)) from the scale LP.
+ *
+ * Conventions
+ *  - All functions return an int status (CADMM_OK = 0 on success); no
+ *    exception or abort crosses the ABI. cadmm_strerror(code) gives the
+ *    meaning, cadmm_last_error() the detail of the last failure.
+ *  - Device memory always belongs to the caller (workspace and every I/O
+ *    buffer). The library allocates host memory for handles only.
+ *  - Computation is FP32 on the device. Host descriptors are FP64.
+ *  - A handle is bound to one stream and is not thread-safe.
+ *
+ * Canonical pair layout (used by every state buffer below)
+ *  - Pair blocks b enumerate (scenario s, part i, obstacle j) in that nesting
+ *    order (j runs over the scenario's obstacles). Block b holds the N pairs
+ *    t = 1..N and has n_b = n_r,i + n_o,j + 1 dual rows (lambda, mu, gamma).
+ *  - y: block b occupies n_b * N floats starting at y_off(b) =
+ *    N * sum_{b' < b} n_b', row-major [row][t-1].
+ *  - zeta[b*N + t-1]; xi[(b*dim + c)*N + t-1]; alpha[b*N + t-1].
+ *  - x[(s*(N+1) + t)*n_s + k] for t = 0..N; u[(s*N + t)*n_u + k] for t = 0..N-1.
+ */
+#ifndef CADMM_H
+#define CADMM_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CADMM_OK = 0,
+    CADMM_INVALID = 1,        /* bad descriptor: sizes, b_i <= 0, non-finite, zero normal, ... */
+    CADMM_DEVICE = 2,         /* a HIP call failed (detail in cadmm_last_error) */
+    CADMM_WORKSPACE = 3,      /* workspace too small or misaligned */
+    CADMM_NOT_CONVERGED = 4   /* warning from admm_solve: outputs are written */
+};
+
+enum { CADMM_ATT_YAW = 0, CADMM_ATT_EULER_ZYX = 1 };
+
+/* Limits of this build. */
+#define CADMM_MAX_N 64           /* horizon */
+#define CADMM_MAX_NS 16          /* state size */
+#define CADMM_MAX_NU 8           /* input size */
+#define CADMM_MAX_PART_FACES 8   /* faces of one robot part */
+#define CADMM_MAX_OBS_FACES 32   /* faces of one obstacle */
+
+/*
+ * Problem descriptor. Host pointers, read only during collision_admm_setup.
+ *  dim           spatial dimension, 2 (planar, attitude = yaw) or 3 (ZYX Euler)
+ *  n_s, n_u, N   state size, input size, horizon (1..CADMM_MAX_N)
+ *  n_parts, part_face_ptr[n_parts+1], part_A[F_r*dim], part_b[F_r] (> 0),
+ *      part_off[n_parts*dim]        robot parts {x : A_i x <= b_i}, centre o_i
+ *  n_scen, obs_ptr[n_scen+1]        obstacles of scenario s: obs_ptr[s]..obs_ptr[s+1]-1
+ *  obs_face_ptr[M+1], obs_C[F_o*dim], obs_d[F_o]   obstacles {y : C_j y <= d_j}
+ *  A_dyn[n_s*n_s], B_dyn[n_s*n_u], c_dyn[n_s]      time-invariant linear model
+ *  pos_idx[dim], att_idx[1|3], att_kind            state indices of rho(s) and attitude
+ *  Q_s[n_s*n_s], Q_u[n_u*n_u] (symmetric), x_ref[n_scen*(N+1)*n_s], x0[n_scen*n_s]
+ *  sigma (ADMM penalty), eps_prox (proximal weight), eps_pri, eps_dual (stop test)
+ *  max_sweeps     Newton sweep budget of each pair QP (0 = default 24)
+ *  waves_per_group  waves per workgroup of the pair kernels (0 = autotune, else 1..8)
+ */
+typedef struct cadmm_desc {
+    int dim, n_s, n_u, N;
+    int n_parts;
+    const int* part_face_ptr;
+    const double* part_A;
+    const double* part_b;
+    const double* part_off;
+    int n_scen;
+    const int* obs_ptr;
+    const int* obs_face_ptr;
+    const double* obs_C;
+    const double* obs_d;
+    const double* A_dyn;
+    const double* B_dyn;
+    const double* c_dyn;
+    const int* pos_idx;
+    const int* att_idx;
+    int att_kind;
+    const double* Q_s;
+    const double* Q_u;
+    const double* x_ref;
+    const double* x0;
+    double sigma, eps_prox, eps_pri, eps_dual;
+    int max_sweeps;
+    int waves_per_group;
+} cadmm_desc;
+
+typedef struct cadmm_handle cadmm_handle;
+
+/* Per-scenario outcome of admm_solve (host struct, one per scenario). */
+typedef struct cadmm_result {
+    int iters;                 /* iterations this scenario ran */
+    int converged;             /* 1 if the stopping test of Sec. IV-B held */
+    float r_pri, r_dual;       /* last sums of squared multiplier / dual changes */
+    float cost;                /* tracking cost F of the final trajectory */
+    float min_alpha;           /* min scale alpha* over the scenario's pairs at the final trajectory */
+    int unconverged_pairs;     /* pair QPs that hit the sweep budget in the last iteration */
+} cadmm_result;
+
+/* Size info of a descriptor: bytes of device workspace, number of pair
+ * blocks, number of pairs, and floats of y (canonical layout). Any output
+ * pointer may be NULL. Validates the descriptor (CADMM_INVALID). */
+int cadmm_workspace_size(const cadmm_desc* desc, size_t* bytes, int* n_blocks,
+                         long long* n_pairs, long long* y_floats);
+
+/* Validates desc, uploads it into the caller's device workspace d_ws
+ * (bytes >= cadmm_workspace_size, 256-byte aligned), builds the work lists,
+ * captures the iteration as a HIP graph and initialises the iterate (obstacle-
+ * free LQ trajectory, scale-LP certificates, zero multipliers) on stream.
+ * On success *out receives a handle owned by the caller (free with
+ * collision_admm_destroy). The workspace must outlive the handle. */
+int collision_admm_setup(const cadmm_desc* desc, void* d_ws, size_t bytes,
+                         hipStream_t stream, cadmm_handle** out);
+
+/* Enqueue n_iters ADMM iterations (Sec. IV-B: pair QPs, trajectory QP,
+ * multiplier update, residuals) on the handle's stream. No host sync.
+ * Scenarios whose stopping test has held are left unchanged. */
+int admm_iterate(cadmm_handle* h, int n_iters);
+
+/* Iterate until every scenario met the stopping test or max_iters
+ * iterations; reads the device convergence flags every check_every
+ * iterations (the only device-to-host syncs). Fills out[n_scen] and returns
+ * CADMM_OK, or CADMM_NOT_CONVERGED (outputs still written). */
+int admm_solve(cadmm_handle* h, int max_iters, int check_every, cadmm_result* out);
+
+/* Reset the iterate to the initial one of setup (same device work as setup). */
+int admm_reset(cadmm_handle* h);
+
+/* Copy the iterate out of (get) or into (set) caller-owned DEVICE buffers in
+ * the canonical layout; any pointer may be NULL to skip that part. Enqueued on
+ * the handle's stream. set also clears the per-scenario stop flags. */
+int admm_get_state(cadmm_handle* h, float* x, float* u, float* y, float* zeta, float* xi);
+int admm_set_state(cadmm_handle* h, const float* x, const float* u, const float* y,
+                   const float* zeta, const float* xi);
+
+/* Residual history: host buffers of max_iters*n_scen floats receive r_pri and
+ * r_dual per iteration (row k, column s; NaN where a scenario had stopped).
+ * Returns the number of rows written. Syncs the stream. */
+int admm_get_history(cadmm_handle* h, int max_rows, float* r_pri, float* r_dual);
+
+/* Scale alpha* of every pair at the current trajectory (Sec. III-A eq.
+ * scale_opt), written to a caller DEVICE buffer alpha[n_pairs] (canonical). */
+int admm_scales(cadmm_handle* h, float* alpha);
+
+/* Profiling: run n_iters iterations with eager (non-graph) launches and
+ * HIP events around each phase on the handle's stream; ms_out[4] receives
+ * the mean milliseconds of (pair QPs + contributions, trajectory QP,
+ * multiplier update, residual test). Advances the iterate. Syncs. */
+int admm_phase_times(cadmm_handle* h, int n_iters, float* ms_out);
+
+/* Launch shape chosen at setup (autotuned unless fixed in the descriptor):
+ * waves (pair blocks) per workgroup and number of workgroups. */
+int admm_launch_config(cadmm_handle* h, int* waves_per_group, int* n_workgroups);
+
+void collision_admm_destroy(cadmm_handle* h);
+
+/*
+ * Stateless batch of dual-update QPs (Sec. IV-C eq. const_least_square with
+ * the proximal term): for each pair p with rows l in row_ptr[p]..row_ptr[p+1]-1
+ *     min_y 1/2 ||K^T y + bhat||^2 + eps/2 sum_l ||K_l||^2 (y_l - yhat_l)^2
+ *     s.t.  kappa^T y = 1,  y >= 0.
+ * All pointers are DEVICE pointers, caller-owned:
+ *   row_ptr[n_pairs+1] (int), K[rows*(dim+1)] row-major, kappa[rows] (>= 0, at
+ *   least one > 0 per pair), yhat[rows], bhat[n_pairs*(dim+1)]
+ *   outputs y[rows], r[n_pairs*(dim+1)] = K^T y + bhat, status[n_pairs]
+ *   (sweeps used, negative if the sweep budget ran out).
+ * A pair may hold at most CADMM_MAX_PART_FACES + CADMM_MAX_OBS_FACES + 1 rows.
+ */
+typedef struct cadmm_pair_batch {
+    int n_pairs, dim;
+    const int* row_ptr;
+    const float* K;
+    const float* kappa;
+    const float* yhat;
+    const float* bhat;
+    float eps;
+    int max_sweeps;
+    float* y;
+    float* r;
+    int* status;
+} cadmm_pair_batch;
+
+int pair_qp_batch(const cadmm_pair_batch* b, hipStream_t stream);
+
+/*
+ * Stateless batch of scale LPs (Sec. III-A eq. scale_opt and its dual Sec.
+ * III-B eq. scale_opt_dual) in the robot part's frame:
+ *     alpha* = min alpha  s.t.  A x <= alpha b,  Cp x <= dp.
+ * DEVICE pointers: a_ptr[n_pairs+1], A[ra*dim], b[ra] (> 0);
+ *   o_ptr[n_pairs+1], Cp[ro*dim], dp[ro]; outputs alpha[n_pairs],
+ *   lam[ra], mu[ro] (the dual certificate), status[n_pairs] (0 ok).
+ */
+typedef struct cadmm_scale_batch {
+    int n_pairs, dim;
+    const int* a_ptr;
+    const float* A;
+    const float* b;
+    const int* o_ptr;
+    const float* Cp;
+    const float* dp;
+    float* alpha;
+    float* lam;
+    float* mu;
+    int* status;
+} cadmm_scale_batch;
+
+int pair_scale_batch(const cadmm_scale_batch* b, hipStream_t stream);
+
+const char* cadmm_strerror(int code);
+const char* cadmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CADMM_H */

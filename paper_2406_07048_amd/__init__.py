@@ -1,0 +1,325 @@
+"""MI355X (gfx950) ADMM collision avoidance for polyhedral robots and obstacles.
+
+Thin Python binding of the C ABI in ``include/cadmm.h`` (method of
+"GPU-Accelerated Optimization-Based Collision Avoidance", arXiv 2406.07048).
+Every step of the path runs in the HIP kernels of ``_libcadmm.so``; this module
+only marshals arguments. PyTorch provides device memory (the caller-owned
+workspace and I/O tensors) and the current HIP stream. There is no CPU
+fallback: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_libcadmm.so")
+_lib = None
+
+CADMM_OK, CADMM_INVALID, CADMM_DEVICE, CADMM_WORKSPACE, CADMM_NOT_CONVERGED = 0, 1, 2, 3, 4
+
+_ip = ctypes.POINTER(ctypes.c_int)
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class CadmmDesc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n_s", ctypes.c_int), ("n_u", ctypes.c_int), ("N", ctypes.c_int),
+        ("n_parts", ctypes.c_int),
+        ("part_face_ptr", _ip), ("part_A", _dp), ("part_b", _dp), ("part_off", _dp),
+        ("n_scen", ctypes.c_int),
+        ("obs_ptr", _ip), ("obs_face_ptr", _ip), ("obs_C", _dp), ("obs_d", _dp),
+        ("A_dyn", _dp), ("B_dyn", _dp), ("c_dyn", _dp),
+        ("pos_idx", _ip), ("att_idx", _ip), ("att_kind", ctypes.c_int),
+        ("Q_s", _dp), ("Q_u", _dp), ("x_ref", _dp), ("x0", _dp),
+        ("sigma", ctypes.c_double), ("eps_prox", ctypes.c_double),
+        ("eps_pri", ctypes.c_double), ("eps_dual", ctypes.c_double),
+        ("max_sweeps", ctypes.c_int), ("waves_per_group", ctypes.c_int),
+    ]
+
+
+class CadmmResult(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int), ("converged", ctypes.c_int),
+        ("r_pri", ctypes.c_float), ("r_dual", ctypes.c_float),
+        ("cost", ctypes.c_float), ("min_alpha", ctypes.c_float),
+        ("unconverged_pairs", ctypes.c_int),
+    ]
+
+
+class CadmmPairBatch(ctypes.Structure):
+    _fields_ = [
+        ("n_pairs", ctypes.c_int), ("dim", ctypes.c_int),
+        ("row_ptr", _vp), ("K", _vp), ("kappa", _vp), ("yhat", _vp), ("bhat", _vp),
+        ("eps", ctypes.c_float), ("max_sweeps", ctypes.c_int),
+        ("y", _vp), ("r", _vp), ("status", _vp),
+    ]
+
+
+class CadmmScaleBatch(ctypes.Structure):
+    _fields_ = [
+        ("n_pairs", ctypes.c_int), ("dim", ctypes.c_int),
+        ("a_ptr", _vp), ("A", _vp), ("b", _vp), ("o_ptr", _vp), ("Cp", _vp), ("dp", _vp),
+        ("alpha", _vp), ("lam", _vp), ("mu", _vp), ("status", _vp),
+    ]
+
+
+# every symbol the header declares, with its ctypes signature
+_SIGNATURES = {
+    "cadmm_workspace_size": (ctypes.c_int, [ctypes.POINTER(CadmmDesc), ctypes.POINTER(ctypes.c_size_t), _ip,
+                                            ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]),
+    "collision_admm_setup": (ctypes.c_int, [ctypes.POINTER(CadmmDesc), _vp, ctypes.c_size_t, _vp,
+                                            ctypes.POINTER(_vp)]),
+    "admm_iterate": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "admm_solve": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(CadmmResult)]),
+    "admm_reset": (ctypes.c_int, [_vp]),
+    "admm_get_state": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "admm_set_state": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "admm_get_history": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
+    "admm_scales": (ctypes.c_int, [_vp, _vp]),
+    "admm_phase_times": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
+    "admm_launch_config": (ctypes.c_int, [_vp, _ip, _ip]),
+    "collision_admm_destroy": (None, [_vp]),
+    "pair_qp_batch": (ctypes.c_int, [ctypes.POINTER(CadmmPairBatch), _vp]),
+    "pair_scale_batch": (ctypes.c_int, [ctypes.POINTER(CadmmScaleBatch), _vp]),
+    "cadmm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "cadmm_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library missing: {LIB_PATH} (build it with __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class CadmmError(RuntimeError):
+    def __init__(self, code, where):
+        L = lib()
+        super().__init__(f"{where}: {L.cadmm_strerror(code).decode()} ({L.cadmm_last_error().decode()})")
+        self.code = code
+
+
+def _check(code, where, allow=(CADMM_OK,)):
+    if code not in allow:
+        raise CadmmError(code, where)
+    return code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(st.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class _DescHolder:
+    """Contiguous host copies backing a CadmmDesc for the duration of a call."""
+
+    def __init__(self, prob, max_sweeps=0, waves_per_group=0):
+        keep = {}
+
+        def dbl(name):
+            a = np.ascontiguousarray(prob[name], dtype=np.float64)
+            keep[name] = a
+            return a.ctypes.data_as(_dp)
+
+        def i32(name):
+            a = np.ascontiguousarray(prob[name], dtype=np.int32)
+            keep[name] = a
+            return a.ctypes.data_as(_ip)
+
+        d = CadmmDesc()
+        d.dim, d.n_s, d.n_u, d.N = int(prob["dim"]), int(prob["n_s"]), int(prob["n_u"]), int(prob["N"])
+        d.n_parts = len(prob["part_face_ptr"]) - 1
+        d.part_face_ptr = i32("part_face_ptr")
+        d.part_A, d.part_b, d.part_off = dbl("part_A"), dbl("part_b"), dbl("part_off")
+        d.n_scen = len(prob["obs_ptr"]) - 1
+        d.obs_ptr, d.obs_face_ptr = i32("obs_ptr"), i32("obs_face_ptr")
+        d.obs_C, d.obs_d = dbl("obs_C"), dbl("obs_d")
+        d.A_dyn, d.B_dyn, d.c_dyn = dbl("A_dyn"), dbl("B_dyn"), dbl("c_dyn")
+        d.pos_idx, d.att_idx = i32("pos_idx"), i32("att_idx")
+        d.att_kind = int(prob["att_kind"])
+        d.Q_s, d.Q_u, d.x_ref, d.x0 = dbl("Q_s"), dbl("Q_u"), dbl("x_ref"), dbl("x0")
+        d.sigma, d.eps_prox = float(prob["sigma"]), float(prob["eps_prox"])
+        d.eps_pri, d.eps_dual = float(prob["eps_pri"]), float(prob["eps_dual"])
+        d.max_sweeps, d.waves_per_group = int(max_sweeps), int(waves_per_group)
+        self.desc = d
+        self.keep = keep
+
+
+def cadmm_workspace_size(prob):
+    """(bytes, n_blocks, n_pairs, y_floats) of a problem; validates it."""
+    h = _DescHolder(prob)
+    nbytes = ctypes.c_size_t()
+    nb = ctypes.c_int()
+    npairs = ctypes.c_longlong()
+    nyf = ctypes.c_longlong()
+    _check(lib().cadmm_workspace_size(ctypes.byref(h.desc), ctypes.byref(nbytes), ctypes.byref(nb),
+                                      ctypes.byref(npairs), ctypes.byref(nyf)), "cadmm_workspace_size")
+    return nbytes.value, nb.value, npairs.value, nyf.value
+
+
+class Handle:
+    """A problem set up on the device (collision_admm_setup) with its workspace."""
+
+    def __init__(self, prob, device="cuda", stream=None, max_sweeps=0, waves_per_group=0):
+        torch = _torch()
+        self.prob = prob
+        holder = _DescHolder(prob, max_sweeps, waves_per_group)
+        nbytes, self.n_blocks, self.n_pairs, self.y_floats = cadmm_workspace_size(prob)
+        self.n_scen = len(prob["obs_ptr"]) - 1
+        self.dim, self.N = int(prob["dim"]), int(prob["N"])
+        self.n_s, self.n_u = int(prob["n_s"]), int(prob["n_u"])
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib().collision_admm_setup(ctypes.byref(holder.desc), ctypes.c_void_p(self._ws_ptr),
+                                          nbytes, _stream_ptr(self.stream), ctypes.byref(h)),
+               "collision_admm_setup")
+        self._h = h
+
+    # -- iteration ------------------------------------------------------
+    def iterate(self, n_iters):
+        _check(lib().admm_iterate(self._h, int(n_iters)), "admm_iterate")
+
+    def solve(self, max_iters, check_every=8):
+        res = (CadmmResult * self.n_scen)()
+        code = lib().admm_solve(self._h, int(max_iters), int(check_every), res)
+        _check(code, "admm_solve", allow=(CADMM_OK, CADMM_NOT_CONVERGED))
+        return code, [dict(iters=r.iters, converged=bool(r.converged), r_pri=r.r_pri, r_dual=r.r_dual,
+                           cost=r.cost, min_alpha=r.min_alpha, unconverged_pairs=r.unconverged_pairs)
+                      for r in res]
+
+    def reset(self):
+        _check(lib().admm_reset(self._h), "admm_reset")
+
+    # -- state ----------------------------------------------------------
+    def _state_tensors(self):
+        torch = _torch()
+        f = dict(dtype=torch.float32, device=self.device)
+        return dict(x=torch.empty(self.n_scen, self.N + 1, self.n_s, **f),
+                    u=torch.empty(self.n_scen, self.N, self.n_u, **f),
+                    y=torch.empty(self.y_floats, **f),
+                    zeta=torch.empty(self.n_pairs, **f),
+                    xi=torch.empty(self.n_pairs * self.dim, **f))
+
+    def get_state(self):
+        st = self._state_tensors()
+        _check(lib().admm_get_state(self._h, _ptr(st["x"]), _ptr(st["u"]), _ptr(st["y"]),
+                                    _ptr(st["zeta"]), _ptr(st["xi"])), "admm_get_state")
+        return st
+
+    def set_state(self, x=None, u=None, y=None, zeta=None, xi=None):
+        torch = _torch()
+
+        def prep(t, n):
+            if t is None:
+                return None
+            t = torch.as_tensor(t, dtype=torch.float32, device=self.device).contiguous()
+            if t.numel() != n:
+                raise ValueError(f"state part has {t.numel()} floats, expected {n}")
+            return t
+        parts = [prep(x, self.n_scen * (self.N + 1) * self.n_s), prep(u, self.n_scen * self.N * self.n_u),
+                 prep(y, self.y_floats), prep(zeta, self.n_pairs), prep(xi, self.n_pairs * self.dim)]
+        _check(lib().admm_set_state(self._h, *[_ptr(p) for p in parts]), "admm_set_state")
+        self._keep_set = parts   # keep alive until the stream has consumed them
+        return parts
+
+    def history(self, max_rows):
+        rp = np.zeros((max_rows, self.n_scen), np.float32)
+        rd = np.zeros((max_rows, self.n_scen), np.float32)
+        rows = lib().admm_get_history(self._h, int(max_rows), rp.ctypes.data_as(_vp), rd.ctypes.data_as(_vp))
+        if rows < 0:
+            raise CadmmError(-rows, "admm_get_history")
+        return rp[:rows], rd[:rows]
+
+    def scales(self):
+        torch = _torch()
+        a = torch.empty(self.n_pairs, dtype=torch.float32, device=self.device)
+        _check(lib().admm_scales(self._h, _ptr(a)), "admm_scales")
+        return a
+
+    def phase_times(self, n_iters):
+        """Mean ms of (pair, trajectory, multiplier, residual) phases over
+        n_iters eagerly launched iterations (advances the iterate)."""
+        out = (ctypes.c_float * 4)()
+        _check(lib().admm_phase_times(self._h, int(n_iters), out), "admm_phase_times")
+        return list(out)
+
+    def launch_config(self):
+        w, g = ctypes.c_int(), ctypes.c_int()
+        _check(lib().admm_launch_config(self._h, ctypes.byref(w), ctypes.byref(g)), "admm_launch_config")
+        return w.value, g.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().collision_admm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def collision_admm_setup(prob, **kw):
+    return Handle(prob, **kw)
+
+
+def pair_qp_batch(row_ptr, K, kappa, yhat, bhat, eps, max_sweeps=0, stream=None):
+    """Stateless batch of proximal dual-update QPs (device tensors in, out).
+
+    row_ptr int32 [P+1]; K float32 [rows, dim+1]; kappa, yhat [rows];
+    bhat [P, dim+1]. Returns (y [rows], r [P, dim+1], status int32 [P])."""
+    torch = _torch()
+    n_pairs = row_ptr.numel() - 1
+    dim = K.shape[1] - 1
+    y = torch.empty_like(yhat)
+    r = torch.empty_like(bhat)
+    status = torch.empty(n_pairs, dtype=torch.int32, device=K.device)
+    b = CadmmPairBatch(n_pairs, dim, _ptr(row_ptr), _ptr(K), _ptr(kappa), _ptr(yhat), _ptr(bhat),
+                       float(eps), int(max_sweeps), _ptr(y), _ptr(r), _ptr(status))
+    _check(lib().pair_qp_batch(ctypes.byref(b), _stream_ptr(stream)), "pair_qp_batch")
+    return y, r, status
+
+
+def pair_scale_batch(a_ptr, A, b, o_ptr, Cp, dp, stream=None):
+    """Stateless batch of scale LPs in the part frame (device tensors).
+
+    Returns (alpha [P], lam [rows of A], mu [rows of Cp], status [P])."""
+    torch = _torch()
+    n_pairs = a_ptr.numel() - 1
+    dim = A.shape[1]
+    alpha = torch.empty(n_pairs, dtype=torch.float32, device=A.device)
+    lam = torch.empty(A.shape[0], dtype=torch.float32, device=A.device)
+    mu = torch.empty(Cp.shape[0], dtype=torch.float32, device=A.device)
+    status = torch.empty(n_pairs, dtype=torch.int32, device=A.device)
+    sb = CadmmScaleBatch(n_pairs, dim, _ptr(a_ptr), _ptr(A), _ptr(b), _ptr(o_ptr), _ptr(Cp), _ptr(dp),
+                         _ptr(alpha), _ptr(lam), _ptr(mu), _ptr(status))
+    _check(lib().pair_scale_batch(ctypes.byref(sb), _stream_ptr(stream)), "pair_scale_batch")
+    return alpha, lam, mu, status

@@ -1,0 +1,699 @@
+// Host side of the C ABI declared in include/cadmm.h: descriptor validation,
+// workspace planning inside caller-owned device memory, work lists, HIP-graph
+// capture of one ADMM iteration, launch-shape autotuning and result readout.
+#include "cadmm.h"
+#include "cadmm_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace cadmm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(CADMM_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr int kHistCap = 4096;
+constexpr int kGraphBlock = 8;    // iterations per captured multi-iteration graph
+
+struct Layout {
+    // sizes
+    int dim, n_s, n_u, N, n_parts, n_scen, M, Fr, Fo, n_blocks;
+    long long n_pairs, y_floats;
+    int nc, nq, n_att, max_pf, max_of;
+    // byte offsets into the workspace
+    size_t part_faces, part_face_ptr, part_off, obs_faces, obs_face_ptr, blocks, block_yoff, wg_items, scen_wg;
+    size_t A_dyn, B_dyn, c_dyn, Q_s, Q_u, x_ref, x0;
+    size_t x, u, y, zeta, xi, y_snap;
+    size_t contrib, rdual_part, rpri_part, unconv_part;
+    size_t r_pri, r_dual, done, iters, unconv, hist_pri, hist_dual, Kgain, alpha, cost, min_alpha;
+    size_t total;
+};
+
+size_t take(size_t& off, size_t bytes)
+{
+    off = (off + 255) & ~size_t(255);
+    size_t r = off;
+    off += bytes;
+    return r;
+}
+
+bool finite_all(const double* p, long long n)
+{
+    if (n > 0 && !p) return false;
+    for (long long i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+int validate_and_plan(const cadmm_desc* d, Layout& L)
+{
+    if (!d) return fail(CADMM_INVALID, "descriptor is NULL");
+    if (d->dim != 2 && d->dim != 3) return fail(CADMM_INVALID, "dim must be 2 or 3");
+    if (d->n_s < 1 || d->n_s > CADMM_MAX_NS) return fail(CADMM_INVALID, "n_s out of range");
+    if (d->n_u < 1 || d->n_u > CADMM_MAX_NU) return fail(CADMM_INVALID, "n_u out of range");
+    if (d->N < 1 || d->N > CADMM_MAX_N) return fail(CADMM_INVALID, "horizon N out of range (1..64)");
+    if (d->n_parts < 1 || d->n_scen < 1) return fail(CADMM_INVALID, "need >= 1 robot part and scenario");
+    if (!d->part_face_ptr || !d->obs_ptr || !d->obs_face_ptr || !d->pos_idx || !d->att_idx)
+        return fail(CADMM_INVALID, "NULL index array");
+    const int dim = d->dim;
+    const int want_att = dim == 2 ? CADMM_ATT_YAW : CADMM_ATT_EULER_ZYX;
+    if (d->att_kind != want_att) return fail(CADMM_INVALID, "att_kind must be YAW for dim 2 and EULER_ZYX for dim 3");
+    const int n_att = dim == 2 ? 1 : 3;
+    for (int r = 0; r < dim; ++r)
+        if (d->pos_idx[r] < 0 || d->pos_idx[r] >= d->n_s) return fail(CADMM_INVALID, "pos_idx out of range");
+    for (int a = 0; a < n_att; ++a)
+        if (d->att_idx[a] < 0 || d->att_idx[a] >= d->n_s) return fail(CADMM_INVALID, "att_idx out of range");
+    if (d->part_face_ptr[0] != 0) return fail(CADMM_INVALID, "part_face_ptr[0] != 0");
+    int max_pf = 0;
+    for (int i = 0; i < d->n_parts; ++i) {
+        const int nf = d->part_face_ptr[i + 1] - d->part_face_ptr[i];
+        if (nf < dim + 1 || nf > CADMM_MAX_PART_FACES) return fail(CADMM_INVALID, "faces per robot part out of range");
+        max_pf = std::max(max_pf, nf);
+    }
+    const int Fr = d->part_face_ptr[d->n_parts];
+    if (!finite_all(d->part_A, (long long)Fr * dim) || !finite_all(d->part_b, Fr) ||
+        !finite_all(d->part_off, (long long)d->n_parts * dim))
+        return fail(CADMM_INVALID, "non-finite robot geometry");
+    for (int k = 0; k < Fr; ++k) {
+        if (!(d->part_b[k] > 0.0)) return fail(CADMM_INVALID, "robot offsets b_i must be > 0 (centre inside the part)");
+        double nn = 0;
+        for (int r = 0; r < dim; ++r) nn += d->part_A[k * dim + r] * d->part_A[k * dim + r];
+        if (!(nn > 0.0)) return fail(CADMM_INVALID, "zero-norm robot face");
+    }
+    if (d->obs_ptr[0] != 0) return fail(CADMM_INVALID, "obs_ptr[0] != 0");
+    for (int s = 0; s < d->n_scen; ++s)
+        if (d->obs_ptr[s + 1] < d->obs_ptr[s]) return fail(CADMM_INVALID, "obs_ptr not monotone");
+    const int M = d->obs_ptr[d->n_scen];
+    if (d->obs_face_ptr[0] != 0) return fail(CADMM_INVALID, "obs_face_ptr[0] != 0");
+    int max_of = 0;
+    for (int j = 0; j < M; ++j) {
+        const int nf = d->obs_face_ptr[j + 1] - d->obs_face_ptr[j];
+        if (nf < dim + 1 || nf > CADMM_MAX_OBS_FACES) return fail(CADMM_INVALID, "faces per obstacle out of range");
+        max_of = std::max(max_of, nf);
+    }
+    const int Fo = M > 0 ? d->obs_face_ptr[M] : 0;
+    if (!finite_all(d->obs_C, (long long)Fo * dim) || !finite_all(d->obs_d, Fo))
+        return fail(CADMM_INVALID, "non-finite obstacle geometry");
+    for (int k = 0; k < Fo; ++k) {
+        double nn = 0;
+        for (int r = 0; r < dim; ++r) nn += d->obs_C[k * dim + r] * d->obs_C[k * dim + r];
+        if (!(nn > 0.0)) return fail(CADMM_INVALID, "zero-norm obstacle face");
+    }
+    const int ns = d->n_s, nu = d->n_u, N = d->N;
+    if (!finite_all(d->A_dyn, (long long)ns * ns) || !finite_all(d->B_dyn, (long long)ns * nu) ||
+        !finite_all(d->c_dyn, ns) || !finite_all(d->Q_s, (long long)ns * ns) || !finite_all(d->Q_u, (long long)nu * nu) ||
+        !finite_all(d->x_ref, (long long)d->n_scen * (N + 1) * ns) || !finite_all(d->x0, (long long)d->n_scen * ns))
+        return fail(CADMM_INVALID, "non-finite model, cost or reference");
+    if (!(d->sigma > 0) || !(d->eps_prox > 0) || !(d->eps_pri >= 0) || !(d->eps_dual >= 0))
+        return fail(CADMM_INVALID, "sigma and eps_prox must be > 0, eps_pri/eps_dual >= 0");
+    if (M > 0 && !pair_variant_supported(dim, max_pf, max_of))
+        return fail(CADMM_INVALID, "face counts exceed the compiled kernel variants");
+    if (d->waves_per_group < 0 || d->waves_per_group > kMaxWavesPerGroup)
+        return fail(CADMM_INVALID, "waves_per_group out of range (0..8)");
+    if (d->max_sweeps < 0 || d->max_sweeps > 1000) return fail(CADMM_INVALID, "max_sweeps out of range");
+
+    L.dim = dim; L.n_s = ns; L.n_u = nu; L.N = N; L.n_parts = d->n_parts; L.n_scen = d->n_scen;
+    L.M = M; L.Fr = Fr; L.Fo = Fo; L.n_att = n_att; L.nq = dim + n_att; L.nc = L.nq * (L.nq + 1) / 2 + L.nq;
+    L.max_pf = max_pf; L.max_of = max_of;
+    L.n_blocks = d->n_parts * M;
+    L.n_pairs = (long long)L.n_blocks * N;
+    long long yf = 0;
+    for (int s = 0; s < d->n_scen; ++s)
+        for (int i = 0; i < d->n_parts; ++i)
+            for (int j = d->obs_ptr[s]; j < d->obs_ptr[s + 1]; ++j)
+                yf += (long long)((d->part_face_ptr[i + 1] - d->part_face_ptr[i]) +
+                                  (d->obs_face_ptr[j + 1] - d->obs_face_ptr[j]) + 1) * N;
+    if (yf >= (1LL << 31)) return fail(CADMM_INVALID, "problem too large (dual variables exceed 2^31 floats)");
+    L.y_floats = yf;
+
+    size_t off = 0;
+    const int nb = std::max(L.n_blocks, 1);
+    L.part_faces = take(off, sizeof(float4) * Fr);
+    L.part_face_ptr = take(off, sizeof(int) * (d->n_parts + 1));
+    L.part_off = take(off, sizeof(float) * 3 * d->n_parts);
+    L.obs_faces = take(off, sizeof(float4) * std::max(Fo, 1));
+    L.obs_face_ptr = take(off, sizeof(int) * (M + 1));
+    L.blocks = take(off, sizeof(int4) * nb);
+    L.block_yoff = take(off, sizeof(int) * nb);
+    L.wg_items = take(off, sizeof(int4) * nb);
+    L.scen_wg = take(off, sizeof(int2) * d->n_scen);
+    L.A_dyn = take(off, sizeof(float) * ns * ns);
+    L.B_dyn = take(off, sizeof(float) * ns * nu);
+    L.c_dyn = take(off, sizeof(float) * ns);
+    L.Q_s = take(off, sizeof(float) * ns * ns);
+    L.Q_u = take(off, sizeof(float) * nu * nu);
+    L.x_ref = take(off, sizeof(float) * d->n_scen * (N + 1) * ns);
+    L.x0 = take(off, sizeof(float) * d->n_scen * ns);
+    L.x = take(off, sizeof(float) * d->n_scen * (N + 1) * ns);
+    L.u = take(off, sizeof(float) * d->n_scen * N * nu);
+    L.y = take(off, sizeof(float) * std::max<long long>(yf, 1));
+    L.zeta = take(off, sizeof(float) * std::max<long long>(L.n_pairs, 1));
+    L.xi = take(off, sizeof(float) * std::max<long long>(L.n_pairs * dim, 1));
+    L.y_snap = take(off, sizeof(float) * std::max<long long>(yf, 1));
+    L.contrib = take(off, sizeof(float) * (size_t)nb * L.nc * 64);
+    L.rdual_part = take(off, sizeof(float) * nb);
+    L.rpri_part = take(off, sizeof(float) * nb);
+    L.unconv_part = take(off, sizeof(int) * nb);
+    L.r_pri = take(off, sizeof(float) * d->n_scen);
+    L.r_dual = take(off, sizeof(float) * d->n_scen);
+    L.done = take(off, sizeof(int) * d->n_scen);
+    L.iters = take(off, sizeof(int) * d->n_scen);
+    L.unconv = take(off, sizeof(int) * d->n_scen);
+    L.hist_pri = take(off, sizeof(float) * (size_t)kHistCap * d->n_scen);
+    L.hist_dual = take(off, sizeof(float) * (size_t)kHistCap * d->n_scen);
+    L.Kgain = take(off, sizeof(float) * (size_t)d->n_scen * N * nu * (ns + 1));
+    L.alpha = take(off, sizeof(float) * std::max<long long>(L.n_pairs, 1));
+    L.cost = take(off, sizeof(float) * d->n_scen);
+    L.min_alpha = take(off, sizeof(float) * d->n_scen);
+    L.total = (off + 255) & ~size_t(255);
+    return CADMM_OK;
+}
+
+}  // namespace
+
+struct cadmm_handle {
+    Layout L;
+    DevProblem P;
+    char* ws;
+    hipStream_t stream;
+    hipStream_t cap;             // private stream used only for graph capture
+    hipGraphExec_t g1, gK;       // 1-iteration and kGraphBlock-iteration graphs
+    int W, grid;
+    std::vector<int> obs_ptr;    // host copy (scenario -> obstacles)
+    std::vector<int4> blocks;    // host copy
+};
+
+namespace {
+
+template <class T>
+T* at(cadmm_handle* h, size_t off) { return reinterpret_cast<T*>(h->ws + off); }
+
+// work lists for W waves (= pair blocks) per workgroup; workgroups never
+// straddle scenarios so per-step sums stay per scenario.
+void build_worklists(const Layout& L, const std::vector<int>& obs_ptr, int W, std::vector<int4>& items,
+                     std::vector<int2>& scen_wg)
+{
+    items.clear();
+    scen_wg.assign(L.n_scen, int2{0, 0});
+    int b = 0;
+    for (int s = 0; s < L.n_scen; ++s) {
+        const int nb_s = L.n_parts * (obs_ptr[s + 1] - obs_ptr[s]);
+        scen_wg[s].x = (int)items.size();
+        int k = 0;
+        for (int b0 = 0; b0 < nb_s; b0 += W, ++k) items.push_back(int4{s, b + b0, b + std::min(nb_s, b0 + W), k});
+        scen_wg[s].y = (int)items.size();
+        b += nb_s;
+    }
+}
+
+int upload_worklists(cadmm_handle* h, int W)
+{
+    std::vector<int4> items;
+    std::vector<int2> sw;
+    build_worklists(h->L, h->obs_ptr, W, items, sw);
+    if (!items.empty())
+        HIP_TRY(hipMemcpyAsync(h->ws + h->L.wg_items, items.data(), sizeof(int4) * items.size(),
+                               hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->ws + h->L.scen_wg, sw.data(), sizeof(int2) * sw.size(), hipMemcpyHostToDevice,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->W = W;
+    h->P.n_wg = (int)items.size();
+    h->grid = std::max(1, h->P.n_wg);
+    return CADMM_OK;
+}
+
+// one ADMM iteration: (1) pair QPs + contributions, (2) trajectory QP,
+// (3) multiplier update, residual sums and stopping test
+int enqueue_iteration(cadmm_handle* h, hipStream_t st)
+{
+    if (h->L.n_blocks > 0) HIP_TRY(launch_pair_phase(h->P, h->W, h->grid, st));
+    HIP_TRY(launch_traj_phase(h->P, h->L.n_blocks == 0 ? 1 : 0, st));
+    if (h->L.n_blocks > 0) HIP_TRY(launch_mult_phase(h->P, h->W, h->grid, st));
+    HIP_TRY(launch_residual(h->P, st));
+    return CADMM_OK;
+}
+
+int capture(cadmm_handle* h, int iters, hipGraphExec_t* out)
+{
+    hipGraph_t g;
+    HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    int rc = CADMM_OK;
+    for (int i = 0; i < iters && rc == CADMM_OK; ++i) rc = enqueue_iteration(h, h->cap);
+    hipError_t e = hipStreamEndCapture(h->cap, &g);
+    if (rc != CADMM_OK) return rc;
+    if (e != hipSuccess) return fail(CADMM_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(CADMM_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return CADMM_OK;
+}
+
+void drop_graphs(cadmm_handle* h)
+{
+    if (h->g1) (void)hipGraphExecDestroy(h->g1);
+    if (h->gK) (void)hipGraphExecDestroy(h->gK);
+    h->g1 = h->gK = nullptr;
+}
+
+int recapture(cadmm_handle* h)
+{
+    drop_graphs(h);
+    int rc = capture(h, 1, &h->g1);
+    if (rc) return rc;
+    return capture(h, kGraphBlock, &h->gK);
+}
+
+// initial iterate (see collision_admm_setup)
+int init_iterate(cadmm_handle* h)
+{
+    const Layout& L = h->L;
+    hipStream_t st = h->stream;
+    HIP_TRY(launch_fill(at<float>(h, L.zeta), L.n_pairs, 0.f, st));
+    HIP_TRY(launch_fill(at<float>(h, L.xi), L.n_pairs * L.dim, 0.f, st));
+    HIP_TRY(launch_fill_int(at<int>(h, L.done), L.n_scen, 0, st));
+    HIP_TRY(launch_fill_int(at<int>(h, L.iters), L.n_scen, 0, st));
+    HIP_TRY(launch_fill_int(at<int>(h, L.unconv), L.n_scen, 0, st));
+    HIP_TRY(launch_fill(at<float>(h, L.r_pri), L.n_scen, NAN, st));
+    HIP_TRY(launch_fill(at<float>(h, L.r_dual), L.n_scen, NAN, st));
+    HIP_TRY(launch_fill(at<float>(h, L.hist_pri), (long long)kHistCap * L.n_scen, NAN, st));
+    HIP_TRY(launch_fill(at<float>(h, L.hist_dual), (long long)kHistCap * L.n_scen, NAN, st));
+    HIP_TRY(launch_traj_phase(h->P, 1, st));
+    if (L.n_blocks > 0) HIP_TRY(launch_init_pairs(h->P, nullptr, 1, st));
+    return CADMM_OK;
+}
+
+// choose waves per workgroup by timing the pair kernel from the same iterate
+int autotune(cadmm_handle* h)
+{
+    const Layout& L = h->L;
+    if (L.n_blocks == 0) return upload_worklists(h, 1);
+    hipStream_t st = h->stream;
+    HIP_TRY(hipMemcpyAsync(h->ws + L.y_snap, h->ws + L.y, sizeof(float) * L.y_floats, hipMemcpyDeviceToDevice, st));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int cands[] = {1, 2, 4, 8};
+    float best = 1e30f;
+    int bestW = 4;
+    for (int W : cands) {
+        if (W > 1 && (W / 2) * 1 >= L.n_blocks) break;
+        int rc = upload_worklists(h, W);
+        if (rc) return rc;
+        float tot = 0.f;
+        for (int rep = 0; rep < 4; ++rep) {
+            HIP_TRY(hipMemcpyAsync(h->ws + L.y, h->ws + L.y_snap, sizeof(float) * L.y_floats, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipEventRecord(e0, st));
+            HIP_TRY(launch_pair_phase(h->P, h->W, h->grid, st));
+            HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) tot += ms;   // first run warms caches and code
+        }
+        if (tot < best) { best = tot; bestW = W; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_TRY(hipMemcpyAsync(h->ws + L.y, h->ws + L.y_snap, sizeof(float) * L.y_floats, hipMemcpyDeviceToDevice, st));
+    return upload_worklists(h, bestW);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cadmm_strerror(int code)
+{
+    switch (code) {
+    case CADMM_OK: return "ok";
+    case CADMM_INVALID: return "invalid descriptor or argument";
+    case CADMM_DEVICE: return "HIP device error";
+    case CADMM_WORKSPACE: return "workspace too small or misaligned";
+    case CADMM_NOT_CONVERGED: return "stopping test not met within the iteration budget (outputs written)";
+    default: return "unknown status";
+    }
+}
+
+const char* cadmm_last_error(void) { return g_last_error.c_str(); }
+
+int cadmm_workspace_size(const cadmm_desc* desc, size_t* bytes, int* n_blocks, long long* n_pairs,
+                         long long* y_floats)
+{
+    Layout L;
+    int rc = validate_and_plan(desc, L);
+    if (rc) return rc;
+    if (bytes) *bytes = L.total;
+    if (n_blocks) *n_blocks = L.n_blocks;
+    if (n_pairs) *n_pairs = L.n_pairs;
+    if (y_floats) *y_floats = L.y_floats;
+    return CADMM_OK;
+}
+
+int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStream_t stream, cadmm_handle** out)
+{
+    if (!out) return fail(CADMM_INVALID, "out handle pointer is NULL");
+    *out = nullptr;
+    Layout L;
+    int rc = validate_and_plan(d, L);
+    if (rc) return rc;
+    if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) & 255) != 0)
+        return fail(CADMM_WORKSPACE, "workspace must be a 256-byte aligned device pointer");
+    if (bytes < L.total)
+        return fail(CADMM_WORKSPACE, "workspace too small: need " + std::to_string(L.total) + " bytes");
+    cadmm_handle* h = new cadmm_handle();
+    h->L = L;
+    h->ws = static_cast<char*>(d_ws);
+    h->stream = stream;
+    h->g1 = h->gK = nullptr;
+    h->obs_ptr.assign(d->obs_ptr, d->obs_ptr + d->n_scen + 1);
+    hipError_t e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(CADMM_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+    auto bail = [&](int code) {
+        drop_graphs(h);
+        (void)hipStreamDestroy(h->cap);
+        delete h;
+        return code;
+    };
+
+    // ---- host staging (FP64 -> FP32, faces packed as float4) ----
+    const int dim = L.dim, ns = L.n_s, nu = L.n_u, N = L.N;
+    std::vector<float4> pf(L.Fr), of(std::max(L.Fo, 1));
+    for (int k = 0; k < L.Fr; ++k)
+        pf[k] = float4{(float)d->part_A[k * dim], (float)d->part_A[k * dim + 1],
+                       dim == 3 ? (float)d->part_A[k * dim + 2] : 0.f, (float)d->part_b[k]};
+    for (int k = 0; k < L.Fo; ++k)
+        of[k] = float4{(float)d->obs_C[k * dim], (float)d->obs_C[k * dim + 1],
+                       dim == 3 ? (float)d->obs_C[k * dim + 2] : 0.f, (float)d->obs_d[k]};
+    std::vector<float> poff(3 * L.n_parts, 0.f);
+    for (int i = 0; i < L.n_parts; ++i)
+        for (int r = 0; r < dim; ++r) poff[i * 3 + r] = (float)d->part_off[i * dim + r];
+    std::vector<int4> blocks;
+    std::vector<int> yoff;
+    long long off = 0;
+    for (int s = 0; s < L.n_scen; ++s)
+        for (int i = 0; i < L.n_parts; ++i)
+            for (int j = d->obs_ptr[s]; j < d->obs_ptr[s + 1]; ++j) {
+                const int n = (d->part_face_ptr[i + 1] - d->part_face_ptr[i]) + (d->obs_face_ptr[j + 1] - d->obs_face_ptr[j]) + 1;
+                blocks.push_back(int4{s, i, j, n});
+                yoff.push_back((int)off);
+                off += (long long)n * N;
+            }
+    h->blocks = blocks;
+    auto f32 = [](const double* p, size_t n) {
+        std::vector<float> v(n);
+        for (size_t i = 0; i < n; ++i) v[i] = (float)p[i];
+        return v;
+    };
+    std::vector<float> Ad = f32(d->A_dyn, ns * ns), Bd = f32(d->B_dyn, ns * nu), cd = f32(d->c_dyn, ns),
+                       Qs = f32(d->Q_s, ns * ns), Qu = f32(d->Q_u, nu * nu),
+                       xr = f32(d->x_ref, (size_t)L.n_scen * (N + 1) * ns), x0 = f32(d->x0, (size_t)L.n_scen * ns);
+    auto up = [&](size_t o, const void* src, size_t nbytes) -> int {
+        if (nbytes == 0) return CADMM_OK;
+        HIP_TRY(hipMemcpyAsync(h->ws + o, src, nbytes, hipMemcpyHostToDevice, stream));
+        return CADMM_OK;
+    };
+    if ((rc = up(L.part_faces, pf.data(), sizeof(float4) * L.Fr)) ||
+        (rc = up(L.part_face_ptr, d->part_face_ptr, sizeof(int) * (L.n_parts + 1))) ||
+        (rc = up(L.part_off, poff.data(), sizeof(float) * poff.size())) ||
+        (rc = up(L.obs_faces, of.data(), sizeof(float4) * L.Fo)) ||
+        (rc = up(L.obs_face_ptr, d->obs_face_ptr, sizeof(int) * (L.M + 1))) ||
+        (rc = up(L.blocks, blocks.data(), sizeof(int4) * blocks.size())) ||
+        (rc = up(L.block_yoff, yoff.data(), sizeof(int) * yoff.size())) ||
+        (rc = up(L.A_dyn, Ad.data(), sizeof(float) * Ad.size())) ||
+        (rc = up(L.B_dyn, Bd.data(), sizeof(float) * Bd.size())) ||
+        (rc = up(L.c_dyn, cd.data(), sizeof(float) * cd.size())) ||
+        (rc = up(L.Q_s, Qs.data(), sizeof(float) * Qs.size())) ||
+        (rc = up(L.Q_u, Qu.data(), sizeof(float) * Qu.size())) ||
+        (rc = up(L.x_ref, xr.data(), sizeof(float) * xr.size())) ||
+        (rc = up(L.x0, x0.data(), sizeof(float) * x0.size())))
+        return bail(rc);
+    // host staging buffers must stay alive until the copies complete
+    if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(CADMM_DEVICE, "upload failed"));
+
+    DevProblem& P = h->P;
+    std::memset(&P, 0, sizeof(P));
+    P.dim = dim; P.n_s = ns; P.n_u = nu; P.N = N; P.n_parts = L.n_parts; P.n_scen = L.n_scen;
+    P.n_blocks = L.n_blocks; P.att_kind = d->att_kind; P.n_att = L.n_att; P.nq = L.nq; P.nc = L.nc;
+    for (int r = 0; r < dim; ++r) P.pos_idx[r] = d->pos_idx[r];
+    for (int a = 0; a < L.n_att; ++a) P.att_idx[a] = d->att_idx[a];
+    P.sigma = (float)d->sigma; P.eps_prox = (float)d->eps_prox;
+    P.eps_pri = (float)d->eps_pri; P.eps_dual = (float)d->eps_dual;
+    P.max_sweeps = d->max_sweeps > 0 ? d->max_sweeps : 24;
+    P.max_part_faces = L.max_pf; P.max_obs_faces = L.max_of;
+    P.part_faces = at<float4>(h, L.part_faces);
+    P.part_face_ptr = at<int>(h, L.part_face_ptr);
+    P.part_off = at<float>(h, L.part_off);
+    P.obs_faces = at<float4>(h, L.obs_faces);
+    P.obs_face_ptr = at<int>(h, L.obs_face_ptr);
+    P.blocks = at<int4>(h, L.blocks);
+    P.block_yoff = at<int>(h, L.block_yoff);
+    P.wg_items = at<int4>(h, L.wg_items);
+    P.scen_wg = at<int2>(h, L.scen_wg);
+    P.A_dyn = at<float>(h, L.A_dyn); P.B_dyn = at<float>(h, L.B_dyn); P.c_dyn = at<float>(h, L.c_dyn);
+    P.Q_s = at<float>(h, L.Q_s); P.Q_u = at<float>(h, L.Q_u);
+    P.x_ref = at<float>(h, L.x_ref); P.x0 = at<float>(h, L.x0);
+    P.x = at<float>(h, L.x); P.u = at<float>(h, L.u); P.y = at<float>(h, L.y);
+    P.zeta = at<float>(h, L.zeta); P.xi = at<float>(h, L.xi);
+    P.contrib = at<float>(h, L.contrib);
+    P.rdual_part = at<float>(h, L.rdual_part); P.rpri_part = at<float>(h, L.rpri_part);
+    P.unconv_part = at<int>(h, L.unconv_part);
+    P.r_pri = at<float>(h, L.r_pri); P.r_dual = at<float>(h, L.r_dual);
+    P.done = at<int>(h, L.done); P.iters = at<int>(h, L.iters); P.unconv = at<int>(h, L.unconv);
+    P.hist_pri = at<float>(h, L.hist_pri); P.hist_dual = at<float>(h, L.hist_dual); P.hist_cap = kHistCap;
+    P.Kgain = at<float>(h, L.Kgain);
+
+    if ((rc = upload_worklists(h, d->waves_per_group > 0 ? d->waves_per_group : 4))) return bail(rc);
+    if ((rc = init_iterate(h))) return bail(rc);
+    if (d->waves_per_group == 0 && (rc = autotune(h))) return bail(rc);
+    if ((rc = recapture(h))) return bail(rc);
+    if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(CADMM_DEVICE, "setup failed"));
+    *out = h;
+    return CADMM_OK;
+}
+
+int admm_iterate(cadmm_handle* h, int n_iters)
+{
+    if (!h || n_iters < 0) return fail(CADMM_INVALID, "bad handle or iteration count");
+    while (n_iters >= kGraphBlock) {
+        HIP_TRY(hipGraphLaunch(h->gK, h->stream));
+        n_iters -= kGraphBlock;
+    }
+    for (int i = 0; i < n_iters; ++i) HIP_TRY(hipGraphLaunch(h->g1, h->stream));
+    return CADMM_OK;
+}
+
+int admm_reset(cadmm_handle* h)
+{
+    if (!h) return fail(CADMM_INVALID, "bad handle");
+    return init_iterate(h);
+}
+
+int admm_solve(cadmm_handle* h, int max_iters, int check_every, cadmm_result* out)
+{
+    if (!h || max_iters < 0) return fail(CADMM_INVALID, "bad handle or iteration count");
+    const Layout& L = h->L;
+    if (check_every <= 0) check_every = kGraphBlock;
+    std::vector<int> done(L.n_scen, 0);
+    int it = 0;
+    while (it < max_iters) {
+        const int chunk = std::min(check_every, max_iters - it);
+        int rc = admm_iterate(h, chunk);
+        if (rc) return rc;
+        it += chunk;
+        HIP_TRY(hipMemcpyAsync(done.data(), h->ws + L.done, sizeof(int) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        bool all = true;
+        for (int s = 0; s < L.n_scen; ++s) all &= done[s] != 0;
+        if (all) break;
+    }
+    // final certificate and cost
+    HIP_TRY(launch_cost(h->P, at<float>(h, L.cost), h->stream));
+    if (L.n_blocks > 0) {
+        HIP_TRY(launch_init_pairs(h->P, at<float>(h, L.alpha), 0, h->stream));
+        HIP_TRY(launch_min_alpha(h->P, at<float>(h, L.alpha), at<float>(h, L.min_alpha), h->stream));
+    } else {
+        HIP_TRY(launch_fill(at<float>(h, L.min_alpha), L.n_scen, INFINITY, h->stream));
+    }
+    std::vector<float> rp(L.n_scen), rdv(L.n_scen), cost(L.n_scen), ma(L.n_scen);
+    std::vector<int> iters(L.n_scen), unc(L.n_scen);
+    HIP_TRY(hipMemcpyAsync(rp.data(), h->ws + L.r_pri, sizeof(float) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(rdv.data(), h->ws + L.r_dual, sizeof(float) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(cost.data(), h->ws + L.cost, sizeof(float) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(ma.data(), h->ws + L.min_alpha, sizeof(float) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(iters.data(), h->ws + L.iters, sizeof(int) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(unc.data(), h->ws + L.unconv, sizeof(int) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(done.data(), h->ws + L.done, sizeof(int) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    bool all = true;
+    for (int s = 0; s < L.n_scen; ++s) {
+        if (out) {
+            out[s].iters = iters[s];
+            out[s].converged = done[s];
+            out[s].r_pri = rp[s];
+            out[s].r_dual = rdv[s];
+            out[s].cost = cost[s];
+            out[s].min_alpha = ma[s];
+            out[s].unconverged_pairs = unc[s];
+        }
+        all &= done[s] != 0;
+    }
+    return all ? CADMM_OK : CADMM_NOT_CONVERGED;
+}
+
+int admm_get_state(cadmm_handle* h, float* x, float* u, float* y, float* zeta, float* xi)
+{
+    if (!h) return fail(CADMM_INVALID, "bad handle");
+    const Layout& L = h->L;
+    auto cp = [&](void* dst, size_t off, size_t nbytes) -> int {
+        if (!dst || nbytes == 0) return CADMM_OK;
+        HIP_TRY(hipMemcpyAsync(dst, h->ws + off, nbytes, hipMemcpyDeviceToDevice, h->stream));
+        return CADMM_OK;
+    };
+    int rc;
+    if ((rc = cp(x, L.x, sizeof(float) * L.n_scen * (L.N + 1) * L.n_s)) ||
+        (rc = cp(u, L.u, sizeof(float) * L.n_scen * L.N * L.n_u)) ||
+        (rc = cp(y, L.y, sizeof(float) * L.y_floats)) ||
+        (rc = cp(zeta, L.zeta, sizeof(float) * L.n_pairs)) ||
+        (rc = cp(xi, L.xi, sizeof(float) * L.n_pairs * L.dim)))
+        return rc;
+    return CADMM_OK;
+}
+
+int admm_set_state(cadmm_handle* h, const float* x, const float* u, const float* y, const float* zeta,
+                   const float* xi)
+{
+    if (!h) return fail(CADMM_INVALID, "bad handle");
+    const Layout& L = h->L;
+    auto cp = [&](const void* src, size_t off, size_t nbytes) -> int {
+        if (!src || nbytes == 0) return CADMM_OK;
+        HIP_TRY(hipMemcpyAsync(h->ws + off, src, nbytes, hipMemcpyDeviceToDevice, h->stream));
+        return CADMM_OK;
+    };
+    int rc;
+    if ((rc = cp(x, L.x, sizeof(float) * L.n_scen * (L.N + 1) * L.n_s)) ||
+        (rc = cp(u, L.u, sizeof(float) * L.n_scen * L.N * L.n_u)) ||
+        (rc = cp(y, L.y, sizeof(float) * L.y_floats)) ||
+        (rc = cp(zeta, L.zeta, sizeof(float) * L.n_pairs)) ||
+        (rc = cp(xi, L.xi, sizeof(float) * L.n_pairs * L.dim)))
+        return rc;
+    HIP_TRY(launch_fill_int(at<int>(h, L.done), L.n_scen, 0, h->stream));
+    return CADMM_OK;
+}
+
+int admm_get_history(cadmm_handle* h, int max_rows, float* r_pri, float* r_dual)
+{
+    if (!h || max_rows < 0) return fail(CADMM_INVALID, "bad handle or size");
+    const Layout& L = h->L;
+    const int rows = std::min(max_rows, kHistCap);
+    if (rows == 0) return 0;
+    const size_t nbytes = sizeof(float) * (size_t)rows * L.n_scen;
+    if (r_pri) HIP_TRY(hipMemcpyAsync(r_pri, h->ws + L.hist_pri, nbytes, hipMemcpyDeviceToHost, h->stream));
+    if (r_dual) HIP_TRY(hipMemcpyAsync(r_dual, h->ws + L.hist_dual, nbytes, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return rows;
+}
+
+int admm_scales(cadmm_handle* h, float* alpha)
+{
+    if (!h || !alpha) return fail(CADMM_INVALID, "bad handle or output");
+    if (h->L.n_blocks == 0) return CADMM_OK;
+    HIP_TRY(launch_init_pairs(h->P, alpha, 0, h->stream));
+    return CADMM_OK;
+}
+
+int admm_phase_times(cadmm_handle* h, int n_iters, float* ms_out)
+{
+    if (!h || n_iters <= 0 || !ms_out) return fail(CADMM_INVALID, "bad handle, count or output");
+    hipEvent_t ev[5];
+    for (int i = 0; i < 5; ++i) HIP_TRY(hipEventCreate(&ev[i]));
+    double acc[4] = {0, 0, 0, 0};
+    hipStream_t st = h->stream;
+    for (int it = 0; it < n_iters; ++it) {
+        HIP_TRY(hipEventRecord(ev[0], st));
+        if (h->L.n_blocks > 0) HIP_TRY(launch_pair_phase(h->P, h->W, h->grid, st));
+        HIP_TRY(hipEventRecord(ev[1], st));
+        HIP_TRY(launch_traj_phase(h->P, h->L.n_blocks == 0 ? 1 : 0, st));
+        HIP_TRY(hipEventRecord(ev[2], st));
+        if (h->L.n_blocks > 0) HIP_TRY(launch_mult_phase(h->P, h->W, h->grid, st));
+        HIP_TRY(hipEventRecord(ev[3], st));
+        HIP_TRY(launch_residual(h->P, st));
+        HIP_TRY(hipEventRecord(ev[4], st));
+        HIP_TRY(hipEventSynchronize(ev[4]));
+        for (int i = 0; i < 4; ++i) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            acc[i] += ms;
+        }
+    }
+    for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i < 4; ++i) ms_out[i] = (float)(acc[i] / n_iters);
+    return CADMM_OK;
+}
+
+int admm_launch_config(cadmm_handle* h, int* waves_per_group, int* n_workgroups)
+{
+    if (!h) return fail(CADMM_INVALID, "bad handle");
+    if (waves_per_group) *waves_per_group = h->W;
+    if (n_workgroups) *n_workgroups = h->P.n_wg;
+    return CADMM_OK;
+}
+
+void collision_admm_destroy(cadmm_handle* h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    (void)hipStreamDestroy(h->cap);
+    delete h;
+}
+
+int pair_qp_batch(const cadmm_pair_batch* b, hipStream_t stream)
+{
+    if (!b) return fail(CADMM_INVALID, "batch is NULL");
+    if (b->dim != 2 && b->dim != 3) return fail(CADMM_INVALID, "dim must be 2 or 3");
+    if (b->n_pairs < 0) return fail(CADMM_INVALID, "n_pairs < 0");
+    if (b->n_pairs == 0) return CADMM_OK;
+    if (!b->row_ptr || !b->K || !b->kappa || !b->yhat || !b->bhat || !b->y || !b->r || !b->status)
+        return fail(CADMM_INVALID, "NULL buffer");
+    if (!(b->eps > 0.f)) return fail(CADMM_INVALID, "eps must be > 0");
+    HIP_TRY(launch_pair_qp_batch(b->n_pairs, b->dim, b->row_ptr, b->K, b->kappa, b->yhat, b->bhat, b->eps,
+                                 b->max_sweeps > 0 ? b->max_sweeps : 24, b->y, b->r, b->status, stream));
+    return CADMM_OK;
+}
+
+int pair_scale_batch(const cadmm_scale_batch* b, hipStream_t stream)
+{
+    if (!b) return fail(CADMM_INVALID, "batch is NULL");
+    if (b->dim != 2 && b->dim != 3) return fail(CADMM_INVALID, "dim must be 2 or 3");
+    if (b->n_pairs < 0) return fail(CADMM_INVALID, "n_pairs < 0");
+    if (b->n_pairs == 0) return CADMM_OK;
+    if (!b->a_ptr || !b->A || !b->b || !b->o_ptr || !b->Cp || !b->dp || !b->alpha || !b->lam || !b->mu || !b->status)
+        return fail(CADMM_INVALID, "NULL buffer");
+    HIP_TRY(launch_scale_batch(b->n_pairs, b->dim, b->a_ptr, b->A, b->b, b->o_ptr, b->Cp, b->dp, b->alpha, b->lam,
+                               b->mu, b->status, stream));
+    return CADMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Internal declarations shared by the host (ABI) and kernel translation units
+// of the gfx950 ADMM collision-avoidance library. Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cadmm {
+
+constexpr int kWave = 64;
+constexpr int kMaxWavesPerGroup = 8;
+#define CADMM_MAX_NU_DEV 8
+
+// Everything a kernel needs, passed by value (kernel argument segment).
+struct DevProblem {
+    int dim, n_s, n_u, N, n_parts, n_scen, n_blocks, n_wg;
+    int att_kind, n_att, nq, nc;      // nq pose coordinates, nc contribution floats
+    int pos_idx[3], att_idx[3];
+    float sigma, eps_prox, eps_pri, eps_dual;
+    int max_sweeps;
+    int max_part_faces, max_obs_faces;   // select the compiled pair-kernel variant
+    // geometry (FP32)
+    const float4* part_faces;    // [F_r] (a_x, a_y, a_z, b)
+    const int* part_face_ptr;    // [P+1]
+    const float* part_off;       // [P*3]
+    const float4* obs_faces;     // [F_o] (c_x, c_y, c_z, d)
+    const int* obs_face_ptr;     // [M+1]
+    // pair blocks and work lists
+    const int4* blocks;          // [n_blocks] (scenario, part, obstacle, n_rows)
+    const int* block_yoff;       // [n_blocks] float offset of the block in y
+    const int4* wg_items;        // [n_wg] (scenario, block_begin, block_end, wg index within scenario)
+    const int2* scen_wg;         // [n_scen] (first wg, end wg)
+    // model and cost
+    const float* A_dyn;          // [n_s*n_s]
+    const float* B_dyn;          // [n_s*n_u]
+    const float* c_dyn;          // [n_s]
+    const float* Q_s;            // [n_s*n_s]
+    const float* Q_u;            // [n_u*n_u]
+    const float* x_ref;          // [n_scen*(N+1)*n_s]
+    const float* x0;             // [n_scen*n_s]
+    // iterate
+    float* x;                    // [n_scen*(N+1)*n_s]
+    float* u;                    // [n_scen*N*n_u]
+    float* y;                    // canonical layout
+    float* zeta;                 // [n_blocks*N]
+    float* xi;                   // [n_blocks*dim*N]
+    // per-iteration scratch
+    float* contrib;              // [n_wg][nc][64]
+    float* rdual_part;           // [n_wg]
+    float* rpri_part;            // [n_wg]
+    int* unconv_part;            // [n_wg]
+    float* r_pri;                // [n_scen]
+    float* r_dual;               // [n_scen]
+    int* done;                   // [n_scen]
+    int* iters;                  // [n_scen]
+    int* unconv;                 // [n_scen]
+    float* hist_pri;             // [hist_cap*n_scen]
+    float* hist_dual;            // [hist_cap*n_scen]
+    int hist_cap;
+    float* Kgain;                // [n_scen][N][n_u*(n_s+1)] Riccati gains scratch
+};
+
+// Kernel launchers (defined in cadmm_kernels.hip). All return hipError_t of the launch.
+hipError_t launch_pair_phase(const DevProblem& P, int waves_per_group, int grid, hipStream_t s);
+hipError_t launch_mult_phase(const DevProblem& P, int waves_per_group, int grid, hipStream_t s);
+hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t s);
+hipError_t launch_residual(const DevProblem& P, hipStream_t s);
+hipError_t launch_init_pairs(const DevProblem& P, float* alpha_out, int write_y, hipStream_t s);
+hipError_t launch_fill(float* p, long long n, float v, hipStream_t s);
+hipError_t launch_fill_int(int* p, long long n, int v, hipStream_t s);
+hipError_t launch_cost(const DevProblem& P, float* cost_out, hipStream_t s);
+hipError_t launch_min_alpha(const DevProblem& P, const float* alpha, float* out, hipStream_t s);
+
+hipError_t launch_pair_qp_batch(int n_pairs, int dim, const int* row_ptr, const float* K,
+                                const float* kappa, const float* yhat, const float* bhat,
+                                float eps, int max_sweeps, float* y, float* r, int* status,
+                                hipStream_t s);
+hipError_t launch_scale_batch(int n_pairs, int dim, const int* a_ptr, const float* A, const float* b,
+                              const int* o_ptr, const float* Cp, const float* dp, float* alpha,
+                              float* lam, float* mu, int* status, hipStream_t s);
+
+// Geometry limits of the compiled pair-kernel variants.
+bool pair_variant_supported(int dim, int max_part_faces, int max_obs_faces);
+
+}  // namespace cadmm

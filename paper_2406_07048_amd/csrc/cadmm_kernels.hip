@@ -1,0 +1,1642 @@
+// gfx950 kernels of the ADMM collision-avoidance path (arXiv 2406.07048).
+//
+// Work decomposition (one wavefront = one pair block):
+//   a pair block is (scenario s, robot part i, obstacle j) with its N pairs
+//   t = 1..N; lane t-1 of the wave owns pair (i, j, t). The block's geometry
+//   (faces of part i and obstacle j) is wave-uniform and is read through the
+//   scalar cache; each lane keeps its pair's small QP in registers.
+//   A workgroup holds up to 16 waves = blocks of the same scenario, so the
+//   per-time-step sums of the trajectory-QP contributions are formed in LDS
+//   (fixed order, no float atomics) and written once per workgroup.
+//
+// Numerics: FP32 throughout. The dual-update QP is solved in its (dim+2)-
+// dimensional dual (residual v = K^T y + bhat and the multiplier nu of the
+// equality) by a semismooth Newton method with an exact-sign line search;
+// the primal y is recovered row by row as max(0, yhat - (K_l v - kappa_l nu)
+// / (eps D_l)).
+#include "cadmm_internal.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace cadmm {
+
+// ------------------------------------------------------------------------
+// small dense helpers (fully unrolled, registers only)
+// ------------------------------------------------------------------------
+
+// In-place Cholesky solve of an SPD system H x = g (H full NV x NV).
+template <int NV>
+__device__ __forceinline__ void chol_solve(float (&H)[NV * NV], float (&g)[NV])
+{
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        float s = H[j * NV + j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= H[j * NV + k] * H[j * NV + k];
+        s = fmaxf(s, 1e-30f);
+        const float L = sqrtf(s);
+        const float iL = 1.0f / L;
+        H[j * NV + j] = L;
+#pragma unroll
+        for (int i = j + 1; i < NV; ++i) {
+            float t = H[i * NV + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= H[i * NV + k] * H[j * NV + k];
+            H[i * NV + j] = t * iL;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        float s = g[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= H[i * NV + k] * g[k];
+        g[i] = s / H[i * NV + i];
+    }
+#pragma unroll
+    for (int i = NV - 1; i >= 0; --i) {
+        float s = g[i];
+#pragma unroll
+        for (int k = i + 1; k < NV; ++k) s -= H[k * NV + i] * g[k];
+        g[i] = s / H[i * NV + i];
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_int(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ------------------------------------------------------------------------
+// pose: R(s), dR/d(attitude), part centre pos_i = rho(s) + R o_i
+// ------------------------------------------------------------------------
+
+template <int DIM>
+struct Pose {
+    static constexpr int NATT = DIM == 2 ? 1 : 3;
+    static constexpr int NQ = DIM + NATT;
+    float R[DIM * DIM];
+    float dR[NATT * DIM * DIM];
+    float pos[DIM];
+    float q[NQ];   // pose coordinates (position, attitude) of the state
+};
+
+template <int DIM>
+__device__ __forceinline__ void make_pose(const DevProblem& P, const float* xs, int part, Pose<DIM>& ps)
+{
+    if constexpr (DIM == 2) {
+        const float th = xs[P.att_idx[0]];
+        float s, c;
+        sincosf(th, &s, &c);
+        ps.R[0] = c; ps.R[1] = -s; ps.R[2] = s; ps.R[3] = c;
+        ps.dR[0] = -s; ps.dR[1] = -c; ps.dR[2] = c; ps.dR[3] = -s;
+        ps.q[2] = th;
+    } else {
+        const float ph = xs[P.att_idx[0]], th = xs[P.att_idx[1]], psi = xs[P.att_idx[2]];
+        float sf, cf, st, ct, sp, cp;
+        sincosf(ph, &sf, &cf);
+        sincosf(th, &st, &ct);
+        sincosf(psi, &sp, &cp);
+        float* R = ps.R;
+        R[0] = cp * ct; R[1] = cp * st * sf - sp * cf; R[2] = cp * st * cf + sp * sf;
+        R[3] = sp * ct; R[4] = sp * st * sf + cp * cf; R[5] = sp * st * cf - cp * sf;
+        R[6] = -st;     R[7] = ct * sf;                R[8] = ct * cf;
+        float* D = ps.dR;   // d/dphi
+        D[0] = 0.f; D[1] = cp * st * cf + sp * sf; D[2] = -cp * st * sf + sp * cf;
+        D[3] = 0.f; D[4] = sp * st * cf - cp * sf; D[5] = -sp * st * sf - cp * cf;
+        D[6] = 0.f; D[7] = ct * cf;                D[8] = -ct * sf;
+        D += 9;             // d/dtheta
+        D[0] = -cp * st; D[1] = cp * ct * sf; D[2] = cp * ct * cf;
+        D[3] = -sp * st; D[4] = sp * ct * sf; D[5] = sp * ct * cf;
+        D[6] = -ct;      D[7] = -st * sf;     D[8] = -st * cf;
+        D += 9;             // d/dpsi
+        D[0] = -sp * ct; D[1] = -sp * st * sf - cp * cf; D[2] = -sp * st * cf + cp * sf;
+        D[3] = cp * ct;  D[4] = cp * st * sf - sp * cf;  D[5] = cp * st * cf + sp * sf;
+        D[6] = 0.f;      D[7] = 0.f;                     D[8] = 0.f;
+        ps.q[3] = ph; ps.q[4] = th; ps.q[5] = psi;
+    }
+    const float* o = P.part_off + part * 3;
+#pragma unroll
+    for (int r = 0; r < DIM; ++r) {
+        float acc = xs[P.pos_idx[r]];
+        ps.q[r] = acc;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc += ps.R[r * DIM + c] * o[c];
+        ps.pos[r] = acc;
+    }
+}
+
+// ------------------------------------------------------------------------
+// the pair sub-problem in the ADMM kernel: structured rows
+//   lambda rows k: K_k = (0, a_k), kappa_k = b_k
+//   mu rows l:     K_l = (d'_l, R^T c_l), d'_l = d_l - c_l.pos, kappa_l = 0
+//   gamma row:     K = (1, 0), kappa = 0
+// Each lane keeps d'_l of its pair (small near the obstacle, so no
+// cancellation against the world-frame offsets); the obstacle normals c_l
+// stay wave-uniform. Slopes use s_l = d'_l v0 + c_l.(R v_r), and the mu-row
+// Hessian block is E M E^T with E = diag(1, R^T) and M = sum f (d', c)(d', c)^T.
+// ------------------------------------------------------------------------
+
+template <int DIM, int MR, int MO>
+struct PairRows {
+    static constexpr int NV = DIM + 2;
+    int nr, no;
+    const float4* rf;          // robot faces of the part (wave-uniform)
+    const float4* of;          // obstacle faces (wave-uniform)
+    float R[DIM * DIM];
+    float bh[DIM + 1];
+    float yhR[MR], yhO[MO], yhG;
+    float ieR[MR], ieO[MO], ieG;    // 1 / (eps D_l)
+    float dpO[MO];                  // d'_l of the pair
+
+    template <bool HESS>
+    __device__ __forceinline__ void pass(const float (&z)[NV], float (&g)[NV], float (&H)[NV * NV],
+                                         float& sc) const
+    {
+        const float v0 = z[0], nu = z[DIM + 1];
+        float vr[DIM];
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) vr[r] = z[1 + r];
+        float w[DIM];   // R v_r
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) {
+            float acc = 0.f;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) acc += R[r * DIM + c] * vr[c];
+            w[r] = acc;
+        }
+        float gl[DIM] = {}, gnu = 0.f, Sd = 0.f, Sc[DIM] = {}, ysc = 0.f;
+        float Hl[DIM * DIM] = {}, Hln[DIM] = {}, Hnn = 0.f;
+        float M[(DIM + 1) * (DIM + 1)] = {};
+#pragma unroll
+        for (int k = 0; k < MR; ++k) {
+            if (k < nr) {
+                const float4 f = rf[k];
+                const float a[3] = {f.x, f.y, f.z};
+                float s = -f.w * nu, an = 0.f;
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) { s += a[r] * vr[r]; an += fabsf(a[r]); }
+                const float y = fmaxf(0.f, yhR[k] - s * ieR[k]);
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) gl[r] += y * a[r];
+                gnu += f.w * y;
+                ysc += y * an;
+                if (HESS) {
+                    const float act = y > 0.f ? ieR[k] : 0.f;
+#pragma unroll
+                    for (int r = 0; r < DIM; ++r) {
+#pragma unroll
+                        for (int c = r; c < DIM; ++c) Hl[r * DIM + c] += act * a[r] * a[c];
+                        Hln[r] += act * f.w * a[r];
+                    }
+                    Hnn += act * f.w * f.w;
+                }
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < MO; ++l) {
+            if (l < no) {
+                const float4 f = of[l];
+                const float ch[4] = {dpO[l], f.x, f.y, f.z};   // (d'_l, c_l)
+                float s = ch[0] * v0, cn = 0.f;
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) { s += ch[1 + r] * w[r]; cn += fabsf(ch[1 + r]); }
+                const float y = fmaxf(0.f, yhO[l] - s * ieO[l]);
+                Sd += ch[0] * y;
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) Sc[r] += ch[1 + r] * y;
+                ysc += y * (fabsf(ch[0]) + cn);
+                if (HESS) {
+                    const float act = y > 0.f ? ieO[l] : 0.f;
+#pragma unroll
+                    for (int r = 0; r <= DIM; ++r)
+#pragma unroll
+                        for (int c = r; c <= DIM; ++c) M[r * (DIM + 1) + c] += act * ch[r] * ch[c];
+                }
+            }
+        }
+        const float yg = fmaxf(0.f, yhG - v0 * ieG);
+        ysc += yg;
+        // gradient of the dual function
+        g[0] = bh[0] - v0 + Sd + yg;
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) {
+            float acc = 0.f;
+#pragma unroll
+            for (int m = 0; m < DIM; ++m) acc += R[m * DIM + r] * Sc[m];
+            g[1 + r] = bh[1 + r] - vr[r] + gl[r] + acc;
+        }
+        g[DIM + 1] = 1.f - gnu;
+        float mx = fabsf(v0);
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) mx = fmaxf(mx, fabsf(vr[r]));
+        float bm = fabsf(bh[0]);
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) bm = fmaxf(bm, fabsf(bh[1 + r]));
+        sc = 1.f + bm + mx + ysc;
+        if (HESS) {
+            // H_vv = I + diag(1, R^T) M diag(1, R)  (+ lambda and gamma rows)
+#pragma unroll
+            for (int r = 0; r <= DIM; ++r)
+#pragma unroll
+                for (int c = 0; c < r; ++c) M[r * (DIM + 1) + c] = M[c * (DIM + 1) + r];
+            float MR_[(DIM + 1) * DIM];   // M[:, 1:] R  -> (DIM+1) x DIM
+#pragma unroll
+            for (int r = 0; r <= DIM; ++r)
+#pragma unroll
+                for (int q = 0; q < DIM; ++q) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int e = 0; e < DIM; ++e) acc += M[r * (DIM + 1) + 1 + e] * R[e * DIM + q];
+                    MR_[r * DIM + q] = acc;
+                }
+            H[0] = M[0] + 1.f + (yg > 0.f ? ieG : 0.f);
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) H[1 + q] = MR_[q];
+#pragma unroll
+            for (int r = 0; r < DIM; ++r)
+#pragma unroll
+                for (int q = r; q < DIM; ++q) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) acc += R[c * DIM + r] * MR_[(1 + c) * DIM + q];
+                    H[(1 + r) * NV + 1 + q] = acc + (r == q ? 1.f : 0.f) + Hl[r * DIM + q];
+                }
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) H[(1 + r) * NV + DIM + 1] = -Hln[r];
+            H[0 * NV + DIM + 1] = 0.f;
+            H[(DIM + 1) * NV + DIM + 1] = Hnn + 1e-6f * (1.f + Hnn);
+#pragma unroll
+            for (int r = 0; r < NV; ++r)
+#pragma unroll
+                for (int c = 0; c < r; ++c) H[r * NV + c] = H[c * NV + r];
+        }
+    }
+};
+
+// ------------------------------------------------------------------------
+// generic rows (stateless batch entry point): K, kappa, yhat from memory
+// ------------------------------------------------------------------------
+
+template <int DIM>
+struct GenRows {
+    static constexpr int NV = DIM + 2;
+    int n;
+    const float* K;
+    const float* kap;
+    const float* yh;
+    float eps;
+    float bh[DIM + 1];
+
+    template <bool HESS>
+    __device__ __forceinline__ void pass(const float (&z)[NV], float (&g)[NV], float (&H)[NV * NV],
+                                         float& sc) const
+    {
+        float gv[DIM + 1] = {}, gnu = 0.f, ysc = 0.f;
+        if (HESS) {
+#pragma unroll
+            for (int i = 0; i < NV * NV; ++i) H[i] = 0.f;
+        }
+        for (int l = 0; l < n; ++l) {
+            float k[DIM + 1];
+            float D = 0.f;
+#pragma unroll
+            for (int c = 0; c <= DIM; ++c) { k[c] = K[l * (DIM + 1) + c]; D += k[c] * k[c]; }
+            const float kl = kap[l];
+            const float ie = 1.0f / (eps * D);
+            float s = -kl * z[DIM + 1];
+#pragma unroll
+            for (int c = 0; c <= DIM; ++c) s += k[c] * z[c];
+            const float y = fmaxf(0.f, yh[l] - s * ie);
+#pragma unroll
+            for (int c = 0; c <= DIM; ++c) gv[c] += y * k[c];
+            gnu += kl * y;
+            ysc += y * sqrtf(D);
+            if (HESS && y > 0.f) {
+                float w[NV];
+#pragma unroll
+                for (int c = 0; c <= DIM; ++c) w[c] = k[c];
+                w[DIM + 1] = -kl;
+#pragma unroll
+                for (int r = 0; r < NV; ++r)
+#pragma unroll
+                    for (int c = r; c < NV; ++c) H[r * NV + c] += ie * w[r] * w[c];
+            }
+        }
+        float mx = 0.f, bm = 0.f;
+#pragma unroll
+        for (int c = 0; c <= DIM; ++c) {
+            g[c] = bh[c] - z[c] + gv[c];
+            mx = fmaxf(mx, fabsf(z[c]));
+            bm = fmaxf(bm, fabsf(bh[c]));
+        }
+        g[DIM + 1] = 1.f - gnu;
+        sc = 1.f + bm + mx + ysc;
+        if (HESS) {
+#pragma unroll
+            for (int c = 0; c <= DIM; ++c) H[c * NV + c] += 1.f;
+            H[(DIM + 1) * NV + DIM + 1] += 1e-6f * (1.f + H[(DIM + 1) * NV + DIM + 1]);
+#pragma unroll
+            for (int r = 0; r < NV; ++r)
+#pragma unroll
+                for (int c = 0; c < r; ++c) H[r * NV + c] = H[c * NV + r];
+        }
+    }
+};
+
+// ------------------------------------------------------------------------
+// semismooth Newton on the concave dual, shared by both row sources.
+// Returns the sweeps used, or -1 if the budget ran out (z is still the last
+// iterate, whose primal y is within the Newton region in practice).
+// ------------------------------------------------------------------------
+
+template <int NV, class Rows>
+__device__ int dual_newton(const Rows& rows, float (&z)[NV], int max_sweeps)
+{
+    float gprev = FLT_MAX;
+    for (int it = 0; it < max_sweeps; ++it) {
+        float g[NV], H[NV * NV], sc;
+        rows.template pass<true>(z, g, H, sc);
+        float gmax = 0.f, zmax = 0.f;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            gmax = fmaxf(gmax, fabsf(g[i]));
+            zmax = fmaxf(zmax, fabsf(z[i]));
+        }
+        // converged, or stalled at the rounding floor of the gradient
+        if (gmax <= 1e-7f * sc || (gmax <= 2e-6f * sc && gmax >= 0.5f * gprev)) return it;
+        gprev = gmax;
+        float dz[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) dz[i] = g[i];
+        chol_solve<NV>(H, dz);
+        // Newton step at the rounding level of z: the active set is settled
+        // and z is the optimum to working precision
+        float dmax = 0.f;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) dmax = fmaxf(dmax, fabsf(dz[i]));
+        if (dmax <= 1e-6f * (zmax + 1e-3f * sc)) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) z[i] += dz[i];
+            return it + 1;
+        }
+        float d0 = 0.f;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) d0 += dz[i] * g[i];
+        if (!(d0 > 0.f)) return it;
+        // directional derivative of the dual along dz at step al
+        auto dphi = [&](float al) {
+            float zt[NV], gt[NV], Hd[NV * NV], sct;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) zt[i] = z[i] + al * dz[i];
+            rows.template pass<false>(zt, gt, Hd, sct);
+            float d = 0.f;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) d += dz[i] * gt[i];
+            return d;
+        };
+        float al = 1.f;
+        const float d1 = dphi(1.f);
+        if (d1 < -1e-3f * d0) {
+            // Illinois regula falsi on the decreasing piecewise-linear dphi
+            float lo = 0.f, hi = 1.f, flo = d0, fhi = d1;
+            int side = 0;
+            for (int ls = 0; ls < 6; ++ls) {
+                al = (lo * (-fhi) + hi * flo) / (flo - fhi);
+                const float fa = dphi(al);
+                if (fa >= -1e-3f * d0) {
+                    lo = al; flo = fa;
+                    if (side == 1) fhi *= 0.5f;
+                    side = 1;
+                    if (fa <= 0.1f * d0) break;
+                } else {
+                    hi = al; fhi = fa;
+                    if (side == -1) flo *= 0.5f;
+                    side = -1;
+                }
+            }
+            al = lo;
+        }
+#pragma unroll
+        for (int i = 0; i < NV; ++i) z[i] += al * dz[i];
+    }
+    return -1;
+}
+
+// ------------------------------------------------------------------------
+// ADMM step 1: dual updates of every pair + linearised contributions
+// ------------------------------------------------------------------------
+
+template <int DIM>
+struct Contrib {
+    static constexpr int NQ = Pose<DIM>::NQ;
+    static constexpr int NC = NQ * (NQ + 1) / 2 + NQ;
+};
+
+template <int DIM, int MR, int MO>
+__global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
+{
+    constexpr int NV = DIM + 2;
+    constexpr int NATT = Pose<DIM>::NATT;
+    constexpr int NQ = Pose<DIM>::NQ;
+    constexpr int NC = Contrib<DIM>::NC;
+    extern __shared__ float lds[];
+    const int W = blockDim.x >> 6;
+    const int wave = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    float* red = lds;                       // [W][NC][64]
+    float* red_rd = lds + W * NC * 64;      // [W]
+    int* red_un = reinterpret_cast<int*>(red_rd + W);
+    const int N = P.N;
+    const float eps = P.eps_prox;
+
+    for (int wg = blockIdx.x; wg < P.n_wg; wg += gridDim.x) {
+        const int4 item = P.wg_items[wg];
+        const int s = uniform(item.x);
+        if (P.done[s]) continue;                 // uniform over the workgroup
+        const int b = uniform(item.y + wave);
+        float con[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) con[c] = 0.f;
+        float rd = 0.f;
+        int unc = 0;
+        const int t = lane + 1;
+        if (b < item.z && t <= N) {
+            const int4 blk = P.blocks[b];
+            const int part = uniform(blk.y), obs = uniform(blk.z);
+            const int fr0 = uniform(P.part_face_ptr[part]);
+            const int fo0 = uniform(P.obs_face_ptr[obs]);
+            PairRows<DIM, MR, MO> pr;
+            pr.nr = uniform(P.part_face_ptr[part + 1] - fr0);
+            pr.no = uniform(P.obs_face_ptr[obs + 1] - fo0);
+            pr.rf = P.part_faces + fr0;
+            pr.of = P.obs_faces + fo0;
+            const int yoff = uniform(P.block_yoff[b]);
+            const float* xs = P.x + ((size_t)s * (N + 1) + t) * P.n_s;
+            Pose<DIM> ps;
+            make_pose<DIM>(P, xs, part, ps);
+#pragma unroll
+            for (int i = 0; i < DIM * DIM; ++i) pr.R[i] = ps.R[i];
+            const float zeta = P.zeta[(size_t)b * N + t - 1];
+            float xi[DIM];
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) xi[r] = P.xi[((size_t)b * DIM + r) * N + t - 1];
+            pr.bh[0] = 1.f + zeta;
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) pr.bh[1 + r] = xi[r];
+            const float* yb = P.y + yoff + (t - 1);
+            // warm start v = K^T yhat + bhat, nu from the largest lambda row
+            float v0 = pr.bh[0], Sc[DIM] = {}, vr[DIM];
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) vr[r] = pr.bh[1 + r];
+            float best = -1.f, nu = 0.f;
+#pragma unroll
+            for (int k = 0; k < MR; ++k) {
+                if (k < pr.nr) {
+                    const float4 f = pr.rf[k];
+                    const float yk = yb[k * N];
+                    pr.yhR[k] = yk;
+                    const float D = f.x * f.x + f.y * f.y + (DIM == 3 ? f.z * f.z : 0.f);
+                    pr.ieR[k] = 1.0f / (eps * D);
+                    vr[0] += yk * f.x;
+                    vr[1] += yk * f.y;
+                    if (DIM == 3) vr[DIM - 1] += yk * f.z;
+                } else {
+                    pr.yhR[k] = 0.f; pr.ieR[k] = 0.f;
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < MO; ++l) {
+                if (l < pr.no) {
+                    const float4 f = pr.of[l];
+                    const float c[3] = {f.x, f.y, f.z};
+                    const float yl = yb[(pr.nr + l) * N];
+                    pr.yhO[l] = yl;
+                    float dp = f.w, cn = 0.f;
+#pragma unroll
+                    for (int r = 0; r < DIM; ++r) { dp -= c[r] * ps.pos[r]; cn += c[r] * c[r]; }
+                    const float D = dp * dp + cn;
+                    pr.ieO[l] = 1.0f / (eps * D);
+                    pr.dpO[l] = dp;
+                    v0 += dp * yl;
+#pragma unroll
+                    for (int r = 0; r < DIM; ++r) Sc[r] += c[r] * yl;
+                } else {
+                    pr.yhO[l] = 0.f; pr.ieO[l] = 0.f; pr.dpO[l] = 0.f;
+                }
+            }
+            pr.yhG = yb[(pr.nr + pr.no) * N];
+            pr.ieG = 1.0f / eps;
+            v0 += pr.yhG;
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) {
+                float acc = 0.f;
+#pragma unroll
+                for (int m = 0; m < DIM; ++m) acc += ps.R[m * DIM + r] * Sc[m];
+                vr[r] += acc;
+            }
+#pragma unroll
+            for (int k = 0; k < MR; ++k) {
+                if (k < pr.nr) {
+                    const float4 f = pr.rf[k];
+                    if (pr.yhR[k] > best) {
+                        best = pr.yhR[k];
+                        float s = f.x * vr[0] + f.y * vr[1] + (DIM == 3 ? f.z * vr[DIM - 1] : 0.f);
+                        nu = s / f.w;
+                    }
+                }
+            }
+            float z[NV];
+            z[0] = v0;
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) z[1 + r] = vr[r];
+            z[DIM + 1] = nu;
+            const int sweeps = dual_newton<NV>(pr, z, P.max_sweeps);
+            unc = sweeps < 0 ? 1 : 0;
+
+            // final pass: primal rows, write-back, residual and Jacobian
+            {
+                const float zv0 = z[0], znu = z[DIM + 1];
+                float w[DIM];
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) acc += ps.R[r * DIM + c] * z[1 + c];
+                    w[r] = acc;
+                }
+                float* yw = P.y + yoff + (t - 1);
+                float Al[DIM] = {}, Sd = 0.f, Scf[DIM] = {};
+#pragma unroll
+                for (int k = 0; k < MR; ++k) {
+                    if (k < pr.nr) {
+                        const float4 f = pr.rf[k];
+                        float s = -f.w * znu + f.x * z[1] + f.y * z[2] + (DIM == 3 ? f.z * z[DIM] : 0.f);
+                        const float y = fmaxf(0.f, pr.yhR[k] - s * pr.ieR[k]);
+                        yw[k * N] = y;
+                        const float dl = y - pr.yhR[k];
+                        rd += dl * dl;
+                        Al[0] += y * f.x;
+                        Al[1] += y * f.y;
+                        if (DIM == 3) Al[DIM - 1] += y * f.z;
+                    }
+                }
+#pragma unroll
+                for (int l = 0; l < MO; ++l) {
+                    if (l < pr.no) {
+                        const float4 f = pr.of[l];
+                        const float c[3] = {f.x, f.y, f.z};
+                        float s = pr.dpO[l] * zv0;
+#pragma unroll
+                        for (int r = 0; r < DIM; ++r) s += c[r] * w[r];
+                        const float y = fmaxf(0.f, pr.yhO[l] - s * pr.ieO[l]);
+                        yw[(pr.nr + l) * N] = y;
+                        const float dl = y - pr.yhO[l];
+                        rd += dl * dl;
+                        Sd += pr.dpO[l] * y;
+#pragma unroll
+                        for (int r = 0; r < DIM; ++r) Scf[r] += c[r] * y;
+                    }
+                }
+                const float yg = fmaxf(0.f, pr.yhG - zv0 * pr.ieG);
+                yw[(pr.nr + pr.no) * N] = yg;
+                // residual e = K^T y + bhat at s^k
+                float e[DIM + 1];
+                e[0] = 1.f + zeta + Sd + yg;
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) {
+                    float acc = Al[r] + xi[r];
+#pragma unroll
+                    for (int m = 0; m < DIM; ++m) acc += ps.R[m * DIM + r] * Scf[m];
+                    e[1 + r] = acc;
+                }
+                // Jacobian of (T, R) in the pose coordinates (position, attitude)
+                const float* o = P.part_off + part * 3;
+                float J[(DIM + 1) * NQ];
+#pragma unroll
+                for (int i = 0; i < (DIM + 1) * NQ; ++i) J[i] = 0.f;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) J[c] = -Scf[c];
+#pragma unroll
+                for (int a = 0; a < NATT; ++a) {
+                    const float* dRa = ps.dR + a * DIM * DIM;
+                    float acc = 0.f;
+#pragma unroll
+                    for (int r = 0; r < DIM; ++r)
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) acc += Scf[r] * dRa[r * DIM + c] * o[c];
+                    J[DIM + a] = -acc;
+#pragma unroll
+                    for (int r = 0; r < DIM; ++r) {
+                        float v = 0.f;
+#pragma unroll
+                        for (int m = 0; m < DIM; ++m) v += dRa[m * DIM + r] * Scf[m];
+                        J[(1 + r) * NQ + DIM + a] = v;
+                    }
+                }
+                float ep[DIM + 1];
+#pragma unroll
+                for (int m = 0; m <= DIM; ++m) {
+                    float acc = e[m];
+#pragma unroll
+                    for (int a = 0; a < NQ; ++a) acc -= J[m * NQ + a] * ps.q[a];
+                    ep[m] = acc;
+                }
+                const float sg = P.sigma;
+                int idx = 0;
+#pragma unroll
+                for (int i = 0; i < NQ; ++i)
+#pragma unroll
+                    for (int j = i; j < NQ; ++j) {
+                        float acc = 0.f;
+#pragma unroll
+                        for (int m = 0; m <= DIM; ++m) acc += J[m * NQ + i] * J[m * NQ + j];
+                        con[idx++] = sg * acc;
+                    }
+#pragma unroll
+                for (int i = 0; i < NQ; ++i) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int m = 0; m <= DIM; ++m) acc += J[m * NQ + i] * ep[m];
+                    con[idx++] = sg * acc;
+                }
+            }
+        }
+        // workgroup reduction in a fixed order (waves = blocks of one scenario)
+        const float rdw = wave_sum(rd);
+        const int unw = wave_sum_int(unc);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) red[(wave * NC + c) * 64 + lane] = con[c];
+        if (lane == 0) { red_rd[wave] = rdw; red_un[wave] = unw; }
+        __syncthreads();
+        float* out = P.contrib + (size_t)wg * NC * 64;
+        for (int e = threadIdx.x; e < NC * 64; e += blockDim.x) {
+            float acc = 0.f;
+            for (int w = 0; w < W; ++w) acc += red[w * NC * 64 + e];
+            out[e] = acc;
+        }
+        if (threadIdx.x == 0) {
+            float a = 0.f;
+            int u = 0;
+            for (int w = 0; w < W; ++w) { a += red_rd[w]; u += red_un[w]; }
+            P.rdual_part[wg] = a;
+            P.unconv_part[wg] = u;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------
+// ADMM step 3: multiplier update zeta += T(s^{k+1}, y^{k+1}),
+// xi += R(s^{k+1}, y^{k+1}) and the primal residual partial sums
+// ------------------------------------------------------------------------
+
+template <int DIM, int MR, int MO>
+__global__ void __launch_bounds__(512) mult_phase_kernel(DevProblem P)
+{
+    extern __shared__ float lds[];
+    const int W = blockDim.x >> 6;
+    const int wave = uniform(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int N = P.N;
+    for (int wg = blockIdx.x; wg < P.n_wg; wg += gridDim.x) {
+        const int4 item = P.wg_items[wg];
+        const int s = uniform(item.x);
+        if (P.done[s]) continue;
+        const int b = uniform(item.y + wave);
+        const int t = lane + 1;
+        float rp = 0.f;
+        if (b < item.z && t <= N) {
+            const int4 blk = P.blocks[b];
+            const int part = uniform(blk.y), obs = uniform(blk.z);
+            const int fr0 = uniform(P.part_face_ptr[part]);
+            const int nr = uniform(P.part_face_ptr[part + 1] - fr0);
+            const int fo0 = uniform(P.obs_face_ptr[obs]);
+            const int no = uniform(P.obs_face_ptr[obs + 1] - fo0);
+            const int yoff = uniform(P.block_yoff[b]);
+            Pose<DIM> ps;
+            make_pose<DIM>(P, P.x + ((size_t)s * (N + 1) + t) * P.n_s, part, ps);
+            const float* yb = P.y + yoff + (t - 1);
+            float Al[DIM] = {}, Sd = 0.f, Sc[DIM] = {};
+#pragma unroll
+            for (int k = 0; k < MR; ++k) {
+                if (k < nr) {
+                    const float4 f = P.part_faces[fr0 + k];
+                    const float y = yb[k * N];
+                    Al[0] += y * f.x;
+                    Al[1] += y * f.y;
+                    if (DIM == 3) Al[DIM - 1] += y * f.z;
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < MO; ++l) {
+                if (l < no) {
+                    const float4 f = P.obs_faces[fo0 + l];
+                    const float y = yb[(nr + l) * N];
+                    float dp = f.w - f.x * ps.pos[0] - f.y * ps.pos[1];
+                    if (DIM == 3) dp -= f.z * ps.pos[DIM - 1];
+                    Sd += dp * y;
+                    Sc[0] += f.x * y;
+                    Sc[1] += f.y * y;
+                    if (DIM == 3) Sc[DIM - 1] += f.z * y;
+                }
+            }
+            const float yg = yb[(nr + no) * N];
+            const float T = 1.f + Sd + yg;
+            float* zp = P.zeta + (size_t)b * N + t - 1;
+            *zp += T;
+            rp = T * T;
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) {
+                float acc = Al[r];
+#pragma unroll
+                for (int m = 0; m < DIM; ++m) acc += ps.R[m * DIM + r] * Sc[m];
+                P.xi[((size_t)b * DIM + r) * N + t - 1] += acc;
+                rp += acc * acc;
+            }
+        }
+        const float rw = wave_sum(rp);
+        if (lane == 0) lds[wave] = rw;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float a = 0.f;
+            for (int w = 0; w < W; ++w) a += lds[w];
+            P.rpri_part[wg] = a;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------
+// residual sums, stopping test (Sec. IV-B) and history; one block/scenario
+// ------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(64) residual_kernel(DevProblem P)
+{
+    const int s = blockIdx.x;
+    if (P.done[s]) return;
+    const int2 r = P.scen_wg[s];
+    float a = 0.f, b = 0.f;
+    int u = 0;
+    for (int w = r.x + threadIdx.x; w < r.y; w += 64) {
+        a += P.rpri_part[w];
+        b += P.rdual_part[w];
+        u += P.unconv_part[w];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    u = wave_sum_int(u);
+    if (threadIdx.x == 0) {
+        const int k = P.iters[s];
+        if (k < P.hist_cap) {
+            P.hist_pri[(size_t)k * P.n_scen + s] = a;
+            P.hist_dual[(size_t)k * P.n_scen + s] = b;
+        }
+        P.iters[s] = k + 1;
+        P.r_pri[s] = a;
+        P.r_dual[s] = b;
+        P.unconv[s] = u;
+        if (a <= P.eps_pri && b <= P.eps_dual) P.done[s] = 1;
+    }
+}
+
+// ------------------------------------------------------------------------
+// ADMM step 2: trajectory QP by a backward Riccati sweep and forward
+// rollout; one workgroup per scenario. Stage cost 1/2 x^T H_t x + h_t^T x
+// with H_t = 2 Q_s + sum_ij sigma J^T J and h_t = -2 Q_s xref_t +
+// sum_ij sigma J^T (e - J q^k) (pose block), input cost u^T Q_u u.
+// ------------------------------------------------------------------------
+
+constexpr int kTrajThreads = 256;
+
+__global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, int obstacle_free)
+{
+    extern __shared__ float sm[];
+    const int s = blockIdx.x;
+    if (!obstacle_free && P.done[s]) return;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int ns = P.n_s, nu = P.n_u, N = P.N, nq = P.nq, nc = P.nc;
+    // LDS layout
+    float* Hq = sm;                      // [N][nc] reduced contributions
+    float* Pm = Hq + N * nc;             // [ns*ns]
+    float* pv = Pm + ns * ns;            // [ns]
+    float* PA = pv + ns;                 // [ns*ns]
+    float* PB = PA + ns * ns;            // [ns*nu]
+    float* wv = PB + ns * nu;            // [ns]
+    float* Quu = wv + ns;                // [nu*nu]
+    float* Qux = Quu + nu * nu;          // [nu*ns]
+    float* qu = Qux + nu * ns;           // [nu]
+    float* Qxx = qu + nu;                // [ns*ns]
+    float* qx = Qxx + ns * ns;           // [ns]
+    float* Kk = qx + ns;                 // [nu*(ns+1)] current gain (K | k)
+    float* xs = Kk + nu * (ns + 1);      // [ns] rollout state
+    float* us = xs + ns;                 // [nu]
+    float* Lq = us + nu;                 // [nu*nu] Cholesky factor of Quu
+    const float* A = P.A_dyn;
+    const float* B = P.B_dyn;
+    const float* c = P.c_dyn;
+    int* qidx = reinterpret_cast<int*>(Lq + nu * nu);   // [nq] state index of each pose coordinate
+    if (tid < P.dim) qidx[tid] = P.pos_idx[tid];
+    else if (tid < P.dim + P.n_att) qidx[tid] = P.att_idx[tid - P.dim];
+
+    // 1. reduce the contribution partials of this scenario's workgroups
+    if (!obstacle_free) {
+        const int2 r = P.scen_wg[s];
+        for (int e = tid; e < N * nc; e += nt) {
+            const int t = e / nc, cc = e % nc;
+            float acc = 0.f;
+            for (int w = r.x; w < r.y; ++w) acc += P.contrib[((size_t)w * nc + cc) * 64 + t];
+            Hq[t * nc + cc] = acc;
+        }
+    } else {
+        for (int e = tid; e < N * nc; e += nt) Hq[e] = 0.f;
+    }
+    __syncthreads();
+    const float* xref = P.x_ref + (size_t)s * (N + 1) * ns;
+    float* Kg = P.Kgain + (size_t)s * N * nu * (ns + 1);
+    // stage Hessian/gradient of step t (1..N) into (Hout, hout)
+    auto stage = [&](int t, float* Hout, float* hout) {
+        for (int e = tid; e < ns * ns; e += nt) Hout[e] = 2.f * P.Q_s[e];
+        for (int i = tid; i < ns; i += nt) {
+            float acc = 0.f;
+            for (int j = 0; j < ns; ++j) acc += P.Q_s[i * ns + j] * xref[t * ns + j];
+            hout[i] = -2.f * acc;
+        }
+        __syncthreads();
+        const float* hq = Hq + (t - 1) * nc;
+        if (tid == 0) {
+            int idx = 0;
+            for (int i = 0; i < nq; ++i)
+                for (int j = i; j < nq; ++j) {
+                    const float v = hq[idx++];
+                    Hout[qidx[i] * ns + qidx[j]] += v;
+                    if (i != j) Hout[qidx[j] * ns + qidx[i]] += v;
+                }
+            for (int i = 0; i < nq; ++i) hout[qidx[i]] += hq[idx++];
+        }
+        __syncthreads();
+    };
+    // 2. backward Riccati sweep: V_{t}(x) = 1/2 x^T P x + p^T x
+    stage(N, Pm, pv);
+    for (int t = N - 1; t >= 0; --t) {
+        for (int e = tid; e < ns * ns; e += nt) {
+            const int i = e / ns, j = e % ns;
+            float acc = 0.f;
+            for (int k = 0; k < ns; ++k) acc += Pm[i * ns + k] * A[k * ns + j];
+            PA[e] = acc;
+        }
+        for (int e = tid; e < ns * nu; e += nt) {
+            const int i = e / nu, j = e % nu;
+            float acc = 0.f;
+            for (int k = 0; k < ns; ++k) acc += Pm[i * ns + k] * B[k * nu + j];
+            PB[e] = acc;
+        }
+        for (int i = tid; i < ns; i += nt) {
+            float acc = pv[i];
+            for (int k = 0; k < ns; ++k) acc += Pm[i * ns + k] * c[k];
+            wv[i] = acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < nu * nu; e += nt) {
+            const int i = e / nu, j = e % nu;
+            float acc = 2.f * P.Q_u[e];
+            for (int k = 0; k < ns; ++k) acc += B[k * nu + i] * PB[k * nu + j];
+            Quu[e] = acc;
+        }
+        for (int e = tid; e < nu * ns; e += nt) {
+            const int i = e / ns, j = e % ns;
+            float acc = 0.f;
+            for (int k = 0; k < ns; ++k) acc += B[k * nu + i] * PA[k * ns + j];
+            Qux[e] = acc;
+        }
+        for (int i = tid; i < nu; i += nt) {
+            float acc = 0.f;
+            for (int k = 0; k < ns; ++k) acc += B[k * nu + i] * wv[k];
+            qu[i] = acc;
+        }
+        __syncthreads();
+        // gains K = -Quu^{-1} [Qux | qu]: Cholesky factor of Quu (nu <= 8) by one
+        // thread into LDS, then one column of the right-hand side per thread,
+        // solved in place in the LDS gain buffer
+        if (tid == 0) {
+            for (int i = 0; i < nu; ++i)
+                for (int j = 0; j <= i; ++j) {
+                    float sum = Quu[i * nu + j];
+                    for (int k = 0; k < j; ++k) sum -= Lq[i * nu + k] * Lq[j * nu + k];
+                    if (i == j) Lq[i * nu + i] = sqrtf(fmaxf(sum, 1e-30f));
+                    else Lq[i * nu + j] = sum / Lq[j * nu + j];
+                }
+        }
+        __syncthreads();
+        for (int col = tid; col <= ns; col += nt) {
+            for (int i = 0; i < nu; ++i) Kk[i * (ns + 1) + col] = -(col < ns ? Qux[i * ns + col] : qu[i]);
+            for (int i = 0; i < nu; ++i) {
+                float sum = Kk[i * (ns + 1) + col];
+                for (int k = 0; k < i; ++k) sum -= Lq[i * nu + k] * Kk[k * (ns + 1) + col];
+                Kk[i * (ns + 1) + col] = sum / Lq[i * nu + i];
+            }
+            for (int i = nu - 1; i >= 0; --i) {
+                float sum = Kk[i * (ns + 1) + col];
+                for (int k = i + 1; k < nu; ++k) sum -= Lq[k * nu + i] * Kk[k * (ns + 1) + col];
+                Kk[i * (ns + 1) + col] = sum / Lq[i * nu + i];
+            }
+            for (int i = 0; i < nu; ++i) Kg[((size_t)t * nu + i) * (ns + 1) + col] = Kk[i * (ns + 1) + col];
+        }
+        if (t == 0) break;
+        // stage terms of step t go into (Qxx, qx), then P_t = Qxx + A^T PA + Qux^T K
+        stage(t, Qxx, qx);
+        for (int e = tid; e < ns * ns; e += nt) {
+            const int i = e / ns, j = e % ns;
+            float acc = Qxx[e];
+            for (int k = 0; k < ns; ++k) acc += A[k * ns + i] * PA[k * ns + j];
+            for (int k = 0; k < nu; ++k) acc += Qux[k * ns + i] * Kk[k * (ns + 1) + j];
+            Qxx[e] = acc;
+        }
+        for (int i = tid; i < ns; i += nt) {
+            float acc = qx[i];
+            for (int k = 0; k < ns; ++k) acc += A[k * ns + i] * wv[k];
+            for (int k = 0; k < nu; ++k) acc += Qux[k * ns + i] * Kk[k * (ns + 1) + ns];
+            qx[i] = acc;
+        }
+        __syncthreads();
+        for (int e = tid; e < ns * ns; e += nt) {
+            const int i = e / ns, j = e % ns;
+            Pm[e] = 0.5f * (Qxx[i * ns + j] + Qxx[j * ns + i]);
+        }
+        for (int i = tid; i < ns; i += nt) pv[i] = qx[i];
+        __syncthreads();
+    }
+    __syncthreads();
+    // 3. forward rollout
+    float* xo = P.x + (size_t)s * (N + 1) * ns;
+    float* uo = P.u + (size_t)s * N * nu;
+    for (int i = tid; i < ns; i += nt) {
+        xs[i] = P.x0[(size_t)s * ns + i];
+        xo[i] = xs[i];
+    }
+    __syncthreads();
+    for (int t = 0; t < N; ++t) {
+        for (int i = tid; i < nu; i += nt) {
+            const float* Kt = Kg + (size_t)t * nu * (ns + 1) + i * (ns + 1);
+            float acc = Kt[ns];
+            for (int k = 0; k < ns; ++k) acc += Kt[k] * xs[k];
+            us[i] = acc;
+            uo[t * nu + i] = acc;
+        }
+        __syncthreads();
+        float nx = 0.f;
+        if (tid < ns) {
+            float acc = c[tid];
+            for (int k = 0; k < ns; ++k) acc += A[tid * ns + k] * xs[k];
+            for (int k = 0; k < nu; ++k) acc += B[tid * nu + k] * us[k];
+            nx = acc;
+        }
+        __syncthreads();
+        if (tid < ns) {
+            xs[tid] = nx;
+            xo[(t + 1) * ns + tid] = nx;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------
+// scale LP (Sec. III-A eq. scale_opt) through its dual (Sec. III-B eq.
+// scale_opt_dual) in standard form
+//   min dp^T mu  s.t.  b^T lam = 1,  A^T lam + Cp^T mu = 0,  lam, mu >= 0,
+// by a two-phase revised simplex (Bland's rule) with an explicit
+// (dim+1) x (dim+1) basis inverse in registers; columns are produced on the
+// fly from the geometry. The optimal basis is re-solved directly at the end.
+// ------------------------------------------------------------------------
+
+template <int DIM, class Cols>
+__device__ int revised_simplex(const Cols& cols, float& alpha, float* xB_out, int* basis_out)
+{
+    constexpr int m = DIM + 1;
+    const int n = cols.n();
+    float Bi[m * m];
+    float xB[m];
+    int basis[m];
+#pragma unroll
+    for (int i = 0; i < m; ++i) {
+#pragma unroll
+        for (int j = 0; j < m; ++j) Bi[i * m + j] = i == j ? 1.f : 0.f;
+        xB[i] = i == 0 ? 1.f : 0.f;
+        basis[i] = n + i;
+    }
+    const float ctol = 1e-6f * (1.f + cols.cmax());
+    const float ptol = 1e-6f;
+    int status = 0;
+    for (int phase = 1; phase <= 2 && status == 0; ++phase) {
+        int it = 0;
+        for (; it < 64; ++it) {
+            float cB[m];
+#pragma unroll
+            for (int i = 0; i < m; ++i)
+                cB[i] = phase == 1 ? (basis[i] >= n ? 1.f : 0.f) : (basis[i] < n ? cols.cost(basis[i]) : 0.f);
+            float pi[m];
+#pragma unroll
+            for (int q = 0; q < m; ++q) {
+                float acc = 0.f;
+#pragma unroll
+                for (int i = 0; i < m; ++i) acc += cB[i] * Bi[i * m + q];
+                pi[q] = acc;
+            }
+            int enter = -1;
+            float Eq[m];
+            for (int j = 0; j < n && enter < 0; ++j) {
+                bool basic = false;
+#pragma unroll
+                for (int i = 0; i < m; ++i) basic |= basis[i] == j;
+                if (basic) continue;
+                float E[m];
+                cols.col(j, E);
+                float rc = phase == 1 ? 0.f : cols.cost(j);
+#pragma unroll
+                for (int q = 0; q < m; ++q) rc -= pi[q] * E[q];
+                if (rc < -ctol) {
+                    enter = j;
+#pragma unroll
+                    for (int q = 0; q < m; ++q) Eq[q] = E[q];
+                }
+            }
+            if (enter < 0) break;
+            float u[m];
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+                float acc = 0.f;
+#pragma unroll
+                for (int q = 0; q < m; ++q) acc += Bi[i * m + q] * Eq[q];
+                u[i] = acc;
+            }
+            int leave = -1;
+            float best = 0.f;
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+                if (u[i] > ptol) {
+                    const float ratio = xB[i] / u[i];
+                    if (leave < 0 || ratio < best || (ratio == best && basis[i] < basis[leave])) {
+                        leave = i;
+                        best = ratio;
+                    }
+                }
+            }
+            if (leave < 0) { status = 2; break; }
+            float ur = 0.f;
+#pragma unroll
+            for (int i = 0; i < m; ++i) ur = i == leave ? u[i] : ur;
+            const float iu = 1.f / ur;
+            float rowB[m], xr = 0.f;
+#pragma unroll
+            for (int q = 0; q < m; ++q) {
+                float v = 0.f;
+#pragma unroll
+                for (int i = 0; i < m; ++i) v = i == leave ? Bi[i * m + q] : v;
+                rowB[q] = v * iu;
+            }
+#pragma unroll
+            for (int i = 0; i < m; ++i) xr = i == leave ? xB[i] : xr;
+            xr *= iu;
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+                if (i == leave) {
+#pragma unroll
+                    for (int q = 0; q < m; ++q) Bi[i * m + q] = rowB[q];
+                    xB[i] = xr;
+                    basis[i] = enter;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < m; ++q) Bi[i * m + q] -= u[i] * rowB[q];
+                    xB[i] = fmaxf(0.f, xB[i] - u[i] * xr);
+                }
+            }
+        }
+        if (it >= 64) status = 3;
+        if (phase == 1 && status == 0) {
+            // pivot zero-level artificials out of the basis
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+                if (basis[i] < n) continue;
+                int piv = -1;
+                float bestv = 1e-5f, uu[m];
+                for (int j = 0; j < n; ++j) {
+                    bool basic = false;
+#pragma unroll
+                    for (int k = 0; k < m; ++k) basic |= basis[k] == j;
+                    if (basic) continue;
+                    float E[m];
+                    cols.col(j, E);
+                    float ui = 0.f;
+#pragma unroll
+                    for (int q = 0; q < m; ++q) ui += Bi[i * m + q] * E[q];
+                    if (fabsf(ui) > bestv) {
+                        bestv = fabsf(ui);
+                        piv = j;
+#pragma unroll
+                        for (int k = 0; k < m; ++k) {
+                            float acc = 0.f;
+#pragma unroll
+                            for (int q = 0; q < m; ++q) acc += Bi[k * m + q] * E[q];
+                            uu[k] = acc;
+                        }
+                    }
+                }
+                if (piv < 0) continue;
+                const float iu = 1.f / uu[i];
+                float rowB[m];
+#pragma unroll
+                for (int q = 0; q < m; ++q) rowB[q] = Bi[i * m + q] * iu;
+                const float xr = xB[i] * iu;
+#pragma unroll
+                for (int k = 0; k < m; ++k) {
+                    if (k == i) {
+#pragma unroll
+                        for (int q = 0; q < m; ++q) Bi[k * m + q] = rowB[q];
+                        xB[k] = xr;
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < m; ++q) Bi[k * m + q] -= uu[k] * rowB[q];
+                        xB[k] -= uu[k] * xr;
+                    }
+                }
+                basis[i] = piv;
+            }
+        }
+    }
+    // re-solve the optimal basis directly: Bmat x_B = f, pi^T Bmat = c_B^T
+    float Bm[m * m];
+#pragma unroll
+    for (int i = 0; i < m; ++i) {
+        float E[m];
+        if (basis[i] < n) cols.col(basis[i], E);
+        else {
+#pragma unroll
+            for (int q = 0; q < m; ++q) E[q] = q == basis[i] - n ? 1.f : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < m; ++q) Bm[q * m + i] = E[q];   // column i of the basis matrix
+    }
+    // Gauss-Jordan inverse with partial pivoting
+    float Inv[m * m];
+#pragma unroll
+    for (int i = 0; i < m; ++i)
+#pragma unroll
+        for (int j = 0; j < m; ++j) Inv[i * m + j] = i == j ? 1.f : 0.f;
+#pragma unroll
+    for (int k = 0; k < m; ++k) {
+        int p = k;
+        float bv = fabsf(Bm[k * m + k]);
+#pragma unroll
+        for (int i = k + 1; i < m; ++i)
+            if (fabsf(Bm[i * m + k]) > bv) { bv = fabsf(Bm[i * m + k]); p = i; }
+        if (bv > 0.f) {
+#pragma unroll
+            for (int i = k + 1; i < m; ++i) {
+                if (i == p) {
+#pragma unroll
+                    for (int j = 0; j < m; ++j) {
+                        float t1 = Bm[k * m + j]; Bm[k * m + j] = Bm[i * m + j]; Bm[i * m + j] = t1;
+                        float t2 = Inv[k * m + j]; Inv[k * m + j] = Inv[i * m + j]; Inv[i * m + j] = t2;
+                    }
+                }
+            }
+            const float ip = 1.f / Bm[k * m + k];
+#pragma unroll
+            for (int j = 0; j < m; ++j) { Bm[k * m + j] *= ip; Inv[k * m + j] *= ip; }
+#pragma unroll
+            for (int i = 0; i < m; ++i) {
+                if (i == k) continue;
+                const float f = Bm[i * m + k];
+#pragma unroll
+                for (int j = 0; j < m; ++j) { Bm[i * m + j] -= f * Bm[k * m + j]; Inv[i * m + j] -= f * Inv[k * m + j]; }
+            }
+        } else {
+            status = status ? status : 4;
+        }
+    }
+    float cB[m];
+#pragma unroll
+    for (int i = 0; i < m; ++i) cB[i] = basis[i] < n ? cols.cost(basis[i]) : 0.f;
+    float pi0 = 0.f;
+#pragma unroll
+    for (int i = 0; i < m; ++i) pi0 += cB[i] * Inv[i * m + 0];
+#pragma unroll
+    for (int i = 0; i < m; ++i) {
+        xB_out[i] = fmaxf(0.f, Inv[i * m + 0]);   // f = e_0
+        basis_out[i] = basis[i];
+    }
+    alpha = -pi0;
+    return status;
+}
+
+// columns of the ADMM problem's pair (part frame through the pose)
+template <int DIM>
+struct PairCols {
+    int nr, no;
+    const float4* rf;
+    const float4* of;
+    float R[DIM * DIM], pos[DIM];
+    float cmx;
+    __device__ int n() const { return nr + no; }
+    __device__ float cmax() const { return cmx; }
+    __device__ float cost(int j) const {
+        if (j < nr) return 0.f;
+        const float4 f = of[j - nr];
+        float dp = f.w - f.x * pos[0] - f.y * pos[1];
+        if (DIM == 3) dp -= f.z * pos[DIM - 1];
+        return dp;
+    }
+    __device__ void col(int j, float (&E)[DIM + 1]) const {
+        if (j < nr) {
+            const float4 f = rf[j];
+            E[0] = f.w;
+            E[1] = f.x;
+            E[2] = f.y;
+            if (DIM == 3) E[DIM] = f.z;
+        } else {
+            const float4 f = of[j - nr];
+            const float c[3] = {f.x, f.y, f.z};
+            E[0] = 0.f;
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) {
+                float acc = 0.f;
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) acc += R[r * DIM + q] * c[r];
+                E[1 + q] = acc;
+            }
+        }
+    }
+};
+
+// initial dual iterate from the scale LP at the current trajectory:
+// y = (lam*, mu*, max(alpha* - 1, 0)); optionally alpha* per pair.
+template <int DIM>
+__global__ void __launch_bounds__(256) init_pairs_kernel(DevProblem P, float* alpha_out, int write_y)
+{
+    const int b = uniform(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int N = P.N, t = lane + 1;
+    if (b >= P.n_blocks || t > N) return;
+    const int4 blk = P.blocks[b];
+    const int s = blk.x, part = uniform(blk.y), obs = uniform(blk.z);
+    const int fr0 = uniform(P.part_face_ptr[part]);
+    const int fo0 = uniform(P.obs_face_ptr[obs]);
+    PairCols<DIM> pc;
+    pc.nr = uniform(P.part_face_ptr[part + 1] - fr0);
+    pc.no = uniform(P.obs_face_ptr[obs + 1] - fo0);
+    pc.rf = P.part_faces + fr0;
+    pc.of = P.obs_faces + fo0;
+    Pose<DIM> ps;
+    make_pose<DIM>(P, P.x + ((size_t)s * (N + 1) + t) * P.n_s, part, ps);
+#pragma unroll
+    for (int i = 0; i < DIM * DIM; ++i) pc.R[i] = ps.R[i];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) pc.pos[i] = ps.pos[i];
+    float cm = 0.f;
+    for (int l = 0; l < pc.no; ++l) cm = fmaxf(cm, fabsf(pc.cost(pc.nr + l)));
+    pc.cmx = cm;
+    float alpha, xB[DIM + 1];
+    int basis[DIM + 1];
+    revised_simplex<DIM>(pc, alpha, xB, basis);
+    if (alpha_out) alpha_out[(size_t)b * N + t - 1] = alpha;
+    if (write_y) {
+        float* yb = P.y + P.block_yoff[b] + (t - 1);
+        const int nrow = pc.nr + pc.no;
+        for (int j = 0; j < nrow; ++j) {
+            float v = 0.f;
+#pragma unroll
+            for (int i = 0; i <= DIM; ++i) v = basis[i] == j ? xB[i] : v;
+            yb[j * N] = v;
+        }
+        yb[nrow * N] = fmaxf(alpha - 1.f, 0.f);
+    }
+}
+
+// ------------------------------------------------------------------------
+// stateless batch entry points
+// ------------------------------------------------------------------------
+
+template <int DIM>
+__global__ void __launch_bounds__(256) pair_qp_batch_kernel(int n_pairs, const int* row_ptr, const float* K,
+                                                            const float* kappa, const float* yhat,
+                                                            const float* bhat, float eps, int max_sweeps,
+                                                            float* y, float* r, int* status)
+{
+    constexpr int NV = DIM + 2;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_pairs) return;
+    const int r0 = row_ptr[p], n = row_ptr[p + 1] - r0;
+    GenRows<DIM> gr;
+    gr.n = n;
+    gr.K = K + (size_t)r0 * (DIM + 1);
+    gr.kap = kappa + r0;
+    gr.yh = yhat + r0;
+    gr.eps = eps;
+#pragma unroll
+    for (int c = 0; c <= DIM; ++c) gr.bh[c] = bhat[(size_t)p * (DIM + 1) + c];
+    // warm start v = K^T yhat + bhat; nu makes the largest kappa-row stationary
+    float z[NV];
+#pragma unroll
+    for (int c = 0; c <= DIM; ++c) z[c] = gr.bh[c];
+    for (int l = 0; l < n; ++l)
+#pragma unroll
+        for (int c = 0; c <= DIM; ++c) z[c] += gr.yh[l] * gr.K[l * (DIM + 1) + c];
+    float best = -1.f, nu = 0.f;
+    for (int l = 0; l < n; ++l) {
+        if (gr.kap[l] > 0.f && gr.yh[l] > best) {
+            best = gr.yh[l];
+            float s = 0.f;
+#pragma unroll
+            for (int c = 0; c <= DIM; ++c) s += gr.K[l * (DIM + 1) + c] * z[c];
+            nu = s / gr.kap[l];
+        }
+    }
+    z[DIM + 1] = nu;
+    const int sw = dual_newton<NV>(gr, z, max_sweeps);
+    float rr[DIM + 1];
+#pragma unroll
+    for (int c = 0; c <= DIM; ++c) rr[c] = gr.bh[c];
+    for (int l = 0; l < n; ++l) {
+        float D = 0.f, s = -gr.kap[l] * z[DIM + 1];
+#pragma unroll
+        for (int c = 0; c <= DIM; ++c) {
+            const float k = gr.K[l * (DIM + 1) + c];
+            D += k * k;
+            s += k * z[c];
+        }
+        const float yl = fmaxf(0.f, gr.yh[l] - s / (eps * D));
+        y[r0 + l] = yl;
+#pragma unroll
+        for (int c = 0; c <= DIM; ++c) rr[c] += yl * gr.K[l * (DIM + 1) + c];
+    }
+#pragma unroll
+    for (int c = 0; c <= DIM; ++c) r[(size_t)p * (DIM + 1) + c] = rr[c];
+    status[p] = sw;
+}
+
+template <int DIM>
+struct MemCols {
+    int nr, no;
+    const float* A;
+    const float* b;
+    const float* Cp;
+    const float* dp;
+    float cmx;
+    __device__ int n() const { return nr + no; }
+    __device__ float cmax() const { return cmx; }
+    __device__ float cost(int j) const { return j < nr ? 0.f : dp[j - nr]; }
+    __device__ void col(int j, float (&E)[DIM + 1]) const {
+        if (j < nr) {
+            E[0] = b[j];
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) E[1 + q] = A[j * DIM + q];
+        } else {
+            E[0] = 0.f;
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) E[1 + q] = Cp[(j - nr) * DIM + q];
+        }
+    }
+};
+
+template <int DIM>
+__global__ void __launch_bounds__(256) scale_batch_kernel(int n_pairs, const int* a_ptr, const float* A,
+                                                          const float* b, const int* o_ptr, const float* Cp,
+                                                          const float* dp, float* alpha, float* lam,
+                                                          float* mu, int* status)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_pairs) return;
+    const int a0 = a_ptr[p], o0 = o_ptr[p];
+    MemCols<DIM> mc;
+    mc.nr = a_ptr[p + 1] - a0;
+    mc.no = o_ptr[p + 1] - o0;
+    mc.A = A + (size_t)a0 * DIM;
+    mc.b = b + a0;
+    mc.Cp = Cp + (size_t)o0 * DIM;
+    mc.dp = dp + o0;
+    float cm = 0.f;
+    for (int l = 0; l < mc.no; ++l) cm = fmaxf(cm, fabsf(mc.dp[l]));
+    mc.cmx = cm;
+    float al, xB[DIM + 1];
+    int basis[DIM + 1];
+    const int st = revised_simplex<DIM>(mc, al, xB, basis);
+    alpha[p] = al;
+    for (int j = 0; j < mc.nr + mc.no; ++j) {
+        float v = 0.f;
+#pragma unroll
+        for (int i = 0; i <= DIM; ++i) v = basis[i] == j ? xB[i] : v;
+        if (j < mc.nr) lam[a0 + j] = v;
+        else mu[o0 + j - mc.nr] = v;
+    }
+    status[p] = st;
+}
+
+// ------------------------------------------------------------------------
+// misc kernels
+// ------------------------------------------------------------------------
+
+__global__ void fill_kernel(float* p, long long n, float v)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_int_kernel(int* p, long long n, int v)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// tracking cost F (Sec. IV-A eq. navigation_cost) of each scenario
+__global__ void __launch_bounds__(64) cost_kernel(DevProblem P, float* out)
+{
+    const int s = blockIdx.x;
+    const int ns = P.n_s, nu = P.n_u, N = P.N;
+    float acc = 0.f;
+    for (int e = threadIdx.x; e < N * (ns + nu); e += 64) {
+        const int t = e / (ns + nu), k = e % (ns + nu);
+        if (k < ns) {
+            const float* xt = P.x + ((size_t)s * (N + 1) + t + 1) * ns;
+            const float* xr = P.x_ref + ((size_t)s * (N + 1) + t + 1) * ns;
+            float qa = 0.f;
+            for (int j = 0; j < ns; ++j) qa += P.Q_s[k * ns + j] * (xt[j] - xr[j]);
+            acc += (xt[k] - xr[k]) * qa;
+        } else {
+            const int i = k - ns;
+            const float* ut = P.u + ((size_t)s * N + t) * nu;
+            float qa = 0.f;
+            for (int j = 0; j < nu; ++j) qa += P.Q_u[i * nu + j] * ut[j];
+            acc += ut[i] * qa;
+        }
+    }
+    acc = wave_sum(acc);
+    if (threadIdx.x == 0) out[s] = acc;
+}
+
+__global__ void __launch_bounds__(64) min_alpha_kernel(DevProblem P, const float* alpha, float* out)
+{
+    const int s = blockIdx.x;
+    const int2 r = P.scen_wg[s];
+    float m = FLT_MAX;
+    if (r.y > r.x) {
+        const int b0 = P.wg_items[r.x].y, b1 = P.wg_items[r.y - 1].z;
+        for (long long e = (long long)b0 * P.N + threadIdx.x; e < (long long)b1 * P.N; e += 64) m = fminf(m, alpha[e]);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fminf(m, __shfl_xor(m, o, 64));
+    if (threadIdx.x == 0) out[s] = m;
+}
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+
+struct Variant { int dim, mr, mo; };
+static const Variant kVariants[] = {{2, 4, 16}, {2, 8, 32}, {3, 6, 24}, {3, 8, 32}};
+
+bool pair_variant_supported(int dim, int mr, int mo)
+{
+    for (const auto& v : kVariants)
+        if (v.dim == dim && mr <= v.mr && mo <= v.mo) return true;
+    return false;
+}
+
+// first compiled variant whose face limits fit the problem
+static int pick_variant(const DevProblem& P)
+{
+    for (int i = 0; i < 4; ++i)
+        if (kVariants[i].dim == P.dim && P.max_part_faces <= kVariants[i].mr &&
+            P.max_obs_faces <= kVariants[i].mo)
+            return i;
+    return -1;
+}
+
+hipError_t launch_pair_phase(const DevProblem& P, int W, int grid, hipStream_t st)
+{
+    const int v = pick_variant(P);
+    const int nc = P.nc;
+    const size_t lds = (size_t)W * nc * 64 * sizeof(float) + 2 * W * sizeof(float);
+    dim3 blk(64 * W), grd(grid);
+    switch (v) {
+    case 0: hipLaunchKernelGGL((pair_phase_kernel<2, 4, 16>), grd, blk, lds, st, P); break;
+    case 1: hipLaunchKernelGGL((pair_phase_kernel<2, 8, 32>), grd, blk, lds, st, P); break;
+    case 2: hipLaunchKernelGGL((pair_phase_kernel<3, 6, 24>), grd, blk, lds, st, P); break;
+    case 3: hipLaunchKernelGGL((pair_phase_kernel<3, 8, 32>), grd, blk, lds, st, P); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mult_phase(const DevProblem& P, int W, int grid, hipStream_t st)
+{
+    const int v = pick_variant(P);
+    const size_t lds = (size_t)W * sizeof(float);
+    dim3 blk(64 * W), grd(grid);
+    switch (v) {
+    case 0: hipLaunchKernelGGL((mult_phase_kernel<2, 4, 16>), grd, blk, lds, st, P); break;
+    case 1: hipLaunchKernelGGL((mult_phase_kernel<2, 8, 32>), grd, blk, lds, st, P); break;
+    case 2: hipLaunchKernelGGL((mult_phase_kernel<3, 6, 24>), grd, blk, lds, st, P); break;
+    case 3: hipLaunchKernelGGL((mult_phase_kernel<3, 8, 32>), grd, blk, lds, st, P); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t st)
+{
+    const int ns = P.n_s, nu = P.n_u;
+    const size_t floats = (size_t)P.N * P.nc + 4 * ns * ns + ns * nu + 2 * nu * nu + nu * ns + nu * (ns + 1) + 6 * ns + 3 * nu + 8;
+    hipLaunchKernelGGL(traj_phase_kernel, dim3(P.n_scen), dim3(kTrajThreads), floats * sizeof(float), st, P,
+                       obstacle_free);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const DevProblem& P, hipStream_t st)
+{
+    hipLaunchKernelGGL(residual_kernel, dim3(P.n_scen), dim3(64), 0, st, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_pairs(const DevProblem& P, float* alpha_out, int write_y, hipStream_t st)
+{
+    const int grid = (P.n_blocks + 3) / 4;
+    if (grid == 0) return hipSuccess;
+    if (P.dim == 2)
+        hipLaunchKernelGGL(init_pairs_kernel<2>, dim3(grid), dim3(256), 0, st, P, alpha_out, write_y);
+    else
+        hipLaunchKernelGGL(init_pairs_kernel<3>, dim3(grid), dim3(256), 0, st, P, alpha_out, write_y);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, long long n, float v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    long long g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)g), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, long long n, int v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    long long g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)g), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_cost(const DevProblem& P, float* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(cost_kernel, dim3(P.n_scen), dim3(64), 0, st, P, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_min_alpha(const DevProblem& P, const float* alpha, float* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(min_alpha_kernel, dim3(P.n_scen), dim3(64), 0, st, P, alpha, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_qp_batch(int n_pairs, int dim, const int* row_ptr, const float* K, const float* kappa,
+                                const float* yhat, const float* bhat, float eps, int max_sweeps, float* y,
+                                float* r, int* status, hipStream_t st)
+{
+    if (n_pairs <= 0) return hipSuccess;
+    const int grid = (n_pairs + 255) / 256;
+    if (dim == 2)
+        hipLaunchKernelGGL(pair_qp_batch_kernel<2>, dim3(grid), dim3(256), 0, st, n_pairs, row_ptr, K, kappa,
+                           yhat, bhat, eps, max_sweeps, y, r, status);
+    else
+        hipLaunchKernelGGL(pair_qp_batch_kernel<3>, dim3(grid), dim3(256), 0, st, n_pairs, row_ptr, K, kappa,
+                           yhat, bhat, eps, max_sweeps, y, r, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_batch(int n_pairs, int dim, const int* a_ptr, const float* A, const float* b,
+                              const int* o_ptr, const float* Cp, const float* dp, float* alpha, float* lam,
+                              float* mu, int* status, hipStream_t st)
+{
+    if (n_pairs <= 0) return hipSuccess;
+    const int grid = (n_pairs + 255) / 256;
+    if (dim == 2)
+        hipLaunchKernelGGL(scale_batch_kernel<2>, dim3(grid), dim3(256), 0, st, n_pairs, a_ptr, A, b, o_ptr, Cp,
+                           dp, alpha, lam, mu, status);
+    else
+        hipLaunchKernelGGL(scale_batch_kernel<3>, dim3(grid), dim3(256), 0, st, n_pairs, a_ptr, A, b, o_ptr, Cp,
+                           dp, alpha, lam, mu, status);
+    return hipGetLastError();
+}
+
+}  // namespace cadmm

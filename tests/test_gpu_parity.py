@@ -1,0 +1,293 @@
+"""Parity of the HIP path (FP32, through the C ABI) with the FP64 oracle.
+
+Bars: scales alpha* 1e-5 relative; dual variables 1e-5 in the proximal-metric
+scaled norm per pair (sqrt(D_l) y_l, D_l = ||row_l K||^2, relative to
+max(norm, 1)); trajectories 1e-4 relative (normwise over x and u per
+scenario)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from _util import (K_rows, gather_pairs, multiplier_scale, per_pair_y_errors, rel, scaled_pair_error,
+                   scaled_y_errors, traj_error)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_TRAJ = 1e-4
+TOL_DUAL = 1e-5
+TOL_SCALE = 1e-5
+
+
+@pytest.fixture(scope="module")
+def cadmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2406_07048_amd as m
+    m.lib()
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def oracle_iterate(prob, k):
+    """Oracle state after k ADMM iterations (from its own initial iterate)."""
+    P = oracle.Problem(prob)
+    st = P.init_state()
+    if k:
+        P.run(st, k)
+    return P, st
+
+
+def to_dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+# --------------------------------------------------------------- stateless QPs
+@pytest.mark.parametrize("name,k", [("c1", 0), ("c1", 5), ("c2", 3), ("c3", 3)])
+def test_pair_qp_batch_parity(cadmm, name, k):
+    prob = workloads.make(name)
+    say(f"[pair_qp_batch] {name} iterate {k}")
+    P, st = oracle_iterate(prob, k)
+    layout = workloads.block_layout(prob)
+    nb = len(layout[0])
+    rng = np.random.default_rng(0)
+    pairs = [(int(rng.integers(nb)), int(rng.integers(1, prob["N"] + 1))) for _ in range(600)]
+    row_ptr, K, kap, yh, bh, geo = gather_pairs(prob, st, pairs, layout)
+    y, r, status = cadmm.pair_qp_batch(to_dev(row_ptr, torch.int32), to_dev(K), to_dev(kap), to_dev(yh),
+                                       to_dev(bh), prob["eps_prox"])
+    torch.cuda.synchronize()
+    y, r, status = y.cpu().numpy().astype(np.float64), r.cpu().numpy(), status.cpu().numpy()
+    worst = 0.0
+    for p, (A, bb, Cp, dp, z, xi) in enumerate(geo):
+        yo, it = oracle.pair_qp(A, bb, Cp, dp, z, xi, yh[row_ptr[p]:row_ptr[p + 1]], prob["eps_prox"])
+        assert it >= 0
+        Kp = K[row_ptr[p]:row_ptr[p + 1]]
+        e = scaled_pair_error(Kp, y[row_ptr[p]:row_ptr[p + 1]], yo)
+        worst = max(worst, e)
+        ro = Kp.T @ yo + bh[p]
+        # r = K^T y + bhat is a sum of terms of size ||K_l||_1 y_l
+        assert np.abs(r[p] - ro).max() <= 1e-5 * (1.0 + (np.abs(Kp).sum(1) * yo).sum())
+    say(f"   worst scaled dual error {worst:.2e}, sweeps max {status.max()}, unconverged {(status < 0).sum()}")
+    assert worst <= TOL_DUAL
+
+
+def test_pair_qp_batch_edge_cases(cadmm):
+    """Empty batch; a single-row-class pair; the largest pair (8 + 32 + 1 rows);
+    a pair whose centre yhat is already optimal."""
+    z = torch.zeros(1, dtype=torch.int32, device="cuda")
+    e = torch.zeros((0, 3), device="cuda")
+    y, r, s = cadmm.pair_qp_batch(z, e, torch.zeros(0, device="cuda"), torch.zeros(0, device="cuda"),
+                                  torch.zeros((0, 3), device="cuda"), 0.1)
+    assert y.numel() == 0 and s.numel() == 0
+    rng = np.random.default_rng(4)
+    for n_o in (3, 32):
+        A = np.concatenate([np.eye(2), -np.eye(2), [[0.6, 0.8], [-0.6, 0.8], [0.6, -0.8], [-0.6, -0.8]]])
+        b = np.r_[1.0, 1.0, 1.0, 1.0, 1.3, 1.3, 1.3, 1.3]
+        ang = np.sort(rng.uniform(0, 2 * np.pi, n_o))
+        Cp = np.stack([np.cos(ang), np.sin(ang)], 1)
+        dp = 1.0 + Cp @ np.array([4.0, 1.0])
+        K = K_rows(A, Cp, dp)
+        yh = np.abs(rng.normal(size=len(K)))
+        bh = np.array([1.3, 0.2, -0.1])
+        y, r, st = cadmm.pair_qp_batch(to_dev(np.array([0, len(K)], np.int32), torch.int32), to_dev(K),
+                                       to_dev(np.r_[b, np.zeros(n_o + 1)]), to_dev(yh), to_dev(bh[None]), 0.1)
+        yo, it = oracle.pair_qp(A, b, Cp, dp, bh[0] - 1.0, bh[1:], yh, 0.1)
+        assert scaled_pair_error(K, y.cpu().numpy().astype(np.float64), yo) <= TOL_DUAL
+
+
+# --------------------------------------------------------------- scale LP
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_scale_batch_parity(cadmm, name):
+    prob = workloads.make(name)
+    say(f"[pair_scale_batch] {name}")
+    P, st = oracle_iterate(prob, 0)
+    layout = workloads.block_layout(prob)
+    nb = len(layout[0])
+    rng = np.random.default_rng(1)
+    pairs = [(int(rng.integers(nb)), int(rng.integers(1, prob["N"] + 1))) for _ in range(400)]
+    row_ptr, K, kap, yh, bh, geo = gather_pairs(prob, st, pairs, layout)
+    a_ptr, o_ptr = [0], [0]
+    A, bv, Cp, dp = [], [], [], []
+    for (Ai, bi, Ci, di, _, _) in geo:
+        A.append(Ai); bv.append(bi); Cp.append(Ci); dp.append(di)
+        a_ptr.append(a_ptr[-1] + len(bi)); o_ptr.append(o_ptr[-1] + len(di))
+    alpha, lam, mu, status = cadmm.pair_scale_batch(
+        to_dev(np.array(a_ptr, np.int32), torch.int32), to_dev(np.concatenate(A)), to_dev(np.concatenate(bv)),
+        to_dev(np.array(o_ptr, np.int32), torch.int32), to_dev(np.concatenate(Cp)), to_dev(np.concatenate(dp)))
+    torch.cuda.synchronize()
+    alpha, lam, mu, status = (t.cpu().numpy() for t in (alpha, lam, mu, status))
+    assert (status == 0).all()
+    worst = 0.0
+    for p, (Ai, bi, Ci, di, _, _) in enumerate(geo):
+        ao, xo, lo, mo, gap, sto = oracle.scale_lp(Ai, bi, Ci, di)
+        e = abs(alpha[p] - ao) / max(abs(ao), 1e-3)
+        worst = max(worst, e)
+        # dual certificate: feasible and attaining alpha (unique unless degenerate)
+        l_g = lam[a_ptr[p]:a_ptr[p + 1]].astype(np.float64)
+        m_g = mu[o_ptr[p]:o_ptr[p + 1]].astype(np.float64)
+        assert abs(bi @ l_g - 1.0) < 1e-5
+        assert np.abs(Ai.T @ l_g + Ci.T @ m_g).max() < 1e-4
+        assert abs(-di @ m_g - ao) <= 1e-4 * max(1.0, abs(ao))
+    say(f"   worst alpha rel error {worst:.2e}")
+    assert worst <= TOL_SCALE
+
+
+def test_scale_box_golden(cadmm):
+    """Hand-worked box cases of the closed form (tests/golden/box_scale.txt)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "box_scale.txt")
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        dim, h, lo, hi, a = [s.strip() for s in line.split("|")]
+        dim = int(dim)
+        h, lo, hi = (np.array(v.split(), float) for v in (h, lo, hi))
+        A = np.concatenate([np.eye(dim), -np.eye(dim)])
+        b = np.r_[h, h]
+        d = np.r_[hi, -lo]
+        alpha, lam, mu, st = cadmm.pair_scale_batch(
+            to_dev(np.array([0, 2 * dim], np.int32), torch.int32), to_dev(A), to_dev(b),
+            to_dev(np.array([0, 2 * dim], np.int32), torch.int32), to_dev(A), to_dev(d))
+        assert abs(alpha.item() - float(a)) <= TOL_SCALE * max(1.0, float(a))
+
+
+# --------------------------------------------------------------- ADMM path
+def gpu_state(h):
+    st = h.get_state()
+    torch.cuda.synchronize()
+    return {k: v.double().cpu().numpy() for k, v in st.items()}
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_setup_initial_iterate(cadmm, name):
+    """Initial iterate: obstacle-free LQ trajectory, zero multipliers and a
+    scale-LP certificate per pair. alpha* is unique and compared; the dual
+    certificate is unique only for non-degenerate LPs (in 3D a triangulated
+    obstacle vertex usually has more than three incident faces, so many
+    optimal duals exist): it is checked for validity, i.e. at s^0 it gives
+    T = max(0, 1 - alpha*) and R = 0, plus exact agreement in 2D."""
+    prob = workloads.make(name)
+    say(f"[setup] {name}")
+    h = cadmm.Handle(prob)
+    g = gpu_state(h)
+    alpha_g = h.scales().double().cpu().numpy()
+    P, st = oracle_iterate(prob, 0)
+    alpha_o = P.scale_all(st["x"])
+    ea = (np.abs(alpha_g - alpha_o) / np.maximum(np.abs(alpha_o), 1e-3)).max()
+    T, R, _ = P.mult_phase(g["x"], g["y"], np.zeros_like(g["zeta"]), np.zeros_like(g["xi"]))
+    msc = multiplier_scale(prob, g["x"], g["y"])
+    eT = (np.abs(T - np.maximum(0.0, 1.0 - alpha_o)) / msc).max()
+    eR = (np.abs(R).reshape(-1, prob["dim"], prob["N"]) / msc.reshape(-1, 1, prob["N"])).max()
+    ny = g["y"] < -1e-7
+    say(f"   s0 err {traj_error(g, st):.1e}, alpha {ea:.2e}, certificate T {eT:.2e} R {eR:.2e}")
+    assert traj_error(g, st) < 1e-5
+    assert ea <= TOL_SCALE
+    assert eT <= 1e-5 and eR <= 1e-5 and not ny.any()
+    if prob["dim"] == 2:
+        errs = per_pair_y_errors(prob, g["y"], st["y"])
+        assert errs.max() <= 1e-4
+    assert np.abs(g["zeta"]).max() == 0 and np.abs(g["xi"]).max() == 0
+    h.close()
+
+
+@pytest.mark.parametrize("name,k", [("c1", 4), ("c2", 10), ("c3", 3)])
+def test_one_step_parity(cadmm, name, k):
+    """From a shared oracle iterate k, one GPU iteration equals one oracle
+    iteration (pair QPs, trajectory QP, multiplier update)."""
+    prob = workloads.make(name)
+    say(f"[one step] {name} from iterate {k}")
+    P, st = oracle_iterate(prob, k)
+    h = cadmm.Handle(prob)
+    h.set_state(x=st["x"], u=st["u"], y=st["y"], zeta=st["zeta"], xi=st["xi"])
+    h.iterate(1)
+    g = gpu_state(h)
+    xk = st["x"].copy()
+    zk, xik = st["zeta"].copy(), st["xi"].copy()
+    P.run(st, 1)
+    et = traj_error(g, st)
+    ey = scaled_y_errors(prob, xk, g["y"], st["y"])
+    dim, N = prob["dim"], prob["N"]
+    msc = multiplier_scale(prob, st["x"], st["y"])
+    # step 3 in isolation: the oracle's multiplier update applied to the GPU's
+    # own (x^{k+1}, y^{k+1}) must give the GPU's multipliers
+    z3, xi3, _ = P.mult_phase(g["x"], g["y"], zk, xik)
+    ez3 = (np.abs(g["zeta"] - z3) / msc).max()
+    exi3 = (np.abs(g["xi"] - xi3).reshape(-1, dim, N) / msc.reshape(-1, 1, N)).max()
+    # end to end the multipliers inherit the trajectory's rounding through T, R
+    ez = (np.abs(g["zeta"] - st["zeta"]) / msc).max()
+    exi = (np.abs(g["xi"] - st["xi"]).reshape(-1, dim, N) / msc.reshape(-1, 1, N)).max()
+    say(f"   traj {et:.2e} y worst {ey.max():.2e} | step-3 zeta {ez3:.2e} xi {exi3:.2e} "
+        f"| end-to-end zeta {ez:.2e} xi {exi:.2e}")
+    assert et <= TOL_TRAJ and ey.max() <= TOL_DUAL
+    assert ez3 <= 1e-5 and exi3 <= 1e-5
+    assert ez <= 1e-3 and exi <= 1e-3
+    h.close()
+
+
+def test_full_run_c1(cadmm):
+    """C1 (the FP64 oracle configuration) run to convergence on the GPU in
+    FP32: trajectory within 1e-4 of the oracle's, same stopping iteration."""
+    prob = workloads.make("c1")
+    say("[full run] c1")
+    h = cadmm.Handle(prob)
+    code, res = h.solve(200, check_every=1)
+    g = gpu_state(h)
+    P, st = oracle_iterate(prob, 0)
+    hist = P.run(st, 200)
+    say(f"   gpu iters {res[0]['iters']} oracle {hist['iters'][0]}; traj err {traj_error(g, st):.2e}")
+    assert traj_error(g, st) <= TOL_TRAJ
+    assert abs(res[0]["iters"] - hist["iters"][0]) <= 1
+    assert res[0]["min_alpha"] > 0.95
+    h.close()
+
+
+def test_batched_equals_separate(cadmm):
+    """Batched scenarios give bit-identical iterates to separate handles
+    (same kernels, same fixed reduction order)."""
+    prob = workloads.config_c4(n_scen=6, m_range=(10, 30))
+    say("[batched vs separate] 6 scenarios")
+    h = cadmm.Handle(prob, waves_per_group=4)
+    h.iterate(12)
+    g = gpu_state(h)
+    h.close()
+    for s in range(6):
+        q = workloads.select_scenarios(prob, [s])
+        hs = cadmm.Handle(q, waves_per_group=4)
+        hs.iterate(12)
+        gs = gpu_state(hs)
+        hs.close()
+        assert np.array_equal(gs["x"][0], g["x"][s])
+
+
+def test_replay_is_deterministic(cadmm):
+    prob = workloads.make("c2")
+    say("[determinism] c2")
+    h = cadmm.Handle(prob)
+    h.iterate(20)
+    a = gpu_state(h)
+    h.reset()
+    h.iterate(13)
+    h.iterate(7)
+    b = gpu_state(h)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    h.close()
+
+
+def test_far_obstacles_fixed_point(cadmm):
+    prob = workloads.make("c1", seed=3)
+    say("[fixed point] c1 seed 3")
+    h = cadmm.Handle(prob)
+    g0 = gpu_state(h)
+    code, res = h.solve(10, check_every=1)
+    g1 = gpu_state(h)
+    assert res[0]["iters"] == 1 and res[0]["converged"]
+    assert np.abs(g1["x"] - g0["x"]).max() < 1e-4
+    # zeta = T at a certificate: zero up to the rounding of 1 + d'^T mu + gamma
+    assert np.abs(g1["zeta"]).max() <= 1e-6 * (1.0 + g0["y"].max())
+    h.close()
