@@ -39,9 +39,9 @@ struct Layout {
     long long n_pairs, y_floats;
     int nc, nq, n_att, max_pf, max_of;
     // byte offsets into the workspace
-    size_t part_faces, part_face_ptr, part_off, obs_faces, obs_face_ptr, blocks, block_yoff, wg_items, scen_wg;
+    size_t part_faces, part_face_ptr, part_off, obs_faces, obs_d64, obs_face_ptr, blocks, block_yoff, wg_items, scen_wg;
     size_t A_dyn, B_dyn, c_dyn, Q_s, Q_u, x_ref, x0;
-    size_t x, u, y, zeta, xi, y_snap;
+    size_t x, u, y, zeta, xi, y_snap, x_snap, u_snap;
     size_t contrib, rdual_part, rpri_part, unconv_part;
     size_t r_pri, r_dual, done, iters, unconv, hist_pri, hist_dual, Kgain, alpha, cost, min_alpha;
     size_t total;
@@ -150,6 +150,7 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
     L.part_face_ptr = take(off, sizeof(int) * (d->n_parts + 1));
     L.part_off = take(off, sizeof(float) * 3 * d->n_parts);
     L.obs_faces = take(off, sizeof(float4) * std::max(Fo, 1));
+    L.obs_d64 = take(off, sizeof(double) * std::max(Fo, 1));
     L.obs_face_ptr = take(off, sizeof(int) * (M + 1));
     L.blocks = take(off, sizeof(int4) * nb);
     L.block_yoff = take(off, sizeof(int) * nb);
@@ -168,6 +169,8 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
     L.zeta = take(off, sizeof(float) * std::max<long long>(L.n_pairs, 1));
     L.xi = take(off, sizeof(float) * std::max<long long>(L.n_pairs * dim, 1));
     L.y_snap = take(off, sizeof(float) * std::max<long long>(yf, 1));
+    L.x_snap = take(off, sizeof(float) * d->n_scen * (N + 1) * ns);
+    L.u_snap = take(off, sizeof(float) * d->n_scen * N * nu);
     L.contrib = take(off, sizeof(float) * (size_t)nb * L.nc * 64);
     L.rdual_part = take(off, sizeof(float) * nb);
     L.rpri_part = take(off, sizeof(float) * nb);
@@ -301,39 +304,51 @@ int init_iterate(cadmm_handle* h)
     return CADMM_OK;
 }
 
-// choose waves per workgroup by timing the pair kernel from the same iterate
+// choose waves per workgroup by timing the pair phase and the trajectory
+// phase (whose per-step reduction reads one partial per workgroup) from the
+// same iterate
 int autotune(cadmm_handle* h)
 {
     const Layout& L = h->L;
     if (L.n_blocks == 0) return upload_worklists(h, 1);
     hipStream_t st = h->stream;
-    HIP_TRY(hipMemcpyAsync(h->ws + L.y_snap, h->ws + L.y, sizeof(float) * L.y_floats, hipMemcpyDeviceToDevice, st));
+    const size_t yb = sizeof(float) * L.y_floats, xb = sizeof(float) * L.n_scen * (L.N + 1) * L.n_s,
+                 ub = sizeof(float) * L.n_scen * L.N * L.n_u;
+    HIP_TRY(hipMemcpyAsync(h->ws + L.y_snap, h->ws + L.y, yb, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(h->ws + L.x_snap, h->ws + L.x, xb, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(h->ws + L.u_snap, h->ws + L.u, ub, hipMemcpyDeviceToDevice, st));
+    auto restore = [&]() -> int {
+        HIP_TRY(hipMemcpyAsync(h->ws + L.y, h->ws + L.y_snap, yb, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(h->ws + L.x, h->ws + L.x_snap, xb, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(h->ws + L.u, h->ws + L.u_snap, ub, hipMemcpyDeviceToDevice, st));
+        return CADMM_OK;
+    };
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     const int cands[] = {1, 2, 4, 8};
     float best = 1e30f;
-    int bestW = 4;
+    int bestW = 4, rc;
     for (int W : cands) {
-        if (W > 1 && (W / 2) * 1 >= L.n_blocks) break;
-        int rc = upload_worklists(h, W);
-        if (rc) return rc;
+        if (W > 1 && W / 2 >= L.n_blocks) break;
+        if ((rc = upload_worklists(h, W))) return rc;
         float tot = 0.f;
         for (int rep = 0; rep < 4; ++rep) {
-            HIP_TRY(hipMemcpyAsync(h->ws + L.y, h->ws + L.y_snap, sizeof(float) * L.y_floats, hipMemcpyDeviceToDevice, st));
+            if ((rc = restore())) return rc;
             HIP_TRY(hipEventRecord(e0, st));
             HIP_TRY(launch_pair_phase(h->P, h->W, h->grid, st));
+            HIP_TRY(launch_traj_phase(h->P, 0, st));
             HIP_TRY(hipEventRecord(e1, st));
             HIP_TRY(hipEventSynchronize(e1));
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (rep > 0) tot += ms;   // first run warms caches and code
+            if (rep > 0) tot += ms;   // the first run warms caches and code
         }
         if (tot < best) { best = tot; bestW = W; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    HIP_TRY(hipMemcpyAsync(h->ws + L.y, h->ws + L.y_snap, sizeof(float) * L.y_floats, hipMemcpyDeviceToDevice, st));
+    if ((rc = restore())) return rc;
     return upload_worklists(h, bestW);
 }
 
@@ -438,6 +453,7 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
         (rc = up(L.part_face_ptr, d->part_face_ptr, sizeof(int) * (L.n_parts + 1))) ||
         (rc = up(L.part_off, poff.data(), sizeof(float) * poff.size())) ||
         (rc = up(L.obs_faces, of.data(), sizeof(float4) * L.Fo)) ||
+        (rc = up(L.obs_d64, d->obs_d, sizeof(double) * L.Fo)) ||
         (rc = up(L.obs_face_ptr, d->obs_face_ptr, sizeof(int) * (L.M + 1))) ||
         (rc = up(L.blocks, blocks.data(), sizeof(int4) * blocks.size())) ||
         (rc = up(L.block_yoff, yoff.data(), sizeof(int) * yoff.size())) ||
@@ -466,6 +482,7 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     P.part_face_ptr = at<int>(h, L.part_face_ptr);
     P.part_off = at<float>(h, L.part_off);
     P.obs_faces = at<float4>(h, L.obs_faces);
+    P.obs_d64 = at<double>(h, L.obs_d64);
     P.obs_face_ptr = at<int>(h, L.obs_face_ptr);
     P.blocks = at<int4>(h, L.blocks);
     P.block_yoff = at<int>(h, L.block_yoff);

@@ -23,6 +23,7 @@ struct DevProblem {
     const int* part_face_ptr;    // [P+1]
     const float* part_off;       // [P*3]
     const float4* obs_faces;     // [F_o] (c_x, c_y, c_z, d)
+    const double* obs_d64;       // [F_o] face offsets d in FP64
     const int* obs_face_ptr;     // [M+1]
     // pair blocks and work lists
     const int4* blocks;          // [n_blocks] (scenario, part, obstacle, n_rows)

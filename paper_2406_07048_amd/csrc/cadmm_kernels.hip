@@ -89,8 +89,21 @@ struct Pose {
     float R[DIM * DIM];
     float dR[NATT * DIM * DIM];
     float pos[DIM];
+    double pos64[DIM];   // the same centre in FP64 (the state entries are exact in it)
     float q[NQ];   // pose coordinates (position, attitude) of the state
 };
+
+// Face offset of an obstacle face in the part frame, d'_l = d_l - c_l.pos.
+// Formed in FP64 from the FP64 offset and the FP64 part centre: both are
+// world-frame numbers of the size of the scene while d'_l is of the size of
+// the clearance, so FP32 would lose most of its digits to cancellation.
+__device__ __forceinline__ float face_offset(const double* d64, int face, const float4& f, const double* pos64,
+                                             int dim)
+{
+    double acc = d64[face] - (double)f.x * pos64[0] - (double)f.y * pos64[1];
+    if (dim == 3) acc -= (double)f.z * pos64[2];
+    return (float)acc;
+}
 
 template <int DIM>
 __device__ __forceinline__ void make_pose(const DevProblem& P, const float* xs, int part, Pose<DIM>& ps)
@@ -129,11 +142,13 @@ __device__ __forceinline__ void make_pose(const DevProblem& P, const float* xs, 
     const float* o = P.part_off + part * 3;
 #pragma unroll
     for (int r = 0; r < DIM; ++r) {
-        float acc = xs[P.pos_idx[r]];
-        ps.q[r] = acc;
+        const float p = xs[P.pos_idx[r]];
+        ps.q[r] = p;
+        float ro = 0.f;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) acc += ps.R[r * DIM + c] * o[c];
-        ps.pos[r] = acc;
+        for (int c = 0; c < DIM; ++c) ro += ps.R[r * DIM + c] * o[c];
+        ps.pos[r] = p + ro;
+        ps.pos64[r] = (double)p + (double)ro;
     }
 }
 
@@ -523,9 +538,10 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
                     const float c[3] = {f.x, f.y, f.z};
                     const float yl = yb[(pr.nr + l) * N];
                     pr.yhO[l] = yl;
-                    float dp = f.w, cn = 0.f;
+                    const float dp = face_offset(P.obs_d64, fo0 + l, f, ps.pos64, DIM);
+                    float cn = 0.f;
 #pragma unroll
-                    for (int r = 0; r < DIM; ++r) { dp -= c[r] * ps.pos[r]; cn += c[r] * c[r]; }
+                    for (int r = 0; r < DIM; ++r) cn += c[r] * c[r];
                     const float D = dp * dp + cn;
                     pr.ieO[l] = 1.0f / (eps * D);
                     pr.dpO[l] = dp;
@@ -744,8 +760,7 @@ __global__ void __launch_bounds__(512) mult_phase_kernel(DevProblem P)
                 if (l < no) {
                     const float4 f = P.obs_faces[fo0 + l];
                     const float y = yb[(nr + l) * N];
-                    float dp = f.w - f.x * ps.pos[0] - f.y * ps.pos[1];
-                    if (DIM == 3) dp -= f.z * ps.pos[DIM - 1];
+                    const float dp = face_offset(P.obs_d64, fo0 + l, f, ps.pos64, DIM);
                     Sd += dp * y;
                     Sc[0] += f.x * y;
                     Sc[1] += f.y * y;
@@ -820,192 +835,272 @@ __global__ void __launch_bounds__(64) residual_kernel(DevProblem P)
 
 constexpr int kTrajThreads = 256;
 
+// Dynamic LDS floats of the trajectory kernel for padded sizes NS, NU.
+__host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc)
+{
+    return N * nc + N * NS + N * NU * (NS + 1);
+}
+
+// Trajectory QP of one scenario per workgroup. State/input sizes are padded
+// to the compile-time NS >= n_s, NU >= n_u with zero dynamics rows/columns
+// and an identity input-cost block, so every small product unrolls.
+template <int NS, int NU>
 __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, int obstacle_free)
 {
-    extern __shared__ float sm[];
+    constexpr int NSU = NS + 1;
+    __shared__ float A[NS * NS], B[NS * NU], c[NS], Q2[NS * NS], R2[NU * NU];
+    __shared__ int hmap[NS * NS], gmap[NS];
+    __shared__ float Pm[NS * NS], pv[NS], PA[NS * NS], PB[NS * NU], wv[NS];
+    __shared__ float Quu[NU * NU], Qux[NU * NS], qu[NU], Qxx[NS * NS], qx[NS];
+    __shared__ float xbuf[2][NS];
+    extern __shared__ float dyn[];
     const int s = blockIdx.x;
     if (!obstacle_free && P.done[s]) return;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x;
     const int ns = P.n_s, nu = P.n_u, N = P.N, nq = P.nq, nc = P.nc;
-    // LDS layout
-    float* Hq = sm;                      // [N][nc] reduced contributions
-    float* Pm = Hq + N * nc;             // [ns*ns]
-    float* pv = Pm + ns * ns;            // [ns]
-    float* PA = pv + ns;                 // [ns*ns]
-    float* PB = PA + ns * ns;            // [ns*nu]
-    float* wv = PB + ns * nu;            // [ns]
-    float* Quu = wv + ns;                // [nu*nu]
-    float* Qux = Quu + nu * nu;          // [nu*ns]
-    float* qu = Qux + nu * ns;           // [nu]
-    float* Qxx = qu + nu;                // [ns*ns]
-    float* qx = Qxx + ns * ns;           // [ns]
-    float* Kk = qx + ns;                 // [nu*(ns+1)] current gain (K | k)
-    float* xs = Kk + nu * (ns + 1);      // [ns] rollout state
-    float* us = xs + ns;                 // [nu]
-    float* Lq = us + nu;                 // [nu*nu] Cholesky factor of Quu
-    const float* A = P.A_dyn;
-    const float* B = P.B_dyn;
-    const float* c = P.c_dyn;
-    int* qidx = reinterpret_cast<int*>(Lq + nu * nu);   // [nq] state index of each pose coordinate
-    if (tid < P.dim) qidx[tid] = P.pos_idx[tid];
-    else if (tid < P.dim + P.n_att) qidx[tid] = P.att_idx[tid - P.dim];
+    float* Hq = dyn;                       // [N][nc] reduced contributions
+    float* qr = Hq + N * nc;               // [N][NS] -2 Q_s xref_t, t = 1..N
+    float* Kall = qr + N * NS;             // [N][NU][NS+1] gains [K | k]
 
-    // 1. reduce the contribution partials of this scenario's workgroups
+    // 0. padded model and cost, pose-coordinate maps
+    for (int e = tid; e < NS * NS; e += kTrajThreads) {
+        const int i = e / NS, j = e % NS;
+        const bool in = i < ns && j < ns;
+        A[e] = in ? P.A_dyn[i * ns + j] : 0.f;
+        Q2[e] = in ? 2.f * P.Q_s[i * ns + j] : 0.f;
+        int ci = -1, cj = -1;
+        for (int a = 0; a < nq; ++a) {
+            const int qa = a < P.dim ? P.pos_idx[a] : P.att_idx[a - P.dim];
+            if (qa == i) ci = a;
+            if (qa == j) cj = a;
+        }
+        int m = -1;
+        if (in && ci >= 0 && cj >= 0) {
+            const int a = ci < cj ? ci : cj, b2 = ci < cj ? cj : ci;
+            m = a * nq - a * (a - 1) / 2 + (b2 - a);     // packed upper-triangle index
+        }
+        hmap[e] = m;
+    }
+    for (int e = tid; e < NS * NU; e += kTrajThreads) {
+        const int i = e / NU, j = e % NU;
+        B[e] = (i < ns && j < nu) ? P.B_dyn[i * nu + j] : 0.f;
+    }
+    for (int e = tid; e < NU * NU; e += kTrajThreads) {
+        const int i = e / NU, j = e % NU;
+        R2[e] = (i < nu && j < nu) ? 2.f * P.Q_u[i * nu + j] : (i == j ? 1.f : 0.f);
+    }
+    if (tid < NS) {
+        c[tid] = tid < ns ? P.c_dyn[tid] : 0.f;
+        int m = -1;
+        for (int a = 0; a < nq; ++a) {
+            const int qa = a < P.dim ? P.pos_idx[a] : P.att_idx[a - P.dim];
+            if (qa == tid && tid < ns) m = nq * (nq + 1) / 2 + a;
+        }
+        gmap[tid] = m;
+    }
+    // 1. per-step sums of the pair contributions (fixed order over this
+    //    scenario's workgroups) and the reference gradients
+    const float* xref = P.x_ref + (size_t)s * (N + 1) * ns;
     if (!obstacle_free) {
         const int2 r = P.scen_wg[s];
-        for (int e = tid; e < N * nc; e += nt) {
-            const int t = e / nc, cc = e % nc;
+        for (int e = tid; e < N * nc; e += kTrajThreads) {
+            const int cc = e / N, t = e % N;
+            const float* src = P.contrib + (size_t)cc * 64 + t;
             float acc = 0.f;
-            for (int w = r.x; w < r.y; ++w) acc += P.contrib[((size_t)w * nc + cc) * 64 + t];
+            for (int w = r.x; w < r.y; ++w) acc += src[(size_t)w * nc * 64];
             Hq[t * nc + cc] = acc;
         }
     } else {
-        for (int e = tid; e < N * nc; e += nt) Hq[e] = 0.f;
+        for (int e = tid; e < N * nc; e += kTrajThreads) Hq[e] = 0.f;
+    }
+    for (int e = tid; e < N * NS; e += kTrajThreads) {
+        const int t = e / NS, i = e % NS;
+        float acc = 0.f;
+        if (i < ns)
+            for (int j = 0; j < ns; ++j) acc += P.Q_s[i * ns + j] * xref[(t + 1) * ns + j];
+        qr[e] = -2.f * acc;
     }
     __syncthreads();
-    const float* xref = P.x_ref + (size_t)s * (N + 1) * ns;
-    float* Kg = P.Kgain + (size_t)s * N * nu * (ns + 1);
-    // stage Hessian/gradient of step t (1..N) into (Hout, hout)
-    auto stage = [&](int t, float* Hout, float* hout) {
-        for (int e = tid; e < ns * ns; e += nt) Hout[e] = 2.f * P.Q_s[e];
-        for (int i = tid; i < ns; i += nt) {
-            float acc = 0.f;
-            for (int j = 0; j < ns; ++j) acc += P.Q_s[i * ns + j] * xref[t * ns + j];
-            hout[i] = -2.f * acc;
-        }
-        __syncthreads();
-        const float* hq = Hq + (t - 1) * nc;
-        if (tid == 0) {
-            int idx = 0;
-            for (int i = 0; i < nq; ++i)
-                for (int j = i; j < nq; ++j) {
-                    const float v = hq[idx++];
-                    Hout[qidx[i] * ns + qidx[j]] += v;
-                    if (i != j) Hout[qidx[j] * ns + qidx[i]] += v;
-                }
-            for (int i = 0; i < nq; ++i) hout[qidx[i]] += hq[idx++];
-        }
-        __syncthreads();
-    };
-    // 2. backward Riccati sweep: V_{t}(x) = 1/2 x^T P x + p^T x
-    stage(N, Pm, pv);
+    // 2. backward Riccati sweep, V_t(x) = 1/2 x^T P x + p^T x, P_N = H_N
+    for (int e = tid; e < NS * NS; e += kTrajThreads) Pm[e] = Q2[e] + (hmap[e] >= 0 ? Hq[(N - 1) * nc + hmap[e]] : 0.f);
+    if (tid < NS) pv[tid] = qr[(N - 1) * NS + tid] + (gmap[tid] >= 0 ? Hq[(N - 1) * nc + gmap[tid]] : 0.f);
+    __syncthreads();
     for (int t = N - 1; t >= 0; --t) {
-        for (int e = tid; e < ns * ns; e += nt) {
-            const int i = e / ns, j = e % ns;
-            float acc = 0.f;
-            for (int k = 0; k < ns; ++k) acc += Pm[i * ns + k] * A[k * ns + j];
-            PA[e] = acc;
-        }
-        for (int e = tid; e < ns * nu; e += nt) {
-            const int i = e / nu, j = e % nu;
-            float acc = 0.f;
-            for (int k = 0; k < ns; ++k) acc += Pm[i * ns + k] * B[k * nu + j];
-            PB[e] = acc;
-        }
-        for (int i = tid; i < ns; i += nt) {
-            float acc = pv[i];
-            for (int k = 0; k < ns; ++k) acc += Pm[i * ns + k] * c[k];
-            wv[i] = acc;
-        }
-        __syncthreads();
-        for (int e = tid; e < nu * nu; e += nt) {
-            const int i = e / nu, j = e % nu;
-            float acc = 2.f * P.Q_u[e];
-            for (int k = 0; k < ns; ++k) acc += B[k * nu + i] * PB[k * nu + j];
-            Quu[e] = acc;
-        }
-        for (int e = tid; e < nu * ns; e += nt) {
-            const int i = e / ns, j = e % ns;
-            float acc = 0.f;
-            for (int k = 0; k < ns; ++k) acc += B[k * nu + i] * PA[k * ns + j];
-            Qux[e] = acc;
-        }
-        for (int i = tid; i < nu; i += nt) {
-            float acc = 0.f;
-            for (int k = 0; k < ns; ++k) acc += B[k * nu + i] * wv[k];
-            qu[i] = acc;
+        // a. PA = P A, PB = P B, w = P c + p
+        for (int e = tid; e < NS * NS + NS * NU + NS; e += kTrajThreads) {
+            if (e < NS * NS) {
+                const int i = e / NS, j = e % NS;
+                float acc = 0.f;
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) acc += Pm[i * NS + k2] * A[k2 * NS + j];
+                PA[e] = acc;
+            } else if (e < NS * NS + NS * NU) {
+                const int f = e - NS * NS, i = f / NU, j = f % NU;
+                float acc = 0.f;
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) acc += Pm[i * NS + k2] * B[k2 * NU + j];
+                PB[f] = acc;
+            } else {
+                const int i = e - NS * NS - NS * NU;
+                float acc = pv[i];
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) acc += Pm[i * NS + k2] * c[k2];
+                wv[i] = acc;
+            }
         }
         __syncthreads();
-        // gains K = -Quu^{-1} [Qux | qu]: Cholesky factor of Quu (nu <= 8) by one
-        // thread into LDS, then one column of the right-hand side per thread,
-        // solved in place in the LDS gain buffer
-        if (tid == 0) {
-            for (int i = 0; i < nu; ++i)
-                for (int j = 0; j <= i; ++j) {
-                    float sum = Quu[i * nu + j];
-                    for (int k = 0; k < j; ++k) sum -= Lq[i * nu + k] * Lq[j * nu + k];
-                    if (i == j) Lq[i * nu + i] = sqrtf(fmaxf(sum, 1e-30f));
-                    else Lq[i * nu + j] = sum / Lq[j * nu + j];
+        // b. Quu = 2Q_u + B^T P B, Qux = B^T P A, qu = B^T w and, for t >= 1,
+        //    the stage-t terms Qxx = H_t + A^T P A, qx = h_t + A^T w
+        constexpr int NB = NU * NU + NU * NS + NU;
+        const int nx = t >= 1 ? NS * NS + NS : 0;
+        for (int e = tid; e < NB + nx; e += kTrajThreads) {
+            if (e < NU * NU) {
+                const int i = e / NU, j = e % NU;
+                float acc = R2[e];
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) acc += B[k2 * NU + i] * PB[k2 * NU + j];
+                Quu[e] = acc;
+            } else if (e < NU * NU + NU * NS) {
+                const int f = e - NU * NU, i = f / NS, j = f % NS;
+                float acc = 0.f;
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) acc += B[k2 * NU + i] * PA[k2 * NS + j];
+                Qux[f] = acc;
+            } else if (e < NB) {
+                const int i = e - NU * NU - NU * NS;
+                float acc = 0.f;
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) acc += B[k2 * NU + i] * wv[k2];
+                qu[i] = acc;
+            } else if (e < NB + NS * NS) {
+                const int f = e - NB, i = f / NS, j = f % NS;
+                float acc = Q2[f] + (hmap[f] >= 0 ? Hq[(t - 1) * nc + hmap[f]] : 0.f);
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) acc += A[k2 * NS + i] * PA[k2 * NS + j];
+                Qxx[f] = acc;
+            } else {
+                const int i = e - NB - NS * NS;
+                float acc = qr[(t - 1) * NS + i] + (gmap[i] >= 0 ? Hq[(t - 1) * nc + gmap[i]] : 0.f);
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) acc += A[k2 * NS + i] * wv[k2];
+                qx[i] = acc;
+            }
+        }
+        __syncthreads();
+        // c. gains [K | k] = -Quu^{-1} [Qux | qu]: one column per thread, with a
+        //    register Cholesky factor of the small input Hessian
+        float* Kt = Kall + (size_t)t * NU * NSU;
+        if (tid <= NS) {
+            float L[NU * NU];
+#pragma unroll
+            for (int i = 0; i < NU * NU; ++i) L[i] = Quu[i];
+#pragma unroll
+            for (int j = 0; j < NU; ++j) {
+                float d = L[j * NU + j];
+#pragma unroll
+                for (int k2 = 0; k2 < j; ++k2) d -= L[j * NU + k2] * L[j * NU + k2];
+                d = sqrtf(fmaxf(d, 1e-30f));
+                L[j * NU + j] = d;
+                const float id = 1.f / d;
+#pragma unroll
+                for (int i = j + 1; i < NU; ++i) {
+                    float v = L[i * NU + j];
+#pragma unroll
+                    for (int k2 = 0; k2 < j; ++k2) v -= L[i * NU + k2] * L[j * NU + k2];
+                    L[i * NU + j] = v * id;
                 }
-        }
-        __syncthreads();
-        for (int col = tid; col <= ns; col += nt) {
-            for (int i = 0; i < nu; ++i) Kk[i * (ns + 1) + col] = -(col < ns ? Qux[i * ns + col] : qu[i]);
-            for (int i = 0; i < nu; ++i) {
-                float sum = Kk[i * (ns + 1) + col];
-                for (int k = 0; k < i; ++k) sum -= Lq[i * nu + k] * Kk[k * (ns + 1) + col];
-                Kk[i * (ns + 1) + col] = sum / Lq[i * nu + i];
             }
-            for (int i = nu - 1; i >= 0; --i) {
-                float sum = Kk[i * (ns + 1) + col];
-                for (int k = i + 1; k < nu; ++k) sum -= Lq[k * nu + i] * Kk[k * (ns + 1) + col];
-                Kk[i * (ns + 1) + col] = sum / Lq[i * nu + i];
+            float r[NU];
+#pragma unroll
+            for (int i = 0; i < NU; ++i) r[i] = -(tid < NS ? Qux[i * NS + tid] : qu[i]);
+#pragma unroll
+            for (int i = 0; i < NU; ++i) {
+                float v = r[i];
+#pragma unroll
+                for (int k2 = 0; k2 < i; ++k2) v -= L[i * NU + k2] * r[k2];
+                r[i] = v / L[i * NU + i];
             }
-            for (int i = 0; i < nu; ++i) Kg[((size_t)t * nu + i) * (ns + 1) + col] = Kk[i * (ns + 1) + col];
+#pragma unroll
+            for (int i = NU - 1; i >= 0; --i) {
+                float v = r[i];
+#pragma unroll
+                for (int k2 = i + 1; k2 < NU; ++k2) v -= L[k2 * NU + i] * r[k2];
+                r[i] = v / L[i * NU + i];
+            }
+#pragma unroll
+            for (int i = 0; i < NU; ++i) Kt[i * NSU + tid] = r[i];
         }
         if (t == 0) break;
-        // stage terms of step t go into (Qxx, qx), then P_t = Qxx + A^T PA + Qux^T K
-        stage(t, Qxx, qx);
-        for (int e = tid; e < ns * ns; e += nt) {
-            const int i = e / ns, j = e % ns;
-            float acc = Qxx[e];
-            for (int k = 0; k < ns; ++k) acc += A[k * ns + i] * PA[k * ns + j];
-            for (int k = 0; k < nu; ++k) acc += Qux[k * ns + i] * Kk[k * (ns + 1) + j];
-            Qxx[e] = acc;
-        }
-        for (int i = tid; i < ns; i += nt) {
-            float acc = qx[i];
-            for (int k = 0; k < ns; ++k) acc += A[k * ns + i] * wv[k];
-            for (int k = 0; k < nu; ++k) acc += Qux[k * ns + i] * Kk[k * (ns + 1) + ns];
-            qx[i] = acc;
-        }
         __syncthreads();
-        for (int e = tid; e < ns * ns; e += nt) {
-            const int i = e / ns, j = e % ns;
-            Pm[e] = 0.5f * (Qxx[i * ns + j] + Qxx[j * ns + i]);
+        // d. P_t = Qxx + Qux^T K (symmetrised), p_t = qx + Qux^T k
+        for (int e = tid; e < NS * NS + NS; e += kTrajThreads) {
+            if (e < NS * NS) {
+                const int i = e / NS, j = e % NS;
+                float aij = Qxx[e], aji = Qxx[j * NS + i];
+#pragma unroll
+                for (int k2 = 0; k2 < NU; ++k2) {
+                    aij += Qux[k2 * NS + i] * Kt[k2 * NSU + j];
+                    aji += Qux[k2 * NS + j] * Kt[k2 * NSU + i];
+                }
+                Pm[e] = 0.5f * (aij + aji);
+            } else {
+                const int i = e - NS * NS;
+                float acc = qx[i];
+#pragma unroll
+                for (int k2 = 0; k2 < NU; ++k2) acc += Qux[k2 * NS + i] * Kt[k2 * NSU + NS];
+                pv[i] = acc;
+            }
         }
-        for (int i = tid; i < ns; i += nt) pv[i] = qx[i];
         __syncthreads();
     }
     __syncthreads();
-    // 3. forward rollout
+    // 3. forward rollout x_{t+1} = A x + B (K x + k) + c; thread i owns x_i
+    //    (rows of A and B in registers), threads NS..NS+NU-1 write u
     float* xo = P.x + (size_t)s * (N + 1) * ns;
     float* uo = P.u + (size_t)s * N * nu;
-    for (int i = tid; i < ns; i += nt) {
-        xs[i] = P.x0[(size_t)s * ns + i];
-        xo[i] = xs[i];
+    float Ar[NS], Br[NU];
+    const int row = tid < NS ? tid : 0;
+#pragma unroll
+    for (int k2 = 0; k2 < NS; ++k2) Ar[k2] = A[row * NS + k2];
+#pragma unroll
+    for (int j = 0; j < NU; ++j) Br[j] = B[row * NU + j];
+    const float cr = c[row];
+    if (tid < NS) {
+        const float v = tid < ns ? P.x0[(size_t)s * ns + tid] : 0.f;
+        xbuf[0][tid] = v;
+        if (tid < ns) xo[tid] = v;
     }
     __syncthreads();
     for (int t = 0; t < N; ++t) {
-        for (int i = tid; i < nu; i += nt) {
-            const float* Kt = Kg + (size_t)t * nu * (ns + 1) + i * (ns + 1);
-            float acc = Kt[ns];
-            for (int k = 0; k < ns; ++k) acc += Kt[k] * xs[k];
-            us[i] = acc;
-            uo[t * nu + i] = acc;
-        }
-        __syncthreads();
-        float nx = 0.f;
-        if (tid < ns) {
-            float acc = c[tid];
-            for (int k = 0; k < ns; ++k) acc += A[tid * ns + k] * xs[k];
-            for (int k = 0; k < nu; ++k) acc += B[tid * nu + k] * us[k];
-            nx = acc;
-        }
-        __syncthreads();
-        if (tid < ns) {
-            xs[tid] = nx;
-            xo[(t + 1) * ns + tid] = nx;
+        const float* xc = xbuf[t & 1];
+        const float* Kt = Kall + (size_t)t * NU * NSU;
+        if (tid < NS + NU) {
+            float xr[NS];
+#pragma unroll
+            for (int k2 = 0; k2 < NS; ++k2) xr[k2] = xc[k2];
+            float uu[NU];
+#pragma unroll
+            for (int j = 0; j < NU; ++j) {
+                float v = Kt[j * NSU + NS];
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) v += Kt[j * NSU + k2] * xr[k2];
+                uu[j] = v;
+            }
+            if (tid < NS) {
+                float acc = cr;
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) acc += Ar[k2] * xr[k2];
+#pragma unroll
+                for (int j = 0; j < NU; ++j) acc += Br[j] * uu[j];
+                xbuf[(t + 1) & 1][tid] = acc;
+                if (tid < ns) xo[(t + 1) * ns + tid] = acc;
+            } else {
+                const int j = tid - NS;
+                float v = 0.f;
+#pragma unroll
+                for (int q = 0; q < NU; ++q) v = q == j ? uu[q] : v;
+                if (j < nu) uo[t * nu + j] = v;
+            }
         }
         __syncthreads();
     }
@@ -1243,19 +1338,18 @@ __device__ int revised_simplex(const Cols& cols, float& alpha, float* xB_out, in
 // columns of the ADMM problem's pair (part frame through the pose)
 template <int DIM>
 struct PairCols {
-    int nr, no;
+    int nr, no, fo0;
     const float4* rf;
     const float4* of;
-    float R[DIM * DIM], pos[DIM];
+    const double* d64;
+    float R[DIM * DIM];
+    double pos64[DIM];
     float cmx;
     __device__ int n() const { return nr + no; }
     __device__ float cmax() const { return cmx; }
     __device__ float cost(int j) const {
         if (j < nr) return 0.f;
-        const float4 f = of[j - nr];
-        float dp = f.w - f.x * pos[0] - f.y * pos[1];
-        if (DIM == 3) dp -= f.z * pos[DIM - 1];
-        return dp;
+        return face_offset(d64, fo0 + j - nr, of[j - nr], pos64, DIM);
     }
     __device__ void col(int j, float (&E)[DIM + 1]) const {
         if (j < nr) {
@@ -1302,7 +1396,9 @@ __global__ void __launch_bounds__(256) init_pairs_kernel(DevProblem P, float* al
 #pragma unroll
     for (int i = 0; i < DIM * DIM; ++i) pc.R[i] = ps.R[i];
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) pc.pos[i] = ps.pos[i];
+    for (int i = 0; i < DIM; ++i) pc.pos64[i] = ps.pos64[i];
+    pc.fo0 = fo0;
+    pc.d64 = P.obs_d64;
     float cm = 0.f;
     for (int l = 0; l < pc.no; ++l) cm = fmaxf(cm, fabsf(pc.cost(pc.nr + l)));
     pc.cmx = cm;
@@ -1555,10 +1651,17 @@ hipError_t launch_mult_phase(const DevProblem& P, int W, int grid, hipStream_t s
 
 hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t st)
 {
-    const int ns = P.n_s, nu = P.n_u;
-    const size_t floats = (size_t)P.N * P.nc + 4 * ns * ns + ns * nu + 2 * nu * nu + nu * ns + nu * (ns + 1) + 6 * ns + 3 * nu + 8;
-    hipLaunchKernelGGL(traj_phase_kernel, dim3(P.n_scen), dim3(kTrajThreads), floats * sizeof(float), st, P,
-                       obstacle_free);
+    dim3 g(P.n_scen), b(kTrajThreads);
+    if (P.n_s <= 4 && P.n_u <= 2) {
+        hipLaunchKernelGGL((traj_phase_kernel<4, 2>), g, b, sizeof(float) * traj_dyn_floats(P.N, 4, 2, P.nc), st, P,
+                           obstacle_free);
+    } else if (P.n_s <= 12 && P.n_u <= 4) {
+        hipLaunchKernelGGL((traj_phase_kernel<12, 4>), g, b, sizeof(float) * traj_dyn_floats(P.N, 12, 4, P.nc), st,
+                           P, obstacle_free);
+    } else {
+        hipLaunchKernelGGL((traj_phase_kernel<16, 8>), g, b, sizeof(float) * traj_dyn_floats(P.N, 16, 8, P.nc), st,
+                           P, obstacle_free);
+    }
     return hipGetLastError();
 }
 

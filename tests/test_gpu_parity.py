@@ -177,7 +177,9 @@ def test_setup_initial_iterate(cadmm, name):
     g = gpu_state(h)
     alpha_g = h.scales().double().cpu().numpy()
     P, st = oracle_iterate(prob, 0)
-    alpha_o = P.scale_all(st["x"])
+    # alpha* is compared at the GPU's own trajectory, so that the check
+    # isolates the LP from the (separately checked) trajectory rounding
+    alpha_o = P.scale_all(g["x"])
     ea = (np.abs(alpha_g - alpha_o) / np.maximum(np.abs(alpha_o), 1e-3)).max()
     T, R, _ = P.mult_phase(g["x"], g["y"], np.zeros_like(g["zeta"]), np.zeros_like(g["xi"]))
     msc = multiplier_scale(prob, g["x"], g["y"])
@@ -243,6 +245,25 @@ def test_full_run_c1(cadmm):
     assert traj_error(g, st) <= TOL_TRAJ
     assert abs(res[0]["iters"] - hist["iters"][0]) <= 1
     assert res[0]["min_alpha"] > 0.95
+    h.close()
+
+
+@pytest.mark.parametrize("name,iters", [("c2", 60), ("c3", 40)])
+def test_full_run_trajectory(cadmm, name, iters):
+    """Longer runs from a shared iterate (the oracle's initial one, since in 3D
+    the initial LP certificate is not unique): the trajectories stay within
+    the parity bar of the oracle's."""
+    prob = workloads.make(name)
+    say(f"[full run] {name} {iters} iterations from the oracle's initial iterate")
+    P, st = oracle_iterate(prob, 0)
+    h = cadmm.Handle(prob)
+    h.set_state(x=st["x"], u=st["u"], y=st["y"], zeta=st["zeta"], xi=st["xi"])
+    h.iterate(iters)
+    g = gpu_state(h)
+    P.run(st, iters)
+    et = traj_error(g, st)
+    say(f"   traj err {et:.2e}")
+    assert et <= TOL_TRAJ
     h.close()
 
 
