@@ -87,6 +87,13 @@ def _declare(L):
     L.orc_cost.argtypes = [PP, ctypes.c_int, _dp, _dp]
     L.orc_admm_run.restype = ctypes.c_int
     L.orc_admm_run.argtypes = [PP, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _ip]
+    L.orc_admm_grad.restype = ctypes.c_int
+    L.orc_admm_grad.argtypes = [PP, ctypes.c_int, _dp, _dp, _dp, _dp]
+    L.orc_pairqp_vjp.restype = ctypes.c_int
+    L.orc_pairqp_vjp.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_double,
+                                 _dp, _dp, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_traj_vjp.restype = ctypes.c_int
+    L.orc_traj_vjp.argtypes = [PP] + [_dp] * 12
     L.orc_set_threads.restype = ctypes.c_int
     L.orc_set_threads.argtypes = [ctypes.c_int]
 
@@ -242,6 +249,18 @@ class Problem:
         lib().orc_mult_phase(self.ref, _d(_f64(x)), _d(_f64(y)), None, _d(zeta), _d(xi), _d(rpri))
         return zeta, xi, rpri
 
+    def traj_vjp(self, state, y_new, xbar, ubar):
+        """Adjoints of (y^{k+1}, zeta^k, xi^k, x^k, obstacle offsets, x0) of the
+        trajectory phase for cotangents (xbar, ubar) of (x^{k+1}, u^{k+1})."""
+        out = dict(y=np.zeros(self.y_size), zeta=np.zeros_like(state["zeta"]), xi=np.zeros_like(state["xi"]),
+                   x=np.zeros_like(state["x"]), d=np.zeros(len(self.p["obs_d"])), x0=np.zeros_like(self.p["x0"]))
+        bad = lib().orc_traj_vjp(self.ref, _d(state["x"]), _d(_f64(y_new)), _d(state["zeta"]), _d(state["xi"]),
+                                 _d(_f64(xbar)), _d(_f64(ubar)), _d(out["y"]), _d(out["zeta"]), _d(out["xi"]),
+                                 _d(out["x"]), _d(out["d"]), _d(out["x0"]))
+        if bad:
+            raise RuntimeError("trajectory VJP failed")
+        return out
+
     def cost(self, x, u, s=0):
         return lib().orc_cost(self.ref, int(s), _d(_f64(x)), _d(_f64(u)))
 
@@ -257,3 +276,44 @@ class Problem:
         if bad:
             raise RuntimeError(f"oracle ADMM: {bad} failed sub-solves")
         return dict(r_pri=hp, r_dual=hd, cost=hc, iters=iters)
+
+
+# ---------------------------------------------------------------- gradient
+def loss_fixed_y0(prob, K, y0):
+    """L = sum_s F_s(x^K, u^K) after exactly K iterations from s^0 = LQ(x0),
+    the given y0 and zero multipliers (no early stop)."""
+    q = dict(prob)
+    q["eps_pri"] = -1.0
+    q["eps_dual"] = -1.0
+    P = Problem(q)
+    st = P.init_state()
+    st["y"][:] = y0
+    P.run(st, K)
+    return sum(P.cost(st["x"], st["u"], s) for s in range(P.n_scen))
+
+
+def grad_fixed_y0(prob, K, y0):
+    """(L, dL/d obstacle offsets [F_o], dL/d x0 [n_scen, n_s]) by the oracle's
+    reverse pass through the K unrolled iterations (y0 held fixed)."""
+    P = Problem(prob)
+    L = np.zeros(1)
+    gd = np.zeros(len(prob["obs_d"]))
+    gx = np.zeros((P.n_scen, int(prob["n_s"])))
+    y0 = _f64(y0)
+    bad = lib().orc_admm_grad(P.ref, int(K), _d(y0), _d(L), _d(gd), _d(gx))
+    if bad:
+        raise RuntimeError(f"oracle gradient: {bad} failed solves")
+    return float(L[0]), gd, gx
+
+
+def pair_qp_vjp(A, b, Cp, dp, zeta, xi, yhat, eps, ybar):
+    """Adjoints (dp, Cp, zeta, xi, yhat) of one pair QP for the cotangent ybar."""
+    A, b, Cp, dp, xi, yhat, ybar = map(_f64, (A, b, Cp, dp, xi, yhat, ybar))
+    dim = A.shape[1]
+    dpb = np.zeros(len(dp)); Cpb = np.zeros_like(Cp); zb = np.zeros(1); xib = np.zeros(dim)
+    yhb = np.zeros(len(yhat))
+    st = lib().orc_pairqp_vjp(dim, len(b), _d(A), _d(b), len(dp), _d(Cp), _d(dp), float(zeta), _d(xi), _d(yhat),
+                              float(eps), _d(ybar), _d(dpb), _d(Cpb), _d(zb), _d(xib), _d(yhb))
+    if st:
+        raise RuntimeError("pair QP VJP failed")
+    return dpb, Cpb, float(zb[0]), xib, yhb

@@ -961,3 +961,715 @@ int orc_set_threads(int n)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* reverse-mode gradient through the unrolled iteration                */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Second derivatives d2R/d(att_a)d(att_b), a, b < n_att, stored [a][b][dim*dim].
+ * Planar: d2R/dtheta2 = -R. ZYX Euler R = Rz(psi) Ry(theta) Rx(phi): products
+ * of the factor matrices and their first and second derivatives.
+ */
+static void rotation_dd(const orc_problem *P, const double *s, double *ddR)
+{
+    if (P->att_kind == 0) {
+        double th = s[P->att_idx[0]], c = cos(th), sn = sin(th);
+        ddR[0] = -c; ddR[1] = sn; ddR[2] = -sn; ddR[3] = -c;
+        return;
+    }
+    double ph = s[P->att_idx[0]], th = s[P->att_idx[1]], ps = s[P->att_idx[2]];
+    double cf = cos(ph), sf = sin(ph), ct = cos(th), st = sin(th), cp = cos(ps), sp = sin(ps);
+    double X[3][9] = {{1, 0, 0, 0, cf, -sf, 0, sf, cf},
+                      {0, 0, 0, 0, -sf, -cf, 0, cf, -sf},
+                      {0, 0, 0, 0, -cf, sf, 0, -sf, -cf}};
+    double Y[3][9] = {{ct, 0, st, 0, 1, 0, -st, 0, ct},
+                      {-st, 0, ct, 0, 0, 0, -ct, 0, -st},
+                      {-ct, 0, -st, 0, 0, 0, st, 0, -ct}};
+    double Z[3][9] = {{cp, -sp, 0, sp, cp, 0, 0, 0, 1},
+                      {-sp, -cp, 0, cp, -sp, 0, 0, 0, 0},
+                      {-cp, sp, 0, -sp, -cp, 0, 0, 0, 0}};
+    /* derivative orders of (phi, theta, psi) for each (a, b) */
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            int o[3] = {0, 0, 0};
+            o[a] += 1;
+            o[b] += 1;
+            const double *F1 = Z[o[2]], *F2 = Y[o[1]], *F3 = X[o[0]];
+            double T1[9];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    double acc = 0;
+                    for (int k = 0; k < 3; ++k) acc += F1[i * 3 + k] * F2[k * 3 + j];
+                    T1[i * 3 + j] = acc;
+                }
+            double *out = ddR + (a * 3 + b) * 9;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    double acc = 0;
+                    for (int k = 0; k < 3; ++k) acc += T1[i * 3 + k] * F3[k * 3 + j];
+                    out[i * 3 + j] = acc;
+                }
+        }
+}
+
+/* T, R and their Jacobian J ((dim+1) x nq, pose coordinates) of one pair at
+   state st with dual rows yb (stride between rows); also cbar = C^T mu. */
+static void pair_lin(const orc_problem *P, const orc_block *q, const double *st, const double *yb, int stride,
+                     double *T, double *Rr, double *J, double *cbar)
+{
+    int dim = P->dim, na = n_att(P), nq = dim + na;
+    double Rm[9], dR[27];
+    rotation(P, st, Rm, dR);
+    pair_TR(P, q, st, yb, stride, T, Rr);
+    const double *Cw = P->obs_C + (size_t)P->obs_face_ptr[q->j] * dim;
+    const double *o = P->part_off + (size_t)q->i * dim;
+    for (int c = 0; c < dim; ++c) cbar[c] = 0.0;
+    for (int l = 0; l < q->no; ++l)
+        for (int c = 0; c < dim; ++c) cbar[c] += Cw[l * dim + c] * yb[(q->nr + l) * stride];
+    for (int i = 0; i < (dim + 1) * nq; ++i) J[i] = 0.0;
+    for (int c = 0; c < dim; ++c) J[c] = -cbar[c];
+    for (int a = 0; a < na; ++a) {
+        const double *dRa = dR + a * dim * dim;
+        double acc = 0.0;
+        for (int r = 0; r < dim; ++r)
+            for (int c = 0; c < dim; ++c) acc += cbar[r] * dRa[r * dim + c] * o[c];
+        J[dim + a] = -acc;
+        for (int c = 0; c < dim; ++c) {
+            double v = 0.0;
+            for (int r = 0; r < dim; ++r) v += dRa[r * dim + c] * cbar[r];
+            J[(1 + c) * nq + dim + a] = v;
+        }
+    }
+}
+
+/* Adjoint of J through cbar (dual rows mu) and through the attitude
+   (second derivatives of R). Adds into ybar (rows, stride) and qbar (nq). */
+static void jac_adjoint(const orc_problem *P, const orc_block *q, const double *st, const double *yb, int stride,
+                        const double *Jbar, double *ybar, int ystride, double *qbar)
+{
+    int dim = P->dim, na = n_att(P), nq = dim + na;
+    double Rm[9], dR[27], ddR[81];
+    rotation(P, st, Rm, dR);
+    rotation_dd(P, st, ddR);
+    const double *Cw = P->obs_C + (size_t)P->obs_face_ptr[q->j] * dim;
+    const double *o = P->part_off + (size_t)q->i * dim;
+    double cbar[3] = {0, 0, 0};
+    for (int l = 0; l < q->no; ++l)
+        for (int c = 0; c < dim; ++c) cbar[c] += Cw[l * dim + c] * yb[(q->nr + l) * stride];
+    double cbb[3] = {0, 0, 0};
+    for (int c = 0; c < dim; ++c) cbb[c] -= Jbar[c];
+    for (int a = 0; a < na; ++a) {
+        const double *dRa = dR + a * dim * dim;
+        for (int r = 0; r < dim; ++r) {
+            double dro = 0.0;
+            for (int c = 0; c < dim; ++c) dro += dRa[r * dim + c] * o[c];
+            cbb[r] -= Jbar[dim + a] * dro;
+            for (int c = 0; c < dim; ++c) cbb[r] += Jbar[(1 + c) * nq + dim + a] * dRa[r * dim + c];
+        }
+    }
+    for (int l = 0; l < q->no; ++l) {
+        double acc = 0.0;
+        for (int c = 0; c < dim; ++c) acc += Cw[l * dim + c] * cbb[c];
+        ybar[(q->nr + l) * ystride] += acc;
+    }
+    for (int b = 0; b < na; ++b) {
+        double acc = 0.0;
+        for (int a = 0; a < na; ++a) {
+            const double *dd = ddR + (a * na + b) * dim * dim;
+            double t0 = 0.0;
+            for (int r = 0; r < dim; ++r)
+                for (int c = 0; c < dim; ++c) t0 += cbar[r] * dd[r * dim + c] * o[c];
+            acc -= Jbar[dim + a] * t0;
+            for (int c = 0; c < dim; ++c) {
+                double v = 0.0;
+                for (int r = 0; r < dim; ++r) v += dd[r * dim + c] * cbar[r];
+                acc += Jbar[(1 + c) * nq + dim + a] * v;
+            }
+        }
+        qbar[dim + b] += acc;
+    }
+    (void)Rm;
+}
+
+/* Adjoint of (T, R) at (st, y) for the row weights (tb, rb[dim]): adds into
+   ybar rows, qbar and the obstacle-offset gradient dbar (faces of q->j). */
+static void TR_adjoint(const orc_problem *P, const orc_block *q, const double *st, const double *yb, int stride,
+                       double tb, const double *rb, double *ybar, int ystride, double *qbar, double *dbar)
+{
+    int dim = P->dim, nq = dim + n_att(P);
+    double R[9], pos[3], Cp[MAXROWS * MAXD], dp[MAXROWS], T, Rr[3], J[4 * 6], cbar[3];
+    part_frame(P, st, q->i, q->j, R, pos, Cp, dp);
+    const double *A = P->part_A + (size_t)P->part_face_ptr[q->i] * dim;
+    for (int k = 0; k < q->nr; ++k) {
+        double acc = 0.0;
+        for (int r = 0; r < dim; ++r) acc += A[k * dim + r] * rb[r];
+        ybar[k * ystride] += acc;
+    }
+    for (int l = 0; l < q->no; ++l) {
+        double acc = dp[l] * tb;
+        for (int r = 0; r < dim; ++r) acc += Cp[l * dim + r] * rb[r];
+        ybar[(q->nr + l) * ystride] += acc;
+        dbar[P->obs_face_ptr[q->j] + l] += yb[(q->nr + l) * stride] * tb;
+    }
+    ybar[(q->n - 1) * ystride] += tb;
+    pair_lin(P, q, st, yb, stride, &T, Rr, J, cbar);
+    for (int a = 0; a < nq; ++a) {
+        double acc = J[a] * tb;
+        for (int r = 0; r < dim; ++r) acc += J[(1 + r) * nq + a] * rb[r];
+        qbar[a] += acc;
+    }
+}
+
+/* Adjoint of one proximal pair QP on its active set (dense KKT transpose).
+   ybar_new (rows of y^{k+1}) -> adds into ybar_old (rows of yhat = y^k),
+   zb (zeta^k), xib[dim] (xi^k), qbar (pose at s^k) and dbar. */
+static int pairqp_adjoint(const orc_problem *P, const orc_block *q, const double *st, const double *yhat,
+                          const double *ynew, int stride, double zeta, const double *xi, const double *ybar_new,
+                          double *ybar_old, int ystride, double *zb, double *xib, double *qbar, double *dbar)
+{
+    int dim = P->dim, na = n_att(P), c = dim + 1, n = q->n;
+    double R[9], dR[27], pos[3], Cp[MAXROWS * MAXD], dp[MAXROWS];
+    part_frame(P, st, q->i, q->j, R, pos, Cp, dp);
+    rotation(P, st, R, dR);
+    const double *A = P->part_A + (size_t)P->part_face_ptr[q->i] * dim;
+    const double *b = P->part_b + P->part_face_ptr[q->i];
+    double K[MAXROWS * (MAXD + 1)];
+    build_K(dim, q->nr, A, q->no, Cp, dp, K);
+    double bh[MAXD + 1], D[MAXROWS], kap[MAXROWS], y[MAXROWS], yh[MAXROWS], yb[MAXROWS];
+    bh[0] = 1.0 + zeta;
+    for (int r = 0; r < dim; ++r) bh[1 + r] = xi[r];
+    for (int l = 0; l < n; ++l) {
+        double s = 0.0;
+        for (int m = 0; m < c; ++m) s += K[l * c + m] * K[l * c + m];
+        D[l] = s;
+        kap[l] = l < q->nr ? b[l] : 0.0;
+        y[l] = ynew[l * stride];
+        yh[l] = yhat[l * stride];
+        yb[l] = ybar_new[l * ystride];
+    }
+    int F[MAXROWS], nf = 0;
+    for (int l = 0; l < n; ++l) if (y[l] > 0.0) F[nf++] = l;
+    /* transposed KKT on the free set: [G_FF kap_F; -kap_F^T 0] [a; beta] = [ybar_F; 0] */
+    int sz = nf + 1;
+    double M[(MAXROWS + 1) * (MAXROWS + 1)], rhs[MAXROWS + 1];
+    for (int i2 = 0; i2 < nf; ++i2) {
+        for (int j2 = 0; j2 < nf; ++j2) {
+            double s = 0.0;
+            for (int m = 0; m < c; ++m) s += K[F[i2] * c + m] * K[F[j2] * c + m];
+            M[i2 * sz + j2] = s + (i2 == j2 ? P->eps_prox * D[F[i2]] : 0.0);
+        }
+        M[i2 * sz + nf] = kap[F[i2]];
+        M[nf * sz + i2] = -kap[F[i2]];
+        rhs[i2] = yb[F[i2]];
+    }
+    M[nf * sz + nf] = 0.0;
+    rhs[nf] = 0.0;
+    if (gauss_solve(sz, M, rhs)) return 1;
+    double gbar[MAXROWS] = {0}, Kbar[MAXROWS * (MAXD + 1)] = {0}, Dbar[MAXROWS] = {0};
+    for (int i2 = 0; i2 < nf; ++i2) gbar[F[i2]] = -rhs[i2];
+    /* Gbar = -a y^T on F x F:  K^bar += (Gbar + Gbar^T) K, Dbar_l += eps Gbar_ll */
+    for (int i2 = 0; i2 < nf; ++i2) {
+        int l = F[i2];
+        double al = rhs[i2];
+        /* (Gbar K)_l = -a_l (y^T K) ; (Gbar^T K)_l = -y_l (a^T K) */
+        for (int m = 0; m < c; ++m) {
+            double yK = 0.0, aK = 0.0;
+            for (int j2 = 0; j2 < nf; ++j2) {
+                yK += y[F[j2]] * K[F[j2] * c + m];
+                aK += rhs[j2] * K[F[j2] * c + m];
+            }
+            Kbar[l * c + m] += -al * yK - y[l] * aK;
+        }
+        Dbar[l] += P->eps_prox * (-al * y[l]);
+    }
+    /* g = K bh - eps D yhat */
+    double bhbar[MAXD + 1] = {0};
+    for (int l = 0; l < n; ++l) {
+        if (gbar[l] == 0.0) continue;
+        for (int m = 0; m < c; ++m) {
+            Kbar[l * c + m] += gbar[l] * bh[m];
+            bhbar[m] += K[l * c + m] * gbar[l];
+        }
+        Dbar[l] += -P->eps_prox * gbar[l] * yh[l];
+        ybar_old[l * ystride] += -P->eps_prox * D[l] * gbar[l];
+    }
+    for (int l = 0; l < n; ++l)
+        for (int m = 0; m < c; ++m) Kbar[l * c + m] += 2.0 * Dbar[l] * K[l * c + m];
+    *zb += bhbar[0];
+    for (int r = 0; r < dim; ++r) xib[r] += bhbar[1 + r];
+    /* K rows of the obstacle: (dp_l, Cp_l) with dp = d - C pos, Cp_l = c_l^T R */
+    const double *Cw = P->obs_C + (size_t)P->obs_face_ptr[q->j] * dim;
+    const double *o = P->part_off + (size_t)q->i * dim;
+    double posbar[3] = {0, 0, 0}, Rbar[9] = {0};
+    for (int l = 0; l < q->no; ++l) {
+        const double *Kb = Kbar + (q->nr + l) * c;
+        dbar[P->obs_face_ptr[q->j] + l] += Kb[0];
+        for (int r = 0; r < dim; ++r) posbar[r] -= Kb[0] * Cw[l * dim + r];
+        /* Cp_lq = sum_r c_lr R_rq */
+        for (int r = 0; r < dim; ++r)
+            for (int m = 0; m < dim; ++m) Rbar[r * dim + m] += Cw[l * dim + r] * Kb[1 + m];
+    }
+    /* pos = rho + R o */
+    for (int r = 0; r < dim; ++r) {
+        qbar[r] += posbar[r];
+        for (int m = 0; m < dim; ++m) Rbar[r * dim + m] += posbar[r] * o[m];
+    }
+    for (int a = 0; a < na; ++a) {
+        double acc = 0.0;
+        for (int i2 = 0; i2 < dim * dim; ++i2) acc += Rbar[i2] * dR[a * dim * dim + i2];
+        qbar[dim + a] += acc;
+    }
+    return 0;
+}
+
+/* Adjoint of the condensed LQ solve. Inputs: stage H (N blocks), the
+   solution (x, u), and the adjoint (xbar over t = 1..N, ubar). Outputs: w
+   (N x n_s, = M abar), and adds x0bar. Hbar_t = -1/2 (w_t x_t^T + x_t w_t^T),
+   hbar_t = -w_t are formed by the caller from w. */
+static int lq_adjoint(int n_s, int n_u, int N, const double *A, const double *B, const double *H,
+                      const double *Q_u, const double *xbar, const double *ubar, double *w, double *x0bar)
+{
+    int nU = N * n_u;
+    double *Mt = (double *)calloc((size_t)N * n_s * nU, sizeof(double));
+    double *Hs = (double *)calloc((size_t)nU * nU, sizeof(double));
+    double *HM = (double *)calloc((size_t)n_s * nU, sizeof(double));
+    double *ab = (double *)calloc(nU, sizeof(double));
+    double *zb = (double *)calloc((size_t)(N + 1) * n_s, sizeof(double));
+    for (int t = 1; t <= N; ++t) {
+        double *Mc = Mt + (size_t)(t - 1) * n_s * nU;
+        const double *Mp = (t >= 2) ? Mt + (size_t)(t - 2) * n_s * nU : NULL;
+        for (int r = 0; r < n_s; ++r) {
+            for (int col = 0; col < nU; ++col) {
+                double a = 0.0;
+                if (Mp) for (int q2 = 0; q2 < n_s; ++q2) a += A[r * n_s + q2] * Mp[q2 * nU + col];
+                Mc[r * nU + col] = a;
+            }
+            for (int k = 0; k < n_u; ++k) Mc[r * nU + (t - 1) * n_u + k] += B[r * n_u + k];
+        }
+    }
+    for (int k = 0; k < N; ++k)
+        for (int a = 0; a < n_u; ++a)
+            for (int b2 = 0; b2 < n_u; ++b2) Hs[(k * n_u + a) * nU + k * n_u + b2] = 2.0 * Q_u[a * n_u + b2];
+    for (int a = 0; a < nU; ++a) ab[a] = ubar ? ubar[a] : 0.0;
+    for (int t = 1; t <= N; ++t) {
+        const double *Mc = Mt + (size_t)(t - 1) * n_s * nU;
+        const double *Ht = H + (size_t)(t - 1) * n_s * n_s;
+        for (int r = 0; r < n_s; ++r)
+            for (int col = 0; col < nU; ++col) {
+                double a = 0.0;
+                for (int q2 = 0; q2 < n_s; ++q2) a += Ht[r * n_s + q2] * Mc[q2 * nU + col];
+                HM[r * nU + col] = a;
+            }
+        for (int a = 0; a < nU; ++a) {
+            for (int b2 = 0; b2 < nU; ++b2) {
+                double acc = 0.0;
+                for (int r = 0; r < n_s; ++r) acc += Mc[r * nU + a] * HM[r * nU + b2];
+                Hs[a * nU + b2] += acc;
+            }
+            double acc = 0.0;
+            for (int r = 0; r < n_s; ++r) acc += Mc[r * nU + a] * xbar[(size_t)(t - 1) * n_s + r];
+            ab[a] += acc;
+        }
+    }
+    int st = chol_solve(nU, Hs, ab);   /* abar = Hs^{-1} (ubar + sum M^T xbar) */
+    if (!st) {
+        for (int t = 1; t <= N; ++t) {
+            const double *Mc = Mt + (size_t)(t - 1) * n_s * nU;
+            const double *Ht = H + (size_t)(t - 1) * n_s * n_s;
+            double *wt = w + (size_t)(t - 1) * n_s;
+            for (int r = 0; r < n_s; ++r) {
+                double acc = 0.0;
+                for (int a = 0; a < nU; ++a) acc += Mc[r * nU + a] * ab[a];
+                wt[r] = acc;
+            }
+            /* zbar_t = xbar_t - H_t w_t */
+            for (int r = 0; r < n_s; ++r) {
+                double acc = xbar[(size_t)(t - 1) * n_s + r];
+                for (int q2 = 0; q2 < n_s; ++q2) acc -= Ht[r * n_s + q2] * wt[q2];
+                zb[t * n_s + r] = acc;
+            }
+        }
+        /* z_t = A z_{t-1} + c, z_0 = x0: backpropagate zbar to x0 */
+        for (int t = N; t >= 1; --t)
+            for (int q2 = 0; q2 < n_s; ++q2) {
+                double acc = 0.0;
+                for (int r = 0; r < n_s; ++r) acc += A[r * n_s + q2] * zb[t * n_s + r];
+                zb[(t - 1) * n_s + q2] += acc;
+            }
+        for (int r = 0; r < n_s; ++r) x0bar[r] += zb[r];
+    }
+    free(Mt); free(Hs); free(HM); free(ab); free(zb);
+    return st;
+}
+
+/* Stage terms of the trajectory QP of iteration k for scenario s (as in
+   orc_traj_phase): H (N blocks), h (N x n_s). */
+static void traj_stage(const orc_problem *P, const orc_block *B, int nb, int s, const double *x_in,
+                       const double *y, const double *zeta, const double *xi, double *H, double *h)
+{
+    int n_s = P->n_s, N = P->N, dim = P->dim, nq = dim + n_att(P);
+    int qidx[6];
+    for (int r = 0; r < dim; ++r) qidx[r] = P->pos_idx[r];
+    for (int a = 0; a < n_att(P); ++a) qidx[dim + a] = P->att_idx[a];
+    lq_stage_base(P, s, H, h);
+    for (int b = 0; b < nb; ++b) {
+        const orc_block *q = &B[b];
+        if (q->s != s) continue;
+        for (int t = 1; t <= N; ++t) {
+            const double *st = state_at(P, x_in, s, t);
+            double T, Rr[3], J[24], cbar[3], r[4], e[4], qk[6];
+            pair_lin(P, q, st, y + q->yoff + (t - 1), N, &T, Rr, J, cbar);
+            r[0] = T + zeta[(size_t)b * N + t - 1];
+            for (int c = 0; c < dim; ++c) r[1 + c] = Rr[c] + xi[((size_t)b * dim + c) * N + t - 1];
+            for (int a = 0; a < nq; ++a) qk[a] = st[qidx[a]];
+            for (int m = 0; m <= dim; ++m) {
+                double acc = r[m];
+                for (int a = 0; a < nq; ++a) acc -= J[m * nq + a] * qk[a];
+                e[m] = acc;
+            }
+            double *Ht = H + (size_t)(t - 1) * n_s * n_s, *ht = h + (size_t)(t - 1) * n_s;
+            for (int a = 0; a < nq; ++a) {
+                for (int c2 = 0; c2 < nq; ++c2) {
+                    double acc = 0.0;
+                    for (int m = 0; m <= dim; ++m) acc += J[m * nq + a] * J[m * nq + c2];
+                    Ht[qidx[a] * n_s + qidx[c2]] += P->sigma * acc;
+                }
+                double acc = 0.0;
+                for (int m = 0; m <= dim; ++m) acc += J[m * nq + a] * e[m];
+                ht[qidx[a]] += P->sigma * acc;
+            }
+        }
+    }
+}
+
+
+/* Adjoint of the trajectory phase (x^k, y^{k+1}, zeta^k, xi^k) -> (x^{k+1},
+   u^{k+1}). Consumes xb (adjoint of x^{k+1}, zeroed on return) and ub
+   (adjoint of u^{k+1}, zeroed); adds into yb (y^{k+1}), zbar, xibar
+   (zeta^k, xi^k), qbar (pose coordinates of x^k, per pair), dbar and x0bar. */
+static int traj_adjoint(const orc_problem *P, const orc_block *B, int nb, const double *Xk, const double *Xn,
+                        const double *Yn, const double *Zk, const double *XIk, double *xb, double *ub, double *yb,
+                        double *zbar, double *xibar, double *qbar, double *grad_d, double *grad_x0)
+{
+    int S = P->n_scen, N = P->N, n_s = P->n_s, n_u = P->n_u, dim = P->dim, nq = dim + n_att(P), bad = 0;
+    int qidx[6];
+    for (int r = 0; r < dim; ++r) qidx[r] = P->pos_idx[r];
+    for (int a = 0; a < n_att(P); ++a) qidx[dim + a] = P->att_idx[a];
+    double *H = (double *)malloc(sizeof(double) * N * n_s * n_s), *h = (double *)malloc(sizeof(double) * N * n_s);
+    double *w = (double *)malloc(sizeof(double) * N * n_s), *xbt = (double *)malloc(sizeof(double) * N * n_s);
+        for (int s = 0; s < S; ++s) {
+        traj_stage(P, B, nb, s, Xk, Yn, Zk, XIk, H, h);
+        for (int t = 1; t <= N; ++t)
+            for (int r = 0; r < n_s; ++r) xbt[(t - 1) * n_s + r] = xb[((size_t)s * (N + 1) + t) * n_s + r];
+        bad += lq_adjoint(n_s, n_u, N, P->A_dyn, P->B_dyn, H, P->Q_u, xbt, ub + (size_t)s * N * n_u, w,
+                          grad_x0 + (size_t)s * n_s);
+        /* x^{k+1} and u^{k+1} do not depend on x^k, u^k except through the stage terms */
+        for (int t = 0; t <= N; ++t)
+            for (int r = 0; r < n_s; ++r) xb[((size_t)s * (N + 1) + t) * n_s + r] = 0.0;
+        for (int i = 0; i < N * n_u; ++i) ub[(size_t)s * N * n_u + i] = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            const orc_block *q = &B[b];
+            if (q->s != s) continue;
+            for (int t = 1; t <= N; ++t) {
+                const double *st = state_at(P, Xk, s, t);
+                const double *xt1 = state_at(P, Xn, s, t);
+                const double *wt = w + (size_t)(t - 1) * n_s;
+                double T, Rr[3], J[24], cbar[3], r[4], ep[4], qk[6], wq[6], xq[6];
+                pair_lin(P, q, st, Yn + q->yoff + t - 1, N, &T, Rr, J, cbar);
+                r[0] = T + Zk[(size_t)b * N + t - 1];
+                for (int c2 = 0; c2 < dim; ++c2) r[1 + c2] = Rr[c2] + XIk[((size_t)b * dim + c2) * N + t - 1];
+                for (int a = 0; a < nq; ++a) { qk[a] = st[qidx[a]]; wq[a] = wt[qidx[a]]; xq[a] = xt1[qidx[a]]; }
+                for (int m = 0; m <= dim; ++m) {
+                    double acc = r[m];
+                    for (int a = 0; a < nq; ++a) acc -= J[m * nq + a] * qk[a];
+                    ep[m] = acc;
+                }
+                /* Hbar (pose block) = -1/2 (w x^T + x w^T), hbar = -w */
+                double Hb[36], hb[6];
+                for (int a = 0; a < nq; ++a) {
+                    hb[a] = -wq[a];
+                    for (int c2 = 0; c2 < nq; ++c2) Hb[a * nq + c2] = -0.5 * (wq[a] * xq[c2] + xq[a] * wq[c2]);
+                }
+                /* H += sigma J^T J ; h += sigma J^T (e - J q^k), e = r */
+                double Jb[24] = {0}, eb[4] = {0}, qb[6] = {0};
+                for (int m = 0; m <= dim; ++m)
+                    for (int a = 0; a < nq; ++a) {
+                        double acc = 0.0;
+                        for (int c2 = 0; c2 < nq; ++c2) acc += J[m * nq + c2] * (Hb[c2 * nq + a] + Hb[a * nq + c2]);
+                        Jb[m * nq + a] += P->sigma * acc;
+                    }
+                double Jh[4] = {0};
+                for (int m = 0; m <= dim; ++m)
+                    for (int a = 0; a < nq; ++a) Jh[m] += J[m * nq + a] * hb[a];
+                for (int m = 0; m <= dim; ++m) {
+                    for (int a = 0; a < nq; ++a) Jb[m * nq + a] += P->sigma * (ep[m] * hb[a] - Jh[m] * qk[a]);
+                    eb[m] += P->sigma * Jh[m];
+                }
+                for (int a = 0; a < nq; ++a) {
+                    double acc = 0.0;
+                    for (int m = 0; m <= dim; ++m) acc += J[m * nq + a] * Jh[m];
+                    qb[a] -= P->sigma * acc;
+                }
+                /* e = (T + zeta, R + xi) at (s^k, y^{k+1}) */
+                zbar[(size_t)b * N + t - 1] += eb[0];
+                for (int c2 = 0; c2 < dim; ++c2) xibar[((size_t)b * dim + c2) * N + t - 1] += eb[1 + c2];
+                TR_adjoint(P, q, st, Yn + q->yoff + t - 1, N, eb[0], eb + 1, yb + q->yoff + t - 1, N, qb, grad_d);
+                jac_adjoint(P, q, st, Yn + q->yoff + t - 1, N, Jb, yb + q->yoff + t - 1, N, qb);
+                for (int a = 0; a < nq; ++a) qbar[((size_t)b * N + t - 1) * nq + a] += qb[a];
+            }
+        }
+    }
+    free(H); free(h); free(w); free(xbt);
+    return bad;
+}
+
+/*
+ * Gradient of L = sum_s F_s(x^K, u^K) after exactly K iterations (no early
+ * stop) from the initial iterate s^0 = obstacle-free LQ(x0), the given y0,
+ * zeta = xi = 0, with respect to every obstacle face offset d (grad_d[F_o])
+ * and every initial state (grad_x0[n_scen * n_s]). y0 is held fixed.
+ * Reverse mode through the stored iterates, with the dense KKT transposes of
+ * each pair QP on its active set and of the condensed trajectory QP.
+ * Returns 0, or the number of failed solves.
+ */
+int orc_admm_grad(const orc_problem *P, int K, const double *y0, double *L_out, double *grad_d, double *grad_x0)
+{
+    int S = P->n_scen, N = P->N, n_s = P->n_s, n_u = P->n_u, dim = P->dim, nq = dim + n_att(P);
+    int nb = count_blocks(P), bad = 0;
+    long ny = orc_y_size(P), npair = (long)nb * N;
+    size_t nx = (size_t)S * (N + 1) * n_s, nu_ = (size_t)S * N * n_u;
+    orc_block *B = (orc_block *)malloc(sizeof(orc_block) * (nb > 0 ? nb : 1));
+    enumerate_blocks(P, B);
+    double *X = (double *)malloc(sizeof(double) * nx * (K + 1));
+    double *U = (double *)malloc(sizeof(double) * nu_ * (K + 1));
+    double *Y = (double *)malloc(sizeof(double) * (ny > 0 ? ny : 1) * (K + 1));
+    double *Zt = (double *)calloc((size_t)(npair > 0 ? npair : 1) * (K + 1), sizeof(double));
+    double *XI = (double *)calloc((size_t)(npair > 0 ? npair : 1) * dim * (K + 1), sizeof(double));
+    double *rp = (double *)calloc(S, sizeof(double));
+    /* forward, storing every iterate */
+    {
+        double *H = (double *)malloc(sizeof(double) * N * n_s * n_s), *h = (double *)malloc(sizeof(double) * N * n_s);
+        for (int s = 0; s < S; ++s) {
+            lq_stage_base(P, s, H, h);
+            bad |= orc_traj_qp(n_s, n_u, N, P->A_dyn, P->B_dyn, P->c_dyn, P->x0 + (size_t)s * n_s, H, h, P->Q_u,
+                               X + (size_t)s * (N + 1) * n_s, U + (size_t)s * N * n_u);
+        }
+        free(H); free(h);
+    }
+    memcpy(Y, y0, sizeof(double) * ny);
+    for (int k = 0; k < K; ++k) {
+        double *Xk = X + nx * k, *Yk = Y + (size_t)ny * k, *Zk = Zt + (size_t)npair * k, *XIk = XI + (size_t)npair * dim * k;
+        double *Xn = X + nx * (k + 1), *Un = U + nu_ * (k + 1), *Yn = Y + (size_t)ny * (k + 1);
+        double *Zn = Zt + (size_t)npair * (k + 1), *XIn = XI + (size_t)npair * dim * (k + 1);
+        memcpy(Yn, Yk, sizeof(double) * ny);
+        bad += orc_pair_phase(P, Xk, Yk, Zk, XIk, NULL, Yn);
+        memcpy(Un, U + nu_ * k, sizeof(double) * nu_);
+        bad += orc_traj_phase(P, Xk, Yn, Zk, XIk, NULL, Xn, Un);
+        memcpy(Zn, Zk, sizeof(double) * npair);
+        memcpy(XIn, XIk, sizeof(double) * npair * dim);
+        orc_mult_phase(P, Xn, Yn, NULL, Zn, XIn, rp);
+    }
+    double L = 0.0;
+    for (int s = 0; s < S; ++s) L += orc_cost(P, s, X + nx * K, U + nu_ * K);
+    *L_out = L;
+    /* adjoints */
+    double *xb = (double *)calloc(nx, sizeof(double)), *ub = (double *)calloc(nu_, sizeof(double));
+    double *yb = (double *)calloc(ny > 0 ? ny : 1, sizeof(double)), *yb_old = (double *)calloc(ny > 0 ? ny : 1, sizeof(double));
+    double *zbar = (double *)calloc(npair > 0 ? npair : 1, sizeof(double));
+    double *xibar = (double *)calloc((npair > 0 ? npair : 1) * dim, sizeof(double));
+    double *qbar = (double *)calloc((size_t)(npair > 0 ? npair : 1) * nq, sizeof(double));
+    int Fo = P->obs_face_ptr[P->obs_ptr[S]];
+    for (int i = 0; i < Fo; ++i) grad_d[i] = 0.0;
+    for (int i = 0; i < S * n_s; ++i) grad_x0[i] = 0.0;
+    int qidx[6];
+    for (int r = 0; r < dim; ++r) qidx[r] = P->pos_idx[r];
+    for (int a = 0; a < n_att(P); ++a) qidx[dim + a] = P->att_idx[a];
+    /* dL/dx^K, dL/du^K of F = sum (x - xref)^T Q_s (x - xref) + u^T Q_u u */
+    for (int s = 0; s < S; ++s) {
+        for (int t = 1; t <= N; ++t) {
+            const double *xt = X + nx * K + ((size_t)s * (N + 1) + t) * n_s;
+            const double *xr = P->x_ref + ((size_t)s * (N + 1) + t) * n_s;
+            for (int r = 0; r < n_s; ++r) {
+                double acc = 0.0;
+                for (int q2 = 0; q2 < n_s; ++q2) acc += 2.0 * P->Q_s[r * n_s + q2] * (xt[q2] - xr[q2]);
+                xb[((size_t)s * (N + 1) + t) * n_s + r] = acc;
+            }
+        }
+        for (int t = 0; t < N; ++t) {
+            const double *ut = U + nu_ * K + ((size_t)s * N + t) * n_u;
+            for (int r = 0; r < n_u; ++r) {
+                double acc = 0.0;
+                for (int q2 = 0; q2 < n_u; ++q2) acc += 2.0 * P->Q_u[r * n_u + q2] * ut[q2];
+                ub[((size_t)s * N + t) * n_u + r] = acc;
+            }
+        }
+    }
+    double *H = (double *)malloc(sizeof(double) * N * n_s * n_s), *h = (double *)malloc(sizeof(double) * N * n_s);
+    double *w = (double *)malloc(sizeof(double) * N * n_s), *xbt = (double *)malloc(sizeof(double) * N * n_s);
+    for (int k = K - 1; k >= 0; --k) {
+        double *Xk = X + nx * k, *Yk = Y + (size_t)ny * k, *Zk = Zt + (size_t)npair * k, *XIk = XI + (size_t)npair * dim * k;
+        double *Xn = X + nx * (k + 1), *Un = U + nu_ * (k + 1), *Yn = Y + (size_t)ny * (k + 1);
+        /* (3) multiplier update adjoint at (s^{k+1}, y^{k+1}) */
+        memset(qbar, 0, sizeof(double) * npair * nq);
+        for (int b = 0; b < nb; ++b)
+            for (int t = 1; t <= N; ++t) {
+                const orc_block *q = &B[b];
+                double rbv[3];
+                for (int r = 0; r < dim; ++r) rbv[r] = xibar[((size_t)b * dim + r) * N + t - 1];
+                TR_adjoint(P, q, state_at(P, Xn, q->s, t), Yn + q->yoff + t - 1, N, zbar[(size_t)b * N + t - 1], rbv,
+                           yb + q->yoff + t - 1, N, qbar + ((size_t)b * N + t - 1) * nq,
+                           grad_d);
+            }
+        for (int b = 0; b < nb; ++b)
+            for (int t = 1; t <= N; ++t)
+                for (int a = 0; a < nq; ++a)
+                    xb[((size_t)B[b].s * (N + 1) + t) * n_s + qidx[a]] += qbar[((size_t)b * N + t - 1) * nq + a];
+        /* zeta^k, xi^k receive the identity part of the update: zbar, xibar unchanged */
+        /* (2) trajectory QP adjoint */
+        memset(qbar, 0, sizeof(double) * npair * nq);
+        bad += traj_adjoint(P, B, nb, Xk, Xn, Yn, Zk, XIk, xb, ub, yb, zbar, xibar, qbar, grad_d, grad_x0);
+        /* (1) pair QP adjoint: y^{k+1} <- (s^k, y^k, zeta^k, xi^k) */
+        memset(yb_old, 0, sizeof(double) * ny);
+        for (int b = 0; b < nb; ++b)
+            for (int t = 1; t <= N; ++t) {
+                const orc_block *q = &B[b];
+                double xr[3], xib[3] = {0, 0, 0};
+                for (int r = 0; r < dim; ++r) xr[r] = XIk[((size_t)b * dim + r) * N + t - 1];
+                bad += pairqp_adjoint(P, q, state_at(P, Xk, q->s, t), Yk + q->yoff + t - 1, Yn + q->yoff + t - 1, N,
+                                      Zk[(size_t)b * N + t - 1], xr, yb + q->yoff + t - 1, yb_old + q->yoff + t - 1, N,
+                                      &zbar[(size_t)b * N + t - 1], xib, qbar + ((size_t)b * N + t - 1) * nq, grad_d);
+                for (int r = 0; r < dim; ++r) xibar[((size_t)b * dim + r) * N + t - 1] += xib[r];
+            }
+        memcpy(yb, yb_old, sizeof(double) * ny);
+        for (int b = 0; b < nb; ++b)
+            for (int t = 1; t <= N; ++t)
+                for (int a = 0; a < nq; ++a)
+                    xb[((size_t)B[b].s * (N + 1) + t) * n_s + qidx[a]] += qbar[((size_t)b * N + t - 1) * nq + a];
+        (void)Un;
+    }
+    /* s^0 = obstacle-free LQ(x0): H_t = 2 Q_s; the u^0 adjoint is zero */
+    for (int s = 0; s < S; ++s) {
+        double *hh = (double *)malloc(sizeof(double) * N * n_s);
+        lq_stage_base(P, s, H, hh);
+        for (int t = 1; t <= N; ++t)
+            for (int r = 0; r < n_s; ++r) xbt[(t - 1) * n_s + r] = xb[((size_t)s * (N + 1) + t) * n_s + r];
+        bad += lq_adjoint(n_s, n_u, N, P->A_dyn, P->B_dyn, H, P->Q_u, xbt, NULL, w, grad_x0 + (size_t)s * n_s);
+        for (int r = 0; r < n_s; ++r) grad_x0[(size_t)s * n_s + r] += xb[((size_t)s * (N + 1)) * n_s + r];
+        free(hh);
+    }
+    free(H); free(h); free(w); free(xbt);
+    free(xb); free(ub); free(yb); free(yb_old); free(zbar); free(xibar); free(qbar);
+    free(B); free(X); free(U); free(Y); free(Zt); free(XI); free(rp);
+    return bad;
+}
+
+/* Test hook: VJP of one pair QP in the part frame. Given ybar (n), returns
+   the adjoints of dp (no), Cp (no x dim), zeta, xi (dim) and yhat (n) by the
+   same active-set KKT transpose as the reverse pass. */
+int orc_pairqp_vjp(int dim, int nr, const double *A, const double *b, int no, const double *Cp, const double *dp,
+                   double zeta, const double *xi, const double *yhat, double eps, const double *ybar,
+                   double *dp_bar, double *Cp_bar, double *zeta_bar, double *xi_bar, double *yhat_bar)
+{
+    int c = dim + 1, n = nr + no + 1;
+    double y[MAXROWS];
+    if (orc_pair_qp(dim, nr, A, b, no, Cp, dp, zeta, xi, yhat, eps, y) < 0) return 1;
+    double K[MAXROWS * (MAXD + 1)];
+    build_K(dim, nr, A, no, Cp, dp, K);
+    double bh[MAXD + 1], D[MAXROWS], kap[MAXROWS];
+    bh[0] = 1.0 + zeta;
+    for (int r = 0; r < dim; ++r) bh[1 + r] = xi[r];
+    for (int l = 0; l < n; ++l) {
+        double s = 0.0;
+        for (int m = 0; m < c; ++m) s += K[l * c + m] * K[l * c + m];
+        D[l] = s;
+        kap[l] = l < nr ? b[l] : 0.0;
+        yhat_bar[l] = 0.0;
+    }
+    int F[MAXROWS], nf = 0;
+    for (int l = 0; l < n; ++l) if (y[l] > 0.0) F[nf++] = l;
+    int sz = nf + 1;
+    double M[(MAXROWS + 1) * (MAXROWS + 1)], rhs[MAXROWS + 1];
+    for (int i2 = 0; i2 < nf; ++i2) {
+        for (int j2 = 0; j2 < nf; ++j2) {
+            double s = 0.0;
+            for (int m = 0; m < c; ++m) s += K[F[i2] * c + m] * K[F[j2] * c + m];
+            M[i2 * sz + j2] = s + (i2 == j2 ? eps * D[F[i2]] : 0.0);
+        }
+        M[i2 * sz + nf] = kap[F[i2]];
+        M[nf * sz + i2] = -kap[F[i2]];
+        rhs[i2] = ybar[F[i2]];
+    }
+    M[nf * sz + nf] = 0.0;
+    rhs[nf] = 0.0;
+    if (gauss_solve(sz, M, rhs)) return 1;
+    double gbar[MAXROWS] = {0}, Kbar[MAXROWS * (MAXD + 1)] = {0}, Dbar[MAXROWS] = {0}, bhbar[MAXD + 1] = {0};
+    for (int i2 = 0; i2 < nf; ++i2) gbar[F[i2]] = -rhs[i2];
+    for (int i2 = 0; i2 < nf; ++i2) {
+        int l = F[i2];
+        for (int m = 0; m < c; ++m) {
+            double yK = 0.0, aK = 0.0;
+            for (int j2 = 0; j2 < nf; ++j2) {
+                yK += y[F[j2]] * K[F[j2] * c + m];
+                aK += rhs[j2] * K[F[j2] * c + m];
+            }
+            Kbar[l * c + m] += -rhs[i2] * yK - y[l] * aK;
+        }
+        Dbar[l] += eps * (-rhs[i2] * y[l]);
+    }
+    for (int l = 0; l < n; ++l) {
+        if (gbar[l] == 0.0) continue;
+        for (int m = 0; m < c; ++m) {
+            Kbar[l * c + m] += gbar[l] * bh[m];
+            bhbar[m] += K[l * c + m] * gbar[l];
+        }
+        Dbar[l] += -eps * gbar[l] * yhat[l];
+        yhat_bar[l] += -eps * D[l] * gbar[l];
+    }
+    for (int l = 0; l < n; ++l)
+        for (int m = 0; m < c; ++m) Kbar[l * c + m] += 2.0 * Dbar[l] * K[l * c + m];
+    for (int l = 0; l < no; ++l) {
+        dp_bar[l] = Kbar[(nr + l) * c];
+        for (int r = 0; r < dim; ++r) Cp_bar[l * dim + r] = Kbar[(nr + l) * c + 1 + r];
+    }
+    *zeta_bar = bhbar[0];
+    for (int r = 0; r < dim; ++r) xi_bar[r] = bhbar[1 + r];
+    return 0;
+}
+
+/* Test hook: VJP of the trajectory phase for cotangents (xbar of x^{k+1},
+   ubar of u^{k+1}); writes the adjoints of y^{k+1}, zeta^k, xi^k, x^k (full
+   state array), the obstacle offsets and x0. Output arrays are overwritten. */
+int orc_traj_vjp(const orc_problem *P, const double *x_in, const double *y, const double *zeta, const double *xi,
+                 const double *xbar_in, const double *ubar_in, double *ybar, double *zbar, double *xibar,
+                 double *xkbar, double *dbar, double *x0bar)
+{
+    int S = P->n_scen, N = P->N, n_s = P->n_s, n_u = P->n_u, dim = P->dim, nq = dim + n_att(P);
+    int nb = count_blocks(P);
+    long ny = orc_y_size(P), npair = (long)nb * N;
+    size_t nx = (size_t)S * (N + 1) * n_s, nu_ = (size_t)S * N * n_u;
+    orc_block *B = (orc_block *)malloc(sizeof(orc_block) * (nb > 0 ? nb : 1));
+    enumerate_blocks(P, B);
+    double *xn = (double *)malloc(sizeof(double) * nx), *un = (double *)calloc(nu_, sizeof(double));
+    int bad = orc_traj_phase(P, x_in, y, zeta, xi, NULL, xn, un);
+    double *xb = (double *)malloc(sizeof(double) * nx), *ub = (double *)malloc(sizeof(double) * nu_);
+    memcpy(xb, xbar_in, sizeof(double) * nx);
+    memcpy(ub, ubar_in, sizeof(double) * nu_);
+    double *qbar = (double *)calloc((size_t)(npair > 0 ? npair : 1) * nq, sizeof(double));
+    memset(ybar, 0, sizeof(double) * ny);
+    memset(zbar, 0, sizeof(double) * npair);
+    memset(xibar, 0, sizeof(double) * npair * dim);
+    memset(xkbar, 0, sizeof(double) * nx);
+    memset(dbar, 0, sizeof(double) * P->obs_face_ptr[P->obs_ptr[S]]);
+    memset(x0bar, 0, sizeof(double) * S * n_s);
+    bad += traj_adjoint(P, B, nb, x_in, xn, y, zeta, xi, xb, ub, ybar, zbar, xibar, qbar, dbar, x0bar);
+    int qidx[6];
+    for (int r = 0; r < dim; ++r) qidx[r] = P->pos_idx[r];
+    for (int a = 0; a < n_att(P); ++a) qidx[dim + a] = P->att_idx[a];
+    for (int b = 0; b < nb; ++b)
+        for (int t = 1; t <= N; ++t)
+            for (int a = 0; a < nq; ++a)
+                xkbar[((size_t)B[b].s * (N + 1) + t) * n_s + qidx[a]] += qbar[((size_t)b * N + t - 1) * nq + a];
+    free(B); free(xn); free(un); free(xb); free(ub); free(qbar);
+    return bad;
+}
