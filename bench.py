@@ -113,6 +113,44 @@ def batched_vs_plain(cadmm, torch, steps=2, iters=50):
                 batched_waves_per_group=wb[0])
 
 
+def differentiation(cadmm, torch, steps=3, iters=100, every=10):
+    """Reverse pass of the 3D configuration unrolled over 100 iterations with
+    a checkpoint every 10: wall time of admm_backward (segment replay +
+    adjoint kernels) against the forward run that records the checkpoints,
+    and against a plain 100-iteration forward solve."""
+    prob = workloads.make("c3")
+    h = cadmm.Handle(prob)
+    nbytes = h.grad_workspace_size(iters, every)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    def plain():
+        h.reset()
+        h.iterate(iters)
+
+    def rec():
+        h.reset()
+        h.record(iters, every)
+
+    plain(); rec(); h.backward()
+    t_plain = timed(plain)
+    t_rec = timed(rec)
+    t_bwd = timed(lambda: h.backward())
+    h.close()
+    n_faces = len(prob["obs_d"])
+    return dict(workload=f"3D quadrotor (3 boxes), 200 hull polyhedra, N=40, {iters} unrolled iterations, "
+                         f"checkpoint every {every}; gradient w.r.t. {n_faces} obstacle offsets and the "
+                         f"{prob['n_s']}-dim initial state",
+                forward_ms=t_rec * 1e3, plain_solve_ms=t_plain * 1e3, backward_ms=t_bwd * 1e3,
+                backward_forward_ratio=t_bwd / t_rec, grad_workspace_mb=nbytes / 1e6)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +159,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -183,6 +222,9 @@ def main():
     if not args.no_batched:
         print("[bench] batched vs plain (256 scenarios)", file=sys.stderr, flush=True)
         out["batched"] = batched_vs_plain(cadmm, torch)
+    if not args.no_grad:
+        print("[bench] reverse pass (3D, 100 unrolled iterations)", file=sys.stderr, flush=True)
+        out["differentiation"] = differentiation(cadmm, torch)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (FP64 oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob, iters)

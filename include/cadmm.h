@@ -180,6 +180,43 @@ int admm_phase_times(cadmm_handle* h, int n_iters, float* ms_out);
  * waves (pair blocks) per workgroup and number of workgroups. */
 int admm_launch_config(cadmm_handle* h, int* waves_per_group, int* n_workgroups);
 
+/* Replace the obstacle face offsets d (host FP64, F_o values in obs_face_ptr
+ * order) and/or the initial states x0 (host FP64, n_scen*n_s); NULL keeps the
+ * current values. The iterate is not touched: call admm_reset (or
+ * admm_record) to start from the new data. Syncs the stream. */
+int admm_set_params(cadmm_handle* h, const double* obs_d, const double* x0);
+
+/*
+ * Differentiation through the unrolled iteration. The differentiated map is
+ *     L(d, x0) = sum_s F_s(x^K, u^K),
+ * the tracking cost (Sec. IV-A eq. navigation_cost) after exactly K
+ * iterations of Sec. IV-B (no stopping test) from s^0 = the obstacle-free LQ
+ * trajectory of x0, zeta^0 = xi^0 = 0 and the dual iterate y^0 that the handle
+ * holds when admm_record is called (after admm_reset: the scale-LP
+ * certificates at s^0). y^0 is held fixed: its dependence on (d, x0) is not
+ * differentiated. Each pair QP is differentiated on its free set
+ * {l : y_l > 0}; where a dual is exactly zero with a zero multiplier the
+ * map has a kink and the one-sided derivative of that active set is taken.
+ *
+ * admm_grad_workspace_size: bytes of the caller-owned DEVICE gradient
+ *   workspace for K = n_iters iterations with a checkpoint of the iterate
+ *   (x, u, y, zeta, xi) every ckpt_every iterations; it grows like
+ *   (K / ckpt_every + ckpt_every) iterates.
+ * admm_record: runs the K iterations on the handle's stream (graph replay),
+ *   keeping the checkpoints in d_gws (256-byte aligned, >= the size above),
+ *   and leaves the handle at iterate K; cost_out (DEVICE, n_scen floats, may
+ *   be NULL) receives F_s(x^K, u^K). No host sync.
+ * admm_backward: the reverse pass over the run recorded in d_gws (same
+ *   pointer): each segment of ckpt_every iterations is replayed from its
+ *   checkpoint (bitwise identical to the recorded run) and reversed step by
+ *   step. Writes dL_scale * dL/dd to grad_d[F_o] and dL_scale * dL/dx0 to
+ *   grad_x0[n_scen*n_s] (DEVICE FP32, overwritten). Leaves the handle at
+ *   iterate K. No host sync. CADMM_INVALID if nothing was recorded in d_gws.
+ */
+int admm_grad_workspace_size(cadmm_handle* h, int n_iters, int ckpt_every, size_t* bytes);
+int admm_record(cadmm_handle* h, int n_iters, int ckpt_every, void* d_gws, size_t bytes, float* cost_out);
+int admm_backward(cadmm_handle* h, void* d_gws, size_t bytes, float dL_scale, float* grad_d, float* grad_x0);
+
 void collision_admm_destroy(cadmm_handle* h);
 
 /*

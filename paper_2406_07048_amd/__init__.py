@@ -82,6 +82,10 @@ _SIGNATURES = {
     "admm_scales": (ctypes.c_int, [_vp, _vp]),
     "admm_phase_times": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
     "admm_launch_config": (ctypes.c_int, [_vp, _ip, _ip]),
+    "admm_set_params": (ctypes.c_int, [_vp, _dp, _dp]),
+    "admm_grad_workspace_size": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "admm_record": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp]),
+    "admm_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_float, _vp, _vp]),
     "collision_admm_destroy": (None, [_vp]),
     "pair_qp_batch": (ctypes.c_int, [ctypes.POINTER(CadmmPairBatch), _vp]),
     "pair_scale_batch": (ctypes.c_int, [ctypes.POINTER(CadmmScaleBatch), _vp]),
@@ -275,6 +279,56 @@ class Handle:
         _check(lib().admm_launch_config(self._h, ctypes.byref(w), ctypes.byref(g)), "admm_launch_config")
         return w.value, g.value
 
+    # -- differentiation --------------------------------------------------
+    def set_params(self, obs_d=None, x0=None):
+        """Replace the obstacle offsets d [F_o] and/or initial states x0
+        [n_scen, n_s] (anything numpy can read; copied as FP64). The iterate
+        is left alone: reset() or record() start from the new data."""
+        d = None if obs_d is None else np.ascontiguousarray(_host(obs_d), dtype=np.float64).ravel()
+        x = None if x0 is None else np.ascontiguousarray(_host(x0), dtype=np.float64).ravel()
+        if d is not None and d.size != len(self.prob["obs_d"]):
+            raise ValueError(f"obs_d has {d.size} values, expected {len(self.prob['obs_d'])}")
+        if x is not None and x.size != self.n_scen * self.n_s:
+            raise ValueError(f"x0 has {x.size} values, expected {self.n_scen * self.n_s}")
+        _check(lib().admm_set_params(self._h, None if d is None else d.ctypes.data_as(_dp),
+                                     None if x is None else x.ctypes.data_as(_dp)), "admm_set_params")
+
+    def grad_workspace_size(self, n_iters, ckpt_every=10):
+        n = ctypes.c_size_t()
+        _check(lib().admm_grad_workspace_size(self._h, int(n_iters), int(ckpt_every), ctypes.byref(n)),
+               "admm_grad_workspace_size")
+        return n.value
+
+    def record(self, n_iters, ckpt_every=10):
+        """Run exactly n_iters iterations from s^0 = LQ(x0), zero multipliers
+        and the current y, keeping checkpoints for backward(). Returns the
+        per-scenario tracking cost of the last iterate (device tensor)."""
+        torch = _torch()
+        nbytes = self.grad_workspace_size(n_iters, ckpt_every)
+        gw = getattr(self, "_grad_ws", None)
+        if gw is None or gw.numel() < nbytes + 256:
+            self._grad_ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self._grad_ws.data_ptr() + 255) & ~255
+        cost = torch.empty(self.n_scen, dtype=torch.float32, device=self.device)
+        _check(lib().admm_record(self._h, int(n_iters), int(ckpt_every), ctypes.c_void_p(ptr), nbytes, _ptr(cost)),
+               "admm_record")
+        self._grad_rec = (ptr, nbytes)
+        return cost
+
+    def backward(self, scale=1.0):
+        """scale * (dL/dd [F_o], dL/dx0 [n_scen, n_s]) of the recorded run,
+        L = sum_s F_s(x^K, u^K), y^0 held fixed (device tensors)."""
+        torch = _torch()
+        rec = getattr(self, "_grad_rec", None)
+        if rec is None:
+            raise RuntimeError("backward() needs a record() first")
+        f = dict(dtype=torch.float32, device=self.device)
+        gd = torch.empty(max(len(self.prob["obs_d"]), 1), **f)
+        gx = torch.empty(self.n_scen, self.n_s, **f)
+        _check(lib().admm_backward(self._h, ctypes.c_void_p(rec[0]), rec[1], float(scale), _ptr(gd), _ptr(gx)),
+               "admm_backward")
+        return gd[:len(self.prob["obs_d"])], gx
+
     def close(self):
         if getattr(self, "_h", None):
             lib().collision_admm_destroy(self._h)
@@ -289,6 +343,54 @@ class Handle:
 
 def collision_admm_setup(prob, **kw):
     return Handle(prob, **kw)
+
+
+def _host(a):
+    """numpy view of an array or tensor (tensors are copied to the host)."""
+    if hasattr(a, "detach"):
+        return a.detach().to("cpu").numpy()
+    return np.asarray(a)
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class CollisionADMMCost(torch.autograd.Function):
+        """L(d, x0) = sum_s F_s(x^K, u^K) after exactly K ADMM iterations from
+        s^0 = LQ(x0), zero multipliers and the scale-LP certificates of s^0 as
+        y^0 (held fixed), with the forward run on the GPU (admm_record) and the
+        gradient from the reverse pass (admm_backward). One pending backward
+        per handle: a second forward on the same handle replaces the first."""
+
+        @staticmethod
+        def forward(ctx, obs_d, x0, handle, n_iters, ckpt_every):
+            handle.set_params(obs_d=obs_d, x0=x0)
+            handle.reset()
+            cost = handle.record(int(n_iters), int(ckpt_every))
+            ctx.handle = handle
+            ctx.shapes = (obs_d.shape, obs_d.dtype, obs_d.device, x0.shape, x0.dtype, x0.device)
+            return cost.sum().to(obs_d.dtype).to(obs_d.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            ds, dd, ddev, xs, xd, xdev = ctx.shapes
+            gd, gx = ctx.handle.backward(float(g))
+            return (gd.reshape(ds).to(dtype=dd, device=ddev), gx.reshape(xs).to(dtype=xd, device=xdev),
+                    None, None, None)
+
+    return CollisionADMMCost
+
+
+_COST_FN = None
+
+
+def collision_admm_cost(obs_d, x0, handle, n_iters, ckpt_every=10):
+    """Differentiable tracking cost after n_iters ADMM iterations (see
+    CollisionADMMCost); obs_d and x0 are torch tensors."""
+    global _COST_FN
+    if _COST_FN is None:
+        _COST_FN = _autograd_function()
+    return _COST_FN.apply(obs_d, x0, handle, n_iters, ckpt_every)
 
 
 def pair_qp_batch(row_ptr, K, kappa, yhat, bhat, eps, max_sweeps=0, stream=None):

@@ -1,0 +1,143 @@
+// Device helpers shared by the forward and reverse kernels of the gfx950
+// ADMM collision-avoidance library: small register solves, wave sums,
+// the pose of a robot part and the FP64 face offsets. Device code only.
+#pragma once
+#include "cadmm_internal.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace cadmm {
+
+// ------------------------------------------------------------------------
+// small dense helpers (fully unrolled, registers only)
+// ------------------------------------------------------------------------
+
+// In-place Cholesky solve of an SPD system H x = g (H full NV x NV).
+template <int NV>
+__device__ __forceinline__ void chol_solve(float (&H)[NV * NV], float (&g)[NV])
+{
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        float s = H[j * NV + j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) s -= H[j * NV + k] * H[j * NV + k];
+        s = fmaxf(s, 1e-30f);
+        const float L = sqrtf(s);
+        const float iL = 1.0f / L;
+        H[j * NV + j] = L;
+#pragma unroll
+        for (int i = j + 1; i < NV; ++i) {
+            float t = H[i * NV + j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= H[i * NV + k] * H[j * NV + k];
+            H[i * NV + j] = t * iL;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        float s = g[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= H[i * NV + k] * g[k];
+        g[i] = s / H[i * NV + i];
+    }
+#pragma unroll
+    for (int i = NV - 1; i >= 0; --i) {
+        float s = g[i];
+#pragma unroll
+        for (int k = i + 1; k < NV; ++k) s -= H[k * NV + i] * g[k];
+        g[i] = s / H[i * NV + i];
+    }
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_int(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ------------------------------------------------------------------------
+// pose: R(s), dR/d(attitude), part centre pos_i = rho(s) + R o_i
+// ------------------------------------------------------------------------
+
+template <int DIM>
+struct Pose {
+    static constexpr int NATT = DIM == 2 ? 1 : 3;
+    static constexpr int NQ = DIM + NATT;
+    float R[DIM * DIM];
+    float dR[NATT * DIM * DIM];
+    float pos[DIM];
+    double pos64[DIM];   // the same centre in FP64 (the state entries are exact in it)
+    float q[NQ];   // pose coordinates (position, attitude) of the state
+};
+
+// Face offset of an obstacle face in the part frame, d'_l = d_l - c_l.pos.
+// Formed in FP64 from the FP64 offset and the FP64 part centre: both are
+// world-frame numbers of the size of the scene while d'_l is of the size of
+// the clearance, so FP32 would lose most of its digits to cancellation.
+__device__ __forceinline__ float face_offset(const double* d64, int face, const float4& f, const double* pos64,
+                                             int dim)
+{
+    double acc = d64[face] - (double)f.x * pos64[0] - (double)f.y * pos64[1];
+    if (dim == 3) acc -= (double)f.z * pos64[2];
+    return (float)acc;
+}
+
+template <int DIM>
+__device__ __forceinline__ void make_pose(const DevProblem& P, const float* xs, int part, Pose<DIM>& ps)
+{
+    if constexpr (DIM == 2) {
+        const float th = xs[P.att_idx[0]];
+        float s, c;
+        sincosf(th, &s, &c);
+        ps.R[0] = c; ps.R[1] = -s; ps.R[2] = s; ps.R[3] = c;
+        ps.dR[0] = -s; ps.dR[1] = -c; ps.dR[2] = c; ps.dR[3] = -s;
+        ps.q[2] = th;
+    } else {
+        const float ph = xs[P.att_idx[0]], th = xs[P.att_idx[1]], psi = xs[P.att_idx[2]];
+        float sf, cf, st, ct, sp, cp;
+        sincosf(ph, &sf, &cf);
+        sincosf(th, &st, &ct);
+        sincosf(psi, &sp, &cp);
+        float* R = ps.R;
+        R[0] = cp * ct; R[1] = cp * st * sf - sp * cf; R[2] = cp * st * cf + sp * sf;
+        R[3] = sp * ct; R[4] = sp * st * sf + cp * cf; R[5] = sp * st * cf - cp * sf;
+        R[6] = -st;     R[7] = ct * sf;                R[8] = ct * cf;
+        float* D = ps.dR;   // d/dphi
+        D[0] = 0.f; D[1] = cp * st * cf + sp * sf; D[2] = -cp * st * sf + sp * cf;
+        D[3] = 0.f; D[4] = sp * st * cf - cp * sf; D[5] = -sp * st * sf - cp * cf;
+        D[6] = 0.f; D[7] = ct * cf;                D[8] = -ct * sf;
+        D += 9;             // d/dtheta
+        D[0] = -cp * st; D[1] = cp * ct * sf; D[2] = cp * ct * cf;
+        D[3] = -sp * st; D[4] = sp * ct * sf; D[5] = sp * ct * cf;
+        D[6] = -ct;      D[7] = -st * sf;     D[8] = -st * cf;
+        D += 9;             // d/dpsi
+        D[0] = -sp * ct; D[1] = -sp * st * sf - cp * cf; D[2] = -sp * st * cf + cp * sf;
+        D[3] = cp * ct;  D[4] = cp * st * sf - sp * cf;  D[5] = cp * st * cf + sp * sf;
+        D[6] = 0.f;      D[7] = 0.f;                     D[8] = 0.f;
+        ps.q[3] = ph; ps.q[4] = th; ps.q[5] = psi;
+    }
+    const float* o = P.part_off + part * 3;
+#pragma unroll
+    for (int r = 0; r < DIM; ++r) {
+        const float p = xs[P.pos_idx[r]];
+        ps.q[r] = p;
+        float ro = 0.f;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) ro += ps.R[r * DIM + c] * o[c];
+        ps.pos[r] = p + ro;
+        ps.pos64[r] = (double)p + (double)ro;
+    }
+}
+
+}  // namespace cadmm

@@ -43,7 +43,7 @@ struct Layout {
     size_t A_dyn, B_dyn, c_dyn, Q_s, Q_u, x_ref, x0;
     size_t x, u, y, zeta, xi, y_snap, x_snap, u_snap;
     size_t contrib, rdual_part, rpri_part, unconv_part;
-    size_t r_pri, r_dual, done, iters, unconv, hist_pri, hist_dual, Kgain, alpha, cost, min_alpha;
+    size_t r_pri, r_dual, done, iters, unconv, hist_pri, hist_dual, alpha, cost, min_alpha;
     size_t total;
 };
 
@@ -182,7 +182,6 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
     L.unconv = take(off, sizeof(int) * d->n_scen);
     L.hist_pri = take(off, sizeof(float) * (size_t)kHistCap * d->n_scen);
     L.hist_dual = take(off, sizeof(float) * (size_t)kHistCap * d->n_scen);
-    L.Kgain = take(off, sizeof(float) * (size_t)d->n_scen * N * nu * (ns + 1));
     L.alpha = take(off, sizeof(float) * std::max<long long>(L.n_pairs, 1));
     L.cost = take(off, sizeof(float) * d->n_scen);
     L.min_alpha = take(off, sizeof(float) * d->n_scen);
@@ -199,7 +198,12 @@ struct cadmm_handle {
     hipStream_t stream;
     hipStream_t cap;             // private stream used only for graph capture
     hipGraphExec_t g1, gK;       // 1-iteration and kGraphBlock-iteration graphs
+    hipGraphExec_t g1n, gKn;     // the same without the stopping test (unrolled runs)
     int W, grid;
+    // the last recorded unrolled run (admm_record), consumed by admm_backward
+    int rec_iters, rec_every;
+    void* rec_ws;
+    size_t rec_bytes;
     std::vector<int> obs_ptr;    // host copy (scenario -> obstacles)
     std::vector<int4> blocks;    // host copy
 };
@@ -246,21 +250,21 @@ int upload_worklists(cadmm_handle* h, int W)
 
 // one ADMM iteration: (1) pair QPs + contributions, (2) trajectory QP,
 // (3) multiplier update, residual sums and stopping test
-int enqueue_iteration(cadmm_handle* h, hipStream_t st)
+int enqueue_iteration(cadmm_handle* h, hipStream_t st, bool stop_test = true, float* hq_save = nullptr)
 {
     if (h->L.n_blocks > 0) HIP_TRY(launch_pair_phase(h->P, h->W, h->grid, st));
-    HIP_TRY(launch_traj_phase(h->P, h->L.n_blocks == 0 ? 1 : 0, st));
+    HIP_TRY(launch_traj_phase(h->P, h->L.n_blocks == 0 ? 1 : 0, st, hq_save));
     if (h->L.n_blocks > 0) HIP_TRY(launch_mult_phase(h->P, h->W, h->grid, st));
-    HIP_TRY(launch_residual(h->P, st));
+    if (stop_test) HIP_TRY(launch_residual(h->P, st));
     return CADMM_OK;
 }
 
-int capture(cadmm_handle* h, int iters, hipGraphExec_t* out)
+int capture(cadmm_handle* h, int iters, hipGraphExec_t* out, bool stop_test = true)
 {
     hipGraph_t g;
     HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
     int rc = CADMM_OK;
-    for (int i = 0; i < iters && rc == CADMM_OK; ++i) rc = enqueue_iteration(h, h->cap);
+    for (int i = 0; i < iters && rc == CADMM_OK; ++i) rc = enqueue_iteration(h, h->cap, stop_test);
     hipError_t e = hipStreamEndCapture(h->cap, &g);
     if (rc != CADMM_OK) return rc;
     if (e != hipSuccess) return fail(CADMM_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
@@ -272,17 +276,110 @@ int capture(cadmm_handle* h, int iters, hipGraphExec_t* out)
 
 void drop_graphs(cadmm_handle* h)
 {
-    if (h->g1) (void)hipGraphExecDestroy(h->g1);
-    if (h->gK) (void)hipGraphExecDestroy(h->gK);
-    h->g1 = h->gK = nullptr;
+    for (hipGraphExec_t* g : {&h->g1, &h->gK, &h->g1n, &h->gKn}) {
+        if (*g) (void)hipGraphExecDestroy(*g);
+        *g = nullptr;
+    }
 }
 
 int recapture(cadmm_handle* h)
 {
     drop_graphs(h);
-    int rc = capture(h, 1, &h->g1);
-    if (rc) return rc;
-    return capture(h, kGraphBlock, &h->gK);
+    int rc;
+    if ((rc = capture(h, 1, &h->g1)) || (rc = capture(h, kGraphBlock, &h->gK)) ||
+        (rc = capture(h, 1, &h->g1n, false)) || (rc = capture(h, kGraphBlock, &h->gKn, false)))
+        return rc;
+    return CADMM_OK;
+}
+
+// n iterations by graph replay, with or without the stopping test
+int launch_graphs(cadmm_handle* h, int n, bool stop_test)
+{
+    hipGraphExec_t gk = stop_test ? h->gK : h->gKn, g1 = stop_test ? h->g1 : h->g1n;
+    while (n >= kGraphBlock) {
+        HIP_TRY(hipGraphLaunch(gk, h->stream));
+        n -= kGraphBlock;
+    }
+    for (int i = 0; i < n; ++i) HIP_TRY(hipGraphLaunch(g1, h->stream));
+    return CADMM_OK;
+}
+
+// ---- reverse pass: layout of the caller's gradient workspace ----
+// An iterate slot holds (x, u, y, zeta, xi); u is kept because the
+// trajectory QP is solved about (x^k, u^k), so a replay from a slot repeats
+// the recorded run bit for bit. Checkpoint c holds the iterate k = c * every;
+// the segment buffer holds the replayed iterates k0+1..k0+every of one
+// segment (its iterate k0 is the checkpoint) and the stage sums of each
+// replayed trajectory QP; 'fin' holds the last iterate.
+struct Slot {
+    size_t x, u, y, zeta, xi;
+};
+
+struct GradLayout {
+    int iters, every, n_ckpt;
+    std::vector<Slot> ckpt, seg;    // seg[0] unused (the checkpoint)
+    std::vector<size_t> hq;
+    Slot fin;
+    size_t yb, zb, xib, qpart, w, gdb, gx0;
+    size_t total;
+};
+
+GradLayout plan_grad(const Layout& L, int n_wg, int iters, int every)
+{
+    GradLayout G;
+    G.iters = iters;
+    G.every = std::min(every, iters);
+    G.n_ckpt = (iters + G.every - 1) / G.every;
+    size_t off = 0;
+    const size_t xf = (size_t)L.n_scen * (L.N + 1) * L.n_s, uf = (size_t)L.n_scen * L.N * L.n_u;
+    const size_t yf = std::max<long long>(L.y_floats, 1), pf = std::max<long long>(L.n_pairs, 1);
+    auto slot = [&]() {
+        Slot q;
+        q.x = take(off, sizeof(float) * xf);
+        q.u = take(off, sizeof(float) * uf);
+        q.y = take(off, sizeof(float) * yf);
+        q.zeta = take(off, sizeof(float) * pf);
+        q.xi = take(off, sizeof(float) * pf * L.dim);
+        return q;
+    };
+    for (int c = 0; c < G.n_ckpt; ++c) G.ckpt.push_back(slot());
+    G.seg.push_back(Slot{0, 0, 0, 0, 0});
+    for (int j = 1; j <= G.every; ++j) G.seg.push_back(slot());
+    for (int j = 0; j < G.every; ++j) G.hq.push_back(take(off, sizeof(float) * (size_t)L.n_scen * L.N * L.nc));
+    G.fin = slot();
+    G.yb = take(off, sizeof(float) * yf);
+    G.zb = take(off, sizeof(float) * pf);
+    G.xib = take(off, sizeof(float) * pf * L.dim);
+    G.qpart = take(off, sizeof(float) * (size_t)std::max(n_wg, 1) * L.nq * 64);
+    G.w = take(off, sizeof(float) * (size_t)L.n_scen * L.N * L.n_s);
+    G.gdb = take(off, sizeof(double) * (size_t)L.n_parts * std::max(L.Fo, 1));
+    G.gx0 = take(off, sizeof(double) * (size_t)L.n_scen * L.n_s);
+    G.total = (off + 255) & ~size_t(255);
+    return G;
+}
+
+// copy the handle's iterate (x, u, y, zeta, xi) to or from a slot of base
+int copy_slot(cadmm_handle* h, char* base, const Slot& q, bool to_slot)
+{
+    const Layout& L = h->L;
+    const size_t xb = sizeof(float) * L.n_scen * (L.N + 1) * L.n_s, ub = sizeof(float) * L.n_scen * L.N * L.n_u,
+                 yb = sizeof(float) * L.y_floats, zb = sizeof(float) * L.n_pairs,
+                 ib = sizeof(float) * L.n_pairs * L.dim;
+    const size_t hs[5] = {L.x, L.u, L.y, L.zeta, L.xi}, qs[5] = {q.x, q.u, q.y, q.zeta, q.xi},
+                 nb[5] = {xb, ub, yb, zb, ib};
+    for (int i = 0; i < 5; ++i) {
+        if (nb[i] == 0) continue;
+        void* dst = to_slot ? (void*)(base + qs[i]) : (void*)(h->ws + hs[i]);
+        const void* src = to_slot ? (const void*)(h->ws + hs[i]) : (const void*)(base + qs[i]);
+        HIP_TRY(hipMemcpyAsync(dst, src, nb[i], hipMemcpyDeviceToDevice, h->stream));
+    }
+    return CADMM_OK;
+}
+
+int fill_zero(void* p, size_t bytes, hipStream_t st)
+{
+    HIP_TRY(launch_fill(static_cast<float*>(p), (long long)(bytes / sizeof(float)), 0.f, st));
+    return CADMM_OK;
 }
 
 // initial iterate (see collision_admm_setup)
@@ -398,7 +495,10 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     h->L = L;
     h->ws = static_cast<char*>(d_ws);
     h->stream = stream;
-    h->g1 = h->gK = nullptr;
+    h->g1 = h->gK = h->g1n = h->gKn = nullptr;
+    h->rec_iters = h->rec_every = 0;
+    h->rec_ws = nullptr;
+    h->rec_bytes = 0;
     h->obs_ptr.assign(d->obs_ptr, d->obs_ptr + d->n_scen + 1);
     hipError_t e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -499,7 +599,6 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     P.r_pri = at<float>(h, L.r_pri); P.r_dual = at<float>(h, L.r_dual);
     P.done = at<int>(h, L.done); P.iters = at<int>(h, L.iters); P.unconv = at<int>(h, L.unconv);
     P.hist_pri = at<float>(h, L.hist_pri); P.hist_dual = at<float>(h, L.hist_dual); P.hist_cap = kHistCap;
-    P.Kgain = at<float>(h, L.Kgain);
 
     if ((rc = upload_worklists(h, d->waves_per_group > 0 ? d->waves_per_group : 4))) return bail(rc);
     if ((rc = init_iterate(h))) return bail(rc);
@@ -513,12 +612,7 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
 int admm_iterate(cadmm_handle* h, int n_iters)
 {
     if (!h || n_iters < 0) return fail(CADMM_INVALID, "bad handle or iteration count");
-    while (n_iters >= kGraphBlock) {
-        HIP_TRY(hipGraphLaunch(h->gK, h->stream));
-        n_iters -= kGraphBlock;
-    }
-    for (int i = 0; i < n_iters; ++i) HIP_TRY(hipGraphLaunch(h->g1, h->stream));
-    return CADMM_OK;
+    return launch_graphs(h, n_iters, true);
 }
 
 int admm_reset(cadmm_handle* h)
@@ -674,6 +768,125 @@ int admm_launch_config(cadmm_handle* h, int* waves_per_group, int* n_workgroups)
     if (!h) return fail(CADMM_INVALID, "bad handle");
     if (waves_per_group) *waves_per_group = h->W;
     if (n_workgroups) *n_workgroups = h->P.n_wg;
+    return CADMM_OK;
+}
+
+int admm_set_params(cadmm_handle* h, const double* obs_d, const double* x0)
+{
+    if (!h) return fail(CADMM_INVALID, "bad handle");
+    const Layout& L = h->L;
+    if (obs_d && !finite_all(obs_d, L.Fo)) return fail(CADMM_INVALID, "non-finite obstacle offsets");
+    if (x0 && !finite_all(x0, (long long)L.n_scen * L.n_s)) return fail(CADMM_INVALID, "non-finite initial states");
+    std::vector<float> x0f;
+    if (obs_d && L.Fo > 0) {
+        HIP_TRY(hipMemcpyAsync(h->ws + L.obs_d64, obs_d, sizeof(double) * L.Fo, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(launch_set_face_offsets(at<float4>(h, L.obs_faces), at<double>(h, L.obs_d64), L.Fo, h->stream));
+    }
+    if (x0) {
+        x0f.resize((size_t)L.n_scen * L.n_s);
+        for (size_t i = 0; i < x0f.size(); ++i) x0f[i] = (float)x0[i];
+        HIP_TRY(hipMemcpyAsync(h->ws + L.x0, x0f.data(), sizeof(float) * x0f.size(), hipMemcpyHostToDevice,
+                               h->stream));
+    }
+    // the host arrays must stay alive until the copies are done
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return CADMM_OK;
+}
+
+int admm_grad_workspace_size(cadmm_handle* h, int n_iters, int ckpt_every, size_t* bytes)
+{
+    if (!h || n_iters < 1 || ckpt_every < 1 || !bytes)
+        return fail(CADMM_INVALID, "bad handle, iteration count, checkpoint interval or output");
+    *bytes = plan_grad(h->L, h->P.n_wg, n_iters, ckpt_every).total;
+    return CADMM_OK;
+}
+
+int admm_record(cadmm_handle* h, int n_iters, int ckpt_every, void* d_gws, size_t bytes, float* cost_out)
+{
+    if (!h || n_iters < 1 || ckpt_every < 1)
+        return fail(CADMM_INVALID, "bad handle, iteration count or checkpoint interval");
+    const Layout& L = h->L;
+    const GradLayout G = plan_grad(L, h->P.n_wg, n_iters, ckpt_every);
+    if (!d_gws || (reinterpret_cast<uintptr_t>(d_gws) & 255) != 0)
+        return fail(CADMM_WORKSPACE, "gradient workspace must be a 256-byte aligned device pointer");
+    if (bytes < G.total)
+        return fail(CADMM_WORKSPACE, "gradient workspace too small: need " + std::to_string(G.total) + " bytes");
+    char* base = static_cast<char*>(d_gws);
+    hipStream_t st = h->stream;
+    h->rec_iters = 0;
+    // s^0 = obstacle-free LQ trajectory, zeta = xi = 0, y^0 as it stands
+    HIP_TRY(launch_fill(at<float>(h, L.zeta), L.n_pairs, 0.f, st));
+    HIP_TRY(launch_fill(at<float>(h, L.xi), L.n_pairs * L.dim, 0.f, st));
+    HIP_TRY(launch_fill_int(at<int>(h, L.done), L.n_scen, 0, st));
+    HIP_TRY(launch_traj_phase(h->P, 1, st));
+    int rc;
+    for (int c = 0; c < G.n_ckpt; ++c) {
+        if ((rc = copy_slot(h, base, G.ckpt[c], true))) return rc;
+        if ((rc = launch_graphs(h, std::min(G.every, n_iters - c * G.every), false))) return rc;
+    }
+    if ((rc = copy_slot(h, base, G.fin, true))) return rc;
+    if (cost_out) HIP_TRY(launch_cost(h->P, cost_out, st));
+    h->rec_iters = n_iters;
+    h->rec_every = ckpt_every;
+    h->rec_ws = d_gws;
+    h->rec_bytes = bytes;
+    return CADMM_OK;
+}
+
+int admm_backward(cadmm_handle* h, void* d_gws, size_t bytes, float dL_scale, float* grad_d, float* grad_x0)
+{
+    if (!h) return fail(CADMM_INVALID, "bad handle");
+    if (h->rec_iters < 1 || d_gws != h->rec_ws || bytes < h->rec_bytes)
+        return fail(CADMM_INVALID, "no recorded run in this gradient workspace (call admm_record first)");
+    const Layout& L = h->L;
+    if (!grad_x0 || (L.Fo > 0 && !grad_d)) return fail(CADMM_INVALID, "NULL gradient output");
+    const GradLayout G = plan_grad(L, h->P.n_wg, h->rec_iters, h->rec_every);
+    char* base = static_cast<char*>(d_gws);
+    hipStream_t st = h->stream;
+    const bool pairs = L.n_blocks > 0;
+    int rc;
+    if ((rc = fill_zero(base + G.yb, sizeof(float) * L.y_floats, st)) ||
+        (rc = fill_zero(base + G.zb, sizeof(float) * L.n_pairs, st)) ||
+        (rc = fill_zero(base + G.xib, sizeof(float) * L.n_pairs * L.dim, st)) ||
+        (rc = fill_zero(base + G.gdb, sizeof(double) * L.n_parts * L.Fo, st)) ||
+        (rc = fill_zero(base + G.gx0, sizeof(double) * L.n_scen * L.n_s, st)))
+        return rc;
+    HIP_TRY(launch_fill_int(at<int>(h, L.done), L.n_scen, 0, st));
+    auto F = [&](size_t off) { return reinterpret_cast<float*>(base + off); };
+    float* w = F(G.w);
+    float* qpart = F(G.qpart);
+    double* gx0 = reinterpret_cast<double*>(base + G.gx0);
+    double* gdb = reinterpret_cast<double*>(base + G.gdb);
+    bool first = true;
+    for (int c = G.n_ckpt - 1; c >= 0; --c) {
+        const int k0 = c * G.every, len = std::min(G.every, G.iters - k0);
+        // replay the segment from its checkpoint, keeping every iterate and
+        // the stage sums of every trajectory QP
+        if ((rc = copy_slot(h, base, G.ckpt[c], false))) return rc;
+        for (int j = 0; j < len; ++j) {
+            if ((rc = enqueue_iteration(h, st, false, F(G.hq[j])))) return rc;
+            if ((rc = copy_slot(h, base, G.seg[j + 1], true))) return rc;
+        }
+        for (int j = len - 1; j >= 0; --j) {
+            const Slot& a = j == 0 ? G.ckpt[c] : G.seg[j];
+            const Slot& n = G.seg[j + 1];
+            // without pair blocks every trajectory QP is the obstacle-free one
+            TrajAdjoint TA{pairs ? F(G.hq[j]) : nullptr, (first || !pairs) ? nullptr : qpart,
+                           first ? F(G.fin.x) : nullptr,
+                           first ? F(G.fin.u) : nullptr, w, gx0};
+            HIP_TRY(launch_traj_adjoint(h->P, TA, st));
+            PairAdjoint PA{F(a.x), F(n.x), F(a.y), F(n.y), F(a.zeta), F(a.xi), w, F(G.yb), F(G.zb), F(G.xib),
+                           qpart, gdb, L.Fo, (k0 + j) >= 1 ? 1 : 0};
+            HIP_TRY(launch_pair_adjoint(h->P, PA, h->W, h->grid, st));
+            first = false;
+        }
+    }
+    // s^0 = obstacle-free LQ(x_0)
+    TrajAdjoint T0{nullptr, pairs ? qpart : nullptr, nullptr, nullptr, w, gx0};
+    HIP_TRY(launch_traj_adjoint(h->P, T0, st));
+    HIP_TRY(launch_grad_finalize(L.n_parts, L.Fo, gdb, L.n_scen * L.n_s, gx0, dL_scale, grad_d, grad_x0, st));
+    // leave the handle at the last iterate of the recorded run
+    if ((rc = copy_slot(h, base, G.fin, false))) return rc;
     return CADMM_OK;
 }
 

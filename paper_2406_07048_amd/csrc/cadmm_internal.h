@@ -57,16 +57,52 @@ struct DevProblem {
     float* hist_pri;             // [hist_cap*n_scen]
     float* hist_dual;            // [hist_cap*n_scen]
     int hist_cap;
-    float* Kgain;                // [n_scen][N][n_u*(n_s+1)] Riccati gains scratch
 };
 
-// Kernel launchers (defined in cadmm_kernels.hip). All return hipError_t of the launch.
+// Inputs and outputs of the trajectory kernel in reverse mode (one adjoint LQ
+// per scenario; see the trajectory kernel).
+struct TrajAdjoint {
+    const float* hq;       // [n_scen][N][nc] stage sums saved by the forward pass; NULL = obstacle-free
+    const float* qpart;    // [n_wg][nq][64] pose cotangents per workgroup; NULL = none
+    const float* xK;       // [n_scen][N+1][n_s] last trajectory for the cost gradient; NULL = none
+    const float* uK;       // [n_scen][N][n_u] last inputs for the cost gradient; NULL = none
+    float* w;              // [n_scen][N][n_s] out: w_t, t = 1..N
+    double* gx0;           // [n_scen][n_s] accumulated cotangent of x_0
+};
+
+// Inputs and outputs of the reverse pair kernel for the step k -> k+1 of the
+// iteration (all canonical layouts; see the reverse pair kernel).
+struct PairAdjoint {
+    const float* xk;       // trajectory x^k (poses of the pair QPs and stage terms)
+    const float* xn;       // trajectory x^{k+1}
+    const float* yk;       // duals y^k (proximal centre; multipliers of step k-1)
+    const float* yn;       // duals y^{k+1}
+    const float* zk;       // zeta^k
+    const float* xik;      // xi^k
+    const float* w;        // [n_scen][N][n_s] adjoint LQ trajectory of step k
+    float* yb;             // in: cotangent of y^{k+1}; out: of y^k
+    float* zb;             // in: of zeta^{k+1}; out: of zeta^k
+    float* xib;            // in: of xi^{k+1}; out: of xi^k
+    float* qpart;          // out: [n_wg][nq][64] pose cotangents of x^k per workgroup
+    double* gdb;           // [n_parts][F_o] accumulated offset cotangents
+    int n_obs_faces;       // F_o (row stride of gdb)
+    int has_mult;          // k >= 1: include the multiplier update of step k-1
+};
+
+// Kernel launchers (defined in cadmm_kernels.hip / cadmm_adjoint.hip). All
+// return hipError_t of the launch.
 hipError_t launch_pair_phase(const DevProblem& P, int waves_per_group, int grid, hipStream_t s);
 hipError_t launch_mult_phase(const DevProblem& P, int waves_per_group, int grid, hipStream_t s);
-hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t s);
+hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t s, float* hq_save = nullptr);
+hipError_t launch_traj_adjoint(const DevProblem& P, const TrajAdjoint& TA, hipStream_t s);
+hipError_t launch_pair_adjoint(const DevProblem& P, const PairAdjoint& A, int waves_per_group, int grid,
+                               hipStream_t s);
+hipError_t launch_grad_finalize(int n_parts, int n_faces, const double* gdb, int n_x0, const double* gx0,
+                                float scale, float* grad_d, float* grad_x0, hipStream_t s);
 hipError_t launch_residual(const DevProblem& P, hipStream_t s);
 hipError_t launch_init_pairs(const DevProblem& P, float* alpha_out, int write_y, hipStream_t s);
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t s);
+hipError_t launch_set_face_offsets(float4* faces, const double* d64, int n, hipStream_t s);
 hipError_t launch_fill_int(int* p, long long n, int v, hipStream_t s);
 hipError_t launch_cost(const DevProblem& P, float* cost_out, hipStream_t s);
 hipError_t launch_min_alpha(const DevProblem& P, const float* alpha, float* out, hipStream_t s);

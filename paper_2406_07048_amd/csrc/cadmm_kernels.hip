@@ -5,7 +5,7 @@
 //   t = 1..N; lane t-1 of the wave owns pair (i, j, t). The block's geometry
 //   (faces of part i and obstacle j) is wave-uniform and is read through the
 //   scalar cache; each lane keeps its pair's small QP in registers.
-//   A workgroup holds up to 16 waves = blocks of the same scenario, so the
+//   A workgroup holds up to 8 waves = blocks of the same scenario, so the
 //   per-time-step sums of the trajectory-QP contributions are formed in LDS
 //   (fixed order, no float atomics) and written once per workgroup.
 //
@@ -14,143 +14,13 @@
 // equality) by a semismooth Newton method with an exact-sign line search;
 // the primal y is recovered row by row as max(0, yhat - (K_l v - kappa_l nu)
 // / (eps D_l)).
-#include "cadmm_internal.h"
+#include "cadmm_device.h"
 
 #include <float.h>
 #include <math.h>
 
 namespace cadmm {
 
-// ------------------------------------------------------------------------
-// small dense helpers (fully unrolled, registers only)
-// ------------------------------------------------------------------------
-
-// In-place Cholesky solve of an SPD system H x = g (H full NV x NV).
-template <int NV>
-__device__ __forceinline__ void chol_solve(float (&H)[NV * NV], float (&g)[NV])
-{
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        float s = H[j * NV + j];
-#pragma unroll
-        for (int k = 0; k < j; ++k) s -= H[j * NV + k] * H[j * NV + k];
-        s = fmaxf(s, 1e-30f);
-        const float L = sqrtf(s);
-        const float iL = 1.0f / L;
-        H[j * NV + j] = L;
-#pragma unroll
-        for (int i = j + 1; i < NV; ++i) {
-            float t = H[i * NV + j];
-#pragma unroll
-            for (int k = 0; k < j; ++k) t -= H[i * NV + k] * H[j * NV + k];
-            H[i * NV + j] = t * iL;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        float s = g[i];
-#pragma unroll
-        for (int k = 0; k < i; ++k) s -= H[i * NV + k] * g[k];
-        g[i] = s / H[i * NV + i];
-    }
-#pragma unroll
-    for (int i = NV - 1; i >= 0; --i) {
-        float s = g[i];
-#pragma unroll
-        for (int k = i + 1; k < NV; ++k) s -= H[k * NV + i] * g[k];
-        g[i] = s / H[i * NV + i];
-    }
-}
-
-__device__ __forceinline__ float wave_sum(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-__device__ __forceinline__ int wave_sum_int(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// ------------------------------------------------------------------------
-// pose: R(s), dR/d(attitude), part centre pos_i = rho(s) + R o_i
-// ------------------------------------------------------------------------
-
-template <int DIM>
-struct Pose {
-    static constexpr int NATT = DIM == 2 ? 1 : 3;
-    static constexpr int NQ = DIM + NATT;
-    float R[DIM * DIM];
-    float dR[NATT * DIM * DIM];
-    float pos[DIM];
-    double pos64[DIM];   // the same centre in FP64 (the state entries are exact in it)
-    float q[NQ];   // pose coordinates (position, attitude) of the state
-};
-
-// Face offset of an obstacle face in the part frame, d'_l = d_l - c_l.pos.
-// Formed in FP64 from the FP64 offset and the FP64 part centre: both are
-// world-frame numbers of the size of the scene while d'_l is of the size of
-// the clearance, so FP32 would lose most of its digits to cancellation.
-__device__ __forceinline__ float face_offset(const double* d64, int face, const float4& f, const double* pos64,
-                                             int dim)
-{
-    double acc = d64[face] - (double)f.x * pos64[0] - (double)f.y * pos64[1];
-    if (dim == 3) acc -= (double)f.z * pos64[2];
-    return (float)acc;
-}
-
-template <int DIM>
-__device__ __forceinline__ void make_pose(const DevProblem& P, const float* xs, int part, Pose<DIM>& ps)
-{
-    if constexpr (DIM == 2) {
-        const float th = xs[P.att_idx[0]];
-        float s, c;
-        sincosf(th, &s, &c);
-        ps.R[0] = c; ps.R[1] = -s; ps.R[2] = s; ps.R[3] = c;
-        ps.dR[0] = -s; ps.dR[1] = -c; ps.dR[2] = c; ps.dR[3] = -s;
-        ps.q[2] = th;
-    } else {
-        const float ph = xs[P.att_idx[0]], th = xs[P.att_idx[1]], psi = xs[P.att_idx[2]];
-        float sf, cf, st, ct, sp, cp;
-        sincosf(ph, &sf, &cf);
-        sincosf(th, &st, &ct);
-        sincosf(psi, &sp, &cp);
-        float* R = ps.R;
-        R[0] = cp * ct; R[1] = cp * st * sf - sp * cf; R[2] = cp * st * cf + sp * sf;
-        R[3] = sp * ct; R[4] = sp * st * sf + cp * cf; R[5] = sp * st * cf - cp * sf;
-        R[6] = -st;     R[7] = ct * sf;                R[8] = ct * cf;
-        float* D = ps.dR;   // d/dphi
-        D[0] = 0.f; D[1] = cp * st * cf + sp * sf; D[2] = -cp * st * sf + sp * cf;
-        D[3] = 0.f; D[4] = sp * st * cf - cp * sf; D[5] = -sp * st * sf - cp * cf;
-        D[6] = 0.f; D[7] = ct * cf;                D[8] = -ct * sf;
-        D += 9;             // d/dtheta
-        D[0] = -cp * st; D[1] = cp * ct * sf; D[2] = cp * ct * cf;
-        D[3] = -sp * st; D[4] = sp * ct * sf; D[5] = sp * ct * cf;
-        D[6] = -ct;      D[7] = -st * sf;     D[8] = -st * cf;
-        D += 9;             // d/dpsi
-        D[0] = -sp * ct; D[1] = -sp * st * sf - cp * cf; D[2] = -sp * st * cf + cp * sf;
-        D[3] = cp * ct;  D[4] = cp * st * sf - sp * cf;  D[5] = cp * st * cf + sp * sf;
-        D[6] = 0.f;      D[7] = 0.f;                     D[8] = 0.f;
-        ps.q[3] = ph; ps.q[4] = th; ps.q[5] = psi;
-    }
-    const float* o = P.part_off + part * 3;
-#pragma unroll
-    for (int r = 0; r < DIM; ++r) {
-        const float p = xs[P.pos_idx[r]];
-        ps.q[r] = p;
-        float ro = 0.f;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) ro += ps.R[r * DIM + c] * o[c];
-        ps.pos[r] = p + ro;
-        ps.pos64[r] = (double)p + (double)ro;
-    }
-}
 
 // ------------------------------------------------------------------------
 // the pair sub-problem in the ADMM kernel: structured rows
@@ -661,14 +531,9 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
                         J[(1 + r) * NQ + DIM + a] = v;
                     }
                 }
-                float ep[DIM + 1];
-#pragma unroll
-                for (int m = 0; m <= DIM; ++m) {
-                    float acc = e[m];
-#pragma unroll
-                    for (int a = 0; a < NQ; ++a) acc -= J[m * NQ + a] * ps.q[a];
-                    ep[m] = acc;
-                }
+                // stage terms in deviation coordinates about x^k (the
+                // trajectory QP solves for x - x^k): Hessian sigma J^T J and
+                // gradient sigma J^T e, with no -J q^k term to cancel
                 const float sg = P.sigma;
                 int idx = 0;
 #pragma unroll
@@ -684,7 +549,7 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
                 for (int i = 0; i < NQ; ++i) {
                     float acc = 0.f;
 #pragma unroll
-                    for (int m = 0; m <= DIM; ++m) acc += J[m * NQ + i] * ep[m];
+                    for (int m = 0; m <= DIM; ++m) acc += J[m * NQ + i] * e[m];
                     con[idx++] = sg * acc;
                 }
             }
@@ -828,39 +693,62 @@ __global__ void __launch_bounds__(64) residual_kernel(DevProblem P)
 
 // ------------------------------------------------------------------------
 // ADMM step 2: trajectory QP by a backward Riccati sweep and forward
-// rollout; one workgroup per scenario. Stage cost 1/2 x^T H_t x + h_t^T x
-// with H_t = 2 Q_s + sum_ij sigma J^T J and h_t = -2 Q_s xref_t +
-// sum_ij sigma J^T (e - J q^k) (pose block), input cost u^T Q_u u.
+// rollout; one workgroup per scenario. The QP is solved in deviation
+// coordinates about the current iterate, dx = x - x^k, du = u - u^k: stage
+// cost 1/2 dx^T H_t dx + g_t^T dx with H_t = 2 Q_s + sum_ij sigma J^T J and
+// g_t = 2 Q_s (x^k_t - xref_t) + sum_ij sigma J^T e (pose block), input cost
+// 1/2 du^T (2 Q_u) du + (2 Q_u u^k_t)^T du, dynamics dx_{t+1} = A dx_t +
+// B du_t + f_t with the defect f_t = A x^k_t + B u^k_t + c - x^k_{t+1} formed
+// in FP64. This is the same QP as in absolute coordinates, without the
+// cancellation of sigma J^T J q^k against the positions of the scene.
+// The obstacle-free solve (initial iterate) uses the base point 0.
+//
+// Reverse mode (ADJ): the same sweep solves the adjoint LQ of one forward
+// trajectory QP. With xbar_t, ubar_t the cotangents of its solution (x, u),
+// the vector abar = Hs^{-1} (ubar + sum_t M_t^T xbar_t) of the condensed
+// problem (Hs its input Hessian, M_t the input-to-state map) is the minimiser
+// of the same LQ with h_t = -xbar_t, an input term -ubar_t, c = 0 and
+// x_0 = 0, and its state trajectory w_t = M_t abar is what the stage
+// adjoints need (Hbar_t = -(w_t x_t^T + x_t w_t^T) / 2, hbar_t = -w_t). The
+// cotangent of x_0 is sum_t (A^T)^t (xbar_t - H_t w_t), accumulated by a
+// Horner sweep after the rollout.
 // ------------------------------------------------------------------------
 
 constexpr int kTrajThreads = 256;
 
-// Dynamic LDS floats of the trajectory kernel for padded sizes NS, NU.
-__host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc)
+// Dynamic LDS floats of the trajectory kernel for padded sizes NS, NU
+// (reverse mode adds the w trajectory).
+__host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bool adj)
 {
-    return N * nc + N * NS + N * NU * (NS + 1);
+    return N * nc + N * NS + N * NU * (NS + 1) + N * NU + N * NS + (adj ? (N + 1) * NS : 0);
 }
 
 // Trajectory QP of one scenario per workgroup. State/input sizes are padded
 // to the compile-time NS >= n_s, NU >= n_u with zero dynamics rows/columns
 // and an identity input-cost block, so every small product unrolls.
-template <int NS, int NU>
-__global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, int obstacle_free)
+template <int NS, int NU, bool ADJ>
+__global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, int obstacle_free, float* hq_save,
+                                                                  TrajAdjoint TA)
 {
     constexpr int NSU = NS + 1;
-    __shared__ float A[NS * NS], B[NS * NU], c[NS], Q2[NS * NS], R2[NU * NU];
-    __shared__ int hmap[NS * NS], gmap[NS];
+    __shared__ float A[NS * NS], B[NS * NU], Q2[NS * NS], R2[NU * NU];
+    __shared__ int hmap[NS * NS], gmap[NS], pmap[NS];
     __shared__ float Pm[NS * NS], pv[NS], PA[NS * NS], PB[NS * NU], wv[NS];
     __shared__ float Quu[NU * NU], Qux[NU * NS], qu[NU], Qxx[NS * NS], qx[NS];
     __shared__ float xbuf[2][NS];
     extern __shared__ float dyn[];
     const int s = blockIdx.x;
-    if (!obstacle_free && P.done[s]) return;
+    if (!ADJ && !obstacle_free && P.done[s]) return;
     const int tid = threadIdx.x;
     const int ns = P.n_s, nu = P.n_u, N = P.N, nq = P.nq, nc = P.nc;
+    // deviation coordinates about the current iterate (else base point 0)
+    const bool dev = !ADJ && !obstacle_free;
     float* Hq = dyn;                       // [N][nc] reduced contributions
-    float* qr = Hq + N * nc;               // [N][NS] -2 Q_s xref_t, t = 1..N
+    float* qr = Hq + N * nc;               // [N][NS] stage gradients g_t (reverse: -xbar_t), t = 1..N
     float* Kall = qr + N * NS;             // [N][NU][NS+1] gains [K | k]
+    float* rin = Kall + N * NU * NSU;      // [N][NU] input gradients 2 Q_u u^k_t (reverse: -ubar_t)
+    float* off = rin + N * NU;             // [N][NS] dynamics offsets f_t (c when the base is 0)
+    float* wl = off + N * NS;              // reverse: [N+1][NS] w_t
 
     // 0. padded model and cost, pose-coordinate maps
     for (int e = tid; e < NS * NS; e += kTrajThreads) {
@@ -890,43 +778,113 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
         R2[e] = (i < nu && j < nu) ? 2.f * P.Q_u[i * nu + j] : (i == j ? 1.f : 0.f);
     }
     if (tid < NS) {
-        c[tid] = tid < ns ? P.c_dyn[tid] : 0.f;
-        int m = -1;
+        int m = -1, pa = -1;
         for (int a = 0; a < nq; ++a) {
             const int qa = a < P.dim ? P.pos_idx[a] : P.att_idx[a - P.dim];
-            if (qa == tid && tid < ns) m = nq * (nq + 1) / 2 + a;
+            if (qa == tid && tid < ns) {
+                m = nq * (nq + 1) / 2 + a;
+                pa = a;
+            }
         }
         gmap[tid] = m;
+        pmap[tid] = pa;
     }
+    __syncthreads();
     // 1. per-step sums of the pair contributions (fixed order over this
-    //    scenario's workgroups) and the reference gradients
+    //    scenario's workgroups) and the reference gradients; in reverse mode
+    //    the stage sums saved by the forward pass, the state cotangents
+    //    (pose coordinates summed over this scenario's workgroups, plus the
+    //    gradient of the tracking cost at the last iterate) and the input
+    //    cotangents
     const float* xref = P.x_ref + (size_t)s * (N + 1) * ns;
-    if (!obstacle_free) {
+    if (ADJ) {
+        for (int e = tid; e < N * nc; e += kTrajThreads)
+            Hq[e] = TA.hq ? TA.hq[(size_t)s * N * nc + e] : 0.f;
         const int2 r = P.scen_wg[s];
-        for (int e = tid; e < N * nc; e += kTrajThreads) {
-            const int cc = e / N, t = e % N;
-            const float* src = P.contrib + (size_t)cc * 64 + t;
+        for (int e = tid; e < N * NS; e += kTrajThreads) {
+            const int t = e / NS, i = e % NS;
             float acc = 0.f;
-            for (int w = r.x; w < r.y; ++w) acc += src[(size_t)w * nc * 64];
-            Hq[t * nc + cc] = acc;
+            if (i < ns) {
+                if (TA.xK) {
+                    const float* xt = TA.xK + ((size_t)s * (N + 1) + t + 1) * ns;
+                    for (int j = 0; j < ns; ++j) acc += 2.f * P.Q_s[i * ns + j] * (xt[j] - xref[(t + 1) * ns + j]);
+                }
+                const int a = pmap[i];
+                if (TA.qpart && a >= 0)
+                    for (int w = r.x; w < r.y; ++w) acc += TA.qpart[((size_t)w * nq + a) * 64 + t];
+            }
+            qr[e] = -acc;
+        }
+        for (int e = tid; e < N * NU; e += kTrajThreads) {
+            const int t = e / NU, j = e % NU;
+            float acc = 0.f;
+            if (TA.uK && j < nu) {
+                const float* ut = TA.uK + ((size_t)s * N + t) * nu;
+                for (int m = 0; m < nu; ++m) acc += 2.f * P.Q_u[j * nu + m] * ut[m];
+            }
+            rin[e] = -acc;
         }
     } else {
-        for (int e = tid; e < N * nc; e += kTrajThreads) Hq[e] = 0.f;
+        if (!obstacle_free) {
+            const int2 r = P.scen_wg[s];
+            for (int e = tid; e < N * nc; e += kTrajThreads) {
+                const int cc = e / N, t = e % N;
+                const float* src = P.contrib + (size_t)cc * 64 + t;
+                float acc = 0.f;
+                for (int w = r.x; w < r.y; ++w) acc += src[(size_t)w * nc * 64];
+                Hq[t * nc + cc] = acc;
+                if (hq_save) hq_save[((size_t)s * N + t) * nc + cc] = acc;
+            }
+        } else {
+            for (int e = tid; e < N * nc; e += kTrajThreads) Hq[e] = 0.f;
+        }
+        const float* xk = P.x + (size_t)s * (N + 1) * ns;
+        const float* uk = P.u + (size_t)s * N * nu;
+        for (int e = tid; e < N * NS; e += kTrajThreads) {
+            const int t = e / NS, i = e % NS;
+            float acc = 0.f;
+            if (i < ns)
+                for (int j = 0; j < ns; ++j)
+                    acc += P.Q_s[i * ns + j] * ((dev ? xk[(t + 1) * ns + j] : 0.f) - xref[(t + 1) * ns + j]);
+            qr[e] = 2.f * acc;
+        }
+        for (int e = tid; e < N * NU; e += kTrajThreads) {
+            const int t = e / NU, j = e % NU;
+            float acc = 0.f;
+            if (dev && j < nu)
+                for (int m = 0; m < nu; ++m) acc += 2.f * P.Q_u[j * nu + m] * uk[t * nu + m];
+            rin[e] = acc;
+        }
+        for (int e = tid; e < N * NS; e += kTrajThreads) {
+            const int t = e / NS, i = e % NS;
+            float v = 0.f;
+            if (i < ns) {
+                if (dev) {
+                    double acc = (double)P.c_dyn[i] - (double)xk[(t + 1) * ns + i];
+                    for (int j = 0; j < ns; ++j) acc += (double)P.A_dyn[i * ns + j] * (double)xk[t * ns + j];
+                    for (int j = 0; j < nu; ++j) acc += (double)P.B_dyn[i * nu + j] * (double)uk[t * nu + j];
+                    v = (float)acc;
+                } else {
+                    v = P.c_dyn[i];
+                }
+            }
+            off[e] = v;
+        }
     }
-    for (int e = tid; e < N * NS; e += kTrajThreads) {
-        const int t = e / NS, i = e % NS;
-        float acc = 0.f;
-        if (i < ns)
-            for (int j = 0; j < ns; ++j) acc += P.Q_s[i * ns + j] * xref[(t + 1) * ns + j];
-        qr[e] = -2.f * acc;
-    }
+    if (ADJ)
+        for (int e = tid; e < N * NS; e += kTrajThreads) off[e] = 0.f;
     __syncthreads();
+    // the linear stage terms of the forward pass carry the pose-block
+    // gradients of the pair contributions; the adjoint LQ has none
+    auto lin = [&](int t, int i) -> float {
+        return qr[t * NS + i] + ((!ADJ && gmap[i] >= 0) ? Hq[t * nc + gmap[i]] : 0.f);
+    };
     // 2. backward Riccati sweep, V_t(x) = 1/2 x^T P x + p^T x, P_N = H_N
     for (int e = tid; e < NS * NS; e += kTrajThreads) Pm[e] = Q2[e] + (hmap[e] >= 0 ? Hq[(N - 1) * nc + hmap[e]] : 0.f);
-    if (tid < NS) pv[tid] = qr[(N - 1) * NS + tid] + (gmap[tid] >= 0 ? Hq[(N - 1) * nc + gmap[tid]] : 0.f);
+    if (tid < NS) pv[tid] = lin(N - 1, tid);
     __syncthreads();
     for (int t = N - 1; t >= 0; --t) {
-        // a. PA = P A, PB = P B, w = P c + p
+        // a. PA = P A, PB = P B, w = P f_t + p
         for (int e = tid; e < NS * NS + NS * NU + NS; e += kTrajThreads) {
             if (e < NS * NS) {
                 const int i = e / NS, j = e % NS;
@@ -944,13 +902,13 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
                 const int i = e - NS * NS - NS * NU;
                 float acc = pv[i];
 #pragma unroll
-                for (int k2 = 0; k2 < NS; ++k2) acc += Pm[i * NS + k2] * c[k2];
+                for (int k2 = 0; k2 < NS; ++k2) acc += Pm[i * NS + k2] * off[t * NS + k2];
                 wv[i] = acc;
             }
         }
         __syncthreads();
-        // b. Quu = 2Q_u + B^T P B, Qux = B^T P A, qu = B^T w and, for t >= 1,
-        //    the stage-t terms Qxx = H_t + A^T P A, qx = h_t + A^T w
+        // b. Quu = 2Q_u + B^T P B, Qux = B^T P A, qu = B^T w + input gradient and,
+        //    for t >= 1, the stage-t terms Qxx = H_t + A^T P A, qx = h_t + A^T w
         constexpr int NB = NU * NU + NU * NS + NU;
         const int nx = t >= 1 ? NS * NS + NS : 0;
         for (int e = tid; e < NB + nx; e += kTrajThreads) {
@@ -968,7 +926,7 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
                 Qux[f] = acc;
             } else if (e < NB) {
                 const int i = e - NU * NU - NU * NS;
-                float acc = 0.f;
+                float acc = rin[t * NU + i];
 #pragma unroll
                 for (int k2 = 0; k2 < NS; ++k2) acc += B[k2 * NU + i] * wv[k2];
                 qu[i] = acc;
@@ -980,7 +938,7 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
                 Qxx[f] = acc;
             } else {
                 const int i = e - NB - NS * NS;
-                float acc = qr[(t - 1) * NS + i] + (gmap[i] >= 0 ? Hq[(t - 1) * nc + gmap[i]] : 0.f);
+                float acc = lin(t - 1, i);
 #pragma unroll
                 for (int k2 = 0; k2 < NS; ++k2) acc += A[k2 * NS + i] * wv[k2];
                 qx[i] = acc;
@@ -1054,8 +1012,9 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
         __syncthreads();
     }
     __syncthreads();
-    // 3. forward rollout x_{t+1} = A x + B (K x + k) + c; thread i owns x_i
-    //    (rows of A and B in registers), threads NS..NS+NU-1 write u
+    // 3. forward rollout dx_{t+1} = A dx + B (K dx + k) + f_t; thread i owns
+    //    dx_i (rows of A and B in registers) and writes x^k + dx, threads
+    //    NS..NS+NU-1 write u^k + du. The reverse mode rolls w out from w_0 = 0.
     float* xo = P.x + (size_t)s * (N + 1) * ns;
     float* uo = P.u + (size_t)s * N * nu;
     float Ar[NS], Br[NU];
@@ -1064,11 +1023,15 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
     for (int k2 = 0; k2 < NS; ++k2) Ar[k2] = A[row * NS + k2];
 #pragma unroll
     for (int j = 0; j < NU; ++j) Br[j] = B[row * NU + j];
-    const float cr = c[row];
     if (tid < NS) {
-        const float v = tid < ns ? P.x0[(size_t)s * ns + tid] : 0.f;
+        float v = 0.f;
+        if (!ADJ && tid < ns) {
+            const float x0v = P.x0[(size_t)s * ns + tid];
+            v = dev ? x0v - xo[tid] : x0v;
+            xo[tid] = x0v;
+        }
         xbuf[0][tid] = v;
-        if (tid < ns) xo[tid] = v;
+        if (ADJ) wl[tid] = 0.f;
     }
     __syncthreads();
     for (int t = 0; t < N; ++t) {
@@ -1087,23 +1050,60 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
                 uu[j] = v;
             }
             if (tid < NS) {
-                float acc = cr;
+                float acc = off[t * NS + tid];
 #pragma unroll
                 for (int k2 = 0; k2 < NS; ++k2) acc += Ar[k2] * xr[k2];
 #pragma unroll
                 for (int j = 0; j < NU; ++j) acc += Br[j] * uu[j];
                 xbuf[(t + 1) & 1][tid] = acc;
-                if (tid < ns) xo[(t + 1) * ns + tid] = acc;
-            } else {
+                if (ADJ) {
+                    wl[(t + 1) * NS + tid] = acc;
+                    if (tid < ns) TA.w[((size_t)s * N + t) * ns + tid] = acc;
+                } else if (tid < ns) {
+                    float* xp = xo + (t + 1) * ns + tid;
+                    *xp = dev ? *xp + acc : acc;
+                }
+            } else if (!ADJ) {
                 const int j = tid - NS;
                 float v = 0.f;
 #pragma unroll
                 for (int q = 0; q < NU; ++q) v = q == j ? uu[q] : v;
-                if (j < nu) uo[t * nu + j] = v;
+                if (j < nu) {
+                    float* up = uo + t * nu + j;
+                    *up = dev ? *up + v : v;
+                }
             }
         }
         __syncthreads();
     }
+    if (!ADJ) return;
+    // 4. reverse mode: zbar_t = xbar_t - H_t w_t (stored over qr), then
+    //    x0bar = sum_t (A^T)^t zbar_t by a Horner sweep from t = N down to 1
+    for (int e = tid; e < N * NS; e += kTrajThreads) {
+        const int t = e / NS, i = e % NS;
+        const float* wt = wl + (t + 1) * NS;
+        float acc = -qr[e];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int m = hmap[i * NS + j];
+            acc -= (Q2[i * NS + j] + (m >= 0 ? Hq[t * nc + m] : 0.f)) * wt[j];
+        }
+        qr[e] = acc;
+    }
+    if (tid < NS) xbuf[0][tid] = 0.f;
+    __syncthreads();
+    for (int t = N - 1; t >= 0; --t) {
+        if (tid < NS) xbuf[1][tid] = xbuf[0][tid] + qr[t * NS + tid];
+        __syncthreads();
+        if (tid < NS) {
+            float acc = 0.f;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) acc += A[j * NS + tid] * xbuf[1][j];
+            xbuf[0][tid] = acc;
+        }
+        __syncthreads();
+    }
+    if (tid < ns) TA.gx0[(size_t)s * ns + tid] += (double)xbuf[0][tid];
 }
 
 // ------------------------------------------------------------------------
@@ -1548,6 +1548,12 @@ __global__ void fill_kernel(float* p, long long n, float v)
         p[i] = v;
 }
 
+__global__ void set_face_offsets_kernel(float4* faces, const double* d64, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) faces[i].w = (float)d64[i];
+}
+
 __global__ void fill_int_kernel(int* p, long long n, int v)
 {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
@@ -1649,20 +1655,32 @@ hipError_t launch_mult_phase(const DevProblem& P, int W, int grid, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t st)
+template <bool ADJ>
+static hipError_t launch_traj(const DevProblem& P, int obstacle_free, float* hq_save, const TrajAdjoint& TA,
+                              hipStream_t st)
 {
     dim3 g(P.n_scen), b(kTrajThreads);
     if (P.n_s <= 4 && P.n_u <= 2) {
-        hipLaunchKernelGGL((traj_phase_kernel<4, 2>), g, b, sizeof(float) * traj_dyn_floats(P.N, 4, 2, P.nc), st, P,
-                           obstacle_free);
+        hipLaunchKernelGGL((traj_phase_kernel<4, 2, ADJ>), g, b,
+                           sizeof(float) * traj_dyn_floats(P.N, 4, 2, P.nc, ADJ), st, P, obstacle_free, hq_save, TA);
     } else if (P.n_s <= 12 && P.n_u <= 4) {
-        hipLaunchKernelGGL((traj_phase_kernel<12, 4>), g, b, sizeof(float) * traj_dyn_floats(P.N, 12, 4, P.nc), st,
-                           P, obstacle_free);
+        hipLaunchKernelGGL((traj_phase_kernel<12, 4, ADJ>), g, b,
+                           sizeof(float) * traj_dyn_floats(P.N, 12, 4, P.nc, ADJ), st, P, obstacle_free, hq_save, TA);
     } else {
-        hipLaunchKernelGGL((traj_phase_kernel<16, 8>), g, b, sizeof(float) * traj_dyn_floats(P.N, 16, 8, P.nc), st,
-                           P, obstacle_free);
+        hipLaunchKernelGGL((traj_phase_kernel<16, 8, ADJ>), g, b,
+                           sizeof(float) * traj_dyn_floats(P.N, 16, 8, P.nc, ADJ), st, P, obstacle_free, hq_save, TA);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t st, float* hq_save)
+{
+    return launch_traj<false>(P, obstacle_free, hq_save, TrajAdjoint{}, st);
+}
+
+hipError_t launch_traj_adjoint(const DevProblem& P, const TrajAdjoint& TA, hipStream_t st)
+{
+    return launch_traj<true>(P, 0, nullptr, TA, st);
 }
 
 hipError_t launch_residual(const DevProblem& P, hipStream_t st)
@@ -1688,6 +1706,13 @@ hipError_t launch_fill(float* p, long long n, float v, hipStream_t st)
     long long g = (n + 255) / 256;
     if (g > 4096) g = 4096;
     hipLaunchKernelGGL(fill_kernel, dim3((unsigned)g), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_face_offsets(float4* faces, const double* d64, int n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(set_face_offsets_kernel, dim3((n + 255) / 256), dim3(256), 0, st, faces, d64, n);
     return hipGetLastError();
 }
 
