@@ -336,12 +336,13 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
     constexpr int NATT = Pose<DIM>::NATT;
     constexpr int NQ = Pose<DIM>::NQ;
     constexpr int NC = Contrib<DIM>::NC;
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     const int W = blockDim.x >> 6;
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    float* red = lds;                       // [W][NC][64]
-    float* red_rd = lds + W * NC * 64;      // [W]
+    float4* faces = reinterpret_cast<float4*>(lds);   // [W][MR + MO] faces of each wave's block
+    float* red = lds + 4 * W * (MR + MO);             // [W][NC][64]
+    float* red_rd = red + W * NC * 64;                // [W]
     int* red_un = reinterpret_cast<int*>(red_rd + W);
     const int N = P.N;
     const float eps = P.eps_prox;
@@ -351,6 +352,17 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
         const int s = uniform(item.x);
         if (P.done[s]) continue;                 // uniform over the workgroup
         const int b = uniform(item.y + wave);
+        // the block's faces into this wave's LDS slot: every solver pass reads
+        // them, and from LDS they are broadcast reads instead of HBM round trips
+        float4* fl = faces + wave * (MR + MO);
+        if (b < item.z) {
+            const int4 bk = P.blocks[b];
+            const int f0 = P.part_face_ptr[bk.y], nf = P.part_face_ptr[bk.y + 1] - f0;
+            const int g0 = P.obs_face_ptr[bk.z], ng = P.obs_face_ptr[bk.z + 1] - g0;
+            if (lane < nf) fl[lane] = P.part_faces[f0 + lane];
+            else if (lane >= MR && lane - MR < ng) fl[lane] = P.obs_faces[g0 + lane - MR];
+        }
+        __syncthreads();
         float con[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) con[c] = 0.f;
@@ -365,8 +377,8 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
             PairRows<DIM, MR, MO> pr;
             pr.nr = uniform(P.part_face_ptr[part + 1] - fr0);
             pr.no = uniform(P.obs_face_ptr[obs + 1] - fo0);
-            pr.rf = P.part_faces + fr0;
-            pr.of = P.obs_faces + fo0;
+            pr.rf = fl;
+            pr.of = fl + MR;
             const int yoff = uniform(P.block_yoff[b]);
             const float* xs = P.x + ((size_t)s * (N + 1) + t) * P.n_s;
             Pose<DIM> ps;
@@ -716,11 +728,35 @@ __global__ void __launch_bounds__(64) residual_kernel(DevProblem P)
 
 constexpr int kTrajThreads = 256;
 
+// Floats of the gains region, which first holds the staged trajectory
+// (x and x_ref over t = 0..N, u over t = 0..N-1, padded to NS / NU).
+__host__ __device__ inline int traj_gain_floats(int N, int NS, int NU)
+{
+    const int gains = N * NU * (NS + 1), stage = 2 * (N + 1) * NS + N * NU;
+    return gains > stage ? gains : stage;
+}
+
 // Dynamic LDS floats of the trajectory kernel for padded sizes NS, NU
 // (reverse mode adds the w trajectory).
 __host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bool adj)
 {
-    return N * nc + N * NS + N * NU * (NS + 1) + N * NU + N * NS + (adj ? (N + 1) * NS : 0);
+    return N * nc + N * NS + traj_gain_floats(N, NS, NU) + N * NU + N * NS + (adj ? (N + 1) * NS : 0);
+}
+
+// Fixed-order sum of src[w * stride], w = w0..w1-1, with eight independent
+// partial sums (w - w0 mod 8) so that many loads are in flight at once.
+__device__ __forceinline__ float strided_sum(const float* src, size_t stride, int w0, int w1)
+{
+    float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int w = w0;
+    for (; w + 8 <= w1; w += 8) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] += src[(size_t)(w + q) * stride];
+    }
+#pragma unroll
+    for (int q = 0; q < 7; ++q)
+        if (w + q < w1) a[q] += src[(size_t)(w + q) * stride];
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
 // Trajectory QP of one scenario per workgroup. State/input sizes are padded
@@ -731,7 +767,7 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
                                                                   TrajAdjoint TA)
 {
     constexpr int NSU = NS + 1;
-    __shared__ float A[NS * NS], B[NS * NU], Q2[NS * NS], R2[NU * NU];
+    __shared__ float A[NS * NS], B[NS * NU], Q2[NS * NS], R2[NU * NU], cdyn[NS];
     __shared__ int hmap[NS * NS], gmap[NS], pmap[NS];
     __shared__ float Pm[NS * NS], pv[NS], PA[NS * NS], PB[NS * NU], wv[NS];
     __shared__ float Quu[NU * NU], Qux[NU * NS], qu[NU], Qxx[NS * NS], qx[NS];
@@ -746,7 +782,10 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
     float* Hq = dyn;                       // [N][nc] reduced contributions
     float* qr = Hq + N * nc;               // [N][NS] stage gradients g_t (reverse: -xbar_t), t = 1..N
     float* Kall = qr + N * NS;             // [N][NU][NS+1] gains [K | k]
-    float* rin = Kall + N * NU * NSU;      // [N][NU] input gradients 2 Q_u u^k_t (reverse: -ubar_t)
+    float* sx = Kall;                      // staged before the sweep: [N+1][NS] x (reverse: x^K)
+    float* sxr = sx + (N + 1) * NS;        //   [N+1][NS] x_ref
+    float* su = sxr + (N + 1) * NS;        //   [N][NU] u (reverse: u^K)
+    float* rin = Kall + traj_gain_floats(N, NS, NU);   // [N][NU] input gradients 2 Q_u u^k_t (reverse: -ubar_t)
     float* off = rin + N * NU;             // [N][NS] dynamics offsets f_t (c when the base is 0)
     float* wl = off + N * NS;              // reverse: [N+1][NS] w_t
 
@@ -777,7 +816,23 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
         const int i = e / NU, j = e % NU;
         R2[e] = (i < nu && j < nu) ? 2.f * P.Q_u[i * nu + j] : (i == j ? 1.f : 0.f);
     }
+    // the trajectory the stage terms are formed about, into LDS
+    {
+        const float* xsrc = ADJ ? TA.xK : (dev ? P.x : nullptr);
+        const float* usrc = ADJ ? TA.uK : (dev ? P.u : nullptr);
+        const float* xrs = P.x_ref + (size_t)s * (N + 1) * ns;
+        for (int e = tid; e < (N + 1) * NS; e += kTrajThreads) {
+            const int t = e / NS, i = e % NS;
+            sx[e] = (xsrc && i < ns) ? xsrc[((size_t)s * (N + 1) + t) * ns + i] : 0.f;
+            sxr[e] = i < ns ? xrs[t * ns + i] : 0.f;
+        }
+        for (int e = tid; e < N * NU; e += kTrajThreads) {
+            const int t = e / NU, j = e % NU;
+            su[e] = (usrc && j < nu) ? usrc[((size_t)s * N + t) * nu + j] : 0.f;
+        }
+    }
     if (tid < NS) {
+        cdyn[tid] = tid < ns ? P.c_dyn[tid] : 0.f;
         int m = -1, pa = -1;
         for (int a = 0; a < nq; ++a) {
             const int qa = a < P.dim ? P.pos_idx[a] : P.att_idx[a - P.dim];
@@ -791,88 +846,75 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
     }
     __syncthreads();
     // 1. per-step sums of the pair contributions (fixed order over this
-    //    scenario's workgroups) and the reference gradients; in reverse mode
-    //    the stage sums saved by the forward pass, the state cotangents
-    //    (pose coordinates summed over this scenario's workgroups, plus the
-    //    gradient of the tracking cost at the last iterate) and the input
-    //    cotangents
-    const float* xref = P.x_ref + (size_t)s * (N + 1) * ns;
+    //    scenario's workgroups) and the stage and input gradients about the
+    //    staged trajectory; in reverse mode the stage sums saved by the
+    //    forward pass, the state cotangents (pose coordinates summed over this
+    //    scenario's workgroups, plus the gradient of the tracking cost at the
+    //    last iterate) and the input cotangents
+    const int2 wr = P.scen_wg[s];
     if (ADJ) {
         for (int e = tid; e < N * nc; e += kTrajThreads)
             Hq[e] = TA.hq ? TA.hq[(size_t)s * N * nc + e] : 0.f;
-        const int2 r = P.scen_wg[s];
         for (int e = tid; e < N * NS; e += kTrajThreads) {
             const int t = e / NS, i = e % NS;
             float acc = 0.f;
-            if (i < ns) {
-                if (TA.xK) {
-                    const float* xt = TA.xK + ((size_t)s * (N + 1) + t + 1) * ns;
-                    for (int j = 0; j < ns; ++j) acc += 2.f * P.Q_s[i * ns + j] * (xt[j] - xref[(t + 1) * ns + j]);
-                }
-                const int a = pmap[i];
-                if (TA.qpart && a >= 0)
-                    for (int w = r.x; w < r.y; ++w) acc += TA.qpart[((size_t)w * nq + a) * 64 + t];
-            }
+            if (TA.xK)
+#pragma unroll
+                for (int j = 0; j < NS; ++j) acc += Q2[i * NS + j] * (sx[(t + 1) * NS + j] - sxr[(t + 1) * NS + j]);
+            const int a = pmap[i];
+            if (TA.qpart && a >= 0) acc += strided_sum(TA.qpart + (size_t)a * 64 + t, (size_t)nq * 64, wr.x, wr.y);
             qr[e] = -acc;
         }
         for (int e = tid; e < N * NU; e += kTrajThreads) {
             const int t = e / NU, j = e % NU;
             float acc = 0.f;
-            if (TA.uK && j < nu) {
-                const float* ut = TA.uK + ((size_t)s * N + t) * nu;
-                for (int m = 0; m < nu; ++m) acc += 2.f * P.Q_u[j * nu + m] * ut[m];
-            }
+            if (j < nu)
+#pragma unroll
+                for (int m = 0; m < NU; ++m) acc += R2[j * NU + m] * su[t * NU + m];
             rin[e] = -acc;
         }
+        for (int e = tid; e < N * NS; e += kTrajThreads) off[e] = 0.f;
     } else {
         if (!obstacle_free) {
-            const int2 r = P.scen_wg[s];
             for (int e = tid; e < N * nc; e += kTrajThreads) {
                 const int cc = e / N, t = e % N;
-                const float* src = P.contrib + (size_t)cc * 64 + t;
-                float acc = 0.f;
-                for (int w = r.x; w < r.y; ++w) acc += src[(size_t)w * nc * 64];
+                const float acc = strided_sum(P.contrib + (size_t)cc * 64 + t, (size_t)nc * 64, wr.x, wr.y);
                 Hq[t * nc + cc] = acc;
                 if (hq_save) hq_save[((size_t)s * N + t) * nc + cc] = acc;
             }
         } else {
             for (int e = tid; e < N * nc; e += kTrajThreads) Hq[e] = 0.f;
         }
-        const float* xk = P.x + (size_t)s * (N + 1) * ns;
-        const float* uk = P.u + (size_t)s * N * nu;
         for (int e = tid; e < N * NS; e += kTrajThreads) {
             const int t = e / NS, i = e % NS;
             float acc = 0.f;
-            if (i < ns)
-                for (int j = 0; j < ns; ++j)
-                    acc += P.Q_s[i * ns + j] * ((dev ? xk[(t + 1) * ns + j] : 0.f) - xref[(t + 1) * ns + j]);
-            qr[e] = 2.f * acc;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) acc += Q2[i * NS + j] * (sx[(t + 1) * NS + j] - sxr[(t + 1) * NS + j]);
+            qr[e] = acc;
         }
         for (int e = tid; e < N * NU; e += kTrajThreads) {
             const int t = e / NU, j = e % NU;
             float acc = 0.f;
-            if (dev && j < nu)
-                for (int m = 0; m < nu; ++m) acc += 2.f * P.Q_u[j * nu + m] * uk[t * nu + m];
+            if (j < nu)
+#pragma unroll
+                for (int m = 0; m < NU; ++m) acc += R2[j * NU + m] * su[t * NU + m];
             rin[e] = acc;
         }
+        // dynamics offsets: the defects of the staged trajectory, in FP64
+        // (zero-padded rows and columns contribute nothing)
         for (int e = tid; e < N * NS; e += kTrajThreads) {
             const int t = e / NS, i = e % NS;
-            float v = 0.f;
-            if (i < ns) {
-                if (dev) {
-                    double acc = (double)P.c_dyn[i] - (double)xk[(t + 1) * ns + i];
-                    for (int j = 0; j < ns; ++j) acc += (double)P.A_dyn[i * ns + j] * (double)xk[t * ns + j];
-                    for (int j = 0; j < nu; ++j) acc += (double)P.B_dyn[i * nu + j] * (double)uk[t * nu + j];
-                    v = (float)acc;
-                } else {
-                    v = P.c_dyn[i];
-                }
+            double acc = (double)cdyn[i];
+            if (dev) {
+                acc -= (double)sx[(t + 1) * NS + i];
+#pragma unroll
+                for (int j = 0; j < NS; ++j) acc += (double)A[i * NS + j] * (double)sx[t * NS + j];
+#pragma unroll
+                for (int j = 0; j < NU; ++j) acc += (double)B[i * NU + j] * (double)su[t * NU + j];
             }
-            off[e] = v;
+            off[e] = (float)acc;
         }
     }
-    if (ADJ)
-        for (int e = tid; e < N * NS; e += kTrajThreads) off[e] = 0.f;
     __syncthreads();
     // the linear stage terms of the forward pass carry the pose-block
     // gradients of the pair contributions; the adjoint LQ has none
@@ -1628,7 +1670,8 @@ hipError_t launch_pair_phase(const DevProblem& P, int W, int grid, hipStream_t s
 {
     const int v = pick_variant(P);
     const int nc = P.nc;
-    const size_t lds = (size_t)W * nc * 64 * sizeof(float) + 2 * W * sizeof(float);
+    const size_t lds = (size_t)W * (kVariants[v].mr + kVariants[v].mo) * sizeof(float4) +
+                       (size_t)W * nc * 64 * sizeof(float) + 2 * W * sizeof(float);
     dim3 blk(64 * W), grd(grid);
     switch (v) {
     case 0: hipLaunchKernelGGL((pair_phase_kernel<2, 4, 16>), grd, blk, lds, st, P); break;
