@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2406_07048_amd/csrc/cadmm_kernels.hip", "paper_2406_07048_amd/csrc/cadmm_device.h",
+                  "paper_2406_07048_amd/csrc/cadmm_internal.h")
 
 WORKLOADS = {
     "c2": dict(desc="2D cab+trailer (2 parts x 4 faces), 40 hull obstacles (3-10 faces), N=50, "
@@ -45,6 +47,34 @@ def pair_bytes(prob, n_wg, nc):
     sc, part, obs, nrow, yoff, tot = workloads.block_layout(prob)
     N, dim = prob["N"], prob["dim"]
     return 4.0 * (2 * tot + len(sc) * N * (1 + dim)) + 4.0 * n_wg * nc * 64
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    profiles/<name>_hbm_traffic.txt (FETCH_SIZE and WRITE_SIZE per dispatch,
+    scaled by what the same counters read for a plain copy of known size).
+    None when the summary is missing or was taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{name}_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def time_solves(h, iters, steps, torch):
@@ -90,6 +120,13 @@ def batched_vs_plain(cadmm, torch, steps=2, iters=50):
     tb = time_solves(hb, iters, steps, torch)
     _, nb, npairs, _ = cadmm.cadmm_workspace_size(prob)
     wb = hb.launch_config()
+    # HBM roofline of the batched pair phase (the size where HBM, not launch
+    # latency, bounds it), from HIP events on the handle's stream
+    hb.reset()
+    ph = hb.phase_times(10)
+    nq = prob["dim"] + (1 if prob["dim"] == 2 else 3)
+    bytes_launch = pair_bytes(prob, wb[1], nq * (nq + 1) // 2 + nq)
+    gbs = bytes_launch / (ph[0] * 1e-3) / 1e9
     hb.close()
     plain = [cadmm.Handle(workloads.select_scenarios(prob, [s])) for s in range(S)]
     for h in plain:
@@ -110,7 +147,40 @@ def batched_vs_plain(cadmm, torch, steps=2, iters=50):
                          f"per iteration, {iters} iterations",
                 batched_pair_solves_per_s=solves / tb, plain_pair_solves_per_s=solves / tp,
                 batched_ms_per_solve=tb * 1e3, plain_ms_per_solve=tp * 1e3, speedup=tp / tb,
-                batched_waves_per_group=wb[0])
+                batched_blocks_per_group=wb[0], batched_lanes_per_pair=wb[2],
+                pair_phase_ms=ph[0], pair_phase_solves_per_s=npairs / (ph[0] * 1e-3),
+                roofline={"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "pair_phase_kernel",
+                          "bytes_per_launch": bytes_launch})
+
+
+def stream_batch(cadmm, torch, n_pairs=1 << 22, reps=5):
+    """The stateless pair-QP entry point streamed over 2^22 pairs of the
+    batched 2D shape (about 1.4 GB, beyond the 256 MB Infinity Cache): the
+    size at which HBM, not latency, bounds the pair solve. HIP events on the
+    stream the kernel runs on (torch's current stream)."""
+    rp, K, kap, yh, bh = workloads.pair_batch_c4_shape(n_pairs)
+    args = [torch.from_numpy(a).to("cuda") for a in (rp, K, kap, yh, bh)]
+    y, r, status = cadmm.pair_qp_batch(*args, 0.1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        cadmm.pair_qp_batch(*args, 0.1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    rows = int(rp[-1])
+    # read K, kappa, yhat, write y (per row); read bhat, row_ptr, write r, status (per pair)
+    bytes_launch = 4.0 * rows * (3 + 1 + 1 + 1) + 4.0 * n_pairs * (3 + 1 + 3 + 1)
+    gbs = bytes_launch / (ms * 1e-3) / 1e9
+    st = status.cpu().numpy()
+    return dict(workload=f"{n_pairs} stateless pair QPs of the batched 2D shape ({rows} rows, 5-16 per pair)",
+                ms_per_launch=ms, pair_solves_per_s=n_pairs / (ms * 1e-3),
+                sweeps_mean=float(st[st >= 0].mean()), budget_hits=int((st < 0).sum()),
+                roofline={"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "pair_qp_batch_kernel",
+                          "bytes_per_launch": bytes_launch})
 
 
 def differentiation(cadmm, torch, steps=3, iters=100, every=10):
@@ -160,10 +230,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--source-hash", action="store_true", help="print the hash of the kernel sources and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device-to-device copy of MIB MiB (the reference for the HBM "
                          "byte counters) and exit")
     args = ap.parse_args()
+    if args.source_hash:
+        print(kernel_source_hash())
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
@@ -184,11 +259,12 @@ def main():
     prob = workloads.make(args.workload)
     iters = wl["iters"]
     h = cadmm.Handle(prob)
-    W, n_wg = h.launch_config()
+    W, n_wg, G = h.launch_config()
     _, nb, npairs, yf = cadmm.cadmm_workspace_size(prob)
     for _ in range(args.warmup):
         h.reset(); h.iterate(iters); h.scales()
-    print(f"[bench] {args.workload}: warmup done, W={W} workgroups={n_wg}", file=sys.stderr, flush=True)
+    print(f"[bench] {args.workload}: warmup done, blocks/group={W} workgroups={n_wg} lanes/pair={G}",
+          file=sys.stderr, flush=True)
     sec = time_solves(h, iters, args.steps, torch)
     code, res = h.solve(0)
     rp, rd = h.history(iters)
@@ -223,17 +299,22 @@ def main():
         "config": {"workload": f"{args.workload}: {wl['desc']}", "pairs_per_iteration": npairs,
                    "admm_iterations": it_done, "parallelism": "single GPU"},
         "admm_iters_per_s": it_done / sec,
+        "pair_phase_solves_per_s": npairs / (ph[0] * 1e-3),
         "residuals": {"r_pri": res[0]["r_pri"], "r_dual": res[0]["r_dual"], "first_iter_at_1e-4": reached,
                       "converged": res[0]["converged"], "min_alpha": res[0]["min_alpha"], "cost": res[0]["cost"]},
         "phase_ms": {"pair": ph[0], "trajectory": ph[1], "multiplier": ph[2], "residual": ph[3]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(f"pair_phase_{args.workload}") if args.workload == "c2" else None,
                      "kernel": "pair_phase_kernel", "bytes_per_launch": bytes_launch},
     }
     h.close()
     if not args.no_batched:
         print("[bench] batched vs plain (256 scenarios)", file=sys.stderr, flush=True)
         out["batched"] = batched_vs_plain(cadmm, torch)
+    if not args.no_stream:
+        print("[bench] streaming stateless pair QPs (2^22)", file=sys.stderr, flush=True)
+        out["stream"] = stream_batch(cadmm, torch)
     if not args.no_grad:
         print("[bench] reverse pass (3D, 100 unrolled iterations)", file=sys.stderr, flush=True)
         out["differentiation"] = differentiation(cadmm, torch)

@@ -84,7 +84,10 @@ enum { CADMM_ATT_YAW = 0, CADMM_ATT_EULER_ZYX = 1 };
  *  Q_s[n_s*n_s], Q_u[n_u*n_u] (symmetric), x_ref[n_scen*(N+1)*n_s], x0[n_scen*n_s]
  *  sigma (ADMM penalty), eps_prox (proximal weight), eps_pri, eps_dual (stop test)
  *  max_sweeps     Newton sweep budget of each pair QP (0 = default 24)
- *  waves_per_group  waves per workgroup of the pair kernels (0 = autotune, else 1..8)
+ *  waves_per_group  pair blocks per workgroup of the pair kernels (0 = autotune, else 1..8)
+ *  lanes_per_pair   lanes that share one pair QP in the pair phase (0 = autotune, else 1, 2, 4);
+ *                   a block then spans ceil(N / (64 / lanes_per_pair)) waves, and
+ *                   waves_per_group times that may not exceed 8
  */
 typedef struct cadmm_desc {
     int dim, n_s, n_u, N;
@@ -111,6 +114,7 @@ typedef struct cadmm_desc {
     double sigma, eps_prox, eps_pri, eps_dual;
     int max_sweeps;
     int waves_per_group;
+    int lanes_per_pair;
 } cadmm_desc;
 
 typedef struct cadmm_handle cadmm_handle;
@@ -177,8 +181,9 @@ int admm_scales(cadmm_handle* h, float* alpha);
 int admm_phase_times(cadmm_handle* h, int n_iters, float* ms_out);
 
 /* Launch shape chosen at setup (autotuned unless fixed in the descriptor):
- * waves (pair blocks) per workgroup and number of workgroups. */
-int admm_launch_config(cadmm_handle* h, int* waves_per_group, int* n_workgroups);
+ * pair blocks per workgroup, number of workgroups and lanes per pair QP of
+ * the pair phase. Any output pointer may be NULL. */
+int admm_launch_config(cadmm_handle* h, int* waves_per_group, int* n_workgroups, int* lanes_per_pair);
 
 /* Replace the obstacle face offsets d (host FP64, F_o values in obs_face_ptr
  * order) and/or the initial states x0 (host FP64, n_scen*n_s); NULL keeps the

@@ -37,7 +37,7 @@ class CadmmDesc(ctypes.Structure):
         ("Q_s", _dp), ("Q_u", _dp), ("x_ref", _dp), ("x0", _dp),
         ("sigma", ctypes.c_double), ("eps_prox", ctypes.c_double),
         ("eps_pri", ctypes.c_double), ("eps_dual", ctypes.c_double),
-        ("max_sweeps", ctypes.c_int), ("waves_per_group", ctypes.c_int),
+        ("max_sweeps", ctypes.c_int), ("waves_per_group", ctypes.c_int), ("lanes_per_pair", ctypes.c_int),
     ]
 
 
@@ -81,7 +81,7 @@ _SIGNATURES = {
     "admm_get_history": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp]),
     "admm_scales": (ctypes.c_int, [_vp, _vp]),
     "admm_phase_times": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
-    "admm_launch_config": (ctypes.c_int, [_vp, _ip, _ip]),
+    "admm_launch_config": (ctypes.c_int, [_vp, _ip, _ip, _ip]),
     "admm_set_params": (ctypes.c_int, [_vp, _dp, _dp]),
     "admm_grad_workspace_size": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "admm_record": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp]),
@@ -100,6 +100,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library missing: {LIB_PATH} (build it with __graft_entry__.build())")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded, so both share one runtime, device list and streams
+        _torch()
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGNATURES.items():
             fn = getattr(L, name)
@@ -140,7 +143,7 @@ def _ptr(t):
 class _DescHolder:
     """Contiguous host copies backing a CadmmDesc for the duration of a call."""
 
-    def __init__(self, prob, max_sweeps=0, waves_per_group=0):
+    def __init__(self, prob, max_sweeps=0, waves_per_group=0, lanes_per_pair=0):
         keep = {}
 
         def dbl(name):
@@ -168,6 +171,7 @@ class _DescHolder:
         d.sigma, d.eps_prox = float(prob["sigma"]), float(prob["eps_prox"])
         d.eps_pri, d.eps_dual = float(prob["eps_pri"]), float(prob["eps_dual"])
         d.max_sweeps, d.waves_per_group = int(max_sweeps), int(waves_per_group)
+        d.lanes_per_pair = int(lanes_per_pair)
         self.desc = d
         self.keep = keep
 
@@ -187,10 +191,10 @@ def cadmm_workspace_size(prob):
 class Handle:
     """A problem set up on the device (collision_admm_setup) with its workspace."""
 
-    def __init__(self, prob, device="cuda", stream=None, max_sweeps=0, waves_per_group=0):
+    def __init__(self, prob, device="cuda", stream=None, max_sweeps=0, waves_per_group=0, lanes_per_pair=0):
         torch = _torch()
         self.prob = prob
-        holder = _DescHolder(prob, max_sweeps, waves_per_group)
+        holder = _DescHolder(prob, max_sweeps, waves_per_group, lanes_per_pair)
         nbytes, self.n_blocks, self.n_pairs, self.y_floats = cadmm_workspace_size(prob)
         self.n_scen = len(prob["obs_ptr"]) - 1
         self.dim, self.N = int(prob["dim"]), int(prob["N"])
@@ -275,9 +279,11 @@ class Handle:
         return list(out)
 
     def launch_config(self):
-        w, g = ctypes.c_int(), ctypes.c_int()
-        _check(lib().admm_launch_config(self._h, ctypes.byref(w), ctypes.byref(g)), "admm_launch_config")
-        return w.value, g.value
+        """(pair blocks per workgroup, workgroups, lanes per pair QP)."""
+        w, g, l = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().admm_launch_config(self._h, ctypes.byref(w), ctypes.byref(g), ctypes.byref(l)),
+               "admm_launch_config")
+        return w.value, g.value, l.value
 
     # -- differentiation --------------------------------------------------
     def set_params(self, obs_d=None, x0=None):

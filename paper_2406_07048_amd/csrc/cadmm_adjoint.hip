@@ -21,6 +21,7 @@
 // trajectory launch sums per step; offset cotangents are summed over the
 // lanes of a wave and accumulated in FP64 per (part, face), a slot owned by
 // exactly one pair block. No float atomics: the pass is bitwise repeatable.
+#include "cadmm.h"
 #include "cadmm_device.h"
 
 namespace cadmm {
@@ -118,8 +119,14 @@ __global__ void __launch_bounds__(512) pair_adjoint_kernel(DevProblem P, PairAdj
     constexpr int D1 = DIM + 1;
     constexpr int NATT = Pose<DIM>::NATT;
     constexpr int NQ = Pose<DIM>::NQ;
-    extern __shared__ float lds[];          // [W][NQ][64]
+    constexpr int MF = CADMM_MAX_PART_FACES + CADMM_MAX_OBS_FACES;
+    extern __shared__ __align__(16) float lds[];
     const int W = blockDim.x >> 6;
+    // per wave: the block's faces [MF] float4 and obstacle offsets in FP64
+    // [CADMM_MAX_OBS_FACES], then the pose partials [W][NQ][64]
+    float4* faces_all = reinterpret_cast<float4*>(lds);
+    double* d64_all = reinterpret_cast<double*>(faces_all + W * MF);
+    float* red = reinterpret_cast<float*>(d64_all + W * CADMM_MAX_OBS_FACES);
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int N = P.N;
@@ -135,6 +142,21 @@ __global__ void __launch_bounds__(512) pair_adjoint_kernel(DevProblem P, PairAdj
         float qbar[NQ];
 #pragma unroll
         for (int a = 0; a < NQ; ++a) qbar[a] = 0.f;
+        // the block's faces and FP64 offsets into this wave's LDS slot (read
+        // by all three row passes)
+        float4* fl = faces_all + wave * MF;
+        double* dl = d64_all + wave * CADMM_MAX_OBS_FACES;
+        if (b < item.z) {
+            const int4 bk = P.blocks[b];
+            const int f0 = P.part_face_ptr[bk.y], nf = P.part_face_ptr[bk.y + 1] - f0;
+            const int g0 = P.obs_face_ptr[bk.z], ng = P.obs_face_ptr[bk.z + 1] - g0;
+            if (lane < nf) fl[lane] = P.part_faces[f0 + lane];
+            if (lane < ng) {
+                fl[CADMM_MAX_PART_FACES + lane] = P.obs_faces[g0 + lane];
+                dl[lane] = P.obs_d64[g0 + lane];
+            }
+        }
+        __syncthreads();
         if (b < item.z) {
             const int4 blk = P.blocks[b];
             const int part = uniform(blk.y), obs = uniform(blk.z);
@@ -143,8 +165,8 @@ __global__ void __launch_bounds__(512) pair_adjoint_kernel(DevProblem P, PairAdj
             const int fo0 = uniform(P.obs_face_ptr[obs]);
             const int no = uniform(P.obs_face_ptr[obs + 1] - fo0);
             const int yoff = uniform(P.block_yoff[b]);
-            const float4* rf = P.part_faces + fr0;
-            const float4* of = P.obs_faces + fo0;
+            const float4* rf = fl;
+            const float4* of = fl + CADMM_MAX_PART_FACES;
             const size_t col = (size_t)yoff + (tc - 1);
             const float* yn = A.yn + col;
             const float* yk = A.yk + col;
@@ -185,7 +207,7 @@ __global__ void __launch_bounds__(512) pair_adjoint_kernel(DevProblem P, PairAdj
             for (int l = 0; l < no; ++l) {
                 const float4 f = of[l];
                 const float y = yn[(size_t)(nr + l) * N];
-                Sd += face_offset(P.obs_d64, fo0 + l, f, ps.pos64, DIM) * y;
+                Sd += face_offset(dl, l, f, ps.pos64, DIM) * y;
                 cb[0] += y * f.x;
                 cb[1] += y * f.y;
                 if (DIM == 3) cb[DIM - 1] += y * f.z;
@@ -336,7 +358,7 @@ __global__ void __launch_bounds__(512) pair_adjoint_kernel(DevProblem P, PairAdj
                 if (DIM == 3) cbk[DIM - 1] += yh * f.z;
                 const float y1 = yn[(size_t)(nr + l) * N];
                 if (y1 > 0.f) {
-                    const float dp = face_offset(P.obs_d64, fo0 + l, f, ps.pos64, DIM);
+                    const float dp = face_offset(dl, l, f, ps.pos64, DIM);
                     float om[D1];
                     om[0] = dp;
                     om[1] = f.x;
@@ -456,7 +478,7 @@ __global__ void __launch_bounds__(512) pair_adjoint_kernel(DevProblem P, PairAdj
                 const float c3[3] = {f.x, f.y, f.z};
                 const float y1 = yn[(size_t)(nr + l) * N];
                 const float yh = yk[(size_t)(nr + l) * N];
-                const float dp = face_offset(P.obs_d64, fo0 + l, f, ps.pos64, DIM);
+                const float dp = face_offset(dl, l, f, ps.pos64, DIM);
                 float dbar = y1 * rbar[0] + (mult ? yh * tb : 0.f);
                 float g = 0.f;
                 if (y1 > 0.f) {
@@ -525,12 +547,12 @@ __global__ void __launch_bounds__(512) pair_adjoint_kernel(DevProblem P, PairAdj
         }
         // workgroup sum of the pose cotangents (fixed order over the waves)
 #pragma unroll
-        for (int a = 0; a < NQ; ++a) lds[(wave * NQ + a) * 64 + lane] = act ? qbar[a] : 0.f;
+        for (int a = 0; a < NQ; ++a) red[(wave * NQ + a) * 64 + lane] = act ? qbar[a] : 0.f;
         __syncthreads();
         float* out = A.qpart + (size_t)wg * NQ * 64;
         for (int e = threadIdx.x; e < NQ * 64; e += blockDim.x) {
             float acc = 0.f;
-            for (int w = 0; w < W; ++w) acc += lds[w * NQ * 64 + e];
+            for (int w = 0; w < W; ++w) acc += red[w * NQ * 64 + e];
             out[e] = acc;
         }
         __syncthreads();
@@ -554,10 +576,14 @@ hipError_t launch_pair_adjoint(const DevProblem& P, const PairAdjoint& A, int W,
 {
     if (P.n_blocks == 0) return hipSuccess;
     dim3 blk(64 * W), grd(grid);
+    const size_t slot = sizeof(float4) * (CADMM_MAX_PART_FACES + CADMM_MAX_OBS_FACES) +
+                        sizeof(double) * CADMM_MAX_OBS_FACES;
     if (P.dim == 2)
-        hipLaunchKernelGGL(pair_adjoint_kernel<2>, grd, blk, sizeof(float) * W * Pose<2>::NQ * 64, st, P, A);
+        hipLaunchKernelGGL(pair_adjoint_kernel<2>, grd, blk, W * slot + sizeof(float) * W * Pose<2>::NQ * 64, st, P,
+                           A);
     else
-        hipLaunchKernelGGL(pair_adjoint_kernel<3>, grd, blk, sizeof(float) * W * Pose<3>::NQ * 64, st, P, A);
+        hipLaunchKernelGGL(pair_adjoint_kernel<3>, grd, blk, W * slot + sizeof(float) * W * Pose<3>::NQ * 64, st, P,
+                           A);
     return hipGetLastError();
 }
 

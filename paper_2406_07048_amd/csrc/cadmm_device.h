@@ -66,6 +66,32 @@ __device__ __forceinline__ int wave_sum_int(int v)
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Lane groups of G = 1, 2 or 4 consecutive lanes (aligned within a quad).
+// quad_perm [1,0,3,2] exchanges lanes 2i and 2i+1, [2,3,0,1] lanes i and
+// i^2; both stay inside a quad, so groups never read another group's lanes.
+__device__ __forceinline__ float dpp_xor1(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float dpp_xor2(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ int dpp_xor1_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_xor2_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false); }
+
+// Sum over a lane group. Every lane of the group gets the bitwise same value
+// (pairwise sums in the same order: a + b = b + a exactly).
+template <int G>
+__device__ __forceinline__ float group_sum(float v)
+{
+    if constexpr (G >= 2) v += dpp_xor1(v);
+    if constexpr (G >= 4) v += dpp_xor2(v);
+    return v;
+}
+
 // ------------------------------------------------------------------------
 // pose: R(s), dR/d(attitude), part centre pos_i = rho(s) + R o_i
 // ------------------------------------------------------------------------

@@ -32,6 +32,7 @@ int fail(int code, const std::string& msg)
 
 constexpr int kHistCap = 4096;
 constexpr int kGraphBlock = 8;    // iterations per captured multi-iteration graph
+constexpr int kTuneWarmIters = 16; // iterations run before the launch shapes are timed
 
 struct Layout {
     // sizes
@@ -128,6 +129,8 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
         return fail(CADMM_INVALID, "face counts exceed the compiled kernel variants");
     if (d->waves_per_group < 0 || d->waves_per_group > kMaxWavesPerGroup)
         return fail(CADMM_INVALID, "waves_per_group out of range (0..8)");
+    if (d->lanes_per_pair != 0 && d->lanes_per_pair != 1 && d->lanes_per_pair != 2 && d->lanes_per_pair != 4)
+        return fail(CADMM_INVALID, "lanes_per_pair must be 0 (autotune), 1, 2 or 4");
     if (d->max_sweeps < 0 || d->max_sweeps > 1000) return fail(CADMM_INVALID, "max_sweeps out of range");
 
     L.dim = dim; L.n_s = ns; L.n_u = nu; L.N = N; L.n_parts = d->n_parts; L.n_scen = d->n_scen;
@@ -199,7 +202,7 @@ struct cadmm_handle {
     hipStream_t cap;             // private stream used only for graph capture
     hipGraphExec_t g1, gK;       // 1-iteration and kGraphBlock-iteration graphs
     hipGraphExec_t g1n, gKn;     // the same without the stopping test (unrolled runs)
-    int W, grid;
+    int W, G, grid;             // pair blocks and lanes per pair of the pair-phase launch
     // the last recorded unrolled run (admm_record), consumed by admm_backward
     int rec_iters, rec_every;
     void* rec_ws;
@@ -252,7 +255,7 @@ int upload_worklists(cadmm_handle* h, int W)
 // (3) multiplier update, residual sums and stopping test
 int enqueue_iteration(cadmm_handle* h, hipStream_t st, bool stop_test = true, float* hq_save = nullptr)
 {
-    if (h->L.n_blocks > 0) HIP_TRY(launch_pair_phase(h->P, h->W, h->grid, st));
+    if (h->L.n_blocks > 0) HIP_TRY(launch_pair_phase(h->P, h->W, h->G, h->grid, st));
     HIP_TRY(launch_traj_phase(h->P, h->L.n_blocks == 0 ? 1 : 0, st, hq_save));
     if (h->L.n_blocks > 0) HIP_TRY(launch_mult_phase(h->P, h->W, h->grid, st));
     if (stop_test) HIP_TRY(launch_residual(h->P, st));
@@ -404,13 +407,28 @@ int init_iterate(cadmm_handle* h)
 // choose waves per workgroup by timing the pair phase and the trajectory
 // phase (whose per-step reduction reads one partial per workgroup) from the
 // same iterate
-int autotune(cadmm_handle* h)
+int autotune(cadmm_handle* h, int fixed_W, int fixed_G)
 {
     const Layout& L = h->L;
-    if (L.n_blocks == 0) return upload_worklists(h, 1);
+    if (L.n_blocks == 0) {
+        h->G = 1;
+        return upload_worklists(h, 1);
+    }
     hipStream_t st = h->stream;
     const size_t yb = sizeof(float) * L.y_floats, xb = sizeof(float) * L.n_scen * (L.N + 1) * L.n_s,
                  ub = sizeof(float) * L.n_scen * L.N * L.n_u;
+    // time the candidates on an iterate of the running solve, not on the
+    // initial one: the pair QPs of the first iterations are far easier (the
+    // scale-LP certificates are near their optimum), so the initial iterate
+    // misjudges the Newton sweeps the shapes have to carry
+    int rc;
+    if ((rc = upload_worklists(h, fixed_W > 0 ? fixed_W : 4))) return rc;
+    h->G = fixed_G > 0 ? fixed_G : 1;
+    if (!pair_group_supported(L.N, h->W, h->G)) {
+        if ((rc = upload_worklists(h, 1))) return rc;
+    }
+    for (int i = 0; i < kTuneWarmIters; ++i)
+        if ((rc = enqueue_iteration(h, st, false))) return rc;
     HIP_TRY(hipMemcpyAsync(h->ws + L.y_snap, h->ws + L.y, yb, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(h->ws + L.x_snap, h->ws + L.x, xb, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(h->ws + L.u_snap, h->ws + L.u, ub, hipMemcpyDeviceToDevice, st));
@@ -423,30 +441,38 @@ int autotune(cadmm_handle* h)
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    const int cands[] = {1, 2, 4, 8};
+    const int Ws[] = {1, 2, 4, 8}, Gs[] = {1, 2, 4};
     float best = 1e30f;
-    int bestW = 4, rc;
-    for (int W : cands) {
-        if (W > 1 && W / 2 >= L.n_blocks) break;
-        if ((rc = upload_worklists(h, W))) return rc;
-        float tot = 0.f;
-        for (int rep = 0; rep < 4; ++rep) {
-            if ((rc = restore())) return rc;
-            HIP_TRY(hipEventRecord(e0, st));
-            HIP_TRY(launch_pair_phase(h->P, h->W, h->grid, st));
-            HIP_TRY(launch_traj_phase(h->P, 0, st));
-            HIP_TRY(hipEventRecord(e1, st));
-            HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (rep > 0) tot += ms;   // the first run warms caches and code
+    int bestW = 0, bestG = 1;
+    for (int G : Gs) {
+        if (fixed_G > 0 && G != fixed_G) continue;
+        for (int W : Ws) {
+            if (fixed_W > 0 && W != fixed_W) continue;
+            if (!pair_group_supported(L.N, W, G)) continue;
+            if (W > 1 && W / 2 >= L.n_blocks) continue;
+            if ((rc = upload_worklists(h, W))) return rc;
+            h->G = G;
+            float tot = 0.f;
+            for (int rep = 0; rep < 4; ++rep) {
+                if ((rc = restore())) return rc;
+                HIP_TRY(hipEventRecord(e0, st));
+                HIP_TRY(launch_pair_phase(h->P, h->W, h->G, h->grid, st));
+                HIP_TRY(launch_traj_phase(h->P, 0, st));
+                HIP_TRY(hipEventRecord(e1, st));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) tot += ms;   // the first run warms caches and code
+            }
+            if (tot < best) { best = tot; bestW = W; bestG = G; }
         }
-        if (tot < best) { best = tot; bestW = W; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if ((rc = restore())) return rc;
-    return upload_worklists(h, bestW);
+    if (bestW == 0) return fail(CADMM_INVALID, "no supported pair-kernel launch shape for this horizon");
+    h->G = bestG;
+    if ((rc = upload_worklists(h, bestW))) return rc;
+    return init_iterate(h);   // back to the initial iterate of setup
 }
 
 }  // namespace
@@ -600,9 +626,15 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     P.done = at<int>(h, L.done); P.iters = at<int>(h, L.iters); P.unconv = at<int>(h, L.unconv);
     P.hist_pri = at<float>(h, L.hist_pri); P.hist_dual = at<float>(h, L.hist_dual); P.hist_cap = kHistCap;
 
-    if ((rc = upload_worklists(h, d->waves_per_group > 0 ? d->waves_per_group : 4))) return bail(rc);
+    h->G = d->lanes_per_pair > 0 ? d->lanes_per_pair : 1;
+    if ((rc = upload_worklists(h, d->waves_per_group > 0 ? d->waves_per_group : 1))) return bail(rc);
     if ((rc = init_iterate(h))) return bail(rc);
-    if (d->waves_per_group == 0 && (rc = autotune(h))) return bail(rc);
+    if (L.n_blocks > 0 && d->waves_per_group > 0 && d->lanes_per_pair > 0) {
+        if (!pair_group_supported(L.N, d->waves_per_group, d->lanes_per_pair))
+            return bail(fail(CADMM_INVALID, "waves_per_group x waves per block exceeds 8 for this horizon"));
+    } else if ((rc = autotune(h, d->waves_per_group, d->lanes_per_pair))) {
+        return bail(rc);
+    }
     if ((rc = recapture(h))) return bail(rc);
     if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(CADMM_DEVICE, "setup failed"));
     *out = h;
@@ -743,7 +775,7 @@ int admm_phase_times(cadmm_handle* h, int n_iters, float* ms_out)
     hipStream_t st = h->stream;
     for (int it = 0; it < n_iters; ++it) {
         HIP_TRY(hipEventRecord(ev[0], st));
-        if (h->L.n_blocks > 0) HIP_TRY(launch_pair_phase(h->P, h->W, h->grid, st));
+        if (h->L.n_blocks > 0) HIP_TRY(launch_pair_phase(h->P, h->W, h->G, h->grid, st));
         HIP_TRY(hipEventRecord(ev[1], st));
         HIP_TRY(launch_traj_phase(h->P, h->L.n_blocks == 0 ? 1 : 0, st));
         HIP_TRY(hipEventRecord(ev[2], st));
@@ -763,11 +795,12 @@ int admm_phase_times(cadmm_handle* h, int n_iters, float* ms_out)
     return CADMM_OK;
 }
 
-int admm_launch_config(cadmm_handle* h, int* waves_per_group, int* n_workgroups)
+int admm_launch_config(cadmm_handle* h, int* waves_per_group, int* n_workgroups, int* lanes_per_pair)
 {
     if (!h) return fail(CADMM_INVALID, "bad handle");
     if (waves_per_group) *waves_per_group = h->W;
     if (n_workgroups) *n_workgroups = h->P.n_wg;
+    if (lanes_per_pair) *lanes_per_pair = h->G;
     return CADMM_OK;
 }
 

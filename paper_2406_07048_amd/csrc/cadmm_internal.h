@@ -91,7 +91,10 @@ struct PairAdjoint {
 
 // Kernel launchers (defined in cadmm_kernels.hip / cadmm_adjoint.hip). All
 // return hipError_t of the launch.
-hipError_t launch_pair_phase(const DevProblem& P, int waves_per_group, int grid, hipStream_t s);
+// Pair phase with W pair blocks per workgroup and G lanes per pair (1, 2, 4);
+// a block takes ceil(N / (64 / G)) waves, and W times that must be <= 8.
+hipError_t launch_pair_phase(const DevProblem& P, int waves_per_group, int lanes_per_pair, int grid, hipStream_t s);
+bool pair_group_supported(int N, int W, int G);
 hipError_t launch_mult_phase(const DevProblem& P, int waves_per_group, int grid, hipStream_t s);
 hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t s, float* hq_save = nullptr);
 hipError_t launch_traj_adjoint(const DevProblem& P, const TrajAdjoint& TA, hipStream_t s);

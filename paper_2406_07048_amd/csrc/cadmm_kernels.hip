@@ -27,23 +27,31 @@ namespace cadmm {
 //   lambda rows k: K_k = (0, a_k), kappa_k = b_k
 //   mu rows l:     K_l = (d'_l, R^T c_l), d'_l = d_l - c_l.pos, kappa_l = 0
 //   gamma row:     K = (1, 0), kappa = 0
-// Each lane keeps d'_l of its pair (small near the obstacle, so no
+// Each lane keeps d'_l of its rows (small near the obstacle, so no
 // cancellation against the world-frame offsets); the obstacle normals c_l
-// stay wave-uniform. Slopes use s_l = d'_l v0 + c_l.(R v_r), and the mu-row
-// Hessian block is E M E^T with E = diag(1, R^T) and M = sum f (d', c)(d', c)^T.
+// come from the block's LDS copy. Slopes use s_l = d'_l v0 + c_l.(R v_r), and
+// the mu-row Hessian block is E M E^T with E = diag(1, R^T) and
+// M = sum f (d', c)(d', c)^T.
+// A pair is solved by a group of G lanes (G = 1, 2, 4): lane q of the group
+// owns the lambda and mu rows with index = q (mod G) and the group sums its
+// partial sums with group_sum, so every lane of the group holds the same
+// Newton iterate. The gamma row is evaluated by every lane and counted once.
 // ------------------------------------------------------------------------
 
-template <int DIM, int MR, int MO>
+template <int DIM, int MR, int MO, int G>
 struct PairRows {
     static constexpr int NV = DIM + 2;
+    static constexpr int RR = (MR + G - 1) / G;   // lambda rows per lane
+    static constexpr int RO = (MO + G - 1) / G;   // mu rows per lane
+    int q;                     // lane within the group
     int nr, no;
-    const float4* rf;          // robot faces of the part (wave-uniform)
-    const float4* of;          // obstacle faces (wave-uniform)
+    const float4* rf;          // robot faces of the part (LDS)
+    const float4* of;          // obstacle faces (LDS)
     float R[DIM * DIM];
     float bh[DIM + 1];
-    float yhR[MR], yhO[MO], yhG;
-    float ieR[MR], ieO[MO], ieG;    // 1 / (eps D_l)
-    float dpO[MO];                  // d'_l of the pair
+    float yhR[RR], yhO[RO], yhG;
+    float ieR[RR], ieO[RO], ieG;    // 1 / (eps D_l)
+    float dpO[RO];                  // d'_l of the pair
 
     template <bool HESS>
     __device__ __forceinline__ void pass(const float (&z)[NV], float (&g)[NV], float (&H)[NV * NV],
@@ -61,28 +69,32 @@ struct PairRows {
             for (int c = 0; c < DIM; ++c) acc += R[r * DIM + c] * vr[c];
             w[r] = acc;
         }
+        // partial sums of this lane's rows
+        constexpr int NH = DIM * (DIM + 1) / 2;          // lambda-row Hessian block (upper)
+        constexpr int NM = (DIM + 1) * (DIM + 2) / 2;    // mu-row (d', c) moments (upper)
         float gl[DIM] = {}, gnu = 0.f, Sd = 0.f, Sc[DIM] = {}, ysc = 0.f;
-        float Hl[DIM * DIM] = {}, Hln[DIM] = {}, Hnn = 0.f;
-        float M[(DIM + 1) * (DIM + 1)] = {};
+        float Hl[NH] = {}, Hln[DIM] = {}, Hnn = 0.f, M[NM] = {};
 #pragma unroll
-        for (int k = 0; k < MR; ++k) {
+        for (int m = 0; m < RR; ++m) {
+            const int k = q + G * m;
             if (k < nr) {
                 const float4 f = rf[k];
                 const float a[3] = {f.x, f.y, f.z};
                 float s = -f.w * nu, an = 0.f;
 #pragma unroll
                 for (int r = 0; r < DIM; ++r) { s += a[r] * vr[r]; an += fabsf(a[r]); }
-                const float y = fmaxf(0.f, yhR[k] - s * ieR[k]);
+                const float y = fmaxf(0.f, yhR[m] - s * ieR[m]);
 #pragma unroll
                 for (int r = 0; r < DIM; ++r) gl[r] += y * a[r];
                 gnu += f.w * y;
                 ysc += y * an;
                 if (HESS) {
-                    const float act = y > 0.f ? ieR[k] : 0.f;
+                    const float act = y > 0.f ? ieR[m] : 0.f;
+                    int h = 0;
 #pragma unroll
                     for (int r = 0; r < DIM; ++r) {
 #pragma unroll
-                        for (int c = r; c < DIM; ++c) Hl[r * DIM + c] += act * a[r] * a[c];
+                        for (int c = r; c < DIM; ++c) Hl[h++] += act * a[r] * a[c];
                         Hln[r] += act * f.w * a[r];
                     }
                     Hnn += act * f.w * f.w;
@@ -90,26 +102,46 @@ struct PairRows {
             }
         }
 #pragma unroll
-        for (int l = 0; l < MO; ++l) {
+        for (int m = 0; m < RO; ++m) {
+            const int l = q + G * m;
             if (l < no) {
                 const float4 f = of[l];
-                const float ch[4] = {dpO[l], f.x, f.y, f.z};   // (d'_l, c_l)
+                const float ch[4] = {dpO[m], f.x, f.y, f.z};   // (d'_l, c_l)
                 float s = ch[0] * v0, cn = 0.f;
 #pragma unroll
                 for (int r = 0; r < DIM; ++r) { s += ch[1 + r] * w[r]; cn += fabsf(ch[1 + r]); }
-                const float y = fmaxf(0.f, yhO[l] - s * ieO[l]);
+                const float y = fmaxf(0.f, yhO[m] - s * ieO[m]);
                 Sd += ch[0] * y;
 #pragma unroll
                 for (int r = 0; r < DIM; ++r) Sc[r] += ch[1 + r] * y;
                 ysc += y * (fabsf(ch[0]) + cn);
                 if (HESS) {
-                    const float act = y > 0.f ? ieO[l] : 0.f;
+                    const float act = y > 0.f ? ieO[m] : 0.f;
+                    int h = 0;
 #pragma unroll
                     for (int r = 0; r <= DIM; ++r)
 #pragma unroll
-                        for (int c = r; c <= DIM; ++c) M[r * (DIM + 1) + c] += act * ch[r] * ch[c];
+                        for (int c = r; c <= DIM; ++c) M[h++] += act * ch[r] * ch[c];
                 }
             }
+        }
+        // group sums (every lane of the group gets the same values)
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) {
+            gl[r] = group_sum<G>(gl[r]);
+            Sc[r] = group_sum<G>(Sc[r]);
+        }
+        gnu = group_sum<G>(gnu);
+        Sd = group_sum<G>(Sd);
+        ysc = group_sum<G>(ysc);
+        if (HESS) {
+#pragma unroll
+            for (int h = 0; h < NH; ++h) Hl[h] = group_sum<G>(Hl[h]);
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) Hln[r] = group_sum<G>(Hln[r]);
+            Hnn = group_sum<G>(Hnn);
+#pragma unroll
+            for (int h = 0; h < NM; ++h) M[h] = group_sum<G>(M[h]);
         }
         const float yg = fmaxf(0.f, yhG - v0 * ieG);
         ysc += yg;
@@ -131,32 +163,50 @@ struct PairRows {
         for (int r = 0; r < DIM; ++r) bm = fmaxf(bm, fabsf(bh[1 + r]));
         sc = 1.f + bm + mx + ysc;
         if (HESS) {
+            // full symmetric (d', c) moment matrix and lambda block
+            float Mf[(DIM + 1) * (DIM + 1)], Hf[DIM * DIM];
+            {
+                int h = 0;
+#pragma unroll
+                for (int r = 0; r <= DIM; ++r)
+#pragma unroll
+                    for (int c = r; c <= DIM; ++c) {
+                        Mf[r * (DIM + 1) + c] = M[h];
+                        Mf[c * (DIM + 1) + r] = M[h];
+                        ++h;
+                    }
+                h = 0;
+#pragma unroll
+                for (int r = 0; r < DIM; ++r)
+#pragma unroll
+                    for (int c = r; c < DIM; ++c) {
+                        Hf[r * DIM + c] = Hl[h];
+                        Hf[c * DIM + r] = Hl[h];
+                        ++h;
+                    }
+            }
             // H_vv = I + diag(1, R^T) M diag(1, R)  (+ lambda and gamma rows)
-#pragma unroll
-            for (int r = 0; r <= DIM; ++r)
-#pragma unroll
-                for (int c = 0; c < r; ++c) M[r * (DIM + 1) + c] = M[c * (DIM + 1) + r];
             float MR_[(DIM + 1) * DIM];   // M[:, 1:] R  -> (DIM+1) x DIM
 #pragma unroll
             for (int r = 0; r <= DIM; ++r)
 #pragma unroll
-                for (int q = 0; q < DIM; ++q) {
+                for (int qq = 0; qq < DIM; ++qq) {
                     float acc = 0.f;
 #pragma unroll
-                    for (int e = 0; e < DIM; ++e) acc += M[r * (DIM + 1) + 1 + e] * R[e * DIM + q];
-                    MR_[r * DIM + q] = acc;
+                    for (int e = 0; e < DIM; ++e) acc += Mf[r * (DIM + 1) + 1 + e] * R[e * DIM + qq];
+                    MR_[r * DIM + qq] = acc;
                 }
-            H[0] = M[0] + 1.f + (yg > 0.f ? ieG : 0.f);
+            H[0] = Mf[0] + 1.f + (yg > 0.f ? ieG : 0.f);
 #pragma unroll
-            for (int q = 0; q < DIM; ++q) H[1 + q] = MR_[q];
+            for (int qq = 0; qq < DIM; ++qq) H[1 + qq] = MR_[qq];
 #pragma unroll
             for (int r = 0; r < DIM; ++r)
 #pragma unroll
-                for (int q = r; q < DIM; ++q) {
+                for (int qq = r; qq < DIM; ++qq) {
                     float acc = 0.f;
 #pragma unroll
-                    for (int c = 0; c < DIM; ++c) acc += R[c * DIM + r] * MR_[(1 + c) * DIM + q];
-                    H[(1 + r) * NV + 1 + q] = acc + (r == q ? 1.f : 0.f) + Hl[r * DIM + q];
+                    for (int c = 0; c < DIM; ++c) acc += R[c * DIM + r] * MR_[(1 + c) * DIM + qq];
+                    H[(1 + r) * NV + 1 + qq] = acc + (r == qq ? 1.f : 0.f) + Hf[r * DIM + qq];
                 }
 #pragma unroll
             for (int r = 0; r < DIM; ++r) H[(1 + r) * NV + DIM + 1] = -Hln[r];
@@ -250,6 +300,7 @@ template <int NV, class Rows>
 __device__ int dual_newton(const Rows& rows, float (&z)[NV], int max_sweeps)
 {
     float gprev = FLT_MAX;
+    float al_prev = 1.f;   // step accepted by the previous sweep
     for (int it = 0; it < max_sweeps; ++it) {
         float g[NV], H[NV * NV], sc;
         rows.template pass<true>(z, g, H, sc);
@@ -259,13 +310,38 @@ __device__ int dual_newton(const Rows& rows, float (&z)[NV], int max_sweeps)
             gmax = fmaxf(gmax, fabsf(g[i]));
             zmax = fmaxf(zmax, fabsf(z[i]));
         }
-        // converged, or stalled at the rounding floor of the gradient
-        if (gmax <= 1e-7f * sc || (gmax <= 2e-6f * sc && gmax >= 0.5f * gprev)) return it;
+        // converged, or stalled at the rounding floor of the gradient. On C3
+        // pairs (FP32 against the FP64 active-set solution) every iterate with
+        // gmax <= 1e-6 sc had a scaled dual error <= 3.4e-6, and iterates that
+        // stop improving below 4e-6 sc sit at the FP32 floor of the gradient
+        // (error <= 7e-6); iterating on there only spent the sweep budget.
+        if (gmax <= 1e-6f * sc || (gmax <= 4e-6f * sc && gmax >= 0.7f * gprev)) return it;
         gprev = gmax;
         float dz[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) dz[i] = g[i];
         chol_solve<NV>(H, dz);
+        // After a short step the direction is often steered by rows whose
+        // dual is about to reach zero; they stop it at the first kink every
+        // sweep. Re-solve with the generalised Hessian of the active set at
+        // the full step (a primal-dual active-set correction) and take that
+        // direction when it is still an ascent direction.
+        if (al_prev < 0.1f) {
+            float zt[NV], gt[NV], Ht[NV * NV], sct, dz2[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) zt[i] = z[i] + dz[i];
+            rows.template pass<true>(zt, gt, Ht, sct);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) dz2[i] = g[i];
+            chol_solve<NV>(Ht, dz2);
+            float e0 = 0.f;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) e0 += dz2[i] * g[i];
+            if (e0 > 0.f) {
+#pragma unroll
+                for (int i = 0; i < NV; ++i) dz[i] = dz2[i];
+            }
+        }
         // Newton step at the rounding level of z: the active set is settled
         // and z is the optimum to working precision
         float dmax = 0.f;
@@ -312,9 +388,14 @@ __device__ int dual_newton(const Rows& rows, float (&z)[NV], int max_sweeps)
                 }
             }
             al = lo;
+            // no step along dz passes the test: at the FP32 floor of the
+            // directional derivative z cannot be improved, and every further
+            // sweep would repeat this one exactly
+            if (al == 0.f) return it + 1;
         }
 #pragma unroll
         for (int i = 0; i < NV; ++i) z[i] += al * dz[i];
+        al_prev = al;
     }
     return -1;
 }
@@ -329,33 +410,66 @@ struct Contrib {
     static constexpr int NC = NQ * (NQ + 1) / 2 + NQ;
 };
 
-template <int DIM, int MR, int MO>
+// Arg-max of (value, payload) over a lane group with ties to the smaller
+// key; every lane of the group ends with the same triple.
+template <int G>
+__device__ __forceinline__ void group_argmax(float& v, float& pay, int& key)
+{
+    if constexpr (G >= 2) {
+        const float ov = dpp_xor1(v), op = dpp_xor1(pay);
+        const int ok = dpp_xor1_i(key);
+        if (ov > v || (ov == v && ok < key)) { v = ov; pay = op; key = ok; }
+    }
+    if constexpr (G >= 4) {
+        const float ov = dpp_xor2(v), op = dpp_xor2(pay);
+        const int ok = dpp_xor2_i(key);
+        if (ov > v || (ov == v && ok < key)) { v = ov; pay = op; key = ok; }
+    }
+}
+
+// Waves per pair block: a wave holds 64 / G pairs.
+__host__ __device__ constexpr int pair_waves_per_block(int N, int G)
+{
+    return (N + 64 / G - 1) / (64 / G);
+}
+
+// One workgroup = WB pair blocks of one scenario, each spread over
+// pair_waves_per_block(N, G) waves; lane L of a block's wave c solves pair
+// t = c * (64 / G) + L / G + 1 with its group lane q = L % G.
+template <int DIM, int MR, int MO, int G>
 __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
 {
     constexpr int NV = DIM + 2;
     constexpr int NATT = Pose<DIM>::NATT;
     constexpr int NQ = Pose<DIM>::NQ;
     constexpr int NC = Contrib<DIM>::NC;
+    constexpr int PPW = 64 / G;                    // pairs per wave
+    using Rows = PairRows<DIM, MR, MO, G>;
     extern __shared__ __align__(16) float lds[];
-    const int W = blockDim.x >> 6;
+    const int N = P.N;
+    const int nw = pair_waves_per_block(N, G);
+    const int W = blockDim.x >> 6;                 // waves in the workgroup
+    const int WB = W / nw;                         // blocks in the workgroup
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    float4* faces = reinterpret_cast<float4*>(lds);   // [W][MR + MO] faces of each wave's block
-    float* red = lds + 4 * W * (MR + MO);             // [W][NC][64]
-    float* red_rd = red + W * NC * 64;                // [W]
+    const int bslot = wave / nw, chunk = wave % nw;
+    const int q = lane % G;
+    const int t = chunk * PPW + lane / G + 1;
+    float4* faces = reinterpret_cast<float4*>(lds);   // [WB][MR + MO] faces of each block
+    float* red = lds + 4 * WB * (MR + MO);            // [WB][NC][64] contributions by step
+    float* red_rd = red + WB * NC * 64;               // [W]
     int* red_un = reinterpret_cast<int*>(red_rd + W);
-    const int N = P.N;
     const float eps = P.eps_prox;
 
     for (int wg = blockIdx.x; wg < P.n_wg; wg += gridDim.x) {
         const int4 item = P.wg_items[wg];
         const int s = uniform(item.x);
         if (P.done[s]) continue;                 // uniform over the workgroup
-        const int b = uniform(item.y + wave);
-        // the block's faces into this wave's LDS slot: every solver pass reads
-        // them, and from LDS they are broadcast reads instead of HBM round trips
-        float4* fl = faces + wave * (MR + MO);
-        if (b < item.z) {
+        const int b = uniform(item.y + bslot);
+        // the block's faces into its LDS slot: every solver pass reads them,
+        // and from LDS they are cheap reads instead of HBM round trips
+        float4* fl = faces + bslot * (MR + MO);
+        if (b < item.z && chunk == 0) {
             const int4 bk = P.blocks[b];
             const int f0 = P.part_face_ptr[bk.y], nf = P.part_face_ptr[bk.y + 1] - f0;
             const int g0 = P.obs_face_ptr[bk.z], ng = P.obs_face_ptr[bk.z + 1] - g0;
@@ -368,13 +482,13 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
         for (int c = 0; c < NC; ++c) con[c] = 0.f;
         float rd = 0.f;
         int unc = 0;
-        const int t = lane + 1;
         if (b < item.z && t <= N) {
             const int4 blk = P.blocks[b];
             const int part = uniform(blk.y), obs = uniform(blk.z);
             const int fr0 = uniform(P.part_face_ptr[part]);
             const int fo0 = uniform(P.obs_face_ptr[obs]);
-            PairRows<DIM, MR, MO> pr;
+            Rows pr;
+            pr.q = q;
             pr.nr = uniform(P.part_face_ptr[part + 1] - fr0);
             pr.no = uniform(P.obs_face_ptr[obs + 1] - fo0);
             pr.rf = fl;
@@ -394,74 +508,81 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
             for (int r = 0; r < DIM; ++r) pr.bh[1 + r] = xi[r];
             const float* yb = P.y + yoff + (t - 1);
             // warm start v = K^T yhat + bhat, nu from the largest lambda row
-            float v0 = pr.bh[0], Sc[DIM] = {}, vr[DIM];
+            float v0 = 0.f, Sc[DIM] = {}, vr[DIM] = {};
 #pragma unroll
-            for (int r = 0; r < DIM; ++r) vr[r] = pr.bh[1 + r];
-            float best = -1.f, nu = 0.f;
-#pragma unroll
-            for (int k = 0; k < MR; ++k) {
+            for (int m = 0; m < Rows::RR; ++m) {
+                const int k = q + G * m;
                 if (k < pr.nr) {
                     const float4 f = pr.rf[k];
                     const float yk = yb[k * N];
-                    pr.yhR[k] = yk;
+                    pr.yhR[m] = yk;
                     const float D = f.x * f.x + f.y * f.y + (DIM == 3 ? f.z * f.z : 0.f);
-                    pr.ieR[k] = 1.0f / (eps * D);
+                    pr.ieR[m] = 1.0f / (eps * D);
                     vr[0] += yk * f.x;
                     vr[1] += yk * f.y;
                     if (DIM == 3) vr[DIM - 1] += yk * f.z;
                 } else {
-                    pr.yhR[k] = 0.f; pr.ieR[k] = 0.f;
+                    pr.yhR[m] = 0.f; pr.ieR[m] = 0.f;
                 }
             }
 #pragma unroll
-            for (int l = 0; l < MO; ++l) {
+            for (int m = 0; m < Rows::RO; ++m) {
+                const int l = q + G * m;
                 if (l < pr.no) {
                     const float4 f = pr.of[l];
                     const float c[3] = {f.x, f.y, f.z};
                     const float yl = yb[(pr.nr + l) * N];
-                    pr.yhO[l] = yl;
+                    pr.yhO[m] = yl;
                     const float dp = face_offset(P.obs_d64, fo0 + l, f, ps.pos64, DIM);
                     float cn = 0.f;
 #pragma unroll
                     for (int r = 0; r < DIM; ++r) cn += c[r] * c[r];
                     const float D = dp * dp + cn;
-                    pr.ieO[l] = 1.0f / (eps * D);
-                    pr.dpO[l] = dp;
+                    pr.ieO[m] = 1.0f / (eps * D);
+                    pr.dpO[m] = dp;
                     v0 += dp * yl;
 #pragma unroll
                     for (int r = 0; r < DIM; ++r) Sc[r] += c[r] * yl;
                 } else {
-                    pr.yhO[l] = 0.f; pr.ieO[l] = 0.f; pr.dpO[l] = 0.f;
+                    pr.yhO[m] = 0.f; pr.ieO[m] = 0.f; pr.dpO[m] = 0.f;
                 }
+            }
+            v0 = group_sum<G>(v0);
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) {
+                vr[r] = group_sum<G>(vr[r]);
+                Sc[r] = group_sum<G>(Sc[r]);
             }
             pr.yhG = yb[(pr.nr + pr.no) * N];
             pr.ieG = 1.0f / eps;
-            v0 += pr.yhG;
+            v0 += pr.bh[0] + pr.yhG;
 #pragma unroll
             for (int r = 0; r < DIM; ++r) {
                 float acc = 0.f;
 #pragma unroll
                 for (int m = 0; m < DIM; ++m) acc += ps.R[m * DIM + r] * Sc[m];
-                vr[r] += acc;
+                vr[r] += pr.bh[1 + r] + acc;
             }
+            float best = -1.f, nu = 0.f;
+            int kbest = 1 << 30;
 #pragma unroll
-            for (int k = 0; k < MR; ++k) {
-                if (k < pr.nr) {
+            for (int m = 0; m < Rows::RR; ++m) {
+                const int k = q + G * m;
+                if (k < pr.nr && pr.yhR[m] > best) {
                     const float4 f = pr.rf[k];
-                    if (pr.yhR[k] > best) {
-                        best = pr.yhR[k];
-                        float s = f.x * vr[0] + f.y * vr[1] + (DIM == 3 ? f.z * vr[DIM - 1] : 0.f);
-                        nu = s / f.w;
-                    }
+                    best = pr.yhR[m];
+                    kbest = k;
+                    nu = (f.x * vr[0] + f.y * vr[1] + (DIM == 3 ? f.z * vr[DIM - 1] : 0.f)) / f.w;
                 }
             }
+            group_argmax<G>(best, nu, kbest);
             float z[NV];
             z[0] = v0;
 #pragma unroll
             for (int r = 0; r < DIM; ++r) z[1 + r] = vr[r];
             z[DIM + 1] = nu;
             const int sweeps = dual_newton<NV>(pr, z, P.max_sweeps);
-            unc = sweeps < 0 ? 1 : 0;
+            unc = (sweeps < 0 && q == 0) ? 1 : 0;
 
             // final pass: primal rows, write-back, residual and Jacobian
             {
@@ -477,13 +598,14 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
                 float* yw = P.y + yoff + (t - 1);
                 float Al[DIM] = {}, Sd = 0.f, Scf[DIM] = {};
 #pragma unroll
-                for (int k = 0; k < MR; ++k) {
+                for (int m = 0; m < Rows::RR; ++m) {
+                    const int k = q + G * m;
                     if (k < pr.nr) {
                         const float4 f = pr.rf[k];
                         float s = -f.w * znu + f.x * z[1] + f.y * z[2] + (DIM == 3 ? f.z * z[DIM] : 0.f);
-                        const float y = fmaxf(0.f, pr.yhR[k] - s * pr.ieR[k]);
+                        const float y = fmaxf(0.f, pr.yhR[m] - s * pr.ieR[m]);
                         yw[k * N] = y;
-                        const float dl = y - pr.yhR[k];
+                        const float dl = y - pr.yhR[m];
                         rd += dl * dl;
                         Al[0] += y * f.x;
                         Al[1] += y * f.y;
@@ -491,24 +613,31 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
                     }
                 }
 #pragma unroll
-                for (int l = 0; l < MO; ++l) {
+                for (int m = 0; m < Rows::RO; ++m) {
+                    const int l = q + G * m;
                     if (l < pr.no) {
                         const float4 f = pr.of[l];
                         const float c[3] = {f.x, f.y, f.z};
-                        float s = pr.dpO[l] * zv0;
+                        float s = pr.dpO[m] * zv0;
 #pragma unroll
                         for (int r = 0; r < DIM; ++r) s += c[r] * w[r];
-                        const float y = fmaxf(0.f, pr.yhO[l] - s * pr.ieO[l]);
+                        const float y = fmaxf(0.f, pr.yhO[m] - s * pr.ieO[m]);
                         yw[(pr.nr + l) * N] = y;
-                        const float dl = y - pr.yhO[l];
+                        const float dl = y - pr.yhO[m];
                         rd += dl * dl;
-                        Sd += pr.dpO[l] * y;
+                        Sd += pr.dpO[m] * y;
 #pragma unroll
                         for (int r = 0; r < DIM; ++r) Scf[r] += c[r] * y;
                     }
                 }
+                Sd = group_sum<G>(Sd);
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) {
+                    Al[r] = group_sum<G>(Al[r]);
+                    Scf[r] = group_sum<G>(Scf[r]);
+                }
                 const float yg = fmaxf(0.f, pr.yhG - zv0 * pr.ieG);
-                yw[(pr.nr + pr.no) * N] = yg;
+                if (q == 0) yw[(pr.nr + pr.no) * N] = yg;   // gamma is not in the dual residual sum
                 // residual e = K^T y + bhat at s^k
                 float e[DIM + 1];
                 e[0] = 1.f + zeta + Sd + yg;
@@ -566,17 +695,22 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
                 }
             }
         }
-        // workgroup reduction in a fixed order (waves = blocks of one scenario)
+        // contributions by step t into the block's slot (lane q = 0 of each
+        // group; lanes of empty slots write zeros), then the workgroup sum
+        // over its blocks in a fixed order
         const float rdw = wave_sum(rd);
         const int unw = wave_sum_int(unc);
+        if (q == 0 && t <= 64) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) red[(wave * NC + c) * 64 + lane] = con[c];
+            for (int c = 0; c < NC; ++c) red[(bslot * NC + c) * 64 + t - 1] = con[c];
+        }
         if (lane == 0) { red_rd[wave] = rdw; red_un[wave] = unw; }
         __syncthreads();
         float* out = P.contrib + (size_t)wg * NC * 64;
         for (int e = threadIdx.x; e < NC * 64; e += blockDim.x) {
             float acc = 0.f;
-            for (int w = 0; w < W; ++w) acc += red[w * NC * 64 + e];
+            if ((e & 63) < N)
+                for (int w = 0; w < WB; ++w) acc += red[w * NC * 64 + e];
             out[e] = acc;
         }
         if (threadIdx.x == 0) {
@@ -726,7 +860,12 @@ __global__ void __launch_bounds__(64) residual_kernel(DevProblem P)
 // Horner sweep after the rollout.
 // ------------------------------------------------------------------------
 
-constexpr int kTrajThreads = 256;
+// Threads of the trajectory kernel: one output per thread in every phase of
+// the sweep (512 for the 16/8 padding, 256 otherwise).
+__host__ __device__ constexpr int traj_threads(int NS, int NU)
+{
+    return (NS * NS + NS * NU + NS > 256 || NU * NU + NU * NS + NU + NS * NS + NS > 256) ? 512 : 256;
+}
 
 // Floats of the gains region, which first holds the staged trajectory
 // (x and x_ref over t = 0..N, u over t = 0..N-1, padded to NS / NU).
@@ -743,29 +882,43 @@ __host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bo
     return N * nc + N * NS + traj_gain_floats(N, NS, NU) + N * NU + N * NS + (adj ? (N + 1) * NS : 0);
 }
 
-// Fixed-order sum of src[w * stride], w = w0..w1-1, with eight independent
-// partial sums (w - w0 mod 8) so that many loads are in flight at once.
-__device__ __forceinline__ float strided_sum(const float* src, size_t stride, int w0, int w1)
+// Fixed-order sum of the float4 src[w * stride], w = w0..w1-1, with eight
+// independent partial sums (w - w0 mod 8), so that many loads are in flight.
+__device__ __forceinline__ float4 strided_sum4(const float4* src, size_t stride, int w0, int w1)
 {
-    float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float4 a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     int w = w0;
     for (; w + 8 <= w1; w += 8) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) a[q] += src[(size_t)(w + q) * stride];
+        for (int q = 0; q < 8; ++q) {
+            const float4 v = src[(size_t)(w + q) * stride];
+            a[q].x += v.x; a[q].y += v.y; a[q].z += v.z; a[q].w += v.w;
+        }
     }
 #pragma unroll
     for (int q = 0; q < 7; ++q)
-        if (w + q < w1) a[q] += src[(size_t)(w + q) * stride];
-    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        if (w + q < w1) {
+            const float4 v = src[(size_t)(w + q) * stride];
+            a[q].x += v.x; a[q].y += v.y; a[q].z += v.z; a[q].w += v.w;
+        }
+    float4 r;
+    r.x = ((a[0].x + a[1].x) + (a[2].x + a[3].x)) + ((a[4].x + a[5].x) + (a[6].x + a[7].x));
+    r.y = ((a[0].y + a[1].y) + (a[2].y + a[3].y)) + ((a[4].y + a[5].y) + (a[6].y + a[7].y));
+    r.z = ((a[0].z + a[1].z) + (a[2].z + a[3].z)) + ((a[4].z + a[5].z) + (a[6].z + a[7].z));
+    r.w = ((a[0].w + a[1].w) + (a[2].w + a[3].w)) + ((a[4].w + a[5].w) + (a[6].w + a[7].w));
+    return r;
 }
 
 // Trajectory QP of one scenario per workgroup. State/input sizes are padded
 // to the compile-time NS >= n_s, NU >= n_u with zero dynamics rows/columns
 // and an identity input-cost block, so every small product unrolls.
 template <int NS, int NU, bool ADJ>
-__global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, int obstacle_free, float* hq_save,
-                                                                  TrajAdjoint TA)
+__global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevProblem P, int obstacle_free,
+                                                                          float* hq_save, TrajAdjoint TA)
 {
+    constexpr int TT = traj_threads(NS, NU);
     constexpr int NSU = NS + 1;
     __shared__ float A[NS * NS], B[NS * NU], Q2[NS * NS], R2[NU * NU], cdyn[NS];
     __shared__ int hmap[NS * NS], gmap[NS], pmap[NS];
@@ -790,7 +943,7 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
     float* wl = off + N * NS;              // reverse: [N+1][NS] w_t
 
     // 0. padded model and cost, pose-coordinate maps
-    for (int e = tid; e < NS * NS; e += kTrajThreads) {
+    for (int e = tid; e < NS * NS; e += TT) {
         const int i = e / NS, j = e % NS;
         const bool in = i < ns && j < ns;
         A[e] = in ? P.A_dyn[i * ns + j] : 0.f;
@@ -808,11 +961,11 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
         }
         hmap[e] = m;
     }
-    for (int e = tid; e < NS * NU; e += kTrajThreads) {
+    for (int e = tid; e < NS * NU; e += TT) {
         const int i = e / NU, j = e % NU;
         B[e] = (i < ns && j < nu) ? P.B_dyn[i * nu + j] : 0.f;
     }
-    for (int e = tid; e < NU * NU; e += kTrajThreads) {
+    for (int e = tid; e < NU * NU; e += TT) {
         const int i = e / NU, j = e % NU;
         R2[e] = (i < nu && j < nu) ? 2.f * P.Q_u[i * nu + j] : (i == j ? 1.f : 0.f);
     }
@@ -821,12 +974,12 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
         const float* xsrc = ADJ ? TA.xK : (dev ? P.x : nullptr);
         const float* usrc = ADJ ? TA.uK : (dev ? P.u : nullptr);
         const float* xrs = P.x_ref + (size_t)s * (N + 1) * ns;
-        for (int e = tid; e < (N + 1) * NS; e += kTrajThreads) {
+        for (int e = tid; e < (N + 1) * NS; e += TT) {
             const int t = e / NS, i = e % NS;
             sx[e] = (xsrc && i < ns) ? xsrc[((size_t)s * (N + 1) + t) * ns + i] : 0.f;
             sxr[e] = i < ns ? xrs[t * ns + i] : 0.f;
         }
-        for (int e = tid; e < N * NU; e += kTrajThreads) {
+        for (int e = tid; e < N * NU; e += TT) {
             const int t = e / NU, j = e % NU;
             su[e] = (usrc && j < nu) ? usrc[((size_t)s * N + t) * nu + j] : 0.f;
         }
@@ -853,19 +1006,30 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
     //    last iterate) and the input cotangents
     const int2 wr = P.scen_wg[s];
     if (ADJ) {
-        for (int e = tid; e < N * nc; e += kTrajThreads)
+        for (int e = tid; e < N * nc; e += TT)
             Hq[e] = TA.hq ? TA.hq[(size_t)s * N * nc + e] : 0.f;
-        for (int e = tid; e < N * NS; e += kTrajThreads) {
-            const int t = e / NS, i = e % NS;
-            float acc = 0.f;
-            if (TA.xK)
-#pragma unroll
-                for (int j = 0; j < NS; ++j) acc += Q2[i * NS + j] * (sx[(t + 1) * NS + j] - sxr[(t + 1) * NS + j]);
+        // four steps per thread: the pose partials are summed as float4
+        const int N4 = (N + 3) / 4;
+        for (int e = tid; e < N4 * NS; e += TT) {
+            const int t4 = e / NS, i = e % NS;
             const int a = pmap[i];
-            if (TA.qpart && a >= 0) acc += strided_sum(TA.qpart + (size_t)a * 64 + t, (size_t)nq * 64, wr.x, wr.y);
-            qr[e] = -acc;
+            float4 part = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (TA.qpart && a >= 0)
+                part = strided_sum4(reinterpret_cast<const float4*>(TA.qpart + (size_t)a * 64) + t4, (size_t)nq * 16,
+                                    wr.x, wr.y);
+            const float pq[4] = {part.x, part.y, part.z, part.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = 4 * t4 + q;
+                if (t >= N) break;
+                float acc = pq[q];
+                if (TA.xK)
+#pragma unroll
+                    for (int j = 0; j < NS; ++j) acc += Q2[i * NS + j] * (sx[(t + 1) * NS + j] - sxr[(t + 1) * NS + j]);
+                qr[t * NS + i] = -acc;
+            }
         }
-        for (int e = tid; e < N * NU; e += kTrajThreads) {
+        for (int e = tid; e < N * NU; e += TT) {
             const int t = e / NU, j = e % NU;
             float acc = 0.f;
             if (j < nu)
@@ -873,26 +1037,35 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
                 for (int m = 0; m < NU; ++m) acc += R2[j * NU + m] * su[t * NU + m];
             rin[e] = -acc;
         }
-        for (int e = tid; e < N * NS; e += kTrajThreads) off[e] = 0.f;
+        for (int e = tid; e < N * NS; e += TT) off[e] = 0.f;
     } else {
         if (!obstacle_free) {
-            for (int e = tid; e < N * nc; e += kTrajThreads) {
-                const int cc = e / N, t = e % N;
-                const float acc = strided_sum(P.contrib + (size_t)cc * 64 + t, (size_t)nc * 64, wr.x, wr.y);
-                Hq[t * nc + cc] = acc;
-                if (hq_save) hq_save[((size_t)s * N + t) * nc + cc] = acc;
+            // four steps per thread, the partials summed as float4
+            const int N4 = (N + 3) / 4;
+            for (int e = tid; e < N4 * nc; e += TT) {
+                const int cc = e / N4, t4 = e % N4;
+                const float4 v = strided_sum4(reinterpret_cast<const float4*>(P.contrib + (size_t)cc * 64) + t4,
+                                              (size_t)nc * 16, wr.x, wr.y);
+                const float vq[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int t = 4 * t4 + q;
+                    if (t >= N) break;
+                    Hq[t * nc + cc] = vq[q];
+                    if (hq_save) hq_save[((size_t)s * N + t) * nc + cc] = vq[q];
+                }
             }
         } else {
-            for (int e = tid; e < N * nc; e += kTrajThreads) Hq[e] = 0.f;
+            for (int e = tid; e < N * nc; e += TT) Hq[e] = 0.f;
         }
-        for (int e = tid; e < N * NS; e += kTrajThreads) {
+        for (int e = tid; e < N * NS; e += TT) {
             const int t = e / NS, i = e % NS;
             float acc = 0.f;
 #pragma unroll
             for (int j = 0; j < NS; ++j) acc += Q2[i * NS + j] * (sx[(t + 1) * NS + j] - sxr[(t + 1) * NS + j]);
             qr[e] = acc;
         }
-        for (int e = tid; e < N * NU; e += kTrajThreads) {
+        for (int e = tid; e < N * NU; e += TT) {
             const int t = e / NU, j = e % NU;
             float acc = 0.f;
             if (j < nu)
@@ -902,7 +1075,7 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
         }
         // dynamics offsets: the defects of the staged trajectory, in FP64
         // (zero-padded rows and columns contribute nothing)
-        for (int e = tid; e < N * NS; e += kTrajThreads) {
+        for (int e = tid; e < N * NS; e += TT) {
             const int t = e / NS, i = e % NS;
             double acc = (double)cdyn[i];
             if (dev) {
@@ -916,84 +1089,124 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
         }
     }
     __syncthreads();
+    // 2. backward Riccati sweep, V_t(x) = 1/2 x^T P x + p^T x, P_N = H_N.
+    //    Every phase is one strided dot product per thread, so a wave never
+    //    runs several output types one after the other:
+    //      out = bias + sum_k X[k * xs] Y[k * ys]
+    //    (a) PA = P A, PB = P B, w = P f_t + p;
+    //    (b) Quu = 2Q_u + B^T PB, Qux = B^T PA, qu = B^T w + input gradient,
+    //        Qxx = H_t + A^T PA, qx = h_t + A^T w (t >= 1);
+    //    (c) gains [K | k] = -Quu^{-1} [Qux | qu] and the update
+    //        P_t = Qxx + Qux^T K (symmetrised), p_t = qx + Qux^T k: each
+    //        thread factors the small Quu itself, so (c) needs no extra barrier.
+    //    (Folding (a) into (b) for tiny NS, NS^2 terms per output, measured
+    //    slower than the extra barrier on gfx950.)
+    constexpr bool kFold = false;
     // the linear stage terms of the forward pass carry the pose-block
     // gradients of the pair contributions; the adjoint LQ has none
     auto lin = [&](int t, int i) -> float {
         return qr[t * NS + i] + ((!ADJ && gmap[i] >= 0) ? Hq[t * nc + gmap[i]] : 0.f);
     };
-    // 2. backward Riccati sweep, V_t(x) = 1/2 x^T P x + p^T x, P_N = H_N
-    for (int e = tid; e < NS * NS; e += kTrajThreads) Pm[e] = Q2[e] + (hmap[e] >= 0 ? Hq[(N - 1) * nc + hmap[e]] : 0.f);
+    for (int e = tid; e < NS * NS; e += TT) Pm[e] = Q2[e] + (hmap[e] >= 0 ? Hq[(N - 1) * nc + hmap[e]] : 0.f);
     if (tid < NS) pv[tid] = lin(N - 1, tid);
+    // phase (a) descriptor of this thread: one output of PA, PB or w
+    constexpr int NA = NS * NS + NS * NU + NS;
+    int a_type = -1, a_i = 0, a_j = 0;
+    if (tid < NS * NS) { a_type = 0; a_i = tid / NS; a_j = tid % NS; }
+    else if (tid < NS * NS + NS * NU) { a_type = 1; a_i = (tid - NS * NS) / NU; a_j = (tid - NS * NS) % NU; }
+    else if (tid < NA) { a_type = 2; a_i = tid - NS * NS - NS * NU; }
+    // phase (b) descriptor: one output of Quu, Qux, qu, Qxx or qx
+    constexpr int NB = NU * NU + NU * NS + NU;
+    constexpr int NBX = NB + NS * NS + NS;
+    int b_type = -1, b_i = 0, b_j = 0;
+    if (tid < NU * NU) { b_type = 0; b_i = tid / NU; b_j = tid % NU; }
+    else if (tid < NU * NU + NU * NS) { b_type = 1; b_i = (tid - NU * NU) / NS; b_j = (tid - NU * NU) % NS; }
+    else if (tid < NB) { b_type = 2; b_i = tid - NU * NU - NU * NS; }
+    else if (tid < NB + NS * NS) { b_type = 3; b_i = (tid - NB) / NS; b_j = (tid - NB) % NS; }
+    else if (tid < NBX) { b_type = 4; b_i = tid - NB - NS * NS; }
+    // phase (c) descriptor: P(i, j) for j >= i, or p(i) (j = NS)
+    constexpr int NCP = NS * (NS + 1) / 2 + NS;
+    int c_i = -1, c_j = 0;
+    if (tid < NCP) {
+        int r = tid;
+        if (r < NS * (NS + 1) / 2) {
+            int i = 0;
+            while (r >= NS - i) { r -= NS - i; ++i; }
+            c_i = i;
+            c_j = i + r;
+        } else {
+            c_i = r - NS * (NS + 1) / 2;
+            c_j = NS;
+        }
+    }
     __syncthreads();
     for (int t = N - 1; t >= 0; --t) {
-        // a. PA = P A, PB = P B, w = P f_t + p
-        for (int e = tid; e < NS * NS + NS * NU + NS; e += kTrajThreads) {
-            if (e < NS * NS) {
-                const int i = e / NS, j = e % NS;
-                float acc = 0.f;
+        const float* ft = off + t * NS;
+        if (!kFold) {
+            // (a)
+            if (a_type >= 0) {
+                const float* X = Pm + a_i * NS;
+                const float* Y = a_type == 0 ? A + a_j : (a_type == 1 ? B + a_j : ft);
+                const int ys = a_type == 0 ? NS : (a_type == 1 ? NU : 1);
+                float acc = a_type == 2 ? pv[a_i] : 0.f;
 #pragma unroll
-                for (int k2 = 0; k2 < NS; ++k2) acc += Pm[i * NS + k2] * A[k2 * NS + j];
-                PA[e] = acc;
-            } else if (e < NS * NS + NS * NU) {
-                const int f = e - NS * NS, i = f / NU, j = f % NU;
-                float acc = 0.f;
-#pragma unroll
-                for (int k2 = 0; k2 < NS; ++k2) acc += Pm[i * NS + k2] * B[k2 * NU + j];
-                PB[f] = acc;
-            } else {
-                const int i = e - NS * NS - NS * NU;
-                float acc = pv[i];
-#pragma unroll
-                for (int k2 = 0; k2 < NS; ++k2) acc += Pm[i * NS + k2] * off[t * NS + k2];
-                wv[i] = acc;
+                for (int k2 = 0; k2 < NS; ++k2) acc += X[k2] * Y[k2 * ys];
+                float* O = a_type == 0 ? PA + a_i * NS + a_j : (a_type == 1 ? PB + a_i * NU + a_j : wv + a_i);
+                *O = acc;
             }
+            __syncthreads();
+        }
+        // (b)
+        if (b_type >= 0 && (t >= 1 || b_type <= 2)) {
+            // X: column b_i of B (types 0-2) or of A (types 3-4)
+            const float* X = b_type <= 2 ? B + b_i : A + b_i;
+            const int xs = b_type <= 2 ? NU : NS;
+            float bias;
+            if (b_type == 0) bias = R2[b_i * NU + b_j];
+            else if (b_type == 1) bias = 0.f;
+            else if (b_type == 2) bias = rin[t * NU + b_i];
+            else if (b_type == 3) bias = Q2[b_i * NS + b_j] + (hmap[b_i * NS + b_j] >= 0 ? Hq[(t - 1) * nc + hmap[b_i * NS + b_j]] : 0.f);
+            else bias = lin(t - 1, b_i);
+            float acc = bias;
+            if (kFold) {
+                // Y column j of P B, P A or the vector P f_t + p, formed here
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) {
+                    float y;
+                    if (b_type == 0) {
+                        y = 0.f;
+#pragma unroll
+                        for (int l = 0; l < NS; ++l) y += Pm[k2 * NS + l] * B[l * NU + b_j];
+                    } else if (b_type == 1 || b_type == 3) {
+                        y = 0.f;
+#pragma unroll
+                        for (int l = 0; l < NS; ++l) y += Pm[k2 * NS + l] * A[l * NS + b_j];
+                    } else {
+                        y = pv[k2];
+#pragma unroll
+                        for (int l = 0; l < NS; ++l) y += Pm[k2 * NS + l] * ft[l];
+                    }
+                    acc += X[k2 * xs] * y;
+                }
+            } else {
+                const float* Y = b_type == 0 ? PB + b_j : ((b_type == 1 || b_type == 3) ? PA + b_j : wv);
+                const int ys = b_type == 0 ? NU : ((b_type == 1 || b_type == 3) ? NS : 1);
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) acc += X[k2 * xs] * Y[k2 * ys];
+            }
+            float* O = b_type == 0 ? Quu + b_i * NU + b_j
+                     : b_type == 1 ? Qux + b_i * NS + b_j
+                     : b_type == 2 ? qu + b_i
+                     : b_type == 3 ? Qxx + b_i * NS + b_j
+                                   : qx + b_i;
+            *O = acc;
         }
         __syncthreads();
-        // b. Quu = 2Q_u + B^T P B, Qux = B^T P A, qu = B^T w + input gradient and,
-        //    for t >= 1, the stage-t terms Qxx = H_t + A^T P A, qx = h_t + A^T w
-        constexpr int NB = NU * NU + NU * NS + NU;
-        const int nx = t >= 1 ? NS * NS + NS : 0;
-        for (int e = tid; e < NB + nx; e += kTrajThreads) {
-            if (e < NU * NU) {
-                const int i = e / NU, j = e % NU;
-                float acc = R2[e];
-#pragma unroll
-                for (int k2 = 0; k2 < NS; ++k2) acc += B[k2 * NU + i] * PB[k2 * NU + j];
-                Quu[e] = acc;
-            } else if (e < NU * NU + NU * NS) {
-                const int f = e - NU * NU, i = f / NS, j = f % NS;
-                float acc = 0.f;
-#pragma unroll
-                for (int k2 = 0; k2 < NS; ++k2) acc += B[k2 * NU + i] * PA[k2 * NS + j];
-                Qux[f] = acc;
-            } else if (e < NB) {
-                const int i = e - NU * NU - NU * NS;
-                float acc = rin[t * NU + i];
-#pragma unroll
-                for (int k2 = 0; k2 < NS; ++k2) acc += B[k2 * NU + i] * wv[k2];
-                qu[i] = acc;
-            } else if (e < NB + NS * NS) {
-                const int f = e - NB, i = f / NS, j = f % NS;
-                float acc = Q2[f] + (hmap[f] >= 0 ? Hq[(t - 1) * nc + hmap[f]] : 0.f);
-#pragma unroll
-                for (int k2 = 0; k2 < NS; ++k2) acc += A[k2 * NS + i] * PA[k2 * NS + j];
-                Qxx[f] = acc;
-            } else {
-                const int i = e - NB - NS * NS;
-                float acc = lin(t - 1, i);
-#pragma unroll
-                for (int k2 = 0; k2 < NS; ++k2) acc += A[k2 * NS + i] * wv[k2];
-                qx[i] = acc;
-            }
-        }
-        __syncthreads();
-        // c. gains [K | k] = -Quu^{-1} [Qux | qu]: one column per thread, with a
-        //    register Cholesky factor of the small input Hessian
-        float* Kt = Kall + (size_t)t * NU * NSU;
-        if (tid <= NS) {
+        // (c) gains and, for t >= 1, the value function of step t
+        if (c_i >= 0 && (t >= 1 || c_j == c_i || (c_j == NS && c_i == 0))) {
             float L[NU * NU];
 #pragma unroll
-            for (int i = 0; i < NU * NU; ++i) L[i] = Quu[i];
+            for (int q = 0; q < NU * NU; ++q) L[q] = Quu[q];
 #pragma unroll
             for (int j = 0; j < NU; ++j) {
                 float d = L[j * NU + j];
@@ -1010,55 +1223,64 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
                     L[i * NU + j] = v * id;
                 }
             }
-            float r[NU];
+            // columns c_i and c_j of the gains [K | k] (c_j = NS: feedforward)
+            auto gain = [&](int col, float (&r)[NU]) {
 #pragma unroll
-            for (int i = 0; i < NU; ++i) r[i] = -(tid < NS ? Qux[i * NS + tid] : qu[i]);
+                for (int i = 0; i < NU; ++i) r[i] = -(col < NS ? Qux[i * NS + col] : qu[i]);
 #pragma unroll
-            for (int i = 0; i < NU; ++i) {
-                float v = r[i];
+                for (int i = 0; i < NU; ++i) {
+                    float v = r[i];
 #pragma unroll
-                for (int k2 = 0; k2 < i; ++k2) v -= L[i * NU + k2] * r[k2];
-                r[i] = v / L[i * NU + i];
-            }
-#pragma unroll
-            for (int i = NU - 1; i >= 0; --i) {
-                float v = r[i];
-#pragma unroll
-                for (int k2 = i + 1; k2 < NU; ++k2) v -= L[k2 * NU + i] * r[k2];
-                r[i] = v / L[i * NU + i];
-            }
-#pragma unroll
-            for (int i = 0; i < NU; ++i) Kt[i * NSU + tid] = r[i];
-        }
-        if (t == 0) break;
-        __syncthreads();
-        // d. P_t = Qxx + Qux^T K (symmetrised), p_t = qx + Qux^T k
-        for (int e = tid; e < NS * NS + NS; e += kTrajThreads) {
-            if (e < NS * NS) {
-                const int i = e / NS, j = e % NS;
-                float aij = Qxx[e], aji = Qxx[j * NS + i];
-#pragma unroll
-                for (int k2 = 0; k2 < NU; ++k2) {
-                    aij += Qux[k2 * NS + i] * Kt[k2 * NSU + j];
-                    aji += Qux[k2 * NS + j] * Kt[k2 * NSU + i];
+                    for (int k2 = 0; k2 < i; ++k2) v -= L[i * NU + k2] * r[k2];
+                    r[i] = v / L[i * NU + i];
                 }
-                Pm[e] = 0.5f * (aij + aji);
-            } else {
-                const int i = e - NS * NS;
-                float acc = qx[i];
 #pragma unroll
-                for (int k2 = 0; k2 < NU; ++k2) acc += Qux[k2 * NS + i] * Kt[k2 * NSU + NS];
-                pv[i] = acc;
+                for (int i = NU - 1; i >= 0; --i) {
+                    float v = r[i];
+#pragma unroll
+                    for (int k2 = i + 1; k2 < NU; ++k2) v -= L[k2 * NU + i] * r[k2];
+                    r[i] = v / L[i * NU + i];
+                }
+            };
+            float Ki[NU], Kj[NU];
+            gain(c_i, Ki);
+            gain(c_j, Kj);
+            float* Kt = Kall + (size_t)t * NU * NSU;
+            // the diagonal threads own the gain columns, thread p(0) the feedforward
+            if (c_j == c_i) {
+#pragma unroll
+                for (int i = 0; i < NU; ++i) Kt[i * NSU + c_i] = Ki[i];
+            }
+            if (c_j == NS && c_i == 0) {
+#pragma unroll
+                for (int i = 0; i < NU; ++i) Kt[i * NSU + NS] = Kj[i];
+            }
+            if (t >= 1) {
+                if (c_j < NS) {
+                    float aij = Qxx[c_i * NS + c_j] + Qxx[c_j * NS + c_i];
+#pragma unroll
+                    for (int k2 = 0; k2 < NU; ++k2)
+                        aij += Qux[k2 * NS + c_i] * Kj[k2] + Qux[k2 * NS + c_j] * Ki[k2];
+                    Pm[c_i * NS + c_j] = 0.5f * aij;
+                    Pm[c_j * NS + c_i] = 0.5f * aij;
+                } else {
+                    float acc = qx[c_i];
+#pragma unroll
+                    for (int k2 = 0; k2 < NU; ++k2) acc += Qux[k2 * NS + c_i] * Kj[k2];
+                    pv[c_i] = acc;
+                }
             }
         }
         __syncthreads();
     }
-    __syncthreads();
-    // 3. forward rollout dx_{t+1} = A dx + B (K dx + k) + f_t; thread i owns
-    //    dx_i (rows of A and B in registers) and writes x^k + dx, threads
-    //    NS..NS+NU-1 write u^k + du. The reverse mode rolls w out from w_0 = 0.
+    // 3. rollout dx_{t+1} = A dx + B (K dx + k) + f_t; thread i owns dx_i
+    //    (rows of A and B in registers), threads NS..NS+NU-1 the inputs. The
+    //    deviations stay in LDS (forward: over qr and rin, dead after the
+    //    sweep; reverse: w in wl) and are written out by one parallel pass.
     float* xo = P.x + (size_t)s * (N + 1) * ns;
     float* uo = P.u + (size_t)s * N * nu;
+    float* dX = ADJ ? wl : qr;             // forward: dx_t at (t-1) * NS, t = 1..N; reverse: w_t at t * NS
+    float* dU = rin;                       // forward: du_t at t * NU
     float Ar[NS], Br[NU];
     const int row = tid < NS ? tid : 0;
 #pragma unroll
@@ -1070,7 +1292,6 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
         if (!ADJ && tid < ns) {
             const float x0v = P.x0[(size_t)s * ns + tid];
             v = dev ? x0v - xo[tid] : x0v;
-            xo[tid] = x0v;
         }
         xbuf[0][tid] = v;
         if (ADJ) wl[tid] = 0.f;
@@ -1098,30 +1319,41 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
 #pragma unroll
                 for (int j = 0; j < NU; ++j) acc += Br[j] * uu[j];
                 xbuf[(t + 1) & 1][tid] = acc;
-                if (ADJ) {
-                    wl[(t + 1) * NS + tid] = acc;
-                    if (tid < ns) TA.w[((size_t)s * N + t) * ns + tid] = acc;
-                } else if (tid < ns) {
-                    float* xp = xo + (t + 1) * ns + tid;
-                    *xp = dev ? *xp + acc : acc;
-                }
+                if (ADJ) wl[(t + 1) * NS + tid] = acc;
+                else dX[t * NS + tid] = acc;
             } else if (!ADJ) {
                 const int j = tid - NS;
                 float v = 0.f;
 #pragma unroll
                 for (int q = 0; q < NU; ++q) v = q == j ? uu[q] : v;
-                if (j < nu) {
-                    float* up = uo + t * nu + j;
-                    *up = dev ? *up + v : v;
-                }
+                dU[t * NU + j] = v;
             }
         }
         __syncthreads();
     }
-    if (!ADJ) return;
-    // 4. reverse mode: zbar_t = xbar_t - H_t w_t (stored over qr), then
-    //    x0bar = sum_t (A^T)^t zbar_t by a Horner sweep from t = N down to 1
-    for (int e = tid; e < N * NS; e += kTrajThreads) {
+    if (!ADJ) {
+        // x_t = x^k_t + dx_t (t = 1..N), u_t = u^k_t + du_t, x_0 = x0
+        for (int e = tid; e < N * ns; e += TT) {
+            const int t = e / ns, i = e % ns;
+            float* xp = xo + (t + 1) * ns + i;
+            *xp = (dev ? *xp : 0.f) + dX[t * NS + i];
+        }
+        for (int e = tid; e < N * nu; e += TT) {
+            const int t = e / nu, j = e % nu;
+            float* up = uo + t * nu + j;
+            *up = (dev ? *up : 0.f) + dU[t * NU + j];
+        }
+        if (tid < ns) xo[tid] = P.x0[(size_t)s * ns + tid];
+        return;
+    }
+    // 4. reverse mode: w_t out, zbar_t = xbar_t - H_t w_t (stored over qr),
+    //    then x0bar = sum_t (A^T)^t zbar_t by a Horner sweep from t = N down
+    //    to 1 (one barrier per step, double-buffered)
+    for (int e = tid; e < N * ns; e += TT) {
+        const int t = e / ns, i = e % ns;
+        TA.w[((size_t)s * N + t) * ns + i] = wl[(t + 1) * NS + i];
+    }
+    for (int e = tid; e < N * NS; e += TT) {
         const int t = e / NS, i = e % NS;
         const float* wt = wl + (t + 1) * NS;
         float acc = -qr[e];
@@ -1134,18 +1366,18 @@ __global__ void __launch_bounds__(kTrajThreads) traj_phase_kernel(DevProblem P, 
     }
     if (tid < NS) xbuf[0][tid] = 0.f;
     __syncthreads();
+    int cur = 0;
     for (int t = N - 1; t >= 0; --t) {
-        if (tid < NS) xbuf[1][tid] = xbuf[0][tid] + qr[t * NS + tid];
-        __syncthreads();
         if (tid < NS) {
             float acc = 0.f;
 #pragma unroll
-            for (int j = 0; j < NS; ++j) acc += A[j * NS + tid] * xbuf[1][j];
-            xbuf[0][tid] = acc;
+            for (int j = 0; j < NS; ++j) acc += A[j * NS + tid] * (xbuf[cur][j] + qr[t * NS + j]);
+            xbuf[cur ^ 1][tid] = acc;
         }
+        cur ^= 1;
         __syncthreads();
     }
-    if (tid < ns) TA.gx0[(size_t)s * ns + tid] += (double)xbuf[0][tid];
+    if (tid < ns) TA.gx0[(size_t)s * ns + tid] += (double)xbuf[cur][tid];
 }
 
 // ------------------------------------------------------------------------
@@ -1666,18 +1898,32 @@ static int pick_variant(const DevProblem& P)
     return -1;
 }
 
-hipError_t launch_pair_phase(const DevProblem& P, int W, int grid, hipStream_t st)
+template <int DIM, int MR, int MO>
+static void launch_pair_g(const DevProblem& P, int W, int G, int grid, hipStream_t st)
 {
-    const int v = pick_variant(P);
     const int nc = P.nc;
-    const size_t lds = (size_t)W * (kVariants[v].mr + kVariants[v].mo) * sizeof(float4) +
-                       (size_t)W * nc * 64 * sizeof(float) + 2 * W * sizeof(float);
-    dim3 blk(64 * W), grd(grid);
-    switch (v) {
-    case 0: hipLaunchKernelGGL((pair_phase_kernel<2, 4, 16>), grd, blk, lds, st, P); break;
-    case 1: hipLaunchKernelGGL((pair_phase_kernel<2, 8, 32>), grd, blk, lds, st, P); break;
-    case 2: hipLaunchKernelGGL((pair_phase_kernel<3, 6, 24>), grd, blk, lds, st, P); break;
-    case 3: hipLaunchKernelGGL((pair_phase_kernel<3, 8, 32>), grd, blk, lds, st, P); break;
+    const int nw = pair_waves_per_block(P.N, G);
+    const size_t lds = (size_t)W * (MR + MO) * sizeof(float4) + (size_t)W * nc * 64 * sizeof(float) +
+                       2 * (size_t)W * nw * sizeof(float);
+    dim3 blk(64 * W * nw), grd(grid);
+    if (G == 4) hipLaunchKernelGGL((pair_phase_kernel<DIM, MR, MO, 4>), grd, blk, lds, st, P);
+    else if (G == 2) hipLaunchKernelGGL((pair_phase_kernel<DIM, MR, MO, 2>), grd, blk, lds, st, P);
+    else hipLaunchKernelGGL((pair_phase_kernel<DIM, MR, MO, 1>), grd, blk, lds, st, P);
+}
+
+bool pair_group_supported(int N, int W, int G)
+{
+    return (G == 1 || G == 2 || G == 4) && W >= 1 && W * pair_waves_per_block(N, G) <= 8;
+}
+
+hipError_t launch_pair_phase(const DevProblem& P, int W, int G, int grid, hipStream_t st)
+{
+    if (!pair_group_supported(P.N, W, G)) return hipErrorInvalidValue;
+    switch (pick_variant(P)) {
+    case 0: launch_pair_g<2, 4, 16>(P, W, G, grid, st); break;
+    case 1: launch_pair_g<2, 8, 32>(P, W, G, grid, st); break;
+    case 2: launch_pair_g<3, 6, 24>(P, W, G, grid, st); break;
+    case 3: launch_pair_g<3, 8, 32>(P, W, G, grid, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1702,14 +1948,17 @@ template <bool ADJ>
 static hipError_t launch_traj(const DevProblem& P, int obstacle_free, float* hq_save, const TrajAdjoint& TA,
                               hipStream_t st)
 {
-    dim3 g(P.n_scen), b(kTrajThreads);
+    dim3 g(P.n_scen);
     if (P.n_s <= 4 && P.n_u <= 2) {
+        const dim3 b(traj_threads(4, 2));
         hipLaunchKernelGGL((traj_phase_kernel<4, 2, ADJ>), g, b,
                            sizeof(float) * traj_dyn_floats(P.N, 4, 2, P.nc, ADJ), st, P, obstacle_free, hq_save, TA);
     } else if (P.n_s <= 12 && P.n_u <= 4) {
+        const dim3 b(traj_threads(12, 4));
         hipLaunchKernelGGL((traj_phase_kernel<12, 4, ADJ>), g, b,
                            sizeof(float) * traj_dyn_floats(P.N, 12, 4, P.nc, ADJ), st, P, obstacle_free, hq_save, TA);
     } else {
+        const dim3 b(traj_threads(16, 8));
         hipLaunchKernelGGL((traj_phase_kernel<16, 8, ADJ>), g, b,
                            sizeof(float) * traj_dyn_floats(P.N, 16, 8, P.nc, ADJ), st, P, obstacle_free, hq_save, TA);
     }

@@ -267,18 +267,20 @@ def test_full_run_trajectory(cadmm, name, iters):
     h.close()
 
 
-def test_batched_equals_separate(cadmm):
+@pytest.mark.parametrize("G", [1, 2, 4])
+def test_batched_equals_separate(cadmm, G):
     """Batched scenarios give bit-identical iterates to separate handles
-    (same kernels, same fixed reduction order)."""
+    (same kernels, same fixed reduction order), for each lane-group size."""
     prob = workloads.config_c4(n_scen=6, m_range=(10, 30))
-    say("[batched vs separate] 6 scenarios")
-    h = cadmm.Handle(prob, waves_per_group=4)
+    say(f"[batched vs separate] 6 scenarios, {G} lanes per pair")
+    W = 1 if G == 4 else 2
+    h = cadmm.Handle(prob, waves_per_group=W, lanes_per_pair=G)
     h.iterate(12)
     g = gpu_state(h)
     h.close()
     for s in range(6):
         q = workloads.select_scenarios(prob, [s])
-        hs = cadmm.Handle(q, waves_per_group=4)
+        hs = cadmm.Handle(q, waves_per_group=W, lanes_per_pair=G)
         hs.iterate(12)
         gs = gpu_state(hs)
         hs.close()
@@ -312,3 +314,25 @@ def test_far_obstacles_fixed_point(cadmm):
     # zeta = T at a certificate: zero up to the rounding of 1 + d'^T mu + gamma
     assert np.abs(g1["zeta"]).max() <= 1e-6 * (1.0 + g0["y"].max())
     h.close()
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_lane_groups_agree(cadmm, name):
+    """1, 2 or 4 lanes per pair QP: each launch shape, run 8 iterations from
+    the oracle's initial iterate, stays within the trajectory bar of the
+    oracle (the groups only reorder the sums of one pair QP)."""
+    prob = workloads.make(name)
+    say(f"[lane groups] {name}")
+    P, st0 = oracle_iterate(prob, 0)
+    st = {k: v.copy() for k, v in st0.items()}
+    P.run(st, 8)
+    for G in (1, 2, 4):
+        h = cadmm.Handle(prob, waves_per_group=1, lanes_per_pair=G)
+        assert h.launch_config()[2] == G
+        h.set_state(x=st0["x"], u=st0["u"], y=st0["y"], zeta=st0["zeta"], xi=st0["xi"])
+        h.iterate(8)
+        g = gpu_state(h)
+        h.close()
+        et = traj_error(g, st)
+        say(f"   G={G} traj err {et:.2e}")
+        assert et <= TOL_TRAJ

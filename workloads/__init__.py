@@ -254,6 +254,43 @@ def config_c4(seed=101, n_scen=256, m_range=(10, 80), f_range=(3, 12)):
     return _assemble_2d(parts, scen, N, dt, v, np.asarray(starts), sigma=1.0)
 
 
+def pair_batch_c4_shape(n_pairs, seed=7):
+    """A stateless batch of dual-update QP inputs of the batched 2D shape, for
+    streaming the stateless pair-QP entry point: per pair the 4.5 x 2 m
+    rectangle's 4 rows (0, a_k) with kappa = b, F ~ U{3..12} obstacle rows
+    (d', c) with unit normals at uniform angles and clearances
+    d' ~ U(-0.5, 6) m, and the row (1, 0); yhat >= 0 exponential, bhat near
+    (1, 0, 0). Returns row_ptr int32 [P+1], K [rows, 3], kappa, yhat [rows],
+    bhat [P, 3] (float32)."""
+    rng = np.random.default_rng(seed)
+    A_r, b_r = box_faces([2.25, 1.0])
+    F = rng.integers(3, 13, size=n_pairs)
+    n = 4 + F + 1
+    row_ptr = np.zeros(n_pairs + 1, np.int64)
+    np.cumsum(n, out=row_ptr[1:])
+    rows = int(row_ptr[-1])
+    K = np.zeros((rows, 3), np.float32)
+    kap = np.zeros(rows, np.float32)
+    start = row_ptr[:-1]
+    for k in range(4):
+        K[start + k, 1:] = A_r[k]
+        kap[start + k] = b_r[k]
+    # obstacle rows: row index start + 4 + j for j < F
+    pair_of_row = np.repeat(np.arange(n_pairs), n)
+    local = np.arange(rows) - start[pair_of_row]
+    obs_rows = np.nonzero((local >= 4) & (local < n[pair_of_row] - 1))[0]
+    ang = rng.uniform(0.0, 2 * np.pi, size=obs_rows.size)
+    K[obs_rows, 0] = rng.uniform(-0.5, 6.0, size=obs_rows.size)
+    K[obs_rows, 1] = np.cos(ang)
+    K[obs_rows, 2] = np.sin(ang)
+    K[row_ptr[1:] - 1, 0] = 1.0
+    yhat = rng.exponential(0.1, size=rows).astype(np.float32)
+    bhat = np.zeros((n_pairs, 3), np.float32)
+    bhat[:, 0] = 1.0 + rng.normal(0.0, 0.1, size=n_pairs)
+    bhat[:, 1:] = rng.normal(0.0, 0.1, size=(n_pairs, 2))
+    return row_ptr.astype(np.int32), K, kap, yhat, bhat
+
+
 def _assemble_2d(parts, scen_obstacles, N, dt, v, starts, sigma):
     ptr, A, b, off = _pack_parts(parts)
     obs_ptr, face_ptr, C, d = _pack_obstacles(scen_obstacles)
