@@ -76,7 +76,7 @@ def _declare(L):
     L.orc_admm_init.restype = ctypes.c_int
     L.orc_admm_init.argtypes = [PP, _dp, _dp, _dp, _dp, _dp]
     L.orc_scale_all.restype = ctypes.c_int
-    L.orc_scale_all.argtypes = [PP, _dp, _dp]
+    L.orc_scale_all.argtypes = [PP, _dp, _dp, _dp]
     L.orc_pair_phase.restype = ctypes.c_int
     L.orc_pair_phase.argtypes = [PP, _dp, _dp, _dp, _dp, _up, _dp]
     L.orc_traj_phase.restype = ctypes.c_int
@@ -213,13 +213,16 @@ class Problem:
             raise RuntimeError("oracle init: scale LP failed")
         return s
 
-    def scale_all(self, x):
+    def scale_all(self, x, with_y=False):
+        """alpha* of every pair at trajectory x; with_y: also the LP
+        certificates (lam*, mu*, max(alpha* - 1, 0)) in the layout of y."""
         N = self.st.N
         alpha = np.zeros(self.n_blocks * N)
-        bad = lib().orc_scale_all(self.ref, _d(_f64(x)), _d(alpha))
+        y = np.zeros(self.y_size) if with_y else None
+        bad = lib().orc_scale_all(self.ref, _d(_f64(x)), _d(alpha), _d(y) if with_y else None)
         if bad:
             raise RuntimeError("oracle scale LP failed")
-        return alpha
+        return (alpha, y) if with_y else alpha
 
     def pair_phase(self, state, active=None):
         y_out = state["y"].copy()

@@ -698,8 +698,10 @@ int orc_admm_init(const orc_problem *P, double *x, double *u, double *y, double 
     return bad;
 }
 
-/* Scale alpha* of every pair at the trajectory x (certificate check). */
-int orc_scale_all(const orc_problem *P, const double *x, double *alpha_out)
+/* Scale alpha* of every pair at the trajectory x (certificate check), and,
+   when y_out is not NULL, the LP certificates (lam*, mu*, max(alpha* - 1, 0))
+   in the layout of y. */
+int orc_scale_all(const orc_problem *P, const double *x, double *alpha_out, double *y_out)
 {
     int N = P->N, dim = P->dim, nb = count_blocks(P), bad = 0;
     orc_block *B = (orc_block *)malloc(sizeof(orc_block) * (nb > 0 ? nb : 1));
@@ -713,6 +715,12 @@ int orc_scale_all(const orc_problem *P, const double *x, double *alpha_out)
         bad |= (orc_scale_lp(dim, q->nr, P->part_A + (size_t)P->part_face_ptr[q->i] * dim,
                              P->part_b + P->part_face_ptr[q->i], q->no, Cp, dp,
                              &alpha_out[pidx], xs, lam, mu, NULL) != 0);
+        if (y_out) {
+            double *yb = y_out + q->yoff + (t - 1);
+            for (int k = 0; k < q->nr; ++k) yb[k * N] = lam[k];
+            for (int l = 0; l < q->no; ++l) yb[(q->nr + l) * N] = mu[l];
+            yb[(q->n - 1) * N] = alpha_out[pidx] > 1.0 ? alpha_out[pidx] - 1.0 : 0.0;
+        }
     }
     free(B);
     return bad;

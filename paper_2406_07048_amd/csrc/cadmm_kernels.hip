@@ -883,32 +883,222 @@ __host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bo
 }
 
 // Fixed-order sum of the float4 src[w * stride], w = w0..w1-1, with eight
-// independent partial sums (w - w0 mod 8), so that many loads are in flight.
+// independent partial sums (w - w0 mod 8). Loads are issued sixteen at a
+// time ahead of their use (the scheduling barrier keeps the compiler from
+// interleaving each load with its add, which serialises the L2 round trips).
 __device__ __forceinline__ float4 strided_sum4(const float4* src, size_t stride, int w0, int w1)
 {
     float4 a[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) a[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     int w = w0;
-    for (; w + 8 <= w1; w += 8) {
+    for (; w + 16 <= w1; w += 16) {
+        float4 v[16];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float4 v = src[(size_t)(w + q) * stride];
-            a[q].x += v.x; a[q].y += v.y; a[q].z += v.z; a[q].w += v.w;
+        for (int q = 0; q < 16; ++q) v[q] = src[(size_t)(w + q) * stride];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            a[q & 7].x += v[q].x; a[q & 7].y += v[q].y; a[q & 7].z += v[q].z; a[q & 7].w += v[q].w;
         }
     }
+    if (w + 8 <= w1) {
+        float4 v[8];
 #pragma unroll
-    for (int q = 0; q < 7; ++q)
-        if (w + q < w1) {
-            const float4 v = src[(size_t)(w + q) * stride];
-            a[q].x += v.x; a[q].y += v.y; a[q].z += v.z; a[q].w += v.w;
+        for (int q = 0; q < 8; ++q) v[q] = src[(size_t)(w + q) * stride];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            a[q].x += v[q].x; a[q].y += v[q].y; a[q].z += v[q].z; a[q].w += v[q].w;
         }
+        w += 8;
+    }
+    {
+        float4 v[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q)
+            v[q] = w + q < w1 ? src[(size_t)(w + q) * stride] : make_float4(0.f, 0.f, 0.f, 0.f);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < 7; ++q)
+            if (w + q < w1) {
+                a[q].x += v[q].x; a[q].y += v[q].y; a[q].z += v[q].z; a[q].w += v[q].w;
+            }
+    }
     float4 r;
     r.x = ((a[0].x + a[1].x) + (a[2].x + a[3].x)) + ((a[4].x + a[5].x) + (a[6].x + a[7].x));
     r.y = ((a[0].y + a[1].y) + (a[2].y + a[3].y)) + ((a[4].y + a[5].y) + (a[6].y + a[7].y));
     r.z = ((a[0].z + a[1].z) + (a[2].z + a[3].z)) + ((a[4].z + a[5].z) + (a[6].z + a[7].z));
     r.w = ((a[0].w + a[1].w) + (a[2].w + a[3].w)) + ((a[4].w + a[5].w) + (a[6].w + a[7].w));
     return r;
+}
+
+// Riccati sweep and rollout for 4 states and 2 inputs, held in the registers
+// of one wave: lane (i, j) = 4 i + j of each row of 16 lanes owns entry
+// (i, j) of the 4 x 4 blocks (rows 1-3 of the wave repeat row 0). Row i of a
+// block reaches lane (i, j) by quad broadcasts, column j by rotations of the
+// row by 4, 8 and 12 lanes, so the sweep needs no barrier. Per step, with P = P_{t+1}:
+//   (a) PA = P A, PAT = (P A)^T (P symmetric), PB_{i, j mod 2} = (P B), w = P f_t + p;
+//   (b) Qxx = H_t + A^T PA and its transpose, Qux_{i mod 2, j} = (B^T PA),
+//       Qux^T, Quu = 2Q_u + B^T PB, qu = r_t + B^T w, qx = h_t + A^T w;
+//   (c) K = -Quu^{-1} Qux, k = -Quu^{-1} qu (2 x 2 inverse by its adjugate),
+//       P_t = Qxx - Qux^T Quu^{-1} Qux averaged with its transpose,
+//       p_t = qx - Qux^T Quu^{-1} qu.
+// The sums over rows run in the lane's rotation order, so lanes that hold
+// the same entry may differ in the last bits; P_t is made exactly symmetric
+// by one ds_bpermute per step. The step-dependent LDS terms
+// of step t - 1 are read while step t computes. Gains go to Kall[t][2][5];
+// the rollout then keeps dx_r in lane r (quads repeat) and writes dx
+// (forward: dX[t][4], du in dU[t][2]; reverse: w in W[t + 1][4]).
+template <bool ADJ>
+__device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, const float* Q2, const float* R2,
+                                                const int* hmap, const int* gmap, const float* Hq, const float* qr,
+                                                const float* rin, const float* off, float* Kall, float* dX, float* dU,
+                                                float* W, int N, int nc, float x0dev)
+{
+    const int lane = threadIdx.x & 15;
+    const int i = lane >> 2, j = lane & 3, a = i & 1, b = j & 1;
+    int km[4];
+    km[0] = i;
+    km[1] = row_ror_i<4>(i);
+    km[2] = row_ror_i<8>(i);
+    km[3] = row_ror_i<12>(i);
+    float Acol[4], Bcol[4], Arot[4], Brot[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        Acol[k] = A[k * 4 + j];
+        Bcol[k] = B[k * 2 + b];
+        Arot[k] = A[km[k] * 4 + i];
+        Brot[k] = B[km[k] * 2 + a];
+    }
+    const float q2ij = Q2[i * 4 + j], q2ji = Q2[j * 4 + i], r2ab = R2[a * 2 + b];
+    const int hmij = hmap[i * 4 + j], hmji = hmap[j * 4 + i], gmi = ADJ ? -1 : gmap[i];
+    const int tsrc = (((int)threadIdx.x & ~15) | (i <= j ? lane : j * 4 + i)) << 2;   // ds_bpermute byte address
+    float Pv = q2ij + (hmij >= 0 ? Hq[(N - 1) * nc + hmij] : 0.f);
+    float pv = qr[(N - 1) * 4 + i] + (gmi >= 0 ? Hq[(N - 1) * nc + gmi] : 0.f);
+    // step-dependent terms of step t: H_{t-1} (i, j) and (j, i), h_{t-1}(i), f_t, r_t
+    float nHij = 0.f, nHji = 0.f, nh = 0.f, nf[4], nr;
+    auto fetch = [&](int t) {
+        if (t >= 1) {
+            const float* hq = Hq + (t - 1) * nc;
+            nHij = q2ij + (hmij >= 0 ? hq[hmij] : 0.f);
+            nHji = q2ji + (hmji >= 0 ? hq[hmji] : 0.f);
+            nh = qr[(t - 1) * 4 + i] + (gmi >= 0 ? hq[gmi] : 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nf[k] = off[t * 4 + k];
+        nr = rin[t * 2 + a];
+    };
+    fetch(N - 1);
+    for (int t = N - 1; t >= 0; --t) {
+        const float Hij = nHij, Hji = nHji, h = nh, r = nr;
+        float f[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f[k] = nf[k];
+        if (t >= 1) fetch(t - 1);
+        // (a)
+        const float Pb[4] = {quad_bcast<0>(Pv), quad_bcast<1>(Pv), quad_bcast<2>(Pv), quad_bcast<3>(Pv)};
+        const float Pr[4] = {Pv, row_ror<4>(Pv), row_ror<8>(Pv), row_ror<12>(Pv)};
+        float PA = 0.f, PAT = 0.f, PB = 0.f, w = pv;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            PA += Pb[k] * Acol[k];
+            PB += Pb[k] * Bcol[k];
+            w += Pb[k] * f[k];
+            PAT += Pr[k] * Arot[k];
+        }
+        // (b)
+        const float PAr[4] = {PA, row_ror<4>(PA), row_ror<8>(PA), row_ror<12>(PA)};
+        const float PBr[4] = {PB, row_ror<4>(PB), row_ror<8>(PB), row_ror<12>(PB)};
+        const float wr[4] = {w, row_ror<4>(w), row_ror<8>(w), row_ror<12>(w)};
+        float Qux = 0.f, Quu = r2ab, qu = r;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            Qux += Brot[k] * PAr[k];
+            Quu += Brot[k] * PBr[k];
+            qu += Brot[k] * wr[k];
+        }
+        // (c) Quu entries from the lanes of the other row / column parity
+        const float xo = dpp_xor1(Quu);
+        const float y = row_ror<4>(Quu), yo = row_ror<4>(xo);
+        const float Q00 = a ? (b ? yo : y) : (b ? xo : Quu);
+        const float Q11 = a ? (b ? Quu : xo) : (b ? y : yo);
+        const float Q01 = a ? (b ? y : yo) : (b ? Quu : xo);
+        const float idet = __builtin_amdgcn_rcpf(Q00 * Q11 - Q01 * Q01);
+        const float I00 = Q11 * idet, I11 = Q00 * idet, I01 = -Q01 * idet;
+        const float uxr = row_ror<4>(Qux);
+        const float U0j = a ? uxr : Qux, U1j = a ? Qux : uxr;
+        const float G0j = I00 * U0j + I01 * U1j, G1j = I01 * U0j + I11 * U1j;
+        const float qur = row_ror<4>(qu);
+        const float qu0 = a ? qur : qu, qu1 = a ? qu : qur;
+        const float g0 = I00 * qu0 + I01 * qu1, g1 = I01 * qu0 + I11 * qu1;
+        float* Kt = Kall + t * 10;
+        if (threadIdx.x < 4) {
+            Kt[j] = -G0j;
+            Kt[5 + j] = -G1j;
+            if (j == 0) {
+                Kt[4] = -g0;
+                Kt[9] = -g1;
+            }
+        }
+        if (t >= 1) {
+            float Qxx = Hij, qx = h, QxxT = Hji, QuxT = 0.f;
+            const float PATb[4] = {quad_bcast<0>(PAT), quad_bcast<1>(PAT), quad_bcast<2>(PAT), quad_bcast<3>(PAT)};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                Qxx += Arot[k] * PAr[k];
+                qx += Arot[k] * wr[k];
+                QxxT += Acol[k] * PATb[k];
+                QuxT += Bcol[k] * PATb[k];
+            }
+            const float U0i = quad_bcast<0>(QuxT), U1i = quad_bcast<1>(QuxT);
+            const float G0i = I00 * U0i + I01 * U1i, G1i = I01 * U0i + I11 * U1i;
+            const float pij = Qxx - (U0i * G0j + U1i * G1j);
+            const float pji = QxxT - (U0j * G0i + U1j * G1i);
+            // exact symmetry: lane (i, j), i > j, takes the value of lane (j, i)
+            // (an antisymmetric part would not be removed by the averaging
+            // and grows along the sweep)
+            Pv = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
+                     tsrc, __builtin_bit_cast(int, 0.5f * (pij + pji))));
+            pv = qx - (U0i * g0 + U1i * g1);
+        }
+    }
+    // rollout: lane r = j of each quad holds dx_r
+    float Ar[4], Br[2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Ar[k] = A[j * 4 + k];
+    Br[0] = B[j * 2];
+    Br[1] = B[j * 2 + 1];
+    float xv = x0dev;
+    float nK[10], nft;
+    auto fetchK = [&](int t) {
+#pragma unroll
+        for (int q = 0; q < 10; ++q) nK[q] = Kall[t * 10 + q];
+        nft = off[t * 4 + j];
+    };
+    fetchK(0);
+    for (int t = 0; t < N; ++t) {
+        float K[10];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) K[q] = nK[q];
+        const float ft = nft;
+        if (t + 1 < N) fetchK(t + 1);
+        const float xb[4] = {quad_bcast<0>(xv), quad_bcast<1>(xv), quad_bcast<2>(xv), quad_bcast<3>(xv)};
+        float u0 = K[4], u1 = K[9], xn = ft;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            u0 += K[k] * xb[k];
+            u1 += K[5 + k] * xb[k];
+            xn += Ar[k] * xb[k];
+        }
+        xn += Br[0] * u0 + Br[1] * u1;
+        if (threadIdx.x < 4) {
+            if (ADJ) W[(t + 1) * 4 + j] = xn;
+            else dX[t * 4 + j] = xn;
+            if (!ADJ && j < 2) dU[t * 2 + j] = j == 0 ? u0 : u1;
+        }
+        xv = xn;
+    }
 }
 
 // Trajectory QP of one scenario per workgroup. State/input sizes are padded
@@ -1089,6 +1279,24 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         }
     }
     __syncthreads();
+    float* xo = P.x + (size_t)s * (N + 1) * ns;
+    float* uo = P.u + (size_t)s * N * nu;
+    float* dX = ADJ ? wl : qr;             // forward: dx_t at (t-1) * NS, t = 1..N; reverse: w_t at t * NS
+    float* dU = rin;                       // forward: du_t at t * NU
+    if constexpr (NS == 4 && NU == 2) {
+        // 2-3. the sweep and the rollout in the registers of wave 0
+        if (tid < 64) {
+            const int r = tid & 3;
+            float x0d = 0.f;
+            if (!ADJ && r < ns) {
+                const float x0v = P.x0[(size_t)s * ns + r];
+                x0d = dev ? x0v - xo[r] : x0v;
+            }
+            if (ADJ && tid < 4) wl[tid] = 0.f;
+            riccati_regs_42<ADJ>(A, B, Q2, R2, hmap, gmap, Hq, qr, rin, off, Kall, dX, dU, wl, N, nc, x0d);
+        }
+        __syncthreads();
+    } else {
     // 2. backward Riccati sweep, V_t(x) = 1/2 x^T P x + p^T x, P_N = H_N.
     //    Every phase is one strided dot product per thread, so a wave never
     //    runs several output types one after the other:
@@ -1139,9 +1347,21 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
             c_j = NS;
         }
     }
+    // the (b) bias of this thread: its constant part in a register, the
+    // step-dependent part read at the top of each step so that its LDS
+    // latency hides under phase (a)
+    float b_q2 = 0.f;
+    int b_hm = -1;
+    if (b_type == 0) b_q2 = R2[b_i * NU + b_j];
+    else if (b_type == 3) { b_q2 = Q2[b_i * NS + b_j]; b_hm = hmap[b_i * NS + b_j]; }
+    else if (b_type == 4) b_hm = ADJ ? -1 : gmap[b_i];
     __syncthreads();
     for (int t = N - 1; t >= 0; --t) {
         const float* ft = off + t * NS;
+        float bias = b_q2;
+        if (b_type == 2) bias = rin[t * NU + b_i];
+        else if (b_type == 3 && t >= 1) bias += b_hm >= 0 ? Hq[(t - 1) * nc + b_hm] : 0.f;
+        else if (b_type == 4 && t >= 1) bias = qr[(t - 1) * NS + b_i] + (b_hm >= 0 ? Hq[(t - 1) * nc + b_hm] : 0.f);
         if (!kFold) {
             // (a)
             if (a_type >= 0) {
@@ -1161,12 +1381,6 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
             // X: column b_i of B (types 0-2) or of A (types 3-4)
             const float* X = b_type <= 2 ? B + b_i : A + b_i;
             const int xs = b_type <= 2 ? NU : NS;
-            float bias;
-            if (b_type == 0) bias = R2[b_i * NU + b_j];
-            else if (b_type == 1) bias = 0.f;
-            else if (b_type == 2) bias = rin[t * NU + b_i];
-            else if (b_type == 3) bias = Q2[b_i * NS + b_j] + (hmap[b_i * NS + b_j] >= 0 ? Hq[(t - 1) * nc + hmap[b_i * NS + b_j]] : 0.f);
-            else bias = lin(t - 1, b_i);
             float acc = bias;
             if (kFold) {
                 // Y column j of P B, P A or the vector P f_t + p, formed here
@@ -1212,9 +1426,9 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
                 float d = L[j * NU + j];
 #pragma unroll
                 for (int k2 = 0; k2 < j; ++k2) d -= L[j * NU + k2] * L[j * NU + k2];
-                d = sqrtf(fmaxf(d, 1e-30f));
-                L[j * NU + j] = d;
-                const float id = 1.f / d;
+                // v_rsq_f32 (about 1 ulp); the diagonal keeps 1 / l_jj
+                const float id = __builtin_amdgcn_rsqf(fmaxf(d, 1e-30f));
+                L[j * NU + j] = id;
 #pragma unroll
                 for (int i = j + 1; i < NU; ++i) {
                     float v = L[i * NU + j];
@@ -1232,14 +1446,14 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
                     float v = r[i];
 #pragma unroll
                     for (int k2 = 0; k2 < i; ++k2) v -= L[i * NU + k2] * r[k2];
-                    r[i] = v / L[i * NU + i];
+                    r[i] = v * L[i * NU + i];
                 }
 #pragma unroll
                 for (int i = NU - 1; i >= 0; --i) {
                     float v = r[i];
 #pragma unroll
                     for (int k2 = i + 1; k2 < NU; ++k2) v -= L[k2 * NU + i] * r[k2];
-                    r[i] = v / L[i * NU + i];
+                    r[i] = v * L[i * NU + i];
                 }
             };
             float Ki[NU], Kj[NU];
@@ -1277,10 +1491,6 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     //    (rows of A and B in registers), threads NS..NS+NU-1 the inputs. The
     //    deviations stay in LDS (forward: over qr and rin, dead after the
     //    sweep; reverse: w in wl) and are written out by one parallel pass.
-    float* xo = P.x + (size_t)s * (N + 1) * ns;
-    float* uo = P.u + (size_t)s * N * nu;
-    float* dX = ADJ ? wl : qr;             // forward: dx_t at (t-1) * NS, t = 1..N; reverse: w_t at t * NS
-    float* dU = rin;                       // forward: du_t at t * NU
     float Ar[NS], Br[NU];
     const int row = tid < NS ? tid : 0;
 #pragma unroll
@@ -1330,6 +1540,7 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
             }
         }
         __syncthreads();
+    }
     }
     if (!ADJ) {
         // x_t = x^k_t + dx_t (t = 1..N), u_t = u^k_t + du_t, x_0 = x0
