@@ -1,0 +1,797 @@
+// gfx950 kernels of the trajectory-QP step of the ADMM collision-avoidance
+// path (arXiv 2406.07048, Sec. IV-B state update): per-step sums of the pair
+// contributions, the backward Riccati sweep and the forward rollout, in
+// forward mode and as the adjoint LQ of the reverse pass.
+#include "cadmm_device.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace cadmm {
+
+// ------------------------------------------------------------------------
+// ADMM step 2: trajectory QP by a backward Riccati sweep and forward
+// rollout; one workgroup per scenario. The QP is solved in deviation
+// coordinates about the current iterate, dx = x - x^k, du = u - u^k: stage
+// cost 1/2 dx^T H_t dx + g_t^T dx with H_t = 2 Q_s + sum_ij sigma J^T J and
+// g_t = 2 Q_s (x^k_t - xref_t) + sum_ij sigma J^T e (pose block), input cost
+// 1/2 du^T (2 Q_u) du + (2 Q_u u^k_t)^T du, dynamics dx_{t+1} = A dx_t +
+// B du_t + f_t with the defect f_t = A x^k_t + B u^k_t + c - x^k_{t+1} formed
+// in FP64. This is the same QP as in absolute coordinates, without the
+// cancellation of sigma J^T J q^k against the positions of the scene.
+// The obstacle-free solve (initial iterate) uses the base point 0.
+//
+// Reverse mode (ADJ): the same sweep solves the adjoint LQ of one forward
+// trajectory QP. With xbar_t, ubar_t the cotangents of its solution (x, u),
+// the vector abar = Hs^{-1} (ubar + sum_t M_t^T xbar_t) of the condensed
+// problem (Hs its input Hessian, M_t the input-to-state map) is the minimiser
+// of the same LQ with h_t = -xbar_t, an input term -ubar_t, c = 0 and
+// x_0 = 0, and its state trajectory w_t = M_t abar is what the stage
+// adjoints need (Hbar_t = -(w_t x_t^T + x_t w_t^T) / 2, hbar_t = -w_t). The
+// cotangent of x_0 is sum_t (A^T)^t (xbar_t - H_t w_t), accumulated by a
+// Horner sweep after the rollout.
+// ------------------------------------------------------------------------
+
+// Threads of the trajectory kernel: one output per thread in every phase of
+// the sweep (512 for the 16/8 padding, 256 otherwise).
+__host__ __device__ constexpr int traj_threads(int NS, int NU)
+{
+    return (NS * NS + NS * NU + NS > 256 || NU * NU + NU * NS + NU + NS * NS + NS > 256) ? 512 : 256;
+}
+
+// Floats of the gains region, which first holds the staged trajectory
+// (x and x_ref over t = 0..N, u over t = 0..N-1, padded to NS / NU).
+__host__ __device__ inline int traj_gain_floats(int N, int NS, int NU)
+{
+    const int gains = N * NU * (NS + 1), stage = 2 * (N + 1) * NS + N * NU;
+    return gains > stage ? gains : stage;
+}
+
+// Dynamic LDS floats of the trajectory kernel for padded sizes NS, NU
+// (reverse mode adds the w trajectory).
+__host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bool adj)
+{
+    return N * nc + N * NS + traj_gain_floats(N, NS, NU) + N * NU + N * NS + (adj ? (N + 1) * NS : 0);
+}
+
+// Fixed-order sum of the float4 src[w * stride], w = w0..w1-1, with eight
+// independent partial sums (w - w0 mod 8). Loads are issued sixteen at a
+// time ahead of their use (the scheduling barrier keeps the compiler from
+// interleaving each load with its add, which serialises the L2 round trips).
+__device__ __forceinline__ float4 strided_sum4(const float4* src, size_t stride, int w0, int w1)
+{
+    float4 a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    int w = w0;
+    for (; w + 16 <= w1; w += 16) {
+        float4 v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = src[(size_t)(w + q) * stride];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            a[q & 7].x += v[q].x; a[q & 7].y += v[q].y; a[q & 7].z += v[q].z; a[q & 7].w += v[q].w;
+        }
+    }
+    if (w + 8 <= w1) {
+        float4 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = src[(size_t)(w + q) * stride];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            a[q].x += v[q].x; a[q].y += v[q].y; a[q].z += v[q].z; a[q].w += v[q].w;
+        }
+        w += 8;
+    }
+    {
+        float4 v[7];
+#pragma unroll
+        for (int q = 0; q < 7; ++q)
+            v[q] = w + q < w1 ? src[(size_t)(w + q) * stride] : make_float4(0.f, 0.f, 0.f, 0.f);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < 7; ++q)
+            if (w + q < w1) {
+                a[q].x += v[q].x; a[q].y += v[q].y; a[q].z += v[q].z; a[q].w += v[q].w;
+            }
+    }
+    float4 r;
+    r.x = ((a[0].x + a[1].x) + (a[2].x + a[3].x)) + ((a[4].x + a[5].x) + (a[6].x + a[7].x));
+    r.y = ((a[0].y + a[1].y) + (a[2].y + a[3].y)) + ((a[4].y + a[5].y) + (a[6].y + a[7].y));
+    r.z = ((a[0].z + a[1].z) + (a[2].z + a[3].z)) + ((a[4].z + a[5].z) + (a[6].z + a[7].z));
+    r.w = ((a[0].w + a[1].w) + (a[2].w + a[3].w)) + ((a[4].w + a[5].w) + (a[6].w + a[7].w));
+    return r;
+}
+
+// Riccati sweep and rollout for 4 states and 2 inputs, held in the registers
+// of one wave: lane (i, j) = 4 i + j of each row of 16 lanes owns entry
+// (i, j) of the 4 x 4 blocks (rows 1-3 of the wave repeat row 0). Row i of a
+// block reaches lane (i, j) by quad broadcasts, column j by rotations of the
+// row by 4, 8 and 12 lanes, so the sweep needs no barrier. Per step, with P = P_{t+1}:
+//   (a) PA = P A, PAT = (P A)^T (P symmetric), PB_{i, j mod 2} = (P B), w = P f_t + p;
+//   (b) Qxx = H_t + A^T PA and its transpose, Qux_{i mod 2, j} = (B^T PA),
+//       Qux^T, Quu = 2Q_u + B^T PB, qu = r_t + B^T w, qx = h_t + A^T w;
+//   (c) K = -Quu^{-1} Qux, k = -Quu^{-1} qu (2 x 2 inverse by its adjugate),
+//       P_t = Qxx - Qux^T Quu^{-1} Qux averaged with its transpose,
+//       p_t = qx - Qux^T Quu^{-1} qu.
+// The sums over rows run in the lane's rotation order, so lanes that hold
+// the same entry may differ in the last bits; P_t is made exactly symmetric
+// by one ds_bpermute per step. The step-dependent LDS terms
+// of step t - 1 are read while step t computes. Gains go to Kall[t][2][5];
+// the rollout then keeps dx_r in lane r (quads repeat) and writes dx
+// (forward: dX[t][4], du in dU[t][2]; reverse: w in W[t + 1][4]).
+template <bool ADJ>
+__device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, const float* Q2, const float* R2,
+                                                const int* hmap, const int* gmap, const float* Hq, const float* qr,
+                                                const float* rin, const float* off, float* Kall, float* dX, float* dU,
+                                                float* W, int N, int nc, float x0dev)
+{
+    const int lane = threadIdx.x & 15;
+    const int i = lane >> 2, j = lane & 3, a = i & 1, b = j & 1;
+    int km[4];
+    km[0] = i;
+    km[1] = row_ror_i<4>(i);
+    km[2] = row_ror_i<8>(i);
+    km[3] = row_ror_i<12>(i);
+    float Acol[4], Bcol[4], Arot[4], Brot[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        Acol[k] = A[k * 4 + j];
+        Bcol[k] = B[k * 2 + b];
+        Arot[k] = A[km[k] * 4 + i];
+        Brot[k] = B[km[k] * 2 + a];
+    }
+    const float q2ij = Q2[i * 4 + j], q2ji = Q2[j * 4 + i], r2ab = R2[a * 2 + b];
+    const int hmij = hmap[i * 4 + j], hmji = hmap[j * 4 + i], gmi = ADJ ? -1 : gmap[i];
+    const int tsrc = (((int)threadIdx.x & ~15) | (i <= j ? lane : j * 4 + i)) << 2;   // ds_bpermute byte address
+    float Pv = q2ij + (hmij >= 0 ? Hq[(N - 1) * nc + hmij] : 0.f);
+    float pv = qr[(N - 1) * 4 + i] + (gmi >= 0 ? Hq[(N - 1) * nc + gmi] : 0.f);
+    // step-dependent terms of step t: H_{t-1} (i, j) and (j, i), h_{t-1}(i), f_t, r_t
+    float nHij = 0.f, nHji = 0.f, nh = 0.f, nf[4], nr;
+    auto fetch = [&](int t) {
+        if (t >= 1) {
+            const float* hq = Hq + (t - 1) * nc;
+            nHij = q2ij + (hmij >= 0 ? hq[hmij] : 0.f);
+            nHji = q2ji + (hmji >= 0 ? hq[hmji] : 0.f);
+            nh = qr[(t - 1) * 4 + i] + (gmi >= 0 ? hq[gmi] : 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) nf[k] = off[t * 4 + k];
+        nr = rin[t * 2 + a];
+    };
+    fetch(N - 1);
+    for (int t = N - 1; t >= 0; --t) {
+        const float Hij = nHij, Hji = nHji, h = nh, r = nr;
+        float f[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f[k] = nf[k];
+        if (t >= 1) fetch(t - 1);
+        // (a)
+        const float Pb[4] = {quad_bcast<0>(Pv), quad_bcast<1>(Pv), quad_bcast<2>(Pv), quad_bcast<3>(Pv)};
+        const float Pr[4] = {Pv, row_ror<4>(Pv), row_ror<8>(Pv), row_ror<12>(Pv)};
+        float PA = 0.f, PAT = 0.f, PB = 0.f, w = pv;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            PA += Pb[k] * Acol[k];
+            PB += Pb[k] * Bcol[k];
+            w += Pb[k] * f[k];
+            PAT += Pr[k] * Arot[k];
+        }
+        // (b)
+        const float PAr[4] = {PA, row_ror<4>(PA), row_ror<8>(PA), row_ror<12>(PA)};
+        const float PBr[4] = {PB, row_ror<4>(PB), row_ror<8>(PB), row_ror<12>(PB)};
+        const float wr[4] = {w, row_ror<4>(w), row_ror<8>(w), row_ror<12>(w)};
+        float Qux = 0.f, Quu = r2ab, qu = r;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            Qux += Brot[k] * PAr[k];
+            Quu += Brot[k] * PBr[k];
+            qu += Brot[k] * wr[k];
+        }
+        // (c) Quu entries from the lanes of the other row / column parity
+        const float xo = dpp_xor1(Quu);
+        const float y = row_ror<4>(Quu), yo = row_ror<4>(xo);
+        const float Q00 = a ? (b ? yo : y) : (b ? xo : Quu);
+        const float Q11 = a ? (b ? Quu : xo) : (b ? y : yo);
+        const float Q01 = a ? (b ? y : yo) : (b ? Quu : xo);
+        const float idet = __builtin_amdgcn_rcpf(Q00 * Q11 - Q01 * Q01);
+        const float I00 = Q11 * idet, I11 = Q00 * idet, I01 = -Q01 * idet;
+        const float uxr = row_ror<4>(Qux);
+        const float U0j = a ? uxr : Qux, U1j = a ? Qux : uxr;
+        const float G0j = I00 * U0j + I01 * U1j, G1j = I01 * U0j + I11 * U1j;
+        const float qur = row_ror<4>(qu);
+        const float qu0 = a ? qur : qu, qu1 = a ? qu : qur;
+        const float g0 = I00 * qu0 + I01 * qu1, g1 = I01 * qu0 + I11 * qu1;
+        float* Kt = Kall + t * 10;
+        if (threadIdx.x < 4) {
+            Kt[j] = -G0j;
+            Kt[5 + j] = -G1j;
+            if (j == 0) {
+                Kt[4] = -g0;
+                Kt[9] = -g1;
+            }
+        }
+        if (t >= 1) {
+            float Qxx = Hij, qx = h, QxxT = Hji, QuxT = 0.f;
+            const float PATb[4] = {quad_bcast<0>(PAT), quad_bcast<1>(PAT), quad_bcast<2>(PAT), quad_bcast<3>(PAT)};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                Qxx += Arot[k] * PAr[k];
+                qx += Arot[k] * wr[k];
+                QxxT += Acol[k] * PATb[k];
+                QuxT += Bcol[k] * PATb[k];
+            }
+            const float U0i = quad_bcast<0>(QuxT), U1i = quad_bcast<1>(QuxT);
+            const float G0i = I00 * U0i + I01 * U1i, G1i = I01 * U0i + I11 * U1i;
+            const float pij = Qxx - (U0i * G0j + U1i * G1j);
+            const float pji = QxxT - (U0j * G0i + U1j * G1i);
+            // exact symmetry: lane (i, j), i > j, takes the value of lane (j, i)
+            // (an antisymmetric part would not be removed by the averaging
+            // and grows along the sweep)
+            Pv = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
+                     tsrc, __builtin_bit_cast(int, 0.5f * (pij + pji))));
+            pv = qx - (U0i * g0 + U1i * g1);
+        }
+    }
+    // rollout: lane r = j of each quad holds dx_r
+    float Ar[4], Br[2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Ar[k] = A[j * 4 + k];
+    Br[0] = B[j * 2];
+    Br[1] = B[j * 2 + 1];
+    float xv = x0dev;
+    float nK[10], nft;
+    auto fetchK = [&](int t) {
+#pragma unroll
+        for (int q = 0; q < 10; ++q) nK[q] = Kall[t * 10 + q];
+        nft = off[t * 4 + j];
+    };
+    fetchK(0);
+    for (int t = 0; t < N; ++t) {
+        float K[10];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) K[q] = nK[q];
+        const float ft = nft;
+        if (t + 1 < N) fetchK(t + 1);
+        const float xb[4] = {quad_bcast<0>(xv), quad_bcast<1>(xv), quad_bcast<2>(xv), quad_bcast<3>(xv)};
+        float u0 = K[4], u1 = K[9], xn = ft;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            u0 += K[k] * xb[k];
+            u1 += K[5 + k] * xb[k];
+            xn += Ar[k] * xb[k];
+        }
+        xn += Br[0] * u0 + Br[1] * u1;
+        if (threadIdx.x < 4) {
+            if (ADJ) W[(t + 1) * 4 + j] = xn;
+            else dX[t * 4 + j] = xn;
+            if (!ADJ && j < 2) dU[t * 2 + j] = j == 0 ? u0 : u1;
+        }
+        xv = xn;
+    }
+}
+
+// Trajectory QP of one scenario per workgroup. State/input sizes are padded
+// to the compile-time NS >= n_s, NU >= n_u with zero dynamics rows/columns
+// and an identity input-cost block, so every small product unrolls.
+template <int NS, int NU, bool ADJ>
+__global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevProblem P, int obstacle_free,
+                                                                          float* hq_save, TrajAdjoint TA)
+{
+    constexpr int TT = traj_threads(NS, NU);
+    constexpr int NSU = NS + 1;
+    __shared__ float A[NS * NS], B[NS * NU], Q2[NS * NS], R2[NU * NU], cdyn[NS];
+    __shared__ int hmap[NS * NS], gmap[NS], pmap[NS];
+    __shared__ float Pm[NS * NS], pv[NS], PA[NS * NS], PB[NS * NU], wv[NS];
+    __shared__ float Quu[NU * NU], Qux[NU * NS], qu[NU], Qxx[NS * NS], qx[NS];
+    __shared__ float xbuf[2][NS];
+    extern __shared__ float dyn[];
+    const int s = blockIdx.x;
+    if (!ADJ && !obstacle_free && P.done[s]) return;
+    const int tid = threadIdx.x;
+    const int ns = P.n_s, nu = P.n_u, N = P.N, nq = P.nq, nc = P.nc;
+    // deviation coordinates about the current iterate (else base point 0)
+    const bool dev = !ADJ && !obstacle_free;
+    float* Hq = dyn;                       // [N][nc] reduced contributions
+    float* qr = Hq + N * nc;               // [N][NS] stage gradients g_t (reverse: -xbar_t), t = 1..N
+    float* Kall = qr + N * NS;             // [N][NU][NS+1] gains [K | k]
+    float* sx = Kall;                      // staged before the sweep: [N+1][NS] x (reverse: x^K)
+    float* sxr = sx + (N + 1) * NS;        //   [N+1][NS] x_ref
+    float* su = sxr + (N + 1) * NS;        //   [N][NU] u (reverse: u^K)
+    float* rin = Kall + traj_gain_floats(N, NS, NU);   // [N][NU] input gradients 2 Q_u u^k_t (reverse: -ubar_t)
+    float* off = rin + N * NU;             // [N][NS] dynamics offsets f_t (c when the base is 0)
+    float* wl = off + N * NS;              // reverse: [N+1][NS] w_t
+
+    // 0. padded model and cost, pose-coordinate maps
+    for (int e = tid; e < NS * NS; e += TT) {
+        const int i = e / NS, j = e % NS;
+        const bool in = i < ns && j < ns;
+        A[e] = in ? P.A_dyn[i * ns + j] : 0.f;
+        Q2[e] = in ? 2.f * P.Q_s[i * ns + j] : 0.f;
+        int ci = -1, cj = -1;
+        for (int a = 0; a < nq; ++a) {
+            const int qa = a < P.dim ? P.pos_idx[a] : P.att_idx[a - P.dim];
+            if (qa == i) ci = a;
+            if (qa == j) cj = a;
+        }
+        int m = -1;
+        if (in && ci >= 0 && cj >= 0) {
+            const int a = ci < cj ? ci : cj, b2 = ci < cj ? cj : ci;
+            m = a * nq - a * (a - 1) / 2 + (b2 - a);     // packed upper-triangle index
+        }
+        hmap[e] = m;
+    }
+    for (int e = tid; e < NS * NU; e += TT) {
+        const int i = e / NU, j = e % NU;
+        B[e] = (i < ns && j < nu) ? P.B_dyn[i * nu + j] : 0.f;
+    }
+    for (int e = tid; e < NU * NU; e += TT) {
+        const int i = e / NU, j = e % NU;
+        R2[e] = (i < nu && j < nu) ? 2.f * P.Q_u[i * nu + j] : (i == j ? 1.f : 0.f);
+    }
+    // the trajectory the stage terms are formed about, into LDS
+    {
+        const float* xsrc = ADJ ? TA.xK : (dev ? P.x : nullptr);
+        const float* usrc = ADJ ? TA.uK : (dev ? P.u : nullptr);
+        const float* xrs = P.x_ref + (size_t)s * (N + 1) * ns;
+        for (int e = tid; e < (N + 1) * NS; e += TT) {
+            const int t = e / NS, i = e % NS;
+            sx[e] = (xsrc && i < ns) ? xsrc[((size_t)s * (N + 1) + t) * ns + i] : 0.f;
+            sxr[e] = i < ns ? xrs[t * ns + i] : 0.f;
+        }
+        for (int e = tid; e < N * NU; e += TT) {
+            const int t = e / NU, j = e % NU;
+            su[e] = (usrc && j < nu) ? usrc[((size_t)s * N + t) * nu + j] : 0.f;
+        }
+    }
+    if (tid < NS) {
+        cdyn[tid] = tid < ns ? P.c_dyn[tid] : 0.f;
+        int m = -1, pa = -1;
+        for (int a = 0; a < nq; ++a) {
+            const int qa = a < P.dim ? P.pos_idx[a] : P.att_idx[a - P.dim];
+            if (qa == tid && tid < ns) {
+                m = nq * (nq + 1) / 2 + a;
+                pa = a;
+            }
+        }
+        gmap[tid] = m;
+        pmap[tid] = pa;
+    }
+    __syncthreads();
+    // 1. per-step sums of the pair contributions (fixed order over this
+    //    scenario's workgroups) and the stage and input gradients about the
+    //    staged trajectory; in reverse mode the stage sums saved by the
+    //    forward pass, the state cotangents (pose coordinates summed over this
+    //    scenario's workgroups, plus the gradient of the tracking cost at the
+    //    last iterate) and the input cotangents
+    const int2 wr = P.scen_wg[s];
+    if (ADJ) {
+        for (int e = tid; e < N * nc; e += TT)
+            Hq[e] = TA.hq ? TA.hq[(size_t)s * N * nc + e] : 0.f;
+        // four steps per thread: the pose partials are summed as float4
+        const int N4 = (N + 3) / 4;
+        for (int e = tid; e < N4 * NS; e += TT) {
+            const int t4 = e / NS, i = e % NS;
+            const int a = pmap[i];
+            float4 part = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (TA.qpart && a >= 0)
+                part = strided_sum4(reinterpret_cast<const float4*>(TA.qpart + (size_t)a * 64) + t4, (size_t)nq * 16,
+                                    wr.x, wr.y);
+            const float pq[4] = {part.x, part.y, part.z, part.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int t = 4 * t4 + q;
+                if (t >= N) break;
+                float acc = pq[q];
+                if (TA.xK)
+#pragma unroll
+                    for (int j = 0; j < NS; ++j) acc += Q2[i * NS + j] * (sx[(t + 1) * NS + j] - sxr[(t + 1) * NS + j]);
+                qr[t * NS + i] = -acc;
+            }
+        }
+        for (int e = tid; e < N * NU; e += TT) {
+            const int t = e / NU, j = e % NU;
+            float acc = 0.f;
+            if (j < nu)
+#pragma unroll
+                for (int m = 0; m < NU; ++m) acc += R2[j * NU + m] * su[t * NU + m];
+            rin[e] = -acc;
+        }
+        for (int e = tid; e < N * NS; e += TT) off[e] = 0.f;
+    } else {
+        if (!obstacle_free) {
+            // four steps per thread, the partials summed as float4
+            const int N4 = (N + 3) / 4;
+            for (int e = tid; e < N4 * nc; e += TT) {
+                const int cc = e / N4, t4 = e % N4;
+                const float4 v = strided_sum4(reinterpret_cast<const float4*>(P.contrib + (size_t)cc * 64) + t4,
+                                              (size_t)nc * 16, wr.x, wr.y);
+                const float vq[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int t = 4 * t4 + q;
+                    if (t >= N) break;
+                    Hq[t * nc + cc] = vq[q];
+                    if (hq_save) hq_save[((size_t)s * N + t) * nc + cc] = vq[q];
+                }
+            }
+        } else {
+            for (int e = tid; e < N * nc; e += TT) Hq[e] = 0.f;
+        }
+        for (int e = tid; e < N * NS; e += TT) {
+            const int t = e / NS, i = e % NS;
+            float acc = 0.f;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) acc += Q2[i * NS + j] * (sx[(t + 1) * NS + j] - sxr[(t + 1) * NS + j]);
+            qr[e] = acc;
+        }
+        for (int e = tid; e < N * NU; e += TT) {
+            const int t = e / NU, j = e % NU;
+            float acc = 0.f;
+            if (j < nu)
+#pragma unroll
+                for (int m = 0; m < NU; ++m) acc += R2[j * NU + m] * su[t * NU + m];
+            rin[e] = acc;
+        }
+        // dynamics offsets: the defects of the staged trajectory, in FP64
+        // (zero-padded rows and columns contribute nothing)
+        for (int e = tid; e < N * NS; e += TT) {
+            const int t = e / NS, i = e % NS;
+            double acc = (double)cdyn[i];
+            if (dev) {
+                acc -= (double)sx[(t + 1) * NS + i];
+#pragma unroll
+                for (int j = 0; j < NS; ++j) acc += (double)A[i * NS + j] * (double)sx[t * NS + j];
+#pragma unroll
+                for (int j = 0; j < NU; ++j) acc += (double)B[i * NU + j] * (double)su[t * NU + j];
+            }
+            off[e] = (float)acc;
+        }
+    }
+    __syncthreads();
+    float* xo = P.x + (size_t)s * (N + 1) * ns;
+    float* uo = P.u + (size_t)s * N * nu;
+    float* dX = ADJ ? wl : qr;             // forward: dx_t at (t-1) * NS, t = 1..N; reverse: w_t at t * NS
+    float* dU = rin;                       // forward: du_t at t * NU
+    if constexpr (NS == 4 && NU == 2) {
+        // 2-3. the sweep and the rollout in the registers of wave 0
+        if (tid < 64) {
+            const int r = tid & 3;
+            float x0d = 0.f;
+            if (!ADJ && r < ns) {
+                const float x0v = P.x0[(size_t)s * ns + r];
+                x0d = dev ? x0v - xo[r] : x0v;
+            }
+            if (ADJ && tid < 4) wl[tid] = 0.f;
+            riccati_regs_42<ADJ>(A, B, Q2, R2, hmap, gmap, Hq, qr, rin, off, Kall, dX, dU, wl, N, nc, x0d);
+        }
+        __syncthreads();
+    } else {
+    // 2. backward Riccati sweep, V_t(x) = 1/2 x^T P x + p^T x, P_N = H_N.
+    //    Every phase is one strided dot product per thread, so a wave never
+    //    runs several output types one after the other:
+    //      out = bias + sum_k X[k * xs] Y[k * ys]
+    //    (a) PA = P A, PB = P B, w = P f_t + p;
+    //    (b) Quu = 2Q_u + B^T PB, Qux = B^T PA, qu = B^T w + input gradient,
+    //        Qxx = H_t + A^T PA, qx = h_t + A^T w (t >= 1);
+    //    (c) gains [K | k] = -Quu^{-1} [Qux | qu] and the update
+    //        P_t = Qxx + Qux^T K (symmetrised), p_t = qx + Qux^T k: each
+    //        thread factors the small Quu itself, so (c) needs no extra barrier.
+    //    (Folding (a) into (b) for tiny NS, NS^2 terms per output, measured
+    //    slower than the extra barrier on gfx950.)
+    constexpr bool kFold = false;
+    // the linear stage terms of the forward pass carry the pose-block
+    // gradients of the pair contributions; the adjoint LQ has none
+    auto lin = [&](int t, int i) -> float {
+        return qr[t * NS + i] + ((!ADJ && gmap[i] >= 0) ? Hq[t * nc + gmap[i]] : 0.f);
+    };
+    for (int e = tid; e < NS * NS; e += TT) Pm[e] = Q2[e] + (hmap[e] >= 0 ? Hq[(N - 1) * nc + hmap[e]] : 0.f);
+    if (tid < NS) pv[tid] = lin(N - 1, tid);
+    // phase (a) descriptor of this thread: one output of PA, PB or w
+    constexpr int NA = NS * NS + NS * NU + NS;
+    int a_type = -1, a_i = 0, a_j = 0;
+    if (tid < NS * NS) { a_type = 0; a_i = tid / NS; a_j = tid % NS; }
+    else if (tid < NS * NS + NS * NU) { a_type = 1; a_i = (tid - NS * NS) / NU; a_j = (tid - NS * NS) % NU; }
+    else if (tid < NA) { a_type = 2; a_i = tid - NS * NS - NS * NU; }
+    // phase (b) descriptor: one output of Quu, Qux, qu, Qxx or qx
+    constexpr int NB = NU * NU + NU * NS + NU;
+    constexpr int NBX = NB + NS * NS + NS;
+    int b_type = -1, b_i = 0, b_j = 0;
+    if (tid < NU * NU) { b_type = 0; b_i = tid / NU; b_j = tid % NU; }
+    else if (tid < NU * NU + NU * NS) { b_type = 1; b_i = (tid - NU * NU) / NS; b_j = (tid - NU * NU) % NS; }
+    else if (tid < NB) { b_type = 2; b_i = tid - NU * NU - NU * NS; }
+    else if (tid < NB + NS * NS) { b_type = 3; b_i = (tid - NB) / NS; b_j = (tid - NB) % NS; }
+    else if (tid < NBX) { b_type = 4; b_i = tid - NB - NS * NS; }
+    // phase (c) descriptor: P(i, j) for j >= i, or p(i) (j = NS)
+    constexpr int NCP = NS * (NS + 1) / 2 + NS;
+    int c_i = -1, c_j = 0;
+    if (tid < NCP) {
+        int r = tid;
+        if (r < NS * (NS + 1) / 2) {
+            int i = 0;
+            while (r >= NS - i) { r -= NS - i; ++i; }
+            c_i = i;
+            c_j = i + r;
+        } else {
+            c_i = r - NS * (NS + 1) / 2;
+            c_j = NS;
+        }
+    }
+    // the (b) bias of this thread: its constant part in a register, the
+    // step-dependent part read at the top of each step so that its LDS
+    // latency hides under phase (a)
+    float b_q2 = 0.f;
+    int b_hm = -1;
+    if (b_type == 0) b_q2 = R2[b_i * NU + b_j];
+    else if (b_type == 3) { b_q2 = Q2[b_i * NS + b_j]; b_hm = hmap[b_i * NS + b_j]; }
+    else if (b_type == 4) b_hm = ADJ ? -1 : gmap[b_i];
+    __syncthreads();
+    for (int t = N - 1; t >= 0; --t) {
+        const float* ft = off + t * NS;
+        float bias = b_q2;
+        if (b_type == 2) bias = rin[t * NU + b_i];
+        else if (b_type == 3 && t >= 1) bias += b_hm >= 0 ? Hq[(t - 1) * nc + b_hm] : 0.f;
+        else if (b_type == 4 && t >= 1) bias = qr[(t - 1) * NS + b_i] + (b_hm >= 0 ? Hq[(t - 1) * nc + b_hm] : 0.f);
+        if (!kFold) {
+            // (a)
+            if (a_type >= 0) {
+                const float* X = Pm + a_i * NS;
+                const float* Y = a_type == 0 ? A + a_j : (a_type == 1 ? B + a_j : ft);
+                const int ys = a_type == 0 ? NS : (a_type == 1 ? NU : 1);
+                float acc = a_type == 2 ? pv[a_i] : 0.f;
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) acc += X[k2] * Y[k2 * ys];
+                float* O = a_type == 0 ? PA + a_i * NS + a_j : (a_type == 1 ? PB + a_i * NU + a_j : wv + a_i);
+                *O = acc;
+            }
+            __syncthreads();
+        }
+        // (b)
+        if (b_type >= 0 && (t >= 1 || b_type <= 2)) {
+            // X: column b_i of B (types 0-2) or of A (types 3-4)
+            const float* X = b_type <= 2 ? B + b_i : A + b_i;
+            const int xs = b_type <= 2 ? NU : NS;
+            float acc = bias;
+            if (kFold) {
+                // Y column j of P B, P A or the vector P f_t + p, formed here
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) {
+                    float y;
+                    if (b_type == 0) {
+                        y = 0.f;
+#pragma unroll
+                        for (int l = 0; l < NS; ++l) y += Pm[k2 * NS + l] * B[l * NU + b_j];
+                    } else if (b_type == 1 || b_type == 3) {
+                        y = 0.f;
+#pragma unroll
+                        for (int l = 0; l < NS; ++l) y += Pm[k2 * NS + l] * A[l * NS + b_j];
+                    } else {
+                        y = pv[k2];
+#pragma unroll
+                        for (int l = 0; l < NS; ++l) y += Pm[k2 * NS + l] * ft[l];
+                    }
+                    acc += X[k2 * xs] * y;
+                }
+            } else {
+                const float* Y = b_type == 0 ? PB + b_j : ((b_type == 1 || b_type == 3) ? PA + b_j : wv);
+                const int ys = b_type == 0 ? NU : ((b_type == 1 || b_type == 3) ? NS : 1);
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) acc += X[k2 * xs] * Y[k2 * ys];
+            }
+            float* O = b_type == 0 ? Quu + b_i * NU + b_j
+                     : b_type == 1 ? Qux + b_i * NS + b_j
+                     : b_type == 2 ? qu + b_i
+                     : b_type == 3 ? Qxx + b_i * NS + b_j
+                                   : qx + b_i;
+            *O = acc;
+        }
+        __syncthreads();
+        // (c) gains and, for t >= 1, the value function of step t
+        if (c_i >= 0 && (t >= 1 || c_j == c_i || (c_j == NS && c_i == 0))) {
+            float L[NU * NU];
+#pragma unroll
+            for (int q = 0; q < NU * NU; ++q) L[q] = Quu[q];
+#pragma unroll
+            for (int j = 0; j < NU; ++j) {
+                float d = L[j * NU + j];
+#pragma unroll
+                for (int k2 = 0; k2 < j; ++k2) d -= L[j * NU + k2] * L[j * NU + k2];
+                // v_rsq_f32 (about 1 ulp); the diagonal keeps 1 / l_jj
+                const float id = __builtin_amdgcn_rsqf(fmaxf(d, 1e-30f));
+                L[j * NU + j] = id;
+#pragma unroll
+                for (int i = j + 1; i < NU; ++i) {
+                    float v = L[i * NU + j];
+#pragma unroll
+                    for (int k2 = 0; k2 < j; ++k2) v -= L[i * NU + k2] * L[j * NU + k2];
+                    L[i * NU + j] = v * id;
+                }
+            }
+            // columns c_i and c_j of the gains [K | k] (c_j = NS: feedforward)
+            auto gain = [&](int col, float (&r)[NU]) {
+#pragma unroll
+                for (int i = 0; i < NU; ++i) r[i] = -(col < NS ? Qux[i * NS + col] : qu[i]);
+#pragma unroll
+                for (int i = 0; i < NU; ++i) {
+                    float v = r[i];
+#pragma unroll
+                    for (int k2 = 0; k2 < i; ++k2) v -= L[i * NU + k2] * r[k2];
+                    r[i] = v * L[i * NU + i];
+                }
+#pragma unroll
+                for (int i = NU - 1; i >= 0; --i) {
+                    float v = r[i];
+#pragma unroll
+                    for (int k2 = i + 1; k2 < NU; ++k2) v -= L[k2 * NU + i] * r[k2];
+                    r[i] = v * L[i * NU + i];
+                }
+            };
+            float Ki[NU], Kj[NU];
+            gain(c_i, Ki);
+            gain(c_j, Kj);
+            float* Kt = Kall + (size_t)t * NU * NSU;
+            // the diagonal threads own the gain columns, thread p(0) the feedforward
+            if (c_j == c_i) {
+#pragma unroll
+                for (int i = 0; i < NU; ++i) Kt[i * NSU + c_i] = Ki[i];
+            }
+            if (c_j == NS && c_i == 0) {
+#pragma unroll
+                for (int i = 0; i < NU; ++i) Kt[i * NSU + NS] = Kj[i];
+            }
+            if (t >= 1) {
+                if (c_j < NS) {
+                    float aij = Qxx[c_i * NS + c_j] + Qxx[c_j * NS + c_i];
+#pragma unroll
+                    for (int k2 = 0; k2 < NU; ++k2)
+                        aij += Qux[k2 * NS + c_i] * Kj[k2] + Qux[k2 * NS + c_j] * Ki[k2];
+                    Pm[c_i * NS + c_j] = 0.5f * aij;
+                    Pm[c_j * NS + c_i] = 0.5f * aij;
+                } else {
+                    float acc = qx[c_i];
+#pragma unroll
+                    for (int k2 = 0; k2 < NU; ++k2) acc += Qux[k2 * NS + c_i] * Kj[k2];
+                    pv[c_i] = acc;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // 3. rollout dx_{t+1} = A dx + B (K dx + k) + f_t; thread i owns dx_i
+    //    (rows of A and B in registers), threads NS..NS+NU-1 the inputs. The
+    //    deviations stay in LDS (forward: over qr and rin, dead after the
+    //    sweep; reverse: w in wl) and are written out by one parallel pass.
+    float Ar[NS], Br[NU];
+    const int row = tid < NS ? tid : 0;
+#pragma unroll
+    for (int k2 = 0; k2 < NS; ++k2) Ar[k2] = A[row * NS + k2];
+#pragma unroll
+    for (int j = 0; j < NU; ++j) Br[j] = B[row * NU + j];
+    if (tid < NS) {
+        float v = 0.f;
+        if (!ADJ && tid < ns) {
+            const float x0v = P.x0[(size_t)s * ns + tid];
+            v = dev ? x0v - xo[tid] : x0v;
+        }
+        xbuf[0][tid] = v;
+        if (ADJ) wl[tid] = 0.f;
+    }
+    __syncthreads();
+    for (int t = 0; t < N; ++t) {
+        const float* xc = xbuf[t & 1];
+        const float* Kt = Kall + (size_t)t * NU * NSU;
+        if (tid < NS + NU) {
+            float xr[NS];
+#pragma unroll
+            for (int k2 = 0; k2 < NS; ++k2) xr[k2] = xc[k2];
+            float uu[NU];
+#pragma unroll
+            for (int j = 0; j < NU; ++j) {
+                float v = Kt[j * NSU + NS];
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) v += Kt[j * NSU + k2] * xr[k2];
+                uu[j] = v;
+            }
+            if (tid < NS) {
+                float acc = off[t * NS + tid];
+#pragma unroll
+                for (int k2 = 0; k2 < NS; ++k2) acc += Ar[k2] * xr[k2];
+#pragma unroll
+                for (int j = 0; j < NU; ++j) acc += Br[j] * uu[j];
+                xbuf[(t + 1) & 1][tid] = acc;
+                if (ADJ) wl[(t + 1) * NS + tid] = acc;
+                else dX[t * NS + tid] = acc;
+            } else if (!ADJ) {
+                const int j = tid - NS;
+                float v = 0.f;
+#pragma unroll
+                for (int q = 0; q < NU; ++q) v = q == j ? uu[q] : v;
+                dU[t * NU + j] = v;
+            }
+        }
+        __syncthreads();
+    }
+    }
+    if (!ADJ) {
+        // x_t = x^k_t + dx_t (t = 1..N), u_t = u^k_t + du_t, x_0 = x0
+        for (int e = tid; e < N * ns; e += TT) {
+            const int t = e / ns, i = e % ns;
+            float* xp = xo + (t + 1) * ns + i;
+            *xp = (dev ? *xp : 0.f) + dX[t * NS + i];
+        }
+        for (int e = tid; e < N * nu; e += TT) {
+            const int t = e / nu, j = e % nu;
+            float* up = uo + t * nu + j;
+            *up = (dev ? *up : 0.f) + dU[t * NU + j];
+        }
+        if (tid < ns) xo[tid] = P.x0[(size_t)s * ns + tid];
+        return;
+    }
+    // 4. reverse mode: w_t out, zbar_t = xbar_t - H_t w_t (stored over qr),
+    //    then x0bar = sum_t (A^T)^t zbar_t by a Horner sweep from t = N down
+    //    to 1 (one barrier per step, double-buffered)
+    for (int e = tid; e < N * ns; e += TT) {
+        const int t = e / ns, i = e % ns;
+        TA.w[((size_t)s * N + t) * ns + i] = wl[(t + 1) * NS + i];
+    }
+    for (int e = tid; e < N * NS; e += TT) {
+        const int t = e / NS, i = e % NS;
+        const float* wt = wl + (t + 1) * NS;
+        float acc = -qr[e];
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            const int m = hmap[i * NS + j];
+            acc -= (Q2[i * NS + j] + (m >= 0 ? Hq[t * nc + m] : 0.f)) * wt[j];
+        }
+        qr[e] = acc;
+    }
+    if (tid < NS) xbuf[0][tid] = 0.f;
+    __syncthreads();
+    int cur = 0;
+    for (int t = N - 1; t >= 0; --t) {
+        if (tid < NS) {
+            float acc = 0.f;
+#pragma unroll
+            for (int j = 0; j < NS; ++j) acc += A[j * NS + tid] * (xbuf[cur][j] + qr[t * NS + j]);
+            xbuf[cur ^ 1][tid] = acc;
+        }
+        cur ^= 1;
+        __syncthreads();
+    }
+    if (tid < ns) TA.gx0[(size_t)s * ns + tid] += (double)xbuf[cur][tid];
+}
+
+template <bool ADJ>
+static hipError_t launch_traj(const DevProblem& P, int obstacle_free, float* hq_save, const TrajAdjoint& TA,
+                              hipStream_t st)
+{
+    dim3 g(P.n_scen);
+    if (P.n_s <= 4 && P.n_u <= 2) {
+        const dim3 b(traj_threads(4, 2));
+        hipLaunchKernelGGL((traj_phase_kernel<4, 2, ADJ>), g, b,
+                           sizeof(float) * traj_dyn_floats(P.N, 4, 2, P.nc, ADJ), st, P, obstacle_free, hq_save, TA);
+    } else if (P.n_s <= 12 && P.n_u <= 4) {
+        const dim3 b(traj_threads(12, 4));
+        hipLaunchKernelGGL((traj_phase_kernel<12, 4, ADJ>), g, b,
+                           sizeof(float) * traj_dyn_floats(P.N, 12, 4, P.nc, ADJ), st, P, obstacle_free, hq_save, TA);
+    } else {
+        const dim3 b(traj_threads(16, 8));
+        hipLaunchKernelGGL((traj_phase_kernel<16, 8, ADJ>), g, b,
+                           sizeof(float) * traj_dyn_floats(P.N, 16, 8, P.nc, ADJ), st, P, obstacle_free, hq_save, TA);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t st, float* hq_save)
+{
+    return launch_traj<false>(P, obstacle_free, hq_save, TrajAdjoint{}, st);
+}
+
+hipError_t launch_traj_adjoint(const DevProblem& P, const TrajAdjoint& TA, hipStream_t st)
+{
+    return launch_traj<true>(P, 0, nullptr, TA, st);
+}
+
+} // namespace cadmm
