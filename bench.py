@@ -123,7 +123,7 @@ def batched_vs_plain(cadmm, torch, steps=2, iters=50):
     # HBM roofline of the batched pair phase (the size where HBM, not launch
     # latency, bounds it), from HIP events on the handle's stream
     hb.reset()
-    ph = hb.phase_times(10)
+    ph = hb.phase_times(iters)
     nq = prob["dim"] + (1 if prob["dim"] == 2 else 3)
     bytes_launch = pair_bytes(prob, wb[1], nq * (nq + 1) // 2 + nq)
     gbs = bytes_launch / (ph[0] * 1e-3) / 1e9
@@ -275,10 +275,12 @@ def main():
             reached = k + 1
             break
     solves = npairs * it_done
-    # roofline figure of the dominant kernel (pair phase), measured with HIP
-    # events on the handle's stream from the initial iterate
+    # roofline figure of the dominant kernel (pair phase): HIP events recorded
+    # around each launch's own execution on the handle's stream, over the
+    # same iterations as the timed solves (the first iterations carry more
+    # Newton sweeps than the later ones, so a shorter window would differ)
     h.reset()
-    ph = h.phase_times(20)
+    ph = h.phase_times(it_done)
     nq = prob["dim"] + (1 if prob["dim"] == 2 else 3)
     nc = nq * (nq + 1) // 2 + nq
     bytes_launch = pair_bytes(prob, n_wg, nc)
@@ -306,7 +308,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(f"pair_phase_{args.workload}") if args.workload == "c2" else None,
-                     "kernel": "pair_phase_kernel", "bytes_per_launch": bytes_launch},
+                     "kernel": "pair_phase_kernel", "bytes_per_launch": bytes_launch,
+                     "launch": {"blocks_per_group": W, "workgroups": n_wg, "lanes_per_pair": G}},
     }
     h.close()
     if not args.no_batched:

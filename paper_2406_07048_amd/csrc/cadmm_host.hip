@@ -464,7 +464,9 @@ int autotune(cadmm_handle* h, int fixed_W, int fixed_G)
                 HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
                 if (rep > 0) tot += ms;   // the first run warms caches and code
             }
-            if (tot < best) { best = tot; bestW = W; bestG = G; }
+            // a later shape has to win by 3%, so that run-to-run timing noise
+            // does not flip the choice between near-equal shapes
+            if (tot < 0.97f * best) { best = tot; bestW = W; bestG = G; }
         }
     }
     (void)hipEventDestroy(e0);
@@ -769,28 +771,36 @@ int admm_scales(cadmm_handle* h, float* alpha)
 int admm_phase_times(cadmm_handle* h, int n_iters, float* ms_out)
 {
     if (!h || n_iters <= 0 || !ms_out) return fail(CADMM_INVALID, "bad handle, count or output");
-    hipEvent_t ev[5];
-    for (int i = 0; i < 5; ++i) HIP_TRY(hipEventCreate(&ev[i]));
+    // events recorded around each kernel's own execution (hipExtLaunchKernel),
+    // a set per iteration, read after one synchronisation at the end, so that
+    // the iterations run back to back
+    std::vector<hipEvent_t> ev((size_t)8 * n_iters, nullptr);
+    int rc = CADMM_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) { e = nullptr; rc = CADMM_DEVICE; }
     double acc[4] = {0, 0, 0, 0};
     hipStream_t st = h->stream;
-    for (int it = 0; it < n_iters; ++it) {
-        HIP_TRY(hipEventRecord(ev[0], st));
-        if (h->L.n_blocks > 0) HIP_TRY(launch_pair_phase(h->P, h->W, h->G, h->grid, st));
-        HIP_TRY(hipEventRecord(ev[1], st));
-        HIP_TRY(launch_traj_phase(h->P, h->L.n_blocks == 0 ? 1 : 0, st));
-        HIP_TRY(hipEventRecord(ev[2], st));
-        if (h->L.n_blocks > 0) HIP_TRY(launch_mult_phase(h->P, h->W, h->grid, st));
-        HIP_TRY(hipEventRecord(ev[3], st));
-        HIP_TRY(launch_residual(h->P, st));
-        HIP_TRY(hipEventRecord(ev[4], st));
-        HIP_TRY(hipEventSynchronize(ev[4]));
-        for (int i = 0; i < 4; ++i) {
+    const bool pairs = h->L.n_blocks > 0;
+    hipError_t err = hipSuccess;
+    for (int it = 0; it < n_iters && rc == CADMM_OK && err == hipSuccess; ++it) {
+        hipEvent_t* e = &ev[(size_t)8 * it];
+        if (pairs) err = launch_pair_phase(h->P, h->W, h->G, h->grid, st, e[0], e[1]);
+        if (err == hipSuccess) err = launch_traj_phase(h->P, pairs ? 0 : 1, st, nullptr, e[2], e[3]);
+        if (err == hipSuccess && pairs) err = launch_mult_phase(h->P, h->W, h->grid, st, e[4], e[5]);
+        if (err == hipSuccess) err = launch_residual(h->P, st, e[6], e[7]);
+    }
+    if (rc == CADMM_OK && err == hipSuccess) err = hipStreamSynchronize(st);
+    for (int it = 0; it < n_iters && rc == CADMM_OK && err == hipSuccess; ++it)
+        for (int i = 0; i < 4 && err == hipSuccess; ++i) {
+            if (!pairs && (i == 0 || i == 2)) continue;
             float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            err = hipEventElapsedTime(&ms, ev[(size_t)8 * it + 2 * i], ev[(size_t)8 * it + 2 * i + 1]);
             acc[i] += ms;
         }
-    }
-    for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+    for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc != CADMM_OK) return fail(CADMM_DEVICE, "hipEventCreate failed");
+    if (err != hipSuccess) return fail(CADMM_DEVICE, std::string("phase timing: ") + hipGetErrorString(err));
     for (int i = 0; i < 4; ++i) ms_out[i] = (float)(acc[i] / n_iters);
     return CADMM_OK;
 }

@@ -2,6 +2,7 @@
 // of the gfx950 ADMM collision-avoidance library. Not part of the public ABI.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace cadmm {
@@ -93,16 +94,28 @@ struct PairAdjoint {
 // return hipError_t of the launch.
 // Pair phase with W pair blocks per workgroup and G lanes per pair (1, 2, 4);
 // a block takes ceil(N / (64 / G)) waves, and W times that must be <= 8.
-hipError_t launch_pair_phase(const DevProblem& P, int waves_per_group, int lanes_per_pair, int grid, hipStream_t s);
+// Launches of the ADMM phases. Given a pair of events (ev0 != nullptr), the
+// launch records them around the kernel's own execution (hipExtLaunchKernel),
+// which is what the per-phase timings use; graphs capture plain launches.
+#define CADMM_LAUNCH(kernel, grid, block, lds, stream, ev0, ev1, ...)                                 \
+    do {                                                                                           \
+        if (ev0) hipExtLaunchKernelGGL(kernel, grid, block, lds, stream, ev0, ev1, 0, __VA_ARGS__); \
+        else hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);                     \
+    } while (0)
+
+hipError_t launch_pair_phase(const DevProblem& P, int waves_per_group, int lanes_per_pair, int grid, hipStream_t s,
+                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 bool pair_group_supported(int N, int W, int G);
-hipError_t launch_mult_phase(const DevProblem& P, int waves_per_group, int grid, hipStream_t s);
-hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t s, float* hq_save = nullptr);
+hipError_t launch_mult_phase(const DevProblem& P, int waves_per_group, int grid, hipStream_t s,
+                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t s, float* hq_save = nullptr,
+                             hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_traj_adjoint(const DevProblem& P, const TrajAdjoint& TA, hipStream_t s);
 hipError_t launch_pair_adjoint(const DevProblem& P, const PairAdjoint& A, int waves_per_group, int grid,
                                hipStream_t s);
 hipError_t launch_grad_finalize(int n_parts, int n_faces, const double* gdb, int n_x0, const double* gx0,
                                 float scale, float* grad_d, float* grad_x0, hipStream_t s);
-hipError_t launch_residual(const DevProblem& P, hipStream_t s);
+hipError_t launch_residual(const DevProblem& P, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_init_pairs(const DevProblem& P, float* alpha_out, int write_y, hipStream_t s);
 hipError_t launch_fill(float* p, long long n, float v, hipStream_t s);
 hipError_t launch_set_face_offsets(float4* faces, const double* d64, int n, hipStream_t s);

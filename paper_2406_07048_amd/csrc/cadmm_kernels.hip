@@ -1356,16 +1356,16 @@ static int pick_variant(const DevProblem& P)
 }
 
 template <int DIM, int MR, int MO>
-static void launch_pair_g(const DevProblem& P, int W, int G, int grid, hipStream_t st)
+static void launch_pair_g(const DevProblem& P, int W, int G, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
     const int nc = P.nc;
     const int nw = pair_waves_per_block(P.N, G);
     const size_t lds = (size_t)W * (MR + MO) * sizeof(float4) + (size_t)W * nc * 64 * sizeof(float) +
                        2 * (size_t)W * nw * sizeof(float);
     dim3 blk(64 * W * nw), grd(grid);
-    if (G == 4) hipLaunchKernelGGL((pair_phase_kernel<DIM, MR, MO, 4>), grd, blk, lds, st, P);
-    else if (G == 2) hipLaunchKernelGGL((pair_phase_kernel<DIM, MR, MO, 2>), grd, blk, lds, st, P);
-    else hipLaunchKernelGGL((pair_phase_kernel<DIM, MR, MO, 1>), grd, blk, lds, st, P);
+    if (G == 4) CADMM_LAUNCH((pair_phase_kernel<DIM, MR, MO, 4>), grd, blk, lds, st, e0, e1, P);
+    else if (G == 2) CADMM_LAUNCH((pair_phase_kernel<DIM, MR, MO, 2>), grd, blk, lds, st, e0, e1, P);
+    else CADMM_LAUNCH((pair_phase_kernel<DIM, MR, MO, 1>), grd, blk, lds, st, e0, e1, P);
 }
 
 bool pair_group_supported(int N, int W, int G)
@@ -1373,37 +1373,38 @@ bool pair_group_supported(int N, int W, int G)
     return (G == 1 || G == 2 || G == 4) && W >= 1 && W * pair_waves_per_block(N, G) <= 8;
 }
 
-hipError_t launch_pair_phase(const DevProblem& P, int W, int G, int grid, hipStream_t st)
+hipError_t launch_pair_phase(const DevProblem& P, int W, int G, int grid, hipStream_t st, hipEvent_t e0,
+                             hipEvent_t e1)
 {
     if (!pair_group_supported(P.N, W, G)) return hipErrorInvalidValue;
     switch (pick_variant(P)) {
-    case 0: launch_pair_g<2, 4, 16>(P, W, G, grid, st); break;
-    case 1: launch_pair_g<2, 8, 32>(P, W, G, grid, st); break;
-    case 2: launch_pair_g<3, 6, 24>(P, W, G, grid, st); break;
-    case 3: launch_pair_g<3, 8, 32>(P, W, G, grid, st); break;
+    case 0: launch_pair_g<2, 4, 16>(P, W, G, grid, st, e0, e1); break;
+    case 1: launch_pair_g<2, 8, 32>(P, W, G, grid, st, e0, e1); break;
+    case 2: launch_pair_g<3, 6, 24>(P, W, G, grid, st, e0, e1); break;
+    case 3: launch_pair_g<3, 8, 32>(P, W, G, grid, st, e0, e1); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_mult_phase(const DevProblem& P, int W, int grid, hipStream_t st)
+hipError_t launch_mult_phase(const DevProblem& P, int W, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
     const int v = pick_variant(P);
     const size_t lds = (size_t)W * sizeof(float);
     dim3 blk(64 * W), grd(grid);
     switch (v) {
-    case 0: hipLaunchKernelGGL((mult_phase_kernel<2, 4, 16>), grd, blk, lds, st, P); break;
-    case 1: hipLaunchKernelGGL((mult_phase_kernel<2, 8, 32>), grd, blk, lds, st, P); break;
-    case 2: hipLaunchKernelGGL((mult_phase_kernel<3, 6, 24>), grd, blk, lds, st, P); break;
-    case 3: hipLaunchKernelGGL((mult_phase_kernel<3, 8, 32>), grd, blk, lds, st, P); break;
+    case 0: CADMM_LAUNCH((mult_phase_kernel<2, 4, 16>), grd, blk, lds, st, e0, e1, P); break;
+    case 1: CADMM_LAUNCH((mult_phase_kernel<2, 8, 32>), grd, blk, lds, st, e0, e1, P); break;
+    case 2: CADMM_LAUNCH((mult_phase_kernel<3, 6, 24>), grd, blk, lds, st, e0, e1, P); break;
+    case 3: CADMM_LAUNCH((mult_phase_kernel<3, 8, 32>), grd, blk, lds, st, e0, e1, P); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_residual(const DevProblem& P, hipStream_t st)
+hipError_t launch_residual(const DevProblem& P, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
-    hipLaunchKernelGGL(residual_kernel, dim3(P.n_scen), dim3(64), 0, st, P);
+    CADMM_LAUNCH(residual_kernel, dim3(P.n_scen), dim3(64), 0, st, e0, e1, P);
     return hipGetLastError();
 }
 

@@ -765,28 +765,29 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
 
 template <bool ADJ>
 static hipError_t launch_traj(const DevProblem& P, int obstacle_free, float* hq_save, const TrajAdjoint& TA,
-                              hipStream_t st)
+                              hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     dim3 g(P.n_scen);
     if (P.n_s <= 4 && P.n_u <= 2) {
         const dim3 b(traj_threads(4, 2));
-        hipLaunchKernelGGL((traj_phase_kernel<4, 2, ADJ>), g, b,
-                           sizeof(float) * traj_dyn_floats(P.N, 4, 2, P.nc, ADJ), st, P, obstacle_free, hq_save, TA);
+        CADMM_LAUNCH((traj_phase_kernel<4, 2, ADJ>), g, b,
+                           sizeof(float) * traj_dyn_floats(P.N, 4, 2, P.nc, ADJ), st, e0, e1, P, obstacle_free, hq_save, TA);
     } else if (P.n_s <= 12 && P.n_u <= 4) {
         const dim3 b(traj_threads(12, 4));
-        hipLaunchKernelGGL((traj_phase_kernel<12, 4, ADJ>), g, b,
-                           sizeof(float) * traj_dyn_floats(P.N, 12, 4, P.nc, ADJ), st, P, obstacle_free, hq_save, TA);
+        CADMM_LAUNCH((traj_phase_kernel<12, 4, ADJ>), g, b,
+                           sizeof(float) * traj_dyn_floats(P.N, 12, 4, P.nc, ADJ), st, e0, e1, P, obstacle_free, hq_save, TA);
     } else {
         const dim3 b(traj_threads(16, 8));
-        hipLaunchKernelGGL((traj_phase_kernel<16, 8, ADJ>), g, b,
-                           sizeof(float) * traj_dyn_floats(P.N, 16, 8, P.nc, ADJ), st, P, obstacle_free, hq_save, TA);
+        CADMM_LAUNCH((traj_phase_kernel<16, 8, ADJ>), g, b,
+                           sizeof(float) * traj_dyn_floats(P.N, 16, 8, P.nc, ADJ), st, e0, e1, P, obstacle_free, hq_save, TA);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t st, float* hq_save)
+hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t st, float* hq_save, hipEvent_t e0,
+                             hipEvent_t e1)
 {
-    return launch_traj<false>(P, obstacle_free, hq_save, TrajAdjoint{}, st);
+    return launch_traj<false>(P, obstacle_free, hq_save, TrajAdjoint{}, st, e0, e1);
 }
 
 hipError_t launch_traj_adjoint(const DevProblem& P, const TrajAdjoint& TA, hipStream_t st)
