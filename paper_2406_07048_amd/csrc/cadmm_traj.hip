@@ -32,12 +32,12 @@ namespace cadmm {
 // Horner sweep after the rollout.
 // ------------------------------------------------------------------------
 
-// Threads of the trajectory kernel: one output per thread in every phase of
-// the sweep (512 for the 16/8 padding, 256 otherwise).
-__host__ __device__ constexpr int traj_threads(int NS, int NU)
-{
-    return (NS * NS + NS * NU + NS > 256 || NU * NU + NU * NS + NU + NS * NS + NS > 256) ? 512 : 256;
-}
+// Threads of the trajectory kernel: enough for one output per thread in
+// every phase of the LDS sweep (at most 400 for the 16/8 padding), and for
+// the per-step sums to split each output's workgroup partials over several
+// threads (C3: 270 outputs over 1024 threads). The 16/8 padding keeps 512,
+// whose register budget holds its larger sweep without spills.
+__host__ __device__ constexpr int traj_threads(int NS, int) { return NS > 12 ? 512 : 1024; }
 
 // Floats of the gains region, which first holds the staged trajectory
 // (x and x_ref over t = 0..N, u over t = 0..N-1, padded to NS / NU).
@@ -51,7 +51,8 @@ __host__ __device__ inline int traj_gain_floats(int N, int NS, int NU)
 // (reverse mode adds the w trajectory).
 __host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bool adj)
 {
-    return N * nc + N * NS + traj_gain_floats(N, NS, NU) + N * NU + N * NS + (adj ? (N + 1) * NS : 0);
+    return N * nc + N * NS + traj_gain_floats(N, NS, NU) + N * NU + N * NS + (adj ? (N + 1) * NS : 0) + 3 +
+           4 * traj_threads(NS, NU);
 }
 
 // Fixed-order sum of the float4 src[w * stride], w = w0..w1-1, with eight
@@ -103,6 +104,38 @@ __device__ __forceinline__ float4 strided_sum4(const float4* src, size_t stride,
     r.z = ((a[0].z + a[1].z) + (a[2].z + a[3].z)) + ((a[4].z + a[5].z) + (a[6].z + a[7].z));
     r.w = ((a[0].w + a[1].w) + (a[2].w + a[3].w)) + ((a[4].w + a[5].w) + (a[6].w + a[7].w));
     return r;
+}
+
+// Fixed-order sums over the workgroup partials [w0, w1) for O float4
+// outputs (src(o): the float4 of output o in workgroup w0, stride between
+// workgroups). With TT >= 2 O threads each output's workgroups are split
+// into S <= 8 contiguous chunks, summed by S threads and combined in chunk
+// order through red4 (TT float4 of LDS); out(o, v) receives the sums.
+// Every thread of the block calls it (it may hold a barrier).
+template <int TT, class Src, class Out>
+__device__ __forceinline__ void split_sums(int O, int w0, int w1, size_t stride, float4* red4, Src src, Out out)
+{
+    const int tid = threadIdx.x;
+    const int S = O > 0 ? max(1, min(8, TT / O)) : 1;
+    if (S == 1) {
+        for (int o = tid; o < O; o += TT) out(o, strided_sum4(src(o), stride, w0, w1));
+        return;
+    }
+    const int chunk = (w1 - w0 + S - 1) / S;
+    if (tid < O * S) {
+        const int o = tid % O, k = tid / O;
+        const int a = w0 + k * chunk, b = min(w1, a + chunk);
+        red4[tid] = a < b ? strided_sum4(src(o), stride, a, b) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __syncthreads();
+    if (tid < O) {
+        float4 v = red4[tid];
+        for (int k = 1; k < S; ++k) {
+            const float4 u = red4[k * O + tid];
+            v.x += u.x; v.y += u.y; v.z += u.z; v.w += u.w;
+        }
+        out(tid, v);
+    }
 }
 
 // Riccati sweep and rollout for 4 states and 2 inputs, held in the registers
@@ -287,7 +320,7 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     __shared__ float Pm[NS * NS], pv[NS], PA[NS * NS], PB[NS * NU], wv[NS];
     __shared__ float Quu[NU * NU], Qux[NU * NS], qu[NU], Qxx[NS * NS], qx[NS];
     __shared__ float xbuf[2][NS];
-    extern __shared__ float dyn[];
+    extern __shared__ __align__(16) float dyn[];
     const int s = blockIdx.x;
     if (!ADJ && !obstacle_free && P.done[s]) return;
     const int tid = threadIdx.x;
@@ -303,6 +336,9 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     float* rin = Kall + traj_gain_floats(N, NS, NU);   // [N][NU] input gradients 2 Q_u u^k_t (reverse: -ubar_t)
     float* off = rin + N * NU;             // [N][NS] dynamics offsets f_t (c when the base is 0)
     float* wl = off + N * NS;              // reverse: [N+1][NS] w_t
+    // [TT] chunk sums of split_sums, at a 16-byte boundary
+    const int red_off = (int)((wl + (ADJ ? (N + 1) * NS : 0)) - dyn);
+    float4* red4 = reinterpret_cast<float4*>(dyn + ((red_off + 3) & ~3));
 
     // 0. padded model and cost, pose-coordinate maps
     for (int e = tid; e < NS * NS; e += TT) {
@@ -370,15 +406,11 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     if (ADJ) {
         for (int e = tid; e < N * nc; e += TT)
             Hq[e] = TA.hq ? TA.hq[(size_t)s * N * nc + e] : 0.f;
-        // four steps per thread: the pose partials are summed as float4
+        // four steps per output: the pose partials are summed as float4 (for
+        // the pose coordinates; the others have none), plus the gradient of
+        // the tracking cost at the last iterate
         const int N4 = (N + 3) / 4;
-        for (int e = tid; e < N4 * NS; e += TT) {
-            const int t4 = e / NS, i = e % NS;
-            const int a = pmap[i];
-            float4 part = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (TA.qpart && a >= 0)
-                part = strided_sum4(reinterpret_cast<const float4*>(TA.qpart + (size_t)a * 64) + t4, (size_t)nq * 16,
-                                    wr.x, wr.y);
+        auto seed = [&](int t4, int i, float4 part) {
             const float pq[4] = {part.x, part.y, part.z, part.w};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -390,6 +422,20 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
                     for (int j = 0; j < NS; ++j) acc += Q2[i * NS + j] * (sx[(t + 1) * NS + j] - sxr[(t + 1) * NS + j]);
                 qr[t * NS + i] = -acc;
             }
+        };
+        if (TA.qpart) {
+            split_sums<TT>(
+                N4 * nq, wr.x, wr.y, (size_t)nq * 16, red4,
+                [&](int o) { return reinterpret_cast<const float4*>(TA.qpart + (size_t)(o / N4) * 64) + o % N4; },
+                [&](int o, float4 v) {
+                    const int a = o / N4;
+                    const int i = a < P.dim ? P.pos_idx[a] : P.att_idx[a - P.dim];
+                    seed(o % N4, i, v);
+                });
+        }
+        for (int e = tid; e < N4 * NS; e += TT) {
+            const int t4 = e / NS, i = e % NS;
+            if (!TA.qpart || pmap[i] < 0) seed(t4, i, make_float4(0.f, 0.f, 0.f, 0.f));
         }
         for (int e = tid; e < N * NU; e += TT) {
             const int t = e / NU, j = e % NU;
@@ -402,21 +448,22 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         for (int e = tid; e < N * NS; e += TT) off[e] = 0.f;
     } else {
         if (!obstacle_free) {
-            // four steps per thread, the partials summed as float4
+            // four steps per output, the partials summed as float4
             const int N4 = (N + 3) / 4;
-            for (int e = tid; e < N4 * nc; e += TT) {
-                const int cc = e / N4, t4 = e % N4;
-                const float4 v = strided_sum4(reinterpret_cast<const float4*>(P.contrib + (size_t)cc * 64) + t4,
-                                              (size_t)nc * 16, wr.x, wr.y);
-                const float vq[4] = {v.x, v.y, v.z, v.w};
+            split_sums<TT>(
+                N4 * nc, wr.x, wr.y, (size_t)nc * 16, red4,
+                [&](int o) { return reinterpret_cast<const float4*>(P.contrib + (size_t)(o / N4) * 64) + o % N4; },
+                [&](int o, float4 v) {
+                    const int cc = o / N4, t4 = o % N4;
+                    const float vq[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int t = 4 * t4 + q;
-                    if (t >= N) break;
-                    Hq[t * nc + cc] = vq[q];
-                    if (hq_save) hq_save[((size_t)s * N + t) * nc + cc] = vq[q];
-                }
-            }
+                    for (int q = 0; q < 4; ++q) {
+                        const int t = 4 * t4 + q;
+                        if (t >= N) break;
+                        Hq[t * nc + cc] = vq[q];
+                        if (hq_save) hq_save[((size_t)s * N + t) * nc + cc] = vq[q];
+                    }
+                });
         } else {
             for (int e = tid; e < N * nc; e += TT) Hq[e] = 0.f;
         }
