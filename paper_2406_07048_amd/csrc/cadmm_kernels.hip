@@ -356,15 +356,24 @@ __device__ int dual_newton(const Rows& rows, float (&z)[NV], int max_sweeps)
 #pragma unroll
         for (int i = 0; i < NV; ++i) d0 += dz[i] * g[i];
         if (!(d0 > 0.f)) return it;
-        // directional derivative of the dual along dz at step al
+        // directional derivative of the dual along dz at step al; the trial
+        // with the smallest gradient is kept as a fallback
+        float best_al = 0.f, best_g = gmax;
         auto dphi = [&](float al) {
             float zt[NV], gt[NV], Hd[NV * NV], sct;
 #pragma unroll
             for (int i = 0; i < NV; ++i) zt[i] = z[i] + al * dz[i];
             rows.template pass<false>(zt, gt, Hd, sct);
-            float d = 0.f;
+            float d = 0.f, gm = 0.f;
 #pragma unroll
-            for (int i = 0; i < NV; ++i) d += dz[i] * gt[i];
+            for (int i = 0; i < NV; ++i) {
+                d += dz[i] * gt[i];
+                gm = fmaxf(gm, fabsf(gt[i]));
+            }
+            if (gm < best_g) {
+                best_g = gm;
+                best_al = al;
+            }
             return d;
         };
         float al = 1.f;
@@ -388,10 +397,14 @@ __device__ int dual_newton(const Rows& rows, float (&z)[NV], int max_sweeps)
                 }
             }
             al = lo;
-            // no step along dz passes the test: at the FP32 floor of the
-            // directional derivative z cannot be improved, and every further
-            // sweep would repeat this one exactly
-            if (al == 0.f) return it + 1;
+            // no step along dz passes the sign test (the directional
+            // derivative is at its FP32 floor): take the trial that lowered
+            // the gradient most, else z cannot be improved along dz and every
+            // further sweep would repeat this one exactly
+            if (al == 0.f) {
+                if (best_al == 0.f) return it + 1;
+                al = best_al;
+            }
         }
 #pragma unroll
         for (int i = 0; i < NV; ++i) z[i] += al * dz[i];

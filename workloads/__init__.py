@@ -354,6 +354,88 @@ def config_c3(seed=25, M=200, N=40, k_range=(7, 12)):
         x_ref=x_ref, x0=x_ref[:, 0, :].copy(), sigma=SIGMA_PAPER))
 
 
+def regular_polygon_faces(n_faces, radius):
+    """Faces (A, b) of a regular polygon with n_faces edges whose vertices lie
+    on a circle of the given radius, centred at the origin (b > 0)."""
+    ang = 2.0 * np.pi * (np.arange(n_faces) + 0.5) / n_faces
+    A = np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    b = np.full(n_faces, radius * np.cos(np.pi / n_faces))
+    return A, b
+
+
+def config_edge_2d(seed=3, N=20, M=4, f_range=(17, 32), part_faces=8, sigma=SIGMA_PAPER):
+    """Edge sizes in 2D: one robot part with part_faces faces (a regular
+    polygon of radius 2 m), M polygon obstacles with F ~ U{f_range} faces on
+    circles of radius U(1, 2.5) m placed along the first 2/3 of the path with
+    lateral offsets of 2.5-4.5 m (so that pairs become active), bicycle at
+    10 m/s, horizon N."""
+    rng = np.random.default_rng(seed)
+    dt, v = 0.1, 10.0
+    A_r, b_r = regular_polygon_faces(part_faces, 2.0)
+    parts = [(A_r, b_r, np.zeros(2))]
+    start = np.array([0.0, 20.0])
+    start_pts = [start, start + np.array([v * dt, 0.0])]
+    length = max(v * dt * N * 2.0 / 3.0, 8.0)
+    obs = []
+    while len(obs) < M:
+        F = int(rng.integers(f_range[0], f_range[1] + 1))
+        rad = rng.uniform(1.0, 2.5)
+        c = start + np.array([rng.uniform(4.0, 4.0 + length), rng.choice([-1.0, 1.0]) * rng.uniform(2.5, 4.5)])
+        if _reject_near_start(c, rad, start_pts, 2.0):
+            continue
+        C, dl = polygon_on_circle(rng, F, rad)
+        obs.append((C, dl + C @ c))
+    return _assemble_2d(parts, [obs], N, dt, v, start[None, :], sigma=sigma)
+
+
+def prism_faces(n_sides, radius, half_height, R):
+    """Faces (A, b) of a regular n_sides-gon prism (circumradius radius,
+    height 2 half_height) rotated by R, centred at the origin: n_sides + 2
+    faces, b > 0."""
+    ang = 2.0 * np.pi * (np.arange(n_sides) + 0.5) / n_sides
+    side = np.stack([np.cos(ang), np.sin(ang), np.zeros(n_sides)], axis=1)
+    A = np.concatenate([side, [[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]]]) @ R.T
+    b = np.concatenate([np.full(n_sides, radius * np.cos(np.pi / n_sides)), [half_height, half_height]])
+    return A, b
+
+
+def random_rotation(rng):
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def config_edge_3d(seed=5, N=10, M=6, side_range=(23, 30), sigma=SIGMA_PAPER):
+    """Edge sizes in 3D: the C3 quadrotor and model, M randomly rotated
+    regular prisms with n ~ U{side_range} sides (n + 2 = 25..32 faces,
+    circumradius U(0.6, 1.5) m, half height U(0.4, 1.2) m) along the path,
+    their centres 0-0.6 m beyond their bounding radius from it, horizon N."""
+    rng = np.random.default_rng(seed)
+    dt, v = 0.1, 12.5
+    base = config_c3(seed=25, M=1, N=N)
+    start = np.array([0.0, 25.0, 25.0])
+    start_pts = [start, start + np.array([v * dt, 0, 0])]
+    length = max(v * dt * N * 2.0 / 3.0, 4.0)
+    obs = []
+    while len(obs) < M:
+        n = int(rng.integers(side_range[0], side_range[1] + 1))
+        rad, hh = rng.uniform(0.6, 1.5), rng.uniform(0.4, 1.2)
+        C, dl = prism_faces(n, rad, hh, random_rotation(rng))
+        u = rng.standard_normal(2)
+        u /= np.linalg.norm(u)
+        c = start + np.array([rng.uniform(3.0, 3.0 + length), 0.0, 0.0])
+        c[1:] += u * (np.hypot(rad, hh) + rng.uniform(0.0, 0.6))
+        if _reject_near_start(c, np.hypot(rad, hh), start_pts, 0.45):
+            continue
+        obs.append((C, dl + C @ c))
+    out = with_obstacles(base, [obs])
+    out["sigma"] = sigma
+    return out
+
+
 CONFIGS = {
     "c1": config_c1,
     "c2": config_c2,
