@@ -49,10 +49,12 @@ __host__ __device__ inline int traj_gain_floats(int N, int NS, int NU)
 
 // Dynamic LDS floats of the trajectory kernel for padded sizes NS, NU
 // (reverse mode adds the w trajectory).
+__host__ __device__ constexpr int al4(int n) { return (n + 3) & ~3; }
+
 __host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bool adj)
 {
-    return N * nc + N * NS + traj_gain_floats(N, NS, NU) + N * NU + N * NS + (adj ? (N + 1) * NS : 0) + 3 +
-           4 * traj_threads(NS, NU);
+    return al4(N * nc) + al4(N * NS) + al4(traj_gain_floats(N, NS, NU)) + al4(N * NU) + al4(N * NS) +
+           (adj ? al4((N + 1) * NS) : 0) + 4 * traj_threads(NS, NU);
 }
 
 // Fixed-order sum of the float4 src[w * stride], w = w0..w1-1, with eight
@@ -136,6 +138,24 @@ __device__ __forceinline__ void split_sums(int O, int w0, int w1, size_t stride,
         }
         out(tid, v);
     }
+}
+
+// acc + x . y for two 16-byte aligned NS-vectors in LDS (NS a multiple of 4),
+// summed in index order, read as float4.
+template <int NS>
+__device__ __forceinline__ float dot_lds(const float* x, const float* y, float acc)
+{
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    const float4* y4 = reinterpret_cast<const float4*>(y);
+#pragma unroll
+    for (int q = 0; q < NS / 4; ++q) {
+        const float4 a = x4[q], b = y4[q];
+        acc += a.x * b.x;
+        acc += a.y * b.y;
+        acc += a.z * b.z;
+        acc += a.w * b.w;
+    }
+    return acc;
 }
 
 // Riccati sweep and rollout for 4 states and 2 inputs, held in the registers
@@ -316,8 +336,16 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     constexpr int TT = traj_threads(NS, NU);
     constexpr int NSU = NS + 1;
     __shared__ float A[NS * NS], B[NS * NU], Q2[NS * NS], R2[NU * NU], cdyn[NS];
+    // A^T, B^T (their rows are the columns of A, B), P, (P A)^T, (P B)^T and
+    // w: the operands of the sweep's float4 dot products
+    __shared__ __align__(16) float AT[NS * NS];
+    __shared__ __align__(16) float BT[NU * NS];
     __shared__ int hmap[NS * NS], gmap[NS], pmap[NS];
-    __shared__ float Pm[NS * NS], pv[NS], PA[NS * NS], PB[NS * NU], wv[NS];
+    __shared__ __align__(16) float Pm[NS * NS];
+    __shared__ __align__(16) float PAT[NS * NS];
+    __shared__ __align__(16) float PBT[NU * NS];
+    __shared__ __align__(16) float wv[NS];
+    __shared__ float pv[NS];
     __shared__ float Quu[NU * NU], Qux[NU * NS], qu[NU], Qxx[NS * NS], qx[NS];
     __shared__ float xbuf[2][NS];
     extern __shared__ __align__(16) float dyn[];
@@ -327,18 +355,17 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     const int ns = P.n_s, nu = P.n_u, N = P.N, nq = P.nq, nc = P.nc;
     // deviation coordinates about the current iterate (else base point 0)
     const bool dev = !ADJ && !obstacle_free;
+    // regions start at 16-byte boundaries (sizes rounded up to 4 floats)
     float* Hq = dyn;                       // [N][nc] reduced contributions
-    float* qr = Hq + N * nc;               // [N][NS] stage gradients g_t (reverse: -xbar_t), t = 1..N
-    float* Kall = qr + N * NS;             // [N][NU][NS+1] gains [K | k]
+    float* qr = Hq + al4(N * nc);          // [N][NS] stage gradients g_t (reverse: -xbar_t), t = 1..N
+    float* Kall = qr + al4(N * NS);        // [N][NU][NS+1] gains [K | k]
     float* sx = Kall;                      // staged before the sweep: [N+1][NS] x (reverse: x^K)
     float* sxr = sx + (N + 1) * NS;        //   [N+1][NS] x_ref
     float* su = sxr + (N + 1) * NS;        //   [N][NU] u (reverse: u^K)
-    float* rin = Kall + traj_gain_floats(N, NS, NU);   // [N][NU] input gradients 2 Q_u u^k_t (reverse: -ubar_t)
-    float* off = rin + N * NU;             // [N][NS] dynamics offsets f_t (c when the base is 0)
-    float* wl = off + N * NS;              // reverse: [N+1][NS] w_t
-    // [TT] chunk sums of split_sums, at a 16-byte boundary
-    const int red_off = (int)((wl + (ADJ ? (N + 1) * NS : 0)) - dyn);
-    float4* red4 = reinterpret_cast<float4*>(dyn + ((red_off + 3) & ~3));
+    float* rin = Kall + al4(traj_gain_floats(N, NS, NU));   // [N][NU] input gradients 2 Q_u u^k_t (reverse: -ubar_t)
+    float* off = rin + al4(N * NU);        // [N][NS] dynamics offsets f_t (c when the base is 0)
+    float* wl = off + al4(N * NS);         // reverse: [N+1][NS] w_t
+    float4* red4 = reinterpret_cast<float4*>(wl + (ADJ ? al4((N + 1) * NS) : 0));   // [TT] chunk sums of split_sums
 
     // 0. padded model and cost, pose-coordinate maps
     for (int e = tid; e < NS * NS; e += TT) {
@@ -361,7 +388,13 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     }
     for (int e = tid; e < NS * NU; e += TT) {
         const int i = e / NU, j = e % NU;
-        B[e] = (i < ns && j < nu) ? P.B_dyn[i * nu + j] : 0.f;
+        const float v = (i < ns && j < nu) ? P.B_dyn[i * nu + j] : 0.f;
+        B[e] = v;
+        BT[j * NS + i] = v;
+    }
+    for (int e = tid; e < NS * NS; e += TT) {
+        const int i = e / NS, j = e % NS;
+        AT[j * NS + i] = (i < ns && j < ns) ? P.A_dyn[i * ns + j] : 0.f;
     }
     for (int e = tid; e < NU * NU; e += TT) {
         const int i = e / NU, j = e % NU;
@@ -517,18 +550,17 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         __syncthreads();
     } else {
     // 2. backward Riccati sweep, V_t(x) = 1/2 x^T P x + p^T x, P_N = H_N.
-    //    Every phase is one strided dot product per thread, so a wave never
-    //    runs several output types one after the other:
-    //      out = bias + sum_k X[k * xs] Y[k * ys]
-    //    (a) PA = P A, PB = P B, w = P f_t + p;
+    //    Every phase is one dot product of two contiguous, 16-byte aligned
+    //    NS-vectors in LDS per thread (read as float4), so a wave never runs
+    //    several output types one after the other:
+    //    (a) (P A)^T, (P B)^T (stored transposed, so that (b) reads their
+    //        columns as rows), w = P f_t + p;
     //    (b) Quu = 2Q_u + B^T PB, Qux = B^T PA, qu = B^T w + input gradient,
-    //        Qxx = H_t + A^T PA, qx = h_t + A^T w (t >= 1);
+    //        Qxx = H_t + A^T PA, qx = h_t + A^T w (t >= 1), with A^T and B^T
+    //        kept in LDS beside A and B;
     //    (c) gains [K | k] = -Quu^{-1} [Qux | qu] and the update
     //        P_t = Qxx + Qux^T K (symmetrised), p_t = qx + Qux^T k: each
     //        thread factors the small Quu itself, so (c) needs no extra barrier.
-    //    (Folding (a) into (b) for tiny NS, NS^2 terms per output, measured
-    //    slower than the extra barrier on gfx950.)
-    constexpr bool kFold = false;
     // the linear stage terms of the forward pass carry the pose-block
     // gradients of the pair contributions; the adjoint LQ has none
     auto lin = [&](int t, int i) -> float {
@@ -581,52 +613,20 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         if (b_type == 2) bias = rin[t * NU + b_i];
         else if (b_type == 3 && t >= 1) bias += b_hm >= 0 ? Hq[(t - 1) * nc + b_hm] : 0.f;
         else if (b_type == 4 && t >= 1) bias = qr[(t - 1) * NS + b_i] + (b_hm >= 0 ? Hq[(t - 1) * nc + b_hm] : 0.f);
-        if (!kFold) {
-            // (a)
-            if (a_type >= 0) {
-                const float* X = Pm + a_i * NS;
-                const float* Y = a_type == 0 ? A + a_j : (a_type == 1 ? B + a_j : ft);
-                const int ys = a_type == 0 ? NS : (a_type == 1 ? NU : 1);
-                float acc = a_type == 2 ? pv[a_i] : 0.f;
-#pragma unroll
-                for (int k2 = 0; k2 < NS; ++k2) acc += X[k2] * Y[k2 * ys];
-                float* O = a_type == 0 ? PA + a_i * NS + a_j : (a_type == 1 ? PB + a_i * NU + a_j : wv + a_i);
-                *O = acc;
-            }
-            __syncthreads();
+        // (a)
+        if (a_type >= 0) {
+            const float* Y = a_type == 0 ? AT + a_j * NS : (a_type == 1 ? BT + a_j * NS : ft);
+            const float acc = dot_lds<NS>(Pm + a_i * NS, Y, a_type == 2 ? pv[a_i] : 0.f);
+            float* O = a_type == 0 ? PAT + a_j * NS + a_i : (a_type == 1 ? PBT + a_j * NS + a_i : wv + a_i);
+            *O = acc;
         }
+        __syncthreads();
         // (b)
         if (b_type >= 0 && (t >= 1 || b_type <= 2)) {
-            // X: column b_i of B (types 0-2) or of A (types 3-4)
-            const float* X = b_type <= 2 ? B + b_i : A + b_i;
-            const int xs = b_type <= 2 ? NU : NS;
-            float acc = bias;
-            if (kFold) {
-                // Y column j of P B, P A or the vector P f_t + p, formed here
-#pragma unroll
-                for (int k2 = 0; k2 < NS; ++k2) {
-                    float y;
-                    if (b_type == 0) {
-                        y = 0.f;
-#pragma unroll
-                        for (int l = 0; l < NS; ++l) y += Pm[k2 * NS + l] * B[l * NU + b_j];
-                    } else if (b_type == 1 || b_type == 3) {
-                        y = 0.f;
-#pragma unroll
-                        for (int l = 0; l < NS; ++l) y += Pm[k2 * NS + l] * A[l * NS + b_j];
-                    } else {
-                        y = pv[k2];
-#pragma unroll
-                        for (int l = 0; l < NS; ++l) y += Pm[k2 * NS + l] * ft[l];
-                    }
-                    acc += X[k2 * xs] * y;
-                }
-            } else {
-                const float* Y = b_type == 0 ? PB + b_j : ((b_type == 1 || b_type == 3) ? PA + b_j : wv);
-                const int ys = b_type == 0 ? NU : ((b_type == 1 || b_type == 3) ? NS : 1);
-#pragma unroll
-                for (int k2 = 0; k2 < NS; ++k2) acc += X[k2 * xs] * Y[k2 * ys];
-            }
+            // X: column b_i of B (types 0-2) or of A (types 3-4), as a row of B^T / A^T
+            const float* X = b_type <= 2 ? BT + b_i * NS : AT + b_i * NS;
+            const float* Y = b_type == 0 ? PBT + b_j * NS : ((b_type == 1 || b_type == 3) ? PAT + b_j * NS : wv);
+            const float acc = dot_lds<NS>(X, Y, bias);
             float* O = b_type == 0 ? Quu + b_i * NU + b_j
                      : b_type == 1 ? Qux + b_i * NS + b_j
                      : b_type == 2 ? qu + b_i
