@@ -51,10 +51,14 @@ __host__ __device__ inline int traj_gain_floats(int N, int NS, int NU)
 // (reverse mode adds the w trajectory).
 __host__ __device__ constexpr int al4(int n) { return (n + 3) & ~3; }
 
-__host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bool adj)
+// The last region holds the chunk sums of the per-step sums (4 TT floats),
+// and afterwards, for the closed-loop rollout (cl), A + B K_t and f_t + B k_t
+// of every step (N NS (NS + 1) floats).
+__host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bool adj, bool cl)
 {
+    const int tail = cl && N * NS * (NS + 1) > 4 * traj_threads(NS, NU) ? N * NS * (NS + 1) : 4 * traj_threads(NS, NU);
     return al4(N * nc) + al4(N * NS) + al4(traj_gain_floats(N, NS, NU)) + al4(N * NU) + al4(N * NS) +
-           (adj ? al4((N + 1) * NS) : 0) + 4 * traj_threads(NS, NU);
+           (adj ? al4((N + 1) * NS) : 0) + tail;
 }
 
 // Fixed-order sum of the float4 src[w * stride], w = w0..w1-1, with eight
@@ -331,7 +335,7 @@ __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, 
 // and an identity input-cost block, so every small product unrolls.
 template <int NS, int NU, bool ADJ>
 __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevProblem P, int obstacle_free,
-                                                                          float* hq_save, TrajAdjoint TA)
+                                                                          float* hq_save, TrajAdjoint TA, int cl)
 {
     constexpr int TT = traj_threads(NS, NU);
     constexpr int NSU = NS + 1;
@@ -347,7 +351,8 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     __shared__ __align__(16) float wv[NS];
     __shared__ float pv[NS];
     __shared__ float Quu[NU * NU], Qux[NU * NS], qu[NU], Qxx[NS * NS], qx[NS];
-    __shared__ float xbuf[2][NS];
+    __shared__ __align__(16) float xbuf[2][NS];
+    __shared__ float x0s[NS];
     extern __shared__ __align__(16) float dyn[];
     const int s = blockIdx.x;
     if (!ADJ && !obstacle_free && P.done[s]) return;
@@ -706,6 +711,56 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         }
         __syncthreads();
     }
+    if (cl) {
+    // 3. rollout on the closed loop, dx_{t+1} = (A + B K_t) dx_t + (f_t + B k_t):
+    //    the matrices of all steps are formed first, in parallel, so that a
+    //    step is one float4 dot product per state (thread i owns dx_i); the
+    //    inputs du_t = K_t dx_t + k_t follow in parallel over t.
+    float* Acl = reinterpret_cast<float*>(red4);          // [N][NS][NS]
+    float* Ccl = Acl + (size_t)N * NS * NS;               // [N][NS]
+    for (int e = tid; e < N * NS * (NS + 1); e += TT) {
+        const int t = e / (NS * (NS + 1)), r = e % (NS * (NS + 1));
+        const int i = r / (NS + 1), j = r % (NS + 1);     // j = NS: the offset
+        const float* Kt = Kall + (size_t)t * NU * NSU;
+        float acc = j < NS ? A[i * NS + j] : off[t * NS + i];
+#pragma unroll
+        for (int c = 0; c < NU; ++c) acc += B[i * NU + c] * Kt[c * NSU + j];
+        if (j < NS) Acl[((size_t)t * NS + i) * NS + j] = acc;
+        else Ccl[t * NS + i] = acc;
+    }
+    if (tid < NS) {
+        float v = 0.f;
+        if (!ADJ && tid < ns) {
+            const float x0v = P.x0[(size_t)s * ns + tid];
+            v = dev ? x0v - xo[tid] : x0v;
+        }
+        xbuf[0][tid] = v;
+        x0s[tid] = v;
+        if (ADJ) wl[tid] = 0.f;
+    }
+    __syncthreads();
+    for (int t = 0; t < N; ++t) {
+        if (tid < NS) {
+            const float acc = dot_lds<NS>(Acl + ((size_t)t * NS + tid) * NS, xbuf[t & 1], Ccl[t * NS + tid]);
+            xbuf[(t + 1) & 1][tid] = acc;
+            if (ADJ) wl[(t + 1) * NS + tid] = acc;
+            else dX[t * NS + tid] = acc;
+        }
+        __syncthreads();
+    }
+    if (!ADJ) {
+        for (int e = tid; e < N * NU; e += TT) {
+            const int t = e / NU, c = e % NU;
+            const float* Kt = Kall + (size_t)t * NU * NSU + c * NSU;
+            const float* xt = t == 0 ? x0s : dX + (t - 1) * NS;
+            float u = Kt[NS];
+#pragma unroll
+            for (int k2 = 0; k2 < NS; ++k2) u += Kt[k2] * xt[k2];
+            dU[e] = u;
+        }
+        __syncthreads();
+    }
+    } else {
     // 3. rollout dx_{t+1} = A dx + B (K dx + k) + f_t; thread i owns dx_i
     //    (rows of A and B in registers), threads NS..NS+NU-1 the inputs. The
     //    deviations stay in LDS (forward: over qr and rin, dead after the
@@ -759,6 +814,7 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
             }
         }
         __syncthreads();
+    }
     }
     }
     if (!ADJ) {
@@ -815,18 +871,26 @@ static hipError_t launch_traj(const DevProblem& P, int obstacle_free, float* hq_
                               hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
 {
     dim3 g(P.n_scen);
+    // closed-loop rollout where its matrices fit in the 64 KB of LDS beside
+    // the rest (the static arrays take 5.3 KB at 12/4, 10.1 KB at 16/8)
+    auto cl_fits = [&](int NS, int NU) {
+        const size_t budget = NS <= 12 ? 56 * 1024 : 52 * 1024;
+        return (size_t)traj_dyn_floats(P.N, NS, NU, P.nc, ADJ, true) * sizeof(float) <= budget;
+    };
     if (P.n_s <= 4 && P.n_u <= 2) {
         const dim3 b(traj_threads(4, 2));
-        CADMM_LAUNCH((traj_phase_kernel<4, 2, ADJ>), g, b,
-                           sizeof(float) * traj_dyn_floats(P.N, 4, 2, P.nc, ADJ), st, e0, e1, P, obstacle_free, hq_save, TA);
+        CADMM_LAUNCH((traj_phase_kernel<4, 2, ADJ>), g, b, sizeof(float) * traj_dyn_floats(P.N, 4, 2, P.nc, ADJ, false),
+                     st, e0, e1, P, obstacle_free, hq_save, TA, 0);
     } else if (P.n_s <= 12 && P.n_u <= 4) {
         const dim3 b(traj_threads(12, 4));
-        CADMM_LAUNCH((traj_phase_kernel<12, 4, ADJ>), g, b,
-                           sizeof(float) * traj_dyn_floats(P.N, 12, 4, P.nc, ADJ), st, e0, e1, P, obstacle_free, hq_save, TA);
+        const bool cl = cl_fits(12, 4);
+        CADMM_LAUNCH((traj_phase_kernel<12, 4, ADJ>), g, b, sizeof(float) * traj_dyn_floats(P.N, 12, 4, P.nc, ADJ, cl),
+                     st, e0, e1, P, obstacle_free, hq_save, TA, cl ? 1 : 0);
     } else {
         const dim3 b(traj_threads(16, 8));
-        CADMM_LAUNCH((traj_phase_kernel<16, 8, ADJ>), g, b,
-                           sizeof(float) * traj_dyn_floats(P.N, 16, 8, P.nc, ADJ), st, e0, e1, P, obstacle_free, hq_save, TA);
+        const bool cl = cl_fits(16, 8);
+        CADMM_LAUNCH((traj_phase_kernel<16, 8, ADJ>), g, b, sizeof(float) * traj_dyn_floats(P.N, 16, 8, P.nc, ADJ, cl),
+                     st, e0, e1, P, obstacle_free, hq_save, TA, cl ? 1 : 0);
     }
     return hipGetLastError();
 }
