@@ -452,14 +452,15 @@ int autotune(cadmm_handle* h, int fixed_W, int fixed_G)
             if (W > 1 && W / 2 >= L.n_blocks) continue;
             if ((rc = upload_worklists(h, W))) return rc;
             h->G = G;
-            // four iterations' pair and trajectory phases from the snapshot
-            // (a spread of pair difficulty), best of three runs after one
-            // that warms caches and code
+            // sixteen iterations' pair and trajectory phases from the snapshot
+            // (the spread of pair difficulty of a solve: shorter windows
+            // ranked the lane-group sizes differently from whole solves),
+            // best of two runs after one that warms caches and code
             float tot = 1e30f;
-            for (int rep = 0; rep < 4; ++rep) {
+            for (int rep = 0; rep < 3; ++rep) {
                 if ((rc = restore())) return rc;
                 HIP_TRY(hipEventRecord(e0, st));
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < 16; ++k) {
                     HIP_TRY(launch_pair_phase(h->P, h->W, h->G, h->grid, st));
                     HIP_TRY(launch_traj_phase(h->P, 0, st));
                 }
