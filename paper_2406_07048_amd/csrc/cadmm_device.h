@@ -13,7 +13,11 @@ namespace cadmm {
 // small dense helpers (fully unrolled, registers only)
 // ------------------------------------------------------------------------
 
-// In-place Cholesky solve of an SPD system H x = g (H full NV x NV).
+// In-place Cholesky solve of an SPD system H x = g (H full NV x NV). The
+// pivots use v_rsq_f32 (about 1 ulp) and the factor keeps 1 / l_jj on its
+// diagonal, so the factorisation and both substitutions multiply instead of
+// running IEEE square roots and divisions (each an instruction sequence of
+// its own, together most of a small Newton step's VALU work).
 template <int NV>
 __device__ __forceinline__ void chol_solve(float (&H)[NV * NV], float (&g)[NV])
 {
@@ -22,10 +26,8 @@ __device__ __forceinline__ void chol_solve(float (&H)[NV * NV], float (&g)[NV])
         float s = H[j * NV + j];
 #pragma unroll
         for (int k = 0; k < j; ++k) s -= H[j * NV + k] * H[j * NV + k];
-        s = fmaxf(s, 1e-30f);
-        const float L = sqrtf(s);
-        const float iL = 1.0f / L;
-        H[j * NV + j] = L;
+        const float iL = __builtin_amdgcn_rsqf(fmaxf(s, 1e-30f));
+        H[j * NV + j] = iL;
 #pragma unroll
         for (int i = j + 1; i < NV; ++i) {
             float t = H[i * NV + j];
@@ -39,14 +41,14 @@ __device__ __forceinline__ void chol_solve(float (&H)[NV * NV], float (&g)[NV])
         float s = g[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) s -= H[i * NV + k] * g[k];
-        g[i] = s / H[i * NV + i];
+        g[i] = s * H[i * NV + i];
     }
 #pragma unroll
     for (int i = NV - 1; i >= 0; --i) {
         float s = g[i];
 #pragma unroll
         for (int k = i + 1; k < NV; ++k) s -= H[k * NV + i] * g[k];
-        g[i] = s / H[i * NV + i];
+        g[i] = s * H[i * NV + i];
     }
 }
 

@@ -249,7 +249,8 @@ struct GenRows {
 #pragma unroll
             for (int c = 0; c <= DIM; ++c) { k[c] = K[l * (DIM + 1) + c]; D += k[c] * k[c]; }
             const float kl = kap[l];
-            const float ie = 1.0f / (eps * D);
+            // v_rcp_f32 / v_rsq_f32 (about 1 ulp): this runs per row and per pass
+            const float ie = __builtin_amdgcn_rcpf(eps * D);
             float s = -kl * z[DIM + 1];
 #pragma unroll
             for (int c = 0; c <= DIM; ++c) s += k[c] * z[c];
@@ -257,7 +258,7 @@ struct GenRows {
 #pragma unroll
             for (int c = 0; c <= DIM; ++c) gv[c] += y * k[c];
             gnu += kl * y;
-            ysc += y * sqrtf(D);
+            ysc += y * (D * __builtin_amdgcn_rsqf(fmaxf(D, 1e-30f)));
             if (HESS && y > 0.f) {
                 float w[NV];
 #pragma unroll
@@ -1218,7 +1219,7 @@ __global__ void __launch_bounds__(256) pair_qp_batch_kernel(int n_pairs, const i
             D += k * k;
             s += k * z[c];
         }
-        const float yl = fmaxf(0.f, gr.yh[l] - s / (eps * D));
+        const float yl = fmaxf(0.f, gr.yh[l] - s * __builtin_amdgcn_rcpf(eps * D));
         y[r0 + l] = yl;
 #pragma unroll
         for (int c = 0; c <= DIM; ++c) rr[c] += yl * gr.K[l * (DIM + 1) + c];
