@@ -231,6 +231,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--shape", default="", metavar="W,G",
+                    help="fix the pair-kernel launch shape of the main workload (blocks per workgroup W, lanes "
+                         "per pair G) instead of autotuning it; the counter runs behind profiles/ use the "
+                         "shape the autotuner picks, so that their dispatches are the bench's")
     ap.add_argument("--source-hash", action="store_true", help="print the hash of the kernel sources and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device-to-device copy of MIB MiB (the reference for the HBM "
@@ -258,7 +262,11 @@ def main():
     wl = WORKLOADS[args.workload]
     prob = workloads.make(args.workload)
     iters = wl["iters"]
-    h = cadmm.Handle(prob)
+    if args.shape:
+        sw, sg = (int(v) for v in args.shape.split(","))
+        h = cadmm.Handle(prob, waves_per_group=sw, lanes_per_pair=sg)
+    else:
+        h = cadmm.Handle(prob)
     W, n_wg, G = h.launch_config()
     _, nb, npairs, yf = cadmm.cadmm_workspace_size(prob)
     for _ in range(args.warmup):

@@ -387,7 +387,7 @@ __device__ int dual_newton(const Rows& rows, float (&z)[NV], int max_sweeps, flo
             float lo = 0.f, hi = 1.f, flo = d0, fhi = d1;
             int side = 0;
             for (int ls = 0; ls < 6; ++ls) {
-                al = (lo * (-fhi) + hi * flo) / (flo - fhi);
+                al = (lo * (-fhi) + hi * flo) * __builtin_amdgcn_rcpf(flo - fhi);
                 const float fa = dphi(al);
                 if (fa >= -1e-3f * d0) {
                     lo = al; flo = fa;
@@ -534,7 +534,7 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
                     const float yk = yb[k * N];
                     pr.yhR[m] = yk;
                     const float D = f.x * f.x + f.y * f.y + (DIM == 3 ? f.z * f.z : 0.f);
-                    pr.ieR[m] = 1.0f / (eps * D);
+                    pr.ieR[m] = __builtin_amdgcn_rcpf(eps * D);
                     vr[0] += yk * f.x;
                     vr[1] += yk * f.y;
                     if (DIM == 3) vr[DIM - 1] += yk * f.z;
@@ -555,7 +555,7 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
 #pragma unroll
                     for (int r = 0; r < DIM; ++r) cn += c[r] * c[r];
                     const float D = dp * dp + cn;
-                    pr.ieO[m] = 1.0f / (eps * D);
+                    pr.ieO[m] = __builtin_amdgcn_rcpf(eps * D);
                     pr.dpO[m] = dp;
                     v0 += dp * yl;
 #pragma unroll
