@@ -168,14 +168,14 @@ __device__ __forceinline__ float dot_lds(const float* x, const float* y, float a
 // block reaches lane (i, j) by quad broadcasts, column j by rotations of the
 // row by 4, 8 and 12 lanes, so the sweep needs no barrier. Per step, with P = P_{t+1}:
 //   (a) PA = P A, PAT = (P A)^T (P symmetric), PB_{i, j mod 2} = (P B), w = P f_t + p;
-//   (b) Qxx = H_t + A^T PA and its transpose, Qux_{i mod 2, j} = (B^T PA),
-//       Qux^T, Quu = 2Q_u + B^T PB, qu = r_t + B^T w, qx = h_t + A^T w;
+//   (b) Qxx = H_t + A^T PA, Qux_{i mod 2, j} = (B^T PA) and from PAT its
+//       transpose, Quu = 2Q_u + B^T PB, qu = r_t + B^T w, qx = h_t + A^T w;
 //   (c) K = -Quu^{-1} Qux, k = -Quu^{-1} qu (2 x 2 inverse by its adjugate),
-//       P_t = Qxx - Qux^T Quu^{-1} Qux averaged with its transpose,
-//       p_t = qx - Qux^T Quu^{-1} qu.
+//       P_t = Qxx - Qux^T Quu^{-1} Qux, p_t = qx - Qux^T Quu^{-1} qu.
 // The sums over rows run in the lane's rotation order, so lanes that hold
 // the same entry may differ in the last bits; P_t is made exactly symmetric
-// by one ds_bpermute per step. The step-dependent LDS terms
+// by one ds_bpermute per step (the lanes below the diagonal take the values
+// of those above it). The step-dependent LDS terms
 // of step t - 1 are read while step t computes. Gains go to Kall[t][2][5];
 // the rollout then keeps dx_r in lane r (quads repeat) and writes dx
 // (forward: dX[t][4], du in dU[t][2]; reverse: w in W[t + 1][4]).
@@ -200,18 +200,17 @@ __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, 
         Arot[k] = A[km[k] * 4 + i];
         Brot[k] = B[km[k] * 2 + a];
     }
-    const float q2ij = Q2[i * 4 + j], q2ji = Q2[j * 4 + i], r2ab = R2[a * 2 + b];
-    const int hmij = hmap[i * 4 + j], hmji = hmap[j * 4 + i], gmi = ADJ ? -1 : gmap[i];
+    const float q2ij = Q2[i * 4 + j], r2ab = R2[a * 2 + b];
+    const int hmij = hmap[i * 4 + j], gmi = ADJ ? -1 : gmap[i];
     const int tsrc = (((int)threadIdx.x & ~15) | (i <= j ? lane : j * 4 + i)) << 2;   // ds_bpermute byte address
     float Pv = q2ij + (hmij >= 0 ? Hq[(N - 1) * nc + hmij] : 0.f);
     float pv = qr[(N - 1) * 4 + i] + (gmi >= 0 ? Hq[(N - 1) * nc + gmi] : 0.f);
-    // step-dependent terms of step t: H_{t-1} (i, j) and (j, i), h_{t-1}(i), f_t, r_t
-    float nHij = 0.f, nHji = 0.f, nh = 0.f, nf[4], nr;
+    // step-dependent terms of step t: H_{t-1} (i, j), h_{t-1}(i), f_t, r_t
+    float nHij = 0.f, nh = 0.f, nf[4], nr;
     auto fetch = [&](int t) {
         if (t >= 1) {
             const float* hq = Hq + (t - 1) * nc;
             nHij = q2ij + (hmij >= 0 ? hq[hmij] : 0.f);
-            nHji = q2ji + (hmji >= 0 ? hq[hmji] : 0.f);
             nh = qr[(t - 1) * 4 + i] + (gmi >= 0 ? hq[gmi] : 0.f);
         }
 #pragma unroll
@@ -220,7 +219,7 @@ __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, 
     };
     fetch(N - 1);
     for (int t = N - 1; t >= 0; --t) {
-        const float Hij = nHij, Hji = nHji, h = nh, r = nr;
+        const float Hij = nHij, h = nh, r = nr;
         float f[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) f[k] = nf[k];
@@ -271,24 +270,20 @@ __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, 
             }
         }
         if (t >= 1) {
-            float Qxx = Hij, qx = h, QxxT = Hji, QuxT = 0.f;
+            float Qxx = Hij, qx = h, QuxT = 0.f;
             const float PATb[4] = {quad_bcast<0>(PAT), quad_bcast<1>(PAT), quad_bcast<2>(PAT), quad_bcast<3>(PAT)};
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 Qxx += Arot[k] * PAr[k];
                 qx += Arot[k] * wr[k];
-                QxxT += Acol[k] * PATb[k];
                 QuxT += Bcol[k] * PATb[k];
             }
             const float U0i = quad_bcast<0>(QuxT), U1i = quad_bcast<1>(QuxT);
-            const float G0i = I00 * U0i + I01 * U1i, G1i = I01 * U0i + I11 * U1i;
             const float pij = Qxx - (U0i * G0j + U1i * G1j);
-            const float pji = QxxT - (U0j * G0i + U1j * G1i);
             // exact symmetry: lane (i, j), i > j, takes the value of lane (j, i)
-            // (an antisymmetric part would not be removed by the averaging
-            // and grows along the sweep)
-            Pv = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
-                     tsrc, __builtin_bit_cast(int, 0.5f * (pij + pji))));
+            // (the two lanes sum in different orders; an antisymmetric part
+            // would grow along the sweep)
+            Pv = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(tsrc, __builtin_bit_cast(int, pij)));
             pv = qx - (U0i * g0 + U1i * g1);
         }
     }
