@@ -175,9 +175,13 @@ int admm_get_history(cadmm_handle* h, int max_rows, float* r_pri, float* r_dual)
 int admm_scales(cadmm_handle* h, float* alpha);
 
 /* Profiling: run n_iters iterations with eager (non-graph) launches and
- * HIP events around each phase on the handle's stream; ms_out[4] receives
- * the mean milliseconds of (pair QPs + contributions, trajectory QP,
- * multiplier update, residual test). Advances the iterate. Syncs. */
+ * events recorded around each kernel's own execution (hipExtLaunchKernel)
+ * on the handle's stream, one set per iteration, read after one
+ * synchronisation at the end; ms_out[4] receives the mean milliseconds of
+ * (pair QPs + contributions, trajectory QP, multiplier update, residual
+ * test). The durations include the dispatch overhead the events carry (a
+ * few microseconds above a profiler's kernel times). Advances the iterate.
+ * Syncs. */
 int admm_phase_times(cadmm_handle* h, int n_iters, float* ms_out);
 
 /* Launch shape chosen at setup (autotuned unless fixed in the descriptor):
