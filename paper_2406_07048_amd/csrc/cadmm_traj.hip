@@ -183,7 +183,7 @@ template <bool ADJ>
 __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, const float* Q2, const float* R2,
                                                 const int* hmap, const int* gmap, const float* Hq, const float* qr,
                                                 const float* rin, const float* off, float* Kall, float* dX, float* dU,
-                                                float* W, int N, int nc, float x0dev)
+                                                float* W, int N, int nc, float x0dev, bool rollout)
 {
     const int lane = threadIdx.x & 15;
     const int i = lane >> 2, j = lane & 3, a = i & 1, b = j & 1;
@@ -287,6 +287,7 @@ __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, 
             pv = qx - (U0i * g0 + U1i * g1);
         }
     }
+    if (!rollout) return;
     // rollout: lane r = j of each quad holds dx_r
     float Ar[4], Br[2];
 #pragma unroll
@@ -322,6 +323,82 @@ __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, 
             if (!ADJ && j < 2) dU[t * 2 + j] = j == 0 ? u0 : u1;
         }
         xv = xn;
+    }
+}
+
+// Rollout of the 4/2 closed loop x_{t+1} = M_t x_t + c_t, M_t = A + B K_t,
+// c_t = B k_t + f_t (gains [K | k] in Kall[t][2][5], offsets f_t in off), by
+// a log-depth inclusive scan of the affine maps: G_t <- G_t o G_{t-d} for
+// d = 1, 2, 4, ... (Hillis-Steele), one map entry (16 of M, 4 of c) per
+// thread, in two buffers of N * 20 floats; then x_{t+1} = G_t(x_0) and
+// u_t = K_t x_t + k_t, all steps at once. Replaces the N dependent steps of
+// the sequential rollout by ceil(log2 N) compositions. Writes dX[t][4] =
+// x_{t+1} and dU[t][2] = u_t (reverse mode: W[t + 1][4] = x_{t+1}).
+template <bool ADJ, int TT>
+__device__ __forceinline__ void rollout_scan_42(const float* A, const float* B, const float* Kall, const float* off,
+                                                const float* x0, float* buf, float* dX, float* dU, float* W, int N)
+{
+    const int tid = threadIdx.x;
+    const int ne = N * 20;
+    float* cur = buf;
+    float* nxt = buf + ne;
+    for (int e = tid; e < ne; e += TT) {
+        const int t = e / 20, q = e % 20;
+        const float* K = Kall + t * 10;
+        float v;
+        if (q < 16) {
+            const int i = q >> 2, j = q & 3;
+            v = A[i * 4 + j] + B[i * 2] * K[j] + B[i * 2 + 1] * K[5 + j];
+        } else {
+            const int i = q - 16;
+            v = off[t * 4 + i] + B[i * 2] * K[4] + B[i * 2 + 1] * K[9];
+        }
+        cur[e] = v;
+    }
+    __syncthreads();
+    for (int d = 1; d < N; d <<= 1) {
+        for (int e = tid; e < ne; e += TT) {
+            const int t = e / 20, q = e % 20;
+            float v = cur[e];
+            if (t >= d) {
+                // [M_t | c_t] times column j of [G_{t-d} | g_{t-d}] (j = 4: the offset column,
+                // plus c_t)
+                const float* Mt = cur + t * 20;
+                const float* Gp = cur + (t - d) * 20;
+                const bool mat = q < 16;
+                const int i = mat ? q >> 2 : q - 16;
+                const int base = mat ? (q & 3) : 16, stride = mat ? 4 : 1;
+                v = mat ? 0.f : Mt[16 + i];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v += Mt[i * 4 + k] * Gp[base + k * stride];
+            }
+            nxt[e] = v;
+        }
+        __syncthreads();
+        float* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    for (int e = tid; e < N * 4; e += TT) {
+        const int t = e >> 2, i = e & 3;
+        const float* G = cur + t * 20;
+        float v = G[16 + i];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v += G[i * 4 + k] * x0[k];
+        if (ADJ) W[(t + 1) * 4 + i] = v;
+        else dX[t * 4 + i] = v;
+    }
+    if (!ADJ) {
+        __syncthreads();
+        for (int e = tid; e < N * 2; e += TT) {
+            const int t = e >> 1, a = e & 1;
+            const float* K = Kall + t * 10 + 5 * a;
+            const float* xt = t == 0 ? x0 : dX + (t - 1) * 4;
+            float v = K[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v += K[k] * xt[k];
+            dU[t * 2 + a] = v;
+        }
     }
 }
 
@@ -536,7 +613,10 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     float* dX = ADJ ? wl : qr;             // forward: dx_t at (t-1) * NS, t = 1..N; reverse: w_t at t * NS
     float* dU = rin;                       // forward: du_t at t * NU
     if constexpr (NS == 4 && NU == 2) {
-        // 2-3. the sweep and the rollout in the registers of wave 0
+        // 2. the sweep in the registers of wave 0; 3. the rollout by a scan
+        // over all threads where its two buffers fit in the chunk-sum region
+        // (N <= 102), else in the registers of wave 0 after the sweep
+        const bool scan = 40 * N <= 4 * TT;
         if (tid < 64) {
             const int r = tid & 3;
             float x0d = 0.f;
@@ -545,9 +625,14 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
                 x0d = dev ? x0v - xo[r] : x0v;
             }
             if (ADJ && tid < 4) wl[tid] = 0.f;
-            riccati_regs_42<ADJ>(A, B, Q2, R2, hmap, gmap, Hq, qr, rin, off, Kall, dX, dU, wl, N, nc, x0d);
+            if (scan && tid < 4) x0s[tid] = x0d;
+            riccati_regs_42<ADJ>(A, B, Q2, R2, hmap, gmap, Hq, qr, rin, off, Kall, dX, dU, wl, N, nc, x0d, !scan);
         }
         __syncthreads();
+        if (scan) {
+            rollout_scan_42<ADJ, TT>(A, B, Kall, off, x0s, reinterpret_cast<float*>(red4), dX, dU, wl, N);
+            __syncthreads();
+        }
     } else {
     // 2. backward Riccati sweep, V_t(x) = 1/2 x^T P x + p^T x, P_N = H_N.
     //    Every phase is one dot product of two contiguous, 16-byte aligned
