@@ -2,6 +2,7 @@
 // path (arXiv 2406.07048, Sec. IV-B state update): per-step sums of the pair
 // contributions, the backward Riccati sweep and the forward rollout, in
 // forward mode and as the adjoint LQ of the reverse pass.
+#include "cadmm.h"
 #include "cadmm_device.h"
 
 #include <float.h>
@@ -162,7 +163,7 @@ __device__ __forceinline__ float dot_lds(const float* x, const float* y, float a
     return acc;
 }
 
-// Riccati sweep and rollout for 4 states and 2 inputs, held in the registers
+// Riccati sweep for 4 states and 2 inputs, held in the registers
 // of one wave: lane (i, j) = 4 i + j of each row of 16 lanes owns entry
 // (i, j) of the 4 x 4 blocks (rows 1-3 of the wave repeat row 0). Row i of a
 // block reaches lane (i, j) by quad broadcasts, column j by rotations of the
@@ -176,14 +177,12 @@ __device__ __forceinline__ float dot_lds(const float* x, const float* y, float a
 // the same entry may differ in the last bits; P_t is made exactly symmetric
 // by one ds_bpermute per step (the lanes below the diagonal take the values
 // of those above it). The step-dependent LDS terms
-// of step t - 1 are read while step t computes. Gains go to Kall[t][2][5];
-// the rollout then keeps dx_r in lane r (quads repeat) and writes dx
-// (forward: dX[t][4], du in dU[t][2]; reverse: w in W[t + 1][4]).
+// of step t - 1 are read while step t computes. Gains go to Kall[t][2][5]
+// for the rollout (rollout_scan_42).
 template <bool ADJ>
 __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, const float* Q2, const float* R2,
                                                 const int* hmap, const int* gmap, const float* Hq, const float* qr,
-                                                const float* rin, const float* off, float* Kall, float* dX, float* dU,
-                                                float* W, int N, int nc, float x0dev, bool rollout)
+                                                const float* rin, const float* off, float* Kall, int N, int nc)
 {
     const int lane = threadIdx.x & 15;
     const int i = lane >> 2, j = lane & 3, a = i & 1, b = j & 1;
@@ -287,43 +286,6 @@ __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, 
             pv = qx - (U0i * g0 + U1i * g1);
         }
     }
-    if (!rollout) return;
-    // rollout: lane r = j of each quad holds dx_r
-    float Ar[4], Br[2];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) Ar[k] = A[j * 4 + k];
-    Br[0] = B[j * 2];
-    Br[1] = B[j * 2 + 1];
-    float xv = x0dev;
-    float nK[10], nft;
-    auto fetchK = [&](int t) {
-#pragma unroll
-        for (int q = 0; q < 10; ++q) nK[q] = Kall[t * 10 + q];
-        nft = off[t * 4 + j];
-    };
-    fetchK(0);
-    for (int t = 0; t < N; ++t) {
-        float K[10];
-#pragma unroll
-        for (int q = 0; q < 10; ++q) K[q] = nK[q];
-        const float ft = nft;
-        if (t + 1 < N) fetchK(t + 1);
-        const float xb[4] = {quad_bcast<0>(xv), quad_bcast<1>(xv), quad_bcast<2>(xv), quad_bcast<3>(xv)};
-        float u0 = K[4], u1 = K[9], xn = ft;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            u0 += K[k] * xb[k];
-            u1 += K[5 + k] * xb[k];
-            xn += Ar[k] * xb[k];
-        }
-        xn += Br[0] * u0 + Br[1] * u1;
-        if (threadIdx.x < 4) {
-            if (ADJ) W[(t + 1) * 4 + j] = xn;
-            else dX[t * 4 + j] = xn;
-            if (!ADJ && j < 2) dU[t * 2 + j] = j == 0 ? u0 : u1;
-        }
-        xv = xn;
-    }
 }
 
 // Rollout of the 4/2 closed loop x_{t+1} = M_t x_t + c_t, M_t = A + B K_t,
@@ -331,8 +293,8 @@ __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, 
 // a log-depth inclusive scan of the affine maps: G_t <- G_t o G_{t-d} for
 // d = 1, 2, 4, ... (Hillis-Steele), one map entry (16 of M, 4 of c) per
 // thread, in two buffers of N * 20 floats; then x_{t+1} = G_t(x_0) and
-// u_t = K_t x_t + k_t, all steps at once. Replaces the N dependent steps of
-// the sequential rollout by ceil(log2 N) compositions. Writes dX[t][4] =
+// u_t = K_t x_t + k_t, all steps at once: ceil(log2 N) compositions in
+// place of N dependent steps. Writes dX[t][4] =
 // x_{t+1} and dU[t][2] = u_t (reverse mode: W[t + 1][4] = x_{t+1}).
 template <bool ADJ, int TT>
 __device__ __forceinline__ void rollout_scan_42(const float* A, const float* B, const float* Kall, const float* off,
@@ -614,25 +576,21 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     float* dU = rin;                       // forward: du_t at t * NU
     if constexpr (NS == 4 && NU == 2) {
         // 2. the sweep in the registers of wave 0; 3. the rollout by a scan
-        // over all threads where its two buffers fit in the chunk-sum region
-        // (N <= 102), else in the registers of wave 0 after the sweep
-        const bool scan = 40 * N <= 4 * TT;
-        if (tid < 64) {
-            const int r = tid & 3;
+        // over all threads, its two buffers in the chunk-sum region
+        static_assert(40 * CADMM_MAX_N <= 4 * TT, "rollout scan buffers exceed the chunk-sum region");
+        if (tid < 4) {
             float x0d = 0.f;
-            if (!ADJ && r < ns) {
-                const float x0v = P.x0[(size_t)s * ns + r];
-                x0d = dev ? x0v - xo[r] : x0v;
+            if (!ADJ && tid < ns) {
+                const float x0v = P.x0[(size_t)s * ns + tid];
+                x0d = dev ? x0v - xo[tid] : x0v;
             }
-            if (ADJ && tid < 4) wl[tid] = 0.f;
-            if (scan && tid < 4) x0s[tid] = x0d;
-            riccati_regs_42<ADJ>(A, B, Q2, R2, hmap, gmap, Hq, qr, rin, off, Kall, dX, dU, wl, N, nc, x0d, !scan);
+            x0s[tid] = x0d;
+            if (ADJ) wl[tid] = 0.f;
         }
+        if (tid < 64) riccati_regs_42<ADJ>(A, B, Q2, R2, hmap, gmap, Hq, qr, rin, off, Kall, N, nc);
         __syncthreads();
-        if (scan) {
-            rollout_scan_42<ADJ, TT>(A, B, Kall, off, x0s, reinterpret_cast<float*>(red4), dX, dU, wl, N);
-            __syncthreads();
-        }
+        rollout_scan_42<ADJ, TT>(A, B, Kall, off, x0s, reinterpret_cast<float*>(red4), dX, dU, wl, N);
+        __syncthreads();
     } else {
     // 2. backward Riccati sweep, V_t(x) = 1/2 x^T P x + p^T x, P_N = H_N.
     //    Every phase is one dot product of two contiguous, 16-byte aligned
