@@ -36,6 +36,7 @@ WORKLOADS = {
     "c3": dict(desc="3D quadrotor (3 boxes), 200 hull polyhedra (6-20 faces), N=40, "
                     "24000 pair QPs/iteration, 200 ADMM iterations, sigma=300", iters=200),
     "c1": dict(desc="2D rectangle, 3 obstacles, N=20, 60 pair QPs/iteration, 50 ADMM iterations", iters=50),
+    "c4": dict(desc="256 2D scenarios, obstacles U{10..80}, faces U{3..12}, N=50, 50 ADMM iterations", iters=50),
 }
 
 
@@ -58,11 +59,13 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name):
+def measured_traffic(name, launch=None):
     """HBM bytes per launch of a kernel from the committed counter summary
     profiles/<name>_hbm_traffic.txt (FETCH_SIZE and WRITE_SIZE per dispatch,
     scaled by what the same counters read for a plain copy of known size).
-    None when the summary is missing or was taken from other kernel sources."""
+    None when the summary is missing, was taken from other kernel sources or,
+    given launch = (blocks per workgroup, lanes per pair), at another launch
+    shape."""
     path = os.path.join(ROOT, "profiles", f"{name}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -73,6 +76,8 @@ def measured_traffic(name):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("source_hash") != kernel_source_hash():
+        return None
+    if launch is not None and kv.get("launch") != f"{launch[0]},{launch[1]}":
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -150,8 +155,8 @@ def batched_vs_plain(cadmm, torch, steps=2, iters=50):
                 batched_blocks_per_group=wb[0], batched_lanes_per_pair=wb[2],
                 pair_phase_ms=ph[0], pair_phase_solves_per_s=npairs / (ph[0] * 1e-3),
                 roofline={"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "pair_phase_kernel",
-                          "bytes_per_launch": bytes_launch})
+                          "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic("pair_phase_c4", (wb[0], wb[2])),
+                          "kernel": "pair_phase_kernel", "bytes_per_launch": bytes_launch})
 
 
 def stream_batch(cadmm, torch, n_pairs=1 << 22, reps=5):
