@@ -77,6 +77,7 @@ enum { CADMM_ATT_YAW = 0, CADMM_ATT_EULER_ZYX = 1 };
  *  n_s, n_u, N   state size, input size, horizon (1..CADMM_MAX_N)
  *  n_parts, part_face_ptr[n_parts+1], part_A[F_r*dim], part_b[F_r] (> 0),
  *      part_off[n_parts*dim]        robot parts {x : A_i x <= b_i}, centre o_i
+ *                                   (1 <= n_parts <= 32767)
  *  n_scen, obs_ptr[n_scen+1]        obstacles of scenario s: obs_ptr[s]..obs_ptr[s+1]-1
  *  obs_face_ptr[M+1], obs_C[F_o*dim], obs_d[F_o]   obstacles {y : C_j y <= d_j}
  *  A_dyn[n_s*n_s], B_dyn[n_s*n_u], c_dyn[n_s]      time-invariant linear model

@@ -40,7 +40,8 @@ struct Layout {
     long long n_pairs, y_floats;
     int nc, nq, n_att, max_pf, max_of;
     // byte offsets into the workspace
-    size_t part_faces, part_face_ptr, part_off, obs_faces, obs_d64, obs_face_ptr, blocks, block_yoff, wg_items, scen_wg;
+    size_t part_faces, part_face_ptr, part_off, obs_faces, obs_d64, obs_face_ptr, blocks, block_yoff, bdesc, wg_items,
+        scen_wg;
     size_t A_dyn, B_dyn, c_dyn, Q_s, Q_u, x_ref, x0;
     size_t x, u, y, zeta, xi, y_snap, x_snap, u_snap;
     size_t contrib, rdual_part, rpri_part, unconv_part;
@@ -72,6 +73,7 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
     if (d->n_u < 1 || d->n_u > CADMM_MAX_NU) return fail(CADMM_INVALID, "n_u out of range");
     if (d->N < 1 || d->N > CADMM_MAX_N) return fail(CADMM_INVALID, "horizon N out of range (1..64)");
     if (d->n_parts < 1 || d->n_scen < 1) return fail(CADMM_INVALID, "need >= 1 robot part and scenario");
+    if (d->n_parts > 32767) return fail(CADMM_INVALID, "more than 32767 robot parts");
     if (!d->part_face_ptr || !d->obs_ptr || !d->obs_face_ptr || !d->pos_idx || !d->att_idx)
         return fail(CADMM_INVALID, "NULL index array");
     const int dim = d->dim;
@@ -157,6 +159,7 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
     L.obs_face_ptr = take(off, sizeof(int) * (M + 1));
     L.blocks = take(off, sizeof(int4) * nb);
     L.block_yoff = take(off, sizeof(int) * nb);
+    L.bdesc = take(off, sizeof(int4) * nb);
     L.wg_items = take(off, sizeof(int4) * nb);
     L.scen_wg = take(off, sizeof(int2) * d->n_scen);
     L.A_dyn = take(off, sizeof(float) * ns * ns);
@@ -558,14 +561,19 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     std::vector<float> poff(3 * L.n_parts, 0.f);
     for (int i = 0; i < L.n_parts; ++i)
         for (int r = 0; r < dim; ++r) poff[i * 3 + r] = (float)d->part_off[i * dim + r];
-    std::vector<int4> blocks;
+    std::vector<int4> blocks, bdesc;
     std::vector<int> yoff;
     long long off = 0;
     for (int s = 0; s < L.n_scen; ++s)
         for (int i = 0; i < L.n_parts; ++i)
             for (int j = d->obs_ptr[s]; j < d->obs_ptr[s + 1]; ++j) {
-                const int n = (d->part_face_ptr[i + 1] - d->part_face_ptr[i]) + (d->obs_face_ptr[j + 1] - d->obs_face_ptr[j]) + 1;
+                const int nr = d->part_face_ptr[i + 1] - d->part_face_ptr[i];
+                const int no = d->obs_face_ptr[j + 1] - d->obs_face_ptr[j];
+                const int n = nr + no + 1;
                 blocks.push_back(int4{s, i, j, n});
+                // face counts fit 8 bits (the compiled pair kernels take at most 32) and
+                // part indices 16 (checked with the descriptor)
+                bdesc.push_back(int4{d->part_face_ptr[i], d->obs_face_ptr[j], (int)off, nr | (no << 8) | (i << 16)});
                 yoff.push_back((int)off);
                 off += (long long)n * N;
             }
@@ -591,6 +599,7 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
         (rc = up(L.obs_face_ptr, d->obs_face_ptr, sizeof(int) * (L.M + 1))) ||
         (rc = up(L.blocks, blocks.data(), sizeof(int4) * blocks.size())) ||
         (rc = up(L.block_yoff, yoff.data(), sizeof(int) * yoff.size())) ||
+        (rc = up(L.bdesc, bdesc.data(), sizeof(int4) * bdesc.size())) ||
         (rc = up(L.A_dyn, Ad.data(), sizeof(float) * Ad.size())) ||
         (rc = up(L.B_dyn, Bd.data(), sizeof(float) * Bd.size())) ||
         (rc = up(L.c_dyn, cd.data(), sizeof(float) * cd.size())) ||
@@ -620,6 +629,7 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     P.obs_face_ptr = at<int>(h, L.obs_face_ptr);
     P.blocks = at<int4>(h, L.blocks);
     P.block_yoff = at<int>(h, L.block_yoff);
+    P.bdesc = at<int4>(h, L.bdesc);
     P.wg_items = at<int4>(h, L.wg_items);
     P.scen_wg = at<int2>(h, L.scen_wg);
     P.A_dyn = at<float>(h, L.A_dyn); P.B_dyn = at<float>(h, L.B_dyn); P.c_dyn = at<float>(h, L.c_dyn);

@@ -29,6 +29,8 @@ struct DevProblem {
     // pair blocks and work lists
     const int4* blocks;          // [n_blocks] (scenario, part, obstacle, n_rows)
     const int* block_yoff;       // [n_blocks] float offset of the block in y
+    const int4* bdesc;           // [n_blocks] (first robot face, first obstacle face, y offset,
+                                 //  robot faces | obstacle faces << 8 | part << 16)
     const int4* wg_items;        // [n_wg] (scenario, block_begin, block_end, wg index within scenario)
     const int2* scen_wg;         // [n_scen] (first wg, end wg)
     // model and cost

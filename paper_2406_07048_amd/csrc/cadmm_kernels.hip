@@ -481,17 +481,18 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
     for (int wg = blockIdx.x; wg < P.n_wg; wg += gridDim.x) {
         const int4 item = P.wg_items[wg];
         const int s = uniform(item.x);
-        if (P.done[s]) continue;                 // uniform over the workgroup
         const int b = uniform(item.y + bslot);
+        // the block's descriptor is loaded beside the done flag
+        const int4 bd = b < item.z ? P.bdesc[b] : int4{0, 0, 0, 0};
+        if (P.done[s]) continue;                 // uniform over the workgroup
+        const int fr0 = uniform(bd.x), fo0 = uniform(bd.y), yoff = uniform(bd.z);
+        const int nrb = uniform(bd.w & 0xff), nob = uniform((bd.w >> 8) & 0xff), part = uniform(bd.w >> 16);
         // the block's faces into its LDS slot: every solver pass reads them,
         // and from LDS they are cheap reads instead of HBM round trips
         float4* fl = faces + bslot * (MR + MO);
         if (b < item.z && chunk == 0) {
-            const int4 bk = P.blocks[b];
-            const int f0 = P.part_face_ptr[bk.y], nf = P.part_face_ptr[bk.y + 1] - f0;
-            const int g0 = P.obs_face_ptr[bk.z], ng = P.obs_face_ptr[bk.z + 1] - g0;
-            if (lane < nf) fl[lane] = P.part_faces[f0 + lane];
-            else if (lane >= MR && lane - MR < ng) fl[lane] = P.obs_faces[g0 + lane - MR];
+            if (lane < nrb) fl[lane] = P.part_faces[fr0 + lane];
+            else if (lane >= MR && lane - MR < nob) fl[lane] = P.obs_faces[fo0 + lane - MR];
         }
         __syncthreads();
         float con[NC];
@@ -500,17 +501,12 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
         float rd = 0.f;
         int unc = 0;
         if (b < item.z && t <= N) {
-            const int4 blk = P.blocks[b];
-            const int part = uniform(blk.y), obs = uniform(blk.z);
-            const int fr0 = uniform(P.part_face_ptr[part]);
-            const int fo0 = uniform(P.obs_face_ptr[obs]);
             Rows pr;
             pr.q = q;
-            pr.nr = uniform(P.part_face_ptr[part + 1] - fr0);
-            pr.no = uniform(P.obs_face_ptr[obs + 1] - fo0);
+            pr.nr = nrb;
+            pr.no = nob;
             pr.rf = fl;
             pr.of = fl + MR;
-            const int yoff = uniform(P.block_yoff[b]);
             const float* xs = P.x + ((size_t)s * (N + 1) + t) * P.n_s;
             Pose<DIM> ps;
             make_pose<DIM>(P, xs, part, ps);
@@ -757,18 +753,15 @@ __global__ void __launch_bounds__(512) mult_phase_kernel(DevProblem P)
     for (int wg = blockIdx.x; wg < P.n_wg; wg += gridDim.x) {
         const int4 item = P.wg_items[wg];
         const int s = uniform(item.x);
-        if (P.done[s]) continue;
         const int b = uniform(item.y + wave);
+        // the block's descriptor is loaded beside the done flag
+        const int4 bd = b < item.z ? P.bdesc[b] : int4{0, 0, 0, 0};
+        if (P.done[s]) continue;
         const int t = lane + 1;
         float rp = 0.f;
         if (b < item.z && t <= N) {
-            const int4 blk = P.blocks[b];
-            const int part = uniform(blk.y), obs = uniform(blk.z);
-            const int fr0 = uniform(P.part_face_ptr[part]);
-            const int nr = uniform(P.part_face_ptr[part + 1] - fr0);
-            const int fo0 = uniform(P.obs_face_ptr[obs]);
-            const int no = uniform(P.obs_face_ptr[obs + 1] - fo0);
-            const int yoff = uniform(P.block_yoff[b]);
+            const int fr0 = uniform(bd.x), fo0 = uniform(bd.y), yoff = uniform(bd.z);
+            const int nr = uniform(bd.w & 0xff), no = uniform((bd.w >> 8) & 0xff), part = uniform(bd.w >> 16);
             Pose<DIM> ps;
             make_pose<DIM>(P, P.x + ((size_t)s * (N + 1) + t) * P.n_s, part, ps);
             const float* yb = P.y + yoff + (t - 1);
