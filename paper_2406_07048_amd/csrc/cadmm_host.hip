@@ -211,6 +211,8 @@ struct cadmm_handle {
     void* rec_ws;
     size_t rec_bytes;
     std::vector<int> obs_ptr;    // host copy (scenario -> obstacles)
+    int* hdone;                  // pinned host copies of the done flags, [2][n_scen] (admm_solve)
+    hipEvent_t ev_done[2];       // recorded behind each copy
     std::vector<int4> blocks;    // host copy
 };
 
@@ -286,6 +288,17 @@ void drop_graphs(cadmm_handle* h)
         if (*g) (void)hipGraphExecDestroy(*g);
         *g = nullptr;
     }
+}
+
+// everything the handle owns besides the caller's workspace and stream
+void release(cadmm_handle* h)
+{
+    drop_graphs(h);
+    for (hipEvent_t& e : h->ev_done)
+        if (e) (void)hipEventDestroy(e);
+    if (h->hdone) (void)hipHostFree(h->hdone);
+    (void)hipStreamDestroy(h->cap);
+    delete h;
 }
 
 int recapture(cadmm_handle* h)
@@ -537,17 +550,21 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     h->rec_ws = nullptr;
     h->rec_bytes = 0;
     h->obs_ptr.assign(d->obs_ptr, d->obs_ptr + d->n_scen + 1);
+    h->hdone = nullptr;
+    h->ev_done[0] = h->ev_done[1] = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete h;
         return fail(CADMM_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
     }
     auto bail = [&](int code) {
-        drop_graphs(h);
-        (void)hipStreamDestroy(h->cap);
-        delete h;
+        release(h);
         return code;
     };
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->hdone), sizeof(int) * 2 * (size_t)d->n_scen) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_done[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_done[1], hipEventDisableTiming) != hipSuccess)
+        return bail(fail(CADMM_DEVICE, "pinned host buffer or events for the stopping flags"));
 
     // ---- host staging (FP64 -> FP32, faces packed as float4) ----
     const int dim = L.dim, ns = L.n_s, nu = L.n_u, N = L.N;
@@ -677,17 +694,33 @@ int admm_solve(cadmm_handle* h, int max_iters, int check_every, cadmm_result* ou
     const Layout& L = h->L;
     if (check_every <= 0) check_every = kGraphBlock;
     std::vector<int> done(L.n_scen, 0);
+    // chunks of check_every iterations, each followed by a copy of the done
+    // flags into pinned memory and an event; chunk c + 1 is queued before the
+    // flags of chunk c are read, so the GPU never waits for the host. Once
+    // every scenario has stopped, the chunk already queued runs as no-ops
+    // (the kernels skip stopped scenarios), so results do not depend on it.
     int it = 0;
-    while (it < max_iters) {
+    auto queue_chunk = [&](int c) -> int {
         const int chunk = std::min(check_every, max_iters - it);
         int rc = admm_iterate(h, chunk);
         if (rc) return rc;
         it += chunk;
-        HIP_TRY(hipMemcpyAsync(done.data(), h->ws + L.done, sizeof(int) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
-        HIP_TRY(hipStreamSynchronize(h->stream));
-        bool all = true;
-        for (int s = 0; s < L.n_scen; ++s) all &= done[s] != 0;
-        if (all) break;
+        HIP_TRY(hipMemcpyAsync(h->hdone + (size_t)(c & 1) * L.n_scen, h->ws + L.done, sizeof(int) * L.n_scen,
+                               hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipEventRecord(h->ev_done[c & 1], h->stream));
+        return CADMM_OK;
+    };
+    if (max_iters > 0) {
+        int rc = queue_chunk(0);
+        if (rc) return rc;
+        for (int c = 0;; ++c) {
+            const bool more = it < max_iters;
+            if (more && (rc = queue_chunk(c + 1))) return rc;
+            HIP_TRY(hipEventSynchronize(h->ev_done[c & 1]));
+            bool all = true;
+            for (int s = 0; s < L.n_scen; ++s) all &= h->hdone[(size_t)(c & 1) * L.n_scen + s] != 0;
+            if (all || !more) break;
+        }
     }
     // final certificate and cost
     HIP_TRY(launch_cost(h->P, at<float>(h, L.cost), h->stream));
@@ -953,9 +986,7 @@ void collision_admm_destroy(cadmm_handle* h)
 {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
-    drop_graphs(h);
-    (void)hipStreamDestroy(h->cap);
-    delete h;
+    release(h);
 }
 
 int pair_qp_batch(const cadmm_pair_batch* b, hipStream_t stream)
