@@ -152,8 +152,12 @@ int admm_iterate(cadmm_handle* h, int n_iters);
 
 /* Iterate until every scenario met the stopping test or max_iters
  * iterations; reads the device convergence flags every check_every
- * iterations (the only device-to-host syncs). Fills out[n_scen] and returns
- * CADMM_OK, or CADMM_NOT_CONVERGED (outputs still written). */
+ * iterations (the only device-to-host syncs; check_every <= 0 means 8).
+ * The next chunk of iterations is queued before the flags of the previous
+ * one are read, so one more chunk may run after every scenario stopped; it
+ * changes nothing (stopped scenarios are left unchanged) and the total never
+ * exceeds max_iters. Fills out[n_scen] and returns CADMM_OK, or
+ * CADMM_NOT_CONVERGED (outputs still written). */
 int admm_solve(cadmm_handle* h, int max_iters, int check_every, cadmm_result* out);
 
 /* Reset the iterate to the initial one of setup (same device work as setup). */
