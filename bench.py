@@ -1,17 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the ADMM collision-avoidance hot path on one MI355X.
 
-A step is one complete solve of the workload with inputs resident in HBM:
-reset to the initial iterate (obstacle-free LQ trajectory, scale-LP
-certificates), the ADMM iterations (pair QPs, trajectory QP, multiplier
-update, residual test, all inside a HIP graph) and the final scale
-certificate at the last trajectory. The headline value is pair-QP solves per
-second over the timed steps; ADMM iterations per second and the residuals
-reached are reported beside it, together with the batched-vs-plain comparison
-on 256 scenarios, the pair kernel's roofline figure and the FP64 oracle timed
-on the host cores.
+Headline (top level): the batched workload, 256 independent 2D scenarios
+(obstacle counts U{10..80}, faces U{3..12}, N = 50, about 560k pair QPs per
+iteration) in one handle. A step is one batched solve with inputs resident in
+HBM: reset to the initial iterate (obstacle-free LQ trajectory, scale-LP
+certificates), 50 ADMM iterations by HIP-graph replay (pair QPs, trajectory
+QP, multiplier update, residual test; scenarios whose stopping test holds are
+skipped from then on) and the final scale certificate. `value` counts the pair
+QPs actually solved (sum over scenarios of pairs x iterations run) per second.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Beside it: the batched-vs-plain comparison (the same 256 scenarios as 256
+separate handles on one stream), the pair kernel's HBM roofline figure (HIP
+events on the handle's stream), the single-scenario legs C2 (2D, solved to the
+1e-4 residuals) and C3 (3D), the stateless pair-QP entry point streamed over
+2^22 pairs, the reverse pass (backward/forward), and the FP64 oracle on the
+host cores over the same batched workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs ...]
 """
 import argparse
 import json
@@ -29,25 +35,44 @@ import workloads  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2406_07048_amd/csrc/cadmm_kernels.hip", "paper_2406_07048_amd/csrc/cadmm_device.h",
                   "paper_2406_07048_amd/csrc/cadmm_internal.h")
+METRIC = "pair-QP solves/sec & ADMM iters/sec at res 1e-4 (batched vs plain); backward/forward ratio"
 
 WORKLOADS = {
+    "c4": dict(desc="256 2D scenarios (4.5x2 m rectangle, bicycle at 8 m/s), obstacles U{10..80} with "
+                    "U{3..12} faces in a 40x40 m field, N=50, sigma=1, 50 ADMM iterations", iters=50),
     "c2": dict(desc="2D cab+trailer (2 parts x 4 faces), 40 hull obstacles (3-10 faces), N=50, "
-                    "4000 pair QPs/iteration, 200 ADMM iterations, sigma=300", iters=200),
+                    "4000 pair QPs/iteration, up to 200 ADMM iterations, sigma=300", iters=200),
     "c3": dict(desc="3D quadrotor (3 boxes), 200 hull polyhedra (6-20 faces), N=40, "
-                    "24000 pair QPs/iteration, 200 ADMM iterations, sigma=300", iters=200),
+                    "24000 pair QPs/iteration, up to 200 ADMM iterations, sigma=300", iters=200),
     "c1": dict(desc="2D rectangle, 3 obstacles, N=20, 60 pair QPs/iteration, 50 ADMM iterations", iters=50),
-    "c4": dict(desc="256 2D scenarios, obstacles U{10..80}, faces U{3..12}, N=50, 50 ADMM iterations", iters=50),
 }
+ALL_LEGS = ("c4", "plain", "c2", "c3", "stream", "grad", "cpu")
 
 
-def pair_bytes(prob, n_wg, nc):
-    """Algorithmic HBM bytes of one pair-phase launch: each pair reads its
+def say(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pair_bytes(prob):
+    """Algorithmic HBM bytes of one pair-phase launch: every pair reads its
     previous duals (n floats), writes the new ones (n floats) and reads its
-    multipliers (1 + dim floats); each workgroup writes nc x 64 floats of
-    per-step contribution sums. Geometry and poses are cache-resident."""
+    multipliers (1 + dim floats); every obstacle face (normal and offset,
+    dim + 1 floats) is read once. The trajectory is a few KB per scenario."""
     sc, part, obs, nrow, yoff, tot = workloads.block_layout(prob)
     N, dim = prob["N"], prob["dim"]
-    return 4.0 * (2 * tot + len(sc) * N * (1 + dim)) + 4.0 * n_wg * nc * 64
+    return 4.0 * (2 * tot + len(sc) * N * (1 + dim)) + 4.0 * len(prob["obs_d"]) * (dim + 1)
+
+
+def partial_bytes(n_wg, prob):
+    """Bytes of per-workgroup contribution sums the pair kernel writes beside
+    the algorithmic traffic (nc floats for each of the 64 step slots)."""
+    nq = prob["dim"] + (1 if prob["dim"] == 2 else 3)
+    return 4.0 * n_wg * (nq * (nq + 1) // 2 + nq) * 64
+
+
+def pairs_per_scenario(prob):
+    sc = workloads.block_layout(prob)[0]
+    return np.bincount(sc, minlength=workloads.n_scenarios(prob)) * prob["N"]
 
 
 def kernel_source_hash():
@@ -82,7 +107,17 @@ def measured_traffic(name, launch=None):
     return float(kv["traffic_bytes_per_launch"])
 
 
+def roofline(bytes_launch, ms, traffic, kernel, **extra):
+    gbs = bytes_launch / (ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+           "traffic": traffic, "kernel": kernel, "bytes_per_launch": bytes_launch, "ms_per_launch": ms}
+    out.update(extra)
+    return out
+
+
 def time_solves(h, iters, steps, torch):
+    """Mean seconds of reset + iters iterations (graph replay) + the final
+    scale certificate, with no host synchronisation inside a step."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -93,46 +128,63 @@ def time_solves(h, iters, steps, torch):
     return (time.perf_counter() - t0) / steps
 
 
-def cpu_baseline(prob, iters, budget_s=12.0):
-    """The FP64 oracle on the host cores over a bounded sample of the same
-    solve: whole solves (init + iterations) repeated until the budget."""
-    import oracle
-    cores = oracle.set_threads(0)
-    P = oracle.Problem(prob)
-    n = 0
-    pairs = 0
-    t0 = time.perf_counter()
-    while True:
-        st = P.init_state()
-        hist = P.run(st, iters)
-        n += 1
-        pairs += P.n_blocks * prob["N"] * int(hist["iters"].max())
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    el = time.perf_counter() - t0
-    return dict(value=pairs / el, unit="pair-QP solves/s", cores=int(cores), kind="oracle",
-                sample=f"{n} complete FP64 oracle solve(s) of the same workload "
-                       f"(init + {iters} iterations), {el:.1f} s wall")
+def make_handle(cadmm, prob, shape):
+    if shape:
+        w, g = (int(v) for v in shape.split(","))
+        return cadmm.Handle(prob, waves_per_group=w, lanes_per_pair=g)
+    return cadmm.Handle(prob)
 
 
-def batched_vs_plain(cadmm, torch, steps=2, iters=50):
-    """256 scenarios of the 2D batched configuration in one handle vs 256
-    separate handles launched one after another on one stream."""
+def residual_summary(prob, res, rp, rd):
+    """Per-scenario residuals after the timed solve, and the first iteration
+    at which the literal stopping test (Sec. IV-B, 1e-4) held."""
+    first = []
+    for s in range(rp.shape[1]):
+        ok = np.nonzero((rp[:, s] <= prob["eps_pri"]) & (rd[:, s] <= prob["eps_dual"]))[0]
+        first.append(int(ok[0]) + 1 if ok.size else None)
+    conv = [r["converged"] for r in res]
+    out = {"scenarios": len(res), "converged_at_1e-4": int(sum(conv)),
+           "r_pri_median": float(np.median([r["r_pri"] for r in res])),
+           "r_dual_median": float(np.median([r["r_dual"] for r in res])),
+           "min_alpha_min": float(min(r["min_alpha"] for r in res))}
+    if len(res) == 1:
+        out.update(r_pri=res[0]["r_pri"], r_dual=res[0]["r_dual"], first_iter_at_1e-4=first[0],
+                   cost=res[0]["cost"], min_alpha=res[0]["min_alpha"])
+    return out
+
+
+def leg_c4(cadmm, torch, args):
+    """Headline: the 256 batched scenarios in one handle."""
     prob = workloads.make("c4")
-    S = len(prob["obs_ptr"]) - 1
-    hb = cadmm.Handle(prob)
-    time_solves(hb, iters, 1, torch)
-    tb = time_solves(hb, iters, steps, torch)
-    _, nb, npairs, _ = cadmm.cadmm_workspace_size(prob)
-    wb = hb.launch_config()
-    # HBM roofline of the batched pair phase (the size where HBM, not launch
-    # latency, bounds it), from HIP events on the handle's stream
-    hb.reset()
-    ph = hb.phase_times(iters)
-    nq = prob["dim"] + (1 if prob["dim"] == 2 else 3)
-    bytes_launch = pair_bytes(prob, wb[1], nq * (nq + 1) // 2 + nq)
-    gbs = bytes_launch / (ph[0] * 1e-3) / 1e9
-    hb.close()
+    iters = WORKLOADS["c4"]["iters"]
+    h = make_handle(cadmm, prob, args.shape)
+    W, n_wg, G = h.launch_config()
+    for _ in range(args.warmup):
+        h.reset(); h.iterate(iters); h.scales()
+    say(f"c4: warmup done, blocks/group={W} workgroups={n_wg} lanes/pair={G}")
+    sec = time_solves(h, iters, args.steps, torch)
+    code, res = h.solve(0)
+    rp, rd = h.history(iters)
+    it = np.array([r["iters"] for r in res])
+    solves = float((pairs_per_scenario(prob) * it).sum())
+    h.reset()
+    ph = h.phase_times(iters)
+    h.close()
+    bl = pair_bytes(prob)
+    out = dict(sec=sec, solves=solves, iters=it, res=res, ph=ph, launch=(W, n_wg, G),
+               npairs=int(pairs_per_scenario(prob).sum()))
+    out["summary"] = residual_summary(prob, res, rp, rd)
+    out["roofline"] = roofline(bl, ph[0], measured_traffic("pair_phase_c4", (W, G)), "pair_phase_kernel",
+                               overhead_bytes=partial_bytes(n_wg, prob),
+                               launch={"blocks_per_group": W, "workgroups": n_wg, "lanes_per_pair": G})
+    return out
+
+
+def leg_plain(cadmm, torch, iters=50, steps=2):
+    """The same 256 scenarios as 256 separate handles launched one after
+    another on one stream (the plain per-scenario form)."""
+    prob = workloads.make("c4")
+    S = workloads.n_scenarios(prob)
     plain = [cadmm.Handle(workloads.select_scenarios(prob, [s])) for s in range(S)]
     for h in plain:
         h.reset(); h.iterate(2)
@@ -145,28 +197,56 @@ def batched_vs_plain(cadmm, torch, steps=2, iters=50):
             h.scales()
     torch.cuda.synchronize()
     tp = (time.perf_counter() - t0) / steps
+    solves = 0.0
+    for s, h in enumerate(plain):
+        _, res = h.solve(0)
+        solves += pairs_per_scenario(workloads.select_scenarios(prob, [s]))[0] * res[0]["iters"]
     for h in plain:
         h.close()
-    solves = npairs * iters
-    return dict(workload=f"{S} 2D scenarios, obstacles U{{10..80}}, faces U{{3..12}}, N=50, {npairs} pair QPs "
-                         f"per iteration, {iters} iterations",
-                batched_pair_solves_per_s=solves / tb, plain_pair_solves_per_s=solves / tp,
-                batched_ms_per_solve=tb * 1e3, plain_ms_per_solve=tp * 1e3, speedup=tp / tb,
-                batched_blocks_per_group=wb[0], batched_lanes_per_pair=wb[2],
-                pair_phase_ms=ph[0], pair_phase_solves_per_s=npairs / (ph[0] * 1e-3),
-                roofline={"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic("pair_phase_c4", (wb[0], wb[2])),
-                          "kernel": "pair_phase_kernel", "bytes_per_launch": bytes_launch})
+    return dict(sec=tp, solves=solves)
 
 
-def stream_batch(cadmm, torch, n_pairs=1 << 22, reps=5):
+def leg_single(cadmm, torch, name, args, steps=10):
+    """One scenario solved to the stopping test (or the iteration cap): the
+    time of admm_solve (graph chunks of 16 iterations, done flags read after
+    each), the pair solves it ran, the residuals and the per-phase times."""
+    prob = workloads.make(name)
+    cap = WORKLOADS[name]["iters"]
+    h = make_handle(cadmm, prob, args.shape if name == args.workload else "")
+    W, n_wg, G = h.launch_config()
+    h.reset(); h.solve(cap, check_every=16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h.reset()
+        code, res = h.solve(cap, check_every=16)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    rp, rd = h.history(cap)
+    it = res[0]["iters"]
+    npairs = int(pairs_per_scenario(prob).sum())
+    h.reset()
+    ph = h.phase_times(it)
+    h.close()
+    bl = pair_bytes(prob)
+    return dict(workload=f"{name}: {WORKLOADS[name]['desc']}", pairs_per_iteration=npairs, admm_iterations=it,
+                ms_per_solve=sec * 1e3, pair_solves_per_s=npairs * it / sec, admm_iters_per_s=it / sec,
+                pair_phase_solves_per_s=npairs / (ph[0] * 1e-3),
+                residuals=residual_summary(prob, res, rp, rd),
+                phase_ms={"pair": ph[0], "trajectory": ph[1], "multiplier": ph[2], "residual": ph[3]},
+                roofline=roofline(bl, ph[0], measured_traffic(f"pair_phase_{name}", (W, G)), "pair_phase_kernel",
+                                  overhead_bytes=partial_bytes(n_wg, prob),
+                                  launch={"blocks_per_group": W, "workgroups": n_wg, "lanes_per_pair": G}))
+
+
+def leg_stream(cadmm, torch, n_pairs=1 << 22, reps=5):
     """The stateless pair-QP entry point streamed over 2^22 pairs of the
     batched 2D shape (about 1.4 GB, beyond the 256 MB Infinity Cache): the
     size at which HBM, not latency, bounds the pair solve. HIP events on the
     stream the kernel runs on (torch's current stream)."""
     rp, K, kap, yh, bh = workloads.pair_batch_c4_shape(n_pairs)
     args = [torch.from_numpy(a).to("cuda") for a in (rp, K, kap, yh, bh)]
-    y, r, status = cadmm.pair_qp_batch(*args, 0.1)
+    y, r, nu, status = cadmm.pair_qp_batch(*args, 0.1)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -176,19 +256,16 @@ def stream_batch(cadmm, torch, n_pairs=1 << 22, reps=5):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     rows = int(rp[-1])
-    # read K, kappa, yhat, write y (per row); read bhat, row_ptr, write r, status (per pair)
-    bytes_launch = 4.0 * rows * (3 + 1 + 1 + 1) + 4.0 * n_pairs * (3 + 1 + 3 + 1)
-    gbs = bytes_launch / (ms * 1e-3) / 1e9
+    # per row: read K (3), kappa, yhat, write y; per pair: read row_ptr, bhat (3), write r (3), nu, status
+    bytes_launch = 4.0 * rows * (3 + 1 + 1 + 1) + 4.0 * n_pairs * (1 + 3 + 3 + 1 + 1)
     st = status.cpu().numpy()
     return dict(workload=f"{n_pairs} stateless pair QPs of the batched 2D shape ({rows} rows, 5-16 per pair)",
                 ms_per_launch=ms, pair_solves_per_s=n_pairs / (ms * 1e-3),
                 sweeps_mean=float(st[st >= 0].mean()), budget_hits=int((st < 0).sum()),
-                roofline={"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "pair_qp_batch_kernel",
-                          "bytes_per_launch": bytes_launch})
+                roofline=roofline(bytes_launch, ms, measured_traffic("pair_qp_batch_stream"), "pair_qp_batch_kernel"))
 
 
-def differentiation(cadmm, torch, steps=3, iters=100, every=10):
+def leg_grad(cadmm, torch, steps=3, iters=100, every=10):
     """Reverse pass of the 3D configuration unrolled over 100 iterations with
     a checkpoint every 10: wall time of admm_backward (segment replay +
     adjoint kernels) against the forward run that records the checkpoints,
@@ -226,18 +303,44 @@ def differentiation(cadmm, torch, steps=3, iters=100, every=10):
                 backward_forward_ratio=t_bwd / t_rec, grad_workspace_mb=nbytes / 1e6)
 
 
+def leg_cpu(prob, iters, budget_s=25.0):
+    """The FP64 oracle (OpenMP over the pair QPs) on the host cores, on the
+    headline workload: its scenarios in order, each initialised and iterated
+    like the GPU run, until the time budget is spent."""
+    import oracle
+    cores = oracle.set_threads(0)
+    S = workloads.n_scenarios(prob)
+    pps = pairs_per_scenario(prob)
+    solves = 0.0
+    done = 0
+    t0 = time.perf_counter()
+    chunk = 16
+    for s0 in range(0, S, chunk):
+        idx = list(range(s0, min(S, s0 + chunk)))
+        P = oracle.Problem(workloads.select_scenarios(prob, idx))
+        st = P.init_state()
+        hist = P.run(st, iters)
+        solves += float((pps[idx] * hist["iters"]).sum())
+        done += len(idx)
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return dict(value=solves / el, unit="pair-QP solves/s", cores=int(cores), kind="oracle",
+                sample=f"{done} of {S} scenarios of the same batched workload (init + {iters} iterations each, "
+                       f"{int(solves)} pair QPs), {el:.1f} s wall")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-grad", action="store_true")
-    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--workload", default="c4", choices=("c4",),
+                    help="the headline workload (the 256 batched scenarios)")
+    ap.add_argument("--legs", default=",".join(ALL_LEGS),
+                    help="comma list of legs to run: " + ",".join(ALL_LEGS))
     ap.add_argument("--shape", default="", metavar="W,G",
-                    help="fix the pair-kernel launch shape of the main workload (blocks per workgroup W, lanes "
+                    help="fix the pair-kernel launch shape of the headline handle (blocks per workgroup W, lanes "
                          "per pair G) instead of autotuning it; the counter runs behind profiles/ use the "
                          "shape the autotuner picks, so that their dispatches are the bench's")
     ap.add_argument("--source-hash", action="store_true", help="print the hash of the kernel sources and exit")
@@ -249,9 +352,13 @@ def main():
         print(kernel_source_hash())
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU only (this build runs on a single GPU; the batched scenarios would "
+              f"shard across GPUs with no exchange); got --gpus {args.gpus}", file=sys.stderr)
         sys.exit(2)
+    legs = [l for l in args.legs.split(",") if l]
+    for l in legs:
+        if l not in ALL_LEGS:
+            ap.error(f"unknown leg {l}")
     import torch
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 4
@@ -264,79 +371,45 @@ def main():
         return
     import paper_2406_07048_amd as cadmm
 
-    wl = WORKLOADS[args.workload]
-    prob = workloads.make(args.workload)
-    iters = wl["iters"]
-    if args.shape:
-        sw, sg = (int(v) for v in args.shape.split(","))
-        h = cadmm.Handle(prob, waves_per_group=sw, lanes_per_pair=sg)
-    else:
-        h = cadmm.Handle(prob)
-    W, n_wg, G = h.launch_config()
-    _, nb, npairs, yf = cadmm.cadmm_workspace_size(prob)
-    for _ in range(args.warmup):
-        h.reset(); h.iterate(iters); h.scales()
-    print(f"[bench] {args.workload}: warmup done, blocks/group={W} workgroups={n_wg} lanes/pair={G}",
-          file=sys.stderr, flush=True)
-    sec = time_solves(h, iters, args.steps, torch)
-    code, res = h.solve(0)
-    rp, rd = h.history(iters)
-    it_done = max(r["iters"] for r in res)
-    reached = None
-    for k in range(rp.shape[0]):
-        if rp[k, 0] <= prob["eps_pri"] and rd[k, 0] <= prob["eps_dual"]:
-            reached = k + 1
-            break
-    solves = npairs * it_done
-    # roofline figure of the dominant kernel (pair phase): HIP events recorded
-    # around each launch's own execution on the handle's stream, over the
-    # same iterations as the timed solves (the first iterations carry more
-    # Newton sweeps than the later ones, so a shorter window would differ)
-    h.reset()
-    ph = h.phase_times(it_done)
-    nq = prob["dim"] + (1 if prob["dim"] == 2 else 3)
-    nc = nq * (nq + 1) // 2 + nq
-    bytes_launch = pair_bytes(prob, n_wg, nc)
-    achieved = bytes_launch / (ph[0] * 1e-3) / 1e9
-    out = {
-        "metric": "pair-QP solves/sec & ADMM iters/sec at res 1e-4 (batched vs plain); backward/forward ratio",
-        "value": solves / sec,
-        "unit": "pair-QP solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": sec * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {wl['desc']}", "pairs_per_iteration": npairs,
-                   "admm_iterations": it_done, "parallelism": "single GPU"},
-        "admm_iters_per_s": it_done / sec,
-        "pair_phase_solves_per_s": npairs / (ph[0] * 1e-3),
-        "residuals": {"r_pri": res[0]["r_pri"], "r_dual": res[0]["r_dual"], "first_iter_at_1e-4": reached,
-                      "converged": res[0]["converged"], "min_alpha": res[0]["min_alpha"], "cost": res[0]["cost"]},
-        "phase_ms": {"pair": ph[0], "trajectory": ph[1], "multiplier": ph[2], "residual": ph[3]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(f"pair_phase_{args.workload}") if args.workload == "c2" else None,
-                     "kernel": "pair_phase_kernel", "bytes_per_launch": bytes_launch,
-                     "launch": {"blocks_per_group": W, "workgroups": n_wg, "lanes_per_pair": G}},
-    }
-    h.close()
-    if not args.no_batched:
-        print("[bench] batched vs plain (256 scenarios)", file=sys.stderr, flush=True)
-        out["batched"] = batched_vs_plain(cadmm, torch)
-    if not args.no_stream:
-        print("[bench] streaming stateless pair QPs (2^22)", file=sys.stderr, flush=True)
-        out["stream"] = stream_batch(cadmm, torch)
-    if not args.no_grad:
-        print("[bench] reverse pass (3D, 100 unrolled iterations)", file=sys.stderr, flush=True)
-        out["differentiation"] = differentiation(cadmm, torch)
-    if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (FP64 oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prob, iters)
+    prob = workloads.make("c4")
+    iters = WORKLOADS["c4"]["iters"]
+    out = {"metric": METRIC, "value": None, "unit": "pair-QP solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"c4: {WORKLOADS['c4']['desc']}", "scenarios": workloads.n_scenarios(prob),
+                      "admm_iterations": iters, "parallelism": "single GPU"}}
+    if "c4" in legs:
+        c4 = leg_c4(cadmm, torch, args)
+        sec = c4["sec"]
+        out["value"] = c4["solves"] / sec
+        out["ms_per_step"] = sec * 1e3
+        out["config"]["pairs_per_iteration"] = c4["npairs"]
+        out["pair_solves_per_step"] = c4["solves"]
+        out["admm_iters_per_s"] = iters / sec
+        out["scenario_iters_per_s"] = float(c4["iters"].sum()) / sec
+        out["pair_phase_solves_per_s"] = c4["npairs"] / (c4["ph"][0] * 1e-3)
+        out["residuals"] = c4["summary"]
+        out["phase_ms"] = dict(zip(("pair", "trajectory", "multiplier", "residual"), c4["ph"]))
+        out["roofline"] = c4["roofline"]
+        if "plain" in legs:
+            say("plain: 256 separate handles")
+            pl = leg_plain(cadmm, torch, iters)
+            out["batched_vs_plain"] = {"plain_pair_solves_per_s": pl["solves"] / pl["sec"],
+                                       "plain_ms_per_step": pl["sec"] * 1e3,
+                                       "speedup": pl["sec"] / sec * (c4["solves"] / max(pl["solves"], 1.0))}
+    for name in ("c2", "c3"):
+        if name in legs:
+            say(f"{name}: single scenario to the stopping test")
+            out[name] = leg_single(cadmm, torch, name, args)
+    if "stream" in legs:
+        say("stream: stateless pair QPs (2^22)")
+        out["stream"] = leg_stream(cadmm, torch)
+    if "grad" in legs:
+        say("grad: reverse pass (3D, 100 unrolled iterations)")
+        out["differentiation"] = leg_grad(cadmm, torch)
+    if "cpu" in legs:
+        say("cpu: FP64 oracle on the headline workload")
+        out["cpu_baseline"] = leg_cpu(prob, iters)
     print(json.dumps(out), flush=True)
 
 

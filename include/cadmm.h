@@ -241,7 +241,9 @@ void collision_admm_destroy(cadmm_handle* h);
  * All pointers are DEVICE pointers, caller-owned:
  *   row_ptr[n_pairs+1] (int), K[rows*(dim+1)] row-major, kappa[rows] (>= 0, at
  *   least one > 0 per pair), yhat[rows], bhat[n_pairs*(dim+1)]
- *   outputs y[rows], r[n_pairs*(dim+1)] = K^T y + bhat, status[n_pairs]
+ *   outputs y[rows], r[n_pairs*(dim+1)] = K^T y + bhat, nu[n_pairs] (the
+ *   multiplier of kappa^T y = 1 in the stationarity condition
+ *   K r + eps D (y - yhat) - nu kappa - w = 0, w >= 0, w^T y = 0), status[n_pairs]
  *   (sweeps used, negative if the sweep budget ran out).
  * A pair may hold at most CADMM_MAX_PART_FACES + CADMM_MAX_OBS_FACES + 1 rows.
  */
@@ -256,6 +258,7 @@ typedef struct cadmm_pair_batch {
     int max_sweeps;
     float* y;
     float* r;
+    float* nu;
     int* status;
 } cadmm_pair_batch;
 

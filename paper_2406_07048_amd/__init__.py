@@ -55,7 +55,7 @@ class CadmmPairBatch(ctypes.Structure):
         ("n_pairs", ctypes.c_int), ("dim", ctypes.c_int),
         ("row_ptr", _vp), ("K", _vp), ("kappa", _vp), ("yhat", _vp), ("bhat", _vp),
         ("eps", ctypes.c_float), ("max_sweeps", ctypes.c_int),
-        ("y", _vp), ("r", _vp), ("status", _vp),
+        ("y", _vp), ("r", _vp), ("nu", _vp), ("status", _vp),
     ]
 
 
@@ -403,17 +403,18 @@ def pair_qp_batch(row_ptr, K, kappa, yhat, bhat, eps, max_sweeps=0, stream=None)
     """Stateless batch of proximal dual-update QPs (device tensors in, out).
 
     row_ptr int32 [P+1]; K float32 [rows, dim+1]; kappa, yhat [rows];
-    bhat [P, dim+1]. Returns (y [rows], r [P, dim+1], status int32 [P])."""
+    bhat [P, dim+1]. Returns (y [rows], r [P, dim+1], nu [P], status int32 [P])."""
     torch = _torch()
     n_pairs = row_ptr.numel() - 1
     dim = K.shape[1] - 1
     y = torch.empty_like(yhat)
     r = torch.empty_like(bhat)
+    nu = torch.empty(n_pairs, dtype=torch.float32, device=K.device)
     status = torch.empty(n_pairs, dtype=torch.int32, device=K.device)
     b = CadmmPairBatch(n_pairs, dim, _ptr(row_ptr), _ptr(K), _ptr(kappa), _ptr(yhat), _ptr(bhat),
-                       float(eps), int(max_sweeps), _ptr(y), _ptr(r), _ptr(status))
+                       float(eps), int(max_sweeps), _ptr(y), _ptr(r), _ptr(nu), _ptr(status))
     _check(lib().pair_qp_batch(ctypes.byref(b), _stream_ptr(stream)), "pair_qp_batch")
-    return y, r, status
+    return y, r, nu, status
 
 
 def pair_scale_batch(a_ptr, A, b, o_ptr, Cp, dp, stream=None):

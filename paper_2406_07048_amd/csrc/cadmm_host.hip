@@ -995,11 +995,11 @@ int pair_qp_batch(const cadmm_pair_batch* b, hipStream_t stream)
     if (b->dim != 2 && b->dim != 3) return fail(CADMM_INVALID, "dim must be 2 or 3");
     if (b->n_pairs < 0) return fail(CADMM_INVALID, "n_pairs < 0");
     if (b->n_pairs == 0) return CADMM_OK;
-    if (!b->row_ptr || !b->K || !b->kappa || !b->yhat || !b->bhat || !b->y || !b->r || !b->status)
+    if (!b->row_ptr || !b->K || !b->kappa || !b->yhat || !b->bhat || !b->y || !b->r || !b->nu || !b->status)
         return fail(CADMM_INVALID, "NULL buffer");
     if (!(b->eps > 0.f)) return fail(CADMM_INVALID, "eps must be > 0");
     HIP_TRY(launch_pair_qp_batch(b->n_pairs, b->dim, b->row_ptr, b->K, b->kappa, b->yhat, b->bhat, b->eps,
-                                 b->max_sweeps > 0 ? b->max_sweeps : 24, b->y, b->r, b->status, stream));
+                                 b->max_sweeps > 0 ? b->max_sweeps : 24, b->y, b->r, b->nu, b->status, stream));
     return CADMM_OK;
 }
 

@@ -127,7 +127,7 @@ hipError_t launch_min_alpha(const DevProblem& P, const float* alpha, float* out,
 
 hipError_t launch_pair_qp_batch(int n_pairs, int dim, const int* row_ptr, const float* K,
                                 const float* kappa, const float* yhat, const float* bhat,
-                                float eps, int max_sweeps, float* y, float* r, int* status,
+                                float eps, int max_sweeps, float* y, float* r, float* nu, int* status,
                                 hipStream_t s);
 hipError_t launch_scale_batch(int n_pairs, int dim, const int* a_ptr, const float* A, const float* b,
                               const int* o_ptr, const float* Cp, const float* dp, float* alpha,

@@ -1168,7 +1168,7 @@ template <int DIM>
 __global__ void __launch_bounds__(256) pair_qp_batch_kernel(int n_pairs, const int* row_ptr, const float* K,
                                                             const float* kappa, const float* yhat,
                                                             const float* bhat, float eps, int max_sweeps,
-                                                            float* y, float* r, int* status)
+                                                            float* y, float* r, float* nu_out, int* status)
 {
     constexpr int NV = DIM + 2;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1219,6 +1219,7 @@ __global__ void __launch_bounds__(256) pair_qp_batch_kernel(int n_pairs, const i
     }
 #pragma unroll
     for (int c = 0; c <= DIM; ++c) r[(size_t)p * (DIM + 1) + c] = rr[c];
+    nu_out[p] = z[DIM + 1];
     status[p] = sw;
 }
 
@@ -1468,16 +1469,16 @@ hipError_t launch_min_alpha(const DevProblem& P, const float* alpha, float* out,
 
 hipError_t launch_pair_qp_batch(int n_pairs, int dim, const int* row_ptr, const float* K, const float* kappa,
                                 const float* yhat, const float* bhat, float eps, int max_sweeps, float* y,
-                                float* r, int* status, hipStream_t st)
+                                float* r, float* nu, int* status, hipStream_t st)
 {
     if (n_pairs <= 0) return hipSuccess;
     const int grid = (n_pairs + 255) / 256;
     if (dim == 2)
         hipLaunchKernelGGL(pair_qp_batch_kernel<2>, dim3(grid), dim3(256), 0, st, n_pairs, row_ptr, K, kappa,
-                           yhat, bhat, eps, max_sweeps, y, r, status);
+                           yhat, bhat, eps, max_sweeps, y, r, nu, status);
     else
         hipLaunchKernelGGL(pair_qp_batch_kernel<3>, dim3(grid), dim3(256), 0, st, n_pairs, row_ptr, K, kappa,
-                           yhat, bhat, eps, max_sweeps, y, r, status);
+                           yhat, bhat, eps, max_sweeps, y, r, nu, status);
     return hipGetLastError();
 }
 

@@ -47,7 +47,24 @@ def to_dev(a, dtype=torch.float32):
 
 
 # --------------------------------------------------------------- stateless QPs
-@pytest.mark.parametrize("name,k", [("c1", 0), ("c1", 5), ("c2", 3), ("c3", 3)])
+def oracle_nu(Kp, kap, yh, y, bh, eps):
+    """Multiplier of kappa^T y = 1 implied by a solution y: stationarity
+    K r + eps D (y - yhat) - nu kappa - w = 0 on a row with y_l > 0 and
+    kappa_l > 0 (w_l = 0 there); the row with the largest kappa_l y_l."""
+    r = Kp.T @ y + bh
+    D = (Kp ** 2).sum(1)
+    l = int(np.argmax(np.where(kap > 0, kap * y, -1.0)))
+    return (Kp[l] @ r + eps * D[l] * (y[l] - yh[l])) / kap[l]
+
+
+def nu_bar(Kp, kap, y):
+    """FP32 bar on nu: the residual bar (1e-5 of the summed terms of
+    K^T y + bhat) carried through K_l . r / kappa_l on the lambda rows."""
+    lam = kap > 0
+    return 2e-5 * (1.0 + (np.abs(Kp).sum(1) * y).sum()) * (np.abs(Kp[lam]).sum(1) / kap[lam]).max()
+
+
+@pytest.mark.parametrize("name,k", [("c1", 0), ("c1", 5), ("c2", 3), ("c2", 60), ("c3", 3), ("c3", 30)])
 def test_pair_qp_batch_parity(cadmm, name, k):
     prob = workloads.make(name)
     say(f"[pair_qp_batch] {name} iterate {k}")
@@ -57,46 +74,71 @@ def test_pair_qp_batch_parity(cadmm, name, k):
     rng = np.random.default_rng(0)
     pairs = [(int(rng.integers(nb)), int(rng.integers(1, prob["N"] + 1))) for _ in range(600)]
     row_ptr, K, kap, yh, bh, geo = gather_pairs(prob, st, pairs, layout)
-    y, r, status = cadmm.pair_qp_batch(to_dev(row_ptr, torch.int32), to_dev(K), to_dev(kap), to_dev(yh),
-                                       to_dev(bh), prob["eps_prox"])
+    y, r, nu, status = cadmm.pair_qp_batch(to_dev(row_ptr, torch.int32), to_dev(K), to_dev(kap), to_dev(yh),
+                                           to_dev(bh), prob["eps_prox"])
     torch.cuda.synchronize()
-    y, r, status = y.cpu().numpy().astype(np.float64), r.cpu().numpy(), status.cpu().numpy()
-    worst = 0.0
+    y, r, nu, status = y.cpu().numpy().astype(np.float64), r.cpu().numpy(), nu.cpu().numpy(), status.cpu().numpy()
+    worst = worst_nu = 0.0
     for p, (A, bb, Cp, dp, z, xi) in enumerate(geo):
-        yo, it = oracle.pair_qp(A, bb, Cp, dp, z, xi, yh[row_ptr[p]:row_ptr[p + 1]], prob["eps_prox"])
+        sl = slice(row_ptr[p], row_ptr[p + 1])
+        yo, it = oracle.pair_qp(A, bb, Cp, dp, z, xi, yh[sl], prob["eps_prox"])
         assert it >= 0
-        Kp = K[row_ptr[p]:row_ptr[p + 1]]
-        e = scaled_pair_error(Kp, y[row_ptr[p]:row_ptr[p + 1]], yo)
+        Kp = K[sl]
+        e = scaled_pair_error(Kp, y[sl], yo)
         worst = max(worst, e)
         ro = Kp.T @ yo + bh[p]
         # r = K^T y + bhat is a sum of terms of size ||K_l||_1 y_l
         assert np.abs(r[p] - ro).max() <= 1e-5 * (1.0 + (np.abs(Kp).sum(1) * yo).sum())
-    say(f"   worst scaled dual error {worst:.2e}, sweeps max {status.max()}, unconverged {(status < 0).sum()}")
+        en = abs(nu[p] - oracle_nu(Kp, kap[sl], yh[sl], yo, bh[p], prob["eps_prox"])) / nu_bar(Kp, kap[sl], yo)
+        worst_nu = max(worst_nu, en)
+    say(f"   worst scaled dual error {worst:.2e}, nu error / bar {worst_nu:.2f}, sweeps max {status.max()}, "
+        f"unconverged {(status < 0).sum()}")
+    assert (status >= 0).all()
     assert worst <= TOL_DUAL
+    assert worst_nu <= 1.0
 
 
 def test_pair_qp_batch_edge_cases(cadmm):
-    """Empty batch; a single-row-class pair; the largest pair (8 + 32 + 1 rows);
-    a pair whose centre yhat is already optimal."""
+    """Empty batch; the largest pair (8 + 32 + 1 rows); a pair with no
+    obstacle rows (one row class plus the slack row); a pair whose proximal
+    centre is already the optimum (the scale-LP certificate of a disjoint
+    pair with zero multipliers: K^T y + bhat = 0, so y = yhat)."""
     z = torch.zeros(1, dtype=torch.int32, device="cuda")
     e = torch.zeros((0, 3), device="cuda")
-    y, r, s = cadmm.pair_qp_batch(z, e, torch.zeros(0, device="cuda"), torch.zeros(0, device="cuda"),
-                                  torch.zeros((0, 3), device="cuda"), 0.1)
+    y, r, nu, s = cadmm.pair_qp_batch(z, e, torch.zeros(0, device="cuda"), torch.zeros(0, device="cuda"),
+                                      torch.zeros((0, 3), device="cuda"), 0.1)
     assert y.numel() == 0 and s.numel() == 0
     rng = np.random.default_rng(4)
-    for n_o in (3, 32):
-        A = np.concatenate([np.eye(2), -np.eye(2), [[0.6, 0.8], [-0.6, 0.8], [0.6, -0.8], [-0.6, -0.8]]])
-        b = np.r_[1.0, 1.0, 1.0, 1.0, 1.3, 1.3, 1.3, 1.3]
+    A = np.concatenate([np.eye(2), -np.eye(2), [[0.6, 0.8], [-0.6, 0.8], [0.6, -0.8], [-0.6, -0.8]]])
+    b = np.r_[1.0, 1.0, 1.0, 1.0, 1.3, 1.3, 1.3, 1.3]
+    cases = []
+    for n_o in (32, 0):
         ang = np.sort(rng.uniform(0, 2 * np.pi, n_o))
-        Cp = np.stack([np.cos(ang), np.sin(ang)], 1)
+        Cp = np.stack([np.cos(ang), np.sin(ang)], 1).reshape(n_o, 2)
         dp = 1.0 + Cp @ np.array([4.0, 1.0])
         K = K_rows(A, Cp, dp)
         yh = np.abs(rng.normal(size=len(K)))
-        bh = np.array([1.3, 0.2, -0.1])
-        y, r, st = cadmm.pair_qp_batch(to_dev(np.array([0, len(K)], np.int32), torch.int32), to_dev(K),
-                                       to_dev(np.r_[b, np.zeros(n_o + 1)]), to_dev(yh), to_dev(bh[None]), 0.1)
-        yo, it = oracle.pair_qp(A, b, Cp, dp, bh[0] - 1.0, bh[1:], yh, 0.1)
-        assert scaled_pair_error(K, y.cpu().numpy().astype(np.float64), yo) <= TOL_DUAL
+        cases.append((f"{n_o} obstacle rows", A, b, Cp, dp, K, yh, np.array([1.3, 0.2, -0.1])))
+    # optimal centre: a square obstacle 3 m away along x, zero multipliers
+    Cp = np.concatenate([np.eye(2), -np.eye(2)])
+    dp = np.r_[5.0, 1.0, -4.0, 1.0]
+    alpha, _, lam, mu, gap, stl = oracle.scale_lp(A, b, Cp, dp)
+    assert stl == 0 and alpha > 1.0
+    K = K_rows(A, Cp, dp)
+    cases.append(("optimal centre", A, b, Cp, dp, K, np.r_[lam, mu, alpha - 1.0], np.array([1.0, 0.0, 0.0])))
+    for what, A_, b_, Cp_, dp_, K, yh, bh in cases:
+        kap = np.r_[b_, np.zeros(len(dp_) + 1)]
+        y, r, nu, st = cadmm.pair_qp_batch(to_dev(np.array([0, len(K)], np.int32), torch.int32), to_dev(K),
+                                           to_dev(kap), to_dev(yh), to_dev(bh[None]), 0.1)
+        torch.cuda.synchronize()
+        yo, it = oracle.pair_qp(A_, b_, Cp_, dp_, bh[0] - 1.0, bh[1:], yh, 0.1)
+        err = scaled_pair_error(K, y.cpu().numpy().astype(np.float64), yo)
+        say(f"   {what}: scaled dual error {err:.2e}, sweeps {st.item()}")
+        assert st.item() >= 0
+        assert err <= TOL_DUAL
+        if what == "optimal centre":
+            assert scaled_pair_error(K, yo, yh) <= 1e-9
+            assert np.abs(r.cpu().numpy()).max() <= 1e-5
 
 
 # --------------------------------------------------------------- scale LP
