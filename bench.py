@@ -148,8 +148,8 @@ def residual_summary(prob, res, rp, rd):
            "r_dual_median": float(np.median([r["r_dual"] for r in res])),
            "min_alpha_min": float(min(r["min_alpha"] for r in res))}
     if len(res) == 1:
-        out.update(r_pri=res[0]["r_pri"], r_dual=res[0]["r_dual"], first_iter_at_1e-4=first[0],
-                   cost=res[0]["cost"], min_alpha=res[0]["min_alpha"])
+        out.update({"r_pri": res[0]["r_pri"], "r_dual": res[0]["r_dual"], "first_iter_at_1e-4": first[0],
+                    "cost": res[0]["cost"], "min_alpha": res[0]["min_alpha"]})
     return out
 
 
