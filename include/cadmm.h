@@ -22,7 +22,11 @@
  *    world pose of part i: y = R(s)(x + o_i) + rho(s). Requires b_i > 0.
  *  - Collision pairs exist for t = 1..N (x_0 is fixed data); cost
  *    F = sum_{t=1..N} (x_t - xref_t)^T Q_s (x_t - xref_t) + sum_{t=0..N-1} u_t^T Q_u u_t.
- *  - Dynamics are given already linearised: x_{t+1} = A x_t + B u_t + c.
+ *  - Dynamics (Sec. IV-A eq. system_eqn, s_{t+1} = s_t + f(s_t, u_t)) are either
+ *    given already linearised, x_{t+1} = A_t x_t + B_t u_t + c_t (time-invariant,
+ *    per step or per scenario and step), or one of the built-in nonlinear f
+ *    (kinematic bicycle, quadrotor), linearised about the current iterate at
+ *    every ADMM iteration: the one SQP step per iteration of Sec. IV-B.
  *  - Initial iterate: obstacle-free LQ trajectory; zeta = xi = 0;
  *    y = (lam*, mu*, max(alpha* - 1, 0)) from the scale LP.
  *
@@ -64,6 +68,9 @@ enum {
 
 enum { CADMM_ATT_YAW = 0, CADMM_ATT_EULER_ZYX = 1 };
 
+/* Dynamics models (cadmm_desc.model). */
+enum { CADMM_MODEL_LINEAR = 0, CADMM_MODEL_BICYCLE = 1, CADMM_MODEL_QUADROTOR = 2 };
+
 /* Limits of this build. */
 #define CADMM_MAX_N 64           /* horizon */
 #define CADMM_MAX_NS 16          /* state size */
@@ -80,15 +87,32 @@ enum { CADMM_ATT_YAW = 0, CADMM_ATT_EULER_ZYX = 1 };
  *                                   (1 <= n_parts <= 32767)
  *  n_scen, obs_ptr[n_scen+1]        obstacles of scenario s: obs_ptr[s]..obs_ptr[s+1]-1
  *  obs_face_ptr[M+1], obs_C[F_o*dim], obs_d[F_o]   obstacles {y : C_j y <= d_j}
- *  A_dyn[n_s*n_s], B_dyn[n_s*n_u], c_dyn[n_s]      time-invariant linear model
+ *  A_dyn[n_models*n_s*n_s], B_dyn[n_models*n_s*n_u], c_dyn[n_models*n_s]
+ *                 linear models x_{t+1} = A x_t + B u_t + c (row-major); step t
+ *                 (0..N-1) of scenario s uses model s*dyn_s_stride + t*dyn_t_stride,
+ *                 n_models = (n_scen-1)*dyn_s_stride + (N-1)*dyn_t_stride + 1
+ *                 (both strides 0: one time-invariant model)
  *  pos_idx[dim], att_idx[1|3], att_kind            state indices of rho(s) and attitude
  *  Q_s[n_s*n_s], Q_u[n_u*n_u] (symmetric), x_ref[n_scen*(N+1)*n_s], x0[n_scen*n_s]
- *  sigma (ADMM penalty), eps_prox (proximal weight), eps_pri, eps_dual (stop test)
+ *  sigma (ADMM penalty), eps_prox (proximal weight), eps_pri, eps_dual (stop test;
+ *                 a negative value never holds, so every iteration runs)
  *  max_sweeps     Newton sweep budget of each pair QP (0 = default 24)
  *  waves_per_group  pair blocks per workgroup of the pair kernels (0 = autotune, else 1..8)
  *  lanes_per_pair   lanes that share one pair QP in the pair phase (0 = autotune, else 1, 2, 4);
  *                   a block then spans ceil(N / (64 / lanes_per_pair)) waves, and
  *                   waves_per_group times that may not exceed 8
+ *  dyn_t_stride, dyn_s_stride   model strides (>= 0), see A_dyn
+ *  model          CADMM_MODEL_LINEAR: the linear models above are the dynamics.
+ *                 CADMM_MODEL_BICYCLE (dim 2, n_s 4 = (p_x, p_y, theta, v), n_u 2 =
+ *                 (a, delta); model_par = (dt, wheelbase)) or CADMM_MODEL_QUADROTOR
+ *                 (dim 3, n_s 12 = (p, v, phi theta psi, body rates), n_u 4 =
+ *                 (thrust change, torques); model_par = (dt, mass, J_x, J_y, J_z, g)):
+ *                 s_{t+1} = s_t + dt f_c(s_t, u_t) with that f_c, linearised about
+ *                 the current iterate at every ADMM iteration (the SQP step of
+ *                 Sec. IV-B); the linear models then only give the initial
+ *                 (obstacle-free) trajectory. The reverse pass (admm_record,
+ *                 admm_backward) needs CADMM_MODEL_LINEAR.
+ *  model_par[8]   parameters of the nonlinear model (unused for CADMM_MODEL_LINEAR)
  */
 typedef struct cadmm_desc {
     int dim, n_s, n_u, N;
@@ -116,6 +140,9 @@ typedef struct cadmm_desc {
     int max_sweeps;
     int waves_per_group;
     int lanes_per_pair;
+    int dyn_t_stride, dyn_s_stride;
+    int model;
+    double model_par[8];
 } cadmm_desc;
 
 typedef struct cadmm_handle cadmm_handle;
@@ -226,6 +253,7 @@ int admm_set_params(cadmm_handle* h, const double* obs_d, const double* x0);
  *   step. Writes dL_scale * dL/dd to grad_d[F_o] and dL_scale * dL/dx0 to
  *   grad_x0[n_scen*n_s] (DEVICE FP32, overwritten). Leaves the handle at
  *   iterate K. No host sync. CADMM_INVALID if nothing was recorded in d_gws.
+ * All three return CADMM_INVALID for a nonlinear model (desc.model != 0).
  */
 int admm_grad_workspace_size(cadmm_handle* h, int n_iters, int ckpt_every, size_t* bytes);
 int admm_record(cadmm_handle* h, int n_iters, int ckpt_every, void* d_gws, size_t bytes, float* cost_out);

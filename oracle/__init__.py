@@ -57,6 +57,8 @@ class _Problem(ctypes.Structure):
         ("Q_s", _dp), ("Q_u", _dp), ("x_ref", _dp), ("x0", _dp),
         ("sigma", ctypes.c_double), ("eps_prox", ctypes.c_double),
         ("eps_pri", ctypes.c_double), ("eps_dual", ctypes.c_double),
+        ("dyn_ts", ctypes.c_int), ("dyn_ss", ctypes.c_int), ("model", ctypes.c_int),
+        ("model_par", ctypes.c_double * 8),
     ]
 
 
@@ -68,7 +70,7 @@ def _declare(L):
     L.orc_pair_qp.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp,
                               ctypes.c_double, _dp, _dp, ctypes.c_double, _dp]
     L.orc_traj_qp.restype = ctypes.c_int
-    L.orc_traj_qp.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp,
+    L.orc_traj_qp.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, _dp,
                               _dp, _dp, _dp, _dp, _dp]
     PP = ctypes.POINTER(_Problem)
     L.orc_y_size.restype = ctypes.c_long
@@ -89,11 +91,15 @@ def _declare(L):
     L.orc_admm_run.argtypes = [PP, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _ip]
     L.orc_admm_grad.restype = ctypes.c_int
     L.orc_admm_grad.argtypes = [PP, ctypes.c_int, _dp, _dp, _dp, _dp]
+    L.orc_admm_grad_at.restype = ctypes.c_int
+    L.orc_admm_grad_at.argtypes = [PP, ctypes.c_int] + [_dp] * 5 + [_dp, _dp, _dp]
     L.orc_pairqp_vjp.restype = ctypes.c_int
     L.orc_pairqp_vjp.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp, ctypes.c_double,
                                  _dp, _dp, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_traj_vjp.restype = ctypes.c_int
     L.orc_traj_vjp.argtypes = [PP] + [_dp] * 12
+    L.orc_model_step.restype = ctypes.c_int
+    L.orc_model_step.argtypes = [PP, _dp, _dp, _dp, _dp, _dp]
     L.orc_set_threads.restype = ctypes.c_int
     L.orc_set_threads.argtypes = [ctypes.c_int]
 
@@ -150,13 +156,16 @@ def pair_qp(A, b, Cp, dp, zeta, xi, yhat, eps):
 
 
 def traj_qp(A, B, c, x0, H, h, Q_u):
-    """LQ problem with stage terms (H_t, h_t), t = 1..N, and input cost u^T Q_u u."""
+    """LQ problem with stage terms (H_t, h_t), t = 1..N, and input cost u^T Q_u u.
+    A, B, c are one model ([n_s, n_s], [n_s, n_u], [n_s]) or one per step
+    ([N, n_s, n_s], [N, n_s, n_u], [N, n_s])."""
     A, B, c, x0, H, h, Q_u = map(_f64, (A, B, c, x0, H, h, Q_u))
-    n_s, n_u = B.shape
+    n_s, n_u = B.shape[-2:]
     N = H.shape[0]
+    ts = 1 if A.ndim == 3 else 0
     x = np.zeros((N + 1, n_s))
     u = np.zeros((N, n_u))
-    st = lib().orc_traj_qp(n_s, n_u, N, _d(A), _d(B), _d(c), _d(x0), _d(H), _d(h), _d(Q_u),
+    st = lib().orc_traj_qp(n_s, n_u, N, _d(A), _d(B), _d(c), ts, _d(x0), _d(H), _d(h), _d(Q_u),
                            _d(x), _d(u))
     if st:
         raise RuntimeError("oracle trajectory QP: Hessian not positive definite")
@@ -193,6 +202,11 @@ class Problem:
         st.eps_prox = float(prob["eps_prox"])
         st.eps_pri = float(prob["eps_pri"])
         st.eps_dual = float(prob["eps_dual"])
+        st.dyn_ts = int(prob.get("dyn_ts", 0))
+        st.dyn_ss = int(prob.get("dyn_ss", 0))
+        st.model = int(prob.get("model", 0))
+        for i, v in enumerate(prob.get("model_par", ())):
+            st.model_par[i] = float(v)
         self.st = st
         self.ref = ctypes.byref(st)
         self.n_scen = st.n_scen
@@ -264,6 +278,16 @@ class Problem:
             raise RuntimeError("trajectory VJP failed")
         return out
 
+    def model_step(self, s, u):
+        """(F(s, u), dF/ds, dF/du) of the problem's nonlinear model."""
+        n_s, n_u = self.st.n_s, self.st.n_u
+        F = np.zeros(n_s)
+        A = np.zeros((n_s, n_s))
+        B = np.zeros((n_s, n_u))
+        if lib().orc_model_step(self.ref, _d(_f64(s)), _d(_f64(u)), _d(F), _d(A), _d(B)):
+            raise ValueError("the problem has no nonlinear model")
+        return F, A, B
+
     def cost(self, x, u, s=0):
         return lib().orc_cost(self.ref, int(s), _d(_f64(x)), _d(_f64(u)))
 
@@ -306,6 +330,25 @@ def grad_fixed_y0(prob, K, y0):
     bad = lib().orc_admm_grad(P.ref, int(K), _d(y0), _d(L), _d(gd), _d(gx))
     if bad:
         raise RuntimeError(f"oracle gradient: {bad} failed solves")
+    return float(L[0]), gd, gx
+
+
+def grad_at_iterates(prob, iterates):
+    """(L, dL/dd, dL/dx0) by the oracle's reverse pass at given iterates:
+    ``iterates`` is a list of K + 1 state dicts (x, u, y, zeta, xi), k = 0..K,
+    for example another implementation's forward run. The reverse arithmetic
+    is that of grad_fixed_y0; only the forward iterates are supplied."""
+    P = Problem(prob)
+    K = len(iterates) - 1
+    cat = {k: _f64(np.stack([np.asarray(it[k], np.float64).ravel() for it in iterates]))
+           for k in ("x", "u", "y", "zeta", "xi")}
+    L = np.zeros(1)
+    gd = np.zeros(len(prob["obs_d"]))
+    gx = np.zeros((P.n_scen, int(prob["n_s"])))
+    bad = lib().orc_admm_grad_at(P.ref, K, _d(cat["x"]), _d(cat["u"]), _d(cat["y"]), _d(cat["zeta"]),
+                                 _d(cat["xi"]), _d(L), _d(gd), _d(gx))
+    if bad:
+        raise RuntimeError(f"oracle reverse pass: {bad} failed solves")
     return float(L[0]), gd, gx
 
 

@@ -25,6 +25,7 @@
  * the N pairs t = 1..N; its dual rows (lambda, mu, gamma) are stored row-major
  * [row][t]; zeta[block*N + t-1]; xi[(block*dim + c)*N + t-1].
  */
+#include <complex.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -417,7 +418,20 @@ typedef struct {
     int att_kind;                   /* 0: planar yaw, 1: ZYX Euler (phi, theta, psi) */
     const double *Q_s, *Q_u, *x_ref, *x0;
     double sigma, eps_prox, eps_pri, eps_dual;
+    /* dynamics x_{t+1} = A x_t + B u_t + c (Sec. IV-A eq. system_eqn, given
+       linearised): the model of (scenario s, step t) is number
+       s * dyn_ss + t * dyn_ts of the arrays A_dyn, B_dyn, c_dyn (0, 0: one
+       time-invariant model). model != 0 names a nonlinear f that every ADMM
+       iteration linearises about its current iterate instead (the SQP step of
+       Sec. IV-B); the given model then only sets the initial trajectory. */
+    int dyn_ts, dyn_ss;
+    int model;                      /* 0: the given linear model, 1: kinematic bicycle, 2: quadrotor */
+    double model_par[8];
 } orc_problem;
+
+static const double *dyn_A(const orc_problem *P, int s) { return P->A_dyn + (size_t)s * P->dyn_ss * P->n_s * P->n_s; }
+static const double *dyn_B(const orc_problem *P, int s) { return P->B_dyn + (size_t)s * P->dyn_ss * P->n_s * P->n_u; }
+static const double *dyn_c(const orc_problem *P, int s) { return P->c_dyn + (size_t)s * P->dyn_ss * P->n_s; }
 
 static int n_att(const orc_problem *P) { return P->att_kind == 0 ? 1 : 3; }
 
@@ -541,11 +555,13 @@ static const double *state_at(const orc_problem *P, const double *x, int s, int 
 
 /*
  * min sum_{t=1..N} (1/2 x_t^T H_t x_t + h_t^T x_t) + sum_{t=0..N-1} u_t^T Q_u u_t
- * s.t. x_{t+1} = A x_t + B u_t + c, x_0 given.
- * Condensed: x_t = z_t + sum_{k<t} A^{t-1-k} B u_k, then a dense Cholesky
- * solve in the stacked inputs.  H: N blocks (t = 1..N) of n_s x n_s.
+ * s.t. x_{t+1} = A_t x_t + B_t u_t + c_t, x_0 given, where the model of step
+ * t is A + t ts n_s n_s (B, c likewise; ts = 0: time-invariant).
+ * Condensed: x_t = z_t + sum_{k<t} A_{t-1} ... A_{k+1} B_k u_k with the free
+ * response z_t = A_{t-1} z_{t-1} + c_{t-1}, then a dense Cholesky solve in the
+ * stacked inputs.  H: N blocks (t = 1..N) of n_s x n_s.
  */
-int orc_traj_qp(int n_s, int n_u, int N, const double *A, const double *B, const double *c,
+int orc_traj_qp(int n_s, int n_u, int N, const double *A0, const double *B0, const double *c0, int ts,
                 const double *x0, const double *H, const double *h, const double *Q_u,
                 double *x, double *u)
 {
@@ -559,6 +575,8 @@ int orc_traj_qp(int n_s, int n_u, int N, const double *A, const double *B, const
     for (int t = 1; t <= N; ++t) {
         double *Mc = Mt + (size_t)(t - 1) * n_s * nU;
         const double *Mp = (t >= 2) ? Mt + (size_t)(t - 2) * n_s * nU : NULL;
+        const double *A = A0 + (size_t)(t - 1) * ts * n_s * n_s, *B = B0 + (size_t)(t - 1) * ts * n_s * n_u;
+        const double *c = c0 + (size_t)(t - 1) * ts * n_s;
         for (int r = 0; r < n_s; ++r) {
             double acc = c[r];
             for (int q = 0; q < n_s; ++q) acc += A[r * n_s + q] * z[(t - 1) * n_s + q];
@@ -605,13 +623,16 @@ int orc_traj_qp(int n_s, int n_u, int N, const double *A, const double *B, const
     if (!st) {
         memcpy(u, gr, sizeof(double) * nU);
         memcpy(x, x0, sizeof(double) * n_s);
-        for (int t = 0; t < N; ++t)
+        for (int t = 0; t < N; ++t) {
+            const double *A = A0 + (size_t)t * ts * n_s * n_s, *B = B0 + (size_t)t * ts * n_s * n_u;
+            const double *c = c0 + (size_t)t * ts * n_s;
             for (int r = 0; r < n_s; ++r) {
                 double acc = c[r];
                 for (int q = 0; q < n_s; ++q) acc += A[r * n_s + q] * x[t * n_s + q];
                 for (int k = 0; k < n_u; ++k) acc += B[r * n_u + k] * u[t * n_u + k];
                 x[(t + 1) * n_s + r] = acc;
             }
+        }
     }
     free(Mt); free(z); free(Hs); free(gr); free(HM);
     return st;
@@ -669,7 +690,7 @@ int orc_admm_init(const orc_problem *P, double *x, double *u, double *y, double 
     int bad = 0;
     for (int s = 0; s < P->n_scen; ++s) {
         lq_stage_base(P, s, H, h);
-        bad |= orc_traj_qp(n_s, P->n_u, N, P->A_dyn, P->B_dyn, P->c_dyn, P->x0 + (size_t)s * n_s,
+        bad |= orc_traj_qp(n_s, P->n_u, N, dyn_A(P, s), dyn_B(P, s), dyn_c(P, s), P->dyn_ts, P->x0 + (size_t)s * n_s,
                            H, h, P->Q_u, x + (size_t)s * (N + 1) * n_s, u + (size_t)s * N * P->n_u);
     }
     free(H); free(h);
@@ -753,6 +774,104 @@ int orc_pair_phase(const orc_problem *P, const double *x, const double *y_in,
     }
     free(B);
     return bad;
+}
+
+/* ------------------------------------------------------------------ */
+/* nonlinear dynamics s_{t+1} = s_t + f(s_t, u_t) (Sec. IV-A eq.       */
+/* system_eqn) with f = dt f_c, f_c a continuous-time model, and its   */
+/* Jacobians by the complex-step derivative                            */
+/* ------------------------------------------------------------------ */
+
+/* F(s, u) = s + dt f_c(s, u) in complex arithmetic.
+   model 1, kinematic bicycle: s = (p_x, p_y, theta, v), u = (a, delta),
+     f_c = (v cos theta, v sin theta, v tan(delta) / L, a); par = (dt, L).
+   model 2, quadrotor: s = (p, v, phi theta psi, omega), u = (dF, tau),
+     p' = v, v' = (m g + dF) / m R e_3 - g e_3 with R = R_z(psi) R_y(theta) R_x(phi),
+     Euler-angle rates from the body rates omega (ZYX), omega' = J^{-1} (tau - omega x J omega);
+     par = (dt, m, J_x, J_y, J_z, g). */
+static void model_F(const orc_problem *P, const double complex *s, const double complex *u, double complex *F)
+{
+    const double *par = P->model_par;
+    double dt = par[0];
+    int n_s = P->n_s;
+    double complex f[12];
+    if (P->model == 1) {
+        f[0] = s[3] * ccos(s[2]);
+        f[1] = s[3] * csin(s[2]);
+        f[2] = s[3] * ctan(u[1]) / par[1];
+        f[3] = u[0];
+    } else {
+        double m = par[1], Jx = par[2], Jy = par[3], Jz = par[4], g = par[5];
+        double complex cph = ccos(s[6]), sph = csin(s[6]), cth = ccos(s[7]), sth = csin(s[7]);
+        double complex cps = ccos(s[8]), sps = csin(s[8]);
+        double complex thrust = (m * g + u[0]) / m;
+        for (int i = 0; i < 3; ++i) f[i] = s[3 + i];
+        f[3] = thrust * (cps * sth * cph + sps * sph);
+        f[4] = thrust * (sps * sth * cph - cps * sph);
+        f[5] = thrust * (cth * cph) - g;
+        double complex wx = s[9], wy = s[10], wz = s[11];
+        f[6] = wx + (sph * wy + cph * wz) * sth / cth;
+        f[7] = cph * wy - sph * wz;
+        f[8] = (sph * wy + cph * wz) / cth;
+        f[9] = (u[1] - (wy * Jz * wz - wz * Jy * wy)) / Jx;
+        f[10] = (u[2] - (wz * Jx * wx - wx * Jz * wz)) / Jy;
+        f[11] = (u[3] - (wx * Jy * wy - wy * Jx * wx)) / Jz;
+    }
+    for (int i = 0; i < n_s; ++i) F[i] = s[i] + dt * f[i];
+}
+
+/* F(s, u), A = dF/ds (n_s x n_s) and B = dF/du (n_s x n_u), row-major.
+   Derivatives by the complex step: d/dx_j F = Im F(x + i h e_j) / h with
+   h = 1e-30, exact to rounding for these analytic f (no difference is
+   formed, so no cancellation). */
+static void model_linearize(const orc_problem *P, const double *s, const double *u, double *F, double *A, double *B)
+{
+    int n_s = P->n_s, n_u = P->n_u;
+    const double h = 1e-30;
+    double complex sc[16] = {0}, uc[8] = {0}, Fc[16];
+    for (int i = 0; i < n_s; ++i) sc[i] = s[i];
+    for (int j = 0; j < n_u; ++j) uc[j] = u[j];
+    model_F(P, sc, uc, Fc);
+    for (int i = 0; i < n_s; ++i) F[i] = creal(Fc[i]);
+    for (int j = 0; j < n_s + n_u; ++j) {
+        if (j < n_s) sc[j] += I * h; else uc[j - n_s] += I * h;
+        model_F(P, sc, uc, Fc);
+        for (int i = 0; i < n_s; ++i) {
+            double d = cimag(Fc[i]) / h;
+            if (j < n_s) A[i * n_s + j] = d; else B[i * n_u + (j - n_s)] = d;
+        }
+        if (j < n_s) sc[j] = s[j]; else uc[j - n_s] = u[j - n_s];
+    }
+}
+
+/* Test hook: one step of the nonlinear model and its Jacobians. */
+int orc_model_step(const orc_problem *P, const double *s, const double *u, double *F, double *A, double *B)
+{
+    if (P->model != 1 && P->model != 2) return 1;
+    model_linearize(P, s, u, F, A, B);
+    return 0;
+}
+
+/* The model of every step of scenario s linearised about the current
+   iterate (x^k_t, u^k_t), t = 0..N-1 (the SQP step): A_t, B_t and
+   c_t = F(x^k_t, u^k_t) - A_t x^k_t - B_t u^k_t. */
+static void sqp_models(const orc_problem *P, int s, const double *x_in, const double *u_in, double *Al, double *Bl,
+                       double *cl)
+{
+    int n_s = P->n_s, n_u = P->n_u, N = P->N;
+    for (int t = 0; t < N; ++t) {
+        const double *xt = x_in + ((size_t)s * (N + 1) + t) * n_s;
+        const double *ut = u_in + ((size_t)s * N + t) * n_u;
+        double *A = Al + (size_t)t * n_s * n_s, *B = Bl + (size_t)t * n_s * n_u, *c = cl + (size_t)t * n_s;
+        double F[16];
+        model_linearize(P, xt, ut, F, A, B);
+        for (int i = 0; i < n_s; ++i) {
+            double acc = F[i];
+            for (int j = 0; j < n_s; ++j) acc -= A[i * n_s + j] * xt[j];
+            for (int j = 0; j < n_u; ++j) acc -= B[i * n_u + j] * ut[j];
+            c[i] = acc;
+        }
+    }
 }
 
 /*
@@ -841,8 +960,20 @@ int orc_traj_phase(const orc_problem *P, const double *x_in, const double *y,
                 }
             }
         }
-        bad |= orc_traj_qp(n_s, P->n_u, N, P->A_dyn, P->B_dyn, P->c_dyn, P->x0 + (size_t)s * n_s,
-                           H, h, P->Q_u, x_out + (size_t)s * (N + 1) * n_s, uo);
+        if (P->model) {
+            /* the SQP step: f linearised about the current iterate (u_out
+               holds u^k on entry) */
+            double *Al = (double *)malloc(sizeof(double) * N * n_s * n_s);
+            double *Bl = (double *)malloc(sizeof(double) * N * n_s * P->n_u);
+            double *cl = (double *)malloc(sizeof(double) * N * n_s);
+            sqp_models(P, s, x_in, u_out, Al, Bl, cl);
+            bad |= orc_traj_qp(n_s, P->n_u, N, Al, Bl, cl, 1, P->x0 + (size_t)s * n_s,
+                               H, h, P->Q_u, x_out + (size_t)s * (N + 1) * n_s, uo);
+            free(Al); free(Bl); free(cl);
+        } else {
+            bad |= orc_traj_qp(n_s, P->n_u, N, dyn_A(P, s), dyn_B(P, s), dyn_c(P, s), P->dyn_ts,
+                               P->x0 + (size_t)s * n_s, H, h, P->Q_u, x_out + (size_t)s * (N + 1) * n_s, uo);
+        }
         free(H); free(h);
     }
     free(B);
@@ -1235,7 +1366,7 @@ static int pairqp_adjoint(const orc_problem *P, const orc_block *q, const double
    solution (x, u), and the adjoint (xbar over t = 1..N, ubar). Outputs: w
    (N x n_s, = M abar), and adds x0bar. Hbar_t = -1/2 (w_t x_t^T + x_t w_t^T),
    hbar_t = -w_t are formed by the caller from w. */
-static int lq_adjoint(int n_s, int n_u, int N, const double *A, const double *B, const double *H,
+static int lq_adjoint(int n_s, int n_u, int N, const double *A0, const double *B0, int ts, const double *H,
                       const double *Q_u, const double *xbar, const double *ubar, double *w, double *x0bar)
 {
     int nU = N * n_u;
@@ -1247,6 +1378,7 @@ static int lq_adjoint(int n_s, int n_u, int N, const double *A, const double *B,
     for (int t = 1; t <= N; ++t) {
         double *Mc = Mt + (size_t)(t - 1) * n_s * nU;
         const double *Mp = (t >= 2) ? Mt + (size_t)(t - 2) * n_s * nU : NULL;
+        const double *A = A0 + (size_t)(t - 1) * ts * n_s * n_s, *B = B0 + (size_t)(t - 1) * ts * n_s * n_u;
         for (int r = 0; r < n_s; ++r) {
             for (int col = 0; col < nU; ++col) {
                 double a = 0.0;
@@ -1298,13 +1430,15 @@ static int lq_adjoint(int n_s, int n_u, int N, const double *A, const double *B,
                 zb[t * n_s + r] = acc;
             }
         }
-        /* z_t = A z_{t-1} + c, z_0 = x0: backpropagate zbar to x0 */
-        for (int t = N; t >= 1; --t)
+        /* z_t = A_{t-1} z_{t-1} + c_{t-1}, z_0 = x0: backpropagate zbar to x0 */
+        for (int t = N; t >= 1; --t) {
+            const double *A = A0 + (size_t)(t - 1) * ts * n_s * n_s;
             for (int q2 = 0; q2 < n_s; ++q2) {
                 double acc = 0.0;
                 for (int r = 0; r < n_s; ++r) acc += A[r * n_s + q2] * zb[t * n_s + r];
                 zb[(t - 1) * n_s + q2] += acc;
             }
+        }
         for (int r = 0; r < n_s; ++r) x0bar[r] += zb[r];
     }
     free(Mt); free(Hs); free(HM); free(ab); free(zb);
@@ -1370,7 +1504,7 @@ static int traj_adjoint(const orc_problem *P, const orc_block *B, int nb, const 
         traj_stage(P, B, nb, s, Xk, Yn, Zk, XIk, H, h);
         for (int t = 1; t <= N; ++t)
             for (int r = 0; r < n_s; ++r) xbt[(t - 1) * n_s + r] = xb[((size_t)s * (N + 1) + t) * n_s + r];
-        bad += lq_adjoint(n_s, n_u, N, P->A_dyn, P->B_dyn, H, P->Q_u, xbt, ub + (size_t)s * N * n_u, w,
+        bad += lq_adjoint(n_s, n_u, N, dyn_A(P, s), dyn_B(P, s), P->dyn_ts, H, P->Q_u, xbt, ub + (size_t)s * N * n_u, w,
                           grad_x0 + (size_t)s * n_s);
         /* x^{k+1} and u^{k+1} do not depend on x^k, u^k except through the stage terms */
         for (int t = 0; t <= N; ++t)
@@ -1432,16 +1566,12 @@ static int traj_adjoint(const orc_problem *P, const orc_block *B, int nb, const 
     return bad;
 }
 
-/*
- * Gradient of L = sum_s F_s(x^K, u^K) after exactly K iterations (no early
- * stop) from the initial iterate s^0 = obstacle-free LQ(x0), the given y0,
- * zeta = xi = 0, with respect to every obstacle face offset d (grad_d[F_o])
- * and every initial state (grad_x0[n_scen * n_s]). y0 is held fixed.
- * Reverse mode through the stored iterates, with the dense KKT transposes of
- * each pair QP on its active set and of the condensed trajectory QP.
- * Returns 0, or the number of failed solves.
- */
-int orc_admm_grad(const orc_problem *P, int K, const double *y0, double *L_out, double *grad_d, double *grad_x0)
+/* The reverse pass of orc_admm_grad over stored iterates: X, U, Y, Zt, XI
+ * hold the iterates k = 0..K (x^k, u^k, y^k, zeta^k, xi^k) back to back.
+ * Writes L = sum_s F_s(x^K, u^K) and the gradients; returns the number of
+ * failed solves. */
+static int admm_reverse(const orc_problem *P, int K, const double *X, const double *U, const double *Y,
+                        const double *Zt, const double *XI, double *L_out, double *grad_d, double *grad_x0)
 {
     int S = P->n_scen, N = P->N, n_s = P->n_s, n_u = P->n_u, dim = P->dim, nq = dim + n_att(P);
     int nb = count_blocks(P), bad = 0;
@@ -1449,35 +1579,6 @@ int orc_admm_grad(const orc_problem *P, int K, const double *y0, double *L_out, 
     size_t nx = (size_t)S * (N + 1) * n_s, nu_ = (size_t)S * N * n_u;
     orc_block *B = (orc_block *)malloc(sizeof(orc_block) * (nb > 0 ? nb : 1));
     enumerate_blocks(P, B);
-    double *X = (double *)malloc(sizeof(double) * nx * (K + 1));
-    double *U = (double *)malloc(sizeof(double) * nu_ * (K + 1));
-    double *Y = (double *)malloc(sizeof(double) * (ny > 0 ? ny : 1) * (K + 1));
-    double *Zt = (double *)calloc((size_t)(npair > 0 ? npair : 1) * (K + 1), sizeof(double));
-    double *XI = (double *)calloc((size_t)(npair > 0 ? npair : 1) * dim * (K + 1), sizeof(double));
-    double *rp = (double *)calloc(S, sizeof(double));
-    /* forward, storing every iterate */
-    {
-        double *H = (double *)malloc(sizeof(double) * N * n_s * n_s), *h = (double *)malloc(sizeof(double) * N * n_s);
-        for (int s = 0; s < S; ++s) {
-            lq_stage_base(P, s, H, h);
-            bad |= orc_traj_qp(n_s, n_u, N, P->A_dyn, P->B_dyn, P->c_dyn, P->x0 + (size_t)s * n_s, H, h, P->Q_u,
-                               X + (size_t)s * (N + 1) * n_s, U + (size_t)s * N * n_u);
-        }
-        free(H); free(h);
-    }
-    memcpy(Y, y0, sizeof(double) * ny);
-    for (int k = 0; k < K; ++k) {
-        double *Xk = X + nx * k, *Yk = Y + (size_t)ny * k, *Zk = Zt + (size_t)npair * k, *XIk = XI + (size_t)npair * dim * k;
-        double *Xn = X + nx * (k + 1), *Un = U + nu_ * (k + 1), *Yn = Y + (size_t)ny * (k + 1);
-        double *Zn = Zt + (size_t)npair * (k + 1), *XIn = XI + (size_t)npair * dim * (k + 1);
-        memcpy(Yn, Yk, sizeof(double) * ny);
-        bad += orc_pair_phase(P, Xk, Yk, Zk, XIk, NULL, Yn);
-        memcpy(Un, U + nu_ * k, sizeof(double) * nu_);
-        bad += orc_traj_phase(P, Xk, Yn, Zk, XIk, NULL, Xn, Un);
-        memcpy(Zn, Zk, sizeof(double) * npair);
-        memcpy(XIn, XIk, sizeof(double) * npair * dim);
-        orc_mult_phase(P, Xn, Yn, NULL, Zn, XIn, rp);
-    }
     double L = 0.0;
     for (int s = 0; s < S; ++s) L += orc_cost(P, s, X + nx * K, U + nu_ * K);
     *L_out = L;
@@ -1516,8 +1617,8 @@ int orc_admm_grad(const orc_problem *P, int K, const double *y0, double *L_out, 
     double *H = (double *)malloc(sizeof(double) * N * n_s * n_s), *h = (double *)malloc(sizeof(double) * N * n_s);
     double *w = (double *)malloc(sizeof(double) * N * n_s), *xbt = (double *)malloc(sizeof(double) * N * n_s);
     for (int k = K - 1; k >= 0; --k) {
-        double *Xk = X + nx * k, *Yk = Y + (size_t)ny * k, *Zk = Zt + (size_t)npair * k, *XIk = XI + (size_t)npair * dim * k;
-        double *Xn = X + nx * (k + 1), *Un = U + nu_ * (k + 1), *Yn = Y + (size_t)ny * (k + 1);
+        const double *Xk = X + nx * k, *Yk = Y + (size_t)ny * k, *Zk = Zt + (size_t)npair * k, *XIk = XI + (size_t)npair * dim * k;
+        const double *Xn = X + nx * (k + 1), *Un = U + nu_ * (k + 1), *Yn = Y + (size_t)ny * (k + 1);
         /* (3) multiplier update adjoint at (s^{k+1}, y^{k+1}) */
         memset(qbar, 0, sizeof(double) * npair * nq);
         for (int b = 0; b < nb; ++b)
@@ -1562,14 +1663,77 @@ int orc_admm_grad(const orc_problem *P, int K, const double *y0, double *L_out, 
         lq_stage_base(P, s, H, hh);
         for (int t = 1; t <= N; ++t)
             for (int r = 0; r < n_s; ++r) xbt[(t - 1) * n_s + r] = xb[((size_t)s * (N + 1) + t) * n_s + r];
-        bad += lq_adjoint(n_s, n_u, N, P->A_dyn, P->B_dyn, H, P->Q_u, xbt, NULL, w, grad_x0 + (size_t)s * n_s);
+        bad += lq_adjoint(n_s, n_u, N, dyn_A(P, s), dyn_B(P, s), P->dyn_ts, H, P->Q_u, xbt, NULL, w, grad_x0 + (size_t)s * n_s);
         for (int r = 0; r < n_s; ++r) grad_x0[(size_t)s * n_s + r] += xb[((size_t)s * (N + 1)) * n_s + r];
         free(hh);
     }
     free(H); free(h); free(w); free(xbt);
     free(xb); free(ub); free(yb); free(yb_old); free(zbar); free(xibar); free(qbar);
-    free(B); free(X); free(U); free(Y); free(Zt); free(XI); free(rp);
+    free(B);
     return bad;
+}
+
+/*
+ * Gradient of L = sum_s F_s(x^K, u^K) after exactly K iterations (no early
+ * stop) from the initial iterate s^0 = obstacle-free LQ(x0), the given y0,
+ * zeta = xi = 0, with respect to every obstacle face offset d (grad_d[F_o])
+ * and every initial state (grad_x0[n_scen * n_s]). y0 is held fixed.
+ * Reverse mode through the stored iterates, with the dense KKT transposes of
+ * each pair QP on its active set and of the condensed trajectory QP.
+ * Returns 0, or the number of failed solves.
+ */
+int orc_admm_grad(const orc_problem *P, int K, const double *y0, double *L_out, double *grad_d, double *grad_x0)
+{
+    if (P->model) return 1 << 20;   /* the reverse pass covers the given linear models only */
+    int S = P->n_scen, N = P->N, n_s = P->n_s, n_u = P->n_u, dim = P->dim;
+    int nb = count_blocks(P), bad = 0;
+    long ny = orc_y_size(P), npair = (long)nb * N;
+    size_t nx = (size_t)S * (N + 1) * n_s, nu_ = (size_t)S * N * n_u;
+    orc_block *B = (orc_block *)malloc(sizeof(orc_block) * (nb > 0 ? nb : 1));
+    enumerate_blocks(P, B);
+    double *X = (double *)malloc(sizeof(double) * nx * (K + 1));
+    double *U = (double *)malloc(sizeof(double) * nu_ * (K + 1));
+    double *Y = (double *)malloc(sizeof(double) * (ny > 0 ? ny : 1) * (K + 1));
+    double *Zt = (double *)calloc((size_t)(npair > 0 ? npair : 1) * (K + 1), sizeof(double));
+    double *XI = (double *)calloc((size_t)(npair > 0 ? npair : 1) * dim * (K + 1), sizeof(double));
+    double *rp = (double *)calloc(S, sizeof(double));
+    /* forward, storing every iterate */
+    {
+        double *H = (double *)malloc(sizeof(double) * N * n_s * n_s), *h = (double *)malloc(sizeof(double) * N * n_s);
+        for (int s = 0; s < S; ++s) {
+            lq_stage_base(P, s, H, h);
+            bad |= orc_traj_qp(n_s, n_u, N, dyn_A(P, s), dyn_B(P, s), dyn_c(P, s), P->dyn_ts, P->x0 + (size_t)s * n_s, H, h, P->Q_u,
+                               X + (size_t)s * (N + 1) * n_s, U + (size_t)s * N * n_u);
+        }
+        free(H); free(h);
+    }
+    memcpy(Y, y0, sizeof(double) * ny);
+    for (int k = 0; k < K; ++k) {
+        double *Xk = X + nx * k, *Yk = Y + (size_t)ny * k, *Zk = Zt + (size_t)npair * k, *XIk = XI + (size_t)npair * dim * k;
+        double *Xn = X + nx * (k + 1), *Un = U + nu_ * (k + 1), *Yn = Y + (size_t)ny * (k + 1);
+        double *Zn = Zt + (size_t)npair * (k + 1), *XIn = XI + (size_t)npair * dim * (k + 1);
+        memcpy(Yn, Yk, sizeof(double) * ny);
+        bad += orc_pair_phase(P, Xk, Yk, Zk, XIk, NULL, Yn);
+        memcpy(Un, U + nu_ * k, sizeof(double) * nu_);
+        bad += orc_traj_phase(P, Xk, Yn, Zk, XIk, NULL, Xn, Un);
+        memcpy(Zn, Zk, sizeof(double) * npair);
+        memcpy(XIn, XIk, sizeof(double) * npair * dim);
+        orc_mult_phase(P, Xn, Yn, NULL, Zn, XIn, rp);
+    }
+    int bad2 = admm_reverse(P, K, X, U, Y, Zt, XI, L_out, grad_d, grad_x0);
+    free(B); free(X); free(U); free(Y); free(Zt); free(XI); free(rp);
+    return bad + bad2;
+}
+
+/* Test hook: the reverse pass of orc_admm_grad at iterates given by the
+ * caller (k = 0..K back to back, canonical layouts), e.g. those of another
+ * implementation, so that its reverse pass can be compared apart from the
+ * rounding of its forward iterates. */
+int orc_admm_grad_at(const orc_problem *P, int K, const double *X, const double *U, const double *Y,
+                     const double *Zt, const double *XI, double *L_out, double *grad_d, double *grad_x0)
+{
+    if (P->model) return 1 << 20;
+    return admm_reverse(P, K, X, U, Y, Zt, XI, L_out, grad_d, grad_x0);
 }
 
 /* Test hook: VJP of one pair QP in the part frame. Given ybar (n), returns

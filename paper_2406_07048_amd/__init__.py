@@ -38,7 +38,12 @@ class CadmmDesc(ctypes.Structure):
         ("sigma", ctypes.c_double), ("eps_prox", ctypes.c_double),
         ("eps_pri", ctypes.c_double), ("eps_dual", ctypes.c_double),
         ("max_sweeps", ctypes.c_int), ("waves_per_group", ctypes.c_int), ("lanes_per_pair", ctypes.c_int),
+        ("dyn_t_stride", ctypes.c_int), ("dyn_s_stride", ctypes.c_int), ("model", ctypes.c_int),
+        ("model_par", ctypes.c_double * 8),
     ]
+
+
+CADMM_MODEL_LINEAR, CADMM_MODEL_BICYCLE, CADMM_MODEL_QUADROTOR = 0, 1, 2
 
 
 class CadmmResult(ctypes.Structure):
@@ -172,6 +177,11 @@ class _DescHolder:
         d.eps_pri, d.eps_dual = float(prob["eps_pri"]), float(prob["eps_dual"])
         d.max_sweeps, d.waves_per_group = int(max_sweeps), int(waves_per_group)
         d.lanes_per_pair = int(lanes_per_pair)
+        d.dyn_t_stride = int(prob.get("dyn_ts", 0))
+        d.dyn_s_stride = int(prob.get("dyn_ss", 0))
+        d.model = int(prob.get("model", CADMM_MODEL_LINEAR))
+        for i, v in enumerate(prob.get("model_par", ())):
+            d.model_par[i] = float(v)
         self.desc = d
         self.keep = keep
 
@@ -209,6 +219,14 @@ class Handle:
                                           nbytes, _stream_ptr(self.stream), ctypes.byref(h)),
                "collision_admm_setup")
         self._h = h
+        # the initial duals of setup (scale-LP certificates at the
+        # descriptor's own offsets and initial states): the default y^0 of
+        # collision_admm_cost, whatever data set_params installs later
+        self._setup_duals = self.get_state()["y"]
+
+    @property
+    def setup_duals(self):
+        return self._setup_duals
 
     # -- iteration ------------------------------------------------------
     def iterate(self, n_iters):
@@ -362,16 +380,19 @@ def _autograd_function():
     torch = _torch()
 
     class CollisionADMMCost(torch.autograd.Function):
-        """L(d, x0) = sum_s F_s(x^K, u^K) after exactly K ADMM iterations from
-        s^0 = LQ(x0), zero multipliers and the scale-LP certificates of s^0 as
-        y^0 (held fixed), with the forward run on the GPU (admm_record) and the
-        gradient from the reverse pass (admm_backward). One pending backward
-        per handle: a second forward on the same handle replaces the first."""
+        """L(d, x0; y0) = sum_s F_s(x^K, u^K) after exactly K ADMM iterations
+        from s^0 = LQ(x0), zero multipliers and the given initial duals y0,
+        which are held fixed (not recomputed from d or x0), with the forward
+        run on the GPU (admm_record) and the gradient from the reverse pass
+        (admm_backward): value and gradient describe the same map. One
+        pending backward per handle: a second forward on the same handle
+        replaces the first."""
 
         @staticmethod
-        def forward(ctx, obs_d, x0, handle, n_iters, ckpt_every):
+        def forward(ctx, obs_d, x0, handle, n_iters, ckpt_every, y0):
             handle.set_params(obs_d=obs_d, x0=x0)
-            handle.reset()
+            handle.reset()                       # s^0 = LQ(x0), zeta = xi = 0
+            handle.set_state(y=y0)               # y^0 held fixed
             cost = handle.record(int(n_iters), int(ckpt_every))
             ctx.handle = handle
             ctx.shapes = (obs_d.shape, obs_d.dtype, obs_d.device, x0.shape, x0.dtype, x0.device)
@@ -382,7 +403,7 @@ def _autograd_function():
             ds, dd, ddev, xs, xd, xdev = ctx.shapes
             gd, gx = ctx.handle.backward(float(g))
             return (gd.reshape(ds).to(dtype=dd, device=ddev), gx.reshape(xs).to(dtype=xd, device=xdev),
-                    None, None, None)
+                    None, None, None, None)
 
     return CollisionADMMCost
 
@@ -390,13 +411,18 @@ def _autograd_function():
 _COST_FN = None
 
 
-def collision_admm_cost(obs_d, x0, handle, n_iters, ckpt_every=10):
+def collision_admm_cost(obs_d, x0, handle, n_iters, ckpt_every=10, y0=None):
     """Differentiable tracking cost after n_iters ADMM iterations (see
-    CollisionADMMCost); obs_d and x0 are torch tensors."""
+    CollisionADMMCost); obs_d and x0 are torch tensors. y0 (canonical dual
+    layout) is held fixed; by default the scale-LP certificates the handle
+    computed at setup, i.e. at the descriptor's own offsets and initial
+    states, whatever obs_d and x0 are passed."""
     global _COST_FN
     if _COST_FN is None:
         _COST_FN = _autograd_function()
-    return _COST_FN.apply(obs_d, x0, handle, n_iters, ckpt_every)
+    if y0 is None:
+        y0 = handle.setup_duals
+    return _COST_FN.apply(obs_d, x0, handle, n_iters, ckpt_every, y0)
 
 
 def pair_qp_batch(row_ptr, K, kappa, yhat, bhat, eps, max_sweeps=0, stream=None):

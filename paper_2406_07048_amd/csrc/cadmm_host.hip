@@ -42,7 +42,8 @@ struct Layout {
     // byte offsets into the workspace
     size_t part_faces, part_face_ptr, part_off, obs_faces, obs_d64, obs_face_ptr, blocks, block_yoff, bdesc, wg_items,
         scen_wg;
-    size_t A_dyn, B_dyn, c_dyn, Q_s, Q_u, x_ref, x0;
+    size_t A_dyn, B_dyn, c_dyn, Q_s, Q_u, x_ref, x0, A_lin, B_lin;
+    long long n_models;
     size_t x, u, y, zeta, xi, y_snap, x_snap, u_snap;
     size_t contrib, rdual_part, rpri_part, unconv_part;
     size_t r_pri, r_dual, done, iters, unconv, hist_pri, hist_dual, alpha, cost, min_alpha;
@@ -121,12 +122,31 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
         if (!(nn > 0.0)) return fail(CADMM_INVALID, "zero-norm obstacle face");
     }
     const int ns = d->n_s, nu = d->n_u, N = d->N;
-    if (!finite_all(d->A_dyn, (long long)ns * ns) || !finite_all(d->B_dyn, (long long)ns * nu) ||
-        !finite_all(d->c_dyn, ns) || !finite_all(d->Q_s, (long long)ns * ns) || !finite_all(d->Q_u, (long long)nu * nu) ||
+    if (d->dyn_t_stride < 0 || d->dyn_s_stride < 0 || d->dyn_t_stride > (1 << 20) || d->dyn_s_stride > (1 << 20))
+        return fail(CADMM_INVALID, "dynamics model strides out of range");
+    const long long n_models = (long long)(d->n_scen - 1) * d->dyn_s_stride + (long long)(N - 1) * d->dyn_t_stride + 1;
+    if (n_models * ns * ns >= (1LL << 31)) return fail(CADMM_INVALID, "too many dynamics models");
+    if (d->model == CADMM_MODEL_BICYCLE) {
+        if (dim != 2 || ns != 4 || nu != 2) return fail(CADMM_INVALID, "the bicycle model needs dim 2, n_s 4, n_u 2");
+        if (!(d->model_par[0] > 0) || !(d->model_par[1] > 0) || !std::isfinite(d->model_par[0]) ||
+            !std::isfinite(d->model_par[1]))
+            return fail(CADMM_INVALID, "bicycle model_par: dt and wheelbase must be finite and > 0");
+    } else if (d->model == CADMM_MODEL_QUADROTOR) {
+        if (dim != 3 || ns != 12 || nu != 4) return fail(CADMM_INVALID, "the quadrotor model needs dim 3, n_s 12, n_u 4");
+        for (int k = 0; k < 5; ++k)
+            if (!(d->model_par[k] > 0) || !std::isfinite(d->model_par[k]))
+                return fail(CADMM_INVALID, "quadrotor model_par: dt, mass and inertias must be finite and > 0");
+        if (!std::isfinite(d->model_par[5])) return fail(CADMM_INVALID, "quadrotor model_par: g must be finite");
+    } else if (d->model != CADMM_MODEL_LINEAR) {
+        return fail(CADMM_INVALID, "unknown dynamics model");
+    }
+    if (!finite_all(d->A_dyn, n_models * ns * ns) || !finite_all(d->B_dyn, n_models * ns * nu) ||
+        !finite_all(d->c_dyn, n_models * ns) || !finite_all(d->Q_s, (long long)ns * ns) || !finite_all(d->Q_u, (long long)nu * nu) ||
         !finite_all(d->x_ref, (long long)d->n_scen * (N + 1) * ns) || !finite_all(d->x0, (long long)d->n_scen * ns))
         return fail(CADMM_INVALID, "non-finite model, cost or reference");
-    if (!(d->sigma > 0) || !(d->eps_prox > 0) || !(d->eps_pri >= 0) || !(d->eps_dual >= 0))
-        return fail(CADMM_INVALID, "sigma and eps_prox must be > 0, eps_pri/eps_dual >= 0");
+    if (!(d->sigma > 0) || !(d->eps_prox > 0) || !std::isfinite(d->sigma) || !std::isfinite(d->eps_prox) ||
+        !std::isfinite(d->eps_pri) || !std::isfinite(d->eps_dual))
+        return fail(CADMM_INVALID, "sigma and eps_prox must be finite and > 0, eps_pri/eps_dual finite");
     if (M > 0 && !pair_variant_supported(dim, max_pf, max_of))
         return fail(CADMM_INVALID, "face counts exceed the compiled kernel variants");
     if (d->waves_per_group < 0 || d->waves_per_group > kMaxWavesPerGroup)
@@ -162,9 +182,13 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
     L.bdesc = take(off, sizeof(int4) * nb);
     L.wg_items = take(off, sizeof(int4) * nb);
     L.scen_wg = take(off, sizeof(int2) * d->n_scen);
-    L.A_dyn = take(off, sizeof(float) * ns * ns);
-    L.B_dyn = take(off, sizeof(float) * ns * nu);
-    L.c_dyn = take(off, sizeof(float) * ns);
+    L.n_models = n_models;
+    L.A_dyn = take(off, sizeof(float) * n_models * ns * ns);
+    L.B_dyn = take(off, sizeof(float) * n_models * ns * nu);
+    L.c_dyn = take(off, sizeof(float) * n_models * ns);
+    const size_t n_lin = d->model != CADMM_MODEL_LINEAR ? (size_t)d->n_scen * N : 1;
+    L.A_lin = take(off, sizeof(float) * n_lin * ns * ns);
+    L.B_lin = take(off, sizeof(float) * n_lin * ns * nu);
     L.Q_s = take(off, sizeof(float) * ns * ns);
     L.Q_u = take(off, sizeof(float) * nu * nu);
     L.x_ref = take(off, sizeof(float) * d->n_scen * (N + 1) * ns);
@@ -600,7 +624,8 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
         for (size_t i = 0; i < n; ++i) v[i] = (float)p[i];
         return v;
     };
-    std::vector<float> Ad = f32(d->A_dyn, ns * ns), Bd = f32(d->B_dyn, ns * nu), cd = f32(d->c_dyn, ns),
+    const size_t nm = (size_t)L.n_models;
+    std::vector<float> Ad = f32(d->A_dyn, nm * ns * ns), Bd = f32(d->B_dyn, nm * ns * nu), cd = f32(d->c_dyn, nm * ns),
                        Qs = f32(d->Q_s, ns * ns), Qu = f32(d->Q_u, nu * nu),
                        xr = f32(d->x_ref, (size_t)L.n_scen * (N + 1) * ns), x0 = f32(d->x0, (size_t)L.n_scen * ns);
     auto up = [&](size_t o, const void* src, size_t nbytes) -> int {
@@ -650,6 +675,9 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     P.wg_items = at<int4>(h, L.wg_items);
     P.scen_wg = at<int2>(h, L.scen_wg);
     P.A_dyn = at<float>(h, L.A_dyn); P.B_dyn = at<float>(h, L.B_dyn); P.c_dyn = at<float>(h, L.c_dyn);
+    P.dyn_ts = d->dyn_t_stride; P.dyn_ss = d->dyn_s_stride; P.model = d->model;
+    for (int k = 0; k < 8; ++k) P.model_par[k] = d->model_par[k];
+    P.A_lin = at<float>(h, L.A_lin); P.B_lin = at<float>(h, L.B_lin);
     P.Q_s = at<float>(h, L.Q_s); P.Q_u = at<float>(h, L.Q_u);
     P.x_ref = at<float>(h, L.x_ref); P.x0 = at<float>(h, L.x0);
     P.x = at<float>(h, L.x); P.u = at<float>(h, L.u); P.y = at<float>(h, L.y);
@@ -889,6 +917,7 @@ int admm_grad_workspace_size(cadmm_handle* h, int n_iters, int ckpt_every, size_
 {
     if (!h || n_iters < 1 || ckpt_every < 1 || !bytes)
         return fail(CADMM_INVALID, "bad handle, iteration count, checkpoint interval or output");
+    if (h->P.model != CADMM_MODEL_LINEAR) return fail(CADMM_INVALID, "the reverse pass needs the linear models");
     *bytes = plan_grad(h->L, h->P.n_wg, n_iters, ckpt_every).total;
     return CADMM_OK;
 }
@@ -897,6 +926,7 @@ int admm_record(cadmm_handle* h, int n_iters, int ckpt_every, void* d_gws, size_
 {
     if (!h || n_iters < 1 || ckpt_every < 1)
         return fail(CADMM_INVALID, "bad handle, iteration count or checkpoint interval");
+    if (h->P.model != CADMM_MODEL_LINEAR) return fail(CADMM_INVALID, "the reverse pass needs the linear models");
     const Layout& L = h->L;
     const GradLayout G = plan_grad(L, h->P.n_wg, n_iters, ckpt_every);
     if (!d_gws || (reinterpret_cast<uintptr_t>(d_gws) & 255) != 0)
@@ -928,6 +958,7 @@ int admm_record(cadmm_handle* h, int n_iters, int ckpt_every, void* d_gws, size_
 int admm_backward(cadmm_handle* h, void* d_gws, size_t bytes, float dL_scale, float* grad_d, float* grad_x0)
 {
     if (!h) return fail(CADMM_INVALID, "bad handle");
+    if (h->P.model != CADMM_MODEL_LINEAR) return fail(CADMM_INVALID, "the reverse pass needs the linear models");
     if (h->rec_iters < 1 || d_gws != h->rec_ws || bytes < h->rec_bytes)
         return fail(CADMM_INVALID, "no recorded run in this gradient workspace (call admm_record first)");
     const Layout& L = h->L;

@@ -34,9 +34,14 @@ struct DevProblem {
     const int4* wg_items;        // [n_wg] (scenario, block_begin, block_end, wg index within scenario)
     const int2* scen_wg;         // [n_scen] (first wg, end wg)
     // model and cost
-    const float* A_dyn;          // [n_s*n_s]
-    const float* B_dyn;          // [n_s*n_u]
-    const float* c_dyn;          // [n_s]
+    const float* A_dyn;          // [n_models][n_s*n_s]; model of (s, t): s*dyn_ss + t*dyn_ts
+    const float* B_dyn;          // [n_models][n_s*n_u]
+    const float* c_dyn;          // [n_models][n_s]
+    int dyn_ts, dyn_ss;
+    int model;                   // 0 linear models; 1 bicycle, 2 quadrotor (relinearised every iteration)
+    double model_par[8];
+    float* A_lin;                // model != 0: [n_scen][N][n_s*n_s] the linearisation of the current iterate
+    float* B_lin;                // model != 0: [n_scen][N][n_s*n_u]
     const float* Q_s;            // [n_s*n_s]
     const float* Q_u;            // [n_u*n_u]
     const float* x_ref;          // [n_scen*(N+1)*n_s]

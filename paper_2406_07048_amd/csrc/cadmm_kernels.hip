@@ -312,14 +312,17 @@ __device__ int dual_newton(const Rows& rows, float (&z)[NV], int max_sweeps, flo
             zmax = fmaxf(zmax, fabsf(z[i]));
         }
         // converged (gradient at gtol of its scale), or stalled: iterates that
-        // stop improving below 4e-6 sc sit at the FP32 floor of the gradient
-        // (scaled dual error <= 7e-6 on C3 pairs against the FP64 active-set
-        // solution); iterating on only spends the budget. Inside the ADMM loop
-        // gtol = 1e-7, near the floor: each solve starts from the previous
-        // iteration's duals, and with 1e-6 the next iteration needed more
-        // sweeps (C3 pair phase 124 -> 90 us). Cold-started stateless batches
-        // use 1e-6 (scaled dual error <= 3.4e-6 on C3 pairs).
-        if (gmax <= gtol * sc || (gmax <= 4e-6f * sc && gmax >= 0.7f * gprev)) return it;
+        // stop improving below 5e-7 sc sit at the FP32 floor of the gradient
+        // (about 3e-8 to 1.3e-7 sc at the optimum of C2/C3 pairs, measured in
+        // an FP32 emulation against the FP64 active-set solution); iterating
+        // on only spends the budget. A looser stall level (4e-6 sc) let pairs
+        // with slow line searches stop with scaled dual errors up to 2e-5;
+        // at 5e-7 the same pairs reach 1e-7 for 3% more row passes. Inside
+        // the ADMM loop gtol = 1e-7, near the floor: each solve starts from
+        // the previous iteration's duals, and with 1e-6 the next iteration
+        // needed more sweeps (C3 pair phase 124 -> 90 us). Cold-started
+        // stateless batches use 1e-6 (scaled dual error <= 3.4e-6 on C3 pairs).
+        if (gmax <= gtol * sc || (gmax <= 5e-7f * sc && gmax >= 0.7f * gprev)) return it;
         gprev = gmax;
         float dz[NV];
 #pragma unroll
@@ -719,11 +722,13 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
         }
         if (lane == 0) { red_rd[wave] = rdw; red_un[wave] = unw; }
         __syncthreads();
+        // only the N step slots are written: the trajectory kernel reads
+        // slots t >= N (float4 loads over four steps) but never uses them
         float* out = P.contrib + (size_t)wg * NC * 64;
         for (int e = threadIdx.x; e < NC * 64; e += blockDim.x) {
+            if ((e & 63) >= N) continue;
             float acc = 0.f;
-            if ((e & 63) < N)
-                for (int w = 0; w < WB; ++w) acc += red[w * NC * 64 + e];
+            for (int w = 0; w < WB; ++w) acc += red[w * NC * 64 + e];
             out[e] = acc;
         }
         if (threadIdx.x == 0) {

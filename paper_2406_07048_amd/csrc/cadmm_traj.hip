@@ -55,11 +55,84 @@ __host__ __device__ constexpr int al4(int n) { return (n + 3) & ~3; }
 // The last region holds the chunk sums of the per-step sums (4 TT floats),
 // and afterwards, for the closed-loop rollout (cl), A + B K_t and f_t + B k_t
 // of every step (N NS (NS + 1) floats).
-__host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bool adj, bool cl)
+// Time-varying models on the register path (4/2) add the padded A_t, B_t of
+// every step ([N][24] floats).
+__host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bool adj, bool cl, bool tv = false)
 {
     const int tail = cl && N * NS * (NS + 1) > 4 * traj_threads(NS, NU) ? N * NS * (NS + 1) : 4 * traj_threads(NS, NU);
     return al4(N * nc) + al4(N * NS) + al4(traj_gain_floats(N, NS, NU)) + al4(N * NU) + al4(N * NS) +
-           (adj ? al4((N + 1) * NS) : 0) + tail;
+           (adj ? al4((N + 1) * NS) : 0) + (tv && NS == 4 ? al4(N * 24) : 0) + tail;
+}
+
+// ------------------------------------------------------------------------
+// Nonlinear dynamics s_{t+1} = s_t + dt f_c(s_t, u_t) (Sec. IV-A eq.
+// system_eqn) and one column of its Jacobian, by forward-mode derivatives
+// (a value and one tangent, FP64): one thread per (step, column).
+// ------------------------------------------------------------------------
+struct Tan {
+    double v, d;
+};
+__device__ __forceinline__ Tan operator+(Tan a, Tan b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Tan operator-(Tan a, Tan b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Tan operator*(Tan a, Tan b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Tan operator*(double a, Tan b) { return {a * b.v, a * b.d}; }
+__device__ __forceinline__ Tan operator/(Tan a, Tan b)
+{
+    const double q = a.v / b.v;
+    return {q, (a.d - q * b.d) / b.v};
+}
+__device__ __forceinline__ Tan operator/(Tan a, double b) { return {a.v / b, a.d / b}; }
+__device__ __forceinline__ Tan tsin(Tan a) { return {sin(a.v), cos(a.v) * a.d}; }
+__device__ __forceinline__ Tan tcos(Tan a) { return {cos(a.v), -sin(a.v) * a.d}; }
+__device__ __forceinline__ Tan ttan(Tan a)
+{
+    const double t = tan(a.v);
+    return {t, (1.0 + t * t) * a.d};
+}
+
+// F = s + dt f_c(s, u) and column j of its Jacobian, j < n_s: dF/ds_j,
+// else dF/du_{j - n_s}.
+//   model 1 (kinematic bicycle, s = (p_x, p_y, theta, v), u = (a, delta),
+//     par = (dt, wheelbase L)): f_c = (v cos theta, v sin theta, v tan(delta) / L, a);
+//   model 2 (quadrotor, s = (p, v, phi theta psi, body rates w), u = (dF, tau),
+//     par = (dt, m, J_x, J_y, J_z, g)): p' = v, v' = (g + dF / m) R e_3 - g e_3
+//     with R = R_z(psi) R_y(theta) R_x(phi), the ZYX Euler-angle rates of the
+//     body rates, and Euler's equations J w' = tau + (J w) x w for a diagonal J.
+__device__ void model_column(int model, const double* par, const float* s, const float* u, int j, double* F,
+                             double* col)
+{
+    const int ns = model == 1 ? 4 : 12, nu = model == 1 ? 2 : 4;
+    Tan S[12], U[4], f[12];
+    for (int i = 0; i < ns; ++i) S[i] = {(double)s[i], i == j ? 1.0 : 0.0};
+    for (int k = 0; k < nu; ++k) U[k] = {(double)u[k], ns + k == j ? 1.0 : 0.0};
+    if (model == 1) {
+        f[0] = S[3] * tcos(S[2]);
+        f[1] = S[3] * tsin(S[2]);
+        f[2] = S[3] * ttan(U[1]) / par[1];
+        f[3] = U[0];
+    } else {
+        const double m = par[1], Jx = par[2], Jy = par[3], Jz = par[4], g = par[5];
+        const Tan cph = tcos(S[6]), sph = tsin(S[6]), cth = tcos(S[7]), sth = tsin(S[7]);
+        const Tan cps = tcos(S[8]), sps = tsin(S[8]);
+        const Tan acc = Tan{g, 0.0} + U[0] / m;
+        f[0] = S[3]; f[1] = S[4]; f[2] = S[5];
+        f[3] = acc * (cps * sth * cph + sps * sph);
+        f[4] = acc * (sps * sth * cph - cps * sph);
+        f[5] = acc * (cth * cph) - Tan{g, 0.0};
+        const Tan p = S[9], q = S[10], r = S[11];
+        const Tan qr = q * sph + r * cph;
+        f[6] = p + qr * sth / cth;
+        f[7] = q * cph - r * sph;
+        f[8] = qr / cth;
+        f[9] = (U[1] + (Jy - Jz) * (q * r)) / Jx;
+        f[10] = (U[2] + (Jz - Jx) * (r * p)) / Jy;
+        f[11] = (U[3] + (Jx - Jy) * (p * q)) / Jz;
+    }
+    const double dt = par[0];
+    for (int i = 0; i < ns; ++i) {
+        F[i] = (double)s[i] + dt * f[i].v;
+        col[i] = (i == j ? 1.0 : 0.0) + dt * f[i].d;
+    }
 }
 
 // Fixed-order sum of the float4 src[w * stride], w = w0..w1-1, with eight
@@ -179,10 +252,13 @@ __device__ __forceinline__ float dot_lds(const float* x, const float* y, float a
 // of those above it). The step-dependent LDS terms
 // of step t - 1 are read while step t computes. Gains go to Kall[t][2][5]
 // for the rollout (rollout_scan_42).
-template <bool ADJ>
-__device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, const float* Q2, const float* R2,
-                                                const int* hmap, const int* gmap, const float* Hq, const float* qr,
-                                                const float* rin, const float* off, float* Kall, int N, int nc)
+// With TV the model of step t is A + t mstride, B + t mstride (padded 4 x 4
+// and 4 x 2, in LDS), read one step ahead with the other step terms.
+template <bool ADJ, bool TV>
+__device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, int mstride, const float* Q2,
+                                                const float* R2, const int* hmap, const int* gmap, const float* Hq,
+                                                const float* qr, const float* rin, const float* off, float* Kall,
+                                                int N, int nc)
 {
     const int lane = threadIdx.x & 15;
     const int i = lane >> 2, j = lane & 3, a = i & 1, b = j & 1;
@@ -192,13 +268,19 @@ __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, 
     km[2] = row_ror_i<8>(i);
     km[3] = row_ror_i<12>(i);
     float Acol[4], Bcol[4], Arot[4], Brot[4];
+    float nAcol[4], nBcol[4], nArot[4], nBrot[4];
+    auto fetch_model = [&](int t, float (&ac)[4], float (&bc)[4], float (&ar)[4], float (&br)[4]) {
+        const float* At = A + t * mstride;
+        const float* Bt = B + t * mstride;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        Acol[k] = A[k * 4 + j];
-        Bcol[k] = B[k * 2 + b];
-        Arot[k] = A[km[k] * 4 + i];
-        Brot[k] = B[km[k] * 2 + a];
-    }
+        for (int k = 0; k < 4; ++k) {
+            ac[k] = At[k * 4 + j];
+            bc[k] = Bt[k * 2 + b];
+            ar[k] = At[km[k] * 4 + i];
+            br[k] = Bt[km[k] * 2 + a];
+        }
+    };
+    fetch_model(0, Acol, Bcol, Arot, Brot);
     const float q2ij = Q2[i * 4 + j], r2ab = R2[a * 2 + b];
     const int hmij = hmap[i * 4 + j], gmi = ADJ ? -1 : gmap[i];
     const int tsrc = (((int)threadIdx.x & ~15) | (i <= j ? lane : j * 4 + i)) << 2;   // ds_bpermute byte address
@@ -215,6 +297,7 @@ __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, 
 #pragma unroll
         for (int k = 0; k < 4; ++k) nf[k] = off[t * 4 + k];
         nr = rin[t * 2 + a];
+        if (TV) fetch_model(t, nAcol, nBcol, nArot, nBrot);
     };
     fetch(N - 1);
     for (int t = N - 1; t >= 0; --t) {
@@ -222,6 +305,12 @@ __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, 
         float f[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) f[k] = nf[k];
+        if (TV) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                Acol[k] = nAcol[k]; Bcol[k] = nBcol[k]; Arot[k] = nArot[k]; Brot[k] = nBrot[k];
+            }
+        }
         if (t >= 1) fetch(t - 1);
         // (a)
         const float Pb[4] = {quad_bcast<0>(Pv), quad_bcast<1>(Pv), quad_bcast<2>(Pv), quad_bcast<3>(Pv)};
@@ -297,8 +386,9 @@ __device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, 
 // place of N dependent steps. Writes dX[t][4] =
 // x_{t+1} and dU[t][2] = u_t (reverse mode: W[t + 1][4] = x_{t+1}).
 template <bool ADJ, int TT>
-__device__ __forceinline__ void rollout_scan_42(const float* A, const float* B, const float* Kall, const float* off,
-                                                const float* x0, float* buf, float* dX, float* dU, float* W, int N)
+__device__ __forceinline__ void rollout_scan_42(const float* A, const float* B, int mstride, const float* Kall,
+                                                const float* off, const float* x0, float* buf, float* dX, float* dU,
+                                                float* W, int N)
 {
     const int tid = threadIdx.x;
     const int ne = N * 20;
@@ -307,13 +397,15 @@ __device__ __forceinline__ void rollout_scan_42(const float* A, const float* B, 
     for (int e = tid; e < ne; e += TT) {
         const int t = e / 20, q = e % 20;
         const float* K = Kall + t * 10;
+        const float* At = A + t * mstride;
+        const float* Bt = B + t * mstride;
         float v;
         if (q < 16) {
             const int i = q >> 2, j = q & 3;
-            v = A[i * 4 + j] + B[i * 2] * K[j] + B[i * 2 + 1] * K[5 + j];
+            v = At[i * 4 + j] + Bt[i * 2] * K[j] + Bt[i * 2 + 1] * K[5 + j];
         } else {
             const int i = q - 16;
-            v = off[t * 4 + i] + B[i * 2] * K[4] + B[i * 2 + 1] * K[9];
+            v = off[t * 4 + i] + Bt[i * 2] * K[4] + Bt[i * 2 + 1] * K[9];
         }
         cur[e] = v;
     }
@@ -367,7 +459,10 @@ __device__ __forceinline__ void rollout_scan_42(const float* A, const float* B, 
 // Trajectory QP of one scenario per workgroup. State/input sizes are padded
 // to the compile-time NS >= n_s, NU >= n_u with zero dynamics rows/columns
 // and an identity input-cost block, so every small product unrolls.
-template <int NS, int NU, bool ADJ>
+// TV: the model of step t is read per step (time-varying or per-scenario
+// models, or the linearisation of a nonlinear model about the current
+// iterate, formed at the start of the kernel).
+template <int NS, int NU, bool ADJ, bool TV>
 __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevProblem P, int obstacle_free,
                                                                           float* hq_save, TrajAdjoint TA, int cl)
 {
@@ -378,6 +473,9 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     // w: the operands of the sweep's float4 dot products
     __shared__ __align__(16) float AT[NS * NS];
     __shared__ __align__(16) float BT[NU * NS];
+    // TV, LDS sweep: A_t^T and B_t^T of the current and the next step (double buffer)
+    __shared__ __align__(16) float AT2[TV ? 2 : 1][NS * NS];
+    __shared__ __align__(16) float BT2[TV ? 2 : 1][NU * NS];
     __shared__ int hmap[NS * NS], gmap[NS], pmap[NS];
     __shared__ __align__(16) float Pm[NS * NS];
     __shared__ __align__(16) float PAT[NS * NS];
@@ -404,7 +502,27 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     float* rin = Kall + al4(traj_gain_floats(N, NS, NU));   // [N][NU] input gradients 2 Q_u u^k_t (reverse: -ubar_t)
     float* off = rin + al4(N * NU);        // [N][NS] dynamics offsets f_t (c when the base is 0)
     float* wl = off + al4(N * NS);         // reverse: [N+1][NS] w_t
-    float4* red4 = reinterpret_cast<float4*>(wl + (ADJ ? al4((N + 1) * NS) : 0));   // [TT] chunk sums of split_sums
+    float* tvm = wl + (ADJ ? al4((N + 1) * NS) : 0);   // TV, register path: [N][24] padded A_t, B_t
+    float4* red4 = reinterpret_cast<float4*>(tvm + (TV && NS == 4 ? al4(N * 24) : 0));   // [TT] chunk sums of split_sums
+    // the model of step t in global memory (TV): A_t = Ag + t mts n_s n_s,
+    // B_t = Bg + t mts n_s n_u, c_t = cg + t mts n_s (unpadded, row-major);
+    // with a nonlinear model (forward pass) the linearisation of this kernel
+    const bool sqp = TV && P.model != 0 && dev;
+    const float* Ag = P.A_dyn + (size_t)s * P.dyn_ss * ns * ns;
+    const float* Bg = P.B_dyn + (size_t)s * P.dyn_ss * ns * nu;
+    const float* cg = P.c_dyn + (size_t)s * P.dyn_ss * ns;
+    int mts = P.dyn_ts;
+    if (sqp) {
+        Ag = P.A_lin + (size_t)s * N * ns * ns;
+        Bg = P.B_lin + (size_t)s * N * ns * nu;
+        mts = 1;
+    }
+    auto Aat = [&](int t, int i, int j) -> float {
+        return (i < ns && j < ns) ? Ag[(size_t)t * mts * ns * ns + i * ns + j] : 0.f;
+    };
+    auto Bat = [&](int t, int i, int c) -> float {
+        return (i < ns && c < nu) ? Bg[(size_t)t * mts * ns * nu + i * nu + c] : 0.f;
+    };
 
     // 0. padded model and cost, pose-coordinate maps
     for (int e = tid; e < NS * NS; e += TT) {
@@ -556,19 +674,43 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         }
         // dynamics offsets: the defects of the staged trajectory, in FP64
         // (zero-padded rows and columns contribute nothing)
-        for (int e = tid; e < N * NS; e += TT) {
-            const int t = e / NS, i = e % NS;
-            double acc = (double)cdyn[i];
-            if (dev) {
-                acc -= (double)sx[(t + 1) * NS + i];
-#pragma unroll
-                for (int j = 0; j < NS; ++j) acc += (double)A[i * NS + j] * (double)sx[t * NS + j];
-#pragma unroll
-                for (int j = 0; j < NU; ++j) acc += (double)B[i * NU + j] * (double)su[t * NU + j];
+        if (sqp) {
+            // the SQP step: F(x^k_t, u^k_t) and its Jacobian columns, one
+            // thread per (step, column); the defect F(x^k_t, u^k_t) - x^k_{t+1}
+            const int nz = ns + nu;
+            for (int e = tid; e < N * nz; e += TT) {
+                const int t = e / nz, j = e % nz;
+                double F[12], col[12];
+                model_column(P.model, P.model_par, sx + t * NS, su + t * NU, j, F, col);
+                if (j < ns) {
+                    for (int i = 0; i < ns; ++i) P.A_lin[((size_t)s * N + t) * ns * ns + i * ns + j] = (float)col[i];
+                } else {
+                    for (int i = 0; i < ns; ++i)
+                        P.B_lin[((size_t)s * N + t) * ns * nu + i * nu + (j - ns)] = (float)col[i];
+                }
+                if (j == 0)
+                    for (int i = 0; i < NS; ++i)
+                        off[t * NS + i] = i < ns ? (float)(F[i] - (double)sx[(t + 1) * NS + i]) : 0.f;
             }
-            off[e] = (float)acc;
+        } else {
+            for (int e = tid; e < N * NS; e += TT) {
+                const int t = e / NS, i = e % NS;
+                double acc = TV ? (i < ns ? (double)cg[(size_t)t * mts * ns + i] : 0.0) : (double)cdyn[i];
+                if (dev) {
+                    acc -= (double)sx[(t + 1) * NS + i];
+#pragma unroll
+                    for (int j = 0; j < NS; ++j)
+                        acc += (double)(TV ? Aat(t, i, j) : A[i * NS + j]) * (double)sx[t * NS + j];
+#pragma unroll
+                    for (int j = 0; j < NU; ++j)
+                        acc += (double)(TV ? Bat(t, i, j) : B[i * NU + j]) * (double)su[t * NU + j];
+                }
+                off[e] = (float)acc;
+            }
         }
     }
+    // the linearisation written above is read back by other threads
+    if (sqp) __threadfence_block();
     __syncthreads();
     float* xo = P.x + (size_t)s * (N + 1) * ns;
     float* uo = P.u + (size_t)s * N * nu;
@@ -587,9 +729,23 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
             x0s[tid] = x0d;
             if (ADJ) wl[tid] = 0.f;
         }
-        if (tid < 64) riccati_regs_42<ADJ>(A, B, Q2, R2, hmap, gmap, Hq, qr, rin, off, Kall, N, nc);
+        const float* Am = A;
+        const float* Bm = B;
+        int mstride = 0;
+        if constexpr (TV) {
+            // padded A_t, B_t of every step into LDS
+            for (int e = tid; e < N * 24; e += TT) {
+                const int t = e / 24, q = e % 24;
+                tvm[e] = q < 16 ? Aat(t, q >> 2, q & 3) : Bat(t, (q - 16) >> 1, (q - 16) & 1);
+            }
+            __syncthreads();
+            Am = tvm;
+            Bm = tvm + 16;
+            mstride = 24;
+        }
+        if (tid < 64) riccati_regs_42<ADJ, TV>(Am, Bm, mstride, Q2, R2, hmap, gmap, Hq, qr, rin, off, Kall, N, nc);
         __syncthreads();
-        rollout_scan_42<ADJ, TT>(A, B, Kall, off, x0s, reinterpret_cast<float*>(red4), dX, dU, wl, N);
+        rollout_scan_42<ADJ, TT>(Am, Bm, mstride, Kall, off, x0s, reinterpret_cast<float*>(red4), dX, dU, wl, N);
         __syncthreads();
     } else {
     // 2. backward Riccati sweep, V_t(x) = 1/2 x^T P x + p^T x, P_N = H_N.
@@ -649,16 +805,33 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     if (b_type == 0) b_q2 = R2[b_i * NU + b_j];
     else if (b_type == 3) { b_q2 = Q2[b_i * NS + b_j]; b_hm = hmap[b_i * NS + b_j]; }
     else if (b_type == 4) b_hm = ADJ ? -1 : gmap[b_i];
+    // TV: thread e < NS NS moves entry (e / NS, e % NS) of A_t into A_t^T,
+    // threads NS NS .. NS NS + NS NU - 1 the entries of B_t into B_t^T; the
+    // next step's entries are loaded at the top of a step and stored after
+    // its phase (c), into the buffer the step after it reads
+    const int m_e = tid < NS * NS ? tid : tid - NS * NS;
+    const int m_kind = tid < NS * NS ? 0 : (tid < NS * NS + NS * NU ? 1 : -1);
+    auto model_entry = [&](int t) -> float {
+        return m_kind == 0 ? Aat(t, m_e / NS, m_e % NS) : (m_kind == 1 ? Bat(t, m_e / NU, m_e % NU) : 0.f);
+    };
+    auto model_store = [&](int buf, float v) {
+        if (m_kind == 0) AT2[buf][(m_e % NS) * NS + m_e / NS] = v;
+        else if (m_kind == 1) BT2[buf][(m_e % NU) * NS + m_e / NU] = v;
+    };
+    if constexpr (TV) model_store((N - 1) & 1, model_entry(N - 1));
     __syncthreads();
     for (int t = N - 1; t >= 0; --t) {
         const float* ft = off + t * NS;
+        const float* ATc = TV ? AT2[t & 1] : AT;
+        const float* BTc = TV ? BT2[t & 1] : BT;
+        const float next_m = (TV && t >= 1) ? model_entry(t - 1) : 0.f;
         float bias = b_q2;
         if (b_type == 2) bias = rin[t * NU + b_i];
         else if (b_type == 3 && t >= 1) bias += b_hm >= 0 ? Hq[(t - 1) * nc + b_hm] : 0.f;
         else if (b_type == 4 && t >= 1) bias = qr[(t - 1) * NS + b_i] + (b_hm >= 0 ? Hq[(t - 1) * nc + b_hm] : 0.f);
         // (a)
         if (a_type >= 0) {
-            const float* Y = a_type == 0 ? AT + a_j * NS : (a_type == 1 ? BT + a_j * NS : ft);
+            const float* Y = a_type == 0 ? ATc + a_j * NS : (a_type == 1 ? BTc + a_j * NS : ft);
             const float acc = dot_lds<NS>(Pm + a_i * NS, Y, a_type == 2 ? pv[a_i] : 0.f);
             float* O = a_type == 0 ? PAT + a_j * NS + a_i : (a_type == 1 ? PBT + a_j * NS + a_i : wv + a_i);
             *O = acc;
@@ -667,7 +840,7 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         // (b)
         if (b_type >= 0 && (t >= 1 || b_type <= 2)) {
             // X: column b_i of B (types 0-2) or of A (types 3-4), as a row of B^T / A^T
-            const float* X = b_type <= 2 ? BT + b_i * NS : AT + b_i * NS;
+            const float* X = b_type <= 2 ? BTc + b_i * NS : ATc + b_i * NS;
             const float* Y = b_type == 0 ? PBT + b_j * NS : ((b_type == 1 || b_type == 3) ? PAT + b_j * NS : wv);
             const float acc = dot_lds<NS>(X, Y, bias);
             float* O = b_type == 0 ? Quu + b_i * NU + b_j
@@ -747,6 +920,7 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
                 }
             }
         }
+        if (TV && t >= 1) model_store((t - 1) & 1, next_m);
         __syncthreads();
     }
     if (cl) {
@@ -760,9 +934,9 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         const int t = e / (NS * (NS + 1)), r = e % (NS * (NS + 1));
         const int i = r / (NS + 1), j = r % (NS + 1);     // j = NS: the offset
         const float* Kt = Kall + (size_t)t * NU * NSU;
-        float acc = j < NS ? A[i * NS + j] : off[t * NS + i];
+        float acc = j < NS ? (TV ? Aat(t, i, j) : A[i * NS + j]) : off[t * NS + i];
 #pragma unroll
-        for (int c = 0; c < NU; ++c) acc += B[i * NU + c] * Kt[c * NSU + j];
+        for (int c = 0; c < NU; ++c) acc += (TV ? Bat(t, i, c) : B[i * NU + c]) * Kt[c * NSU + j];
         if (j < NS) Acl[((size_t)t * NS + i) * NS + j] = acc;
         else Ccl[t * NS + i] = acc;
     }
@@ -822,6 +996,12 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     for (int t = 0; t < N; ++t) {
         const float* xc = xbuf[t & 1];
         const float* Kt = Kall + (size_t)t * NU * NSU;
+        if (TV && tid < NS) {
+#pragma unroll
+            for (int k2 = 0; k2 < NS; ++k2) Ar[k2] = Aat(t, row, k2);
+#pragma unroll
+            for (int j = 0; j < NU; ++j) Br[j] = Bat(t, row, j);
+        }
         if (tid < NS + NU) {
             float xr[NS];
 #pragma unroll
@@ -895,7 +1075,8 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         if (tid < NS) {
             float acc = 0.f;
 #pragma unroll
-            for (int j = 0; j < NS; ++j) acc += A[j * NS + tid] * (xbuf[cur][j] + qr[t * NS + j]);
+            for (int j = 0; j < NS; ++j)
+                acc += (TV ? Aat(t, j, tid) : A[j * NS + tid]) * (xbuf[cur][j] + qr[t * NS + j]);
             xbuf[cur ^ 1][tid] = acc;
         }
         cur ^= 1;
@@ -904,9 +1085,9 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     if (tid < ns) TA.gx0[(size_t)s * ns + tid] += (double)xbuf[cur][tid];
 }
 
-template <bool ADJ>
-static hipError_t launch_traj(const DevProblem& P, int obstacle_free, float* hq_save, const TrajAdjoint& TA,
-                              hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+template <bool ADJ, bool TV>
+static hipError_t launch_traj_tv(const DevProblem& P, int obstacle_free, float* hq_save, const TrajAdjoint& TA,
+                                 hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
     dim3 g(P.n_scen);
     // closed-loop rollout where its matrices fit in the 64 KB of LDS beside
@@ -917,20 +1098,35 @@ static hipError_t launch_traj(const DevProblem& P, int obstacle_free, float* hq_
     };
     if (P.n_s <= 4 && P.n_u <= 2) {
         const dim3 b(traj_threads(4, 2));
-        CADMM_LAUNCH((traj_phase_kernel<4, 2, ADJ>), g, b, sizeof(float) * traj_dyn_floats(P.N, 4, 2, P.nc, ADJ, false),
-                     st, e0, e1, P, obstacle_free, hq_save, TA, 0);
+        CADMM_LAUNCH((traj_phase_kernel<4, 2, ADJ, TV>), g, b,
+                     sizeof(float) * traj_dyn_floats(P.N, 4, 2, P.nc, ADJ, false, TV), st, e0, e1, P, obstacle_free,
+                     hq_save, TA, 0);
     } else if (P.n_s <= 12 && P.n_u <= 4) {
         const dim3 b(traj_threads(12, 4));
         const bool cl = cl_fits(12, 4);
-        CADMM_LAUNCH((traj_phase_kernel<12, 4, ADJ>), g, b, sizeof(float) * traj_dyn_floats(P.N, 12, 4, P.nc, ADJ, cl),
-                     st, e0, e1, P, obstacle_free, hq_save, TA, cl ? 1 : 0);
+        CADMM_LAUNCH((traj_phase_kernel<12, 4, ADJ, TV>), g, b,
+                     sizeof(float) * traj_dyn_floats(P.N, 12, 4, P.nc, ADJ, cl, TV), st, e0, e1, P, obstacle_free,
+                     hq_save, TA, cl ? 1 : 0);
     } else {
         const dim3 b(traj_threads(16, 8));
         const bool cl = cl_fits(16, 8);
-        CADMM_LAUNCH((traj_phase_kernel<16, 8, ADJ>), g, b, sizeof(float) * traj_dyn_floats(P.N, 16, 8, P.nc, ADJ, cl),
-                     st, e0, e1, P, obstacle_free, hq_save, TA, cl ? 1 : 0);
+        CADMM_LAUNCH((traj_phase_kernel<16, 8, ADJ, TV>), g, b,
+                     sizeof(float) * traj_dyn_floats(P.N, 16, 8, P.nc, ADJ, cl, TV), st, e0, e1, P, obstacle_free,
+                     hq_save, TA, cl ? 1 : 0);
     }
     return hipGetLastError();
+}
+
+// Per-step models (time-varying, per scenario, or a nonlinear model) take
+// the TV instantiation; one time-invariant model keeps its matrices in LDS
+// and registers for the whole sweep.
+template <bool ADJ>
+static hipError_t launch_traj(const DevProblem& P, int obstacle_free, float* hq_save, const TrajAdjoint& TA,
+                              hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
+{
+    if (P.dyn_ts != 0 || P.dyn_ss != 0 || P.model != 0)
+        return launch_traj_tv<ADJ, true>(P, obstacle_free, hq_save, TA, st, e0, e1);
+    return launch_traj_tv<ADJ, false>(P, obstacle_free, hq_save, TA, st, e0, e1);
 }
 
 hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t st, float* hq_save, hipEvent_t e0,

@@ -243,17 +243,76 @@ def test_setup_initial_iterate(cadmm, name):
     h.close()
 
 
-@pytest.mark.parametrize("name,k", [("c1", 4), ("c2", 10), ("c3", 3)])
+_ITERATES = {}
+
+
+def cached_iterate(prob, name, k):
+    """Oracle iterate k of a named workload (FP64), computed once per module
+    and continued from the nearest earlier cached iterate."""
+    key = (name, k)
+    if key not in _ITERATES:
+        prev = [j for (n, j) in _ITERATES if n == name and j < k]
+        if prev:
+            j = max(prev)
+            st = {a: v.copy() for a, v in _ITERATES[(name, j)].items()}
+        else:
+            j, st = 0, oracle.Problem(prob).init_state()
+        if k > j:
+            oracle.Problem(prob).run(st, k - j)
+        _ITERATES[key] = {a: v.copy() for a, v in st.items()}
+    return {a: v.copy() for a, v in _ITERATES[key].items()}
+
+
+def fp32(st):
+    """The iterate as the GPU receives it (every entry rounded to FP32)."""
+    return {a: np.asarray(v, np.float32).astype(np.float64) for a, v in st.items()}
+
+
+def deviation_errors(prob, g, o):
+    """Element-wise measures of what the method decides, per scenario (max):
+    ||d(x - x_ref)|| / ||x - x_ref|| over t = 1..N and ||du|| / ||u||."""
+    xr = np.asarray(prob["x_ref"]).reshape(o["x"].shape)
+    ed = eu = 0.0
+    for s in range(o["x"].shape[0]):
+        do = (o["x"][s] - xr[s])[1:]
+        ed = max(ed, np.linalg.norm((g["x"][s] - xr[s])[1:] - do) / max(np.linalg.norm(do), 1e-300))
+        eu = max(eu, np.linalg.norm(g["u"][s] - o["u"][s]) / max(np.linalg.norm(o["u"][s]), 1e-300))
+    return ed, eu
+
+
+ONE_STEP = [("c1", 4), ("c2", 0), ("c2", 30), ("c2", 60), ("c2", 100), ("c2", 150),
+            ("c3", 0), ("c3", 20), ("c3", 40), ("c3", 80)]
+
+
+@pytest.mark.parametrize("name,k", ONE_STEP)
 def test_one_step_parity(cadmm, name, k):
     """From a shared oracle iterate k, one GPU iteration equals one oracle
-    iteration (pair QPs, trajectory QP, multiplier update)."""
+    iteration (pair QPs, trajectory QP, multiplier update). Both start from
+    the iterate rounded to FP32, which is what the GPU receives.
+
+    Bars: trajectories 1e-4 (normwise, literal); duals 1e-5 per pair (scaled);
+    multipliers 1e-5 of their scale for step 3 alone, 1e-3 end to end; and
+    the element-wise measures ||d(x - x_ref)|| / ||x - x_ref|| and
+    ||du|| / ||u|| at 1e-3 in 2D. In 3D the quadrotor stays within
+    millimetres of its 25 m reference (||x - x_ref|| is 1e-5 to 3e-2 against
+    ||x|| = 304), so FP32 storage of the iterate alone moves these measures
+    by 2e-3 to 3e-2 (the oracle's own change when its input is rounded to
+    FP32, computed here); their bar there is 30 times that change (the GPU's
+    FP32 sums over 600 pairs per step and its FP32 Riccati on top), and they
+    are only printed while ||x - x_ref|| is below 100 FP32 units of the
+    trajectory (100 * 2^-23 ||x||: the initial iterates, where the deviation
+    is a few ulps of the positions and has no FP32 meaning)."""
     prob = workloads.make(name)
     say(f"[one step] {name} from iterate {k}")
-    P, st = oracle_iterate(prob, k)
+    st64 = cached_iterate(prob, name, k)
+    st = fp32(st64)
+    P = oracle.Problem(prob)
     h = cadmm.Handle(prob)
     h.set_state(x=st["x"], u=st["u"], y=st["y"], zeta=st["zeta"], xi=st["xi"])
     h.iterate(1)
     g = gpu_state(h)
+    alpha_g = h.scales().double().cpu().numpy()
+    h.close()
     xk = st["x"].copy()
     zk, xik = st["zeta"].copy(), st["xi"].copy()
     P.run(st, 1)
@@ -269,48 +328,100 @@ def test_one_step_parity(cadmm, name, k):
     # end to end the multipliers inherit the trajectory's rounding through T, R
     ez = (np.abs(g["zeta"] - st["zeta"]) / msc).max()
     exi = (np.abs(g["xi"] - st["xi"]).reshape(-1, dim, N) / msc.reshape(-1, 1, N)).max()
-    say(f"   traj {et:.2e} y worst {ey.max():.2e} | step-3 zeta {ez3:.2e} xi {exi3:.2e} "
+    # scales at the new trajectory (the certificate of Sec. III), at the GPU's trajectory
+    alpha_o = P.scale_all(g["x"])
+    ea = (np.abs(alpha_g - alpha_o) / np.maximum(np.abs(alpha_o), 1.0)).max()
+    ed, eu = deviation_errors(prob, g, st)
+    xr = np.asarray(prob["x_ref"]).reshape(st["x"].shape)
+    resolved = np.linalg.norm((st["x"] - xr)[:, 1:]) >= 100 * 2.0 ** -23 * np.linalg.norm(st["x"])
+    if dim == 2:
+        bar_d = bar_u = 1e-3
+    elif not resolved:
+        bar_d = bar_u = np.inf
+    else:
+        ref64 = {a: v.copy() for a, v in st64.items()}
+        P.run(ref64, 1)
+        id_, iu = deviation_errors(prob, st, ref64)
+        bar_d, bar_u = max(1e-3, 30 * id_), max(1e-3, 30 * iu)
+    say(f"   traj {et:.2e} dev {ed:.2e} (bar {bar_d:.1e}) u {eu:.2e} (bar {bar_u:.1e}) | y worst {ey.max():.2e} "
+        f"p99 {np.percentile(ey, 99):.2e} | alpha {ea:.2e} | step-3 zeta {ez3:.2e} xi {exi3:.2e} "
         f"| end-to-end zeta {ez:.2e} xi {exi:.2e}")
     assert et <= TOL_TRAJ and ey.max() <= TOL_DUAL
+    assert ea <= TOL_SCALE
+    assert ed <= bar_d and eu <= bar_u
     assert ez3 <= 1e-5 and exi3 <= 1e-5
     assert ez <= 1e-3 and exi <= 1e-3
-    h.close()
 
 
 def test_full_run_c1(cadmm):
     """C1 (the FP64 oracle configuration) run to convergence on the GPU in
-    FP32: trajectory within 1e-4 of the oracle's, same stopping iteration."""
+    FP32: trajectory within 1e-4 of the oracle's and the element-wise
+    deviation and input measures within 1e-3, same stopping iteration (+-1);
+    the final scale certificates within 1e-5. At the GPU's stopping iteration
+    (about 46) the duals per pair (scaled) against the oracle's at that
+    iteration carry the growth of 46 iterations of a nonconvex iteration
+    (one iteration from a shared iterate stays below 1e-5): bar 1e-4 per
+    pair, measured value printed."""
     prob = workloads.make("c1")
     say("[full run] c1")
     h = cadmm.Handle(prob)
     code, res = h.solve(200, check_every=1)
     g = gpu_state(h)
+    alpha_g = h.scales().double().cpu().numpy()
+    h.close()
     P, st = oracle_iterate(prob, 0)
     hist = P.run(st, 200)
-    say(f"   gpu iters {res[0]['iters']} oracle {hist['iters'][0]}; traj err {traj_error(g, st):.2e}")
+    it_g = res[0]["iters"]
+    ed, eu = deviation_errors(prob, g, st)
+    # the oracle run to the GPU's iteration count, for the duals
+    q = dict(prob)
+    q["eps_pri"] = q["eps_dual"] = -1.0
+    Pq, sq = oracle_iterate(q, 0)
+    Pq.run(sq, it_g)
+    xk_prev = sq["x"]
+    ey = scaled_y_errors(prob, xk_prev, g["y"], sq["y"])
+    ea = (np.abs(alpha_g - P.scale_all(g["x"])) / np.maximum(np.abs(P.scale_all(g["x"])), 1.0)).max()
+    say(f"   gpu iters {it_g} oracle {hist['iters'][0]}; traj err {traj_error(g, st):.2e} dev {ed:.2e} u {eu:.2e}; "
+        f"y worst {ey.max():.2e}; alpha {ea:.2e}; min alpha {res[0]['min_alpha']:.4f}")
     assert traj_error(g, st) <= TOL_TRAJ
-    assert abs(res[0]["iters"] - hist["iters"][0]) <= 1
+    assert ed <= 1e-3 and eu <= 1e-3
+    assert abs(it_g - hist["iters"][0]) <= 1
+    assert ey.max() <= 1e-4
+    assert ea <= TOL_SCALE
     assert res[0]["min_alpha"] > 0.95
-    h.close()
 
 
 @pytest.mark.parametrize("name,iters", [("c2", 60), ("c3", 40)])
 def test_full_run_trajectory(cadmm, name, iters):
     """Longer runs from a shared iterate (the oracle's initial one, since in 3D
     the initial LP certificate is not unique): the trajectories stay within
-    the parity bar of the oracle's."""
+    the parity bar of the oracle's every 10 iterations. The duals are
+    compared per pair every 10 iterations too: the iteration is not a
+    contraction (the collision constraints are nonconvex), so differences of
+    the trajectories feed back into the pair data and grow; the bar is 1e-5
+    for 99% of the pairs and 1e-4 for every pair (measured and printed per
+    checkpoint). The scales at the final trajectory are within 1e-5."""
     prob = workloads.make(name)
     say(f"[full run] {name} {iters} iterations from the oracle's initial iterate")
     P, st = oracle_iterate(prob, 0)
     h = cadmm.Handle(prob)
     h.set_state(x=st["x"], u=st["u"], y=st["y"], zeta=st["zeta"], xi=st["xi"])
-    h.iterate(iters)
-    g = gpu_state(h)
-    P.run(st, iters)
-    et = traj_error(g, st)
-    say(f"   traj err {et:.2e}")
-    assert et <= TOL_TRAJ
+    for k in range(10, iters + 1, 10):
+        h.iterate(10)
+        g = gpu_state(h)
+        P.run(st, 10)
+        et = traj_error(g, st)
+        ey = scaled_y_errors(prob, st["x"], g["y"], st["y"])
+        say(f"   k={k}: traj err {et:.2e}, y worst {ey.max():.2e} p99 {np.percentile(ey, 99):.2e} "
+            f"(pairs above 1e-5: {(ey > TOL_DUAL).sum()} of {ey.size})")
+        assert et <= TOL_TRAJ
+        assert np.percentile(ey, 99) <= TOL_DUAL and ey.max() <= 1e-4
+    alpha_g = h.scales().double().cpu().numpy()
     h.close()
+    alpha_o = P.scale_all(g["x"])
+    ea = (np.abs(alpha_g - alpha_o) / np.maximum(np.abs(alpha_o), 1.0)).max()
+    say(f"   final alpha {ea:.2e}")
+    assert ea <= TOL_SCALE
 
 
 @pytest.mark.parametrize("G", [1, 2, 4])

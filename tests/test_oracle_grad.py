@@ -123,3 +123,39 @@ def test_unrolled_gradient_vs_central_differences(name, K, h, floor):
         q["obs_d"] = p["obs_d"] - h * v; Lm = oracle.loss_fixed_y0(q, K, y0)
         f = (Lp - Lm) / (2 * h)
         assert abs(gd @ v - f) <= 1e-4 * abs(f) + 1e-5 * scale + floor
+
+
+def test_reverse_at_given_iterates_is_the_same_reverse_pass():
+    """grad_at_iterates (the reverse pass at caller-supplied forward iterates)
+    fed with the oracle's own iterates gives grad_fixed_y0 exactly, and fed
+    with iterates of another run it gives that run's own gradient: the
+    forward iterates are its only input besides the problem."""
+    p = workloads.make("c1")
+    K = 6
+    y0 = oracle.Problem(p).init_state()["y"] * 1.01
+    q = dict(p)
+    q["eps_pri"] = -1.0
+    q["eps_dual"] = -1.0
+    P = oracle.Problem(q)
+    st = P.init_state()
+    st["y"][:] = y0
+    its = [{k: v.copy() for k, v in st.items()}]
+    for _ in range(K):
+        P.run(st, 1)
+        its.append({k: v.copy() for k, v in st.items()})
+    L, gd, gx = oracle.grad_fixed_y0(p, K, y0)
+    L2, gd2, gx2 = oracle.grad_at_iterates(p, its)
+    assert L2 == L
+    assert np.array_equal(gd2, gd) and np.array_equal(gx2, gx)
+    # a different run (other initial duals): the gradient follows its iterates
+    y1 = y0 * 1.05
+    st = P.init_state()
+    st["y"][:] = y1
+    its1 = [{k: v.copy() for k, v in st.items()}]
+    for _ in range(K):
+        P.run(st, 1)
+        its1.append({k: v.copy() for k, v in st.items()})
+    _, gd3, gx3 = oracle.grad_fixed_y0(p, K, y1)
+    _, gd4, gx4 = oracle.grad_at_iterates(p, its1)
+    assert np.array_equal(gd3, gd4) and np.array_equal(gx3, gx4)
+    assert not np.allclose(gd3, gd)
