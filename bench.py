@@ -45,8 +45,15 @@ WORKLOADS = {
     "c3": dict(desc="3D quadrotor (3 boxes), 200 hull polyhedra (6-20 faces), N=40, "
                     "24000 pair QPs/iteration, up to 200 ADMM iterations, sigma=300", iters=200),
     "c1": dict(desc="2D rectangle, 3 obstacles, N=20, 60 pair QPs/iteration, 50 ADMM iterations", iters=50),
+    "c2tv": dict(desc="4 2D scenarios on curved references with one linearised bicycle model per scenario and "
+                      "step, 10 hull obstacles each, N=50, up to 200 ADMM iterations, sigma=300", iters=200),
+    "c2sqp": dict(desc="the C2 problem with the nonlinear kinematic bicycle relinearised about every iterate "
+                       "(one SQP step per ADMM iteration), up to 200 iterations", iters=200),
+    "c3sqp": dict(desc="the C3 problem with the nonlinear quadrotor relinearised about every iterate, "
+                       "up to 200 iterations", iters=200),
 }
-ALL_LEGS = ("c4", "plain", "c2", "c3", "stream", "grad", "cpu")
+ALL_LEGS = ("c4", "plain", "c2", "c3", "c2tv", "c2sqp", "c3sqp", "stream", "grad", "cpu")
+VALU_PEAK_INSTS = 256 * 2.4e9   # wave-wide VALU instructions per second: 256 CUs x 2.4 GHz x one per CU clock
 
 
 def say(msg):
@@ -54,20 +61,22 @@ def say(msg):
 
 
 def pair_bytes(prob):
-    """Algorithmic HBM bytes of one pair-phase launch: every pair reads its
-    previous duals (n floats), writes the new ones (n floats) and reads its
-    multipliers (1 + dim floats); every obstacle face (normal and offset,
-    dim + 1 floats) is read once. The trajectory is a few KB per scenario."""
+    """Algorithmic HBM bytes of one pair-phase launch, the per-pair figure of
+    the method's hot path: every pair reads its previous duals and writes the
+    new ones (2 n floats) and reads and writes its multipliers (2 (dim + 1)
+    floats, the update of Sec. IV-B counted with the pair that owns them);
+    every obstacle face (normal and offset, dim + 1 floats) is read once. The
+    trajectory is a few KB per scenario."""
     sc, part, obs, nrow, yoff, tot = workloads.block_layout(prob)
     N, dim = prob["N"], prob["dim"]
-    return 4.0 * (2 * tot + len(sc) * N * (1 + dim)) + 4.0 * len(prob["obs_d"]) * (dim + 1)
+    return 4.0 * (2 * tot + 2 * len(sc) * N * (1 + dim)) + 4.0 * len(prob["obs_d"]) * (dim + 1)
 
 
 def partial_bytes(n_wg, prob):
     """Bytes of per-workgroup contribution sums the pair kernel writes beside
-    the algorithmic traffic (nc floats for each of the 64 step slots)."""
+    the algorithmic traffic (nc floats for each of the N steps)."""
     nq = prob["dim"] + (1 if prob["dim"] == 2 else 3)
-    return 4.0 * n_wg * (nq * (nq + 1) // 2 + nq) * 64
+    return 4.0 * n_wg * (nq * (nq + 1) // 2 + nq) * prob["N"]
 
 
 def pairs_per_scenario(prob):
@@ -105,6 +114,36 @@ def measured_traffic(name, launch=None):
     if launch is not None and kv.get("launch") != f"{launch[0]},{launch[1]}":
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def measured_valu(name, launch=None):
+    """VALU instructions per launch of a kernel from the committed counter
+    summary profiles/<name>_valu.txt (SQ_INSTS_VALU per dispatch, with the
+    busy counters beside it); None when missing, taken from other sources or
+    at another launch shape."""
+    path = os.path.join(ROOT, "profiles", f"{name}_valu.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    if launch is not None and kv.get("launch") != f"{launch[0]},{launch[1]}":
+        return None
+    return float(kv["valu_insts_per_dispatch"])
+
+
+def valu_rate(insts, ms):
+    """Wave-wide VALU instructions issued per second against the issue peak
+    (one per CU per clock), from counted instructions and the live duration."""
+    if insts is None:
+        return None
+    rate = insts / (ms * 1e-3)
+    return {"insts_per_launch": insts, "issue_rate": rate, "peak": VALU_PEAK_INSTS, "frac": rate / VALU_PEAK_INSTS}
 
 
 def roofline(bytes_launch, ms, traffic, kernel, **extra):
@@ -176,6 +215,7 @@ def leg_c4(cadmm, torch, args):
     out["summary"] = residual_summary(prob, res, rp, rd)
     out["roofline"] = roofline(bl, ph[0], measured_traffic("pair_phase_c4", (W, G)), "pair_phase_kernel",
                                overhead_bytes=partial_bytes(n_wg, prob),
+                               valu=valu_rate(measured_valu("pair_phase_c4", (W, G)), ph[0]),
                                launch={"blocks_per_group": W, "workgroups": n_wg, "lanes_per_pair": G})
     return out
 
@@ -262,7 +302,8 @@ def leg_stream(cadmm, torch, n_pairs=1 << 22, reps=5):
     return dict(workload=f"{n_pairs} stateless pair QPs of the batched 2D shape ({rows} rows, 5-16 per pair)",
                 ms_per_launch=ms, pair_solves_per_s=n_pairs / (ms * 1e-3),
                 sweeps_mean=float(st[st >= 0].mean()), budget_hits=int((st < 0).sum()),
-                roofline=roofline(bytes_launch, ms, measured_traffic("pair_qp_batch_stream"), "pair_qp_batch_kernel"))
+                roofline=roofline(bytes_launch, ms, measured_traffic("pair_qp_batch_stream"), "pair_qp_batch_kernel",
+                                  valu=valu_rate(measured_valu("pair_qp_batch_stream"), ms)))
 
 
 def leg_grad(cadmm, torch, steps=3, iters=100, every=10):
@@ -303,10 +344,11 @@ def leg_grad(cadmm, torch, steps=3, iters=100, every=10):
                 backward_forward_ratio=t_bwd / t_rec, grad_workspace_mb=nbytes / 1e6)
 
 
-def leg_cpu(prob, iters, budget_s=25.0):
+def leg_cpu(prob, iters, budget_s=25.0, min_s=10.0):
     """The FP64 oracle (OpenMP over the pair QPs) on the host cores, on the
     headline workload: its scenarios in order, each initialised and iterated
-    like the GPU run, until the time budget is spent."""
+    like the GPU run, in chunks of 16 scenarios, until at least min_s seconds
+    (starting over after the last scenario) or the budget is spent."""
     import oracle
     cores = oracle.set_threads(0)
     S = workloads.n_scenarios(prob)
@@ -315,19 +357,22 @@ def leg_cpu(prob, iters, budget_s=25.0):
     done = 0
     t0 = time.perf_counter()
     chunk = 16
-    for s0 in range(0, S, chunk):
+    s0 = 0
+    while True:
         idx = list(range(s0, min(S, s0 + chunk)))
         P = oracle.Problem(workloads.select_scenarios(prob, idx))
         st = P.init_state()
         hist = P.run(st, iters)
         solves += float((pps[idx] * hist["iters"]).sum())
         done += len(idx)
-        if time.perf_counter() - t0 >= budget_s:
+        s0 = 0 if s0 + chunk >= S else s0 + chunk
+        el = time.perf_counter() - t0
+        if el >= budget_s or (el >= min_s and s0 == 0):
             break
     el = time.perf_counter() - t0
     return dict(value=solves / el, unit="pair-QP solves/s", cores=int(cores), kind="oracle",
-                sample=f"{done} of {S} scenarios of the same batched workload (init + {iters} iterations each, "
-                       f"{int(solves)} pair QPs), {el:.1f} s wall")
+                sample=f"{done} scenario solves of the same batched workload ({S} scenarios, init + {iters} "
+                       f"iterations each, {int(solves)} pair QPs), {el:.1f} s wall")
 
 
 def main():
@@ -397,7 +442,7 @@ def main():
             out["batched_vs_plain"] = {"plain_pair_solves_per_s": pl["solves"] / pl["sec"],
                                        "plain_ms_per_step": pl["sec"] * 1e3,
                                        "speedup": pl["sec"] / sec * (c4["solves"] / max(pl["solves"], 1.0))}
-    for name in ("c2", "c3"):
+    for name in ("c2", "c3", "c2tv", "c2sqp", "c3sqp"):
         if name in legs:
             say(f"{name}: single scenario to the stopping test")
             out[name] = leg_single(cadmm, torch, name, args)

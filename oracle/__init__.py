@@ -69,6 +69,9 @@ def _declare(L):
     L.orc_pair_qp.restype = ctypes.c_int
     L.orc_pair_qp.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp,
                               ctypes.c_double, _dp, _dp, ctypes.c_double, _dp]
+    L.orc_pair_qp_lemke.restype = ctypes.c_int
+    L.orc_pair_qp_lemke.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp,
+                                    ctypes.c_double, _dp, _dp, ctypes.c_double, _dp]
     L.orc_traj_qp.restype = ctypes.c_int
     L.orc_traj_qp.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, _dp,
                               _dp, _dp, _dp, _dp, _dp]
@@ -153,6 +156,20 @@ def pair_qp(A, b, Cp, dp, zeta, xi, yhat, eps):
     it = lib().orc_pair_qp(dim, len(b), _d(A), _d(b), len(dp), _d(Cp), _d(dp),
                            float(zeta), _d(xi), _d(yhat), float(eps), _d(y))
     return y, it
+
+
+def pair_qp_lemke(A, b, Cp, dp, zeta, xi, yhat, eps):
+    """The dual-update sub-problem solved the paper's way (Sec. IV-C): the
+    equality eliminated, the KKT conditions as an LCP, Lemke's method.
+
+    Returns (y, status); status 0 = solved."""
+    A, b, Cp, dp = _f64(A), _f64(b), _f64(Cp), _f64(dp)
+    xi, yhat = _f64(xi), _f64(yhat)
+    dim = A.shape[1]
+    y = np.zeros(len(b) + len(dp) + 1)
+    st = lib().orc_pair_qp_lemke(dim, len(b), _d(A), _d(b), len(dp), _d(Cp), _d(dp),
+                                 float(zeta), _d(xi), _d(yhat), float(eps), _d(y))
+    return y, st
 
 
 def traj_qp(A, B, c, x0, H, h, Q_u):

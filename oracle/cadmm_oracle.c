@@ -404,6 +404,158 @@ int orc_pair_qp(int dim, int nr, const double *A, const double *b,
 }
 
 /* ------------------------------------------------------------------ */
+/* the paper's route for the dual-update QP (Sec. IV-C): elimination   */
+/* of the equality, the KKT conditions as an LCP, Lemke's method       */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Lemke's complementary pivoting for the LCP  w = M z + q, w, z >= 0,
+ * w^T z = 0  (n unknowns, M row-major). With q >= 0, z = 0. Otherwise an
+ * artificial variable z0 with covering vector e = 1 enters; each pivot
+ * brings in the complement of the variable that just left, with the
+ * lexicographic minimum-ratio rule (rows of the basis inverse break ties),
+ * until z0 leaves. Returns 0 (z written), 1 (secondary ray) or 2 (pivot
+ * limit).
+ */
+static int lemke(int n, const double *M, const double *q, double *z)
+{
+    int cols = 2 * n + 2;      /* w_1..w_n, z_1..z_n, z0, rhs */
+    double *T = (double *)calloc((size_t)n * cols, sizeof(double));
+    int *basis = (int *)malloc(sizeof(int) * n);
+    int st = 0;
+    /* rows: I w - M z - e z0 = q */
+    for (int i = 0; i < n; ++i) {
+        T[i * cols + i] = 1.0;
+        for (int j = 0; j < n; ++j) T[i * cols + n + j] = -M[i * n + j];
+        T[i * cols + 2 * n] = -1.0;
+        T[i * cols + 2 * n + 1] = q[i];
+        basis[i] = i;
+    }
+    int qmin = 0;
+    for (int i = 1; i < n; ++i) if (q[i] < q[qmin]) qmin = i;
+    for (int i = 0; i < n; ++i) z[i] = 0.0;
+    if (n == 0 || q[qmin] >= 0.0) { free(T); free(basis); return 0; }
+    int enter = 2 * n, leave_row = qmin;
+    for (int piv = 0; piv < 50 * n + 50; ++piv) {
+        /* pivot on (leave_row, enter) */
+        double pv = T[leave_row * cols + enter];
+        for (int j = 0; j < cols; ++j) T[leave_row * cols + j] /= pv;
+        for (int i = 0; i < n; ++i) {
+            if (i == leave_row) continue;
+            double f = T[i * cols + enter];
+            if (f != 0.0)
+                for (int j = 0; j < cols; ++j) T[i * cols + j] -= f * T[leave_row * cols + j];
+        }
+        int left = basis[leave_row];
+        basis[leave_row] = enter;
+        if (left == 2 * n) goto done;                    /* z0 left: solution */
+        enter = left < n ? n + left : left - n;           /* complement of the leaving variable */
+        /* lexicographic ratio test over rows with a positive entry */
+        leave_row = -1;
+        for (int i = 0; i < n; ++i) {
+            double a = T[i * cols + enter];
+            if (a <= 1e-12) continue;
+            if (leave_row < 0) { leave_row = i; continue; }
+            double ai = T[leave_row * cols + enter];
+            double r1 = T[i * cols + 2 * n + 1] / a, r0 = T[leave_row * cols + 2 * n + 1] / ai;
+            if (r1 < r0 - 1e-12 * (1.0 + fabs(r0))) { leave_row = i; continue; }
+            if (r1 > r0 + 1e-12 * (1.0 + fabs(r0))) continue;
+            for (int k = 0; k < n; ++k) {
+                double l1 = T[i * cols + k] / a, l0 = T[leave_row * cols + k] / ai;
+                if (l1 < l0 - 1e-14) { leave_row = i; break; }
+                if (l1 > l0 + 1e-14) break;
+            }
+        }
+        if (leave_row < 0) { st = 1; goto out; }
+    }
+    st = 2;
+    goto out;
+done:
+    for (int i = 0; i < n; ++i)
+        if (basis[i] >= n && basis[i] < 2 * n) z[basis[i] - n] = T[i * cols + 2 * n + 1];
+out:
+    free(T);
+    free(basis);
+    return st;
+}
+
+/*
+ * The dual-update QP of orc_pair_qp solved the paper's way (Sec. IV-C):
+ * (1) one equality variable y_e with kappa_e > 0 (reading: the largest b_k)
+ *     is eliminated, y_e = (eta - kappa_u^T y_u) / kappa_e, eta = 1, and its
+ *     sign condition becomes the inequality kappa~^T y_u <= eta~ with
+ *     kappa~ = kappa_u / kappa_e, eta~ = eta / kappa_e (eq.
+ *     const_least_square_ineq);
+ * (2) the KKT conditions of that QP (eq. kkt_conditions) are the LCP with
+ *     z = (y_u, phi), M = [[Q, kappa~], [-kappa~^T, 0]], q = (c, eta~)
+ *     (eq. linear_complementarity_problem), where Q and c are the Hessian
+ *     and gradient at y_u = 0 of the reduced objective: K~ K~^T and K~ b~
+ *     of the paper plus the proximal term eps/2 sum_l D_l (y_l - yhat_l)^2
+ *     carried through the elimination;
+ * (3) Lemke's method solves the LCP.
+ * Output y (n); returns 0, or a Lemke status (1 ray, 2 pivot limit) + 1.
+ */
+int orc_pair_qp_lemke(int dim, int nr, const double *A, const double *b,
+                      int no, const double *Cp, const double *dp,
+                      double zeta, const double *xi, const double *yhat, double eps,
+                      double *y)
+{
+    const int c = dim + 1;
+    double K[MAXROWS * (MAXD + 1)];
+    int n = build_K(dim, nr, A, no, Cp, dp, K);
+    double bh[MAXD + 1];
+    bh[0] = 1.0 + zeta;
+    for (int r = 0; r < dim; ++r) bh[1 + r] = xi[r];
+    double D[MAXROWS];
+    for (int l = 0; l < n; ++l) {
+        double s = 0.0;
+        for (int q = 0; q < c; ++q) s += K[l * c + q] * K[l * c + q];
+        D[l] = s;
+    }
+    int e = 0;
+    for (int k = 1; k < nr; ++k) if (b[k] > b[e]) e = k;
+    const double eta = 1.0, ke = b[e];
+    /* y = E y_u + f: y_e = eta~ - kappa~^T y_u, the others copy y_u */
+    int m = n - 1, map[MAXROWS];
+    for (int l = 0, u = 0; l < n; ++l) if (l != e) map[u++] = l;
+    double kt[MAXROWS];
+    for (int u = 0; u < m; ++u) kt[u] = map[u] < nr ? b[map[u]] / ke : 0.0;
+    const double etat = eta / ke;
+    /* Kt rows = K_u - kappa~ K_e; bt = bhat + K_e^T eta~ */
+    double Kt[MAXROWS * (MAXD + 1)], bt[MAXD + 1];
+    for (int u = 0; u < m; ++u)
+        for (int q = 0; q < c; ++q) Kt[u * c + q] = K[map[u] * c + q] - kt[u] * K[e * c + q];
+    for (int q = 0; q < c; ++q) bt[q] = bh[q] + K[e * c + q] * etat;
+    int nz = m + 1;
+    double *Mm = (double *)calloc((size_t)nz * nz, sizeof(double));
+    double qv[MAXROWS + 1], zz[MAXROWS + 1];
+    for (int u = 0; u < m; ++u) {
+        for (int v = 0; v < m; ++v) {
+            double s = 0.0;
+            for (int q = 0; q < c; ++q) s += Kt[u * c + q] * Kt[v * c + q];
+            s += eps * D[e] * kt[u] * kt[v];
+            if (u == v) s += eps * D[map[u]];
+            Mm[u * nz + v] = s;
+        }
+        Mm[u * nz + m] = kt[u];
+        Mm[m * nz + u] = -kt[u];
+        double s = 0.0;
+        for (int q = 0; q < c; ++q) s += Kt[u * c + q] * bt[q];
+        /* proximal gradient at y_u = 0: y_e = eta~, y_u = 0 */
+        s += eps * (-kt[u] * D[e] * (etat - yhat[e]) - D[map[u]] * yhat[map[u]]);
+        qv[u] = s;
+    }
+    qv[m] = etat;
+    int st = lemke(nz, Mm, qv, zz);
+    free(Mm);
+    if (st) return st + 1;
+    double ye = etat;
+    for (int u = 0; u < m; ++u) { y[map[u]] = zz[u]; ye -= kt[u] * zz[u]; }
+    y[e] = ye;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* pose R(s), rho(s) and their derivatives                             */
 /* ------------------------------------------------------------------ */
 

@@ -179,6 +179,11 @@ class _DescHolder:
         d.lanes_per_pair = int(lanes_per_pair)
         d.dyn_t_stride = int(prob.get("dyn_ts", 0))
         d.dyn_s_stride = int(prob.get("dyn_ss", 0))
+        # the library reads n_models models from these host arrays
+        n_models = (d.n_scen - 1) * max(d.dyn_s_stride, 0) + (d.N - 1) * max(d.dyn_t_stride, 0) + 1
+        for name, per in (("A_dyn", d.n_s * d.n_s), ("B_dyn", d.n_s * d.n_u), ("c_dyn", d.n_s)):
+            if keep[name].size < n_models * per:
+                raise ValueError(f"{name} holds {keep[name].size // per} models, the strides need {n_models}")
         d.model = int(prob.get("model", CADMM_MODEL_LINEAR))
         for i, v in enumerate(prob.get("model_par", ())):
             d.model_par[i] = float(v)

@@ -40,7 +40,7 @@ struct Layout {
     long long n_pairs, y_floats;
     int nc, nq, n_att, max_pf, max_of;
     // byte offsets into the workspace
-    size_t part_faces, part_face_ptr, part_off, obs_faces, obs_d64, obs_face_ptr, blocks, block_yoff, bdesc, wg_items,
+    size_t part_faces, part_face_ptr, part_off, obs_faces, obs_d64, obs_c64, obs_face_ptr, blocks, block_yoff, bdesc, wg_items,
         scen_wg;
     size_t A_dyn, B_dyn, c_dyn, Q_s, Q_u, x_ref, x0, A_lin, B_lin;
     long long n_models;
@@ -176,6 +176,7 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
     L.part_off = take(off, sizeof(float) * 3 * d->n_parts);
     L.obs_faces = take(off, sizeof(float4) * std::max(Fo, 1));
     L.obs_d64 = take(off, sizeof(double) * std::max(Fo, 1));
+    L.obs_c64 = take(off, sizeof(double) * 3 * std::max(Fo, 1));
     L.obs_face_ptr = take(off, sizeof(int) * (M + 1));
     L.blocks = take(off, sizeof(int4) * nb);
     L.block_yoff = take(off, sizeof(int) * nb);
@@ -226,7 +227,6 @@ struct cadmm_handle {
     DevProblem P;
     char* ws;
     hipStream_t stream;
-    hipStream_t cap;             // private stream used only for graph capture
     hipGraphExec_t g1, gK;       // 1-iteration and kGraphBlock-iteration graphs
     hipGraphExec_t g1n, gKn;     // the same without the stopping test (unrolled runs)
     int W, G, grid;             // pair blocks and lanes per pair of the pair-phase launch
@@ -285,19 +285,22 @@ int upload_worklists(cadmm_handle* h, int W)
 int enqueue_iteration(cadmm_handle* h, hipStream_t st, bool stop_test = true, float* hq_save = nullptr)
 {
     if (h->L.n_blocks > 0) HIP_TRY(launch_pair_phase(h->P, h->W, h->G, h->grid, st));
-    HIP_TRY(launch_traj_phase(h->P, h->L.n_blocks == 0 ? 1 : 0, st, hq_save));
+    // without pair blocks the LQ of a linear model is its own fixed point
+    // (solved from base 0); a nonlinear model is relinearised every iteration
+    const int no_pairs = h->L.n_blocks == 0 && h->P.model == CADMM_MODEL_LINEAR;
+    HIP_TRY(launch_traj_phase(h->P, no_pairs, st, hq_save));
     if (h->L.n_blocks > 0) HIP_TRY(launch_mult_phase(h->P, h->W, h->grid, st));
     if (stop_test) HIP_TRY(launch_residual(h->P, st));
     return CADMM_OK;
 }
 
-int capture(cadmm_handle* h, int iters, hipGraphExec_t* out, bool stop_test = true)
+int capture(cadmm_handle* h, hipStream_t cap, int iters, hipGraphExec_t* out, bool stop_test = true)
 {
     hipGraph_t g;
-    HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     int rc = CADMM_OK;
-    for (int i = 0; i < iters && rc == CADMM_OK; ++i) rc = enqueue_iteration(h, h->cap, stop_test);
-    hipError_t e = hipStreamEndCapture(h->cap, &g);
+    for (int i = 0; i < iters && rc == CADMM_OK; ++i) rc = enqueue_iteration(h, cap, stop_test);
+    hipError_t e = hipStreamEndCapture(cap, &g);
     if (rc != CADMM_OK) return rc;
     if (e != hipSuccess) return fail(CADMM_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
@@ -321,17 +324,24 @@ void release(cadmm_handle* h)
     for (hipEvent_t& e : h->ev_done)
         if (e) (void)hipEventDestroy(e);
     if (h->hdone) (void)hipHostFree(h->hdone);
-    (void)hipStreamDestroy(h->cap);
     delete h;
 }
 
+// The four graphs are captured on a stream of their own (capture cannot
+// run on a caller's legacy default stream), created for the capture and
+// destroyed right after it: a handle keeps no stream besides the caller's.
 int recapture(cadmm_handle* h)
 {
     drop_graphs(h);
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
     int rc;
-    if ((rc = capture(h, 1, &h->g1)) || (rc = capture(h, kGraphBlock, &h->gK)) ||
-        (rc = capture(h, 1, &h->g1n, false)) || (rc = capture(h, kGraphBlock, &h->gKn, false)))
+    if ((rc = capture(h, cap, 1, &h->g1)) || (rc = capture(h, cap, kGraphBlock, &h->gK)) ||
+        (rc = capture(h, cap, 1, &h->g1n, false)) || (rc = capture(h, cap, kGraphBlock, &h->gKn, false))) {
+        (void)hipStreamDestroy(cap);
         return rc;
+    }
+    HIP_TRY(hipStreamDestroy(cap));
     return CADMM_OK;
 }
 
@@ -576,11 +586,6 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     h->obs_ptr.assign(d->obs_ptr, d->obs_ptr + d->n_scen + 1);
     h->hdone = nullptr;
     h->ev_done[0] = h->ev_done[1] = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        delete h;
-        return fail(CADMM_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e));
-    }
     auto bail = [&](int code) {
         release(h);
         return code;
@@ -599,6 +604,9 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     for (int k = 0; k < L.Fo; ++k)
         of[k] = float4{(float)d->obs_C[k * dim], (float)d->obs_C[k * dim + 1],
                        dim == 3 ? (float)d->obs_C[k * dim + 2] : 0.f, (float)d->obs_d[k]};
+    std::vector<double> c64(3 * (size_t)std::max(L.Fo, 1), 0.0);
+    for (int k = 0; k < L.Fo; ++k)
+        for (int r = 0; r < dim; ++r) c64[3 * (size_t)k + r] = d->obs_C[k * dim + r];
     std::vector<float> poff(3 * L.n_parts, 0.f);
     for (int i = 0; i < L.n_parts; ++i)
         for (int r = 0; r < dim; ++r) poff[i * 3 + r] = (float)d->part_off[i * dim + r];
@@ -638,6 +646,7 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
         (rc = up(L.part_off, poff.data(), sizeof(float) * poff.size())) ||
         (rc = up(L.obs_faces, of.data(), sizeof(float4) * L.Fo)) ||
         (rc = up(L.obs_d64, d->obs_d, sizeof(double) * L.Fo)) ||
+        (rc = up(L.obs_c64, c64.data(), sizeof(double) * c64.size())) ||
         (rc = up(L.obs_face_ptr, d->obs_face_ptr, sizeof(int) * (L.M + 1))) ||
         (rc = up(L.blocks, blocks.data(), sizeof(int4) * blocks.size())) ||
         (rc = up(L.block_yoff, yoff.data(), sizeof(int) * yoff.size())) ||
@@ -668,6 +677,7 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     P.part_off = at<float>(h, L.part_off);
     P.obs_faces = at<float4>(h, L.obs_faces);
     P.obs_d64 = at<double>(h, L.obs_d64);
+    P.obs_c64 = at<double>(h, L.obs_c64);
     P.obs_face_ptr = at<int>(h, L.obs_face_ptr);
     P.blocks = at<int4>(h, L.blocks);
     P.block_yoff = at<int>(h, L.block_yoff);
@@ -862,7 +872,8 @@ int admm_phase_times(cadmm_handle* h, int n_iters, float* ms_out)
     for (int it = 0; it < n_iters && rc == CADMM_OK && err == hipSuccess; ++it) {
         hipEvent_t* e = &ev[(size_t)8 * it];
         if (pairs) err = launch_pair_phase(h->P, h->W, h->G, h->grid, st, e[0], e[1]);
-        if (err == hipSuccess) err = launch_traj_phase(h->P, pairs ? 0 : 1, st, nullptr, e[2], e[3]);
+        if (err == hipSuccess)
+            err = launch_traj_phase(h->P, !pairs && h->P.model == CADMM_MODEL_LINEAR, st, nullptr, e[2], e[3]);
         if (err == hipSuccess && pairs) err = launch_mult_phase(h->P, h->W, h->grid, st, e[4], e[5]);
         if (err == hipSuccess) err = launch_residual(h->P, st, e[6], e[7]);
     }

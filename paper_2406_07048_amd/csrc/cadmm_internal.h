@@ -25,6 +25,7 @@ struct DevProblem {
     const float* part_off;       // [P*3]
     const float4* obs_faces;     // [F_o] (c_x, c_y, c_z, d)
     const double* obs_d64;       // [F_o] face offsets d in FP64
+    const double* obs_c64;       // [F_o][3] face normals in FP64 (z = 0 in 2D)
     const int* obs_face_ptr;     // [M+1]
     // pair blocks and work lists
     const int4* blocks;          // [n_blocks] (scenario, part, obstacle, n_rows)

@@ -549,7 +549,7 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
                     const float c[3] = {f.x, f.y, f.z};
                     const float yl = yb[(pr.nr + l) * N];
                     pr.yhO[m] = yl;
-                    const float dp = face_offset(P.obs_d64, fo0 + l, f, ps.pos64, DIM);
+                    const float dp = face_offset(P.obs_d64, P.obs_c64, fo0 + l, ps.pos64, DIM);
                     float cn = 0.f;
 #pragma unroll
                     for (int r = 0; r < DIM; ++r) cn += c[r] * c[r];
@@ -786,7 +786,7 @@ __global__ void __launch_bounds__(512) mult_phase_kernel(DevProblem P)
                 if (l < no) {
                     const float4 f = P.obs_faces[fo0 + l];
                     const float y = yb[(nr + l) * N];
-                    const float dp = face_offset(P.obs_d64, fo0 + l, f, ps.pos64, DIM);
+                    const float dp = face_offset(P.obs_d64, P.obs_c64, fo0 + l, ps.pos64, DIM);
                     Sd += dp * y;
                     Sc[0] += f.x * y;
                     Sc[1] += f.y * y;
@@ -1088,6 +1088,7 @@ struct PairCols {
     const float4* rf;
     const float4* of;
     const double* d64;
+    const double* c64;
     float R[DIM * DIM];
     double pos64[DIM];
     float cmx;
@@ -1095,7 +1096,7 @@ struct PairCols {
     __device__ float cmax() const { return cmx; }
     __device__ float cost(int j) const {
         if (j < nr) return 0.f;
-        return face_offset(d64, fo0 + j - nr, of[j - nr], pos64, DIM);
+        return face_offset(d64, c64, fo0 + j - nr, pos64, DIM);
     }
     __device__ void col(int j, float (&E)[DIM + 1]) const {
         if (j < nr) {
@@ -1145,6 +1146,7 @@ __global__ void __launch_bounds__(256) init_pairs_kernel(DevProblem P, float* al
     for (int i = 0; i < DIM; ++i) pc.pos64[i] = ps.pos64[i];
     pc.fo0 = fo0;
     pc.d64 = P.obs_d64;
+    pc.c64 = P.obs_c64;
     float cm = 0.f;
     for (int l = 0; l < pc.no; ++l) cm = fmaxf(cm, fabsf(pc.cost(pc.nr + l)));
     pc.cmx = cm;

@@ -81,3 +81,39 @@ def test_too_many_faces_rejected():
     d = np.full(40, 1.0) + C @ np.array([20.0, 20.0])
     q = workloads.with_obstacles(p, [[(C, d)]])
     assert _size_code(q) == 1
+
+
+def test_time_varying_and_nonlinear_models_accepted():
+    """Per-scenario-and-step models and the nonlinear bicycle / quadrotor
+    pass validation; the workspace grows by the uploaded models."""
+    import paper_2406_07048_amd as cadmm
+    for name in ("c2tv", "c2sqp", "c3sqp"):
+        assert _size_code(workloads.make(name)) == 0
+    p = workloads.make("c2tv")
+    n_tv = cadmm.cadmm_workspace_size(p)[0]
+    q = dict(p)
+    q.update(A_dyn=p["A_dyn"][0], B_dyn=p["B_dyn"][0], c_dyn=p["c_dyn"][0], dyn_ts=0, dyn_ss=0)
+    assert n_tv > cadmm.cadmm_workspace_size(q)[0]
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda p: p.__setitem__("dyn_ts", -1),                                          # negative stride
+    lambda p: p.__setitem__("model", 7),                                            # unknown model
+    lambda p: p.__setitem__("model", 2),                                            # quadrotor needs 3D, 12/4
+    lambda p: p.update(model=1, model_par=np.array([0.0, 2.7])),                    # dt must be > 0
+])
+def test_invalid_dynamics_rejected(mutate):
+    p = workloads.make("c2tv")
+    p = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    mutate(p)
+    assert _size_code(p) == 1
+
+
+def test_short_model_arrays_refused_by_the_binding():
+    """The C ABI takes raw host pointers, so the binding checks that the
+    model arrays hold as many models as the strides address."""
+    import paper_2406_07048_amd as cadmm
+    p = workloads.make("c2tv")
+    p["A_dyn"] = p["A_dyn"][:10]
+    with pytest.raises(ValueError):
+        cadmm.cadmm_workspace_size(p)

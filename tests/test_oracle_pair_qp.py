@@ -201,3 +201,58 @@ def test_row_rescaling_invariance():
         y1, _ = oracle.pair_qp(A, b, Cp * s[:, None], dp * s, zeta, xi, yh1, 0.1)
         y1[len(b):len(b) + len(dp)] *= s
         assert np.allclose(y1, y0, atol=1e-9)
+
+
+@pytest.mark.parametrize("dim,eps", [(2, 1e-1), (3, 1e-1), (2, 1e-3), (3, 1e-3)])
+def test_lemke_route_equals_active_set(dim, eps):
+    """The paper's route (Sec. IV-C: the equality eliminated, eq.
+    const_least_square_ineq; its KKT conditions as the LCP of eq.
+    linear_complementarity_problem; Lemke's method) and the primal
+    active-set method give the same unique minimiser of the proximal QP."""
+    rng = np.random.default_rng(31 + dim)
+    worst = 0.0
+    for _ in range(40):
+        A, b, Cp, dp = make_pair(rng, dim, n_pts=9 if dim == 3 else 8)
+        zeta, xi, yhat = random_inputs(rng, A, b, Cp, dp)
+        y1, it = oracle.pair_qp(A, b, Cp, dp, zeta, xi, yhat, eps)
+        y2, st = oracle.pair_qp_lemke(A, b, Cp, dp, zeta, xi, yhat, eps)
+        assert it >= 0 and st == 0
+        worst = max(worst, np.abs(y1 - y2).max() / max(1.0, np.abs(y1).max()))
+    assert worst < 1e-8
+
+
+def test_lemke_route_without_proximal_term_is_optimal():
+    """eps = 0, the paper's QP as printed (Sec. IV-C eq. const_least_square):
+    the minimiser is not unique (the Hessian K K^T has rank <= dim + 1), so
+    the check is the KKT system of that QP, which certifies optimality of a
+    convex QP: y >= 0, kappa^T y = 1, K (K^T y + b) - nu kappa = w >= 0,
+    w^T y = 0; and the optimal value 0 exactly when alpha* >= 1 for zero
+    multipliers (LP duality, Sec. III-B)."""
+    rng = np.random.default_rng(5)
+    for dim in (2, 3):
+        for trial in range(30):
+            A, b, Cp, dp = make_pair(rng, dim, n_pts=8)
+            zeta, xi = (0.0, np.zeros(dim)) if trial % 2 == 0 else (rng.normal(), 0.3 * rng.normal(size=dim))
+            yhat = np.zeros(len(b) + len(dp) + 1)
+            y, st = oracle.pair_qp_lemke(A, b, Cp, dp, zeta, xi, yhat, 0.0)
+            assert st == 0
+            K = K_of(A, Cp, dp)
+            kap = np.r_[b, np.zeros(len(dp) + 1)]
+            r = K.T @ y + np.r_[1.0 + zeta, xi]
+            g = K @ r
+            free = y > 1e-9 * max(1.0, y.max())
+            # nu from the free rows with kappa > 0 (least squares over them)
+            fk = free & (kap > 0)
+            nu = (g[fk] @ kap[fk]) / (kap[fk] @ kap[fk]) if fk.any() else 0.0
+            w = g - nu * kap
+            scale = 1.0 + np.abs(K).sum() * (1.0 + y.max())
+            assert y.min() >= -1e-12 and abs(kap @ y - 1.0) < 1e-10
+            assert np.abs(w[free]).max() < 1e-8 * scale
+            assert w[~free].min() > -1e-8 * scale
+            if trial % 2 == 0:
+                alpha = oracle.scale_lp(A, b, Cp, dp)[0]
+                val = 0.5 * r @ r
+                if alpha > 1.0 + 1e-6:
+                    assert val < 1e-12
+                elif alpha < 1.0 - 1e-6:
+                    assert val > 1e-12

@@ -17,7 +17,12 @@ Problem dictionary (all numpy arrays, float64 unless noted):
   obs_ptr int32[n_scen+1]       obstacle range of each scenario
   obs_face_ptr int32[M_tot+1]   face range of each obstacle
   obs_C [F_o, dim] (unit normals), obs_d [F_o]
-  A_dyn [n_s, n_s], B_dyn [n_s, n_u], c_dyn [n_s]   (time-invariant)
+  A_dyn [n_s, n_s], B_dyn [n_s, n_u], c_dyn [n_s]   (one time-invariant model), or
+        [n_models, ...] with dyn_ts, dyn_ss: step t of scenario s uses model
+        s * dyn_ss + t * dyn_ts (optional keys, default 0)
+  model, model_par   optional nonlinear model (1 bicycle, 2 quadrotor) that the
+        method relinearises about every iterate; A_dyn/B_dyn/c_dyn then give the
+        initial trajectory only
   pos_idx int32[dim], att_idx int32[1|3], att_kind (0 planar yaw, 1 ZYX Euler)
   Q_s [n_s, n_s], Q_u [n_u, n_u], x_ref [n_scen, N+1, n_s], x0 [n_scen, n_s]
   sigma, eps_prox, eps_pri, eps_dual
@@ -129,6 +134,35 @@ def quadrotor_model(dt=0.1, mass=1.0, J=(0.01, 0.01, 0.02), g=9.81):
     return np.eye(12) + dt * Ac, dt * Bc, np.zeros(12)
 
 
+MODEL_LINEAR, MODEL_BICYCLE, MODEL_QUADROTOR = 0, 1, 2
+
+
+def bicycle_step(x, u, dt=0.1, wheelbase=2.7):
+    """One Euler step of the kinematic bicycle (p_x, p_y, theta, v), (a, delta)."""
+    px, py, th, v = x
+    a, de = u
+    return np.array([px + dt * v * np.cos(th), py + dt * v * np.sin(th),
+                     th + dt * v * np.tan(de) / wheelbase, v + dt * a])
+
+
+def bicycle_linearised(x, u, dt=0.1, wheelbase=2.7):
+    """(A, B, c) of the bicycle step linearised about (x, u):
+    step(x', u') ~ A x' + B u' + c."""
+    px, py, th, v = x
+    a, de = u
+    A = np.eye(4)
+    A[0, 2] = -dt * v * np.sin(th)
+    A[0, 3] = dt * np.cos(th)
+    A[1, 2] = dt * v * np.cos(th)
+    A[1, 3] = dt * np.sin(th)
+    A[2, 3] = dt * np.tan(de) / wheelbase
+    B = np.zeros((4, 2))
+    B[2, 1] = dt * v / (wheelbase * np.cos(de) ** 2)
+    B[3, 0] = dt
+    c = bicycle_step(x, u, dt, wheelbase) - A @ x - B @ u
+    return A, B, c
+
+
 # --------------------------------------------------------------------------
 # problem assembly
 # --------------------------------------------------------------------------
@@ -225,6 +259,73 @@ def config_c2(seed=10):
     start_pts = [start, start + np.array([v * dt, 0.0])]
     obs = _obstacles_2d_hull(rng, 40, 0.0, 100.0, start_pts, np.hypot(6.0, 1.25), (3, 10))
     return _assemble_2d(parts, [obs], N, dt, v, start[None, :], sigma=SIGMA_PAPER)
+
+
+def config_c2tv(seed=13, n_scen=4, N=50, M=10, v=12.0, steer=(-0.05, -0.02, 0.02, 0.05)):
+    """2D, time-varying models: n_scen scenarios of the C1 rectangle, each
+    following its own arc (constant steering angle, 12 m/s) with the bicycle
+    linearised about every step of its reference (one model per scenario and
+    step: dyn_ss = N, dyn_ts = 1); M hull obstacles (3-10 faces, 2 m discs)
+    centred 2.5-5 m to either side of the arc."""
+    rng = np.random.default_rng(seed)
+    dt, L = 0.1, 2.7
+    A_r, b_r = box_faces([2.25, 1.0])
+    parts = [(A_r, b_r, np.zeros(2))]
+    x_ref = np.zeros((n_scen, N + 1, 4))
+    Ad = np.zeros((n_scen * N, 4, 4))
+    Bd = np.zeros((n_scen * N, 4, 2))
+    cd = np.zeros((n_scen * N, 4))
+    scen = []
+    for s in range(n_scen):
+        de = steer[s % len(steer)]
+        x = np.array([0.0, 20.0, 0.0, v])
+        x_ref[s, 0] = x
+        for t in range(N):
+            Ad[s * N + t], Bd[s * N + t], cd[s * N + t] = bicycle_linearised(x, (0.0, de), dt, L)
+            x = bicycle_step(x, (0.0, de), dt, L)
+            x_ref[s, t + 1] = x
+        start_pts = [x_ref[s, 0, :2], x_ref[s, 1, :2], x_ref[s, 2, :2]]
+        obs = []
+        while len(obs) < M:
+            t = int(rng.integers(10, N + 1))
+            th = x_ref[s, t, 2]
+            nrm = np.array([-np.sin(th), np.cos(th)])
+            c = x_ref[s, t, :2] + rng.choice([-1.0, 1.0]) * rng.uniform(2.5, 5.0) * nrm
+            pts = disc_points(rng, 12, 2.0, 2)
+            C, dl = hull_faces(pts)
+            if not (3 <= len(dl) <= 10):
+                continue
+            rad = np.linalg.norm(pts, axis=1).max()
+            if _reject_near_start(c, rad, start_pts, np.hypot(2.25, 1.0)):
+                continue
+            obs.append((C, dl + C @ c))
+        scen.append(obs)
+    ptr, A, b, off = _pack_parts(parts)
+    obs_ptr, face_ptr, C, d = _pack_obstacles(scen)
+    return _finish(dict(
+        dim=2, n_s=4, n_u=2, N=N, dt=dt,
+        part_face_ptr=ptr, part_A=A, part_b=b, part_off=off,
+        obs_ptr=obs_ptr, obs_face_ptr=face_ptr, obs_C=C, obs_d=d,
+        A_dyn=Ad, B_dyn=Bd, c_dyn=cd, dyn_ts=1, dyn_ss=N,
+        pos_idx=np.array([0, 1], np.int32), att_idx=np.array([2], np.int32), att_kind=ATT_YAW,
+        Q_s=np.diag([1.0, 1.0, 0.1, 0.1]), Q_u=np.diag([0.1, 0.1]),
+        x_ref=x_ref, x0=x_ref[:, 0, :].copy(), sigma=SIGMA_PAPER))
+
+
+def config_c2sqp(seed=10):
+    """C2 with the nonlinear kinematic bicycle relinearised about every
+    iterate (the given straight-line linearisation sets the initial
+    trajectory only)."""
+    p = config_c2(seed)
+    p.update(model=MODEL_BICYCLE, model_par=np.array([p["dt"], 2.7]))
+    return p
+
+
+def config_c3sqp(seed=25):
+    """C3 with the nonlinear quadrotor relinearised about every iterate."""
+    p = config_c3(seed)
+    p.update(model=MODEL_QUADROTOR, model_par=np.array([p["dt"], 1.0, 0.01, 0.01, 0.02, 9.81]))
+    return p
 
 
 def config_c4(seed=101, n_scen=256, m_range=(10, 80), f_range=(3, 12)):
@@ -441,6 +542,9 @@ CONFIGS = {
     "c2": config_c2,
     "c3": config_c3,
     "c4": config_c4,
+    "c2tv": config_c2tv,
+    "c2sqp": config_c2sqp,
+    "c3sqp": config_c3sqp,
 }
 
 
@@ -469,6 +573,15 @@ def select_scenarios(prob, idx):
     out["obs_d"] = np.concatenate(d) if d else np.zeros(0)
     out["x_ref"] = prob["x_ref"][list(idx)].copy()
     out["x0"] = prob["x0"][list(idx)].copy()
+    ss = int(prob.get("dyn_ss", 0))
+    if ss:
+        # per-scenario models: the models of the kept scenarios, in order
+        ts, N = int(prob.get("dyn_ts", 0)), prob["N"]
+        span = (N - 1) * ts + 1
+        sel = np.concatenate([np.arange(s * ss, s * ss + span) for s in idx])
+        for k in ("A_dyn", "B_dyn", "c_dyn"):
+            out[k] = np.asarray(prob[k])[sel].copy()
+        out["dyn_ss"] = span
     return out
 
 
