@@ -33,8 +33,14 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("paper_2406_07048_amd/csrc/cadmm_kernels.hip", "paper_2406_07048_amd/csrc/cadmm_device.h",
-                  "paper_2406_07048_amd/csrc/cadmm_internal.h")
+_CSRC = "paper_2406_07048_amd/csrc/"
+_COMMON = (_CSRC + "cadmm_solvers.h", _CSRC + "cadmm_device.h", _CSRC + "cadmm_internal.h")
+# the sources each profiled kernel is built from (a committed counter summary
+# counts only while they are unchanged)
+KERNEL_SOURCES = {
+    "pair_phase_kernel": (_CSRC + "cadmm_kernels.hip",) + _COMMON,
+    "pair_qp_batch_kernel": (_CSRC + "cadmm_batch.hip",) + _COMMON,
+}
 METRIC = "pair-QP solves/sec & ADMM iters/sec at res 1e-4 (batched vs plain); backward/forward ratio"
 
 WORKLOADS = {
@@ -84,57 +90,52 @@ def pairs_per_scenario(prob):
     return np.bincount(sc, minlength=workloads.n_scenarios(prob)) * prob["N"]
 
 
-def kernel_source_hash():
+def kernel_source_hash(kernel="pair_phase_kernel"):
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name, launch=None):
+def _summary(name, suffix, kernel, launch):
+    """Key-value lines of profiles/<name>_<suffix>.txt when it was taken from
+    the current sources of `kernel` (and, given, at the launch shape)."""
+    path = os.path.join(ROOT, "profiles", f"{name}_{suffix}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash(kernel):
+        return None
+    if launch is not None and kv.get("launch") != f"{launch[0]},{launch[1]}":
+        return None
+    return kv
+
+
+def measured_traffic(name, launch=None, kernel="pair_phase_kernel"):
     """HBM bytes per launch of a kernel from the committed counter summary
     profiles/<name>_hbm_traffic.txt (FETCH_SIZE and WRITE_SIZE per dispatch,
     scaled by what the same counters read for a plain copy of known size).
     None when the summary is missing, was taken from other kernel sources or,
     given launch = (blocks per workgroup, lanes per pair), at another launch
     shape."""
-    path = os.path.join(ROOT, "profiles", f"{name}_hbm_traffic.txt")
-    if not os.path.exists(path):
-        return None
-    kv = {}
-    with open(path) as f:
-        for line in f:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
-    if kv.get("source_hash") != kernel_source_hash():
-        return None
-    if launch is not None and kv.get("launch") != f"{launch[0]},{launch[1]}":
-        return None
-    return float(kv["traffic_bytes_per_launch"])
+    kv = _summary(name, "hbm_traffic", kernel, launch)
+    return None if kv is None else float(kv["traffic_bytes_per_launch"])
 
 
-def measured_valu(name, launch=None):
+def measured_valu(name, launch=None, kernel="pair_phase_kernel"):
     """VALU instructions per launch of a kernel from the committed counter
     summary profiles/<name>_valu.txt (SQ_INSTS_VALU per dispatch, with the
     busy counters beside it); None when missing, taken from other sources or
     at another launch shape."""
-    path = os.path.join(ROOT, "profiles", f"{name}_valu.txt")
-    if not os.path.exists(path):
-        return None
-    kv = {}
-    with open(path) as f:
-        for line in f:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
-    if kv.get("source_hash") != kernel_source_hash():
-        return None
-    if launch is not None and kv.get("launch") != f"{launch[0]},{launch[1]}":
-        return None
-    return float(kv["valu_insts_per_dispatch"])
+    kv = _summary(name, "valu", kernel, launch)
+    return None if kv is None else float(kv["valu_insts_per_dispatch"])
 
 
 def valu_rate(insts, ms):
@@ -302,8 +303,10 @@ def leg_stream(cadmm, torch, n_pairs=1 << 22, reps=5):
     return dict(workload=f"{n_pairs} stateless pair QPs of the batched 2D shape ({rows} rows, 5-16 per pair)",
                 ms_per_launch=ms, pair_solves_per_s=n_pairs / (ms * 1e-3),
                 sweeps_mean=float(st[st >= 0].mean()), budget_hits=int((st < 0).sum()),
-                roofline=roofline(bytes_launch, ms, measured_traffic("pair_qp_batch_stream"), "pair_qp_batch_kernel",
-                                  valu=valu_rate(measured_valu("pair_qp_batch_stream"), ms)))
+                roofline=roofline(bytes_launch, ms, measured_traffic("pair_qp_batch_stream", kernel="pair_qp_batch_kernel"),
+                                  "pair_qp_batch_kernel",
+                                  valu=valu_rate(measured_valu("pair_qp_batch_stream", kernel="pair_qp_batch_kernel"),
+                                                 ms)))
 
 
 def leg_grad(cadmm, torch, steps=3, iters=100, every=10):
@@ -388,13 +391,14 @@ def main():
                     help="fix the pair-kernel launch shape of the headline handle (blocks per workgroup W, lanes "
                          "per pair G) instead of autotuning it; the counter runs behind profiles/ use the "
                          "shape the autotuner picks, so that their dispatches are the bench's")
-    ap.add_argument("--source-hash", action="store_true", help="print the hash of the kernel sources and exit")
+    ap.add_argument("--source-hash", action="store_true",
+                    help="print the hashes of the profiled kernels' sources and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one plain device-to-device copy of MIB MiB (the reference for the HBM "
                          "byte counters) and exit")
     args = ap.parse_args()
     if args.source_hash:
-        print(kernel_source_hash())
+        print(json.dumps({k: kernel_source_hash(k) for k in KERNEL_SOURCES}))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build runs on a single GPU; the batched scenarios would "

@@ -261,6 +261,9 @@ int admm_backward(cadmm_handle* h, void* d_gws, size_t bytes, float dL_scale, fl
 
 void collision_admm_destroy(cadmm_handle* h);
 
+/* Solvers of the stateless pair-QP batch (cadmm_pair_batch.solver). */
+enum { CADMM_PAIR_NEWTON = 0, CADMM_PAIR_LEMKE = 1 };
+
 /*
  * Stateless batch of dual-update QPs (Sec. IV-C eq. const_least_square with
  * the proximal term): for each pair p with rows l in row_ptr[p]..row_ptr[p+1]-1
@@ -272,8 +275,24 @@ void collision_admm_destroy(cadmm_handle* h);
  *   outputs y[rows], r[n_pairs*(dim+1)] = K^T y + bhat, nu[n_pairs] (the
  *   multiplier of kappa^T y = 1 in the stationarity condition
  *   K r + eps D (y - yhat) - nu kappa - w = 0, w >= 0, w^T y = 0), status[n_pairs]
- *   (sweeps used, negative if the sweep budget ran out).
+ *   (sweeps used, -1 if the sweep budget ran out, -3 if the pair holds more
+ *   rows than the solver's row tile).
  * A pair may hold at most CADMM_MAX_PART_FACES + CADMM_MAX_OBS_FACES + 1 rows.
+ * solver: CADMM_PAIR_NEWTON, the dual semismooth Newton method in the
+ *   (dim+2)-dimensional dual (one lane per pair; max_sweeps 0 = 24); or
+ *   CADMM_PAIR_LEMKE, the route of Sec. IV-C: the equality variable with the
+ *   largest kappa eliminated (eq. const_least_square_ineq), the KKT
+ *   conditions as an LCP (eq. linear_complementarity_problem, the proximal
+ *   term carried through the elimination) solved by Lemke's complementary
+ *   pivoting, one wavefront per pair; max_sweeps then bounds the pivots
+ *   (0 = 200), status holds the pivots used or -1 (secondary ray), -2 (pivot
+ *   budget), -3 (rows outside 2..CADMM_MAX_PART_FACES + CADMM_MAX_OBS_FACES + 1).
+ * work, work_bytes: optional caller-owned DEVICE workspace (256-byte aligned,
+ *   work_bytes >= pair_qp_batch_workspace_size) for the dual Newton solver's
+ *   two-launch form: a wavefront runs as long as its slowest pair, so the
+ *   first launch stops every solve after three sweeps and queues the
+ *   unfinished ones, which a second launch resumes one per lane. The outputs
+ *   are bitwise those of the one-launch form (NULL work). Ignored by Lemke.
  */
 typedef struct cadmm_pair_batch {
     int n_pairs, dim;
@@ -288,9 +307,16 @@ typedef struct cadmm_pair_batch {
     float* r;
     float* nu;
     int* status;
+    int solver;
+    void* work;
+    size_t work_bytes;
 } cadmm_pair_batch;
 
 int pair_qp_batch(const cadmm_pair_batch* b, hipStream_t stream);
+
+/* Bytes of the workspace of pair_qp_batch's two-launch form for n_pairs pairs
+ * (a counter and one queue entry per pair). */
+int pair_qp_batch_workspace_size(int n_pairs, size_t* bytes);
 
 /*
  * Stateless batch of scale LPs (Sec. III-A eq. scale_opt and its dual Sec.

@@ -60,8 +60,12 @@ class CadmmPairBatch(ctypes.Structure):
         ("n_pairs", ctypes.c_int), ("dim", ctypes.c_int),
         ("row_ptr", _vp), ("K", _vp), ("kappa", _vp), ("yhat", _vp), ("bhat", _vp),
         ("eps", ctypes.c_float), ("max_sweeps", ctypes.c_int),
-        ("y", _vp), ("r", _vp), ("nu", _vp), ("status", _vp),
+        ("y", _vp), ("r", _vp), ("nu", _vp), ("status", _vp), ("solver", ctypes.c_int),
+        ("work", _vp), ("work_bytes", ctypes.c_size_t),
     ]
+
+
+CADMM_PAIR_NEWTON, CADMM_PAIR_LEMKE = 0, 1
 
 
 class CadmmScaleBatch(ctypes.Structure):
@@ -93,6 +97,7 @@ _SIGNATURES = {
     "admm_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_float, _vp, _vp]),
     "collision_admm_destroy": (None, [_vp]),
     "pair_qp_batch": (ctypes.c_int, [ctypes.POINTER(CadmmPairBatch), _vp]),
+    "pair_qp_batch_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "pair_scale_batch": (ctypes.c_int, [ctypes.POINTER(CadmmScaleBatch), _vp]),
     "cadmm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "cadmm_last_error": (ctypes.c_char_p, []),
@@ -430,11 +435,16 @@ def collision_admm_cost(obs_d, x0, handle, n_iters, ckpt_every=10, y0=None):
     return _COST_FN.apply(obs_d, x0, handle, n_iters, ckpt_every, y0)
 
 
-def pair_qp_batch(row_ptr, K, kappa, yhat, bhat, eps, max_sweeps=0, stream=None):
+def pair_qp_batch(row_ptr, K, kappa, yhat, bhat, eps, max_sweeps=0, stream=None, solver=CADMM_PAIR_NEWTON,
+                  work=None):
     """Stateless batch of proximal dual-update QPs (device tensors in, out).
 
     row_ptr int32 [P+1]; K float32 [rows, dim+1]; kappa, yhat [rows];
-    bhat [P, dim+1]. Returns (y [rows], r [P, dim+1], nu [P], status int32 [P])."""
+    bhat [P, dim+1]. Returns (y [rows], r [P, dim+1], nu [P], status int32 [P]).
+    solver: CADMM_PAIR_NEWTON (dual Newton) or CADMM_PAIR_LEMKE (the
+    elimination / LCP / Lemke route). work: a device uint8 tensor for the
+    dual Newton's two-launch form (pair_qp_batch_workspace_size bytes past a
+    256-byte aligned start)."""
     torch = _torch()
     n_pairs = row_ptr.numel() - 1
     dim = K.shape[1] - 1
@@ -442,10 +452,21 @@ def pair_qp_batch(row_ptr, K, kappa, yhat, bhat, eps, max_sweeps=0, stream=None)
     r = torch.empty_like(bhat)
     nu = torch.empty(n_pairs, dtype=torch.float32, device=K.device)
     status = torch.empty(n_pairs, dtype=torch.int32, device=K.device)
+    wptr, wbytes = None, 0
+    if work is not None:
+        wptr = (work.data_ptr() + 255) & ~255
+        wbytes = work.numel() - (wptr - work.data_ptr())
     b = CadmmPairBatch(n_pairs, dim, _ptr(row_ptr), _ptr(K), _ptr(kappa), _ptr(yhat), _ptr(bhat),
-                       float(eps), int(max_sweeps), _ptr(y), _ptr(r), _ptr(nu), _ptr(status))
+                       float(eps), int(max_sweeps), _ptr(y), _ptr(r), _ptr(nu), _ptr(status), int(solver),
+                       wptr, int(wbytes))
     _check(lib().pair_qp_batch(ctypes.byref(b), _stream_ptr(stream)), "pair_qp_batch")
     return y, r, nu, status
+
+
+def pair_qp_batch_workspace_size(n_pairs):
+    n = ctypes.c_size_t()
+    _check(lib().pair_qp_batch_workspace_size(int(n_pairs), ctypes.byref(n)), "pair_qp_batch_workspace_size")
+    return n.value
 
 
 def pair_scale_batch(a_ptr, A, b, o_ptr, Cp, dp, stream=None):

@@ -164,7 +164,7 @@ __global__ void __launch_bounds__(512) pair_adjoint_kernel(DevProblem P, PairAdj
             const int nr = uniform(P.part_face_ptr[part + 1] - fr0);
             const int fo0 = uniform(P.obs_face_ptr[obs]);
             const int no = uniform(P.obs_face_ptr[obs + 1] - fo0);
-            const double* cl = P.obs_c64 + 3 * (size_t)fo0;   // FP64 normals of the obstacle
+            const float4* cl = P.obs_dc + fo0;   // rounding of the obstacle's FP32 normals
             const int yoff = uniform(P.block_yoff[b]);
             const float4* rf = fl;
             const float4* of = fl + CADMM_MAX_PART_FACES;
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(512) pair_adjoint_kernel(DevProblem P, PairAdj
             for (int l = 0; l < no; ++l) {
                 const float4 f = of[l];
                 const float y = yn[(size_t)(nr + l) * N];
-                Sd += face_offset(dl, cl, l, ps.pos64, DIM) * y;
+                Sd += face_offset(dl, l, f, cl[l], ps.pos64, ps.pos, DIM) * y;
                 cb[0] += y * f.x;
                 cb[1] += y * f.y;
                 if (DIM == 3) cb[DIM - 1] += y * f.z;
@@ -359,7 +359,7 @@ __global__ void __launch_bounds__(512) pair_adjoint_kernel(DevProblem P, PairAdj
                 if (DIM == 3) cbk[DIM - 1] += yh * f.z;
                 const float y1 = yn[(size_t)(nr + l) * N];
                 if (y1 > 0.f) {
-                    const float dp = face_offset(dl, cl, l, ps.pos64, DIM);
+                    const float dp = face_offset(dl, l, f, cl[l], ps.pos64, ps.pos, DIM);
                     float om[D1];
                     om[0] = dp;
                     om[1] = f.x;
@@ -479,7 +479,7 @@ __global__ void __launch_bounds__(512) pair_adjoint_kernel(DevProblem P, PairAdj
                 const float c3[3] = {f.x, f.y, f.z};
                 const float y1 = yn[(size_t)(nr + l) * N];
                 const float yh = yk[(size_t)(nr + l) * N];
-                const float dp = face_offset(dl, cl, l, ps.pos64, DIM);
+                const float dp = face_offset(dl, l, f, cl[l], ps.pos64, ps.pos, DIM);
                 float dbar = y1 * rbar[0] + (mult ? yh * tb : 0.f);
                 float g = 0.f;
                 if (y1 > 0.f) {

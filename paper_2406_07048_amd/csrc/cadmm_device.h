@@ -131,18 +131,23 @@ struct Pose {
 };
 
 // Face offset of an obstacle face in the part frame, d'_l = d_l - c_l.pos.
-// Formed in FP64 from the FP64 offset, the FP64 normal (c64: 3 per face) and
-// the FP64 part centre: d_l and c_l.pos are world-frame numbers of the size
-// of the scene while d'_l is of the size of the clearance, so FP32 would
-// lose most of its digits to cancellation (with the FP32-rounded normal the
-// error alone is about 6e-8 |pos|, 6e-6 m at 100 m).
-__device__ __forceinline__ float face_offset(const double* d64, const double* c64, int face, const double* pos64,
-                                             int dim)
+// d_l and c_l.pos are world-frame numbers of the size of the scene while
+// d'_l is of the size of the clearance, so FP32 would lose most of its
+// digits to cancellation. Formed in FP64 from the FP64 offset d64, the FP32
+// normal f and the FP64 part centre, plus the normal's rounding dc = c_l -
+// (float)c_l (stored in FP32, |dc| <= 2^-24 |c_l|) times the FP32 centre:
+// without that term the rounded normal alone leaves 6e-8 |pos| (6e-6 m at
+// 100 m); with it the error is about 2^-48 |pos|.
+__device__ __forceinline__ float face_offset(const double* d64, int face, const float4& f, const float4& dc,
+                                             const double* pos64, const float* pos, int dim)
 {
-    const double* c = c64 + 3 * (size_t)face;
-    double acc = d64[face] - c[0] * pos64[0] - c[1] * pos64[1];
-    if (dim == 3) acc -= c[2] * pos64[2];
-    return (float)acc;
+    double acc = d64[face] - (double)f.x * pos64[0] - (double)f.y * pos64[1];
+    float corr = dc.x * pos[0] + dc.y * pos[1];
+    if (dim == 3) {
+        acc -= (double)f.z * pos64[2];
+        corr += dc.z * pos[2];
+    }
+    return (float)(acc - (double)corr);
 }
 
 template <int DIM>

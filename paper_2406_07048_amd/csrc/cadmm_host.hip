@@ -40,7 +40,7 @@ struct Layout {
     long long n_pairs, y_floats;
     int nc, nq, n_att, max_pf, max_of;
     // byte offsets into the workspace
-    size_t part_faces, part_face_ptr, part_off, obs_faces, obs_d64, obs_c64, obs_face_ptr, blocks, block_yoff, bdesc, wg_items,
+    size_t part_faces, part_face_ptr, part_off, obs_faces, obs_d64, obs_dc, obs_face_ptr, blocks, block_yoff, bdesc, wg_items,
         scen_wg;
     size_t A_dyn, B_dyn, c_dyn, Q_s, Q_u, x_ref, x0, A_lin, B_lin;
     long long n_models;
@@ -176,7 +176,7 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
     L.part_off = take(off, sizeof(float) * 3 * d->n_parts);
     L.obs_faces = take(off, sizeof(float4) * std::max(Fo, 1));
     L.obs_d64 = take(off, sizeof(double) * std::max(Fo, 1));
-    L.obs_c64 = take(off, sizeof(double) * 3 * std::max(Fo, 1));
+    L.obs_dc = take(off, sizeof(float4) * std::max(Fo, 1));
     L.obs_face_ptr = take(off, sizeof(int) * (M + 1));
     L.blocks = take(off, sizeof(int4) * nb);
     L.block_yoff = take(off, sizeof(int) * nb);
@@ -604,9 +604,13 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     for (int k = 0; k < L.Fo; ++k)
         of[k] = float4{(float)d->obs_C[k * dim], (float)d->obs_C[k * dim + 1],
                        dim == 3 ? (float)d->obs_C[k * dim + 2] : 0.f, (float)d->obs_d[k]};
-    std::vector<double> c64(3 * (size_t)std::max(L.Fo, 1), 0.0);
-    for (int k = 0; k < L.Fo; ++k)
-        for (int r = 0; r < dim; ++r) c64[3 * (size_t)k + r] = d->obs_C[k * dim + r];
+    // the rounding of each FP32 normal, kept for the FP64 face offsets
+    std::vector<float4> dc(std::max(L.Fo, 1), float4{0.f, 0.f, 0.f, 0.f});
+    for (int k = 0; k < L.Fo; ++k) {
+        float e[3] = {0.f, 0.f, 0.f};
+        for (int r = 0; r < dim; ++r) e[r] = (float)(d->obs_C[k * dim + r] - (double)(float)d->obs_C[k * dim + r]);
+        dc[k] = float4{e[0], e[1], e[2], 0.f};
+    }
     std::vector<float> poff(3 * L.n_parts, 0.f);
     for (int i = 0; i < L.n_parts; ++i)
         for (int r = 0; r < dim; ++r) poff[i * 3 + r] = (float)d->part_off[i * dim + r];
@@ -646,7 +650,7 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
         (rc = up(L.part_off, poff.data(), sizeof(float) * poff.size())) ||
         (rc = up(L.obs_faces, of.data(), sizeof(float4) * L.Fo)) ||
         (rc = up(L.obs_d64, d->obs_d, sizeof(double) * L.Fo)) ||
-        (rc = up(L.obs_c64, c64.data(), sizeof(double) * c64.size())) ||
+        (rc = up(L.obs_dc, dc.data(), sizeof(float4) * dc.size())) ||
         (rc = up(L.obs_face_ptr, d->obs_face_ptr, sizeof(int) * (L.M + 1))) ||
         (rc = up(L.blocks, blocks.data(), sizeof(int4) * blocks.size())) ||
         (rc = up(L.block_yoff, yoff.data(), sizeof(int) * yoff.size())) ||
@@ -677,7 +681,7 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     P.part_off = at<float>(h, L.part_off);
     P.obs_faces = at<float4>(h, L.obs_faces);
     P.obs_d64 = at<double>(h, L.obs_d64);
-    P.obs_c64 = at<double>(h, L.obs_c64);
+    P.obs_dc = at<float4>(h, L.obs_dc);
     P.obs_face_ptr = at<int>(h, L.obs_face_ptr);
     P.blocks = at<int4>(h, L.blocks);
     P.block_yoff = at<int>(h, L.block_yoff);
@@ -1031,7 +1035,8 @@ void collision_admm_destroy(cadmm_handle* h)
     release(h);
 }
 
-int pair_qp_batch(const cadmm_pair_batch* b, hipStream_t stream)
+namespace {
+int check_pair_batch(const cadmm_pair_batch* b)
 {
     if (!b) return fail(CADMM_INVALID, "batch is NULL");
     if (b->dim != 2 && b->dim != 3) return fail(CADMM_INVALID, "dim must be 2 or 3");
@@ -1040,8 +1045,35 @@ int pair_qp_batch(const cadmm_pair_batch* b, hipStream_t stream)
     if (!b->row_ptr || !b->K || !b->kappa || !b->yhat || !b->bhat || !b->y || !b->r || !b->nu || !b->status)
         return fail(CADMM_INVALID, "NULL buffer");
     if (!(b->eps > 0.f)) return fail(CADMM_INVALID, "eps must be > 0");
+    if (b->max_sweeps < 0) return fail(CADMM_INVALID, "max_sweeps < 0");
+    return CADMM_OK;
+}
+}  // namespace
+
+int pair_qp_batch_workspace_size(int n_pairs, size_t* bytes)
+{
+    if (n_pairs < 0 || !bytes) return fail(CADMM_INVALID, "n_pairs < 0 or NULL output");
+    *bytes = pair_qp_batch_work_bytes(n_pairs);
+    return CADMM_OK;
+}
+
+int pair_qp_batch(const cadmm_pair_batch* b, hipStream_t stream)
+{
+    int rc = check_pair_batch(b);
+    if (rc != CADMM_OK || b->n_pairs == 0) return rc;
+    if (b->solver == CADMM_PAIR_LEMKE) {
+        HIP_TRY(launch_pair_qp_lemke(b->n_pairs, b->dim, b->row_ptr, b->K, b->kappa, b->yhat, b->bhat, b->eps,
+                                     b->max_sweeps > 0 ? b->max_sweeps : 200, b->y, b->r, b->nu, b->status, stream));
+        return CADMM_OK;
+    }
+    if (b->solver != CADMM_PAIR_NEWTON) return fail(CADMM_INVALID, "unknown pair solver");
+    if (b->work) {
+        if ((reinterpret_cast<uintptr_t>(b->work) & 255) != 0 || b->work_bytes < pair_qp_batch_work_bytes(b->n_pairs))
+            return fail(CADMM_WORKSPACE, "pair-batch workspace misaligned or smaller than pair_qp_batch_workspace_size");
+    }
     HIP_TRY(launch_pair_qp_batch(b->n_pairs, b->dim, b->row_ptr, b->K, b->kappa, b->yhat, b->bhat, b->eps,
-                                 b->max_sweeps > 0 ? b->max_sweeps : 24, b->y, b->r, b->nu, b->status, stream));
+                                 b->max_sweeps > 0 ? b->max_sweeps : 24, b->y, b->r, b->nu, b->status, stream,
+                                 b->work));
     return CADMM_OK;
 }
 

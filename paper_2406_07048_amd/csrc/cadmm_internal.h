@@ -25,7 +25,7 @@ struct DevProblem {
     const float* part_off;       // [P*3]
     const float4* obs_faces;     // [F_o] (c_x, c_y, c_z, d)
     const double* obs_d64;       // [F_o] face offsets d in FP64
-    const double* obs_c64;       // [F_o][3] face normals in FP64 (z = 0 in 2D)
+    const float4* obs_dc;        // [F_o] rounding of the FP32 normals, c - (float)c (FP32; w unused)
     const int* obs_face_ptr;     // [M+1]
     // pair blocks and work lists
     const int4* blocks;          // [n_blocks] (scenario, part, obstacle, n_rows)
@@ -131,10 +131,17 @@ hipError_t launch_fill_int(int* p, long long n, int v, hipStream_t s);
 hipError_t launch_cost(const DevProblem& P, float* cost_out, hipStream_t s);
 hipError_t launch_min_alpha(const DevProblem& P, const float* alpha, float* out, hipStream_t s);
 
+// Stateless pair-QP batch by the dual Newton method; with work (a counter and
+// a queue, pair_qp_batch_work_bytes) in two launches: the second resumes the
+// solves still running after a few sweeps.
 hipError_t launch_pair_qp_batch(int n_pairs, int dim, const int* row_ptr, const float* K,
                                 const float* kappa, const float* yhat, const float* bhat,
                                 float eps, int max_sweeps, float* y, float* r, float* nu, int* status,
-                                hipStream_t s);
+                                hipStream_t s, void* work = nullptr);
+size_t pair_qp_batch_work_bytes(int n_pairs);
+hipError_t launch_pair_qp_lemke(int n_pairs, int dim, const int* row_ptr, const float* K, const float* kappa,
+                                const float* yhat, const float* bhat, float eps, int max_pivots, float* y, float* r,
+                                float* nu, int* status, hipStream_t s);
 hipError_t launch_scale_batch(int n_pairs, int dim, const int* a_ptr, const float* A, const float* b,
                               const int* o_ptr, const float* Cp, const float* dp, float* alpha,
                               float* lam, float* mu, int* status, hipStream_t s);

@@ -14,7 +14,7 @@
 // equality) by a semismooth Newton method with an exact-sign line search;
 // the primal y is recovered row by row as max(0, yhat - (K_l v - kappa_l nu)
 // / (eps D_l)).
-#include "cadmm_device.h"
+#include "cadmm_solvers.h"
 
 #include <float.h>
 #include <math.h>
@@ -221,206 +221,6 @@ struct PairRows {
 };
 
 // ------------------------------------------------------------------------
-// generic rows (stateless batch entry point): K, kappa, yhat from memory
-// ------------------------------------------------------------------------
-
-template <int DIM>
-struct GenRows {
-    static constexpr int NV = DIM + 2;
-    int n;
-    const float* K;
-    const float* kap;
-    const float* yh;
-    float eps;
-    float bh[DIM + 1];
-
-    template <bool HESS>
-    __device__ __forceinline__ void pass(const float (&z)[NV], float (&g)[NV], float (&H)[NV * NV],
-                                         float& sc) const
-    {
-        float gv[DIM + 1] = {}, gnu = 0.f, ysc = 0.f;
-        if (HESS) {
-#pragma unroll
-            for (int i = 0; i < NV * NV; ++i) H[i] = 0.f;
-        }
-        for (int l = 0; l < n; ++l) {
-            float k[DIM + 1];
-            float D = 0.f;
-#pragma unroll
-            for (int c = 0; c <= DIM; ++c) { k[c] = K[l * (DIM + 1) + c]; D += k[c] * k[c]; }
-            const float kl = kap[l];
-            // v_rcp_f32 / v_rsq_f32 (about 1 ulp): this runs per row and per pass
-            const float ie = __builtin_amdgcn_rcpf(eps * D);
-            float s = -kl * z[DIM + 1];
-#pragma unroll
-            for (int c = 0; c <= DIM; ++c) s += k[c] * z[c];
-            const float y = fmaxf(0.f, yh[l] - s * ie);
-#pragma unroll
-            for (int c = 0; c <= DIM; ++c) gv[c] += y * k[c];
-            gnu += kl * y;
-            ysc += y * (D * __builtin_amdgcn_rsqf(fmaxf(D, 1e-30f)));
-            if (HESS && y > 0.f) {
-                float w[NV];
-#pragma unroll
-                for (int c = 0; c <= DIM; ++c) w[c] = k[c];
-                w[DIM + 1] = -kl;
-#pragma unroll
-                for (int r = 0; r < NV; ++r)
-#pragma unroll
-                    for (int c = r; c < NV; ++c) H[r * NV + c] += ie * w[r] * w[c];
-            }
-        }
-        float mx = 0.f, bm = 0.f;
-#pragma unroll
-        for (int c = 0; c <= DIM; ++c) {
-            g[c] = bh[c] - z[c] + gv[c];
-            mx = fmaxf(mx, fabsf(z[c]));
-            bm = fmaxf(bm, fabsf(bh[c]));
-        }
-        g[DIM + 1] = 1.f - gnu;
-        sc = 1.f + bm + mx + ysc;
-        if (HESS) {
-#pragma unroll
-            for (int c = 0; c <= DIM; ++c) H[c * NV + c] += 1.f;
-            H[(DIM + 1) * NV + DIM + 1] += 1e-6f * (1.f + H[(DIM + 1) * NV + DIM + 1]);
-#pragma unroll
-            for (int r = 0; r < NV; ++r)
-#pragma unroll
-                for (int c = 0; c < r; ++c) H[r * NV + c] = H[c * NV + r];
-        }
-    }
-};
-
-// ------------------------------------------------------------------------
-// semismooth Newton on the concave dual, shared by both row sources.
-// Returns the sweeps used, or -1 if the budget ran out (z is still the last
-// iterate, whose primal y is within the Newton region in practice).
-// ------------------------------------------------------------------------
-
-template <int NV, class Rows>
-__device__ int dual_newton(const Rows& rows, float (&z)[NV], int max_sweeps, float gtol)
-{
-    float gprev = FLT_MAX;
-    float al_prev = 1.f;   // step accepted by the previous sweep
-    for (int it = 0; it < max_sweeps; ++it) {
-        float g[NV], H[NV * NV], sc;
-        rows.template pass<true>(z, g, H, sc);
-        float gmax = 0.f, zmax = 0.f;
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            gmax = fmaxf(gmax, fabsf(g[i]));
-            zmax = fmaxf(zmax, fabsf(z[i]));
-        }
-        // converged (gradient at gtol of its scale), or stalled: iterates that
-        // stop improving below 5e-7 sc sit at the FP32 floor of the gradient
-        // (about 3e-8 to 1.3e-7 sc at the optimum of C2/C3 pairs, measured in
-        // an FP32 emulation against the FP64 active-set solution); iterating
-        // on only spends the budget. A looser stall level (4e-6 sc) let pairs
-        // with slow line searches stop with scaled dual errors up to 2e-5;
-        // at 5e-7 the same pairs reach 1e-7 for 3% more row passes. Inside
-        // the ADMM loop gtol = 1e-7, near the floor: each solve starts from
-        // the previous iteration's duals, and with 1e-6 the next iteration
-        // needed more sweeps (C3 pair phase 124 -> 90 us). Cold-started
-        // stateless batches use 1e-6 (scaled dual error <= 3.4e-6 on C3 pairs).
-        if (gmax <= gtol * sc || (gmax <= 5e-7f * sc && gmax >= 0.7f * gprev)) return it;
-        gprev = gmax;
-        float dz[NV];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) dz[i] = g[i];
-        chol_solve<NV>(H, dz);
-        // After a short step the direction is often steered by rows whose
-        // dual is about to reach zero; they stop it at the first kink every
-        // sweep. Re-solve with the generalised Hessian of the active set at
-        // the full step (a primal-dual active-set correction) and take that
-        // direction when it is still an ascent direction.
-        if (al_prev < 0.1f) {
-            float zt[NV], gt[NV], Ht[NV * NV], sct, dz2[NV];
-#pragma unroll
-            for (int i = 0; i < NV; ++i) zt[i] = z[i] + dz[i];
-            rows.template pass<true>(zt, gt, Ht, sct);
-#pragma unroll
-            for (int i = 0; i < NV; ++i) dz2[i] = g[i];
-            chol_solve<NV>(Ht, dz2);
-            float e0 = 0.f;
-#pragma unroll
-            for (int i = 0; i < NV; ++i) e0 += dz2[i] * g[i];
-            if (e0 > 0.f) {
-#pragma unroll
-                for (int i = 0; i < NV; ++i) dz[i] = dz2[i];
-            }
-        }
-        // Newton step at the rounding level of z: the active set is settled
-        // and z is the optimum to working precision
-        float dmax = 0.f;
-#pragma unroll
-        for (int i = 0; i < NV; ++i) dmax = fmaxf(dmax, fabsf(dz[i]));
-        if (dmax <= 1e-6f * (zmax + 1e-3f * sc)) {
-#pragma unroll
-            for (int i = 0; i < NV; ++i) z[i] += dz[i];
-            return it + 1;
-        }
-        float d0 = 0.f;
-#pragma unroll
-        for (int i = 0; i < NV; ++i) d0 += dz[i] * g[i];
-        if (!(d0 > 0.f)) return it;
-        // directional derivative of the dual along dz at step al; the trial
-        // with the smallest gradient is kept as a fallback
-        float best_al = 0.f, best_g = gmax;
-        auto dphi = [&](float al) {
-            float zt[NV], gt[NV], Hd[NV * NV], sct;
-#pragma unroll
-            for (int i = 0; i < NV; ++i) zt[i] = z[i] + al * dz[i];
-            rows.template pass<false>(zt, gt, Hd, sct);
-            float d = 0.f, gm = 0.f;
-#pragma unroll
-            for (int i = 0; i < NV; ++i) {
-                d += dz[i] * gt[i];
-                gm = fmaxf(gm, fabsf(gt[i]));
-            }
-            if (gm < best_g) {
-                best_g = gm;
-                best_al = al;
-            }
-            return d;
-        };
-        float al = 1.f;
-        const float d1 = dphi(1.f);
-        if (d1 < -1e-3f * d0) {
-            // Illinois regula falsi on the decreasing piecewise-linear dphi
-            float lo = 0.f, hi = 1.f, flo = d0, fhi = d1;
-            int side = 0;
-            for (int ls = 0; ls < 6; ++ls) {
-                al = (lo * (-fhi) + hi * flo) * __builtin_amdgcn_rcpf(flo - fhi);
-                const float fa = dphi(al);
-                if (fa >= -1e-3f * d0) {
-                    lo = al; flo = fa;
-                    if (side == 1) fhi *= 0.5f;
-                    side = 1;
-                    if (fa <= 0.1f * d0) break;
-                } else {
-                    hi = al; fhi = fa;
-                    if (side == -1) flo *= 0.5f;
-                    side = -1;
-                }
-            }
-            al = lo;
-            // no step along dz passes the sign test (the directional
-            // derivative is at its FP32 floor): take the trial that lowered
-            // the gradient most, else z cannot be improved along dz and every
-            // further sweep would repeat this one exactly
-            if (al == 0.f) {
-                if (best_al == 0.f) return it + 1;
-                al = best_al;
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < NV; ++i) z[i] += al * dz[i];
-        al_prev = al;
-    }
-    return -1;
-}
-
-// ------------------------------------------------------------------------
 // ADMM step 1: dual updates of every pair + linearised contributions
 // ------------------------------------------------------------------------
 
@@ -476,7 +276,8 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
     const int q = lane % G;
     const int t = chunk * PPW + lane / G + 1;
     float4* faces = reinterpret_cast<float4*>(lds);   // [WB][MR + MO] faces of each block
-    float* red = lds + 4 * WB * (MR + MO);            // [WB][NC][64] contributions by step
+    float4* dcs = faces + WB * (MR + MO);             // [WB][MO] rounding of the obstacle normals
+    float* red = lds + 4 * WB * (MR + 2 * MO);        // [WB][NC][64] contributions by step
     float* red_rd = red + WB * NC * 64;               // [W]
     int* red_un = reinterpret_cast<int*>(red_rd + W);
     const float eps = P.eps_prox;
@@ -495,7 +296,10 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
         float4* fl = faces + bslot * (MR + MO);
         if (b < item.z && chunk == 0) {
             if (lane < nrb) fl[lane] = P.part_faces[fr0 + lane];
-            else if (lane >= MR && lane - MR < nob) fl[lane] = P.obs_faces[fo0 + lane - MR];
+            else if (lane >= MR && lane - MR < nob) {
+                fl[lane] = P.obs_faces[fo0 + lane - MR];
+                dcs[bslot * MO + lane - MR] = P.obs_dc[fo0 + lane - MR];
+            }
         }
         __syncthreads();
         float con[NC];
@@ -549,7 +353,7 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
                     const float c[3] = {f.x, f.y, f.z};
                     const float yl = yb[(pr.nr + l) * N];
                     pr.yhO[m] = yl;
-                    const float dp = face_offset(P.obs_d64, P.obs_c64, fo0 + l, ps.pos64, DIM);
+                    const float dp = face_offset(P.obs_d64, fo0 + l, f, dcs[bslot * MO + l], ps.pos64, ps.pos, DIM);
                     float cn = 0.f;
 #pragma unroll
                     for (int r = 0; r < DIM; ++r) cn += c[r] * c[r];
@@ -786,7 +590,7 @@ __global__ void __launch_bounds__(512) mult_phase_kernel(DevProblem P)
                 if (l < no) {
                     const float4 f = P.obs_faces[fo0 + l];
                     const float y = yb[(nr + l) * N];
-                    const float dp = face_offset(P.obs_d64, P.obs_c64, fo0 + l, ps.pos64, DIM);
+                    const float dp = face_offset(P.obs_d64, fo0 + l, f, P.obs_dc[fo0 + l], ps.pos64, ps.pos, DIM);
                     Sd += dp * y;
                     Sc[0] += f.x * y;
                     Sc[1] += f.y * y;
@@ -852,251 +656,22 @@ __global__ void __launch_bounds__(64) residual_kernel(DevProblem P)
     }
 }
 
-// ------------------------------------------------------------------------
-// scale LP (Sec. III-A eq. scale_opt) through its dual (Sec. III-B eq.
-// scale_opt_dual) in standard form
-//   min dp^T mu  s.t.  b^T lam = 1,  A^T lam + Cp^T mu = 0,  lam, mu >= 0,
-// by a two-phase revised simplex (Bland's rule) with an explicit
-// (dim+1) x (dim+1) basis inverse in registers; columns are produced on the
-// fly from the geometry. The optimal basis is re-solved directly at the end.
-// ------------------------------------------------------------------------
-
-template <int DIM, class Cols>
-__device__ int revised_simplex(const Cols& cols, float& alpha, float* xB_out, int* basis_out)
-{
-    constexpr int m = DIM + 1;
-    const int n = cols.n();
-    float Bi[m * m];
-    float xB[m];
-    int basis[m];
-#pragma unroll
-    for (int i = 0; i < m; ++i) {
-#pragma unroll
-        for (int j = 0; j < m; ++j) Bi[i * m + j] = i == j ? 1.f : 0.f;
-        xB[i] = i == 0 ? 1.f : 0.f;
-        basis[i] = n + i;
-    }
-    const float ctol = 1e-6f * (1.f + cols.cmax());
-    const float ptol = 1e-6f;
-    int status = 0;
-    for (int phase = 1; phase <= 2 && status == 0; ++phase) {
-        int it = 0;
-        for (; it < 64; ++it) {
-            float cB[m];
-#pragma unroll
-            for (int i = 0; i < m; ++i)
-                cB[i] = phase == 1 ? (basis[i] >= n ? 1.f : 0.f) : (basis[i] < n ? cols.cost(basis[i]) : 0.f);
-            float pi[m];
-#pragma unroll
-            for (int q = 0; q < m; ++q) {
-                float acc = 0.f;
-#pragma unroll
-                for (int i = 0; i < m; ++i) acc += cB[i] * Bi[i * m + q];
-                pi[q] = acc;
-            }
-            int enter = -1;
-            float Eq[m];
-            for (int j = 0; j < n && enter < 0; ++j) {
-                bool basic = false;
-#pragma unroll
-                for (int i = 0; i < m; ++i) basic |= basis[i] == j;
-                if (basic) continue;
-                float E[m];
-                cols.col(j, E);
-                float rc = phase == 1 ? 0.f : cols.cost(j);
-#pragma unroll
-                for (int q = 0; q < m; ++q) rc -= pi[q] * E[q];
-                if (rc < -ctol) {
-                    enter = j;
-#pragma unroll
-                    for (int q = 0; q < m; ++q) Eq[q] = E[q];
-                }
-            }
-            if (enter < 0) break;
-            float u[m];
-#pragma unroll
-            for (int i = 0; i < m; ++i) {
-                float acc = 0.f;
-#pragma unroll
-                for (int q = 0; q < m; ++q) acc += Bi[i * m + q] * Eq[q];
-                u[i] = acc;
-            }
-            int leave = -1;
-            float best = 0.f;
-#pragma unroll
-            for (int i = 0; i < m; ++i) {
-                if (u[i] > ptol) {
-                    const float ratio = xB[i] / u[i];
-                    if (leave < 0 || ratio < best || (ratio == best && basis[i] < basis[leave])) {
-                        leave = i;
-                        best = ratio;
-                    }
-                }
-            }
-            if (leave < 0) { status = 2; break; }
-            float ur = 0.f;
-#pragma unroll
-            for (int i = 0; i < m; ++i) ur = i == leave ? u[i] : ur;
-            const float iu = 1.f / ur;
-            float rowB[m], xr = 0.f;
-#pragma unroll
-            for (int q = 0; q < m; ++q) {
-                float v = 0.f;
-#pragma unroll
-                for (int i = 0; i < m; ++i) v = i == leave ? Bi[i * m + q] : v;
-                rowB[q] = v * iu;
-            }
-#pragma unroll
-            for (int i = 0; i < m; ++i) xr = i == leave ? xB[i] : xr;
-            xr *= iu;
-#pragma unroll
-            for (int i = 0; i < m; ++i) {
-                if (i == leave) {
-#pragma unroll
-                    for (int q = 0; q < m; ++q) Bi[i * m + q] = rowB[q];
-                    xB[i] = xr;
-                    basis[i] = enter;
-                } else {
-#pragma unroll
-                    for (int q = 0; q < m; ++q) Bi[i * m + q] -= u[i] * rowB[q];
-                    xB[i] = fmaxf(0.f, xB[i] - u[i] * xr);
-                }
-            }
-        }
-        if (it >= 64) status = 3;
-        if (phase == 1 && status == 0) {
-            // pivot zero-level artificials out of the basis
-#pragma unroll
-            for (int i = 0; i < m; ++i) {
-                if (basis[i] < n) continue;
-                int piv = -1;
-                float bestv = 1e-5f, uu[m];
-                for (int j = 0; j < n; ++j) {
-                    bool basic = false;
-#pragma unroll
-                    for (int k = 0; k < m; ++k) basic |= basis[k] == j;
-                    if (basic) continue;
-                    float E[m];
-                    cols.col(j, E);
-                    float ui = 0.f;
-#pragma unroll
-                    for (int q = 0; q < m; ++q) ui += Bi[i * m + q] * E[q];
-                    if (fabsf(ui) > bestv) {
-                        bestv = fabsf(ui);
-                        piv = j;
-#pragma unroll
-                        for (int k = 0; k < m; ++k) {
-                            float acc = 0.f;
-#pragma unroll
-                            for (int q = 0; q < m; ++q) acc += Bi[k * m + q] * E[q];
-                            uu[k] = acc;
-                        }
-                    }
-                }
-                if (piv < 0) continue;
-                const float iu = 1.f / uu[i];
-                float rowB[m];
-#pragma unroll
-                for (int q = 0; q < m; ++q) rowB[q] = Bi[i * m + q] * iu;
-                const float xr = xB[i] * iu;
-#pragma unroll
-                for (int k = 0; k < m; ++k) {
-                    if (k == i) {
-#pragma unroll
-                        for (int q = 0; q < m; ++q) Bi[k * m + q] = rowB[q];
-                        xB[k] = xr;
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < m; ++q) Bi[k * m + q] -= uu[k] * rowB[q];
-                        xB[k] -= uu[k] * xr;
-                    }
-                }
-                basis[i] = piv;
-            }
-        }
-    }
-    // re-solve the optimal basis directly: Bmat x_B = f, pi^T Bmat = c_B^T
-    float Bm[m * m];
-#pragma unroll
-    for (int i = 0; i < m; ++i) {
-        float E[m];
-        if (basis[i] < n) cols.col(basis[i], E);
-        else {
-#pragma unroll
-            for (int q = 0; q < m; ++q) E[q] = q == basis[i] - n ? 1.f : 0.f;
-        }
-#pragma unroll
-        for (int q = 0; q < m; ++q) Bm[q * m + i] = E[q];   // column i of the basis matrix
-    }
-    // Gauss-Jordan inverse with partial pivoting
-    float Inv[m * m];
-#pragma unroll
-    for (int i = 0; i < m; ++i)
-#pragma unroll
-        for (int j = 0; j < m; ++j) Inv[i * m + j] = i == j ? 1.f : 0.f;
-#pragma unroll
-    for (int k = 0; k < m; ++k) {
-        int p = k;
-        float bv = fabsf(Bm[k * m + k]);
-#pragma unroll
-        for (int i = k + 1; i < m; ++i)
-            if (fabsf(Bm[i * m + k]) > bv) { bv = fabsf(Bm[i * m + k]); p = i; }
-        if (bv > 0.f) {
-#pragma unroll
-            for (int i = k + 1; i < m; ++i) {
-                if (i == p) {
-#pragma unroll
-                    for (int j = 0; j < m; ++j) {
-                        float t1 = Bm[k * m + j]; Bm[k * m + j] = Bm[i * m + j]; Bm[i * m + j] = t1;
-                        float t2 = Inv[k * m + j]; Inv[k * m + j] = Inv[i * m + j]; Inv[i * m + j] = t2;
-                    }
-                }
-            }
-            const float ip = 1.f / Bm[k * m + k];
-#pragma unroll
-            for (int j = 0; j < m; ++j) { Bm[k * m + j] *= ip; Inv[k * m + j] *= ip; }
-#pragma unroll
-            for (int i = 0; i < m; ++i) {
-                if (i == k) continue;
-                const float f = Bm[i * m + k];
-#pragma unroll
-                for (int j = 0; j < m; ++j) { Bm[i * m + j] -= f * Bm[k * m + j]; Inv[i * m + j] -= f * Inv[k * m + j]; }
-            }
-        } else {
-            status = status ? status : 4;
-        }
-    }
-    float cB[m];
-#pragma unroll
-    for (int i = 0; i < m; ++i) cB[i] = basis[i] < n ? cols.cost(basis[i]) : 0.f;
-    float pi0 = 0.f;
-#pragma unroll
-    for (int i = 0; i < m; ++i) pi0 += cB[i] * Inv[i * m + 0];
-#pragma unroll
-    for (int i = 0; i < m; ++i) {
-        xB_out[i] = fmaxf(0.f, Inv[i * m + 0]);   // f = e_0
-        basis_out[i] = basis[i];
-    }
-    alpha = -pi0;
-    return status;
-}
-
-// columns of the ADMM problem's pair (part frame through the pose)
 template <int DIM>
 struct PairCols {
     int nr, no, fo0;
     const float4* rf;
     const float4* of;
     const double* d64;
-    const double* c64;
+    const float4* dc;
     float R[DIM * DIM];
     double pos64[DIM];
+    float pos[DIM];
     float cmx;
     __device__ int n() const { return nr + no; }
     __device__ float cmax() const { return cmx; }
     __device__ float cost(int j) const {
         if (j < nr) return 0.f;
-        return face_offset(d64, c64, fo0 + j - nr, pos64, DIM);
+        return face_offset(d64, fo0 + j - nr, of[j - nr], dc[fo0 + j - nr], pos64, pos, DIM);
     }
     __device__ void col(int j, float (&E)[DIM + 1]) const {
         if (j < nr) {
@@ -1143,10 +718,13 @@ __global__ void __launch_bounds__(256) init_pairs_kernel(DevProblem P, float* al
 #pragma unroll
     for (int i = 0; i < DIM * DIM; ++i) pc.R[i] = ps.R[i];
 #pragma unroll
-    for (int i = 0; i < DIM; ++i) pc.pos64[i] = ps.pos64[i];
+    for (int i = 0; i < DIM; ++i) {
+        pc.pos64[i] = ps.pos64[i];
+        pc.pos[i] = ps.pos[i];
+    }
     pc.fo0 = fo0;
     pc.d64 = P.obs_d64;
-    pc.c64 = P.obs_c64;
+    pc.dc = P.obs_dc;
     float cm = 0.f;
     for (int l = 0; l < pc.no; ++l) cm = fmaxf(cm, fabsf(pc.cost(pc.nr + l)));
     pc.cmx = cm;
@@ -1165,126 +743,6 @@ __global__ void __launch_bounds__(256) init_pairs_kernel(DevProblem P, float* al
         }
         yb[nrow * N] = fmaxf(alpha - 1.f, 0.f);
     }
-}
-
-// ------------------------------------------------------------------------
-// stateless batch entry points
-// ------------------------------------------------------------------------
-
-template <int DIM>
-__global__ void __launch_bounds__(256) pair_qp_batch_kernel(int n_pairs, const int* row_ptr, const float* K,
-                                                            const float* kappa, const float* yhat,
-                                                            const float* bhat, float eps, int max_sweeps,
-                                                            float* y, float* r, float* nu_out, int* status)
-{
-    constexpr int NV = DIM + 2;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_pairs) return;
-    const int r0 = row_ptr[p], n = row_ptr[p + 1] - r0;
-    GenRows<DIM> gr;
-    gr.n = n;
-    gr.K = K + (size_t)r0 * (DIM + 1);
-    gr.kap = kappa + r0;
-    gr.yh = yhat + r0;
-    gr.eps = eps;
-#pragma unroll
-    for (int c = 0; c <= DIM; ++c) gr.bh[c] = bhat[(size_t)p * (DIM + 1) + c];
-    // warm start v = K^T yhat + bhat; nu makes the largest kappa-row stationary
-    float z[NV];
-#pragma unroll
-    for (int c = 0; c <= DIM; ++c) z[c] = gr.bh[c];
-    for (int l = 0; l < n; ++l)
-#pragma unroll
-        for (int c = 0; c <= DIM; ++c) z[c] += gr.yh[l] * gr.K[l * (DIM + 1) + c];
-    float best = -1.f, nu = 0.f;
-    for (int l = 0; l < n; ++l) {
-        if (gr.kap[l] > 0.f && gr.yh[l] > best) {
-            best = gr.yh[l];
-            float s = 0.f;
-#pragma unroll
-            for (int c = 0; c <= DIM; ++c) s += gr.K[l * (DIM + 1) + c] * z[c];
-            nu = s / gr.kap[l];
-        }
-    }
-    z[DIM + 1] = nu;
-    const int sw = dual_newton<NV>(gr, z, max_sweeps, 1e-6f);
-    float rr[DIM + 1];
-#pragma unroll
-    for (int c = 0; c <= DIM; ++c) rr[c] = gr.bh[c];
-    for (int l = 0; l < n; ++l) {
-        float D = 0.f, s = -gr.kap[l] * z[DIM + 1];
-#pragma unroll
-        for (int c = 0; c <= DIM; ++c) {
-            const float k = gr.K[l * (DIM + 1) + c];
-            D += k * k;
-            s += k * z[c];
-        }
-        const float yl = fmaxf(0.f, gr.yh[l] - s * __builtin_amdgcn_rcpf(eps * D));
-        y[r0 + l] = yl;
-#pragma unroll
-        for (int c = 0; c <= DIM; ++c) rr[c] += yl * gr.K[l * (DIM + 1) + c];
-    }
-#pragma unroll
-    for (int c = 0; c <= DIM; ++c) r[(size_t)p * (DIM + 1) + c] = rr[c];
-    nu_out[p] = z[DIM + 1];
-    status[p] = sw;
-}
-
-template <int DIM>
-struct MemCols {
-    int nr, no;
-    const float* A;
-    const float* b;
-    const float* Cp;
-    const float* dp;
-    float cmx;
-    __device__ int n() const { return nr + no; }
-    __device__ float cmax() const { return cmx; }
-    __device__ float cost(int j) const { return j < nr ? 0.f : dp[j - nr]; }
-    __device__ void col(int j, float (&E)[DIM + 1]) const {
-        if (j < nr) {
-            E[0] = b[j];
-#pragma unroll
-            for (int q = 0; q < DIM; ++q) E[1 + q] = A[j * DIM + q];
-        } else {
-            E[0] = 0.f;
-#pragma unroll
-            for (int q = 0; q < DIM; ++q) E[1 + q] = Cp[(j - nr) * DIM + q];
-        }
-    }
-};
-
-template <int DIM>
-__global__ void __launch_bounds__(256) scale_batch_kernel(int n_pairs, const int* a_ptr, const float* A,
-                                                          const float* b, const int* o_ptr, const float* Cp,
-                                                          const float* dp, float* alpha, float* lam,
-                                                          float* mu, int* status)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_pairs) return;
-    const int a0 = a_ptr[p], o0 = o_ptr[p];
-    MemCols<DIM> mc;
-    mc.nr = a_ptr[p + 1] - a0;
-    mc.no = o_ptr[p + 1] - o0;
-    mc.A = A + (size_t)a0 * DIM;
-    mc.b = b + a0;
-    mc.Cp = Cp + (size_t)o0 * DIM;
-    mc.dp = dp + o0;
-    float cm = 0.f;
-    for (int l = 0; l < mc.no; ++l) cm = fmaxf(cm, fabsf(mc.dp[l]));
-    mc.cmx = cm;
-    float al, xB[DIM + 1];
-    int basis[DIM + 1];
-    const int st = revised_simplex<DIM>(mc, al, xB, basis);
-    alpha[p] = al;
-    for (int j = 0; j < mc.nr + mc.no; ++j) {
-        float v = 0.f;
-#pragma unroll
-        for (int i = 0; i <= DIM; ++i) v = basis[i] == j ? xB[i] : v;
-        if (j < mc.nr) lam[a0 + j] = v;
-        else mu[o0 + j - mc.nr] = v;
-    }
-    status[p] = st;
 }
 
 // ------------------------------------------------------------------------
@@ -1378,7 +836,7 @@ static void launch_pair_g(const DevProblem& P, int W, int G, int grid, hipStream
 {
     const int nc = P.nc;
     const int nw = pair_waves_per_block(P.N, G);
-    const size_t lds = (size_t)W * (MR + MO) * sizeof(float4) + (size_t)W * nc * 64 * sizeof(float) +
+    const size_t lds = (size_t)W * (MR + 2 * MO) * sizeof(float4) + (size_t)W * nc * 64 * sizeof(float) +
                        2 * (size_t)W * nw * sizeof(float);
     dim3 blk(64 * W * nw), grd(grid);
     if (G == 4) CADMM_LAUNCH((pair_phase_kernel<DIM, MR, MO, 4>), grd, blk, lds, st, e0, e1, P);
@@ -1471,36 +929,6 @@ hipError_t launch_cost(const DevProblem& P, float* out, hipStream_t st)
 hipError_t launch_min_alpha(const DevProblem& P, const float* alpha, float* out, hipStream_t st)
 {
     hipLaunchKernelGGL(min_alpha_kernel, dim3(P.n_scen), dim3(64), 0, st, P, alpha, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_pair_qp_batch(int n_pairs, int dim, const int* row_ptr, const float* K, const float* kappa,
-                                const float* yhat, const float* bhat, float eps, int max_sweeps, float* y,
-                                float* r, float* nu, int* status, hipStream_t st)
-{
-    if (n_pairs <= 0) return hipSuccess;
-    const int grid = (n_pairs + 255) / 256;
-    if (dim == 2)
-        hipLaunchKernelGGL(pair_qp_batch_kernel<2>, dim3(grid), dim3(256), 0, st, n_pairs, row_ptr, K, kappa,
-                           yhat, bhat, eps, max_sweeps, y, r, nu, status);
-    else
-        hipLaunchKernelGGL(pair_qp_batch_kernel<3>, dim3(grid), dim3(256), 0, st, n_pairs, row_ptr, K, kappa,
-                           yhat, bhat, eps, max_sweeps, y, r, nu, status);
-    return hipGetLastError();
-}
-
-hipError_t launch_scale_batch(int n_pairs, int dim, const int* a_ptr, const float* A, const float* b,
-                              const int* o_ptr, const float* Cp, const float* dp, float* alpha, float* lam,
-                              float* mu, int* status, hipStream_t st)
-{
-    if (n_pairs <= 0) return hipSuccess;
-    const int grid = (n_pairs + 255) / 256;
-    if (dim == 2)
-        hipLaunchKernelGGL(scale_batch_kernel<2>, dim3(grid), dim3(256), 0, st, n_pairs, a_ptr, A, b, o_ptr, Cp,
-                           dp, alpha, lam, mu, status);
-    else
-        hipLaunchKernelGGL(scale_batch_kernel<3>, dim3(grid), dim3(256), 0, st, n_pairs, a_ptr, A, b, o_ptr, Cp,
-                           dp, alpha, lam, mu, status);
     return hipGetLastError();
 }
 

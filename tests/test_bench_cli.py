@@ -15,8 +15,11 @@ def test_bench_compiles():
 
 
 def test_bench_source_hash():
+    import json
     out = subprocess.run([sys.executable, BENCH, "--source-hash"], capture_output=True, text=True, check=True)
-    assert len(out.stdout.strip()) == 16
+    hashes = json.loads(out.stdout)
+    assert set(hashes) == {"pair_phase_kernel", "pair_qp_batch_kernel"}
+    assert all(len(v) == 16 for v in hashes.values())
 
 
 def test_bench_refuses_several_gpus():
