@@ -318,6 +318,23 @@ int pair_qp_batch(const cadmm_pair_batch* b, hipStream_t stream);
  * (a counter and one queue entry per pair). */
 int pair_qp_batch_workspace_size(int n_pairs, size_t* bytes);
 
+/* Largest batch of pair_qp_batch_noalloc. */
+#define CADMM_NOALLOC_MAX_PAIRS (1 << 19)
+
+/*
+ * pair_qp_batch (dual Newton solver, two-launch form) with the library's own
+ * device buffer in place of b->work, for callers that cannot allocate device
+ * memory (code under HIP-graph capture, tight serving loops): it calls no
+ * allocating routine. The buffer is a static device array of 24 MB, one per
+ * GPU, held until the process ends; its address is looked up on the first
+ * call on each device. Every call on a GPU shares that GPU's buffer, so calls
+ * that overlap on one GPU (other streams, other threads) race; calls on one
+ * stream do not. b->work, b->work_bytes and b->solver are ignored. Returns
+ * CADMM_INVALID for more than CADMM_NOALLOC_MAX_PAIRS pairs (and as
+ * pair_qp_batch), CADMM_DEVICE if the buffer's address cannot be found.
+ */
+int pair_qp_batch_noalloc(const cadmm_pair_batch* b, hipStream_t stream);
+
 /*
  * Stateless batch of scale LPs (Sec. III-A eq. scale_opt and its dual Sec.
  * III-B eq. scale_opt_dual) in the robot part's frame:

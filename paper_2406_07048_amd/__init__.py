@@ -98,6 +98,7 @@ _SIGNATURES = {
     "collision_admm_destroy": (None, [_vp]),
     "pair_qp_batch": (ctypes.c_int, [ctypes.POINTER(CadmmPairBatch), _vp]),
     "pair_qp_batch_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
+    "pair_qp_batch_noalloc": (ctypes.c_int, [ctypes.POINTER(CadmmPairBatch), _vp]),
     "pair_scale_batch": (ctypes.c_int, [ctypes.POINTER(CadmmScaleBatch), _vp]),
     "cadmm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "cadmm_last_error": (ctypes.c_char_p, []),
@@ -436,7 +437,7 @@ def collision_admm_cost(obs_d, x0, handle, n_iters, ckpt_every=10, y0=None):
 
 
 def pair_qp_batch(row_ptr, K, kappa, yhat, bhat, eps, max_sweeps=0, stream=None, solver=CADMM_PAIR_NEWTON,
-                  work=None):
+                  work=None, noalloc=False):
     """Stateless batch of proximal dual-update QPs (device tensors in, out).
 
     row_ptr int32 [P+1]; K float32 [rows, dim+1]; kappa, yhat [rows];
@@ -444,7 +445,8 @@ def pair_qp_batch(row_ptr, K, kappa, yhat, bhat, eps, max_sweeps=0, stream=None,
     solver: CADMM_PAIR_NEWTON (dual Newton) or CADMM_PAIR_LEMKE (the
     elimination / LCP / Lemke route). work: a device uint8 tensor for the
     dual Newton's two-launch form (pair_qp_batch_workspace_size bytes past a
-    256-byte aligned start)."""
+    256-byte aligned start); noalloc: the library's static buffer instead
+    (pair_qp_batch_noalloc)."""
     torch = _torch()
     n_pairs = row_ptr.numel() - 1
     dim = K.shape[1] - 1
@@ -459,7 +461,8 @@ def pair_qp_batch(row_ptr, K, kappa, yhat, bhat, eps, max_sweeps=0, stream=None,
     b = CadmmPairBatch(n_pairs, dim, _ptr(row_ptr), _ptr(K), _ptr(kappa), _ptr(yhat), _ptr(bhat),
                        float(eps), int(max_sweeps), _ptr(y), _ptr(r), _ptr(nu), _ptr(status), int(solver),
                        wptr, int(wbytes))
-    _check(lib().pair_qp_batch(ctypes.byref(b), _stream_ptr(stream)), "pair_qp_batch")
+    fn = lib().pair_qp_batch_noalloc if noalloc else lib().pair_qp_batch
+    _check(fn(ctypes.byref(b), _stream_ptr(stream)), "pair_qp_batch_noalloc" if noalloc else "pair_qp_batch")
     return y, r, nu, status
 
 

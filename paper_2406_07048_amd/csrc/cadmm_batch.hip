@@ -6,6 +6,7 @@
 #include "cadmm_solvers.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace cadmm {
 
@@ -430,6 +431,29 @@ size_t pair_qp_batch_work_bytes(int n_pairs)
     return 256 + (size_t)std::max(n_pairs, 0) * kEntryFloats * sizeof(float);
 }
 
+// The library's own buffer of the two-launch form, for callers that cannot
+// allocate: one copy per GPU (held until the process ends), found through
+// its symbol address once per device, with that device current.
+constexpr int kNoallocMaxPairs = 1 << 19;
+static __device__ __align__(256) unsigned char scratch[256 + (size_t)kNoallocMaxPairs * kEntryFloats * sizeof(float)];
+
+int noalloc_max_pairs() { return kNoallocMaxPairs; }
+
+void* noalloc_scratch()
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* ptr[kMaxDevices] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        ptr[dev] = p;
+    }
+    return ptr[dev];
+}
 
 hipError_t launch_scale_batch(int n_pairs, int dim, const int* a_ptr, const float* A, const float* b,
                               const int* o_ptr, const float* Cp, const float* dp, float* alpha, float* lam,

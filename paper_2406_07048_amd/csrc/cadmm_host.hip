@@ -1057,6 +1057,21 @@ int pair_qp_batch_workspace_size(int n_pairs, size_t* bytes)
     return CADMM_OK;
 }
 
+int pair_qp_batch_noalloc(const cadmm_pair_batch* b, hipStream_t stream)
+{
+    int rc = check_pair_batch(b);
+    if (rc != CADMM_OK || b->n_pairs == 0) return rc;
+    if (b->n_pairs > noalloc_max_pairs())
+        return fail(CADMM_INVALID, "n_pairs exceeds the static buffer of pair_qp_batch_noalloc (" +
+                                       std::to_string(noalloc_max_pairs()) + " pairs)");
+    void* work = noalloc_scratch();
+    if (!work) return fail(CADMM_DEVICE, "address of the static pair-batch buffer on this device");
+    HIP_TRY(launch_pair_qp_batch(b->n_pairs, b->dim, b->row_ptr, b->K, b->kappa, b->yhat, b->bhat, b->eps,
+                                 b->max_sweeps > 0 ? b->max_sweeps : 24, b->y, b->r, b->nu, b->status, stream,
+                                 work));
+    return CADMM_OK;
+}
+
 int pair_qp_batch(const cadmm_pair_batch* b, hipStream_t stream)
 {
     int rc = check_pair_batch(b);

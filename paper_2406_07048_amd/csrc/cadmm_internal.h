@@ -139,6 +139,10 @@ hipError_t launch_pair_qp_batch(int n_pairs, int dim, const int* row_ptr, const 
                                 float eps, int max_sweeps, float* y, float* r, float* nu, int* status,
                                 hipStream_t s, void* work = nullptr);
 size_t pair_qp_batch_work_bytes(int n_pairs);
+// The library's static buffer of the two-launch form on the current device
+// (nullptr if its address cannot be found) and the pairs it holds.
+void* noalloc_scratch();
+int noalloc_max_pairs();
 hipError_t launch_pair_qp_lemke(int n_pairs, int dim, const int* row_ptr, const float* K, const float* kappa,
                                 const float* yhat, const float* bhat, float eps, int max_pivots, float* y, float* r,
                                 float* nu, int* status, hipStream_t s);
