@@ -58,7 +58,7 @@ WORKLOADS = {
     "c3sqp": dict(desc="the C3 problem with the nonlinear quadrotor relinearised about every iterate, "
                        "up to 200 iterations", iters=200),
 }
-ALL_LEGS = ("c4", "plain", "c2", "c3", "c2tv", "c2sqp", "c3sqp", "stream", "grad", "cpu")
+ALL_LEGS = ("c4", "plain", "c2", "c3", "c2tv", "c2sqp", "c3sqp", "stream", "stream2", "lemke", "grad", "cpu")
 VALU_PEAK_INSTS = 256 * 2.4e9   # wave-wide VALU instructions per second: 256 CUs x 2.4 GHz x one per CU clock
 
 
@@ -280,33 +280,78 @@ def leg_single(cadmm, torch, name, args, steps=10):
                                   launch={"blocks_per_group": W, "workgroups": n_wg, "lanes_per_pair": G}))
 
 
-def leg_stream(cadmm, torch, n_pairs=1 << 22, reps=5):
-    """The stateless pair-QP entry point streamed over 2^22 pairs of the
-    batched 2D shape (about 1.4 GB, beyond the 256 MB Infinity Cache): the
-    size at which HBM, not latency, bounds the pair solve. HIP events on the
-    stream the kernel runs on (torch's current stream)."""
-    rp, K, kap, yh, bh = workloads.pair_batch_c4_shape(n_pairs)
-    args = [torch.from_numpy(a).to("cuda") for a in (rp, K, kap, yh, bh)]
-    y, r, nu, status = cadmm.pair_qp_batch(*args, 0.1)
+def stream_bytes(rp, n_pairs):
+    """Algorithmic bytes of one stateless batch: per row read K (dim + 1
+    floats), kappa and yhat, write y; per pair read row_ptr and bhat, write
+    r, nu and status (2D)."""
+    rows = int(rp[-1])
+    return 4.0 * rows * (3 + 1 + 1 + 1) + 4.0 * n_pairs * (1 + 3 + 3 + 1 + 1)
+
+
+def time_batch(cadmm, torch, args, reps, **kw):
+    """Mean ms of one pair_qp_batch call (HIP events on torch's current
+    stream, the stream the kernels run on) and its last outputs."""
+    out = cadmm.pair_qp_batch(*args, 0.1, **kw)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        cadmm.pair_qp_batch(*args, 0.1)
+        out = cadmm.pair_qp_batch(*args, 0.1, **kw)
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    rows = int(rp[-1])
-    # per row: read K (3), kappa, yhat, write y; per pair: read row_ptr, bhat (3), write r (3), nu, status
-    bytes_launch = 4.0 * rows * (3 + 1 + 1 + 1) + 4.0 * n_pairs * (1 + 3 + 3 + 1 + 1)
+    return e0.elapsed_time(e1) / reps, out
+
+
+_STREAM_INPUTS = {}   # the streamed batch, generated once for both forms
+
+
+def leg_stream(cadmm, torch, n_pairs=1 << 22, reps=5, two_launch=False):
+    """The stateless pair-QP entry point streamed over 2^22 pairs of the
+    batched 2D shape (about 1.4 GB, beyond the 256 MB Infinity Cache): the
+    size at which HBM, not latency, bounds the pair solve. two_launch: the
+    form with a workspace, whose second launch resumes the pairs still
+    running after three sweeps."""
+    key = ("stream", n_pairs)
+    if key not in _STREAM_INPUTS:
+        rp, K, kap, yh, bh = workloads.pair_batch_c4_shape(n_pairs)
+        _STREAM_INPUTS[key] = (rp, [torch.from_numpy(a).to("cuda") for a in (rp, K, kap, yh, bh)])
+    rp, args = _STREAM_INPUTS[key]
+    kw = {}
+    if two_launch:
+        kw["work"] = torch.empty(cadmm.pair_qp_batch_workspace_size(n_pairs) + 256, dtype=torch.uint8,
+                                 device="cuda")
+    ms, (y, r, nu, status) = time_batch(cadmm, torch, args, reps, **kw)
+    bytes_launch = stream_bytes(rp, n_pairs)
     st = status.cpu().numpy()
-    return dict(workload=f"{n_pairs} stateless pair QPs of the batched 2D shape ({rows} rows, 5-16 per pair)",
-                ms_per_launch=ms, pair_solves_per_s=n_pairs / (ms * 1e-3),
-                sweeps_mean=float(st[st >= 0].mean()), budget_hits=int((st < 0).sum()),
-                roofline=roofline(bytes_launch, ms, measured_traffic("pair_qp_batch_stream", kernel="pair_qp_batch_kernel"),
-                                  "pair_qp_batch_kernel",
-                                  valu=valu_rate(measured_valu("pair_qp_batch_stream", kernel="pair_qp_batch_kernel"),
-                                                 ms)))
+    name = "pair_qp_batch_stream2" if two_launch else "pair_qp_batch_stream"
+    out = dict(workload=f"{n_pairs} stateless pair QPs of the batched 2D shape ({int(rp[-1])} rows, 5-16 per pair)"
+                        + (", two-launch form" if two_launch else ", one launch"),
+               ms_per_launch=ms, pair_solves_per_s=n_pairs / (ms * 1e-3),
+               sweeps_mean=float(st[st >= 0].mean()), budget_hits=int((st < 0).sum()))
+    if two_launch:
+        out["queued_after_3_sweeps"] = int((st > 3).sum())
+        out["gb_per_s"] = bytes_launch / (ms * 1e-3) / 1e9
+    else:
+        out["roofline"] = roofline(bytes_launch, ms, measured_traffic(name, kernel="pair_qp_batch_kernel"),
+                                   "pair_qp_batch_kernel",
+                                   valu=valu_rate(measured_valu(name, kernel="pair_qp_batch_kernel"), ms))
+    return out
+
+
+def leg_lemke(cadmm, torch, n_pairs=1 << 18, reps=3):
+    """A/B of the two pair solvers on the same stateless batch (2^18 pairs of
+    the batched 2D shape): the dual Newton method against the Sec. IV-C route
+    (elimination, LCP, Lemke pivoting), and the largest difference of their
+    duals scaled by the pair's row norms."""
+    rp, K, kap, yh, bh = workloads.pair_batch_c4_shape(n_pairs, seed=5)
+    args = [torch.from_numpy(a).to("cuda") for a in (rp, K, kap, yh, bh)]
+    ms_n, (yn, _, _, st_n) = time_batch(cadmm, torch, args, reps)
+    ms_l, (yl, _, _, st_l) = time_batch(cadmm, torch, args, reps, solver=cadmm.CADMM_PAIR_LEMKE)
+    stl = st_l.cpu().numpy()
+    return dict(workload=f"{n_pairs} stateless pair QPs of the batched 2D shape", ms_newton=ms_n, ms_lemke=ms_l,
+                lemke_over_newton=ms_l / ms_n, lemke_pivots_mean=float(stl[stl >= 0].mean()),
+                lemke_failures=int((stl < 0).sum()), newton_failures=int((st_n < 0).sum().item()),
+                max_abs_dual_difference=float((yn - yl).abs().max().item()))
 
 
 def leg_grad(cadmm, torch, steps=3, iters=100, every=10):
@@ -453,6 +498,12 @@ def main():
     if "stream" in legs:
         say("stream: stateless pair QPs (2^22)")
         out["stream"] = leg_stream(cadmm, torch)
+    if "stream2" in legs:
+        say("stream2: stateless pair QPs (2^22), two-launch form")
+        out["stream2"] = leg_stream(cadmm, torch, two_launch=True)
+    if "lemke" in legs:
+        say("lemke: Newton vs Lemke pair solvers (2^18)")
+        out["lemke"] = leg_lemke(cadmm, torch)
     if "grad" in legs:
         say("grad: reverse pass (3D, 100 unrolled iterations)")
         out["differentiation"] = leg_grad(cadmm, torch)
