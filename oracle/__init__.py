@@ -59,6 +59,7 @@ class _Problem(ctypes.Structure):
         ("eps_pri", ctypes.c_double), ("eps_dual", ctypes.c_double),
         ("dyn_ts", ctypes.c_int), ("dyn_ss", ctypes.c_int), ("model", ctypes.c_int),
         ("model_par", ctypes.c_double * 8),
+        ("s_lo", _dp), ("s_hi", _dp), ("u_lo", _dp), ("u_hi", _dp),
     ]
 
 
@@ -75,6 +76,9 @@ def _declare(L):
     L.orc_traj_qp.restype = ctypes.c_int
     L.orc_traj_qp.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, _dp,
                               _dp, _dp, _dp, _dp, _dp]
+    L.orc_traj_qp_bounded.restype = ctypes.c_int
+    L.orc_traj_qp_bounded.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, _dp,
+                                      _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _ip]
     PP = ctypes.POINTER(_Problem)
     L.orc_y_size.restype = ctypes.c_long
     L.orc_y_size.argtypes = [PP]
@@ -189,6 +193,25 @@ def traj_qp(A, B, c, x0, H, h, Q_u):
     return x, u
 
 
+def traj_qp_bounded(A, B, c, x0, H, h, Q_u, s_lo=None, s_hi=None, u_lo=None, u_hi=None):
+    """traj_qp with the bounds s_lo <= x_t <= s_hi (t = 1..N) and
+    u_lo <= u_t <= u_hi (t = 0..N-1); None or infinite entries: no bound.
+    Returns (x, u, n_active)."""
+    A, B, c, x0, H, h, Q_u = map(_f64, (A, B, c, x0, H, h, Q_u))
+    n_s, n_u = B.shape[-2:]
+    N = H.shape[0]
+    ts = 1 if A.ndim == 3 else 0
+    lims = [None if v is None else _f64(v) for v in (s_lo, s_hi, u_lo, u_hi)]
+    x = np.zeros((N + 1, n_s))
+    u = np.zeros((N, n_u))
+    na = ctypes.c_int()
+    st = lib().orc_traj_qp_bounded(n_s, n_u, N, _d(A), _d(B), _d(c), ts, _d(x0), _d(H), _d(h), _d(Q_u),
+                                   *[None if v is None else _d(v) for v in lims], _d(x), _d(u), ctypes.byref(na))
+    if st:
+        raise RuntimeError(f"oracle bounded trajectory QP failed (status {st})")
+    return x, u, na.value
+
+
 # ---------------------------------------------------------------- full problem
 class Problem:
     """Holds contiguous copies of a workloads problem dict and its C mirror."""
@@ -224,6 +247,10 @@ class Problem:
         st.model = int(prob.get("model", 0))
         for i, v in enumerate(prob.get("model_par", ())):
             st.model_par[i] = float(v)
+        for key, field in (("s_min", "s_lo"), ("s_max", "s_hi"), ("u_min", "u_lo"), ("u_max", "u_hi")):
+            if prob.get(key) is not None:
+                k[key] = _f64(prob[key])
+                setattr(st, field, _d(k[key]))
         self.st = st
         self.ref = ctypes.byref(st)
         self.n_scen = st.n_scen

@@ -71,8 +71,9 @@ static int gauss_solve(int n, double *M, double *r)
     return 0;
 }
 
-/* Cholesky solve of an SPD system (M destroyed). Returns 1 if not SPD. */
-static int chol_solve(int n, double *M, double *r)
+/* Cholesky factor L (lower triangle, in place) of an SPD matrix. Returns 1
+   if not SPD. */
+static int chol_factor(int n, double *M)
 {
     for (int j = 0; j < n; ++j) {
         double s = M[j * n + j];
@@ -86,6 +87,12 @@ static int chol_solve(int n, double *M, double *r)
             M[i * n + j] = t / L;
         }
     }
+    return 0;
+}
+
+/* Solve L L^T z = r in place with the factor of chol_factor. */
+static void chol_apply(int n, const double *M, double *r)
+{
     for (int i = 0; i < n; ++i) {
         double s = r[i];
         for (int k = 0; k < i; ++k) s -= M[i * n + k] * r[k];
@@ -96,6 +103,13 @@ static int chol_solve(int n, double *M, double *r)
         for (int k = i + 1; k < n; ++k) s -= M[k * n + i] * r[k];
         r[i] = s / M[i * n + i];
     }
+}
+
+/* Cholesky solve of an SPD system (M destroyed). Returns 1 if not SPD. */
+static int chol_solve(int n, double *M, double *r)
+{
+    if (chol_factor(n, M)) return 1;
+    chol_apply(n, M, r);
     return 0;
 }
 
@@ -579,6 +593,10 @@ typedef struct {
     int dyn_ts, dyn_ss;
     int model;                      /* 0: the given linear model, 1: kinematic bicycle, 2: quadrotor */
     double model_par[8];
+    /* state and input bounds (Sec. IV-A eq. MPC_opt_origin, its state and
+       control rows) on x_t, t = 1..N, and u_t, t = 0..N-1: s_lo, s_hi [n_s],
+       u_lo, u_hi [n_u]; NULL or infinite entries: no bound */
+    const double *s_lo, *s_hi, *u_lo, *u_hi;
 } orc_problem;
 
 static const double *dyn_A(const orc_problem *P, int s) { return P->A_dyn + (size_t)s * P->dyn_ss * P->n_s * P->n_s; }
@@ -713,15 +731,15 @@ static const double *state_at(const orc_problem *P, const double *x, int s, int 
  * response z_t = A_{t-1} z_{t-1} + c_{t-1}, then a dense Cholesky solve in the
  * stacked inputs.  H: N blocks (t = 1..N) of n_s x n_s.
  */
-int orc_traj_qp(int n_s, int n_u, int N, const double *A0, const double *B0, const double *c0, int ts,
-                const double *x0, const double *H, const double *h, const double *Q_u,
-                double *x, double *u)
+
+/* The condensed form: free response z (t = 0..N), the maps M_t = dx_t/du
+ * (t = 1..N, n_s x nU each, nU = N n_u), and the input Hessian Hs and the
+ * gradient gr at u = 0 of 1/2 u^T Hs u + gr^T u. */
+static void condense(int n_s, int n_u, int N, const double *A0, const double *B0, const double *c0, int ts,
+                     const double *x0, const double *H, const double *h, const double *Q_u,
+                     double *Mt, double *z, double *Hs, double *gr)
 {
     int nU = N * n_u;
-    double *Mt = (double *)calloc((size_t)N * n_s * nU, sizeof(double));   /* dx_t/du, t=1..N */
-    double *z = (double *)calloc((size_t)(N + 1) * n_s, sizeof(double));
-    double *Hs = (double *)calloc((size_t)nU * nU, sizeof(double));
-    double *gr = (double *)calloc(nU, sizeof(double));
     double *HM = (double *)calloc((size_t)n_s * nU, sizeof(double));
     memcpy(z, x0, sizeof(double) * n_s);
     for (int t = 1; t <= N; ++t) {
@@ -770,23 +788,232 @@ int orc_traj_qp(int n_s, int n_u, int N, const double *A0, const double *B0, con
             gr[a] += acc;
         }
     }
+    free(HM);
+}
+
+/* x_{t+1} = A_t x_t + B_t u_t + c_t for t = 0..N-1 from the x_0 in x. */
+static void rollout(int n_s, int n_u, int N, const double *A0, const double *B0, const double *c0, int ts,
+                    const double *u, double *x)
+{
+    for (int t = 0; t < N; ++t) {
+        const double *A = A0 + (size_t)t * ts * n_s * n_s, *B = B0 + (size_t)t * ts * n_s * n_u;
+        const double *c = c0 + (size_t)t * ts * n_s;
+        for (int r = 0; r < n_s; ++r) {
+            double acc = c[r];
+            for (int q = 0; q < n_s; ++q) acc += A[r * n_s + q] * x[t * n_s + q];
+            for (int k = 0; k < n_u; ++k) acc += B[r * n_u + k] * u[t * n_u + k];
+            x[(t + 1) * n_s + r] = acc;
+        }
+    }
+}
+
+int orc_traj_qp(int n_s, int n_u, int N, const double *A0, const double *B0, const double *c0, int ts,
+                const double *x0, const double *H, const double *h, const double *Q_u,
+                double *x, double *u)
+{
+    int nU = N * n_u;
+    double *Mt = (double *)calloc((size_t)N * n_s * nU, sizeof(double));   /* dx_t/du, t=1..N */
+    double *z = (double *)calloc((size_t)(N + 1) * n_s, sizeof(double));
+    double *Hs = (double *)calloc((size_t)nU * nU, sizeof(double));
+    double *gr = (double *)calloc(nU, sizeof(double));
+    condense(n_s, n_u, N, A0, B0, c0, ts, x0, H, h, Q_u, Mt, z, Hs, gr);
     for (int a = 0; a < nU; ++a) gr[a] = -gr[a];
     int st = chol_solve(nU, Hs, gr);
     if (!st) {
         memcpy(u, gr, sizeof(double) * nU);
         memcpy(x, x0, sizeof(double) * n_s);
-        for (int t = 0; t < N; ++t) {
-            const double *A = A0 + (size_t)t * ts * n_s * n_s, *B = B0 + (size_t)t * ts * n_s * n_u;
-            const double *c = c0 + (size_t)t * ts * n_s;
-            for (int r = 0; r < n_s; ++r) {
-                double acc = c[r];
-                for (int q = 0; q < n_s; ++q) acc += A[r * n_s + q] * x[t * n_s + q];
-                for (int k = 0; k < n_u; ++k) acc += B[r * n_u + k] * u[t * n_u + k];
-                x[(t + 1) * n_s + r] = acc;
-            }
+        rollout(n_s, n_u, N, A0, B0, c0, ts, u, x);
+    }
+    free(Mt); free(z); free(Hs); free(gr);
+    return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* trajectory QP with state and input bounds (Sec. IV-A eq.            */
+/* MPC_opt_origin, state and control rows; the indicator IC_0 of eq.   */
+/* ADMM_Lagrangian in full)                                            */
+/* ------------------------------------------------------------------ */
+
+/* Bound c of the condensed QP as n_c^T u >= b_c over the stacked inputs u
+ * (length nU = N n_u). Bounds are numbered: input lower (t, k) at
+ * 2 (t n_u + k), input upper at 2 (t n_u + k) + 1, then state lower (t, r),
+ * t = 1..N, at 2 nU + 2 ((t-1) n_s + r), state upper one after it. The state
+ * rows come from x_t = z_t + M_t u (z the free response, M_t = dx_t/du). */
+typedef struct {
+    int n_s, n_u, N, nU;
+    const double *Mt, *z;                  /* as in orc_traj_qp */
+    const double *xlo, *xhi, *ulo, *uhi;   /* NULL: no bound of that kind */
+} bqp;
+
+static int bqp_count(const bqp *Q) { return 2 * Q->nU + 2 * Q->N * Q->n_s; }
+
+/* Normal (dense, nU) and right-hand side of bound c; returns 0 if the bound
+ * is absent (infinite). */
+static int bqp_row(const bqp *Q, int c, double *n, double *b)
+{
+    int up = c & 1, v = c >> 1;
+    memset(n, 0, sizeof(double) * Q->nU);
+    if (v < Q->nU) {
+        int k = v % Q->n_u;
+        const double *lim = up ? Q->uhi : Q->ulo;
+        if (!lim || !isfinite(lim[k])) return 0;
+        n[v] = up ? -1.0 : 1.0;
+        *b = up ? -lim[k] : lim[k];
+        return 1;
+    }
+    v -= Q->nU;
+    int t = v / Q->n_s + 1, r = v % Q->n_s;
+    const double *lim = up ? Q->xhi : Q->xlo;
+    if (!lim || !isfinite(lim[r])) return 0;
+    const double *row = Q->Mt + ((size_t)(t - 1) * Q->n_s + r) * Q->nU;
+    for (int a = 0; a < Q->nU; ++a) n[a] = up ? -row[a] : row[a];
+    double zt = Q->z[t * Q->n_s + r];
+    *b = up ? zt - lim[r] : lim[r] - zt;
+    return 1;
+}
+
+/*
+ * min sum_{t=1..N} (1/2 x_t^T H_t x_t + h_t^T x_t) + sum_{t=0..N-1} u_t^T Q_u u_t
+ * s.t. x_{t+1} = A_t x_t + B_t u_t + c_t, x_0 given,
+ *      xlo <= x_t <= xhi (t = 1..N), ulo <= u_t <= uhi (t = 0..N-1),
+ * any bound array NULL or any entry infinite meaning no bound. Condensed as
+ * orc_traj_qp, then the dual active-set method of Goldfarb and Idnani (Math.
+ * Programming 27, 1983) on the strictly convex QP 1/2 u^T G u + g^T u in the
+ * stacked inputs, with G^{-1} formed explicitly: from the unconstrained
+ * minimiser, repeatedly take the most violated bound p and move the primal
+ * point along the direction that keeps the active bounds satisfied while
+ * p's multiplier grows; a bound whose multiplier reaches zero first is
+ * dropped (partial step), else p joins the active set (full step). Every step
+ * raises the dual objective, so no active set repeats.
+ * Returns 0, 1 (G not positive definite), 2 (bounds infeasible), 3 (step cap).
+ * n_active (may be NULL) receives the bounds active at the solution.
+ */
+int orc_traj_qp_bounded(int n_s, int n_u, int N, const double *A0, const double *B0, const double *c0, int ts,
+                        const double *x0, const double *H, const double *h, const double *Q_u,
+                        const double *xlo, const double *xhi, const double *ulo, const double *uhi,
+                        double *x, double *u, int *n_active)
+{
+    int nU = N * n_u;
+    double *Mt = (double *)calloc((size_t)N * n_s * nU, sizeof(double));
+    double *z = (double *)calloc((size_t)(N + 1) * n_s, sizeof(double));
+    double *G = (double *)calloc((size_t)nU * nU, sizeof(double));
+    double *g = (double *)calloc(nU, sizeof(double));
+    condense(n_s, n_u, N, A0, B0, c0, ts, x0, H, h, Q_u, Mt, z, G, g);
+    bqp Q = {n_s, n_u, N, nU, Mt, z, xlo, xhi, ulo, uhi};
+    int nC = bqp_count(&Q), st = 0, nA = 0;
+    double *Gi = (double *)calloc((size_t)nU * nU, sizeof(double));
+    double *L = (double *)malloc(sizeof(double) * nU * nU);
+    /* G^{-1} column by column from one Cholesky factor */
+    memcpy(L, G, sizeof(double) * nU * nU);
+    if (chol_factor(nU, L)) st = 1;
+    for (int col = 0; col < nU && !st; ++col) {
+        double *e = Gi + (size_t)col * nU;     /* G symmetric: column = row */
+        e[col] = 1.0;
+        chol_apply(nU, L, e);
+    }
+    int *act = (int *)malloc(sizeof(int) * (nU + 1));
+    double *lam = (double *)malloc(sizeof(double) * (nU + 1));
+    double *NA = (double *)malloc(sizeof(double) * (size_t)(nU + 1) * nU);    /* active normals */
+    double *WA = (double *)malloc(sizeof(double) * (size_t)(nU + 1) * nU);    /* G^{-1} n_i */
+    double *np_ = (double *)malloc(sizeof(double) * nU), *wp = (double *)malloc(sizeof(double) * nU);
+    double *d = (double *)malloc(sizeof(double) * nU);
+    double *M = (double *)malloc(sizeof(double) * (nU + 1) * (nU + 1));
+    double *r = (double *)malloc(sizeof(double) * (nU + 1));
+    unsigned char *in = (unsigned char *)calloc(nC, 1);
+    double *nrow = (double *)malloc(sizeof(double) * nU);
+    if (!st) {
+        for (int a = 0; a < nU; ++a) {
+            double acc = 0.0;
+            for (int b2 = 0; b2 < nU; ++b2) acc -= Gi[(size_t)a * nU + b2] * g[b2];
+            u[a] = acc;
         }
     }
-    free(Mt); free(z); free(Hs); free(gr); free(HM);
+    int steps = 0, cap = 20 * (nC + nU) + 100;
+    while (!st) {
+        /* the most violated bound not in the active set (scaled by its normal) */
+        int p = -1;
+        double worst = 0.0, bp = 0.0;
+        for (int c = 0; c < nC; ++c) {
+            double b;
+            if (in[c] || !bqp_row(&Q, c, nrow, &b)) continue;
+            double s = -b, nn = 0.0;
+            for (int a = 0; a < nU; ++a) { s += nrow[a] * u[a]; nn += nrow[a] * nrow[a]; }
+            double tol = 1e-11 * (1.0 + fabs(b));
+            if (s < -tol && s / sqrt(nn) < worst) { worst = s / sqrt(nn); p = c; bp = b; }
+        }
+        if (p < 0) break;
+        bqp_row(&Q, p, np_, &bp);
+        double lp = 0.0;
+        for (;;) {
+            if (++steps > cap) { st = 3; break; }
+            for (int a = 0; a < nU; ++a) {
+                double acc = 0.0;
+                for (int b2 = 0; b2 < nU; ++b2) acc += Gi[(size_t)a * nU + b2] * np_[b2];
+                wp[a] = acc;
+            }
+            /* r = (N_A^T G^{-1} N_A)^{-1} N_A^T G^{-1} n_p */
+            for (int i = 0; i < nA; ++i) {
+                double acc = 0.0;
+                for (int a = 0; a < nU; ++a) acc += NA[(size_t)i * nU + a] * wp[a];
+                r[i] = acc;
+                for (int j = 0; j < nA; ++j) {
+                    double m = 0.0;
+                    for (int a = 0; a < nU; ++a) m += NA[(size_t)i * nU + a] * WA[(size_t)j * nU + a];
+                    M[i * nA + j] = m;
+                }
+            }
+            if (nA && gauss_solve(nA, M, r)) { st = 2; break; }
+            double dn = 0.0, pp = 0.0;
+            for (int a = 0; a < nU; ++a) {
+                double acc = wp[a];
+                for (int i = 0; i < nA; ++i) acc -= r[i] * WA[(size_t)i * nU + a];
+                d[a] = acc;
+                dn += np_[a] * acc;
+                pp += np_[a] * wp[a];
+            }
+            /* partial step: the first active multiplier to reach zero */
+            int k = -1;
+            double t2 = INFINITY;
+            for (int i = 0; i < nA; ++i)
+                if (r[i] > 0.0 && lam[i] / r[i] < t2) { t2 = lam[i] / r[i]; k = i; }
+            double s = -bp;
+            for (int a = 0; a < nU; ++a) s += np_[a] * u[a];
+            int dependent = dn <= 1e-12 * pp;
+            if (dependent && k < 0) { st = 2; break; }
+            double t1 = dependent ? INFINITY : -s / dn;
+            double t = t1 < t2 ? t1 : t2;
+            if (!dependent)
+                for (int a = 0; a < nU; ++a) u[a] += t * d[a];
+            for (int i = 0; i < nA; ++i) lam[i] -= t * r[i];
+            lp += t;
+            if (t1 <= t2) {
+                /* full step: p joins the active set */
+                memcpy(NA + (size_t)nA * nU, np_, sizeof(double) * nU);
+                memcpy(WA + (size_t)nA * nU, wp, sizeof(double) * nU);
+                act[nA] = p;
+                lam[nA] = lp;
+                in[p] = 1;
+                ++nA;
+                break;
+            }
+            /* partial step: drop bound k and try p again */
+            in[act[k]] = 0;
+            for (int i = k; i + 1 < nA; ++i) {
+                act[i] = act[i + 1];
+                lam[i] = lam[i + 1];
+                memcpy(NA + (size_t)i * nU, NA + (size_t)(i + 1) * nU, sizeof(double) * nU);
+                memcpy(WA + (size_t)i * nU, WA + (size_t)(i + 1) * nU, sizeof(double) * nU);
+            }
+            --nA;
+        }
+    }
+    if (st != 1) {
+        memcpy(x, x0, sizeof(double) * n_s);
+        rollout(n_s, n_u, N, A0, B0, c0, ts, u, x);
+    }
+    if (n_active) *n_active = nA;
+    free(Mt); free(z); free(G); free(g); free(Gi); free(L); free(act); free(lam); free(NA); free(WA);
+    free(np_); free(wp); free(d); free(M); free(r); free(in); free(nrow);
     return st;
 }
 
@@ -832,6 +1059,28 @@ static int lq_stage_base(const orc_problem *P, int s, double *H, double *h)
     return 0;
 }
 
+static int any_finite(const double *v, int n)
+{
+    if (!v) return 0;
+    for (int i = 0; i < n; ++i)
+        if (isfinite(v[i])) return 1;
+    return 0;
+}
+
+/* The trajectory QP of scenario s for the models (A, B, c, ts), with the
+   problem's state and input bounds when it has any (the indicator IC_0 of
+   Sec. IV-B eq. ADMM_Lagrangian covers them). Nonzero on failure. */
+static int traj_solve(const orc_problem *P, int s, const double *A, const double *B, const double *c, int ts,
+                      const double *H, const double *h, double *x, double *u)
+{
+    const double *x0 = P->x0 + (size_t)s * P->n_s;
+    if (any_finite(P->s_lo, P->n_s) || any_finite(P->s_hi, P->n_s) || any_finite(P->u_lo, P->n_u) ||
+        any_finite(P->u_hi, P->n_u))
+        return orc_traj_qp_bounded(P->n_s, P->n_u, P->N, A, B, c, ts, x0, H, h, P->Q_u, P->s_lo, P->s_hi,
+                                   P->u_lo, P->u_hi, x, u, NULL) != 0;
+    return orc_traj_qp(P->n_s, P->n_u, P->N, A, B, c, ts, x0, H, h, P->Q_u, x, u);
+}
+
 /* Initial iterate: s^0 = obstacle-free LQ, zeta = xi = 0,
    y^0 = (lam*, mu*, max(alpha* - 1, 0)) from the scale LP at s^0. */
 int orc_admm_init(const orc_problem *P, double *x, double *u, double *y, double *zeta, double *xi)
@@ -842,8 +1091,8 @@ int orc_admm_init(const orc_problem *P, double *x, double *u, double *y, double 
     int bad = 0;
     for (int s = 0; s < P->n_scen; ++s) {
         lq_stage_base(P, s, H, h);
-        bad |= orc_traj_qp(n_s, P->n_u, N, dyn_A(P, s), dyn_B(P, s), dyn_c(P, s), P->dyn_ts, P->x0 + (size_t)s * n_s,
-                           H, h, P->Q_u, x + (size_t)s * (N + 1) * n_s, u + (size_t)s * N * P->n_u);
+        bad |= traj_solve(P, s, dyn_A(P, s), dyn_B(P, s), dyn_c(P, s), P->dyn_ts, H, h,
+                          x + (size_t)s * (N + 1) * n_s, u + (size_t)s * N * P->n_u);
     }
     free(H); free(h);
     int nb = count_blocks(P);
@@ -1119,12 +1368,11 @@ int orc_traj_phase(const orc_problem *P, const double *x_in, const double *y,
             double *Bl = (double *)malloc(sizeof(double) * N * n_s * P->n_u);
             double *cl = (double *)malloc(sizeof(double) * N * n_s);
             sqp_models(P, s, x_in, u_out, Al, Bl, cl);
-            bad |= orc_traj_qp(n_s, P->n_u, N, Al, Bl, cl, 1, P->x0 + (size_t)s * n_s,
-                               H, h, P->Q_u, x_out + (size_t)s * (N + 1) * n_s, uo);
+            bad |= traj_solve(P, s, Al, Bl, cl, 1, H, h, x_out + (size_t)s * (N + 1) * n_s, uo);
             free(Al); free(Bl); free(cl);
         } else {
-            bad |= orc_traj_qp(n_s, P->n_u, N, dyn_A(P, s), dyn_B(P, s), dyn_c(P, s), P->dyn_ts,
-                               P->x0 + (size_t)s * n_s, H, h, P->Q_u, x_out + (size_t)s * (N + 1) * n_s, uo);
+            bad |= traj_solve(P, s, dyn_A(P, s), dyn_B(P, s), dyn_c(P, s), P->dyn_ts, H, h,
+                              x_out + (size_t)s * (N + 1) * n_s, uo);
         }
         free(H); free(h);
     }

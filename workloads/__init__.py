@@ -321,6 +321,19 @@ def config_c2sqp(seed=10):
     return p
 
 
+def config_c2b(seed=10, v_range=(19.9, 20.3), a_range=(-3.0, 1.0), steer=0.07):
+    """C2 with state and input bounds: speed in v_range, acceleration in
+    a_range, steering within +-steer (the other states free). The bounds cut
+    what the unbounded C2 solve reaches (speed 19.95-21.7 m/s, acceleration
+    up to 2 m/s^2, steering up to 0.11 rad), so some stay active at the
+    solution."""
+    p = config_c2(seed)
+    inf = np.inf
+    p.update(s_min=np.array([-inf, -inf, -inf, v_range[0]]), s_max=np.array([inf, inf, inf, v_range[1]]),
+             u_min=np.array([a_range[0], -steer]), u_max=np.array([a_range[1], steer]))
+    return p
+
+
 def config_c3sqp(seed=25):
     """C3 with the nonlinear quadrotor relinearised about every iterate."""
     p = config_c3(seed)
@@ -544,6 +557,7 @@ CONFIGS = {
     "c4": config_c4,
     "c2tv": config_c2tv,
     "c2sqp": config_c2sqp,
+    "c2b": config_c2b,
     "c3sqp": config_c3sqp,
 }
 
