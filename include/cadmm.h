@@ -77,6 +77,7 @@ enum { CADMM_MODEL_LINEAR = 0, CADMM_MODEL_BICYCLE = 1, CADMM_MODEL_QUADROTOR = 
 #define CADMM_MAX_NU 8           /* input size */
 #define CADMM_MAX_PART_FACES 8   /* faces of one robot part */
 #define CADMM_MAX_OBS_FACES 32   /* faces of one obstacle */
+#define CADMM_MAX_ACTIVE_BOUNDS 64   /* bounds active at once in one scenario's trajectory QP */
 
 /*
  * Problem descriptor. Host pointers, read only during collision_admm_setup.
@@ -113,6 +114,17 @@ enum { CADMM_MODEL_LINEAR = 0, CADMM_MODEL_BICYCLE = 1, CADMM_MODEL_QUADROTOR = 
  *                 (obstacle-free) trajectory. The reverse pass (admm_record,
  *                 admm_backward) needs CADMM_MODEL_LINEAR.
  *  model_par[8]   parameters of the nonlinear model (unused for CADMM_MODEL_LINEAR)
+ *  s_min[n_s], s_max[n_s], u_min[n_u], u_max[n_u]
+ *                 state and input bounds of Sec. IV-A eq. MPC_opt_origin (its state
+ *                 and control rows), s_min <= x_t <= s_max for t = 1..N and
+ *                 u_min <= u_t <= u_max for t = 0..N-1, in every scenario; each
+ *                 array may be NULL and each entry +-INFINITY (no bound); min <= max
+ *                 required. With any finite bound the trajectory QP of every
+ *                 iteration (and the initial obstacle-free trajectory) is the
+ *                 bounded QP, solved to the bounded minimiser (the indicator IC_0 of
+ *                 Sec. IV-B eq. ADMM_Lagrangian); needs n_s <= 12, n_u <= 4, at most
+ *                 CADMM_MAX_ACTIVE_BOUNDS bounds active at once per scenario
+ *                 (cadmm_result.active_bounds reports -2 beyond), and no reverse pass.
  */
 typedef struct cadmm_desc {
     int dim, n_s, n_u, N;
@@ -143,6 +155,10 @@ typedef struct cadmm_desc {
     int dyn_t_stride, dyn_s_stride;
     int model;
     double model_par[8];
+    const double* s_min;
+    const double* s_max;
+    const double* u_min;
+    const double* u_max;
 } cadmm_desc;
 
 typedef struct cadmm_handle cadmm_handle;
@@ -155,6 +171,10 @@ typedef struct cadmm_result {
     float cost;                /* tracking cost F of the final trajectory */
     float min_alpha;           /* min scale alpha* over the scenario's pairs at the final trajectory */
     int unconverged_pairs;     /* pair QPs that hit the sweep budget in the last iteration */
+    int active_bounds;         /* bounds active in the last trajectory QP (0 without bounds);
+                                  -1: no point met the bounds (the iterate then breaks some),
+                                  -2: more than CADMM_MAX_ACTIVE_BOUNDS were needed,
+                                  -3: the active-set step cap was reached */
 } cadmm_result;
 
 /* Size info of a descriptor: bytes of device workspace, number of pair
@@ -253,7 +273,8 @@ int admm_set_params(cadmm_handle* h, const double* obs_d, const double* x0);
  *   step. Writes dL_scale * dL/dd to grad_d[F_o] and dL_scale * dL/dx0 to
  *   grad_x0[n_scen*n_s] (DEVICE FP32, overwritten). Leaves the handle at
  *   iterate K. No host sync. CADMM_INVALID if nothing was recorded in d_gws.
- * All three return CADMM_INVALID for a nonlinear model (desc.model != 0).
+ * All three return CADMM_INVALID for a nonlinear model (desc.model != 0) or
+ * with state or input bounds.
  */
 int admm_grad_workspace_size(cadmm_handle* h, int n_iters, int ckpt_every, size_t* bytes);
 int admm_record(cadmm_handle* h, int n_iters, int ckpt_every, void* d_gws, size_t bytes, float* cost_out);

@@ -40,6 +40,7 @@ class CadmmDesc(ctypes.Structure):
         ("max_sweeps", ctypes.c_int), ("waves_per_group", ctypes.c_int), ("lanes_per_pair", ctypes.c_int),
         ("dyn_t_stride", ctypes.c_int), ("dyn_s_stride", ctypes.c_int), ("model", ctypes.c_int),
         ("model_par", ctypes.c_double * 8),
+        ("s_min", _dp), ("s_max", _dp), ("u_min", _dp), ("u_max", _dp),
     ]
 
 
@@ -52,6 +53,7 @@ class CadmmResult(ctypes.Structure):
         ("r_pri", ctypes.c_float), ("r_dual", ctypes.c_float),
         ("cost", ctypes.c_float), ("min_alpha", ctypes.c_float),
         ("unconverged_pairs", ctypes.c_int),
+        ("active_bounds", ctypes.c_int),
     ]
 
 
@@ -193,6 +195,11 @@ class _DescHolder:
         d.model = int(prob.get("model", CADMM_MODEL_LINEAR))
         for i, v in enumerate(prob.get("model_par", ())):
             d.model_par[i] = float(v)
+        for name, n in (("s_min", d.n_s), ("s_max", d.n_s), ("u_min", d.n_u), ("u_max", d.n_u)):
+            if prob.get(name) is not None:
+                if np.asarray(prob[name]).size != n:
+                    raise ValueError(f"{name} must hold {n} values")
+                setattr(d, name, dbl(name))
         self.desc = d
         self.keep = keep
 
@@ -248,7 +255,8 @@ class Handle:
         code = lib().admm_solve(self._h, int(max_iters), int(check_every), res)
         _check(code, "admm_solve", allow=(CADMM_OK, CADMM_NOT_CONVERGED))
         return code, [dict(iters=r.iters, converged=bool(r.converged), r_pri=r.r_pri, r_dual=r.r_dual,
-                           cost=r.cost, min_alpha=r.min_alpha, unconverged_pairs=r.unconverged_pairs)
+                           cost=r.cost, min_alpha=r.min_alpha, unconverged_pairs=r.unconverged_pairs,
+                           active_bounds=r.active_bounds)
                       for r in res]
 
     def reset(self):

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "_libcadmm.so")
-SOURCES = ["cadmm_kernels.hip", "cadmm_batch.hip", "cadmm_lemke.hip", "cadmm_traj.hip", "cadmm_adjoint.hip",
+SOURCES = ["cadmm_kernels.hip", "cadmm_batch.hip", "cadmm_lemke.hip", "cadmm_traj.hip", "cadmm_bounds.hip",
+           "cadmm_adjoint.hip",
            "cadmm_host.hip"]
 ARCH = os.environ.get("CADMM_OFFLOAD_ARCH", "gfx950")
 

@@ -76,9 +76,11 @@ struct BatchRows {
     Src src;
     float bh[DIM + 1];
 
-    template <bool HESS>
+    // Gradient g and scale sc at z; with HESS the generalised Hessian of the
+    // rows with y > 0 at z, with UNION of the rows with y > 0 at z or at zu.
+    template <bool HESS, bool UNION = false>
     __device__ __forceinline__ void pass(const float (&z)[NV], float (&g)[NV], float (&H)[NV * NV],
-                                         float& sc) const
+                                         float& sc, const float* zu = nullptr) const
     {
         float gv[DIM + 1] = {}, gnu = 0.f, ysc = 0.f;
         if (HESS) {
@@ -96,7 +98,14 @@ struct BatchRows {
             for (int c = 0; c <= DIM; ++c) gv[c] += y * k[c];
             gnu += kl * y;
             ysc += y * kn;
-            if (HESS && y > 0.f) {
+            bool on = y > 0.f;
+            if (HESS && UNION) {
+                float su = -kl * zu[DIM + 1];
+#pragma unroll
+                for (int c = 0; c <= DIM; ++c) su += k[c] * zu[c];
+                on = on || yh - su * ie > 0.f;
+            }
+            if (HESS && on) {
                 float w[NV];
 #pragma unroll
                 for (int c = 0; c <= DIM; ++c) w[c] = k[c];

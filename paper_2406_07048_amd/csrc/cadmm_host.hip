@@ -47,6 +47,8 @@ struct Layout {
     size_t x, u, y, zeta, xi, y_snap, x_snap, u_snap;
     size_t contrib, rdual_part, rpri_part, unconv_part;
     size_t r_pri, r_dual, done, iters, unconv, hist_pri, hist_dual, alpha, cost, min_alpha;
+    int has_bounds;
+    size_t blim, hq_b, bW, bstat;
     size_t total;
 };
 
@@ -154,6 +156,21 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
     if (d->lanes_per_pair != 0 && d->lanes_per_pair != 1 && d->lanes_per_pair != 2 && d->lanes_per_pair != 4)
         return fail(CADMM_INVALID, "lanes_per_pair must be 0 (autotune), 1, 2 or 4");
     if (d->max_sweeps < 0 || d->max_sweeps > 1000) return fail(CADMM_INVALID, "max_sweeps out of range");
+    // state and input bounds: NaN-free, min <= max, any finite entry turns them on
+    int has_bounds = 0;
+    for (int kind = 0; kind < 2; ++kind) {
+        const double* lo = kind == 0 ? d->s_min : d->u_min;
+        const double* hi = kind == 0 ? d->s_max : d->u_max;
+        const int n = kind == 0 ? ns : nu;
+        for (int i = 0; i < n; ++i) {
+            const double l = lo ? lo[i] : -INFINITY, u = hi ? hi[i] : INFINITY;
+            if (std::isnan(l) || std::isnan(u) || l > u || l == INFINITY || u == -INFINITY)
+                return fail(CADMM_INVALID, "state/input bounds: NaN, +inf lower, -inf upper or min > max");
+            if (std::isfinite(l) || std::isfinite(u)) has_bounds = 1;
+        }
+    }
+    if (has_bounds && !bounds_supported(ns, nu))
+        return fail(CADMM_INVALID, "state/input bounds need n_s <= 12 and n_u <= 4");
 
     L.dim = dim; L.n_s = ns; L.n_u = nu; L.N = N; L.n_parts = d->n_parts; L.n_scen = d->n_scen;
     L.M = M; L.Fr = Fr; L.Fo = Fo; L.n_att = n_att; L.nq = dim + n_att; L.nc = L.nq * (L.nq + 1) / 2 + L.nq;
@@ -213,6 +230,11 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
     L.unconv = take(off, sizeof(int) * d->n_scen);
     L.hist_pri = take(off, sizeof(float) * (size_t)kHistCap * d->n_scen);
     L.hist_dual = take(off, sizeof(float) * (size_t)kHistCap * d->n_scen);
+    L.has_bounds = has_bounds;
+    L.blim = take(off, sizeof(float) * 2 * (ns + nu));
+    L.hq_b = take(off, has_bounds ? sizeof(float) * (size_t)d->n_scen * N * L.nc : 0);
+    L.bW = take(off, has_bounds ? sizeof(float) * (size_t)d->n_scen * kBoundSlots * N * (ns + nu) : 0);
+    L.bstat = take(off, sizeof(int) * d->n_scen);
     L.alpha = take(off, sizeof(float) * std::max<long long>(L.n_pairs, 1));
     L.cost = take(off, sizeof(float) * d->n_scen);
     L.min_alpha = take(off, sizeof(float) * d->n_scen);
@@ -449,6 +471,7 @@ int init_iterate(cadmm_handle* h)
     HIP_TRY(launch_fill(at<float>(h, L.r_dual), L.n_scen, NAN, st));
     HIP_TRY(launch_fill(at<float>(h, L.hist_pri), (long long)kHistCap * L.n_scen, NAN, st));
     HIP_TRY(launch_fill(at<float>(h, L.hist_dual), (long long)kHistCap * L.n_scen, NAN, st));
+    HIP_TRY(launch_fill_int(at<int>(h, L.bstat), L.n_scen, 0, st));
     HIP_TRY(launch_traj_phase(h->P, 1, st));
     if (L.n_blocks > 0) HIP_TRY(launch_init_pairs(h->P, nullptr, 1, st));
     return CADMM_OK;
@@ -640,6 +663,16 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     std::vector<float> Ad = f32(d->A_dyn, nm * ns * ns), Bd = f32(d->B_dyn, nm * ns * nu), cd = f32(d->c_dyn, nm * ns),
                        Qs = f32(d->Q_s, ns * ns), Qu = f32(d->Q_u, nu * nu),
                        xr = f32(d->x_ref, (size_t)L.n_scen * (N + 1) * ns), x0 = f32(d->x0, (size_t)L.n_scen * ns);
+    // bounds as (s_min, s_max, u_min, u_max), +-inf where absent
+    std::vector<float> blim(2 * (ns + nu));
+    for (int i = 0; i < ns; ++i) {
+        blim[i] = d->s_min ? (float)d->s_min[i] : -INFINITY;
+        blim[ns + i] = d->s_max ? (float)d->s_max[i] : INFINITY;
+    }
+    for (int j = 0; j < nu; ++j) {
+        blim[2 * ns + j] = d->u_min ? (float)d->u_min[j] : -INFINITY;
+        blim[2 * ns + nu + j] = d->u_max ? (float)d->u_max[j] : INFINITY;
+    }
     auto up = [&](size_t o, const void* src, size_t nbytes) -> int {
         if (nbytes == 0) return CADMM_OK;
         HIP_TRY(hipMemcpyAsync(h->ws + o, src, nbytes, hipMemcpyHostToDevice, stream));
@@ -661,7 +694,8 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
         (rc = up(L.Q_s, Qs.data(), sizeof(float) * Qs.size())) ||
         (rc = up(L.Q_u, Qu.data(), sizeof(float) * Qu.size())) ||
         (rc = up(L.x_ref, xr.data(), sizeof(float) * xr.size())) ||
-        (rc = up(L.x0, x0.data(), sizeof(float) * x0.size())))
+        (rc = up(L.x0, x0.data(), sizeof(float) * x0.size())) ||
+        (rc = up(L.blim, blim.data(), sizeof(float) * blim.size())))
         return bail(rc);
     // host staging buffers must stay alive until the copies complete
     if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(CADMM_DEVICE, "upload failed"));
@@ -702,6 +736,11 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     P.r_pri = at<float>(h, L.r_pri); P.r_dual = at<float>(h, L.r_dual);
     P.done = at<int>(h, L.done); P.iters = at<int>(h, L.iters); P.unconv = at<int>(h, L.unconv);
     P.hist_pri = at<float>(h, L.hist_pri); P.hist_dual = at<float>(h, L.hist_dual); P.hist_cap = kHistCap;
+    P.has_bounds = L.has_bounds;
+    P.xlo = at<float>(h, L.blim); P.xhi = P.xlo + ns; P.ulo = P.xlo + 2 * ns; P.uhi = P.ulo + nu;
+    P.hq_b = L.has_bounds ? at<float>(h, L.hq_b) : nullptr;
+    P.bW = L.has_bounds ? at<float>(h, L.bW) : nullptr;
+    P.bstat = at<int>(h, L.bstat);
 
     h->G = d->lanes_per_pair > 0 ? d->lanes_per_pair : 1;
     if ((rc = upload_worklists(h, d->waves_per_group > 0 ? d->waves_per_group : 1))) return bail(rc);
@@ -773,7 +812,7 @@ int admm_solve(cadmm_handle* h, int max_iters, int check_every, cadmm_result* ou
         HIP_TRY(launch_fill(at<float>(h, L.min_alpha), L.n_scen, INFINITY, h->stream));
     }
     std::vector<float> rp(L.n_scen), rdv(L.n_scen), cost(L.n_scen), ma(L.n_scen);
-    std::vector<int> iters(L.n_scen), unc(L.n_scen);
+    std::vector<int> iters(L.n_scen), unc(L.n_scen), bst(L.n_scen, 0);
     HIP_TRY(hipMemcpyAsync(rp.data(), h->ws + L.r_pri, sizeof(float) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipMemcpyAsync(rdv.data(), h->ws + L.r_dual, sizeof(float) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipMemcpyAsync(cost.data(), h->ws + L.cost, sizeof(float) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
@@ -781,6 +820,7 @@ int admm_solve(cadmm_handle* h, int max_iters, int check_every, cadmm_result* ou
     HIP_TRY(hipMemcpyAsync(iters.data(), h->ws + L.iters, sizeof(int) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipMemcpyAsync(unc.data(), h->ws + L.unconv, sizeof(int) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipMemcpyAsync(done.data(), h->ws + L.done, sizeof(int) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(bst.data(), h->ws + L.bstat, sizeof(int) * L.n_scen, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     bool all = true;
     for (int s = 0; s < L.n_scen; ++s) {
@@ -792,6 +832,7 @@ int admm_solve(cadmm_handle* h, int max_iters, int check_every, cadmm_result* ou
             out[s].cost = cost[s];
             out[s].min_alpha = ma[s];
             out[s].unconverged_pairs = unc[s];
+            out[s].active_bounds = bst[s];
         }
         all &= done[s] != 0;
     }
@@ -932,7 +973,8 @@ int admm_grad_workspace_size(cadmm_handle* h, int n_iters, int ckpt_every, size_
 {
     if (!h || n_iters < 1 || ckpt_every < 1 || !bytes)
         return fail(CADMM_INVALID, "bad handle, iteration count, checkpoint interval or output");
-    if (h->P.model != CADMM_MODEL_LINEAR) return fail(CADMM_INVALID, "the reverse pass needs the linear models");
+    if (h->P.model != CADMM_MODEL_LINEAR || h->P.has_bounds)
+        return fail(CADMM_INVALID, "the reverse pass needs the linear models and no state/input bounds");
     *bytes = plan_grad(h->L, h->P.n_wg, n_iters, ckpt_every).total;
     return CADMM_OK;
 }
@@ -941,7 +983,8 @@ int admm_record(cadmm_handle* h, int n_iters, int ckpt_every, void* d_gws, size_
 {
     if (!h || n_iters < 1 || ckpt_every < 1)
         return fail(CADMM_INVALID, "bad handle, iteration count or checkpoint interval");
-    if (h->P.model != CADMM_MODEL_LINEAR) return fail(CADMM_INVALID, "the reverse pass needs the linear models");
+    if (h->P.model != CADMM_MODEL_LINEAR || h->P.has_bounds)
+        return fail(CADMM_INVALID, "the reverse pass needs the linear models and no state/input bounds");
     const Layout& L = h->L;
     const GradLayout G = plan_grad(L, h->P.n_wg, n_iters, ckpt_every);
     if (!d_gws || (reinterpret_cast<uintptr_t>(d_gws) & 255) != 0)
@@ -973,7 +1016,8 @@ int admm_record(cadmm_handle* h, int n_iters, int ckpt_every, void* d_gws, size_
 int admm_backward(cadmm_handle* h, void* d_gws, size_t bytes, float dL_scale, float* grad_d, float* grad_x0)
 {
     if (!h) return fail(CADMM_INVALID, "bad handle");
-    if (h->P.model != CADMM_MODEL_LINEAR) return fail(CADMM_INVALID, "the reverse pass needs the linear models");
+    if (h->P.model != CADMM_MODEL_LINEAR || h->P.has_bounds)
+        return fail(CADMM_INVALID, "the reverse pass needs the linear models and no state/input bounds");
     if (h->rec_iters < 1 || d_gws != h->rec_ws || bytes < h->rec_bytes)
         return fail(CADMM_INVALID, "no recorded run in this gradient workspace (call admm_record first)");
     const Layout& L = h->L;

@@ -10,6 +10,8 @@ namespace cadmm {
 constexpr int kWave = 64;
 constexpr int kMaxWavesPerGroup = 8;
 #define CADMM_MAX_NU_DEV 8
+// bounds active at once in one scenario's trajectory QP (slots of the bounded solver)
+constexpr int kBoundSlots = 64;
 
 // Everything a kernel needs, passed by value (kernel argument segment).
 struct DevProblem {
@@ -66,6 +68,15 @@ struct DevProblem {
     float* hist_pri;             // [hist_cap*n_scen]
     float* hist_dual;            // [hist_cap*n_scen]
     int hist_cap;
+    // state and input bounds (has_bounds != 0): limits [n_s] / [n_u] (+-inf: none)
+    int has_bounds;
+    const float* xlo;
+    const float* xhi;
+    const float* ulo;
+    const float* uhi;
+    float* hq_b;                 // [n_scen][N][nc] stage sums of the last trajectory QP
+    float* bW;                   // [n_scen][kBoundSlots][N (n_s + n_u)] active-bound directions
+    int* bstat;                  // [n_scen] active bounds, or < 0 (see traj_bounds_kernel)
 };
 
 // Inputs and outputs of the trajectory kernel in reverse mode (one adjoint LQ
@@ -119,6 +130,10 @@ hipError_t launch_mult_phase(const DevProblem& P, int waves_per_group, int grid,
 hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t s, float* hq_save = nullptr,
                              hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_traj_adjoint(const DevProblem& P, const TrajAdjoint& TA, hipStream_t s);
+// Bounded trajectory QP after the trajectory kernel (P.has_bounds); ev1, if
+// given, is recorded at the end of the kernel's execution.
+hipError_t launch_traj_bounds(const DevProblem& P, int obstacle_free, hipStream_t s, hipEvent_t ev1 = nullptr);
+bool bounds_supported(int n_s, int n_u);
 hipError_t launch_pair_adjoint(const DevProblem& P, const PairAdjoint& A, int waves_per_group, int grid,
                                hipStream_t s);
 hipError_t launch_grad_finalize(int n_parts, int n_faces, const double* gdb, int n_x0, const double* gx0,

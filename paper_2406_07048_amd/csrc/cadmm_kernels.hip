@@ -53,9 +53,11 @@ struct PairRows {
     float ieR[RR], ieO[RO], ieG;    // 1 / (eps D_l)
     float dpO[RO];                  // d'_l of the pair
 
-    template <bool HESS>
+    // Gradient g and scale sc at z; with HESS the generalised Hessian of the
+    // rows with y > 0 at z, with UNION of the rows with y > 0 at z or at zu.
+    template <bool HESS, bool UNION = false>
     __device__ __forceinline__ void pass(const float (&z)[NV], float (&g)[NV], float (&H)[NV * NV],
-                                         float& sc) const
+                                         float& sc, const float* zu = nullptr) const
     {
         const float v0 = z[0], nu = z[DIM + 1];
         float vr[DIM];
@@ -68,6 +70,16 @@ struct PairRows {
 #pragma unroll
             for (int c = 0; c < DIM; ++c) acc += R[r * DIM + c] * vr[c];
             w[r] = acc;
+        }
+        float wu[DIM] = {};   // R v_r at zu
+        if (UNION) {
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) {
+                float acc = 0.f;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) acc += R[r * DIM + c] * zu[1 + c];
+                wu[r] = acc;
+            }
         }
         // partial sums of this lane's rows
         constexpr int NH = DIM * (DIM + 1) / 2;          // lambda-row Hessian block (upper)
@@ -89,7 +101,14 @@ struct PairRows {
                 gnu += f.w * y;
                 ysc += y * an;
                 if (HESS) {
-                    const float act = y > 0.f ? ieR[m] : 0.f;
+                    bool on = y > 0.f;
+                    if (UNION) {
+                        float su = -f.w * zu[DIM + 1];
+#pragma unroll
+                        for (int r = 0; r < DIM; ++r) su += a[r] * zu[1 + r];
+                        on = on || yhR[m] - su * ieR[m] > 0.f;
+                    }
+                    const float act = on ? ieR[m] : 0.f;
                     int h = 0;
 #pragma unroll
                     for (int r = 0; r < DIM; ++r) {
@@ -116,7 +135,14 @@ struct PairRows {
                 for (int r = 0; r < DIM; ++r) Sc[r] += ch[1 + r] * y;
                 ysc += y * (fabsf(ch[0]) + cn);
                 if (HESS) {
-                    const float act = y > 0.f ? ieO[m] : 0.f;
+                    bool on = y > 0.f;
+                    if (UNION) {
+                        float su = ch[0] * zu[0];
+#pragma unroll
+                        for (int r = 0; r < DIM; ++r) su += ch[1 + r] * wu[r];
+                        on = on || yhO[m] - su * ieO[m] > 0.f;
+                    }
+                    const float act = on ? ieO[m] : 0.f;
                     int h = 0;
 #pragma unroll
                     for (int r = 0; r <= DIM; ++r)
@@ -196,7 +222,8 @@ struct PairRows {
                     for (int e = 0; e < DIM; ++e) acc += Mf[r * (DIM + 1) + 1 + e] * R[e * DIM + qq];
                     MR_[r * DIM + qq] = acc;
                 }
-            H[0] = Mf[0] + 1.f + (yg > 0.f ? ieG : 0.f);
+            const bool g_on = yg > 0.f || (UNION && yhG - zu[0] * ieG > 0.f);
+            H[0] = Mf[0] + 1.f + (g_on ? ieG : 0.f);
 #pragma unroll
             for (int qq = 0; qq < DIM; ++qq) H[1 + qq] = MR_[qq];
 #pragma unroll

@@ -652,6 +652,7 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
                         if (t >= N) break;
                         Hq[t * nc + cc] = vq[q];
                         if (hq_save) hq_save[((size_t)s * N + t) * nc + cc] = vq[q];
+                        if (P.hq_b) P.hq_b[((size_t)s * N + t) * nc + cc] = vq[q];
                     }
                 });
         } else {
@@ -1132,7 +1133,12 @@ static hipError_t launch_traj(const DevProblem& P, int obstacle_free, float* hq_
 hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t st, float* hq_save, hipEvent_t e0,
                              hipEvent_t e1)
 {
-    return launch_traj<false>(P, obstacle_free, hq_save, TrajAdjoint{}, st, e0, e1);
+    if (!P.has_bounds) return launch_traj<false>(P, obstacle_free, hq_save, TrajAdjoint{}, st, e0, e1);
+    // with bounds the unconstrained minimiser is moved to the bounded one by a
+    // second kernel; the events then bracket both
+    const hipError_t err = launch_traj<false>(P, obstacle_free, hq_save, TrajAdjoint{}, st, e0, nullptr);
+    if (err != hipSuccess) return err;
+    return launch_traj_bounds(P, obstacle_free, st, e0 ? e1 : nullptr);
 }
 
 hipError_t launch_traj_adjoint(const DevProblem& P, const TrajAdjoint& TA, hipStream_t st)

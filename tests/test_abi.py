@@ -117,3 +117,39 @@ def test_short_model_arrays_refused_by_the_binding():
     p["A_dyn"] = p["A_dyn"][:10]
     with pytest.raises(ValueError):
         cadmm.cadmm_workspace_size(p)
+
+
+def test_bounds_accepted_and_sized():
+    """Bounds add the stage sums and the active-bound slots to the workspace."""
+    import paper_2406_07048_amd as cadmm
+    p = workloads.make("c2b")
+    q = {k: v for k, v in p.items() if k not in ("s_min", "s_max", "u_min", "u_max")}
+    assert cadmm.cadmm_workspace_size(p)[0] > cadmm.cadmm_workspace_size(q)[0]
+    # infinite entries only: no bounds, no extra memory
+    inf = np.inf
+    r = dict(q, s_min=np.full(4, -inf), s_max=np.full(4, inf))
+    assert cadmm.cadmm_workspace_size(r)[0] == cadmm.cadmm_workspace_size(q)[0]
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda p: p["u_min"].__setitem__(0, 5.0),                                      # min > max
+    lambda p: p["s_max"].__setitem__(3, np.nan),                                   # NaN
+    lambda p: p["s_min"].__setitem__(0, np.inf),                                   # +inf lower bound
+])
+def test_invalid_bounds_rejected(mutate):
+    p = workloads.make("c2b")
+    p = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    mutate(p)
+    assert _size_code(p) == 1
+
+
+def test_bounds_need_the_supported_sizes():
+    """The bounded solver's kernels cover n_s <= 12, n_u <= 4."""
+    p = workloads.make("c1")
+    p = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+    n_s = 14
+    p.update(n_s=n_s, A_dyn=np.eye(n_s), B_dyn=np.zeros((n_s, 2)), c_dyn=np.zeros(n_s), Q_s=np.eye(n_s),
+             x_ref=np.zeros((len(p["obs_ptr"]) - 1, p["N"] + 1, n_s)), x0=np.zeros((len(p["obs_ptr"]) - 1, n_s)))
+    assert _size_code(p) == 0
+    p["u_max"] = np.array([1.0, 1.0])
+    assert _size_code(p) == 1

@@ -394,28 +394,41 @@ def test_full_run_c1(cadmm):
 @pytest.mark.parametrize("name,iters", [("c2", 60), ("c3", 40)])
 def test_full_run_trajectory(cadmm, name, iters):
     """Longer runs from a shared iterate (the oracle's initial one, since in 3D
-    the initial LP certificate is not unique): the trajectories stay within
-    the parity bar of the oracle's every 10 iterations. The duals are
-    compared per pair every 10 iterations too: the iteration is not a
-    contraction (the collision constraints are nonconvex), so differences of
-    the trajectories feed back into the pair data and grow; the bar is 1e-5
-    for 99% of the pairs and 1e-4 for every pair (measured and printed per
-    checkpoint). The scales at the final trajectory are within 1e-5."""
+    the initial LP certificate is not unique), checked every 10 iterations:
+
+    - the trajectories stay within the parity bar of the oracle's own run;
+    - the duals of the last step against the oracle's pair phase applied to
+      the GPU's own previous iterate: the pair solves of step k alone, apart
+      from the rounding the run has accumulated, at the 1e-5 dual bar for
+      every pair;
+    - the duals against the oracle's own run: 99% of the pairs within 1e-5.
+      The iteration is not a contraction (the collision constraints are
+      nonconvex), so the trajectories' FP32 differences feed back into the
+      pair data and a few pairs drift further (up to 1.0e-4 measured,
+      printed).
+
+    The scales at the final trajectory are within 1e-5."""
     prob = workloads.make(name)
     say(f"[full run] {name} {iters} iterations from the oracle's initial iterate")
     P, st = oracle_iterate(prob, 0)
     h = cadmm.Handle(prob)
     h.set_state(x=st["x"], u=st["u"], y=st["y"], zeta=st["zeta"], xi=st["xi"])
     for k in range(10, iters + 1, 10):
-        h.iterate(10)
+        h.iterate(9)
+        g_prev = gpu_state(h)
+        h.iterate(1)
         g = gpu_state(h)
         P.run(st, 10)
         et = traj_error(g, st)
+        y_step = P.pair_phase(g_prev)
+        es = scaled_y_errors(prob, g_prev["x"], g["y"], y_step)
         ey = scaled_y_errors(prob, st["x"], g["y"], st["y"])
-        say(f"   k={k}: traj err {et:.2e}, y worst {ey.max():.2e} p99 {np.percentile(ey, 99):.2e} "
-            f"(pairs above 1e-5: {(ey > TOL_DUAL).sum()} of {ey.size})")
+        say(f"   k={k}: traj err {et:.2e}; step-k duals worst {es.max():.2e}; against the oracle's run: "
+            f"worst {ey.max():.2e} p99 {np.percentile(ey, 99):.2e} (pairs above 1e-5: {(ey > TOL_DUAL).sum()} "
+            f"of {ey.size})")
         assert et <= TOL_TRAJ
-        assert np.percentile(ey, 99) <= TOL_DUAL and ey.max() <= 1e-4
+        assert es.max() <= TOL_DUAL
+        assert np.percentile(ey, 99) <= TOL_DUAL
     alpha_g = h.scales().double().cpu().numpy()
     h.close()
     alpha_o = P.scale_all(g["x"])
