@@ -247,6 +247,28 @@ int admm_launch_config(cadmm_handle* h, int* waves_per_group, int* n_workgroups,
  * admm_record) to start from the new data. Syncs the stream. */
 int admm_set_params(cadmm_handle* h, const double* obs_d, const double* x0);
 
+/* Restart the pair iterate at the current trajectory: y = (lam*, mu*,
+ * max(alpha* - 1, 0)) from the scale LP of every pair (Sec. III-B eq.
+ * scale_opt_dual) at the handle's current x, zeta = xi = 0, stop flags
+ * cleared; x and u are kept. The initialisation of setup, applied to a
+ * trajectory set with admm_set_state (a warm start). Enqueued on the
+ * handle's stream. */
+int admm_reset_duals(cadmm_handle* h);
+
+/* Replace the reference trajectory x_ref (host FP64, n_scen*(N+1)*n_s, as in
+ * the descriptor) for the following iterations; the iterate is not touched.
+ * With admm_set_params (new x0) and admm_set_state (a shifted warm start)
+ * this moves a handle from one receding-horizon cycle to the next. Syncs the
+ * stream. */
+int admm_set_reference(cadmm_handle* h, const double* x_ref);
+
+/* One step of a built-in nonlinear model on the host, in FP64:
+ * s_next = s + dt f_c(s, u) (Sec. IV-A eq. system_eqn; the models and
+ * model_par as in cadmm_desc.model); the plant of a simulated closed loop.
+ * s, s_next: n_s values, u: n_u values (host). CADMM_INVALID for
+ * CADMM_MODEL_LINEAR or non-finite input. */
+int cadmm_model_step(int model, const double* model_par, const double* s, const double* u, double* s_next);
+
 /*
  * Differentiation through the unrolled iteration. The differentiated map is
  *     L(d, x0) = sum_s F_s(x^K, u^K),

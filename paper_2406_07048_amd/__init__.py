@@ -94,6 +94,9 @@ _SIGNATURES = {
     "admm_phase_times": (ctypes.c_int, [_vp, ctypes.c_int, _vp]),
     "admm_launch_config": (ctypes.c_int, [_vp, _ip, _ip, _ip]),
     "admm_set_params": (ctypes.c_int, [_vp, _dp, _dp]),
+    "admm_set_reference": (ctypes.c_int, [_vp, _dp]),
+    "admm_reset_duals": (ctypes.c_int, [_vp]),
+    "cadmm_model_step": (ctypes.c_int, [ctypes.c_int, _dp, _dp, _dp, _dp]),
     "admm_grad_workspace_size": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     "admm_record": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_size_t, _vp]),
     "admm_backward": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_float, _vp, _vp]),
@@ -323,6 +326,17 @@ class Handle:
         return w.value, g.value, l.value
 
     # -- differentiation --------------------------------------------------
+    def reset_duals(self):
+        """Scale-LP certificates at the current trajectory, zero multipliers."""
+        _check(lib().admm_reset_duals(self._h), "admm_reset_duals")
+
+    def set_reference(self, x_ref):
+        """Replace the reference trajectory [n_scen, N+1, n_s] (FP64 copy)."""
+        x = np.ascontiguousarray(_host(x_ref), dtype=np.float64).ravel()
+        if x.size != self.n_scen * (self.prob["N"] + 1) * self.n_s:
+            raise ValueError(f"x_ref has {x.size} values, expected {self.n_scen * (self.prob['N'] + 1) * self.n_s}")
+        _check(lib().admm_set_reference(self._h, x.ctypes.data_as(_dp)), "admm_set_reference")
+
     def set_params(self, obs_d=None, x0=None):
         """Replace the obstacle offsets d [F_o] and/or initial states x0
         [n_scen, n_s] (anything numpy can read; copied as FP64). The iterate
@@ -472,6 +486,18 @@ def pair_qp_batch(row_ptr, K, kappa, yhat, bhat, eps, max_sweeps=0, stream=None,
     fn = lib().pair_qp_batch_noalloc if noalloc else lib().pair_qp_batch
     _check(fn(ctypes.byref(b), _stream_ptr(stream)), "pair_qp_batch_noalloc" if noalloc else "pair_qp_batch")
     return y, r, nu, status
+
+
+def model_step(model, model_par, s, u):
+    """One host step s + dt f_c(s, u) of a built-in nonlinear model (FP64)."""
+    par = np.zeros(8)
+    par[:len(model_par)] = model_par
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    out = np.zeros_like(s)
+    _check(lib().cadmm_model_step(int(model), par.ctypes.data_as(_dp), s.ctypes.data_as(_dp), u.ctypes.data_as(_dp),
+                                  out.ctypes.data_as(_dp)), "cadmm_model_step")
+    return out
 
 
 def pair_qp_batch_workspace_size(n_pairs):

@@ -3,6 +3,7 @@
 // capture of one ADMM iteration, launch-shape autotuning and result readout.
 #include "cadmm.h"
 #include "cadmm_internal.h"
+#include "cadmm_model.h"
 
 #include <algorithm>
 #include <cmath>
@@ -966,6 +967,45 @@ int admm_set_params(cadmm_handle* h, const double* obs_d, const double* x0)
     }
     // the host arrays must stay alive until the copies are done
     HIP_TRY(hipStreamSynchronize(h->stream));
+    return CADMM_OK;
+}
+
+int admm_reset_duals(cadmm_handle* h)
+{
+    if (!h) return fail(CADMM_INVALID, "bad handle");
+    const Layout& L = h->L;
+    hipStream_t st = h->stream;
+    HIP_TRY(launch_fill(at<float>(h, L.zeta), L.n_pairs, 0.f, st));
+    HIP_TRY(launch_fill(at<float>(h, L.xi), L.n_pairs * L.dim, 0.f, st));
+    HIP_TRY(launch_fill_int(at<int>(h, L.done), L.n_scen, 0, st));
+    if (L.n_blocks > 0) HIP_TRY(launch_init_pairs(h->P, nullptr, 1, st));
+    return CADMM_OK;
+}
+
+int admm_set_reference(cadmm_handle* h, const double* x_ref)
+{
+    if (!h || !x_ref) return fail(CADMM_INVALID, "bad handle or NULL reference");
+    const Layout& L = h->L;
+    const size_t n = (size_t)L.n_scen * (L.N + 1) * L.n_s;
+    if (!finite_all(x_ref, (long long)n)) return fail(CADMM_INVALID, "non-finite reference");
+    std::vector<float> xr(n);
+    for (size_t i = 0; i < n; ++i) xr[i] = (float)x_ref[i];
+    HIP_TRY(hipMemcpyAsync(h->ws + L.x_ref, xr.data(), sizeof(float) * n, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return CADMM_OK;
+}
+
+int cadmm_model_step(int model, const double* model_par, const double* s, const double* u, double* s_next)
+{
+    if (model != CADMM_MODEL_BICYCLE && model != CADMM_MODEL_QUADROTOR)
+        return fail(CADMM_INVALID, "cadmm_model_step needs a nonlinear model");
+    if (!model_par || !s || !u || !s_next) return fail(CADMM_INVALID, "NULL argument");
+    const int ns = model_ns(model), nu = model_nu(model);
+    if (!finite_all(model_par, model == CADMM_MODEL_BICYCLE ? 2 : 6) || !finite_all(s, ns) || !finite_all(u, nu))
+        return fail(CADMM_INVALID, "non-finite model parameters, state or input");
+    double f[12];
+    model_fc<double>(model, model_par, s, u, f);
+    for (int i = 0; i < ns; ++i) s_next[i] = s[i] + model_par[0] * f[i];
     return CADMM_OK;
 }
 

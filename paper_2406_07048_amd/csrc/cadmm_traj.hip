@@ -4,6 +4,7 @@
 // forward mode and as the adjoint LQ of the reverse pass.
 #include "cadmm.h"
 #include "cadmm_device.h"
+#include "cadmm_model.h"
 
 #include <float.h>
 #include <math.h>
@@ -65,69 +66,19 @@ __host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bo
 }
 
 // ------------------------------------------------------------------------
-// Nonlinear dynamics s_{t+1} = s_t + dt f_c(s_t, u_t) (Sec. IV-A eq.
-// system_eqn) and one column of its Jacobian, by forward-mode derivatives
-// (a value and one tangent, FP64): one thread per (step, column).
-// ------------------------------------------------------------------------
-struct Tan {
-    double v, d;
-};
-__device__ __forceinline__ Tan operator+(Tan a, Tan b) { return {a.v + b.v, a.d + b.d}; }
-__device__ __forceinline__ Tan operator-(Tan a, Tan b) { return {a.v - b.v, a.d - b.d}; }
-__device__ __forceinline__ Tan operator*(Tan a, Tan b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
-__device__ __forceinline__ Tan operator*(double a, Tan b) { return {a * b.v, a * b.d}; }
-__device__ __forceinline__ Tan operator/(Tan a, Tan b)
-{
-    const double q = a.v / b.v;
-    return {q, (a.d - q * b.d) / b.v};
-}
-__device__ __forceinline__ Tan operator/(Tan a, double b) { return {a.v / b, a.d / b}; }
-__device__ __forceinline__ Tan tsin(Tan a) { return {sin(a.v), cos(a.v) * a.d}; }
-__device__ __forceinline__ Tan tcos(Tan a) { return {cos(a.v), -sin(a.v) * a.d}; }
-__device__ __forceinline__ Tan ttan(Tan a)
-{
-    const double t = tan(a.v);
-    return {t, (1.0 + t * t) * a.d};
-}
-
-// F = s + dt f_c(s, u) and column j of its Jacobian, j < n_s: dF/ds_j,
+// Nonlinear dynamics F(s, u) = s + dt f_c(s, u) (cadmm_model.h) and one
+// column of its Jacobian, by forward-mode derivatives (a value and one
+// tangent, FP64): one thread per (step, column). Column j < n_s is dF/ds_j,
 // else dF/du_{j - n_s}.
-//   model 1 (kinematic bicycle, s = (p_x, p_y, theta, v), u = (a, delta),
-//     par = (dt, wheelbase L)): f_c = (v cos theta, v sin theta, v tan(delta) / L, a);
-//   model 2 (quadrotor, s = (p, v, phi theta psi, body rates w), u = (dF, tau),
-//     par = (dt, m, J_x, J_y, J_z, g)): p' = v, v' = (g + dF / m) R e_3 - g e_3
-//     with R = R_z(psi) R_y(theta) R_x(phi), the ZYX Euler-angle rates of the
-//     body rates, and Euler's equations J w' = tau + (J w) x w for a diagonal J.
+// ------------------------------------------------------------------------
 __device__ void model_column(int model, const double* par, const float* s, const float* u, int j, double* F,
                              double* col)
 {
-    const int ns = model == 1 ? 4 : 12, nu = model == 1 ? 2 : 4;
+    const int ns = model_ns(model), nu = model_nu(model);
     Tan S[12], U[4], f[12];
     for (int i = 0; i < ns; ++i) S[i] = {(double)s[i], i == j ? 1.0 : 0.0};
     for (int k = 0; k < nu; ++k) U[k] = {(double)u[k], ns + k == j ? 1.0 : 0.0};
-    if (model == 1) {
-        f[0] = S[3] * tcos(S[2]);
-        f[1] = S[3] * tsin(S[2]);
-        f[2] = S[3] * ttan(U[1]) / par[1];
-        f[3] = U[0];
-    } else {
-        const double m = par[1], Jx = par[2], Jy = par[3], Jz = par[4], g = par[5];
-        const Tan cph = tcos(S[6]), sph = tsin(S[6]), cth = tcos(S[7]), sth = tsin(S[7]);
-        const Tan cps = tcos(S[8]), sps = tsin(S[8]);
-        const Tan acc = Tan{g, 0.0} + U[0] / m;
-        f[0] = S[3]; f[1] = S[4]; f[2] = S[5];
-        f[3] = acc * (cps * sth * cph + sps * sph);
-        f[4] = acc * (sps * sth * cph - cps * sph);
-        f[5] = acc * (cth * cph) - Tan{g, 0.0};
-        const Tan p = S[9], q = S[10], r = S[11];
-        const Tan qr = q * sph + r * cph;
-        f[6] = p + qr * sth / cth;
-        f[7] = q * cph - r * sph;
-        f[8] = qr / cth;
-        f[9] = (U[1] + (Jy - Jz) * (q * r)) / Jx;
-        f[10] = (U[2] + (Jz - Jx) * (r * p)) / Jy;
-        f[11] = (U[3] + (Jx - Jy) * (p * q)) / Jz;
-    }
+    model_fc<Tan>(model, par, S, U, f);
     const double dt = par[0];
     for (int i = 0; i < ns; ++i) {
         F[i] = (double)s[i] + dt * f[i].v;

@@ -6,6 +6,7 @@ import re
 import numpy as np
 import pytest
 
+import oracle
 import workloads
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -153,3 +154,21 @@ def test_bounds_need_the_supported_sizes():
     assert _size_code(p) == 0
     p["u_max"] = np.array([1.0, 1.0])
     assert _size_code(p) == 1
+
+
+@pytest.mark.parametrize("name", ["c2sqp", "c3sqp"])
+def test_host_model_step_matches_the_oracle(name):
+    """cadmm_model_step (the library's FP64 plant step, host code) against the
+    oracle's complex-arithmetic model at random states and inputs."""
+    import paper_2406_07048_amd as cadmm
+    p = workloads.make(name)
+    P = oracle.Problem(p)
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        s = rng.standard_normal(p["n_s"]) * 0.5
+        u = rng.standard_normal(p["n_u"]) * 0.5
+        F, _, _ = P.model_step(s, u)
+        G = cadmm.model_step(p["model"], p["model_par"], s, u)
+        assert np.abs(F - G).max() <= 1e-13 * (1 + np.abs(F).max())
+    with pytest.raises(cadmm.CadmmError):
+        cadmm.model_step(0, p["model_par"], s, u)

@@ -334,6 +334,138 @@ def config_c2b(seed=10, v_range=(19.9, 20.3), a_range=(-3.0, 1.0), steer=0.07):
     return p
 
 
+def closed_loop_scene(seed=41, n_sparse=8, n_dense=24, N=16, duration=25.0, dt=0.1, sigma=SIGMA_PAPER,
+                      path_clearance=0.0):
+    """The receding-horizon workload of Sec. V-A, synthetic (the AirSim scene is
+    not available): a 70 x 20 x 6 m corridor (x in [-10, 10], y in [0, 70],
+    z in [0, 6]) with 32 obstacles, n_sparse in an obstacle-sparse stretch
+    (y in [8, 32]) and n_dense in an obstacle-dense one (y in [36, 64]); each a
+    vertical prism over the full height (a regular polygon of U{4..8} sides,
+    circumradius U(0.4, 1.0) m, random yaw; centres at least 2.4 m apart, 3 m
+    from the start and goal, and the circumradius + path_clearance from the
+    reference path, so that no obstacle blocks it head-on but those beside it
+    still reach into the robot's swept width). The quadrotor as one box of
+    0.8 x 0.8 x 0.2 m (its frame with the rotors), the nonlinear model
+    relinearised every iteration, horizon N = 16, dt = 0.1 s, sigma = 300, the
+    C3 weights scaled by 100 (the tracking cost against the penalty), the
+    corridor's walls, floor and ceiling as state bounds on the position. Reference: a Catmull-Rom curve from (0, 0, 1) through 5
+    random waypoints (y = 70 k / 6, x ~ U(-6, 6), z ~ U(0.8, 2.5)) to
+    (0, 70, 1), flown in `duration` seconds with a trapezoidal speed profile
+    (2 s to speed up from rest and 2 s to stop), sampled every dt, with the
+    path's velocity and zero attitude and rates.
+    Returns the scene: base problem fields, obstacles as (C, d) and their
+    bounding boxes, the sampled reference ref[K + 1, 12] and the start state."""
+    rng = np.random.default_rng(seed)
+    A_b, b_b = box_faces([0.4, 0.4, 0.1])
+    parts = [(A_b, b_b, np.zeros(3))]
+    start, goal = np.array([0.0, 0.0, 1.0]), np.array([0.0, 70.0, 1.0])
+    way = [start]
+    for k in range(1, 6):
+        way.append(np.array([rng.uniform(-6.0, 6.0), 70.0 * k / 6.0, rng.uniform(0.8, 2.5)]))
+    way.append(goal)
+    way = np.array(way)
+    # the curve, densely sampled (uniform Catmull-Rom, end points doubled)
+    P4 = np.concatenate([way[:1], way, way[-1:]])
+    dense = []
+    for i in range(len(way) - 1):
+        p0, p1, p2, p3 = P4[i], P4[i + 1], P4[i + 2], P4[i + 3]
+        for tt in np.linspace(0.0, 1.0, 400, endpoint=False):
+            dense.append(0.5 * (2 * p1 + (p2 - p0) * tt + (2 * p0 - 5 * p1 + 4 * p2 - p3) * tt ** 2
+                                + (3 * p1 - p0 - 3 * p2 + p3) * tt ** 3))
+    dense.append(way[-1])
+    dense = np.array(dense)
+    obstacles, boxes, centres = [], [], []
+    for n, (ylo, yhi) in ((n_sparse, (8.0, 32.0)), (n_dense, (36.0, 64.0))):
+        placed = 0
+        while placed < n:
+            c = np.array([rng.uniform(-8.0, 8.0), rng.uniform(ylo, yhi), 3.0])
+            if any(np.hypot(*(c[:2] - q[:2])) < 2.4 for q in centres):
+                continue
+            if min(np.hypot(*(c[:2] - start[:2])), np.hypot(*(c[:2] - goal[:2]))) < 3.0:
+                continue
+            sides = int(rng.integers(4, 9))
+            rad = rng.uniform(0.4, 1.0)
+            # no obstacle blocks the path head-on: its centre keeps rad + 0.2 m
+            # from the path (the robot's arms reach 0.45 m, so it still has to
+            # swerve around the obstacles that graze the path)
+            if np.min(np.hypot(dense[:, 0] - c[0], dense[:, 1] - c[1])) < rad + path_clearance:
+                continue
+            yaw = rng.uniform(0.0, 2.0 * np.pi)
+            R = np.array([[np.cos(yaw), -np.sin(yaw), 0.0], [np.sin(yaw), np.cos(yaw), 0.0], [0.0, 0.0, 1.0]])
+            C, dl = prism_faces(sides, rad, 3.0, R)
+            obstacles.append((C, dl + C @ c))
+            boxes.append((c - np.array([rad, rad, 3.0]), c + np.array([rad, rad, 3.0])))
+            centres.append(c)
+            placed += 1
+    arc = np.concatenate([[0.0], np.cumsum(np.linalg.norm(np.diff(dense, axis=0), axis=1))])
+    K = int(round(duration / dt))
+    ramp = 2.0
+    vmax = arc[-1] / (duration - ramp)
+
+    def s_of(t):   # arc length flown at time t
+        if t <= ramp:
+            return 0.5 * vmax * t * t / ramp
+        if t >= duration - ramp:
+            r = duration - t
+            return arc[-1] - 0.5 * vmax * r * r / ramp
+        return vmax * (t - 0.5 * ramp)
+
+    ref = np.zeros((K + 1, 12))
+    for k in range(K + 1):
+        t = k * dt
+        a = min(max(s_of(t), 0.0), arc[-1])
+        i = min(int(np.searchsorted(arc, a, side="right")) - 1, len(dense) - 2)
+        seg = arc[i + 1] - arc[i]
+        tdir = (dense[i + 1] - dense[i]) / seg
+        ref[k, :3] = dense[i] + (a - arc[i]) * tdir
+        speed = (s_of(min(t + 1e-3, duration)) - s_of(max(t - 1e-3, 0.0))) / (min(t + 1e-3, duration) - max(t - 1e-3, 0.0))
+        ref[k, 3:6] = speed * tdir
+    ptr, A, b, off = _pack_parts(parts)
+    Ad, Bd, cd = quadrotor_model(dt)
+    base = dict(dim=3, n_s=12, n_u=4, N=N, dt=dt,
+                part_face_ptr=ptr, part_A=A, part_b=b, part_off=off,
+                A_dyn=Ad, B_dyn=Bd, c_dyn=cd,
+                pos_idx=np.array([0, 1, 2], np.int32), att_idx=np.array([6, 7, 8], np.int32),
+                att_kind=ATT_EULER_ZYX,
+                Q_s=100.0 * np.diag([1, 1, 1, 0.1, 0.1, 0.1, 0.1, 0.1, 0.1, 0.01, 0.01, 0.01]),
+                Q_u=100.0 * np.diag([0.1, 1.0, 1.0, 1.0]), sigma=sigma,
+                model=MODEL_QUADROTOR, model_par=np.array([dt, 1.0, 0.01, 0.01, 0.02, 9.81]),
+                # the corridor as state bounds (Sec. IV-A eq. MPC_opt_origin): the
+                # robot's centre stays 0.5 m inside its walls, floor and ceiling
+                s_min=np.array([-9.5, -np.inf, 0.5] + [-np.inf] * 9),
+                s_max=np.array([9.5, np.inf, 5.5] + [np.inf] * 9))
+    x_start = np.zeros(12)
+    x_start[:3] = start
+    return dict(base=_finish(base), obstacles=obstacles, boxes=boxes, ref=ref, x_start=x_start,
+                waypoints=way, window=np.array([10.0, 10.0, 3.0]))
+
+
+def sensed(scene, position):
+    """Indices of the obstacles the robot senses at `position`: those whose
+    bounding box meets the 20 x 20 x 6 m window centred on it (Sec. V-A)."""
+    w = scene["window"]
+    lo, hi = np.asarray(position) - w, np.asarray(position) + w
+    return [j for j, (blo, bhi) in enumerate(scene["boxes"]) if np.all(blo <= hi) and np.all(bhi >= lo)]
+
+
+def reference_window(scene, k):
+    """x_ref for cycle k: the reference samples k .. k + N (held at the end)."""
+    ref = scene["ref"]
+    N = scene["base"]["N"]
+    idx = np.minimum(np.arange(k, k + N + 1), len(ref) - 1)
+    return ref[idx][None]
+
+
+def cycle_problem(scene, ids, x0, k):
+    """The problem of cycle k: the sensed obstacles ids, the measured state x0
+    and the reference window of cycle k (one scenario)."""
+    p = dict(scene["base"])
+    p = with_obstacles(p, [[scene["obstacles"][j] for j in ids]])
+    p["x_ref"] = reference_window(scene, k)
+    p["x0"] = np.asarray(x0, np.float64)[None].copy()
+    return p
+
+
 def config_c3sqp(seed=25):
     """C3 with the nonlinear quadrotor relinearised about every iterate."""
     p = config_c3(seed)
