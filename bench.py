@@ -57,8 +57,11 @@ WORKLOADS = {
                        "(one SQP step per ADMM iteration), up to 200 iterations", iters=200),
     "c3sqp": dict(desc="the C3 problem with the nonlinear quadrotor relinearised about every iterate, "
                        "up to 200 iterations", iters=200),
+    "c2b": dict(desc="the C2 problem with speed, acceleration and steering bounds (bounded trajectory QP every "
+                     "iteration), up to 200 iterations", iters=200),
 }
-ALL_LEGS = ("c4", "plain", "c2", "c3", "c2tv", "c2sqp", "c3sqp", "stream", "stream2", "lemke", "grad", "cpu")
+ALL_LEGS = ("c4", "plain", "c2", "c3", "c2tv", "c2sqp", "c3sqp", "c2b", "stream", "stream2", "lemke", "loop", "grad",
+            "cpu")
 VALU_PEAK_INSTS = 256 * 2.4e9   # wave-wide VALU instructions per second: 256 CUs x 2.4 GHz x one per CU clock
 
 
@@ -354,6 +357,34 @@ def leg_lemke(cadmm, torch, n_pairs=1 << 18, reps=3):
                 max_abs_dual_difference=float((yn - yl).abs().max().item()))
 
 
+def leg_loop(cadmm, torch):
+    """The receding-horizon closed loop of the synthetic Sec. V-A scene (250
+    control cycles of 0.1 s, T = 16, 32 obstacles, a 20 x 20 x 6 m sensing
+    window): wall time per control loop (new set-up when the sensed set
+    changes, x0 and reference update, shifted warm start, admm_solve with at
+    least 5 iterations, state read back), one warm-up run first."""
+    from paper_2406_07048_amd.closed_loop import ClosedLoop
+    scene = workloads.closed_loop_scene()
+    cycles = len(scene["ref"]) - 1
+    ClosedLoop(scene).run(20)
+    loop = ClosedLoop(scene)
+    out = loop.run(cycles)
+    loop.close()
+    recs = out["records"]
+    t = np.array([r["setup_s"] + r["solve_s"] for r in recs]) * 1e3
+    ts = np.array([r["solve_s"] for r in recs if not r["setup"]]) * 1e3
+    it = np.array([r["iters"] for r in recs])
+    pairs = np.array([r["pairs"] for r in recs])
+    return dict(workload="closed loop: 250 cycles of 0.1 s, quadrotor box, 32 pillars in 70x20x6 m, 20x20x6 m "
+                         "sensing, T=16, sigma=300",
+                ms_per_control_loop=float(t.mean()), ms_per_control_loop_max=float(t.max()),
+                ms_per_solve_without_setup=float(ts.mean()) if ts.size else None,
+                setups=int(sum(r["setup"] for r in recs)), iterations_mean=float(it.mean()),
+                iterations_max=int(it.max()), pairs_mean=float(pairs.mean()), pairs_max=int(pairs.max()),
+                goal_distance_m=float(np.linalg.norm(out["x"][-1, :3] - scene["ref"][-1, :3])),
+                min_alpha=float(min(r["min_alpha"] for r in recs)))
+
+
 def leg_grad(cadmm, torch, steps=3, iters=100, every=10):
     """Reverse pass of the 3D configuration unrolled over 100 iterations with
     a checkpoint every 10: wall time of admm_backward (segment replay +
@@ -491,7 +522,7 @@ def main():
             out["batched_vs_plain"] = {"plain_pair_solves_per_s": pl["solves"] / pl["sec"],
                                        "plain_ms_per_step": pl["sec"] * 1e3,
                                        "speedup": pl["sec"] / sec * (c4["solves"] / max(pl["solves"], 1.0))}
-    for name in ("c2", "c3", "c2tv", "c2sqp", "c3sqp"):
+    for name in ("c2", "c3", "c2tv", "c2sqp", "c3sqp", "c2b"):
         if name in legs:
             say(f"{name}: single scenario to the stopping test")
             out[name] = leg_single(cadmm, torch, name, args)
@@ -504,6 +535,9 @@ def main():
     if "lemke" in legs:
         say("lemke: Newton vs Lemke pair solvers (2^18)")
         out["lemke"] = leg_lemke(cadmm, torch)
+    if "loop" in legs:
+        say("loop: receding-horizon closed loop (250 cycles)")
+        out["closed_loop"] = leg_loop(cadmm, torch)
     if "grad" in legs:
         say("grad: reverse pass (3D, 100 unrolled iterations)")
         out["differentiation"] = leg_grad(cadmm, torch)

@@ -12,14 +12,15 @@ namespace cadmm {
 
 // ------------------------------------------------------------------------
 // rows of the stateless batch, staged in LDS: per row (K_0..K_dim, kappa,
-// yhat, 1 / (eps D), ||K||) with D = ||K||^2, the last two formed once at
-// staging instead of in every solver pass
+// yhat); the row scales 1 / (eps D) and ||K|| (D = ||K||^2) are formed in
+// every solver pass (a few VALU instructions against an LDS tile of 5 floats
+// a row instead of 7: 8 waves per CU instead of 5 to hide the LDS latency)
 // ------------------------------------------------------------------------
 
-// 1 / (eps D) and ||K|| = D rsq(D) of a row, D = ||K||^2: formed once per row
-// when staged, and by the same instructions when a resumed solve reads the
-// row from memory (so both see bitwise the same values). v_rcp_f32 /
-// v_rsq_f32, about 1 ulp.
+// 1 / (eps D) and ||K|| = D rsq(D) of a row, D = ||K||^2, by the same
+// instructions whether the row comes from LDS or from memory (a solve
+// resumed in the second launch), so both see bitwise the same values.
+// v_rcp_f32 / v_rsq_f32, about 1 ulp.
 template <int C>
 __device__ __forceinline__ void row_scales(const float (&k)[C], float eps, float& ie, float& kn)
 {
@@ -35,8 +36,9 @@ __device__ __forceinline__ void row_scales(const float (&k)[C], float eps, float
 // formed as at staging.
 template <int DIM>
 struct LdsSrc {
-    static constexpr int RW = DIM + 5;    // floats per staged row
+    static constexpr int RW = DIM + 3;    // floats per staged row
     const float* rows;                    // LDS, RW floats per row
+    float eps;
 
     __device__ __forceinline__ void load(int l, float (&k)[DIM + 1], float& kl, float& yh, float& ie,
                                          float& kn) const
@@ -46,8 +48,7 @@ struct LdsSrc {
         for (int c = 0; c <= DIM; ++c) k[c] = row[c];
         kl = row[DIM + 1];
         yh = row[DIM + 2];
-        ie = row[DIM + 3];
-        kn = row[DIM + 4];
+        row_scales<DIM + 1>(k, eps, ie, kn);
     }
 };
 
@@ -207,10 +208,6 @@ __global__ void __launch_bounds__(kBatchPairs) pair_qp_batch_kernel(int n_pairs,
             }
             row[DIM + 1] = kappa[base + i];
             row[DIM + 2] = yhat[base + i];
-            float ie, kn;
-            row_scales<C>(kk, eps, ie, kn);
-            row[DIM + 3] = ie;
-            row[DIM + 4] = kn;
         }
         __syncthreads();
         const bool act = p >= pa && p < pb;
@@ -221,6 +218,7 @@ __global__ void __launch_bounds__(kBatchPairs) pair_qp_batch_kernel(int n_pairs,
         if (act) {
             sr.n = n;
             sr.src.rows = tile + (rb - base) * RW;
+            sr.src.eps = eps;
 #pragma unroll
             for (int c = 0; c < C; ++c) sr.bh[c] = bhat[(size_t)p * C + c];
             // warm start v = K^T yhat + bhat; nu makes the largest kappa-row stationary
@@ -271,10 +269,14 @@ __global__ void __launch_bounds__(kBatchPairs) pair_qp_batch_kernel(int n_pairs,
             for (int c = 0; c < C; ++c) rr[c] = sr.bh[c];
             for (int l = 0; l < n; ++l) {
                 float* row = tile + (rb - base + l) * RW;
+                float kk[C], ie, kn;
+#pragma unroll
+                for (int c = 0; c < C; ++c) kk[c] = row[c];
+                row_scales<C>(kk, eps, ie, kn);
                 float s = -row[DIM + 1] * z[DIM + 1];
 #pragma unroll
                 for (int c = 0; c < C; ++c) s += row[c] * z[c];
-                const float yl = fmaxf(0.f, row[DIM + 2] - s * row[DIM + 3]);
+                const float yl = fmaxf(0.f, row[DIM + 2] - s * ie);
                 row[DIM + 2] = yl;
 #pragma unroll
                 for (int c = 0; c < C; ++c) rr[c] += yl * row[c];

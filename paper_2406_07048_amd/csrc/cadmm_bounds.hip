@@ -76,6 +76,10 @@ __global__ void __launch_bounds__(kBlock) traj_bounds_kernel(DevProblem P, int o
     __shared__ float lam[SL], rr[SL], ym[SL];
     __shared__ unsigned char act[NMAX * (NS + NU)];   // 0 free, 1 lower active, 2 upper active
     __shared__ int pidx[NS];
+    // the models of the steps in LDS (every sweep reads them step by step):
+    // one time-invariant model, or up to MCS per-step models
+    constexpr int MCS = NS <= 4 ? NMAX : 16;
+    __shared__ float Mc[MCS * (NS * NS + NS * NU)];
 
     const int s = blockIdx.x;
     if (!obstacle_free && P.done[s]) return;
@@ -89,8 +93,21 @@ __global__ void __launch_bounds__(kBlock) traj_bounds_kernel(DevProblem P, int o
     const float* Ag = sqp ? P.A_lin + (size_t)s * N * ns * ns : P.A_dyn + (size_t)s * P.dyn_ss * ns * ns;
     const float* Bg = sqp ? P.B_lin + (size_t)s * N * ns * nu : P.B_dyn + (size_t)s * P.dyn_ss * ns * nu;
     const int mts = sqp ? 1 : P.dyn_ts;
-    auto Am = [&](int t, int i, int j) { return Ag[(size_t)t * mts * ns * ns + i * ns + j]; };
-    auto Bm = [&](int t, int i, int j) { return Bg[(size_t)t * mts * ns * nu + i * nu + j]; };
+    const int msz = ns * ns + ns * nu;               // floats of one cached model
+    const int n_mod = mts == 0 ? 1 : N;
+    const bool cached = n_mod <= MCS;
+    if (cached) {
+        for (int e = threadIdx.x; e < n_mod * msz; e += kBlock) {
+            const int t = e / msz, q = e % msz;
+            Mc[e] = q < ns * ns ? Ag[(size_t)t * mts * ns * ns + q] : Bg[(size_t)t * mts * ns * nu + (q - ns * ns)];
+        }
+    }
+    auto Am = [&](int t, int i, int j) {
+        return cached ? Mc[(mts ? t : 0) * msz + i * ns + j] : Ag[(size_t)t * mts * ns * ns + i * ns + j];
+    };
+    auto Bm = [&](int t, int i, int j) {
+        return cached ? Mc[(mts ? t : 0) * msz + ns * ns + i * nu + j] : Bg[(size_t)t * mts * ns * nu + i * nu + j];
+    };
     float* xo = P.x + (size_t)s * (N + 1) * ns;
     float* uo = P.u + (size_t)s * N * nu;
     auto zval = [&](int v) -> float {
@@ -134,7 +151,10 @@ __global__ void __launch_bounds__(kBlock) traj_bounds_kernel(DevProblem P, int o
     int pid;
     worst_bound(sl, pid);
     if (!(sl < INFINITY)) {
-        if (lane == 0) P.bstat[s] = 0;
+        if (lane == 0) {
+            P.bstat[s] = 0;
+            P.bprev[(size_t)s * (SL + 1)] = 0;
+        }
         return;
     }
 
@@ -241,7 +261,95 @@ __global__ void __launch_bounds__(kBlock) traj_bounds_kernel(DevProblem P, int o
         }
     }
 
-    // 2. dual active-set steps
+    // 2. the directions of the bounds active at the end of the previous
+    //    trajectory QP (usually the ones this one needs), all in one sweep
+    //    pair: the recursion of the single sweep below run on k right-hand
+    //    sides at once, in the same order of operations (bitwise the same
+    //    directions). The backward pass leaves the feedforward of step t in
+    //    the input part of each direction's slot, which the forward pass
+    //    overwrites with the inputs.
+    __shared__ int cid[SL];                 // bound ids of the precomputed directions
+    float* Wc = P.bW + ((size_t)P.n_scen + s) * SL * nv;   // their slots
+    int nC = P.bprev[(size_t)s * (SL + 1)];
+    if (nC < 0 || nC > SL) nC = 0;
+    if (lane < nC) cid[lane] = P.bprev[(size_t)s * (SL + 1) + 1 + lane];
+    __syncthreads();
+    if (nC > 0) {
+        float* Pk = LM;                      // [ns][SL], then [ns][SL] (double buffer)
+        float* Pk2 = LM + NS * SL;
+        float* BK = LM + 2 * NS * SL;        // [nu][SL]
+        auto dvar = [&](int j) { return cid[j] >> 1; };
+        auto dsg = [&](int j) { return (cid[j] & 1) ? -1.f : 1.f; };
+        // p_N: the state directions at x_N
+        for (int e = lane; e < ns * nC; e += kBlock) {
+            const int i = e / nC, j = e % nC, v = dvar(j);
+            Pk[i * SL + j] = (V.is_state(v) && v / ns + 1 == N && v % ns == i) ? -dsg(j) : 0.f;
+        }
+        __syncthreads();
+        for (int t = N - 1; t >= 0; --t) {
+            for (int e = lane; e < nu * nC; e += kBlock) {
+                const int c = e / nC, j = e % nC;
+                float acc = 0.f;
+                for (int r = 0; r < ns; ++r) acc += Bm(t, r, c) * Pk[r * SL + j];
+                BK[c * SL + j] = acc;
+            }
+            __syncthreads();
+            for (int e = lane; e < nu * nC; e += kBlock) {
+                const int c = e / nC, j = e % nC, v = dvar(j);
+                float acc = 0.f;
+                for (int m = 0; m < nu; ++m) acc -= Qi[t][c * NU + m] * BK[m * SL + j];
+                if (!V.is_state(v) && (v - N * ns) / nu == t) acc += dsg(j) * Qi[t][c * NU + (v - N * ns) % nu];
+                Wc[(size_t)j * nv + N * ns + t * nu + c] = acc;
+            }
+            if (t >= 1) {
+                for (int e = lane; e < ns * nC; e += kBlock) {
+                    const int i = e / nC, j = e % nC, v = dvar(j);
+                    float pn = 0.f;
+                    for (int r = 0; r < ns; ++r) pn += Am(t, r, i) * Pk[r * SL + j];
+                    for (int m = 0; m < nu; ++m) pn += Kf[t][m * NS + i] * BK[m * SL + j];
+                    if (!V.is_state(v) && (v - N * ns) / nu == t) pn += -dsg(j) * Kf[t][((v - N * ns) % nu) * NS + i];
+                    if (V.is_state(v) && v / ns + 1 == t && v % ns == i) pn += -dsg(j);
+                    Pk2[i * SL + j] = pn;
+                }
+            }
+            __syncthreads();
+            if (t >= 1)
+                for (int e = lane; e < ns * nC; e += kBlock) Pk[(e / nC) * SL + e % nC] = Pk2[(e / nC) * SL + e % nC];
+            __threadfence_block();
+            __syncthreads();
+        }
+        // forward: dx_0 = 0
+        float* DX = Pk;
+        float* DX2 = Pk2;
+        for (int e = lane; e < ns * nC; e += kBlock) DX[(e / nC) * SL + e % nC] = 0.f;
+        __syncthreads();
+        for (int t = 0; t < N; ++t) {
+            for (int e = lane; e < nu * nC; e += kBlock) {
+                const int c = e / nC, j = e % nC;
+                float* slot = Wc + (size_t)j * nv + N * ns + t * nu + c;
+                float acc = *slot;
+                for (int i = 0; i < ns; ++i) acc += Kf[t][c * NS + i] * DX[i * SL + j];
+                BK[c * SL + j] = acc;
+                *slot = acc;
+            }
+            __syncthreads();
+            for (int e = lane; e < ns * nC; e += kBlock) {
+                const int i = e / nC, j = e % nC;
+                float xn = 0.f;
+                for (int r = 0; r < ns; ++r) xn += Am(t, i, r) * DX[r * SL + j];
+                for (int m = 0; m < nu; ++m) xn += Bm(t, i, m) * BK[m * SL + j];
+                DX2[i * SL + j] = xn;
+                Wc[(size_t)j * nv + t * ns + i] = xn;
+            }
+            __syncthreads();
+            for (int e = lane; e < ns * nC; e += kBlock) DX[(e / nC) * SL + e % nC] = DX2[(e / nC) * SL + e % nC];
+            __syncthreads();
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+
+    // 3. dual active-set steps
     float* W = P.bW + (size_t)s * SL * nv;     // slot i: the direction of active bound i
     int nA = 0, status = 0, steps = 0;
     const int cap = 4 * SL + 2 * nv;
@@ -252,6 +360,15 @@ __global__ void __launch_bounds__(kBlock) traj_bounds_kernel(DevProblem P, int o
             if (nA > 0 || steps > 0) worst_bound(sl, pid);
             if (!(sl < INFINITY)) break;
             lam_p = 0.f;
+            // a direction of the previous active set
+            const unsigned long long hit = __ballot(lane < nC && cid[lane] == pid);
+            if (hit) {
+                const int j = __builtin_ctzll(hit);
+                for (int v = lane; v < nv; v += kBlock) wl[v] = Wc[(size_t)j * nv + v];
+                __syncthreads();
+                have_dir = true;
+                continue;
+            }
             // direction w = sg G^{-1} e_v: the LQ solution for the linear cost
             // -sg e_v (zero initial state, no offsets)
             const int v = pid >> 1;
@@ -426,6 +543,10 @@ __global__ void __launch_bounds__(kBlock) traj_bounds_kernel(DevProblem P, int o
     for (int e = lane + ns; e < (N + 1) * ns; e += kBlock) xo[e] = xs[e];
     for (int e = lane; e < N * nu; e += kBlock) uo[e] = us[e];
     if (lane == 0) P.bstat[s] = status < 0 ? status : nA;
+    // the final active set, whose directions the next trajectory QP computes first
+    const int keep = status < 0 ? 0 : nA;
+    if (lane < keep) P.bprev[(size_t)s * (SL + 1) + 1 + lane] = av[lane];
+    if (lane == 0) P.bprev[(size_t)s * (SL + 1)] = keep;
 }
 
 bool bounds_supported(int n_s, int n_u) { return n_s <= 12 && n_u <= 4; }

@@ -49,7 +49,7 @@ struct Layout {
     size_t contrib, rdual_part, rpri_part, unconv_part;
     size_t r_pri, r_dual, done, iters, unconv, hist_pri, hist_dual, alpha, cost, min_alpha;
     int has_bounds;
-    size_t blim, hq_b, bW, bstat;
+    size_t blim, hq_b, bW, bstat, bprev;
     size_t total;
 };
 
@@ -234,8 +234,9 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
     L.has_bounds = has_bounds;
     L.blim = take(off, sizeof(float) * 2 * (ns + nu));
     L.hq_b = take(off, has_bounds ? sizeof(float) * (size_t)d->n_scen * N * L.nc : 0);
-    L.bW = take(off, has_bounds ? sizeof(float) * (size_t)d->n_scen * kBoundSlots * N * (ns + nu) : 0);
+    L.bW = take(off, has_bounds ? sizeof(float) * 2 * (size_t)d->n_scen * kBoundSlots * N * (ns + nu) : 0);
     L.bstat = take(off, sizeof(int) * d->n_scen);
+    L.bprev = take(off, sizeof(int) * (size_t)d->n_scen * (kBoundSlots + 1));
     L.alpha = take(off, sizeof(float) * std::max<long long>(L.n_pairs, 1));
     L.cost = take(off, sizeof(float) * d->n_scen);
     L.min_alpha = take(off, sizeof(float) * d->n_scen);
@@ -473,6 +474,7 @@ int init_iterate(cadmm_handle* h)
     HIP_TRY(launch_fill(at<float>(h, L.hist_pri), (long long)kHistCap * L.n_scen, NAN, st));
     HIP_TRY(launch_fill(at<float>(h, L.hist_dual), (long long)kHistCap * L.n_scen, NAN, st));
     HIP_TRY(launch_fill_int(at<int>(h, L.bstat), L.n_scen, 0, st));
+    HIP_TRY(launch_fill_int(at<int>(h, L.bprev), (long long)L.n_scen * (kBoundSlots + 1), 0, st));
     HIP_TRY(launch_traj_phase(h->P, 1, st));
     if (L.n_blocks > 0) HIP_TRY(launch_init_pairs(h->P, nullptr, 1, st));
     return CADMM_OK;
@@ -742,6 +744,7 @@ int collision_admm_setup(const cadmm_desc* d, void* d_ws, size_t bytes, hipStrea
     P.hq_b = L.has_bounds ? at<float>(h, L.hq_b) : nullptr;
     P.bW = L.has_bounds ? at<float>(h, L.bW) : nullptr;
     P.bstat = at<int>(h, L.bstat);
+    P.bprev = at<int>(h, L.bprev);
 
     h->G = d->lanes_per_pair > 0 ? d->lanes_per_pair : 1;
     if ((rc = upload_worklists(h, d->waves_per_group > 0 ? d->waves_per_group : 1))) return bail(rc);

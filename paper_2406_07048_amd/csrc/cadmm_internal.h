@@ -75,7 +75,9 @@ struct DevProblem {
     const float* ulo;
     const float* uhi;
     float* hq_b;                 // [n_scen][N][nc] stage sums of the last trajectory QP
-    float* bW;                   // [n_scen][kBoundSlots][N (n_s + n_u)] active-bound directions
+    float* bW;                   // [2 n_scen][kBoundSlots][N (n_s + n_u)] active-bound directions, then
+                                 // the precomputed directions of the previous active sets
+    int* bprev;                  // [n_scen][kBoundSlots + 1] the previous active set (count, bound ids)
     int* bstat;                  // [n_scen] active bounds, or < 0 (see traj_bounds_kernel)
 };
 
