@@ -33,6 +33,7 @@ int fail(int code, const std::string& msg)
 
 constexpr int kHistCap = 4096;
 constexpr int kGraphBlock = 8;    // iterations per captured multi-iteration graph
+constexpr int kPreSumWorkgroups = 128;   // workgroups per scenario from which the sums get their own kernel
 constexpr int kTuneWarmIters = 16; // iterations run before the launch shapes are timed
 
 struct Layout {
@@ -49,7 +50,7 @@ struct Layout {
     size_t contrib, rdual_part, rpri_part, unconv_part;
     size_t r_pri, r_dual, done, iters, unconv, hist_pri, hist_dual, alpha, cost, min_alpha;
     int has_bounds;
-    size_t blim, hq_b, bW, bstat, bprev;
+    size_t blim, hq_b, bW, bstat, bprev, hq_pre;
     size_t total;
 };
 
@@ -237,6 +238,7 @@ int validate_and_plan(const cadmm_desc* d, Layout& L)
     L.bW = take(off, has_bounds ? sizeof(float) * 2 * (size_t)d->n_scen * kBoundSlots * N * (ns + nu) : 0);
     L.bstat = take(off, sizeof(int) * d->n_scen);
     L.bprev = take(off, sizeof(int) * (size_t)d->n_scen * (kBoundSlots + 1));
+    L.hq_pre = take(off, sizeof(float) * (size_t)d->n_scen * N * L.nc);
     L.alpha = take(off, sizeof(float) * std::max<long long>(L.n_pairs, 1));
     L.cost = take(off, sizeof(float) * d->n_scen);
     L.min_alpha = take(off, sizeof(float) * d->n_scen);
@@ -300,6 +302,10 @@ int upload_worklists(cadmm_handle* h, int W)
     HIP_TRY(hipStreamSynchronize(h->stream));
     h->W = W;
     h->P.n_wg = (int)items.size();
+    // scenarios with many pair-phase workgroups: their per-step sums are
+    // spread over many workgroups by a kernel of their own (one trajectory
+    // workgroup reading every partial would be bound by one CU's bandwidth)
+    h->P.hq_pre = h->P.n_wg >= kPreSumWorkgroups * h->L.n_scen ? at<float>(h, h->L.hq_pre) : nullptr;
     h->grid = std::max(1, h->P.n_wg);
     return CADMM_OK;
 }

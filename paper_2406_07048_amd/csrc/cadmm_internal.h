@@ -78,6 +78,10 @@ struct DevProblem {
     float* bW;                   // [2 n_scen][kBoundSlots][N (n_s + n_u)] active-bound directions, then
                                  // the precomputed directions of the previous active sets
     int* bprev;                  // [n_scen][kBoundSlots + 1] the previous active set (count, bound ids)
+    // per-step sums of the pair contributions formed by a separate kernel
+    // (scenarios with many pair-phase workgroups), [n_scen][N][nc]; NULL: the
+    // trajectory kernel sums them itself
+    const float* hq_pre;
     int* bstat;                  // [n_scen] active bounds, or < 0 (see traj_bounds_kernel)
 };
 
@@ -120,7 +124,7 @@ struct PairAdjoint {
 // which is what the per-phase timings use; graphs capture plain launches.
 #define CADMM_LAUNCH(kernel, grid, block, lds, stream, ev0, ev1, ...)                                 \
     do {                                                                                           \
-        if (ev0) hipExtLaunchKernelGGL(kernel, grid, block, lds, stream, ev0, ev1, 0, __VA_ARGS__); \
+        if (ev0 || ev1) hipExtLaunchKernelGGL(kernel, grid, block, lds, stream, ev0, ev1, 0, __VA_ARGS__); \
         else hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);                     \
     } while (0)
 

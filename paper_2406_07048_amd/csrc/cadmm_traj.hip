@@ -588,7 +588,15 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         }
         for (int e = tid; e < N * NS; e += TT) off[e] = 0.f;
     } else {
-        if (!obstacle_free) {
+        if (!obstacle_free && P.hq_pre) {
+            // summed beforehand across many workgroups (sum_partials_kernel)
+            for (int e = tid; e < N * nc; e += TT) {
+                const float v = P.hq_pre[(size_t)s * N * nc + e];
+                Hq[e] = v;
+                if (hq_save) hq_save[(size_t)s * N * nc + e] = v;
+                if (P.hq_b) P.hq_b[(size_t)s * N * nc + e] = v;
+            }
+        } else if (!obstacle_free) {
             // four steps per output, the partials summed as float4
             const int N4 = (N + 3) / 4;
             split_sums<TT>(
@@ -1037,6 +1045,43 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     if (tid < ns) TA.gx0[(size_t)s * ns + tid] += (double)xbuf[cur][tid];
 }
 
+// Per-step sums of the pair contributions of scenarios with many pair-phase
+// workgroups, spread over many workgroups instead of the one of the
+// trajectory kernel (which then reads the sums): workgroup (s, c) sums
+// coordinate c of every step over the scenario's workgroup partials, wave q
+// the workgroups w = first + q (mod 16) in order, the 16 wave partials then
+// in order (a fixed order: runs are bitwise repeatable).
+constexpr int kSumWaves = 16;
+__global__ void __launch_bounds__(64 * kSumWaves) sum_partials_kernel(DevProblem P, float* out)
+{
+    __shared__ float red[kSumWaves][64];
+    const int s = blockIdx.x / P.nc, c = blockIdx.x % P.nc;
+    const int q = threadIdx.x / 64, t = threadIdx.x % 64;
+    const int2 wr = P.scen_wg[s];
+    float acc = 0.f;
+    if (!P.done[s] && t < P.N) {
+        // eight loads in flight ahead of their adds (same order of the adds)
+        const float* src = P.contrib + (size_t)c * 64 + t;
+        const size_t ws = (size_t)P.nc * 64;
+        int w = wr.x + q;
+        for (; w + 7 * kSumWaves < wr.y; w += 8 * kSumWaves) {
+            float a[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a[k] = src[(size_t)(w + k * kSumWaves) * ws];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc += a[k];
+        }
+        for (; w < wr.y; w += kSumWaves) acc += src[(size_t)w * ws];
+    }
+    red[q][t] = acc;
+    __syncthreads();
+    if (q == 0 && t < P.N && !P.done[s]) {
+        float v = red[0][t];
+        for (int k = 1; k < kSumWaves; ++k) v += red[k][t];
+        out[((size_t)s * P.N + t) * P.nc + c] = v;
+    }
+}
+
 template <bool ADJ, bool TV>
 static hipError_t launch_traj_tv(const DevProblem& P, int obstacle_free, float* hq_save, const TrajAdjoint& TA,
                                  hipStream_t st, hipEvent_t e0, hipEvent_t e1)
@@ -1084,12 +1129,20 @@ static hipError_t launch_traj(const DevProblem& P, int obstacle_free, float* hq_
 hipError_t launch_traj_phase(const DevProblem& P, int obstacle_free, hipStream_t st, float* hq_save, hipEvent_t e0,
                              hipEvent_t e1)
 {
-    if (!P.has_bounds) return launch_traj<false>(P, obstacle_free, hq_save, TrajAdjoint{}, st, e0, e1);
-    // with bounds the unconstrained minimiser is moved to the bounded one by a
-    // second kernel; the events then bracket both
-    const hipError_t err = launch_traj<false>(P, obstacle_free, hq_save, TrajAdjoint{}, st, e0, nullptr);
+    // up to three kernels (the per-step sums spread over many workgroups, the
+    // sweep, the bounded QP); the events bracket all of them
+    const bool pre = P.hq_pre && !obstacle_free;
+    if (pre) {
+        const dim3 g(P.n_scen * P.nc), b(64 * kSumWaves);
+        CADMM_LAUNCH(sum_partials_kernel, g, b, 0, st, e0, nullptr, P, const_cast<float*>(P.hq_pre));
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    hipEvent_t t0 = pre ? nullptr : e0;
+    if (!P.has_bounds) return launch_traj<false>(P, obstacle_free, hq_save, TrajAdjoint{}, st, t0, e1);
+    const hipError_t err = launch_traj<false>(P, obstacle_free, hq_save, TrajAdjoint{}, st, t0, nullptr);
     if (err != hipSuccess) return err;
-    return launch_traj_bounds(P, obstacle_free, st, e0 ? e1 : nullptr);
+    return launch_traj_bounds(P, obstacle_free, st, e1);
 }
 
 hipError_t launch_traj_adjoint(const DevProblem& P, const TrajAdjoint& TA, hipStream_t st)
