@@ -407,6 +407,204 @@ __device__ __forceinline__ void rollout_scan_42(const float* A, const float* B, 
     }
 }
 
+// Riccati sweep for 12 states and 4 inputs in one wave, on 16 x 16 x 4
+// FP32 matrix-core tiles (v_mfma_f32_16x16x4f32): no barrier per step. With
+// M = [A | B] (12 x 16, zero rows 12-15) and the value function held as the
+// 16 x 16 tile P^ (P_{t+1} in rows/columns 0-11, p_{t+1} in column 12), a
+// step is
+//   W  = P^T M,                                   (4 products)
+//   Z1 = blkdiag(H_t, 2Q_u) + M^T W,              (4)
+//   Z2 = [H_t | (h_t; r_t)] + W^T [M_x | f^],     (4; f^ = (f_t, 1, 0, 0, 0))
+// so that Z1 holds Quu and Qux (rows 12-15), Z2 column 12 holds
+// qx = h_t + A^T w and qu = r_t + B^T w with w = P f_t + p (row 12 of W is
+// p^T M), and 1/2 (Z1 + Z2) is Qxx exactly symmetric (the two products take
+// the same multiplications in the same order, transposed); then the gains
+// [K | k] = -Quu^{-1} [Qux | qu] by the 2 x 2 block inverse of Quu (its upper
+// triangle, read once per step by every lane; 16 dependent operations where a
+// Cholesky factor and two triangular solves take about 40) and
+//   P^_t = [Qxx qx] + Qux^T [K | k]               (4, rank 4 in row 3 only).
+// Tile layouts of the 16 x 16 x 4 product D = C + A B: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16], and holds D[4 (l / 16) + r][l % 16]
+// in register r. Slice s of each product pairs register s of an accumulator
+// (k = 4 (l / 16) + s) with the matching entry of M, so a result feeds the
+// next product without moving between lanes. The asymmetry that rounding
+// leaves in P^ is dropped by the next step's 1/2 (Z1 + Z2).
+// Rows 12-15 and columns 13-15 of P^ and W, and columns 13-15 of Z2, carry
+// finite values formed anew each step that meet only the zero rows of M
+// (and of f^), so they are left unmasked.
+// Gains go to Kall[t][4][13] (the other lanes' columns to kdump, 256
+// floats); the step terms of step t - 2 (and, TV, the model, from global
+// memory) load while step t computes.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <bool ADJ, bool TV>
+__device__ __forceinline__ void riccati_mfma_124(const float* A, const float* B, const float* Ag, const float* Bg,
+                                                 int astride, int bstride, int ns, int nu, const float* Q2,
+                                                 const float* R2, const int* hmap, const int* gmap, const float* Hq,
+                                                 const float* qr, const float* rin, const float* off, float* Kall,
+                                                 float* kdump, int N, int nc)
+{
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+    const bool c12 = c == 12, r3 = g == 3;
+    // lane constants: 2Q_s and 2Q_u entries, the pose-sum maps (masks 0 / 1
+    // and in-range indices) of H_t (rows/columns 0-11) and h_t (column 12)
+    float q2[4], r2[4], hmk[4], gmk[4];
+    int hmc[4], gmc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 4 * g + r;
+        const bool xx = row < 12 && c < 12;
+        const int hm = xx ? hmap[row * 12 + c] : -1;
+        const int gm = (!ADJ && row < 12 && c12) ? gmap[row] : -1;
+        q2[r] = xx ? Q2[row * 12 + c] : 0.f;
+        r2[r] = (row >= 12 && c >= 12) ? R2[(row - 12) * 4 + (c - 12)] : 0.f;
+        hmk[r] = hm >= 0 ? 1.f : 0.f;
+        gmk[r] = gm >= 0 ? 1.f : 0.f;
+        hmc[r] = hm >= 0 ? hm : 0;
+        gmc[r] = gm >= 0 ? gm : 0;
+    }
+    // M_t[4 g + q][c] of this lane: from LDS (one model), or (TV) from
+    // A_t = Ag + t astride (n_s x n_s), B_t = Bg + t bstride (n_s x n_u),
+    // row-major, loaded from an in-range address (raw; zeroed outside the
+    // model by the step that uses it)
+    const float* mp[4];
+    int mstep[4];
+    bool mok[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k = 4 * g + q, kc = k < ns ? k : ns - 1;
+        const bool isA = c < 12;
+        const int cu = isA ? 0 : c - 12;
+        mp[q] = isA ? Ag + kc * ns + (c < ns ? c : ns - 1) : Bg + kc * nu + (cu < nu ? cu : nu - 1);
+        mstep[q] = isA ? astride : bstride;
+        mok[q] = k < ns && (isA ? c < ns : cu < nu);
+    }
+    auto load_m = [&](int t, float (&m)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * g + q;
+            if constexpr (TV) m[q] = mp[q][(size_t)t * mstep[q]];
+            else m[q] = k < 12 ? (c < 12 ? A[k * 12 + c] : B[k * 4 + (c - 12)]) : 0.f;
+        }
+    };
+    // step terms of step t from in-range addresses, raw: the pose sums of
+    // H_{t-1} and h_{t-1}, qr_{t-1}, r_t, f_t (rows 4 g .. 4 g + 3 of qr
+    // and off, and r_t, are float4s; row 3 of the wave reads rows 8-11)
+    struct Raw {
+        float h[4], gq[4];
+        float4 q, f, ri;
+    };
+    const int g4 = 4 * (g < 3 ? g : 2);
+    auto fetch = [&](int t, Raw& w) {
+        const int tp = t >= 1 ? t - 1 : 0;
+        w.q = *reinterpret_cast<const float4*>(qr + tp * 12 + g4);
+        w.f = *reinterpret_cast<const float4*>(off + t * 12 + g4);
+        w.ri = *reinterpret_cast<const float4*>(rin + t * 4);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            w.h[r] = Hq[tp * nc + hmc[r]];
+            w.gq[r] = Hq[tp * nc + gmc[r]];
+        }
+    };
+    // P^_N: the stage cost of x_N
+    v4f Pm;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 4 * g + r;
+        float v = q2[r] + hmk[r] * Hq[(N - 1) * nc + hmc[r]];
+        if (c12 && row < 12) v = qr[(N - 1) * 12 + row] + gmk[r] * Hq[(N - 1) * nc + gmc[r]];
+        Pm[r] = v;
+    }
+    auto rl = [](float v, int l) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    };
+    // steps alternate between two sets of model registers and step terms,
+    // each reloaded two steps ahead of its use
+    float MX[4], MY[4];
+    Raw RX, RY;
+    load_m(N - 1, MX);
+    if (TV) load_m(N >= 2 ? N - 2 : 0, MY);
+    fetch(N - 1, RX);
+    fetch(N >= 2 ? N - 2 : 0, RY);
+    auto step = [&](int t, float (&Mraw)[4], Raw& R) {
+        // H_t, column 12 and f^ (H_0 and h_0 are not used)
+        v4f Z1, Z2;
+        float Mc[4], B2[4];
+        {
+            const float q[4] = {R.q.x, R.q.y, R.q.z, R.q.w};
+            const float f[4] = {R.f.x, R.f.y, R.f.z, R.f.w};
+            const float ri[4] = {R.ri.x, R.ri.y, R.ri.z, R.ri.w};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float H = q2[r] + hmk[r] * R.h[r];
+                const float colv = r3 ? ri[r] : q[r] + gmk[r] * R.gq[r];
+                Z1[r] = H + r2[r];
+                Z2[r] = c12 ? colv : H;
+                Mc[r] = (!TV || mok[r]) ? Mraw[r] : 0.f;
+                const float fv = r3 ? (r == 0 ? 1.f : 0.f) : f[r];
+                B2[r] = c12 ? fv : Mc[r];
+            }
+        }
+        fetch(t >= 2 ? t - 2 : 0, R);
+        v4f W = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) W = __builtin_amdgcn_mfma_f32_16x16x4f32(Pm[q], Mc[q], W, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mc[q], W[q], Z1, 0, 0, 0);
+        // Quu^{-1} by 2 x 2 blocks, Quu = [a b; b^T d] (its upper triangle
+        // Z1[12 + i][12 + j], lane 60 + j, register i): a^{-1}, E = a^{-1} b
+        // and S^{-1} for the Schur complement S = d - b^T E; formed from Z1
+        // while the products of Z2 run
+        const float a00 = rl(Z1[0], 60), a01 = rl(Z1[0], 61), a11 = rl(Z1[1], 61);
+        const float b00 = rl(Z1[0], 62), b01 = rl(Z1[0], 63), b10 = rl(Z1[1], 62), b11 = rl(Z1[1], 63);
+        const float d00 = rl(Z1[2], 62), d01 = rl(Z1[2], 63), d11 = rl(Z1[3], 63);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Z2 = __builtin_amdgcn_mfma_f32_16x16x4f32(W[q], B2[q], Z2, 0, 0, 0);
+        if constexpr (TV) load_m(t >= 2 ? t - 2 : 0, Mraw);
+        const float ia = __builtin_amdgcn_rcpf(a00 * a11 - a01 * a01);
+        const float ai00 = a11 * ia, ai01 = -a01 * ia, ai11 = a00 * ia;
+        const float e00 = ai00 * b00 + ai01 * b10, e01 = ai00 * b01 + ai01 * b11;
+        const float e10 = ai01 * b00 + ai11 * b10, e11 = ai01 * b01 + ai11 * b11;
+        const float s00 = d00 - (b00 * e00 + b10 * e10), s01 = d01 - (b00 * e01 + b10 * e11);
+        const float s11 = d11 - (b01 * e01 + b11 * e11);
+        const float is = __builtin_amdgcn_rcpf(s00 * s11 - s01 * s01);
+        const float si00 = s11 * is, si01 = -s01 * is, si11 = s00 * is;
+        // column c of -Quu^{-1} [Qux | qu] in row 3 of the wave (Qux column
+        // c in Z1, qu in Z2 at c = 12; the other lanes' columns are unused):
+        // y = a^{-1} v_1, z = S^{-1} (v_2 - b^T y), x = y - E z
+        float v[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) v[a] = c12 ? Z2[a] : Z1[a];
+        const float y0 = ai00 * v[0] + ai01 * v[1], y1 = ai01 * v[0] + ai11 * v[1];
+        const float rr0 = v[2] - (b00 * y0 + b10 * y1), rr1 = v[3] - (b01 * y0 + b11 * y1);
+        const float z0 = si00 * rr0 + si01 * rr1, z1 = si01 * rr0 + si11 * rr1;
+        const float x0 = y0 - (e00 * z0 + e01 * z1), x1 = y1 - (e10 * z0 + e11 * z1);
+        const float Kh[4] = {-x0, -x1, -z0, -z1};
+        {
+            // lanes 48-60 own the gain columns; the others write theirs to a
+            // slot of their own in kdump
+            const bool own = r3 && c <= 12;
+            float* Kt = own ? Kall + t * 52 + c : kdump + lane;
+            const int ks = own ? 13 : 64;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) Kt[a * ks] = Kh[a];
+        }
+        // P^_t (formed at t = 0 too, unused, so that the step has no branch)
+        v4f C3;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) C3[r] = c12 ? Z2[r] : 0.5f * (Z1[r] + Z2[r]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) C3 = __builtin_amdgcn_mfma_f32_16x16x4f32(Z1[q], r3 ? Kh[q] : 0.f, C3, 0, 0, 0);
+        Pm = C3;
+    };
+    int t = N - 1;
+    for (; t >= 1; t -= 2) {
+        step(t, MX, RX);
+        step(t - 1, TV ? MY : MX, RY);
+    }
+    if (t == 0) step(0, MX, RX);
+}
+
 // Trajectory QP of one scenario per workgroup. State/input sizes are padded
 // to the compile-time NS >= n_s, NU >= n_u with zero dynamics rows/columns
 // and an identity input-cost block, so every small product unrolls.
@@ -436,6 +634,7 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     __shared__ float Quu[NU * NU], Qux[NU * NS], qu[NU], Qxx[NS * NS], qx[NS];
     __shared__ __align__(16) float xbuf[2][NS];
     __shared__ float x0s[NS];
+    __shared__ __align__(16) float zero4[4];   // a float4 of zeros (rollout padding lanes)
     extern __shared__ __align__(16) float dyn[];
     const int s = blockIdx.x;
     if (!ADJ && !obstacle_free && P.done[s]) return;
@@ -475,7 +674,18 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         return (i < ns && c < nu) ? Bg[(size_t)t * mts * ns * nu + i * nu + c] : 0.f;
     };
 
-    // 0. padded model and cost, pose-coordinate maps
+    // 0. padded model and cost, pose-coordinate maps; per-step sums formed
+    //    beforehand across many workgroups (sum_partials_kernel) are read
+    //    here, their latency overlapping that of the staged trajectory
+    if (tid < 4) zero4[tid] = 0.f;
+    if (!ADJ && !obstacle_free && P.hq_pre) {
+        for (int e = tid; e < N * nc; e += TT) {
+            const float v = P.hq_pre[(size_t)s * N * nc + e];
+            Hq[e] = v;
+            if (hq_save) hq_save[(size_t)s * N * nc + e] = v;
+            if (P.hq_b) P.hq_b[(size_t)s * N * nc + e] = v;
+        }
+    }
     for (int e = tid; e < NS * NS; e += TT) {
         const int i = e / NS, j = e % NS;
         const bool in = i < ns && j < ns;
@@ -589,13 +799,7 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         for (int e = tid; e < N * NS; e += TT) off[e] = 0.f;
     } else {
         if (!obstacle_free && P.hq_pre) {
-            // summed beforehand across many workgroups (sum_partials_kernel)
-            for (int e = tid; e < N * nc; e += TT) {
-                const float v = P.hq_pre[(size_t)s * N * nc + e];
-                Hq[e] = v;
-                if (hq_save) hq_save[(size_t)s * N * nc + e] = v;
-                if (P.hq_b) P.hq_b[(size_t)s * N * nc + e] = v;
-            }
+            // read in step 0
         } else if (!obstacle_free) {
             // four steps per output, the partials summed as float4
             const int N4 = (N + 3) / 4;
@@ -706,6 +910,13 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         if (tid < 64) riccati_regs_42<ADJ, TV>(Am, Bm, mstride, Q2, R2, hmap, gmap, Hq, qr, rin, off, Kall, N, nc);
         __syncthreads();
         rollout_scan_42<ADJ, TT>(Am, Bm, mstride, Kall, off, x0s, reinterpret_cast<float*>(red4), dX, dU, wl, N);
+        __syncthreads();
+    } else {
+    if constexpr (NS == 12 && NU == 4) {
+        // 2. the sweep in wave 0 on matrix-core tiles
+        if (tid < 64)
+            riccati_mfma_124<ADJ, TV>(A, B, Ag, Bg, mts * ns * ns, mts * ns * nu, ns, nu, Q2, R2, hmap, gmap, Hq,
+                                      qr, rin, off, Kall, reinterpret_cast<float*>(red4), N, nc);
         __syncthreads();
     } else {
     // 2. backward Riccati sweep, V_t(x) = 1/2 x^T P x + p^T x, P_N = H_N.
@@ -883,6 +1094,7 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         if (TV && t >= 1) model_store((t - 1) & 1, next_m);
         __syncthreads();
     }
+    }
     if (cl) {
     // 3. rollout on the closed loop, dx_{t+1} = (A + B K_t) dx_t + (f_t + B k_t):
     //    the matrices of all steps are formed first, in parallel, so that a
@@ -911,15 +1123,55 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         if (ADJ) wl[tid] = 0.f;
     }
     __syncthreads();
-    for (int t = 0; t < N; ++t) {
-        if (tid < NS) {
-            const float acc = dot_lds<NS>(Acl + ((size_t)t * NS + tid) * NS, xbuf[t & 1], Ccl[t * NS + tid]);
-            xbuf[(t + 1) & 1][tid] = acc;
-            if (ADJ) wl[(t + 1) * NS + tid] = acc;
-            else dX[t * NS + tid] = acc;
+    // the steps in wave 0 on 16 x 16 x 4 matrix-core tiles, without
+    // barriers: dx_t is column 0 of the B operand (lane 16 g, register s:
+    // entry 4 g + s), so that D = [c_t | 0] + A^cl_t [dx_t | 0] leaves
+    // dx_{t+1} in the same lanes and registers; slice s takes column
+    // 4 g + s of A^cl_t (lane i + 16 g, one float4 of row i). The rows of
+    // step t + 1 load while step t computes.
+    if (tid < 64) {
+        typedef float v4r __attribute__((ext_vector_type(4)));
+        const int ci = tid & 15, gi = tid >> 4;
+        const bool arow = ci < NS && 4 * gi < NS;
+        const bool xl = ci == 0 && 4 * gi < NS;
+        // lanes outside the tile read the zero block (stride 0)
+        const float* abase = arow ? Acl + ci * NS + 4 * gi : zero4;
+        const float* cbase = xl ? Ccl + 4 * gi : zero4;
+        const int astr = arow ? NS * NS : 0, cstr = xl ? NS : 0;
+        struct Row {
+            float4 a, c;
+        };
+        auto load = [&](int t, Row& r) {
+            const int tc = t < N ? t : N - 1;
+            r.a = *reinterpret_cast<const float4*>(abase + (size_t)tc * astr);
+            r.c = *reinterpret_cast<const float4*>(cbase + tc * cstr);
+        };
+        float xb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xb[q] = xl ? xbuf[0][4 * gi + q] : 0.f;
+        Row RA, RB;
+        load(0, RA);
+        load(1, RB);
+        auto step = [&](int t, Row& R) {
+            const float a[4] = {R.a.x, R.a.y, R.a.z, R.a.w};
+            v4r acc = {R.c.x, R.c.y, R.c.z, R.c.w};
+            load(t + 2, R);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], xb[q], acc, 0, 0, 0);
+            // lanes 0, 16, 32 (and 48 when NS = 16) own dx_{t+1}
+            float* o = ADJ ? wl + (t + 1) * NS + 4 * gi : dX + t * NS + 4 * gi;
+            if (xl) *reinterpret_cast<float4*>(o) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xb[q] = acc[q];
+        };
+        int t = 0;
+        for (; t + 1 < N; t += 2) {
+            step(t, RA);
+            step(t + 1, RB);
         }
-        __syncthreads();
+        if (t < N) step(t, RA);
     }
+    __syncthreads();
     if (!ADJ) {
         for (int e = tid; e < N * NU; e += TT) {
             const int t = e / NU, c = e % NU;
