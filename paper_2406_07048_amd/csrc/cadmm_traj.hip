@@ -55,12 +55,14 @@ __host__ __device__ constexpr int al4(int n) { return (n + 3) & ~3; }
 
 // The last region holds the chunk sums of the per-step sums (4 TT floats),
 // and afterwards, for the closed-loop rollout (cl), A + B K_t and f_t + B k_t
-// of every step (N NS (NS + 1) floats).
+// of every step (N NS (NS + 1) floats; at NS = 12 as 12 x 16 rows of the
+// homogeneous maps, N 192 floats).
 // Time-varying models on the register path (4/2) add the padded A_t, B_t of
 // every step ([N][24] floats).
 __host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bool adj, bool cl, bool tv = false)
 {
-    const int tail = cl && N * NS * (NS + 1) > 4 * traj_threads(NS, NU) ? N * NS * (NS + 1) : 4 * traj_threads(NS, NU);
+    const int clf = NS == 12 ? N * 12 * 16 : N * NS * (NS + 1);
+    const int tail = cl && clf > 4 * traj_threads(NS, NU) ? clf : 4 * traj_threads(NS, NU);
     return al4(N * nc) + al4(N * NS) + al4(traj_gain_floats(N, NS, NU)) + al4(N * NU) + al4(N * NS) +
            (adj ? al4((N + 1) * NS) : 0) + (tv && NS == 4 ? al4(N * 24) : 0) + tail;
 }
@@ -635,6 +637,8 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     __shared__ __align__(16) float xbuf[2][NS];
     __shared__ float x0s[NS];
     __shared__ __align__(16) float zero4[4];   // a float4 of zeros (rollout padding lanes)
+    __shared__ __align__(16) float one4[4];    // (1, 0, 0, 0): row 12 of a homogeneous map
+    __shared__ float xst[4][16];               // homogeneous start states of the rollout chunks
     extern __shared__ __align__(16) float dyn[];
     const int s = blockIdx.x;
     if (!ADJ && !obstacle_free && P.done[s]) return;
@@ -677,7 +681,10 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
     // 0. padded model and cost, pose-coordinate maps; per-step sums formed
     //    beforehand across many workgroups (sum_partials_kernel) are read
     //    here, their latency overlapping that of the staged trajectory
-    if (tid < 4) zero4[tid] = 0.f;
+    if (tid < 4) {
+        zero4[tid] = 0.f;
+        one4[tid] = tid == 0 ? 1.f : 0.f;
+    }
     if (!ADJ && !obstacle_free && P.hq_pre) {
         for (int e = tid; e < N * nc; e += TT) {
             const float v = P.hq_pre[(size_t)s * N * nc + e];
@@ -1095,22 +1102,156 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         __syncthreads();
     }
     }
-    if (cl) {
+    if (cl && NS == 12) {
+    // 3. rollout on the closed loop, dx_{t+1} = (A + B K_t) dx_t + (f_t + B k_t),
+    //    in four chunks of the horizon on four waves (one per SIMD):
+    //    (a) the maps of all steps as homogeneous tiles G_t = [A + B K_t,
+    //        f_t + B k_t; 0 1] (13 x 13 in 16 x 16; rows 0-11 stored, 16
+    //        floats each), in parallel;
+    //    (b) each wave multiplies out its chunk, Phi = G_{e-1} ... G_s, on
+    //        16 x 16 x 4 matrix-core tiles (Phi in the accumulator layout,
+    //        which is the B-operand layout of the next product);
+    //    (c) the chunk start states x_{s_{w+1}} = Phi_w x_{s_w}, chunk by
+    //        chunk (a row sum of the accumulator layout, three barriers);
+    //    (d) each wave steps its chunk out from its start state, x in column
+    //        0 of the B operand (lane 16 g, register q: entry 4 g + q), the
+    //        result landing in the same lanes and registers.
+    //    The inputs du_t = K_t dx_t + k_t follow in parallel over t.
+    float* Gh = reinterpret_cast<float*>(red4);           // [N][12][16]
+    {
+        constexpr int NE = 12 * 16, TS = TT / NE;
+        const int r = tid % NE, t0 = tid / NE;
+        const int i = r / 16, j = r % 16;
+        float Bi[NU];
+#pragma unroll
+        for (int c = 0; c < NU; ++c) Bi[c] = B[i * NU + c];
+        const float Aij = j < NS ? A[i * NS + j] : 0.f;
+        for (int t = t0; t0 < TS && t < N; t += TS) {
+            float acc = 0.f;
+            if (j <= NS) {
+                const float* Kt = Kall + (size_t)t * NU * NSU + j;
+                acc = j < NS ? (TV ? Aat(t, i, j) : Aij) : off[t * NS + i];
+#pragma unroll
+                for (int c = 0; c < NU; ++c) acc += (TV ? Bat(t, i, c) : Bi[c]) * Kt[c * NSU];
+            }
+            Gh[((size_t)t * 12 + i) * 16 + j] = acc;
+        }
+    }
+    if (tid < 16) {
+        float v = tid == NS ? 1.f : 0.f;
+        if (!ADJ && tid < ns) {
+            const float x0v = P.x0[(size_t)s * ns + tid];
+            v = dev ? x0v - xo[tid] : x0v;
+        }
+        xst[0][tid] = v;
+        if (tid < NS) x0s[tid] = v;
+        if (ADJ && tid < NS) wl[tid] = 0.f;
+    }
+    __syncthreads();
+    {
+        typedef float v4h __attribute__((ext_vector_type(4)));
+        constexpr int NCH = 4;
+        const int w = tid >> 6, ci = tid & 15, gi = (tid >> 4) & 3;
+        const int cs = (w * N) / NCH, ce = ((w + 1) * N) / NCH;
+        // lane (i + 16 g) of the A operand: row i, columns 4 g .. 4 g + 3 of G_t
+        const float* gbase = ci < 12 ? Gh + ci * 16 + 4 * gi : ((ci == 12 && gi == 3) ? one4 : zero4);
+        const int gstr = ci < 12 ? 12 * 16 : 0;
+        auto gload = [&](int t) { return *reinterpret_cast<const float4*>(gbase + (size_t)t * gstr); };
+        v4h Phi;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Phi[q] = 4 * gi + q == ci ? 1.f : 0.f;
+        if (w < NCH && cs < ce) {
+            float4 gn = gload(cs);
+            for (int t = cs; t < ce; ++t) {
+                const float a[4] = {gn.x, gn.y, gn.z, gn.w};
+                gn = gload(t + 1 < ce ? t + 1 : t);
+                v4h acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], Phi[q], acc, 0, 0, 0);
+                Phi = acc;
+            }
+        }
+        for (int c2 = 0; c2 < NCH - 1; ++c2) {
+            if (c2 > 0) __syncthreads();
+            if (w == c2) {
+                // (Phi x)[4 g + q] = sum_j Phi[4 g + q][j] x_j: lane (j + 16 g)
+                // holds Phi[4 g + q][j]; sums over the 16 lanes of a row
+                const float xj = xst[c2][ci];
+                float p[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float v = Phi[q] * xj;
+                    v += row_ror<8>(v);
+                    v += row_ror<4>(v);
+                    v += row_ror<2>(v);
+                    v += row_ror<1>(v);
+                    p[q] = v;
+                }
+                if (ci == 0) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) xst[c2 + 1][4 * gi + q] = p[q];
+                }
+            }
+        }
+        __syncthreads();
+        if (w < NCH && cs < ce) {
+            float xb[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) xb[q] = ci == 0 ? xst[w][4 * gi + q] : 0.f;
+            float4 gn = gload(cs);
+            for (int t = cs; t < ce; ++t) {
+                const float a[4] = {gn.x, gn.y, gn.z, gn.w};
+                gn = gload(t + 1 < ce ? t + 1 : t);
+                v4h acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], xb[q], acc, 0, 0, 0);
+                if (ci == 0 && gi < 3) {
+                    float* o = ADJ ? wl + (t + 1) * NS + 4 * gi : dX + t * NS + 4 * gi;
+                    *reinterpret_cast<float4*>(o) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) xb[q] = acc[q];
+            }
+        }
+    }
+    __syncthreads();
+    if (!ADJ) {
+        for (int e = tid; e < N * NU; e += TT) {
+            const int t = e / NU, c = e % NU;
+            const float* Kt = Kall + (size_t)t * NU * NSU + c * NSU;
+            const float* xt = t == 0 ? x0s : dX + (t - 1) * NS;
+            float u = Kt[NS];
+#pragma unroll
+            for (int k2 = 0; k2 < NS; ++k2) u += Kt[k2] * xt[k2];
+            dU[e] = u;
+        }
+        __syncthreads();
+    }
+    } else if (cl) {
     // 3. rollout on the closed loop, dx_{t+1} = (A + B K_t) dx_t + (f_t + B k_t):
     //    the matrices of all steps are formed first, in parallel, so that a
     //    step is one float4 dot product per state (thread i owns dx_i); the
     //    inputs du_t = K_t dx_t + k_t follow in parallel over t.
     float* Acl = reinterpret_cast<float*>(red4);          // [N][NS][NS]
     float* Ccl = Acl + (size_t)N * NS * NS;               // [N][NS]
-    for (int e = tid; e < N * NS * (NS + 1); e += TT) {
-        const int t = e / (NS * (NS + 1)), r = e % (NS * (NS + 1));
-        const int i = r / (NS + 1), j = r % (NS + 1);     // j = NS: the offset
-        const float* Kt = Kall + (size_t)t * NU * NSU;
-        float acc = j < NS ? (TV ? Aat(t, i, j) : A[i * NS + j]) : off[t * NS + i];
+    {
+        // thread -> entry (i, j) of every step t = t0, t0 + TS, ... (j = NS:
+        // the offset), the one-model rows of A and B in registers
+        constexpr int NE = NS * (NS + 1), TS = TT / NE;
+        const int r = tid % NE, t0 = tid / NE;
+        const int i = r / (NS + 1), j = r % (NS + 1);
+        float Bi[NU];
 #pragma unroll
-        for (int c = 0; c < NU; ++c) acc += (TV ? Bat(t, i, c) : B[i * NU + c]) * Kt[c * NSU + j];
-        if (j < NS) Acl[((size_t)t * NS + i) * NS + j] = acc;
-        else Ccl[t * NS + i] = acc;
+        for (int c = 0; c < NU; ++c) Bi[c] = B[i * NU + c];
+        const float Aij = j < NS ? A[i * NS + j] : 0.f;
+        for (int t = t0; t0 < TS && t < N; t += TS) {
+            const float* Kt = Kall + (size_t)t * NU * NSU + j;
+            float acc = j < NS ? (TV ? Aat(t, i, j) : Aij) : off[t * NS + i];
+#pragma unroll
+            for (int c = 0; c < NU; ++c) acc += (TV ? Bat(t, i, c) : Bi[c]) * Kt[c * NSU];
+            if (j < NS) Acl[((size_t)t * NS + i) * NS + j] = acc;
+            else Ccl[t * NS + i] = acc;
+        }
     }
     if (tid < NS) {
         float v = 0.f;
