@@ -442,29 +442,40 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 template <bool ADJ, bool TV>
 __device__ __forceinline__ void riccati_mfma_124(const float* A, const float* B, const float* Ag, const float* Bg,
                                                  int astride, int bstride, int ns, int nu, const float* Q2,
-                                                 const float* R2, const int* hmap, const int* gmap, const float* Hq,
-                                                 const float* qr, const float* rin, const float* off, float* Kall,
-                                                 float* kdump, int N, int nc)
+                                                 const float* R2, const int* hmap, const float* Hq, const float* qx,
+                                                 const float* rin, const float* off, float* Kall, float* kdump,
+                                                 float* mlds, float* qlds, const float* zero4, const float* one4, int N,
+                                                 int nc)
 {
     const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
     const bool c12 = c == 12, r3 = g == 3;
-    // lane constants: 2Q_s and 2Q_u entries, the pose-sum maps (masks 0 / 1
-    // and in-range indices) of H_t (rows/columns 0-11) and h_t (column 12)
-    float q2[4], r2[4], hmk[4], gmk[4];
-    int hmc[4], gmc[4];
+    // lane constants: 2Q_s and 2Q_u entries; per-lane LDS byte addresses and
+    // byte strides (per step) of the step terms, lanes without a term
+    // reading a block of zeros with stride 0:
+    //   H_t - 2Q_s (rows/columns 0-11): the pose sums of step t - 1;
+    //   Z2's accumulator: column 12 h_t = qx_{t-1} (rows 0-11, the pose sums
+    //     of the gradient already in qx) and r_t (rows 12-15), elsewhere
+    //     2Q_s (this lane's slot of qlds);
+    //   column 12 of Z2's B operand, f^: f_t (rows 0-11), (1, 0, 0, 0).
+    // Z1 starts from blkdiag(2Q_s, 2Q_u) and Z2 from 2Q_s, so that
+    // 1/2 (Z1 + Z2) is exactly symmetric with 2Q_s in it.
+    v4f z1c;
+    const char* hp[4];
+    unsigned hs[4];
+    float q2[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int row = 4 * g + r;
         const bool xx = row < 12 && c < 12;
         const int hm = xx ? hmap[row * 12 + c] : -1;
-        const int gm = (!ADJ && row < 12 && c12) ? gmap[row] : -1;
         q2[r] = xx ? Q2[row * 12 + c] : 0.f;
-        r2[r] = (row >= 12 && c >= 12) ? R2[(row - 12) * 4 + (c - 12)] : 0.f;
-        hmk[r] = hm >= 0 ? 1.f : 0.f;
-        gmk[r] = gm >= 0 ? 1.f : 0.f;
-        hmc[r] = hm >= 0 ? hm : 0;
-        gmc[r] = gm >= 0 ? gm : 0;
+        z1c[r] = q2[r] + ((row >= 12 && c >= 12) ? R2[(row - 12) * 4 + (c - 12)] : 0.f);
+        hp[r] = reinterpret_cast<const char*>(hm >= 0 ? Hq + hm : zero4);
+        hs[r] = hm >= 0 ? 4u * nc : 0u;
     }
+    *reinterpret_cast<float4*>(qlds + 4 * lane) = make_float4(q2[0], q2[1], q2[2], q2[3]);
+    const char* colp = reinterpret_cast<const char*>(c12 ? (r3 ? rin : qx + 4 * g) : qlds + 4 * lane);
+    const unsigned col_t = c12 && r3 ? 16u : 0u, col_tp = c12 && !r3 ? 48u : 0u;
     // M_t[4 g + q][c] of this lane: from LDS (one model), or (TV) from
     // A_t = Ag + t astride (n_s x n_s), B_t = Bg + t bstride (n_s x n_u),
     // row-major, loaded from an in-range address (raw; zeroed outside the
@@ -489,32 +500,36 @@ __device__ __forceinline__ void riccati_mfma_124(const float* A, const float* B,
             else m[q] = k < 12 ? (c < 12 ? A[k * 12 + c] : B[k * 4 + (c - 12)]) : 0.f;
         }
     };
-    // step terms of step t from in-range addresses, raw: the pose sums of
-    // H_{t-1} and h_{t-1}, qr_{t-1}, r_t, f_t (rows 4 g .. 4 g + 3 of qr
-    // and off, and r_t, are float4s; row 3 of the wave reads rows 8-11)
+    // the B operand of Z2 = [M_x | f^]: one model keeps M in LDS (this
+    // lane's slot) so that every lane loads its operand
+    if constexpr (!TV) {
+        float m0[4];
+        load_m(0, m0);
+        *reinterpret_cast<float4*>(mlds + 4 * lane) = make_float4(m0[0], m0[1], m0[2], m0[3]);
+    }
+    const char* b2p = reinterpret_cast<const char*>(c12 ? (r3 ? one4 : off + 4 * g) : (TV ? zero4 : mlds + 4 * lane));
+    const unsigned b2s = c12 && !r3 ? 48u : 0u;
     struct Raw {
-        float h[4], gq[4];
-        float4 q, f, ri;
+        float h[4];
+        float4 col, b2;
     };
-    const int g4 = 4 * (g < 3 ? g : 2);
+    auto at = [](const char* p, unsigned i, unsigned stride) {
+        return reinterpret_cast<const float*>(p + __umul24(i, stride));
+    };
     auto fetch = [&](int t, Raw& w) {
-        const int tp = t >= 1 ? t - 1 : 0;
-        w.q = *reinterpret_cast<const float4*>(qr + tp * 12 + g4);
-        w.f = *reinterpret_cast<const float4*>(off + t * 12 + g4);
-        w.ri = *reinterpret_cast<const float4*>(rin + t * 4);
+        const unsigned tu = t, tp = t >= 1 ? t - 1 : 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            w.h[r] = Hq[tp * nc + hmc[r]];
-            w.gq[r] = Hq[tp * nc + gmc[r]];
-        }
+        for (int r = 0; r < 4; ++r) w.h[r] = *at(hp[r], tp, hs[r]);
+        w.col = *reinterpret_cast<const float4*>(at(colp, tu, col_t) + __umul24(tp, col_tp) / 4);
+        w.b2 = *reinterpret_cast<const float4*>(at(b2p, tu, b2s));
     };
     // P^_N: the stage cost of x_N
     v4f Pm;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int row = 4 * g + r;
-        float v = q2[r] + hmk[r] * Hq[(N - 1) * nc + hmc[r]];
-        if (c12 && row < 12) v = qr[(N - 1) * 12 + row] + gmk[r] * Hq[(N - 1) * nc + gmc[r]];
+        float v = q2[r] + *at(hp[r], N - 1, hs[r]);
+        if (c12 && row < 12) v = qx[(N - 1) * 12 + row];
         Pm[r] = v;
     }
     auto rl = [](float v, int l) {
@@ -529,28 +544,20 @@ __device__ __forceinline__ void riccati_mfma_124(const float* A, const float* B,
     fetch(N - 1, RX);
     fetch(N >= 2 ? N - 2 : 0, RY);
     auto step = [&](int t, float (&Mraw)[4], Raw& R) {
-        // H_t, column 12 and f^ (H_0 and h_0 are not used)
-        v4f Z1, Z2;
-        float Mc[4], B2[4];
-        {
-            const float q[4] = {R.q.x, R.q.y, R.q.z, R.q.w};
-            const float f[4] = {R.f.x, R.f.y, R.f.z, R.f.w};
-            const float ri[4] = {R.ri.x, R.ri.y, R.ri.z, R.ri.w};
+        // the pose sums of H_t enter only P^_t; H_0 and h_0 are not used
+        float Mc[4], B2[4], Hp[4];
+        const float b2[4] = {R.b2.x, R.b2.y, R.b2.z, R.b2.w};
+        const v4f Z2c = {R.col.x, R.col.y, R.col.z, R.col.w};
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float H = q2[r] + hmk[r] * R.h[r];
-                const float colv = r3 ? ri[r] : q[r] + gmk[r] * R.gq[r];
-                Z1[r] = H + r2[r];
-                Z2[r] = c12 ? colv : H;
-                Mc[r] = (!TV || mok[r]) ? Mraw[r] : 0.f;
-                const float fv = r3 ? (r == 0 ? 1.f : 0.f) : f[r];
-                B2[r] = c12 ? fv : Mc[r];
-            }
+        for (int r = 0; r < 4; ++r) {
+            Hp[r] = R.h[r];
+            Mc[r] = (!TV || mok[r]) ? Mraw[r] : 0.f;
+            B2[r] = (TV && !c12) ? Mc[r] : b2[r];
         }
-        fetch(t >= 2 ? t - 2 : 0, R);
         v4f W = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 4; ++q) W = __builtin_amdgcn_mfma_f32_16x16x4f32(Pm[q], Mc[q], W, 0, 0, 0);
+        v4f Z1 = z1c;
 #pragma unroll
         for (int q = 0; q < 4; ++q) Z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mc[q], W[q], Z1, 0, 0, 0);
         // Quu^{-1} by 2 x 2 blocks, Quu = [a b; b^T d] (its upper triangle
@@ -560,8 +567,10 @@ __device__ __forceinline__ void riccati_mfma_124(const float* A, const float* B,
         const float a00 = rl(Z1[0], 60), a01 = rl(Z1[0], 61), a11 = rl(Z1[1], 61);
         const float b00 = rl(Z1[0], 62), b01 = rl(Z1[0], 63), b10 = rl(Z1[1], 62), b11 = rl(Z1[1], 63);
         const float d00 = rl(Z1[2], 62), d01 = rl(Z1[2], 63), d11 = rl(Z1[3], 63);
+        v4f Z2 = Z2c;
 #pragma unroll
         for (int q = 0; q < 4; ++q) Z2 = __builtin_amdgcn_mfma_f32_16x16x4f32(W[q], B2[q], Z2, 0, 0, 0);
+        fetch(t >= 2 ? t - 2 : 0, R);
         if constexpr (TV) load_m(t >= 2 ? t - 2 : 0, Mraw);
         const float ia = __builtin_amdgcn_rcpf(a00 * a11 - a01 * a01);
         const float ai00 = a11 * ia, ai01 = -a01 * ia, ai11 = a00 * ia;
@@ -594,7 +603,7 @@ __device__ __forceinline__ void riccati_mfma_124(const float* A, const float* B,
         // P^_t (formed at t = 0 too, unused, so that the step has no branch)
         v4f C3;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) C3[r] = c12 ? Z2[r] : 0.5f * (Z1[r] + Z2[r]);
+        for (int r = 0; r < 4; ++r) C3[r] = c12 ? Z2[r] : 0.5f * (Z1[r] + Z2[r]) + Hp[r];
 #pragma unroll
         for (int q = 0; q < 4; ++q) C3 = __builtin_amdgcn_mfma_f32_16x16x4f32(Z1[q], r3 ? Kh[q] : 0.f, C3, 0, 0, 0);
         Pm = C3;
@@ -920,10 +929,21 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         __syncthreads();
     } else {
     if constexpr (NS == 12 && NU == 4) {
-        // 2. the sweep in wave 0 on matrix-core tiles
-        if (tid < 64)
-            riccati_mfma_124<ADJ, TV>(A, B, Ag, Bg, mts * ns * ns, mts * ns * nu, ns, nu, Q2, R2, hmap, gmap, Hq,
-                                      qr, rin, off, Kall, reinterpret_cast<float*>(red4), N, nc);
+        // 2. the sweep in wave 0 on matrix-core tiles; the pose sums of the
+        //    stage gradients are first added into qr (forward mode), so that
+        //    h_t is one load
+        if (!ADJ) {
+            for (int e = tid; e < N * NS; e += TT) {
+                const int m = gmap[e % NS];
+                if (m >= 0) qr[e] += Hq[(e / NS) * nc + m];
+            }
+            __syncthreads();
+        }
+        if (tid < 64) {
+            float* scratch4 = reinterpret_cast<float*>(red4);
+            riccati_mfma_124<ADJ, TV>(A, B, Ag, Bg, mts * ns * ns, mts * ns * nu, ns, nu, Q2, R2, hmap, Hq, qr, rin,
+                                      off, Kall, scratch4, scratch4 + 256, scratch4 + 512, zero4, one4, N, nc);
+        }
         __syncthreads();
     } else {
     // 2. backward Riccati sweep, V_t(x) = 1/2 x^T P x + p^T x, P_N = H_N.
