@@ -73,14 +73,17 @@ __host__ __device__ inline int traj_dyn_floats(int N, int NS, int NU, int nc, bo
 // tangent, FP64): one thread per (step, column). Column j < n_s is dF/ds_j,
 // else dF/du_{j - n_s}.
 // ------------------------------------------------------------------------
-__device__ void model_column(int model, const double* par, const float* s, const float* u, int j, double* F,
-                             double* col)
+template <int MODEL>
+__device__ __forceinline__ void model_column(int model, const double* par, const float* s, const float* u, int j,
+                                             const ModelTrig& tr, double* F, double* col)
 {
-    const int ns = model_ns(model), nu = model_nu(model);
+    // MODEL > 0: the model fixed at compile time (its sizes unrolled)
+    const int ns = MODEL ? model_ns(MODEL) : model_ns(model), nu = MODEL ? model_nu(MODEL) : model_nu(model);
+    if (MODEL) model = MODEL;
     Tan S[12], U[4], f[12];
     for (int i = 0; i < ns; ++i) S[i] = {(double)s[i], i == j ? 1.0 : 0.0};
     for (int k = 0; k < nu; ++k) U[k] = {(double)u[k], ns + k == j ? 1.0 : 0.0};
-    model_fc<Tan>(model, par, S, U, f);
+    model_fc<Tan>(model, par, S, U, f, &tr);
     const double dt = par[0];
     for (int i = 0; i < ns; ++i) {
         F[i] = (double)s[i] + dt * f[i].v;
@@ -856,12 +859,20 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         // (zero-padded rows and columns contribute nothing)
         if (sqp) {
             // the SQP step: F(x^k_t, u^k_t) and its Jacobian columns, one
-            // thread per (step, column); the defect F(x^k_t, u^k_t) - x^k_{t+1}
+            // thread per (step, column); the defect F(x^k_t, u^k_t) - x^k_{t+1}.
+            // The sines and cosines of each step are formed once (in the
+            // chunk-sum region, free once the sums above are done).
+            ModelTrig* mtrig = reinterpret_cast<ModelTrig*>(red4);
+            __syncthreads();
+            for (int t = tid; t < N; t += TT) model_trig(P.model, sx + t * NS, su + t * NU, mtrig[t]);
+            __syncthreads();
             const int nz = ns + nu;
             for (int e = tid; e < N * nz; e += TT) {
                 const int t = e / nz, j = e % nz;
                 double F[12], col[12];
-                model_column(P.model, P.model_par, sx + t * NS, su + t * NU, j, F, col);
+                // the kernel sizes select the model: 12/4 the quadrotor, 4/2 the bicycle
+                constexpr int MODEL = NS == 12 && NU == 4 ? 2 : (NS == 4 && NU == 2 ? 1 : 0);
+                model_column<MODEL>(P.model, P.model_par, sx + t * NS, su + t * NU, j, mtrig[t], F, col);
                 if (j < ns) {
                     for (int i = 0; i < ns; ++i) P.A_lin[((size_t)s * N + t) * ns * ns + i * ns + j] = (float)col[i];
                 } else {
