@@ -5,7 +5,7 @@
 //
 // One step k -> k+1 of the iteration is reversed by two launches:
 //   - the trajectory kernel in reverse mode (one adjoint LQ per scenario,
-//     giving w, see cadmm_kernels.hip), then
+//     giving w, see cadmm_traj.hip), then
 //   - the reverse pair kernel below, one wavefront per pair block, lane t-1
 //     = pair t, which for every pair at the pose of x^k
 //       (a) reverses the pair's stage terms H_t += sigma J^T J,
