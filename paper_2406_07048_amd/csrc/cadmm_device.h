@@ -88,13 +88,7 @@ __device__ __forceinline__ float dpp_xor2(float v)
 __device__ __forceinline__ int dpp_xor1_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true); }
 __device__ __forceinline__ int dpp_xor2_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true); }
 
-// Within each row of 16 lanes: lane K of every quad broadcast to its quad
-// (quad_perm [K,K,K,K]), and a rotation of the row by R lanes (row_ror).
-template <int K>
-__device__ __forceinline__ float quad_bcast(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), K * 0x55, 0xF, 0xF, true));
-}
+// Within each row of 16 lanes: a rotation of the row by R lanes (row_ror).
 
 template <int R>
 __device__ __forceinline__ float row_ror(float v)
@@ -102,8 +96,6 @@ __device__ __forceinline__ float row_ror(float v)
     return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x120 + R, 0xF, 0xF, true));
 }
 
-template <int R>
-__device__ __forceinline__ int row_ror_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x120 + R, 0xF, 0xF, true); }
 
 // Sum over a lane group. Every lane of the group gets the bitwise same value
 // (pairwise sums in the same order: a + b = b + a exactly).

@@ -11,6 +11,9 @@
 
 namespace cadmm {
 
+// accumulator of a 16 x 16 x 4 FP32 matrix-core product (4 registers a lane)
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 // ------------------------------------------------------------------------
 // ADMM step 2: trajectory QP by a backward Riccati sweep and forward
 // rollout; one workgroup per scenario. The QP is solved in deviation
@@ -192,145 +195,122 @@ __device__ __forceinline__ float dot_lds(const float* x, const float* y, float a
     return acc;
 }
 
-// Riccati sweep for 4 states and 2 inputs, held in the registers
-// of one wave: lane (i, j) = 4 i + j of each row of 16 lanes owns entry
-// (i, j) of the 4 x 4 blocks (rows 1-3 of the wave repeat row 0). Row i of a
-// block reaches lane (i, j) by quad broadcasts, column j by rotations of the
-// row by 4, 8 and 12 lanes, so the sweep needs no barrier. Per step, with P = P_{t+1}:
-//   (a) PA = P A, PAT = (P A)^T (P symmetric), PB_{i, j mod 2} = (P B), w = P f_t + p;
-//   (b) Qxx = H_t + A^T PA, Qux_{i mod 2, j} = (B^T PA) and from PAT its
-//       transpose, Quu = 2Q_u + B^T PB, qu = r_t + B^T w, qx = h_t + A^T w;
-//   (c) K = -Quu^{-1} Qux, k = -Quu^{-1} qu (2 x 2 inverse by its adjugate),
-//       P_t = Qxx - Qux^T Quu^{-1} Qux, p_t = qx - Qux^T Quu^{-1} qu.
-// The sums over rows run in the lane's rotation order, so lanes that hold
-// the same entry may differ in the last bits; P_t is made exactly symmetric
-// by one ds_bpermute per step (the lanes below the diagonal take the values
-// of those above it). The step-dependent LDS terms
-// of step t - 1 are read while step t computes. Gains go to Kall[t][2][5]
-// for the rollout (rollout_scan_42).
-// With TV the model of step t is A + t mstride, B + t mstride (padded 4 x 4
-// and 4 x 2, in LDS), read one step ahead with the other step terms.
+// Riccati sweep for 4 states and 2 inputs in one wave on 16 x 16 x 4 FP32
+// matrix-core tiles (the layouts and the step of riccati_mfma_124), with the
+// variables embedded so that every product needs one or two K-slices: the
+// states at tile indices 0, 4, 8, 12 (slice 0 of lane rows 0-3), input 0 at
+// 1, the affine 1 at 2 and input 1 at 3 (slices 1, 2, 3 of lane row 0).
+//   W  = P^T M                     slice 0            (1 product)
+//   Z1 = blkdiag(H_t, 2Q_u) + M^T W slice 0            (1)
+//   Z2 = H_t, (h_t; r_t) + W^T [M | f^]  slices 0 and 2 (2: row 2 of W is p^T M)
+//   P^_t = [Qxx qx] + Qux^T [K | k]  slices 1 and 3    (2)
+// Qux columns and qu then sit in lane row 0 (registers 1 and 3), so the
+// gains of column c are formed in lane c with the 2 x 2 inverse of Quu (three
+// readlanes); 1/2 (Z1 + Z2) is exactly symmetric as in the 12-state sweep.
+// Gains go to Kall[t][2][5] for rollout_scan_42; with TV the model of step t
+// is A + t mstride, B + t mstride (padded 4 x 4 and 4 x 2, in LDS).
 template <bool ADJ, bool TV>
-__device__ __forceinline__ void riccati_regs_42(const float* A, const float* B, int mstride, const float* Q2,
+__device__ __forceinline__ void riccati_mfma_42(const float* A, const float* B, int mstride, const float* Q2,
                                                 const float* R2, const int* hmap, const int* gmap, const float* Hq,
                                                 const float* qr, const float* rin, const float* off, float* Kall,
-                                                int N, int nc)
+                                                float* kdump, const float* zero4, int N, int nc)
 {
-    const int lane = threadIdx.x & 15;
-    const int i = lane >> 2, j = lane & 3, a = i & 1, b = j & 1;
-    int km[4];
-    km[0] = i;
-    km[1] = row_ror_i<4>(i);
-    km[2] = row_ror_i<8>(i);
-    km[3] = row_ror_i<12>(i);
-    float Acol[4], Bcol[4], Arot[4], Brot[4];
-    float nAcol[4], nBcol[4], nArot[4], nBrot[4];
-    auto fetch_model = [&](int t, float (&ac)[4], float (&bc)[4], float (&ar)[4], float (&br)[4]) {
-        const float* At = A + t * mstride;
-        const float* Bt = B + t * mstride;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            ac[k] = At[k * 4 + j];
-            bc[k] = Bt[k * 2 + b];
-            ar[k] = At[km[k] * 4 + i];
-            br[k] = Bt[km[k] * 2 + a];
-        }
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+    const bool cx = (c & 3) == 0, c2 = c == 2, row0 = g == 0;
+    const int j = c >> 2;                       // state of a state column
+    const int ua = c == 1 ? 0 : 1;              // input of column 1 or 3
+    const bool cu = row0 && (c == 1 || c == 3);
+    // lane constants and per-lane LDS pointers (byte strides per step; lanes
+    // without a term read the zero block with stride 0)
+    const float q2 = cx ? Q2[g * 4 + j] : 0.f;
+    const int hm = cx ? hmap[g * 4 + j] : -1;
+    const int gm = (!ADJ && c2) ? gmap[g] : -1;
+    v4f z1c;
+    z1c[0] = q2;
+    z1c[1] = cu ? R2[0 * 2 + ua] : 0.f;
+    z1c[2] = 0.f;
+    z1c[3] = cu ? R2[1 * 2 + ua] : 0.f;
+    const char* hp = reinterpret_cast<const char*>(hm >= 0 ? Hq + hm : zero4);
+    const unsigned hs = hm >= 0 ? 4u * nc : 0u;
+    const char* qp = reinterpret_cast<const char*>(c2 ? qr + g : zero4);
+    const unsigned qs = c2 ? 16u : 0u;
+    const char* gp = reinterpret_cast<const char*>(gm >= 0 ? Hq + gm : zero4);
+    const unsigned gs = gm >= 0 ? 4u * nc : 0u;
+    const char* rp = reinterpret_cast<const char*>(c2 && row0 ? rin : zero4);
+    const unsigned rs = c2 && row0 ? 8u : 0u;
+    const char* fp = reinterpret_cast<const char*>(c2 ? off + g : zero4);
+    const unsigned fs = c2 ? 16u : 0u;
+    // M_t[4 g][c]: A_t[g][j] at state columns, B_t[g][a] at columns 1 and 3
+    const bool mA = cx, mB = c == 1 || c == 3;
+    const char* mp = reinterpret_cast<const char*>(mA ? A + g * 4 + j : (mB ? B + g * 2 + ua : zero4));
+    const unsigned ms = (mA || mB) ? 4u * mstride : 0u;
+    auto at = [](const char* p0, unsigned i, unsigned stride) {
+        return reinterpret_cast<const float*>(p0 + __umul24(i, stride));
     };
-    fetch_model(0, Acol, Bcol, Arot, Brot);
-    const float q2ij = Q2[i * 4 + j], r2ab = R2[a * 2 + b];
-    const int hmij = hmap[i * 4 + j], gmi = ADJ ? -1 : gmap[i];
-    const int tsrc = (((int)threadIdx.x & ~15) | (i <= j ? lane : j * 4 + i)) << 2;   // ds_bpermute byte address
-    float Pv = q2ij + (hmij >= 0 ? Hq[(N - 1) * nc + hmij] : 0.f);
-    float pv = qr[(N - 1) * 4 + i] + (gmi >= 0 ? Hq[(N - 1) * nc + gmi] : 0.f);
-    // step-dependent terms of step t: H_{t-1} (i, j), h_{t-1}(i), f_t, r_t
-    float nHij = 0.f, nh = 0.f, nf[4], nr;
-    auto fetch = [&](int t) {
-        if (t >= 1) {
-            const float* hq = Hq + (t - 1) * nc;
-            nHij = q2ij + (hmij >= 0 ? hq[hmij] : 0.f);
-            nh = qr[(t - 1) * 4 + i] + (gmi >= 0 ? hq[gmi] : 0.f);
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) nf[k] = off[t * 4 + k];
-        nr = rin[t * 2 + a];
-        if (TV) fetch_model(t, nAcol, nBcol, nArot, nBrot);
+    const float B2s2 = c2 && row0 ? 1.f : 0.f;
+    struct Raw {
+        float h, q, gq, f, m;
+        float2 r;
     };
-    fetch(N - 1);
-    for (int t = N - 1; t >= 0; --t) {
-        const float Hij = nHij, h = nh, r = nr;
-        float f[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) f[k] = nf[k];
-        if (TV) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                Acol[k] = nAcol[k]; Bcol[k] = nBcol[k]; Arot[k] = nArot[k]; Brot[k] = nBrot[k];
-            }
+    auto fetch = [&](int t, Raw& w) {
+        const unsigned tu = t, tp = t >= 1 ? t - 1 : 0;
+        w.h = *at(hp, tp, hs);
+        w.q = *at(qp, tp, qs);
+        w.gq = *at(gp, tp, gs);
+        w.f = *at(fp, tu, fs);
+        w.m = *at(mp, tu, ms);
+        w.r = *reinterpret_cast<const float2*>(at(rp, tu, rs));
+    };
+    // P^_N: the stage cost of x_N (p in column 2)
+    v4f Pm = {0.f, 0.f, 0.f, 0.f};
+    Pm[0] = c2 ? *at(qp, N - 1, qs) + *at(gp, N - 1, gs) : q2 + *at(hp, N - 1, hs);
+    auto rl = [](float v, int l) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    };
+    Raw RX, RY;
+    fetch(N - 1, RX);
+    fetch(N >= 2 ? N - 2 : 0, RY);
+    auto step = [&](int t, Raw& R) {
+        const float Mc = R.m;
+        const float B2s0 = c2 ? R.f : Mc;
+        const float Hp = R.h;                         // pose sum of H_t (state entries)
+        v4f Z2c = {c2 ? R.q + R.gq : q2, c2 && row0 ? R.r.x : 0.f, 0.f, c2 && row0 ? R.r.y : 0.f};
+        if (t == 0) Z2c[0] = c2 ? 0.f : q2;           // h_0 is not used
+        v4f zero = {0.f, 0.f, 0.f, 0.f};
+        fetch(t >= 2 ? t - 2 : 0, R);
+        const v4f W = __builtin_amdgcn_mfma_f32_16x16x4f32(Pm[0], Mc, zero, 0, 0, 0);
+        const v4f Z1 = __builtin_amdgcn_mfma_f32_16x16x4f32(Mc, W[0], z1c, 0, 0, 0);
+        // Quu = Z1 at rows / columns 1 and 3 (lane row 0)
+        const float q00 = rl(Z1[1], 1), q01 = rl(Z1[1], 3), q11 = rl(Z1[3], 3);
+        v4f Z2 = __builtin_amdgcn_mfma_f32_16x16x4f32(W[0], B2s0, Z2c, 0, 0, 0);
+        Z2 = __builtin_amdgcn_mfma_f32_16x16x4f32(W[2], B2s2, Z2, 0, 0, 0);
+        const float id = __builtin_amdgcn_rcpf(q00 * q11 - q01 * q01);
+        const float i00 = q11 * id, i01 = -q01 * id, i11 = q00 * id;
+        // column c of -Quu^{-1} [Qux | qu]
+        const float v0 = c2 ? Z2[1] : Z1[1], v1 = c2 ? Z2[3] : Z1[3];
+        const float k0 = -(i00 * v0 + i01 * v1), k1 = -(i01 * v0 + i11 * v1);
+        {
+            // lanes 0, 4, 8, 12 own the gain columns, lane 2 the feedforward
+            const bool own = row0 && (cx || c2);
+            float* Kt = own ? Kall + t * 10 + (c2 ? 4 : j) : kdump + lane;
+            const int ks = own ? 5 : 64;
+            Kt[0] = k0;
+            Kt[ks] = k1;
         }
-        if (t >= 1) fetch(t - 1);
-        // (a)
-        const float Pb[4] = {quad_bcast<0>(Pv), quad_bcast<1>(Pv), quad_bcast<2>(Pv), quad_bcast<3>(Pv)};
-        const float Pr[4] = {Pv, row_ror<4>(Pv), row_ror<8>(Pv), row_ror<12>(Pv)};
-        float PA = 0.f, PAT = 0.f, PB = 0.f, w = pv;
+        v4f C3;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            PA += Pb[k] * Acol[k];
-            PB += Pb[k] * Bcol[k];
-            w += Pb[k] * f[k];
-            PAT += Pr[k] * Arot[k];
-        }
-        // (b)
-        const float PAr[4] = {PA, row_ror<4>(PA), row_ror<8>(PA), row_ror<12>(PA)};
-        const float PBr[4] = {PB, row_ror<4>(PB), row_ror<8>(PB), row_ror<12>(PB)};
-        const float wr[4] = {w, row_ror<4>(w), row_ror<8>(w), row_ror<12>(w)};
-        float Qux = 0.f, Quu = r2ab, qu = r;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            Qux += Brot[k] * PAr[k];
-            Quu += Brot[k] * PBr[k];
-            qu += Brot[k] * wr[k];
-        }
-        // (c) Quu entries from the lanes of the other row / column parity
-        const float xo = dpp_xor1(Quu);
-        const float y = row_ror<4>(Quu), yo = row_ror<4>(xo);
-        const float Q00 = a ? (b ? yo : y) : (b ? xo : Quu);
-        const float Q11 = a ? (b ? Quu : xo) : (b ? y : yo);
-        const float Q01 = a ? (b ? y : yo) : (b ? Quu : xo);
-        const float idet = __builtin_amdgcn_rcpf(Q00 * Q11 - Q01 * Q01);
-        const float I00 = Q11 * idet, I11 = Q00 * idet, I01 = -Q01 * idet;
-        const float uxr = row_ror<4>(Qux);
-        const float U0j = a ? uxr : Qux, U1j = a ? Qux : uxr;
-        const float G0j = I00 * U0j + I01 * U1j, G1j = I01 * U0j + I11 * U1j;
-        const float qur = row_ror<4>(qu);
-        const float qu0 = a ? qur : qu, qu1 = a ? qu : qur;
-        const float g0 = I00 * qu0 + I01 * qu1, g1 = I01 * qu0 + I11 * qu1;
-        float* Kt = Kall + t * 10;
-        if (threadIdx.x < 4) {
-            Kt[j] = -G0j;
-            Kt[5 + j] = -G1j;
-            if (j == 0) {
-                Kt[4] = -g0;
-                Kt[9] = -g1;
-            }
-        }
-        if (t >= 1) {
-            float Qxx = Hij, qx = h, QuxT = 0.f;
-            const float PATb[4] = {quad_bcast<0>(PAT), quad_bcast<1>(PAT), quad_bcast<2>(PAT), quad_bcast<3>(PAT)};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                Qxx += Arot[k] * PAr[k];
-                qx += Arot[k] * wr[k];
-                QuxT += Bcol[k] * PATb[k];
-            }
-            const float U0i = quad_bcast<0>(QuxT), U1i = quad_bcast<1>(QuxT);
-            const float pij = Qxx - (U0i * G0j + U1i * G1j);
-            // exact symmetry: lane (i, j), i > j, takes the value of lane (j, i)
-            // (the two lanes sum in different orders; an antisymmetric part
-            // would grow along the sweep)
-            Pv = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(tsrc, __builtin_bit_cast(int, pij)));
-            pv = qx - (U0i * g0 + U1i * g1);
-        }
+        for (int r = 0; r < 4; ++r) C3[r] = c2 ? Z2[r] : 0.5f * (Z1[r] + Z2[r]);
+        C3[0] += Hp;
+        C3 = __builtin_amdgcn_mfma_f32_16x16x4f32(Z1[1], row0 ? k0 : 0.f, C3, 0, 0, 0);
+        C3 = __builtin_amdgcn_mfma_f32_16x16x4f32(Z1[3], row0 ? k1 : 0.f, C3, 0, 0, 0);
+        Pm = C3;
+    };
+    int t = N - 1;
+    for (; t >= 1; t -= 2) {
+        step(t, RX);
+        step(t - 1, RY);
     }
+    if (t == 0) step(0, RX);
 }
 
 // Rollout of the 4/2 closed loop x_{t+1} = M_t x_t + c_t, M_t = A + B K_t,
@@ -440,8 +420,6 @@ __device__ __forceinline__ void rollout_scan_42(const float* A, const float* B, 
 // Gains go to Kall[t][4][13] (the other lanes' columns to kdump, 256
 // floats); the step terms of step t - 2 (and, TV, the model, from global
 // memory) load while step t computes.
-typedef float v4f __attribute__((ext_vector_type(4)));
-
 template <bool ADJ, bool TV>
 __device__ __forceinline__ void riccati_mfma_124(const float* A, const float* B, const float* Ag, const float* Bg,
                                                  int astride, int bstride, int ns, int nu, const float* Q2,
@@ -934,7 +912,9 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
             Bm = tvm + 16;
             mstride = 24;
         }
-        if (tid < 64) riccati_regs_42<ADJ, TV>(Am, Bm, mstride, Q2, R2, hmap, gmap, Hq, qr, rin, off, Kall, N, nc);
+        if (tid < 64)
+            riccati_mfma_42<ADJ, TV>(Am, Bm, mstride, Q2, R2, hmap, gmap, Hq, qr, rin, off, Kall,
+                                     reinterpret_cast<float*>(red4), zero4, N, nc);
         __syncthreads();
         rollout_scan_42<ADJ, TT>(Am, Bm, mstride, Kall, off, x0s, reinterpret_cast<float*>(red4), dX, dU, wl, N);
         __syncthreads();
