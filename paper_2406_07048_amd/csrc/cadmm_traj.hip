@@ -668,9 +668,10 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         return (i < ns && c < nu) ? Bg[(size_t)t * mts * ns * nu + i * nu + c] : 0.f;
     };
 
-    // 0. padded model and cost, pose-coordinate maps; per-step sums formed
-    //    beforehand across many workgroups (sum_partials_kernel) are read
-    //    here, their latency overlapping that of the staged trajectory
+    // 0. padded model and cost, pose-coordinate maps; the per-step sums of
+    //    the pair contributions (formed beforehand across many workgroups by
+    //    sum_partials_kernel, else summed here), their loads overlapping
+    //    those of the staged trajectory
     if (tid < 4) {
         zero4[tid] = 0.f;
         one4[tid] = tid == 0 ? 1.f : 0.f;
@@ -682,6 +683,26 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
             if (hq_save) hq_save[(size_t)s * N * nc + e] = v;
             if (P.hq_b) P.hq_b[(size_t)s * N * nc + e] = v;
         }
+    } else if (!ADJ && !obstacle_free) {
+        // the per-step sums over this scenario's workgroup partials (fixed
+        // order), four steps per output summed as float4
+        const int2 wr0 = P.scen_wg[s];
+        const int N4 = (N + 3) / 4;
+        split_sums<TT>(
+            N4 * nc, wr0.x, wr0.y, (size_t)nc * 16, red4,
+            [&](int o) { return reinterpret_cast<const float4*>(P.contrib + (size_t)(o / N4) * 64) + o % N4; },
+            [&](int o, float4 v) {
+                const int cc = o / N4, t4 = o % N4;
+                const float vq[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int t = 4 * t4 + q;
+                    if (t >= N) break;
+                    Hq[t * nc + cc] = vq[q];
+                    if (hq_save) hq_save[((size_t)s * N + t) * nc + cc] = vq[q];
+                    if (P.hq_b) P.hq_b[((size_t)s * N + t) * nc + cc] = vq[q];
+                }
+            });
     }
     for (int e = tid; e < NS * NS; e += TT) {
         const int i = e / NS, j = e % NS;
@@ -798,23 +819,7 @@ __global__ void __launch_bounds__(traj_threads(NS, NU)) traj_phase_kernel(DevPro
         if (!obstacle_free && P.hq_pre) {
             // read in step 0
         } else if (!obstacle_free) {
-            // four steps per output, the partials summed as float4
-            const int N4 = (N + 3) / 4;
-            split_sums<TT>(
-                N4 * nc, wr.x, wr.y, (size_t)nc * 16, red4,
-                [&](int o) { return reinterpret_cast<const float4*>(P.contrib + (size_t)(o / N4) * 64) + o % N4; },
-                [&](int o, float4 v) {
-                    const int cc = o / N4, t4 = o % N4;
-                    const float vq[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int t = 4 * t4 + q;
-                        if (t >= N) break;
-                        Hq[t * nc + cc] = vq[q];
-                        if (hq_save) hq_save[((size_t)s * N + t) * nc + cc] = vq[q];
-                        if (P.hq_b) P.hq_b[((size_t)s * N + t) * nc + cc] = vq[q];
-                    }
-                });
+            // summed in step 0
         } else {
             for (int e = tid; e < N * nc; e += TT) Hq[e] = 0.f;
         }
