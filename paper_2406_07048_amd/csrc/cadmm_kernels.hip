@@ -304,7 +304,8 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
     const int t = chunk * PPW + lane / G + 1;
     float4* faces = reinterpret_cast<float4*>(lds);   // [WB][MR + MO] faces of each block
     float4* dcs = faces + WB * (MR + MO);             // [WB][MO] rounding of the obstacle normals
-    float* red = lds + 4 * WB * (MR + 2 * MO);        // [WB][NC][64] contributions by step
+    double* d64s = reinterpret_cast<double*>(dcs + WB * MO);   // [WB][MO] FP64 obstacle face offsets
+    float* red = reinterpret_cast<float*>(d64s + WB * MO);     // [WB][NC][64] contributions by step
     float* red_rd = red + WB * NC * 64;               // [W]
     int* red_un = reinterpret_cast<int*>(red_rd + W);
     const float eps = P.eps_prox;
@@ -326,6 +327,7 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
             else if (lane >= MR && lane - MR < nob) {
                 fl[lane] = P.obs_faces[fo0 + lane - MR];
                 dcs[bslot * MO + lane - MR] = P.obs_dc[fo0 + lane - MR];
+                d64s[bslot * MO + lane - MR] = P.obs_d64[fo0 + lane - MR];
             }
         }
         __syncthreads();
@@ -354,6 +356,13 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
 #pragma unroll
             for (int r = 0; r < DIM; ++r) pr.bh[1 + r] = xi[r];
             const float* yb = P.y + yoff + (t - 1);
+            // the rows' proximal centres first: unconditional loads from
+            // clamped rows, all in flight at once
+            float yRl[Rows::RR], yOl[Rows::RO];
+#pragma unroll
+            for (int m = 0; m < Rows::RR; ++m) yRl[m] = yb[max(0, min(q + G * m, pr.nr - 1)) * N];
+#pragma unroll
+            for (int m = 0; m < Rows::RO; ++m) yOl[m] = yb[(pr.nr + max(0, min(q + G * m, pr.no - 1))) * N];
             // warm start v = K^T yhat + bhat, nu from the largest lambda row
             float v0 = 0.f, Sc[DIM] = {}, vr[DIM] = {};
 #pragma unroll
@@ -361,7 +370,7 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
                 const int k = q + G * m;
                 if (k < pr.nr) {
                     const float4 f = pr.rf[k];
-                    const float yk = yb[k * N];
+                    const float yk = yRl[m];
                     pr.yhR[m] = yk;
                     const float D = f.x * f.x + f.y * f.y + (DIM == 3 ? f.z * f.z : 0.f);
                     pr.ieR[m] = __builtin_amdgcn_rcpf(eps * D);
@@ -378,9 +387,9 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
                 if (l < pr.no) {
                     const float4 f = pr.of[l];
                     const float c[3] = {f.x, f.y, f.z};
-                    const float yl = yb[(pr.nr + l) * N];
+                    const float yl = yOl[m];
                     pr.yhO[m] = yl;
-                    const float dp = face_offset(P.obs_d64, fo0 + l, f, dcs[bslot * MO + l], ps.pos64, ps.pos, DIM);
+                    const float dp = face_offset(d64s + bslot * MO, l, f, dcs[bslot * MO + l], ps.pos64, ps.pos, DIM);
                     float cn = 0.f;
 #pragma unroll
                     for (int r = 0; r < DIM; ++r) cn += c[r] * c[r];
@@ -581,11 +590,19 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
 template <int DIM, int MR, int MO>
 __global__ void __launch_bounds__(512) mult_phase_kernel(DevProblem P)
 {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     const int W = blockDim.x >> 6;
     const int wave = uniform(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int N = P.N;
+    // each wave's block geometry in LDS (faces, then the obstacle faces'
+    // FP64 offsets and normal roundings): one parallel load per workgroup
+    // instead of a dependent global load per face and lane
+    float4* faces = reinterpret_cast<float4*>(lds) + wave * (MR + 2 * MO);   // [W][MR + MO faces, MO dc]
+    float4* dcs = faces + MR + MO;
+    double* d64 = reinterpret_cast<double*>(reinterpret_cast<float4*>(lds) + W * (MR + 2 * MO)) + wave * MO;
+    float* red = reinterpret_cast<float*>(reinterpret_cast<double*>(reinterpret_cast<float4*>(lds) +
+                                                                    W * (MR + 2 * MO)) + W * MO);   // [W]
     for (int wg = blockIdx.x; wg < P.n_wg; wg += gridDim.x) {
         const int4 item = P.wg_items[wg];
         const int s = uniform(item.x);
@@ -593,20 +610,43 @@ __global__ void __launch_bounds__(512) mult_phase_kernel(DevProblem P)
         // the block's descriptor is loaded beside the done flag
         const int4 bd = b < item.z ? P.bdesc[b] : int4{0, 0, 0, 0};
         if (P.done[s]) continue;
+        const int fr0 = uniform(bd.x), fo0 = uniform(bd.y), yoff = uniform(bd.z);
+        const int nr = uniform(bd.w & 0xff), no = uniform((bd.w >> 8) & 0xff), part = uniform(bd.w >> 16);
+        if (b < item.z) {
+            if (lane < nr) faces[lane] = P.part_faces[fr0 + lane];
+            else if (lane >= MR && lane - MR < no) {
+                faces[lane] = P.obs_faces[fo0 + lane - MR];
+                dcs[lane - MR] = P.obs_dc[fo0 + lane - MR];
+                d64[lane - MR] = P.obs_d64[fo0 + lane - MR];
+            }
+        }
+        __syncthreads();
         const int t = lane + 1;
         float rp = 0.f;
         if (b < item.z && t <= N) {
-            const int fr0 = uniform(bd.x), fo0 = uniform(bd.y), yoff = uniform(bd.z);
-            const int nr = uniform(bd.w & 0xff), no = uniform((bd.w >> 8) & 0xff), part = uniform(bd.w >> 16);
             Pose<DIM> ps;
             make_pose<DIM>(P, P.x + ((size_t)s * (N + 1) + t) * P.n_s, part, ps);
+            // every row's dual first: unconditional loads from clamped rows,
+            // so that they are all in flight at once
             const float* yb = P.y + yoff + (t - 1);
+            float yr[MR], yo[MO];
+#pragma unroll
+            for (int k = 0; k < MR; ++k) yr[k] = yb[max(0, min(k, nr - 1)) * N];
+#pragma unroll
+            for (int l = 0; l < MO; ++l) yo[l] = yb[(nr + max(0, min(l, no - 1))) * N];
+            const float yg = yb[(nr + no) * N];
+            // the multipliers too, before any store (a store could alias them)
+            float* zp = P.zeta + (size_t)b * N + t - 1;
+            const float zeta = *zp;
+            float xi[DIM];
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) xi[r] = P.xi[((size_t)b * DIM + r) * N + t - 1];
             float Al[DIM] = {}, Sd = 0.f, Sc[DIM] = {};
 #pragma unroll
             for (int k = 0; k < MR; ++k) {
                 if (k < nr) {
-                    const float4 f = P.part_faces[fr0 + k];
-                    const float y = yb[k * N];
+                    const float4 f = faces[k];
+                    const float y = yr[k];
                     Al[0] += y * f.x;
                     Al[1] += y * f.y;
                     if (DIM == 3) Al[DIM - 1] += y * f.z;
@@ -615,35 +655,33 @@ __global__ void __launch_bounds__(512) mult_phase_kernel(DevProblem P)
 #pragma unroll
             for (int l = 0; l < MO; ++l) {
                 if (l < no) {
-                    const float4 f = P.obs_faces[fo0 + l];
-                    const float y = yb[(nr + l) * N];
-                    const float dp = face_offset(P.obs_d64, fo0 + l, f, P.obs_dc[fo0 + l], ps.pos64, ps.pos, DIM);
+                    const float4 f = faces[MR + l];
+                    const float y = yo[l];
+                    const float dp = face_offset(d64, l, f, dcs[l], ps.pos64, ps.pos, DIM);
                     Sd += dp * y;
                     Sc[0] += f.x * y;
                     Sc[1] += f.y * y;
                     if (DIM == 3) Sc[DIM - 1] += f.z * y;
                 }
             }
-            const float yg = yb[(nr + no) * N];
             const float T = 1.f + Sd + yg;
-            float* zp = P.zeta + (size_t)b * N + t - 1;
-            *zp += T;
+            *zp = zeta + T;
             rp = T * T;
 #pragma unroll
             for (int r = 0; r < DIM; ++r) {
                 float acc = Al[r];
 #pragma unroll
                 for (int m = 0; m < DIM; ++m) acc += ps.R[m * DIM + r] * Sc[m];
-                P.xi[((size_t)b * DIM + r) * N + t - 1] += acc;
+                P.xi[((size_t)b * DIM + r) * N + t - 1] = xi[r] + acc;
                 rp += acc * acc;
             }
         }
         const float rw = wave_sum(rp);
-        if (lane == 0) lds[wave] = rw;
+        if (lane == 0) red[wave] = rw;
         __syncthreads();
         if (threadIdx.x == 0) {
             float a = 0.f;
-            for (int w = 0; w < W; ++w) a += lds[w];
+            for (int w = 0; w < W; ++w) a += red[w];
             P.rpri_part[wg] = a;
         }
         __syncthreads();
@@ -863,8 +901,8 @@ static void launch_pair_g(const DevProblem& P, int W, int G, int grid, hipStream
 {
     const int nc = P.nc;
     const int nw = pair_waves_per_block(P.N, G);
-    const size_t lds = (size_t)W * (MR + 2 * MO) * sizeof(float4) + (size_t)W * nc * 64 * sizeof(float) +
-                       2 * (size_t)W * nw * sizeof(float);
+    const size_t lds = (size_t)W * (MR + 2 * MO) * sizeof(float4) + (size_t)W * MO * sizeof(double) +
+                       (size_t)W * nc * 64 * sizeof(float) + 2 * (size_t)W * nw * sizeof(float);
     dim3 blk(64 * W * nw), grd(grid);
     if (G == 4) CADMM_LAUNCH((pair_phase_kernel<DIM, MR, MO, 4>), grd, blk, lds, st, e0, e1, P);
     else if (G == 2) CADMM_LAUNCH((pair_phase_kernel<DIM, MR, MO, 2>), grd, blk, lds, st, e0, e1, P);
@@ -893,7 +931,9 @@ hipError_t launch_pair_phase(const DevProblem& P, int W, int G, int grid, hipStr
 hipError_t launch_mult_phase(const DevProblem& P, int W, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1)
 {
     const int v = pick_variant(P);
-    const size_t lds = (size_t)W * sizeof(float);
+    if (v < 0) return hipErrorInvalidValue;
+    const Variant& vv = kVariants[v];
+    const size_t lds = (size_t)W * ((vv.mr + 2 * vv.mo) * sizeof(float4) + vv.mo * sizeof(double) + sizeof(float));
     dim3 blk(64 * W), grd(grid);
     switch (v) {
     case 0: CADMM_LAUNCH((mult_phase_kernel<2, 4, 16>), grd, blk, lds, st, e0, e1, P); break;
