@@ -142,18 +142,21 @@ __device__ __forceinline__ float face_offset(const double* d64, int face, const 
     return (float)(acc - (double)corr);
 }
 
+// The pose from the state's position entries xp, attitude entries xa and the
+// part's offset o (values already loaded; see make_pose).
 template <int DIM>
-__device__ __forceinline__ void make_pose(const DevProblem& P, const float* xs, int part, Pose<DIM>& ps)
+__device__ __forceinline__ void make_pose_v(const float (&xp)[DIM], const float (&xa)[Pose<DIM>::NATT],
+                                            const float (&o)[3], Pose<DIM>& ps)
 {
     if constexpr (DIM == 2) {
-        const float th = xs[P.att_idx[0]];
+        const float th = xa[0];
         float s, c;
         sincosf(th, &s, &c);
         ps.R[0] = c; ps.R[1] = -s; ps.R[2] = s; ps.R[3] = c;
         ps.dR[0] = -s; ps.dR[1] = -c; ps.dR[2] = c; ps.dR[3] = -s;
         ps.q[2] = th;
     } else {
-        const float ph = xs[P.att_idx[0]], th = xs[P.att_idx[1]], psi = xs[P.att_idx[2]];
+        const float ph = xa[0], th = xa[1], psi = xa[2];
         float sf, cf, st, ct, sp, cp;
         sincosf(ph, &sf, &cf);
         sincosf(th, &st, &ct);
@@ -176,7 +179,6 @@ __device__ __forceinline__ void make_pose(const DevProblem& P, const float* xs, 
         D[6] = 0.f;      D[7] = 0.f;                     D[8] = 0.f;
         ps.q[3] = ph; ps.q[4] = th; ps.q[5] = psi;
     }
-    const float* o = P.part_off + part * 3;
     // the part centre rho(s) + R(s) o_i; its FP64 copy takes R o_i from FP64
     // trigonometry (only parts with an offset need it)
     double ro64[DIM] = {};
@@ -186,14 +188,14 @@ __device__ __forceinline__ void make_pose(const DevProblem& P, const float* xs, 
     if (off) {
         if constexpr (DIM == 2) {
             double s, c;
-            sincos((double)xs[P.att_idx[0]], &s, &c);
+            sincos((double)xa[0], &s, &c);
             ro64[0] = c * o[0] - s * o[1];
             ro64[1] = s * o[0] + c * o[1];
         } else {
             double sf, cf, st, ct, sp, cp;
-            sincos((double)xs[P.att_idx[0]], &sf, &cf);
-            sincos((double)xs[P.att_idx[1]], &st, &ct);
-            sincos((double)xs[P.att_idx[2]], &sp, &cp);
+            sincos((double)xa[0], &sf, &cf);
+            sincos((double)xa[1], &st, &ct);
+            sincos((double)xa[2], &sp, &cp);
             const double R64[9] = {cp * ct, cp * st * sf - sp * cf, cp * st * cf + sp * sf,
                                    sp * ct, sp * st * sf + cp * cf, sp * st * cf - cp * sf,
                                    -st,     ct * sf,                ct * cf};
@@ -203,7 +205,7 @@ __device__ __forceinline__ void make_pose(const DevProblem& P, const float* xs, 
     }
 #pragma unroll
     for (int r = 0; r < DIM; ++r) {
-        const float p = xs[P.pos_idx[r]];
+        const float p = xp[r];
         ps.q[r] = p;
         float ro = 0.f;
 #pragma unroll
@@ -211,6 +213,39 @@ __device__ __forceinline__ void make_pose(const DevProblem& P, const float* xs, 
         ps.pos[r] = p + ro;
         ps.pos64[r] = (double)p + ro64[r];
     }
+}
+
+// The state entries of the pose at xs (position, attitude) and the part
+// offset, loaded into registers (a kernel can issue these loads early).
+template <int DIM>
+struct PoseInputs {
+    float xp[DIM], xa[Pose<DIM>::NATT], o[3];
+};
+
+template <int DIM>
+__device__ __forceinline__ void load_pose_state(const DevProblem& P, const float* xs, PoseInputs<DIM>& in)
+{
+#pragma unroll
+    for (int r = 0; r < DIM; ++r) in.xp[r] = xs[P.pos_idx[r]];
+#pragma unroll
+    for (int a = 0; a < Pose<DIM>::NATT; ++a) in.xa[a] = xs[P.att_idx[a]];
+}
+
+template <int DIM>
+__device__ __forceinline__ void load_pose_offset(const DevProblem& P, int part, PoseInputs<DIM>& in)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) in.o[c] = P.part_off[part * 3 + c];
+}
+
+// R(s), dR and the part centre of part `part` at the state xs
+template <int DIM>
+__device__ __forceinline__ void make_pose(const DevProblem& P, const float* xs, int part, Pose<DIM>& ps)
+{
+    PoseInputs<DIM> in;
+    load_pose_state<DIM>(P, xs, in);
+    load_pose_offset<DIM>(P, part, in);
+    make_pose_v<DIM>(in.xp, in.xa, in.o, ps);
 }
 
 }  // namespace cadmm

@@ -314,11 +314,31 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
         const int4 item = P.wg_items[wg];
         const int s = uniform(item.x);
         const int b = uniform(item.y + bslot);
-        // the block's descriptor is loaded beside the done flag
+        // what depends only on (s, b, t) is loaded beside the block's
+        // descriptor and the done flag (an empty slot loads a valid pair's
+        // values and ignores them): the state entries of the pose and the
+        // multipliers
+        const int bq = min(b, item.z - 1), tq = min(t, N);
+        PoseInputs<DIM> pin;
+        load_pose_state<DIM>(P, P.x + ((size_t)s * (N + 1) + tq) * P.n_s, pin);
+        const float zeta = P.zeta[(size_t)bq * N + tq - 1];
+        float xi[DIM];
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) xi[r] = P.xi[((size_t)bq * DIM + r) * N + tq - 1];
         const int4 bd = b < item.z ? P.bdesc[b] : int4{0, 0, 0, 0};
         if (P.done[s]) continue;                 // uniform over the workgroup
         const int fr0 = uniform(bd.x), fo0 = uniform(bd.y), yoff = uniform(bd.z);
         const int nrb = uniform(bd.w & 0xff), nob = uniform((bd.w >> 8) & 0xff), part = uniform(bd.w >> 16);
+        // then, beside the faces, the part offset and the rows' proximal
+        // centres (unconditional loads from clamped rows, all in flight at once)
+        load_pose_offset<DIM>(P, part, pin);
+        const float* yb = P.y + yoff + (tq - 1);
+        float yRl[Rows::RR], yOl[Rows::RO];
+#pragma unroll
+        for (int m = 0; m < Rows::RR; ++m) yRl[m] = yb[max(0, min(q + G * m, nrb - 1)) * N];
+#pragma unroll
+        for (int m = 0; m < Rows::RO; ++m) yOl[m] = yb[(nrb + max(0, min(q + G * m, nob - 1))) * N];
+        const float yG = yb[(nrb + nob) * N];
         // the block's faces into its LDS slot: every solver pass reads them,
         // and from LDS they are cheap reads instead of HBM round trips
         float4* fl = faces + bslot * (MR + MO);
@@ -343,26 +363,13 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
             pr.no = nob;
             pr.rf = fl;
             pr.of = fl + MR;
-            const float* xs = P.x + ((size_t)s * (N + 1) + t) * P.n_s;
             Pose<DIM> ps;
-            make_pose<DIM>(P, xs, part, ps);
+            make_pose_v<DIM>(pin.xp, pin.xa, pin.o, ps);
 #pragma unroll
             for (int i = 0; i < DIM * DIM; ++i) pr.R[i] = ps.R[i];
-            const float zeta = P.zeta[(size_t)b * N + t - 1];
-            float xi[DIM];
-#pragma unroll
-            for (int r = 0; r < DIM; ++r) xi[r] = P.xi[((size_t)b * DIM + r) * N + t - 1];
             pr.bh[0] = 1.f + zeta;
 #pragma unroll
             for (int r = 0; r < DIM; ++r) pr.bh[1 + r] = xi[r];
-            const float* yb = P.y + yoff + (t - 1);
-            // the rows' proximal centres first: unconditional loads from
-            // clamped rows, all in flight at once
-            float yRl[Rows::RR], yOl[Rows::RO];
-#pragma unroll
-            for (int m = 0; m < Rows::RR; ++m) yRl[m] = yb[max(0, min(q + G * m, pr.nr - 1)) * N];
-#pragma unroll
-            for (int m = 0; m < Rows::RO; ++m) yOl[m] = yb[(pr.nr + max(0, min(q + G * m, pr.no - 1))) * N];
             // warm start v = K^T yhat + bhat, nu from the largest lambda row
             float v0 = 0.f, Sc[DIM] = {}, vr[DIM] = {};
 #pragma unroll
@@ -409,7 +416,7 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
                 vr[r] = group_sum<G>(vr[r]);
                 Sc[r] = group_sum<G>(Sc[r]);
             }
-            pr.yhG = yb[(pr.nr + pr.no) * N];
+            pr.yhG = yG;
             pr.ieG = 1.0f / eps;
             v0 += pr.bh[0] + pr.yhG;
 #pragma unroll
@@ -505,7 +512,7 @@ __global__ void __launch_bounds__(512) pair_phase_kernel(DevProblem P)
                     e[1 + r] = acc;
                 }
                 // Jacobian of (T, R) in the pose coordinates (position, attitude)
-                const float* o = P.part_off + part * 3;
+                const float* o = pin.o;
                 float J[(DIM + 1) * NQ];
 #pragma unroll
                 for (int i = 0; i < (DIM + 1) * NQ; ++i) J[i] = 0.f;
@@ -607,11 +614,32 @@ __global__ void __launch_bounds__(512) mult_phase_kernel(DevProblem P)
         const int4 item = P.wg_items[wg];
         const int s = uniform(item.x);
         const int b = uniform(item.y + wave);
-        // the block's descriptor is loaded beside the done flag
+        const int t = lane + 1;
+        // the state entries of the pose and the multipliers are loaded beside
+        // the block's descriptor and the done flag (an empty slot loads a
+        // valid pair's values and ignores them)
+        const int bq = min(b, item.z - 1), tq = min(t, N);
+        PoseInputs<DIM> pin;
+        load_pose_state<DIM>(P, P.x + ((size_t)s * (N + 1) + tq) * P.n_s, pin);
+        float* zp = P.zeta + (size_t)bq * N + tq - 1;
+        const float zeta = *zp;
+        float xi[DIM];
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) xi[r] = P.xi[((size_t)bq * DIM + r) * N + tq - 1];
         const int4 bd = b < item.z ? P.bdesc[b] : int4{0, 0, 0, 0};
         if (P.done[s]) continue;
         const int fr0 = uniform(bd.x), fo0 = uniform(bd.y), yoff = uniform(bd.z);
         const int nr = uniform(bd.w & 0xff), no = uniform((bd.w >> 8) & 0xff), part = uniform(bd.w >> 16);
+        // then, beside the faces, the part offset and every row's dual
+        // (unconditional loads from clamped rows, all in flight at once)
+        load_pose_offset<DIM>(P, part, pin);
+        const float* yb = P.y + yoff + (tq - 1);
+        float yr[MR], yo[MO];
+#pragma unroll
+        for (int k = 0; k < MR; ++k) yr[k] = yb[max(0, min(k, nr - 1)) * N];
+#pragma unroll
+        for (int l = 0; l < MO; ++l) yo[l] = yb[(nr + max(0, min(l, no - 1))) * N];
+        const float yg = yb[(nr + no) * N];
         if (b < item.z) {
             if (lane < nr) faces[lane] = P.part_faces[fr0 + lane];
             else if (lane >= MR && lane - MR < no) {
@@ -621,26 +649,10 @@ __global__ void __launch_bounds__(512) mult_phase_kernel(DevProblem P)
             }
         }
         __syncthreads();
-        const int t = lane + 1;
         float rp = 0.f;
         if (b < item.z && t <= N) {
             Pose<DIM> ps;
-            make_pose<DIM>(P, P.x + ((size_t)s * (N + 1) + t) * P.n_s, part, ps);
-            // every row's dual first: unconditional loads from clamped rows,
-            // so that they are all in flight at once
-            const float* yb = P.y + yoff + (t - 1);
-            float yr[MR], yo[MO];
-#pragma unroll
-            for (int k = 0; k < MR; ++k) yr[k] = yb[max(0, min(k, nr - 1)) * N];
-#pragma unroll
-            for (int l = 0; l < MO; ++l) yo[l] = yb[(nr + max(0, min(l, no - 1))) * N];
-            const float yg = yb[(nr + no) * N];
-            // the multipliers too, before any store (a store could alias them)
-            float* zp = P.zeta + (size_t)b * N + t - 1;
-            const float zeta = *zp;
-            float xi[DIM];
-#pragma unroll
-            for (int r = 0; r < DIM; ++r) xi[r] = P.xi[((size_t)b * DIM + r) * N + t - 1];
+            make_pose_v<DIM>(pin.xp, pin.xa, pin.o, ps);
             float Al[DIM] = {}, Sd = 0.f, Sc[DIM] = {};
 #pragma unroll
             for (int k = 0; k < MR; ++k) {
