@@ -281,8 +281,49 @@ class Handle:
                                     _ptr(st["zeta"]), _ptr(st["xi"])), "admm_get_state")
         return st
 
+    def _state_sizes(self):
+        return (self.n_scen * (self.N + 1) * self.n_s, self.n_scen * self.N * self.n_u, self.y_floats,
+                self.n_pairs, self.n_pairs * self.dim)
+
+    def get_state_host(self):
+        """The iterate as FP64 numpy arrays (shapes as get_state), read back
+        in one device-to-host copy."""
+        torch = _torch()
+        sizes = self._state_sizes()
+        flat = torch.empty(sum(sizes), dtype=torch.float32, device=self.device)
+        views = list(torch.split(flat, sizes))
+        _check(lib().admm_get_state(self._h, *[_ptr(v) for v in views]), "admm_get_state")
+        host = flat.cpu().numpy().astype(np.float64)
+        out, o = {}, 0
+        shapes = ((self.n_scen, self.N + 1, self.n_s), (self.n_scen, self.N, self.n_u), (self.y_floats,),
+                  (self.n_pairs,), (self.n_pairs * self.dim,))
+        for name, n, shp in zip(("x", "u", "y", "zeta", "xi"), sizes, shapes):
+            out[name] = host[o:o + n].reshape(shp)
+            o += n
+        return out
+
     def set_state(self, x=None, u=None, y=None, zeta=None, xi=None):
         torch = _torch()
+        given = (x, u, y, zeta, xi)
+        if all(t is None or isinstance(t, np.ndarray) for t in given):
+            # host arrays: one host-to-device copy for all parts
+            sizes = self._state_sizes()
+            arrs = []
+            for t, n in zip(given, sizes):
+                if t is None:
+                    continue
+                a = np.ascontiguousarray(t, dtype=np.float32).ravel()
+                if a.size != n:
+                    raise ValueError(f"state part has {a.size} floats, expected {n}")
+                arrs.append(a)
+            if not arrs:
+                return [None] * 5
+            dev = torch.from_numpy(np.concatenate(arrs)).to(self.device)
+            views = iter(torch.split(dev, [a.size for a in arrs]))
+            parts = [None if t is None else next(views) for t in given]
+            _check(lib().admm_set_state(self._h, *[_ptr(p) for p in parts]), "admm_set_state")
+            self._keep_set = (dev, parts)   # keep alive until the stream has consumed them
+            return parts
 
         def prep(t, n):
             if t is None:

@@ -121,7 +121,7 @@ class ClosedLoop:
                 # trajectory (admm_reset_duals); the others carried
                 self.h.set_state(x=ws["x"], u=ws["u"])
                 self.h.reset_duals()
-                st0 = {a: v.double().cpu().numpy() for a, v in self.h.get_state().items()}
+                st0 = self.h.get_state_host()
             else:
                 st0 = {a: self.prev[a] for a in ("y", "zeta", "xi")}
             self.h.set_state(**self._warm_state(x_meas, blocks, st0))
@@ -137,7 +137,7 @@ class ClosedLoop:
             iters = res[0]["iters"] - self.count
             self.count = res[0]["iters"]
             min_alpha = res[0]["min_alpha"]
-        st = {a: v.double().cpu().numpy() for a, v in self.h.get_state().items()}
+        st = self.h.get_state_host()
         t2 = time.perf_counter()
         u0 = st["u"][0, 0].copy()
         self.prev = dict(x=st["x"], u=st["u"], y=st["y"], zeta=st["zeta"], xi=st["xi"], blocks=blocks)

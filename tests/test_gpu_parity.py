@@ -457,6 +457,25 @@ def test_batched_equals_separate(cadmm, G):
         assert np.array_equal(gs["x"][0], g["x"][s])
 
 
+def test_state_host_transfers(cadmm):
+    """get_state_host (one copy) returns get_state's values, and set_state
+    from host arrays (one copy) installs them bitwise."""
+    prob = workloads.make("c2")
+    say("[state transfers] c2")
+    h = cadmm.Handle(prob)
+    h.iterate(5)
+    a = gpu_state(h)
+    b = h.get_state_host()
+    for k in a:
+        assert a[k].shape == b[k].shape and np.array_equal(a[k], b[k]), k
+    h.reset()
+    h.set_state(**{k: v.copy() for k, v in b.items()})
+    c = gpu_state(h)
+    for k in a:
+        assert np.array_equal(a[k], c[k]), k
+    h.close()
+
+
 def test_replay_is_deterministic(cadmm):
     prob = workloads.make("c2")
     say("[determinism] c2")
