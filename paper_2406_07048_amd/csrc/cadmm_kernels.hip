@@ -707,11 +707,8 @@ __global__ void __launch_bounds__(512) mult_phase_kernel(DevProblem P)
 __global__ void __launch_bounds__(64) residual_kernel(DevProblem P)
 {
     const int s = blockIdx.x;
-    // the scenario's workgroup range and its iteration count are loaded
-    // beside the done flag (one round trip fewer)
-    const int2 r = P.scen_wg[s];
-    const int k = P.iters[s];
     if (P.done[s]) return;
+    const int2 r = P.scen_wg[s];
     float a = 0.f, b = 0.f;
     int u = 0;
     for (int w = r.x + threadIdx.x; w < r.y; w += 64) {
@@ -723,6 +720,7 @@ __global__ void __launch_bounds__(64) residual_kernel(DevProblem P)
     b = wave_sum(b);
     u = wave_sum_int(u);
     if (threadIdx.x == 0) {
+        const int k = P.iters[s];
         if (k < P.hist_cap) {
             P.hist_pri[(size_t)k * P.n_scen + s] = a;
             P.hist_dual[(size_t)k * P.n_scen + s] = b;
